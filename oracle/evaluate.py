@@ -1,0 +1,205 @@
+"""The evaluation itself, step by step as in Algorithm 1 (Section 2.4).
+
+Precomputation (plan):
+  1. Gaussian-sum table of the kernel (Section 3; `gs_table`).
+  2. The stored coefficient sums  G_k = sum_q w_q prod_j g_q(xi_{k_j})  of
+     eq. (2.12)-(2.13), from the one-dimensional factors (`factors`).  G is even
+     in every index, so it is formed on the octant k_j in [0, n] and extended.
+  3. The Taylor constants A0, c2 of Section 2.3 (`taylor`).
+Actual computation (evaluate):
+  1. rho~ = DFT(pad(rho))                                (eqs. (2.10)-(2.11))
+  2. I1   = (1/M) crop(IDFT(G . rho~))                   (eq. (2.12))
+  3. Lap  = (1/M) crop(IDFT(-|xi|^2 . rho~))             (spectral Laplacian)
+  4. I21~ = A0 rho + c2 Lap                              (eq. (2.19))
+  5. u    = I1 + I21~
+with M = (2n)^d.  The Laplacian is taken on the padded grid with the Nyquist
+mode kept (|xi| = pi/h there).
+
+Dipolar potential (Section 2.4): u = -(n.m) rho - 3 Coul3D(d_n d_m rho), the
+source d_n d_m rho having padded coefficients -(n.xi)(m.xi) rho~.  In the cross
+terms xi_i xi_j (i != j) the Nyquist frequency is taken as 0 (an odd symbol has
+no value there that keeps the result real); squares keep (pi/h)^2.
+
+The operator is real, linear and, the kernel being even, symmetric.  `adjoint`
+applies the transposed steps literally (pad and crop exchanged, DFT signs
+flipped), `energy` is 1/2 h^d sum rho u, and its rho-gradient is h^d u.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import dft
+from .factors import factor_1d
+from .gs_table import GSTable, custom_table, physical_table
+from .taylor import taylor_constants
+
+COULOMB_LIKE = ("coulomb3d", "coulomb2d", "poisson2d", "dipolar3d")
+
+
+@dataclass
+class OraclePlan:
+    kernel: str
+    d: int
+    n: int
+    L: float
+    table: GSTable
+    F: np.ndarray           # (n+1, Q) one-dimensional factors
+    G_oct: np.ndarray       # (n+1)^d regular-part coefficients
+    A0: float
+    c2: float
+    dipole_n: tuple | None = None
+    dipole_m: tuple | None = None
+
+    @property
+    def h(self) -> float:
+        return 2.0 * self.L / self.n
+
+    @property
+    def M(self) -> int:
+        return (2 * self.n) ** self.d
+
+
+def make_plan(kernel: str, d: int, n: int, L: float, eps: float = 1e-14,
+              delta_rel: float = 1e-4, custom=None, dipole=None) -> OraclePlan:
+    if kernel == "gaussian_sum":
+        w, tau = custom
+        table = custom_table(w, tau, d, L)
+    else:
+        table = physical_table(kernel, d, L, eps, delta_rel)
+        if table.d != d:
+            raise ValueError("kernel and dimension disagree")
+    F = factor_1d(table.tau, 2.0 * L, n)
+    Fw = F * table.w[None, :]
+    if d == 2:
+        G = Fw @ F.T
+    else:
+        G = np.empty((n + 1,) * 3)
+        for a in range(n + 1):
+            G[a] = (Fw * F[a][None, :]) @ F.T
+    if kernel == "gaussian_sum":
+        A0, c2 = 0.0, 0.0
+    else:
+        A0, c2 = taylor_constants(kernel, d, table.delta, table.w, table.tau)
+    dn = dm = None
+    if kernel == "dipolar3d":
+        dn, dm = dipole
+    return OraclePlan(kernel, d, n, L, table, F, G, A0, c2, dn, dm)
+
+
+def padded_frequencies(n: int, L: float, odd: bool = False) -> np.ndarray:
+    """xi_k = pi k'/(2L) for padded index k = 0..2n-1, k' = k - 2n for k >= n.
+    The Nyquist index k = n carries -pi n/(2L) (even use) or 0 (odd use)."""
+    k = np.arange(2 * n)
+    ks = np.where(k < n, k, k - 2 * n).astype(np.float64)
+    xi = math.pi * ks / (2.0 * L)
+    if odd:
+        xi[n] = 0.0
+    return xi
+
+
+def _fold_index(n: int) -> np.ndarray:
+    k = np.arange(2 * n)
+    return np.minimum(k, 2 * n - k)
+
+
+def full_spectrum(plan: OraclePlan) -> np.ndarray:
+    idx = _fold_index(plan.n)
+    if plan.d == 2:
+        return plan.G_oct[np.ix_(idx, idx)]
+    return plan.G_oct[np.ix_(idx, idx, idx)]
+
+
+def _axes_vectors(plan: OraclePlan, odd: bool):
+    """Per-axis xi arrays shaped to broadcast over the [z][y][x] (or [y][x]) grid,
+    returned in vector-component order (x, y[, z])."""
+    xi = padded_frequencies(plan.n, plan.L, odd)
+    d = plan.d
+    out = []
+    for comp in range(d):
+        ax = d - 1 - comp                       # x is the last array axis
+        shape = [1] * d
+        shape[ax] = 2 * plan.n
+        out.append(xi.reshape(shape))
+    return out
+
+
+def laplacian_symbol(plan: OraclePlan) -> np.ndarray:
+    xs = _axes_vectors(plan, odd=False)
+    return sum(x * x for x in xs)
+
+
+def dipolar_symbol(plan: OraclePlan) -> np.ndarray:
+    """(n.xi)(m.xi) with squares from the even xi and cross terms from the odd xi."""
+    ev = _axes_vectors(plan, odd=False)
+    od = _axes_vectors(plan, odd=True)
+    nv, mv = plan.dipole_n, plan.dipole_m
+    sym = 0.0
+    for i in range(3):
+        for j in range(3):
+            if i == j:
+                sym = sym + nv[i] * mv[i] * ev[i] * ev[i]
+            else:
+                sym = sym + nv[i] * mv[j] * od[i] * od[j]
+    return sym
+
+
+def _coulomb_steps(plan: OraclePlan, rt: np.ndarray, f: np.ndarray, sign: int = +1) -> np.ndarray:
+    """I1 + A0 f + c2 Lap f for padded coefficients rt of the source f."""
+    M = plan.M
+    G = full_spectrum(plan)
+    I1 = dft.inverse(G * rt, sign).real / M
+    if plan.A0 == 0.0 and plan.c2 == 0.0:
+        return I1
+    lap = dft.inverse(-laplacian_symbol(plan) * rt, sign).real / M
+    return I1 + plan.A0 * f + plan.c2 * lap
+
+
+def evaluate(plan: OraclePlan, rho: np.ndarray) -> np.ndarray:
+    rho = np.asarray(rho, dtype=np.float64)
+    assert rho.shape == (plan.n,) * plan.d
+    rt = dft.forward(rho)
+    if plan.kernel != "dipolar3d":
+        return _coulomb_steps(plan, rt, rho)
+    src_t = -dipolar_symbol(plan) * rt
+    src = dft.inverse(src_t).real / plan.M
+    nm = float(np.dot(plan.dipole_n, plan.dipole_m))
+    return -nm * rho - 3.0 * _coulomb_steps(plan, src_t, src)
+
+
+def adjoint(plan: OraclePlan, v: np.ndarray) -> np.ndarray:
+    """Transpose of `evaluate` as a real linear map: every step transposed in
+    reverse order (crop -> zero-pad, pad -> crop, DFT sign flipped)."""
+    v = np.asarray(v, dtype=np.float64)
+    vt = dft.forward(v, sign=+1)                  # transpose of the crop-inverse
+    M = plan.M
+    if plan.kernel != "dipolar3d":
+        G = full_spectrum(plan)
+        out = dft.inverse(G * vt, sign=-1).real / M
+        if plan.A0 != 0.0 or plan.c2 != 0.0:
+            lap = dft.inverse(-laplacian_symbol(plan) * vt, sign=-1).real / M
+            out = out + plan.A0 * v + plan.c2 * lap
+        return out
+    nm = float(np.dot(plan.dipole_n, plan.dipole_m))
+    G = full_spectrum(plan)
+    sym = dipolar_symbol(plan)
+    lap_sym = laplacian_symbol(plan)
+    # transpose of rho -> -3 [I1 + A0 f + c2 Lap f](src(rho))
+    w1 = G * vt - plan.c2 * lap_sym * vt + plan.A0 * vt
+    out = dft.inverse(-sym * w1, sign=-1).real / M
+    return -nm * v - 3.0 * out
+
+
+def energy(plan: OraclePlan, rho: np.ndarray, u: np.ndarray | None = None) -> float:
+    """Hartree-type energy 1/2 int rho u, by the grid (trapezoidal) sum."""
+    if u is None:
+        u = evaluate(plan, rho)
+    return 0.5 * plan.h ** plan.d * float(np.sum(rho * u))
+
+
+def energy_gradient_rho(plan: OraclePlan, rho: np.ndarray) -> np.ndarray:
+    """dE/drho = 1/2 h^d (A + A^T) rho."""
+    return 0.5 * plan.h ** plan.d * (evaluate(plan, rho) + adjoint(plan, rho))

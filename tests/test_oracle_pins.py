@@ -1,0 +1,418 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check uses printed values of
+the paper (tests/golden), closed-form potentials, an independent quadrature,
+brute-force transforms, or an invariant of the continuous problem.
+"""
+
+import csv
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import closed_forms as cf
+from oracle import dft, gs_table
+from oracle.factors import factor_1d
+from oracle.taylor import taylor_constants
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _rows(path):
+    with open(path) as f:
+        return list(csv.DictReader(line for line in f if not line.startswith("#")))
+
+
+def _exact(kernel, n, L, sigma, x0):
+    d = 3 if kernel.endswith("3d") else 2
+    X = workloads.mesh(n, L, d)
+    if kernel == "dipolar3d":
+        return cf.dipolar3d_gaussian(X[0], X[1], X[2], workloads.PAPER_DIPOLE_N,
+                                     workloads.PAPER_DIPOLE_M, sigma)
+    r = np.sqrt(sum((X[i] - x0[i]) ** 2 for i in range(d)))
+    return {"coulomb3d": cf.coulomb3d_gaussian, "coulomb2d": cf.coulomb2d_gaussian,
+            "poisson2d": cf.poisson2d_gaussian}[kernel](r, sigma)
+
+
+# ---------------------------------------------------------------- paper tables
+
+def _golden_error_rows():
+    here = os.path.join(os.path.dirname(__file__), "golden", "paper_table_errors.csv")
+    return _rows(here)
+
+
+@pytest.mark.parametrize("row", _golden_error_rows(), ids=lambda r: f"{r['kernel']}-L{r['L']}-n{r['n']}")
+def test_paper_table_error(row):
+    kernel, L, n, sigma = row["kernel"], float(row["L"]), int(row["n"]), float(row["sigma"])
+    d = 3 if kernel.endswith("3d") else 2
+    x0 = [float(row["x0"]), float(row["y0"]), float(row["z0"])][:d]
+    eps = 1e-13 if kernel == "poisson2d" else 1e-14
+    dip = (workloads.PAPER_DIPOLE_N, workloads.PAPER_DIPOLE_M) if kernel == "dipolar3d" else None
+    plan = oracle.make_plan(kernel, d, n, L, eps=eps, dipole=dip)
+    rho = workloads.gaussian(n, L, d, sigma=sigma, center=x0)
+    E = relmax(oracle.evaluate(plan, rho), _exact(kernel, n, L, sigma, x0))
+    Ep = float(row["E_paper"])
+    if row["check"] == "rel":
+        assert abs(E - Ep) <= 0.01 * Ep, (E, Ep)
+    elif row["check"] == "rel5":
+        assert abs(E - Ep) <= 0.05 * Ep, (E, Ep)
+    elif row["check"] == "le":
+        assert E <= max(3 * Ep, 3e-15), (E, Ep)
+    else:
+        assert Ep / 10 <= E <= Ep * 10, (E, Ep)
+
+
+def test_paper_max_norms(golden_dir):
+    """Tables 3 and 5 print max|u|; the closed forms must reproduce them."""
+    for row in _rows(os.path.join(golden_dir, "paper_max_norms.csv")):
+        s, g, um = float(row["sigma"]), float(row["gamma"]), float(row["umax"])
+        v = cf.anisotropic3d_max(s, g) if row["kernel"] == "coulomb3d" else cf.anisotropic2d_max(s, g)
+        digits = len(row["umax"].replace("0.", "").replace(".", "").lstrip("0"))
+        assert abs(v - um) <= 0.6 * 10 ** (math.floor(math.log10(um)) - digits + 1), (row, v)
+
+
+def test_anisotropic_oracle_max_norm():
+    """Table 3, gamma = 1: the oracle's max|u| on [-12,12]^3 equals sigma^2/2 = 2."""
+    n, L = 48, 12.0
+    plan = oracle.make_plan("coulomb3d", 3, n, L)
+    u = oracle.evaluate(plan, workloads.gaussian(n, L, 3, sigma=2.0))
+    assert abs(np.max(np.abs(u)) - 2.0) < 1e-8
+
+
+def test_triaxial_closed_form_against_mpmath():
+    a = (1.0, 4.0, 16.0)
+    pts = [(0.0, 0.0, 0.0), (0.3, -0.7, 0.2), (2.0, 1.0, -1.5), (7.0, -3.0, 9.0)]
+    for p in pts:
+        v = cf.coulomb3d_triaxial(*[np.array([c]) for c in p], a=a)[0]
+        assert abs(v - cf.coulomb3d_triaxial_mp(*p, a=a)) < 1e-14 * max(1.0, abs(v))
+    # the isotropic case reduces to the erf form
+    r = math.sqrt(0.3 ** 2 + 0.7 ** 2 + 0.2 ** 2)
+    v = cf.coulomb3d_triaxial(np.array([0.3]), np.array([-0.7]), np.array([0.2]), a=(1, 1, 1))[0]
+    assert abs(v - cf.coulomb3d_gaussian(np.array([r]), 1.0)[0]) < 1e-14
+
+
+# ---------------------------------------------------------------- GS tables
+
+def test_coulomb_table_meets_eps_off_grid():
+    for d, dl in ((3, 1e-4), (2, 1e-3)):
+        w, tau, S = gs_table.coulomb_table(d, dl, 1e-14)
+        rng = np.random.default_rng(1)
+        r = np.exp(rng.uniform(math.log(dl), math.log(2 * math.sqrt(d)), 20000))
+        approx = np.sum(w[None, :] * np.exp(-(tau[None, :] * r[:, None]) ** 2), axis=1)
+        assert np.max(np.abs(1.0 - r * approx)) < 2e-14
+        assert len(w) == S + 1 and tau[0] == 0.0
+
+
+def test_coulomb_table_convergence_rate():
+    """Prop. 1: once the nodes cover the interval the error falls at least like
+    exp(-C S / ln S); and the chosen S is the smallest one meeting eps."""
+    Ss = (160, 200, 240)
+    errs = [gs_table.coulomb_error(S, 1e-4, 2 * math.sqrt(3)) for S in Ss]
+    x = [S / math.log(S) for S in Ss]
+    for i in range(2):
+        assert math.log(errs[i] / errs[i + 1]) / (x[i + 1] - x[i]) > 1.0, errs
+    w, tau, S = gs_table.coulomb_table(3, 1e-4, 1e-14)
+    assert gs_table.coulomb_error(S, 1e-4, 2 * math.sqrt(3)) <= 1e-14
+    assert gs_table.coulomb_error(S - 1, 1e-4, 2 * math.sqrt(3)) > 1e-14
+
+
+def test_poisson_table_meets_eps():
+    dl, eps = 1e-3, 1e-13
+    C0, wh, s, S = gs_table.poisson_table(dl, eps)
+    X = 2 * math.sqrt(2) / dl
+    rng = np.random.default_rng(2)
+    x = np.exp(rng.uniform(0.0, math.log(X), 20000))
+    approx = C0 - np.sum(wh[None, :] * np.exp(-s[None, :] * x[:, None] ** 2), axis=1)
+    assert np.max(np.abs(np.log(x) - approx)) < 2 * eps
+
+
+def test_physical_tables_reproduce_kernels():
+    rng = np.random.default_rng(3)
+    for kernel, d, eps in (("coulomb3d", 3, 1e-14), ("coulomb2d", 2, 1e-14), ("poisson2d", 2, 1e-13)):
+        L = 7.0
+        t = gs_table.physical_table(kernel, d, L, eps)
+        r = np.exp(rng.uniform(math.log(t.delta), math.log(2 * math.sqrt(d) * L), 5000))
+        ugs = np.sum(t.w[None, :] * np.exp(-(t.tau[None, :] * r[:, None]) ** 2), axis=1)
+        if kernel == "coulomb3d":
+            ex = 1 / (4 * math.pi * r)
+            assert np.max(np.abs(ugs / ex - 1)) < 2e-14
+        elif kernel == "coulomb2d":
+            ex = 1 / (2 * math.pi * r)
+            assert np.max(np.abs(ugs / ex - 1)) < 2e-14
+        else:
+            ex = -np.log(r) / (2 * math.pi)
+            assert np.max(np.abs(ugs - ex)) < 3 * eps / (2 * math.pi) + 1e-15 * np.max(np.abs(ex))
+
+
+# ---------------------------------------------------------------- 1-D factors
+
+@pytest.mark.parametrize("L,n", [(8.0, 32), (10.0, 256)])
+def test_factors_against_erf_closed_form(L, n):
+    c = 2 * L
+    taus = np.array([0.0, 1e-4, 0.003, 0.02, 0.1, 0.3, 0.6 / L * 5, 6.4 / c, 6.6 / c, 5.0, 300.0])
+    F = factor_1d(taus, c, n)
+    ks = sorted({0, 1, 2, 7, n // 3, n // 2, n - 1, n})
+    for q, t in enumerate(taus):
+        for k in ks:
+            ref = cf.factor_mp(float(t), c, k)
+            assert abs(F[k, q] - ref) <= 4e-16 * 2 * c, (t, k, F[k, q], ref)
+
+
+def test_factor_special_values():
+    c, n = 16.0, 64
+    F = factor_1d(np.array([0.0, 0.05, 2.0]), c, n)
+    assert F[0, 0] == 2 * c and np.all(F[1:, 0] == 0.0)
+    assert abs(F[0, 1] - math.sqrt(math.pi) * math.erf(0.05 * c) / 0.05) < 1e-15 * 2 * c
+    xi = math.pi * np.arange(n + 1) / c
+    assert np.allclose(F[:, 2], math.sqrt(math.pi) / 2.0 * np.exp(-xi ** 2 / 16.0), rtol=0, atol=1e-18)
+
+
+# ---------------------------------------------------------------- Taylor constants
+
+def _u_of(kernel, r):
+    if kernel == "coulomb3d":
+        return 1 / (4 * mp.pi * r)
+    if kernel == "coulomb2d":
+        return 1 / (2 * mp.pi * r)
+    return -mp.log(r) / (2 * mp.pi)
+
+
+@pytest.mark.parametrize("kernel,d", [("coulomb3d", 3), ("coulomb2d", 2), ("poisson2d", 2)])
+def test_taylor_constants_against_quadrature(kernel, d):
+    """A0, c2 against a direct quadrature of int_0^delta r^m (U - U_GS) dr."""
+    t = gs_table.physical_table(kernel, d, 9.0, 1e-13, delta_rel=1e-3)
+    A0, c2 = taylor_constants(kernel, d, t.delta, t.w, t.tau)
+    with mp.workdps(30):
+        area = 2 * mp.pi ** (mp.mpf(d) / 2) / mp.gamma(mp.mpf(d) / 2)
+        ws = [mp.mpf(float(x)) for x in t.w]
+        ts = [mp.mpf(float(x)) for x in t.tau]
+
+        def diff(r):
+            return _u_of(kernel, r) - mp.fsum(wq * mp.exp(-(tq * r) ** 2) for wq, tq in zip(ws, ts))
+        pts = [0] + [t.delta * 10 ** (-k) for k in range(8, 0, -1)] + [t.delta]
+        q0 = area * mp.quad(lambda r: r ** (d - 1) * diff(r), pts)
+        q2 = area * mp.quad(lambda r: r ** (d + 1) * diff(r), pts) / (2 * d)
+    assert abs(A0 - float(q0)) <= 1e-12 * abs(float(q0))
+    assert abs(c2 - float(q2)) <= 1e-12 * abs(float(q2))
+
+
+def test_taylor_correction_exact_for_cubic_density():
+    """For a cubic polynomial density the ball integral of (U - U_GS) rho(x - y)
+    equals A0 rho(x) + c2 Lap rho(x) exactly (odd and mixed terms vanish)."""
+    kernel, d = "coulomb3d", 3
+    t = gs_table.physical_table(kernel, d, 1.0, 1e-12, delta_rel=0.05)
+    A0, c2 = taylor_constants(kernel, d, t.delta, t.w, t.tau)
+    dl = t.delta
+    # rho(z) = 1 + 2 z1 - z2^2 + 3 z1 z3 + z3^2 + z1^3, at x = 0: rho = 1, Lap = 0 (-2 + 2)+6 z1 = 0
+    # use rho(z) = 1 + z1 + 2 z1^2 + z2^2 - z3^2/2 + z1 z2 + z2^3: Lap(0) = 4 + 2 - 1 = 5
+    with mp.workdps(25):
+        ws = [mp.mpf(float(x)) for x in t.w]
+        ts = [mp.mpf(float(x)) for x in t.tau]
+
+        def radial(r):
+            return 1 / (4 * mp.pi * r) - mp.fsum(wq * mp.exp(-(tq * r) ** 2) for wq, tq in zip(ws, ts))
+
+        def rho_m(y1, y2, y3):      # rho(x - y) at x = 0
+            z1, z2, z3 = -y1, -y2, -y3
+            return 1 + z1 + 2 * z1 ** 2 + z2 ** 2 - z3 ** 2 / 2 + z1 * z2 + z2 ** 3
+
+        # angular average of rho(-r omega) for the polynomial: 1 + r^2 (2 + 1 - 1/2)/3
+        def integrand(r):
+            ang = 4 * mp.pi * (1 + r * r * (mp.mpf(2) + 1 - mp.mpf(1) / 2) / 3)
+            return r * r * radial(r) * ang
+        val = mp.quad(integrand, [0, dl * 1e-6, dl * 1e-3, dl])
+    assert abs(float(val) - (A0 * 1.0 + c2 * 5.0)) <= 1e-12 * abs(float(val))
+
+
+# ---------------------------------------------------------------- transforms
+
+def test_separable_dft_equals_full_dft():
+    rng = np.random.default_rng(4)
+    for shape in ((4, 4, 4), (6, 6), (5, 5, 5)):
+        x = rng.standard_normal(shape)
+        assert relmax(dft.forward(x), dft.full_dft(x)) < 1e-13
+        assert relmax(dft.forward(x, sign=+1), dft.full_dft(x, sign=+1)) < 1e-13
+
+
+def test_operator_is_aperiodic_toeplitz_convolution():
+    """u_i = sum_j K[i - j] rho_j with K from the inverse transform of the
+    spectrum: no wrap-around, independent of the grid origin."""
+    rng = np.random.default_rng(5)
+    for kernel, d, n in (("coulomb2d", 2, 6), ("coulomb3d", 3, 4), ("poisson2d", 2, 5)):
+        L = 3.0
+        plan = oracle.make_plan(kernel, d, n, L, eps=1e-13)
+        M = plan.M
+        Shat = oracle.full_spectrum(plan) + plan.A0 - plan.c2 * oracle.laplacian_symbol(plan)
+        # K[m] for m in Z_{2n}^d from a plain full inverse DFT of the spectrum
+        K = np.real(np.fft.ifftn(Shat)) * (M / M)   # numpy's ifftn divides by M already
+        rho = rng.standard_normal((n,) * d)
+        u = np.zeros_like(rho)
+        idx = list(np.ndindex(*rho.shape))
+        for i in idx:
+            s = 0.0
+            for j in idx:
+                m = tuple((a - b) % (2 * n) for a, b in zip(i, j))
+                s += K[m] * rho[j]
+            u[i] = s
+        assert relmax(oracle.evaluate(plan, rho), u) < 1e-12
+
+
+def test_linearity_reversal_permutation_translation():
+    rng = np.random.default_rng(6)
+    n, L = 16, 4.0
+    plan = oracle.make_plan("coulomb3d", 3, n, L)
+    a = rng.standard_normal((n, n, n))
+    b = rng.standard_normal((n, n, n))
+    ua, ub = oracle.evaluate(plan, a), oracle.evaluate(plan, b)
+    assert relmax(oracle.evaluate(plan, 2 * a - 3 * b), 2 * ua - 3 * ub) < 1e-13
+    assert relmax(oracle.evaluate(plan, a[::-1, :, ::-1].copy()), ua[::-1, :, ::-1]) < 1e-13
+    assert relmax(oracle.evaluate(plan, np.transpose(a, (2, 0, 1)).copy()), np.transpose(ua, (2, 0, 1))) < 1e-13
+    # translation by 3 points along y of a density supported away from the edge
+    c = np.zeros((n, n, n))
+    c[3:9, 2:8, 4:12] = rng.standard_normal((6, 6, 8))
+    cs = np.roll(c, 3, axis=1)
+    u_c, u_cs = oracle.evaluate(plan, c), oracle.evaluate(plan, cs)
+    assert relmax(u_cs[:, 3:, :], u_c[:, :-3, :]) < 1e-13
+
+
+@pytest.mark.parametrize("kernel,d", [("coulomb3d", 3), ("coulomb2d", 2), ("poisson2d", 2)])
+def test_box_scaling_covariance(kernel, d):
+    """u_{sL}(s x) = s^{d-1} u_L(x) for Coulomb; s^2 [u_L(x) - ln(s)/(2pi) int rho] for Poisson."""
+    rng = np.random.default_rng(7)
+    n, L, s = 12, 3.0, 2.0
+    rho = rng.standard_normal((n,) * d)
+    eps = 1e-13 if kernel == "poisson2d" else 1e-14
+    u1 = oracle.evaluate(oracle.make_plan(kernel, d, n, L, eps=eps), rho)
+    u2 = oracle.evaluate(oracle.make_plan(kernel, d, n, s * L, eps=eps), rho)
+    if kernel == "poisson2d":
+        h = 2 * L / n
+        ref = s ** 2 * (u1 - math.log(s) / (2 * math.pi) * h ** 2 * rho.sum())
+    else:
+        ref = s ** (d - 1) * u1
+    assert relmax(u2, ref) < 1e-13
+
+
+def test_tau_zero_term_is_a_constant():
+    n, L, w0 = 10, 2.5, 0.37
+    rng = np.random.default_rng(8)
+    rho = rng.standard_normal((n, n))
+    plan = oracle.make_plan("gaussian_sum", 2, n, L, custom=([w0], [0.0]))
+    u = oracle.evaluate(plan, rho)
+    h = 2 * L / n
+    assert np.max(np.abs(u - w0 * h * h * rho.sum())) < 1e-14 * abs(w0 * h * h * rho.sum()) + 1e-15
+
+
+def test_single_gaussian_kernel_gives_textbook_convolution():
+    """U = exp(-tau^2 r^2) (no Taylor term) applied to exp(-a|x|^2): the product of
+    the one-dimensional Gaussian convolutions sqrt(pi/(tau^2+a)) exp(-tau^2 a x^2/(tau^2+a))."""
+    n, L, tau, a = 48, 6.0, 1.3, 2.0
+    plan = oracle.make_plan("gaussian_sum", 3, n, L, custom=([1.0], [tau]))
+    rho = workloads.gaussian(n, L, 3, sigma=1 / math.sqrt(a))
+    X = workloads.mesh(n, L, 3)
+    ex = 1.0
+    for xi in X:
+        ex = ex * math.sqrt(math.pi / (tau * tau + a)) * np.exp(-tau * tau * a * xi * xi / (tau * tau + a))
+    assert relmax(oracle.evaluate(plan, rho), ex) < 1e-14
+
+
+def test_spectral_laplacian_accuracy():
+    n, L, sg = 64, 8.0, 1.5
+    plan = oracle.make_plan("gaussian_sum", 3, n, L, custom=([0.0], [1.0]))
+    rho = workloads.gaussian(n, L, 3, sigma=sg)
+    lap = dft.inverse(-oracle.laplacian_symbol(plan) * dft.forward(rho)).real / plan.M
+    X = workloads.mesh(n, L, 3)
+    r2 = sum(x * x for x in X)
+    ex = (4 * r2 / sg ** 4 - 6 / sg ** 2) * np.exp(-r2 / sg ** 2)
+    # spectral differentiation amplifies rounding by |xi|_max^2 ~ 500 here
+    assert relmax(lap, ex) < 1e-10
+
+
+def test_each_taylor_term_is_needed():
+    """With delta = 1e-3 L both correction terms are visible: dropping c2 Lap rho
+    leaves ~1e-12, dropping A0 rho as well ~1e-6; with both the error is at roundoff."""
+    n, L, sg = 64, 8.0, 1.2
+    rho = workloads.gaussian(n, L, 3, sigma=sg)
+    X = workloads.mesh(n, L, 3)
+    ex = cf.coulomb3d_gaussian(np.sqrt(sum(x * x for x in X)), sg)
+    plan = oracle.make_plan("coulomb3d", 3, n, L, eps=1e-14, delta_rel=1e-3)
+    e_full = relmax(oracle.evaluate(plan, rho), ex)
+    plan.c2 = 0.0
+    e_noc2 = relmax(oracle.evaluate(plan, rho), ex)
+    plan.A0 = 0.0
+    e_none = relmax(oracle.evaluate(plan, rho), ex)
+    assert e_full < 2e-15 and e_noc2 > 1e-13 and e_none > 1e-7, (e_full, e_noc2, e_none)
+
+
+# ---------------------------------------------------------------- adjoint / energy
+
+@pytest.mark.parametrize("kernel,d", [("coulomb3d", 3), ("poisson2d", 2), ("dipolar3d", 3)])
+def test_adjoint_dot_and_symmetry(kernel, d):
+    rng = np.random.default_rng(9)
+    n, L = 10, 3.0
+    dip = ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8)) if kernel == "dipolar3d" else None
+    plan = oracle.make_plan(kernel, d, n, L, eps=1e-13, dipole=dip)
+    r, v = rng.standard_normal((2,) + (n,) * d)
+    Ar, Atv = oracle.evaluate(plan, r), oracle.adjoint(plan, v)
+    lhs, rhs = float(np.sum(Ar * v)), float(np.sum(r * Atv))
+    assert abs(lhs - rhs) <= 1e-14 * np.sqrt(np.sum(Ar ** 2) * np.sum(v ** 2))
+    assert relmax(Atv, oracle.evaluate(plan, v)) < 1e-13      # the kernel is even
+
+
+def test_mixture_energy_matches_closed_form():
+    rng = np.random.default_rng(10)
+    mix = workloads.draw_mixture(rng, 4, 3, mu_range=1.5, sigma_range=(1.0, 1.6))
+    n, L = 64, 10.0
+    plan = oracle.make_plan("coulomb3d", 3, n, L)
+    rho = workloads.sample_mixture(mix, n, L)
+    E = oracle.energy(plan, rho)
+    Eex = cf.mixture_energy_coulomb3d(mix.a, mix.mu, mix.sigma)
+    assert abs(E - Eex) < 1e-9 * abs(Eex)
+
+
+def test_coulomb_energy_is_positive():
+    rng = np.random.default_rng(11)
+    n, L = 16, 4.0
+    plan = oracle.make_plan("coulomb3d", 3, n, L)
+    for _ in range(3):
+        rho = rng.standard_normal((n, n, n))
+        assert oracle.energy(plan, rho) > 0.0
+
+
+def test_dipolar_seeded_vectors_against_closed_form():
+    p = workloads.config3_dipolar(n=64)
+    plan = oracle.make_plan("dipolar3d", 3, p.n, p.L, dipole=(p.extra["n"], p.extra["m"]))
+    X = workloads.mesh(p.n, p.L, 3)
+    ex = cf.dipolar3d_gaussian(X[0], X[1], X[2], p.extra["n"], p.extra["m"], 1.2)
+    assert relmax(oracle.evaluate(plan, p.rho), ex) < 1e-13
+
+
+def test_dipolar_closed_form_against_mpmath_hessian():
+    """The dipolar closed form (series near 0, Hessian formula elsewhere) against a
+    high-precision numerical Hessian of the erf potential."""
+    nv, mv, sg = (0.6, 0.8, 0.0), (0.0, 0.6, 0.8), 1.2
+    with mp.workdps(40):
+        s = mp.mpf(sg)
+
+        def phi(a, b, c):
+            r = mp.sqrt(a * a + b * b + c * c)
+            return s ** 3 * mp.sqrt(mp.pi) * mp.erf(r / s) / (4 * r)
+        for r in (0.1, 0.359, 0.361, 1.0, 3.0):
+            x = [mp.mpf(r) / mp.sqrt(3)] * 3
+            x[1] = -x[1]
+            H = [[mp.diff(phi, tuple(x), tuple(int(k == i) + int(k == j) for k in range(3)))
+                  for j in range(3)] for i in range(3)]
+            nm = sum(a * b for a, b in zip(nv, mv))
+            ref = -nm * mp.exp(-(r * r) / s ** 2) - 3 * sum(nv[i] * H[i][j] * mv[j] for i in range(3) for j in range(3))
+            v = cf.dipolar3d_gaussian(np.array([float(x[0])]), np.array([float(x[1])]),
+                                      np.array([float(x[2])]), nv, mv, sg)[0]
+            assert abs(v - float(ref)) < 1e-13, (r, v, float(ref))
+    # u(0) = 0: D(0) = -I/3
+    z = cf.dipolar3d_gaussian(np.zeros(1), np.zeros(1), np.zeros(1), nv, mv, 1.2)
+    assert abs(z[0]) < 1e-15

@@ -1,0 +1,191 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module only draws random parameters and samples densities on grids.  It
+holds none of the potential-evaluation arithmetic: neither the oracle nor the
+GPU library imports anything from here, and nothing here imports either of them.
+
+Grid convention (one axis): ``x_j = -L + j*h`` with ``h = 2L/n`` and
+``j = 0..n-1``.  Arrays are C-ordered ``[z][y][x]`` (3D) or ``[y][x]`` (2D), with
+x the last, fastest-varying index.
+
+Workloads follow the experiments of the paper (Section 4): Gaussian densities,
+shifted and anisotropic Gaussians, and Gaussian mixtures on cubic boxes.
+Random draws use ``numpy.random.default_rng(150104438 + config_id)``.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 150104438
+
+# Dipole orientations printed with the dipolar example (Section 4, Example 4.4).
+PAPER_DIPOLE_N = (0.82778, 0.41505, -0.37751)
+PAPER_DIPOLE_M = (0.3118, 0.9378, -0.15214)
+
+
+def axis(n: int, L: float) -> np.ndarray:
+    """Grid points of one axis: ``-L + j*2L/n`` for ``j = 0..n-1``."""
+    return -L + (2.0 * L / n) * np.arange(n, dtype=np.float64)
+
+
+def mesh(n: int, L: float, d: int):
+    """Coordinate arrays (x, y[, z]) broadcastable to the ``[z][y][x]`` grid."""
+    a = axis(n, L)
+    if d == 2:
+        return a[None, :], a[:, None]
+    if d == 3:
+        return a[None, None, :], a[None, :, None], a[:, None, None]
+    raise ValueError("d must be 2 or 3")
+
+
+@dataclass
+class Mixture:
+    """Gaussian mixture ``rho(x) = sum_c a_c exp(-|x - mu_c|^2 / sigma_c^2)``."""
+
+    a: np.ndarray        # (K,)
+    mu: np.ndarray       # (K, d), columns ordered (x, y[, z])
+    sigma: np.ndarray    # (K,)
+
+    @property
+    def d(self) -> int:
+        return self.mu.shape[1]
+
+
+def draw_mixture(rng: np.random.Generator, K: int, d: int, mu_range: float = 2.0,
+                 sigma_range=(0.5, 2.0)) -> Mixture:
+    """Draw sigma ~ U[0.5, 2], a ~ U(-1, 1), mu ~ U[-2, 2]^d, in that order."""
+    sigma = rng.uniform(sigma_range[0], sigma_range[1], K)
+    a = rng.uniform(-1.0, 1.0, K)
+    mu = rng.uniform(-mu_range, mu_range, (K, d))
+    return Mixture(a=a, mu=mu, sigma=sigma)
+
+
+def sample_mixture(m: Mixture, n: int, L: float) -> np.ndarray:
+    d = m.d
+    X = mesh(n, L, d)
+    out = np.zeros((n,) * d)
+    for c in range(len(m.a)):
+        r2 = sum((X[i] - m.mu[c, i]) ** 2 for i in range(d))
+        out += m.a[c] * np.exp(-r2 / m.sigma[c] ** 2)
+    return out
+
+
+def gaussian(n: int, L: float, d: int, sigma: float = 1.0, center=None,
+             gammas=None, scale: float = 1.0) -> np.ndarray:
+    """``scale * exp(-sum_i gamma_i^2 (x_i - c_i)^2 / sigma^2)`` on the grid."""
+    X = mesh(n, L, d)
+    center = np.zeros(d) if center is None else np.asarray(center, float)
+    gammas = np.ones(d) if gammas is None else np.asarray(gammas, float)
+    r2 = sum((gammas[i] * (X[i] - center[i])) ** 2 for i in range(d))
+    return scale * np.exp(-r2 / sigma ** 2)
+
+
+# --------------------------------------------------------------------------
+# The benchmark configurations.
+# --------------------------------------------------------------------------
+
+@dataclass
+class Problem:
+    kernel: str          # "coulomb3d" | "coulomb2d" | "poisson2d" | "dipolar3d"
+    d: int
+    n: int
+    L: float
+    rho: np.ndarray
+    mixture: Mixture | None = None
+    extra: dict = field(default_factory=dict)
+
+
+def config1(n: int = 32) -> Problem:
+    """3D Coulomb, normalised isotropic Gaussian exp(-|x|^2)/pi^(3/2) on [-8,8]^3."""
+    rho = gaussian(n, 8.0, 3, sigma=1.0, scale=math.pi ** -1.5)
+    return Problem("coulomb3d", 3, n, 8.0, rho)
+
+
+def config2_mixture() -> Mixture:
+    rng = np.random.default_rng(SEED_BASE + 2)
+    return draw_mixture(rng, 8, 3)
+
+
+def config2(n: int = 256) -> Problem:
+    """3D Coulomb on [-10,10]^3: triaxial Gaussian exp(-(x^2+4y^2+16z^2)) plus an
+    8-component seeded mixture (sigma in [0.5,2], a in (-1,1), mu in [-2,2]^3)."""
+    L = 10.0
+    mix = config2_mixture()
+    rho = gaussian(n, L, 3, sigma=1.0, gammas=(1.0, 2.0, 4.0)) + sample_mixture(mix, n, L)
+    return Problem("coulomb3d", 3, n, L, rho, mixture=mix,
+                   extra={"triaxial_a": (1.0, 4.0, 16.0)})
+
+
+def config3_mixture() -> Mixture:
+    rng = np.random.default_rng(SEED_BASE + 3)
+    return draw_mixture(rng, 16, 2)
+
+
+def config3_2d(kernel: str, n: int = 1024) -> Problem:
+    """2D Poisson or 2D Coulomb of a seeded 16-Gaussian mixture on [-12,12]^2."""
+    assert kernel in ("poisson2d", "coulomb2d")
+    L = 12.0
+    mix = config3_mixture()
+    return Problem(kernel, 2, n, L, sample_mixture(mix, n, L), mixture=mix)
+
+
+def config3_dipoles():
+    """Seeded unit dipole orientations (normalised standard-normal draws)."""
+    rng = np.random.default_rng(SEED_BASE + 33)
+    v = rng.standard_normal((2, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return tuple(v[0]), tuple(v[1])
+
+
+def config3_dipolar(n: int = 128, paper_vectors: bool = False) -> Problem:
+    """3D dipolar potential of exp(-|x|^2/1.44) on [-8,8]^3 (the density of the
+    dipolar example, sigma = 1.2)."""
+    if paper_vectors:
+        dn, dm = PAPER_DIPOLE_N, PAPER_DIPOLE_M
+    else:
+        dn, dm = config3_dipoles()
+    rho = gaussian(n, 8.0, 3, sigma=1.2)
+    return Problem("dipolar3d", 3, n, 8.0, rho, extra={"n": dn, "m": dm, "sigma": 1.2})
+
+
+BATCH_SIZES = (32, 48, 64, 96, 128)
+
+
+def config4(count: int = 64) -> list[Problem]:
+    """Batch of seeded mixtures (4..32 components) on grids drawn from
+    {32,48,64,96,128}^3, box [-10,10]^3, 3D Coulomb."""
+    rng = np.random.default_rng(SEED_BASE + 4)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(BATCH_SIZES))
+        K = int(rng.integers(4, 33))
+        mix = draw_mixture(rng, K, 3)
+        out.append(Problem("coulomb3d", 3, n, 10.0, None, mixture=mix))
+    return out
+
+
+def materialise(p: Problem) -> Problem:
+    if p.rho is None:
+        p.rho = sample_mixture(p.mixture, p.n, p.L)
+    return p
+
+
+def config5_mixture() -> Mixture:
+    """The 8-component mixture of the differentiation workload (same draws as
+    the headline mixture, without the triaxial term)."""
+    return config2_mixture()
+
+
+def config5(n: int = 256) -> Problem:
+    L = 10.0
+    mix = config5_mixture()
+    return Problem("coulomb3d", 3, n, L, sample_mixture(mix, n, L), mixture=mix)
+
+
+def random_field(rng: np.random.Generator, shape, smooth: bool = False) -> np.ndarray:
+    """Plain random grid data for operator-level checks (linearity, adjoint)."""
+    return rng.standard_normal(shape)
