@@ -1,0 +1,195 @@
+/*
+ * gs.h -- C ABI of the Gaussian-sum nonlocal potential library for AMD MI355X.
+ *
+ * The library evaluates u = U * rho (convolution over R^d, free-space
+ * boundary conditions) for a density rho sampled on a uniform grid over the
+ * box [-L, L]^d, with the method of Exl, Mauser and Zhang, "Accurate and
+ * efficient computation of nonlocal potentials based on Gaussian-sum
+ * approximation": the kernel is split as U = U_GS + (U - U_GS) (Section 2.1,
+ * eqs. (key_form), (GS-Gene)); the regular part is a zero-padded aperiodic FFT
+ * convolution with the tensor-product kernel coefficients (Section 2.2,
+ * eqs. (I1FFT), (tensor)); the near-field part is the Taylor correction
+ * A0 rho + c2 Lap(rho) (Section 2.3, eq. (taylor)).  The precomputation /
+ * evaluation split of Algorithm 1 is the plan / eval split below.
+ *
+ * Conventions shared by every entry point
+ *   - Grids are cubic: n points per axis, box [-L, L]^d, spacing h = 2L/n,
+ *     sample j on an axis at x_j = -L + j h, j = 0..n-1.
+ *   - Arrays are dense, C-ordered FP64: [z][y][x] in 3D, [y][x] in 2D, x the
+ *     last (fastest) index.  `n` and `L` arguments are arrays of length d in
+ *     that same order; all entries must currently be equal.
+ *   - Device pointers are HIP device memory on the plan's device, owned by the
+ *     caller, and must stay valid until the work queued on the plan's stream
+ *     has completed.  Calls are asynchronous with respect to the host.
+ *   - Status codes only; nothing is thrown across the ABI.  Arguments are
+ *     validated before any device work; on a synchronous error the outputs
+ *     are untouched.  Asynchronous HIP failures surface as GS_ERR_HIP on a
+ *     later call.  gs_last_error() returns a thread-local message.
+ *   - A plan is used by one stream at a time.  Plans are independent: several
+ *     plans may run concurrently on different streams.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gs_plan_s* gs_plan;
+
+/* Kernel families (Section 1, eq. (kernelPhy); dipolar kernel, Section 2.4). */
+typedef enum {
+    GS_COULOMB_3D = 0,    /* U = 1/(4 pi |x|),                       d = 3 */
+    GS_COULOMB_2D = 1,    /* U = 1/(2 pi |x|),                       d = 2 */
+    GS_POISSON_2D = 2,    /* U = -ln|x| / (2 pi),                    d = 2 */
+    GS_DIPOLAR_3D = 3,    /* u = -(n.m) rho - 3 Coulomb3D(d_n d_m rho), d = 3 */
+    GS_GAUSSIAN_SUM = 4   /* U = sum_q w_q exp(-tau_q^2 |x|^2) from gs_options,
+                             no near-field term (test hook), d = 2 or 3 */
+} gs_kernel;
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARG = 1,       /* bad d, n, L, eps, pointer, count, option */
+    GS_ERR_UNSUPPORTED_SIZE = 2,  /* n not in the compiled size list          */
+    GS_ERR_ACCURACY = 3,          /* eps not reachable by the sinc table      */
+    GS_ERR_OUT_OF_MEMORY = 4,     /* device allocation failed or over the cap */
+    GS_ERR_NO_DEVICE = 5,         /* no HIP device visible                    */
+    GS_ERR_HIP = 6                /* a HIP runtime call failed                */
+} gs_status;
+
+/* Plan flags. */
+#define GS_PLAN_HOST_ONLY      1  /* tables, factors, constants and a host-assembled
+                                     spectrum only; no device memory, no device
+                                     calls (gs_eval* return GS_ERR_INVALID_ARG) */
+#define GS_PLAN_HOST_ASSEMBLY  2  /* assemble the spectrum on the host and upload it
+                                     instead of the MFMA assembly kernel */
+
+typedef struct {
+    double delta_rel;        /* near-field radius delta / L; 0 selects 1e-4      */
+    double dipole_n[3];      /* GS_DIPOLAR_3D: orientations (x, y, z), non-zero; used as given */
+    double dipole_m[3];
+    const double* gs_w;      /* GS_GAUSSIAN_SUM: weights w_q (host), length gs_q  */
+    const double* gs_tau;    /* GS_GAUSSIAN_SUM: exponents tau_q >= 0 (host)      */
+    int gs_q;
+    void* stream;            /* hipStream_t for all work of the plan; NULL = null stream */
+    int device;              /* HIP device ordinal; -1 = the current device       */
+    int flags;               /* GS_PLAN_* bits                                    */
+} gs_options;
+
+typedef struct {
+    int kernel, d;
+    int64_t n;
+    double L, eps, delta;    /* delta in physical units                          */
+    int S;                   /* sinc truncation: 1/r tables have S+1 terms       */
+    int Q;                   /* number of Gaussians in the table (incl. tau = 0) */
+    double A0, c2;           /* Taylor constants of eq. (taylor)                   */
+    size_t spectrum_bytes;   /* stored spectrum octant (n+1)^d FP64              */
+    size_t workspace_bytes;  /* per-plan device workspace                        */
+    double assembly_ms;      /* device time of the spectrum assembly (0 if host) */
+    double assembly_gflop;   /* 2 Q (n+1)^d, the contraction's algorithmic flops */
+    int host_only;
+} gs_plan_info;
+
+/* Fill `opt` with the defaults (delta_rel 1e-4, null stream, device -1). */
+void gs_options_default(gs_options* opt);
+
+/*
+ * Precomputation (Algorithm 1, "Precomputation"): Gaussian-sum table by sinc
+ * quadrature with the smallest S meeting `eps` on [delta, 2 sqrt(d)] in box
+ * units (Section 3; relative error of 1/r, absolute error of ln r), the
+ * one-dimensional factor integrals of eq. (tensor) at the padded frequencies
+ * pi k/(2L), k = 0..n, the Taylor constants A0, c2 (Section 2.3), and the
+ * stored spectrum octant
+ *     S[k] = ( sum_q w_q prod_j g_q(xi_kj) + A0 - c2 |xi_k|^2 ) / (2n)^d,
+ * assembled on the device by an FP64 matrix-core contraction.  Allocates the
+ * spectrum and the evaluation workspace on the device.
+ *   out     receives the plan (NULL on error).
+ *   k, d    kernel family and dimension (2 or 3).
+ *   n, L    length-d arrays, [z][y][x] order; equal entries; L > 0.
+ *   eps     target accuracy of the Gaussian sum (1e-15 <= eps < 1).
+ *   opt     NULL for defaults.
+ * Errors: INVALID_ARG, UNSUPPORTED_SIZE, ACCURACY, OUT_OF_MEMORY, NO_DEVICE, HIP.
+ * The environment variable GS_MAX_WORKSPACE_BYTES caps the device bytes a plan
+ * may allocate (OUT_OF_MEMORY beyond it).
+ */
+gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n,
+                         const double* L, double eps, const gs_options* opt);
+
+/* Frees the plan and its device memory (synchronises its stream).  NULL is a no-op. */
+gs_status gs_plan_destroy(gs_plan p);
+
+gs_status gs_plan_query(gs_plan p, gs_plan_info* info);
+
+/* Copies the Gaussian-sum table (physical units) into w[0..Q-1], tau[0..Q-1]. */
+gs_status gs_plan_table(gs_plan p, double* w, double* tau, int capacity);
+
+/* Copies the factor matrix F[k][q] = g_q(pi k/(2L)), k = 0..n, row-major (n+1) x Q. */
+gs_status gs_plan_factors(gs_plan p, double* F, size_t capacity);
+
+/* Copies the stored spectrum octant ((n+1)^d FP64, scaled by 1/(2n)^d) to host
+ * memory: from the device for device plans, the host assembly otherwise. */
+gs_status gs_plan_spectrum(gs_plan p, double* host_out, size_t capacity);
+
+/* Sets the HIP stream used by later calls on this plan (NULL = null stream). */
+gs_status gs_plan_set_stream(gs_plan p, void* stream);
+
+/*
+ * Evaluation (Algorithm 1, "Actual computation"): u = I1 + A0 rho + c2 Lap rho
+ * as one pruned, zero-padded FFT convolution with the stored spectrum, five
+ * kernel launches in 3D (x-R2C, y-forward, fused z forward * spectrum *
+ * inverse, y-inverse, x-C2R) and three in 2D.  rho and u are device arrays of
+ * n^d FP64; u may alias rho.  The padding never touches memory.
+ */
+gs_status gs_eval(gs_plan p, const double* rho_dev, double* u_dev);
+
+/*
+ * Adjoint of gs_eval: grad_rho = A^T grad_u, the transposed chain (crop and
+ * zero-padding exchanged, transform signs flipped).  The discrete operator is
+ * a symmetric Toeplitz matrix because every kernel here is even, so the
+ * transposed chain runs the same passes.  Used by autograd: for the energy
+ * E = 1/2 h^d sum rho u, dE/drho = h^d u.
+ */
+gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho_dev);
+
+/*
+ * Batched evaluation of `count` independent problems (each with its own plan,
+ * possibly of different sizes) in one persistent launch.  plans must be
+ * distinct device plans on one device; the first plan's stream is used.
+ * rho[i], u[i] are device arrays of plans[i]'s shape.
+ */
+gs_status gs_eval_batch(int count, const gs_plan* plans,
+                        const double* const* rho_dev, double* const* u_dev);
+
+/* Runs one pass of the evaluation chain on the plan's workspace (1 = x-R2C,
+ * 2 = y-forward, 3 = fused spectrum pass, 4 = y-inverse, 5 = x-C2R; 2D plans
+ * have passes 1, 3, 5).  rho_dev is read only by pass 1 and u_dev written only by
+ * pass 5.  For timing and profiling the passes separately; running 1..5 in order
+ * equals gs_eval. */
+gs_status gs_eval_pass(gs_plan p, const double* rho_dev, double* u_dev, int pass);
+
+/* Copies a plan buffer between the device and host memory, for testing the
+ * passes one at a time: which = 1 workspace X1 ((n+1) n^(d-1) complex, layout
+ * [z][kx][y] / [kx][y]), 2 workspace X2 (3D: 2n n (n+1) complex, [kx][ky][z]),
+ * 3 the stored spectrum octant ((n+1)^d FP64).  to_device = 0 reads into host,
+ * 1 writes from host.  count is in doubles and must equal the buffer size.
+ * Synchronises the plan's stream. */
+gs_status gs_plan_buffer(gs_plan p, int which, int to_device, double* host, size_t count);
+
+/* Human-readable status name, and the last error message of this thread. */
+const char* gs_status_string(gs_status s);
+const char* gs_last_error(void);
+
+/* Number of visible HIP devices (0 when there is none); never fails. */
+int gs_device_count(void);
+
+/* Sizes n for which kernels are compiled (ascending); returns the count. */
+int gs_supported_sizes(int d, int64_t* out, int capacity);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

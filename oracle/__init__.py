@@ -3,10 +3,10 @@
 TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, FP64 CPU
 implementation of the method, written from the paper: the Gaussian-sum table
 from sinc quadrature (Section 3), the one-dimensional factor integrals of the
-tensor-product kernel coefficients (Section 2.2, eq. (2.13)), the zero-padded
+tensor-product kernel coefficients (Section 2.2, eq. (tensor)), the zero-padded
 trigonometric (trapezoidal) Fourier coefficients of the density (eqs.
-(2.10)-(2.11)), the regular integral by the inverse transform (eq. (2.12)), and
-the Taylor near-field correction (Section 2.3, eq. (2.19)), summed as in
+(FourSeriB3), (rho_hat)), the regular integral by the inverse transform (eq. (I1FFT)), and
+the Taylor near-field correction (Section 2.3, eq. (taylor)), summed as in
 Algorithm 1.  Transforms are separable naive DFTs (dense per-axis DFT matrices
 applied by a BLAS matmul); there is no FFT factorisation anywhere.
 

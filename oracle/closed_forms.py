@@ -1,15 +1,15 @@
 """Exact potentials of Gaussian densities and other closed forms (Section 4).
 
 These are the checks the method must hit, independent of the method itself:
-  * 3D Coulomb of exp(-r^2/sigma^2): sigma^3 sqrt(pi) erf(r/sigma)/(4 r)      (eq. (4.2))
+  * 3D Coulomb of exp(-r^2/sigma^2): sigma^3 sqrt(pi) erf(r/sigma)/(4 r)      (eq. (DensGaus))
   * 3D Coulomb of exp(-sum a_i x_i^2) (any axis scales): the one-dimensional
     integral 1/2 int_0^inf prod_i (t^2+a_i)^(-1/2) exp(-a_i t^2 x_i^2/(t^2+a_i)) dt,
-    from the Gaussian integral of 1/r (eq. (3.6)) and Gaussian convolution;
-    a = (1, 1, gamma^2)/sigma^2 gives the anisotropic case of eq. (4.2).
+    from the Gaussian integral of 1/r (eq. (GauInte)) and Gaussian convolution;
+    a = (1, 1, gamma^2)/sigma^2 gives the anisotropic case of eq. (DensGaus).
   * 2D Coulomb of exp(-r^2/sigma^2): (sqrt(pi) sigma/2) I0(r^2/(2 sigma^2)) exp(-r^2/(2 sigma^2))
-  * 2D Coulomb of exp(-(x^2 + gamma^2 y^2)/sigma^2): the integral of eq. (4.3)
+  * 2D Coulomb of exp(-(x^2 + gamma^2 y^2)/sigma^2): the integral of eq. (2.5D-clb-exact)
   * 2D Poisson of exp(-r^2/sigma^2): -(sigma^2/4)[E1(r^2/sigma^2) + 2 ln r],
-    (sigma^2/4)(gamma_e - ln sigma^2) at r = 0                                 (eq. (4.4))
+    (sigma^2/4)(gamma_e - ln sigma^2) at r = 0                                 (eq. (eg-2d-Exact))
   * 3D dipolar of exp(-r^2/sigma^2): -(n.m) rho - 3 n^T D m with the Hessian D
     of the Coulomb potential (Example 4.4)
   * the 1-D factor integral in closed form, (sqrt(pi)/tau) exp(-xi^2/4tau^2)
@@ -93,7 +93,7 @@ def coulomb2d_gaussian(r, sigma: float = 1.0):
 
 
 def anisotropic2d_max(sigma: float, gamma: float) -> float:
-    """max |u| = u(0) for exp(-(x^2+gamma^2 y^2)/sigma^2) (eq. (4.3) at the origin)."""
+    """max |u| = u(0) for exp(-(x^2+gamma^2 y^2)/sigma^2) (eq. (2.5D-clb-exact) at the origin)."""
     with mp.workdps(30):
         g2 = mp.mpf(1) / mp.mpf(gamma) ** 2
         v = mp.quad(lambda t: 1 / (mp.sqrt(t * t + 1) * mp.sqrt(t * t + g2)), [0, 1, mp.inf])

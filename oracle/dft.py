@@ -1,7 +1,7 @@
-"""Separable naive DFTs on the zero-padded grid (Section 2.2, eqs. (2.10)-(2.12)).
+"""Separable naive DFTs on the zero-padded grid (Section 2.2, eqs. (FourSeriB3), (rho_hat), (I1FFT)).
 
 The density, sampled on n points per axis, is zero-padded to 2n points (the
-box [-2L, 2L], Remark after eq. (2.13)); its trapezoidal Fourier coefficients
+box [-2L, 2L], Remark after eq. (tensor)); its trapezoidal Fourier coefficients
 are then unnormalised DFTs of length 2n along every axis, in which only the n
 non-zero inputs take part:
     X[k] = sum_{j<n} x[j] exp(-2 pi i j k / (2n)),      k = 0..2n-1.

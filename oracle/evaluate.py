@@ -3,14 +3,14 @@
 Precomputation (plan):
   1. Gaussian-sum table of the kernel (Section 3; `gs_table`).
   2. The stored coefficient sums  G_k = sum_q w_q prod_j g_q(xi_{k_j})  of
-     eq. (2.12)-(2.13), from the one-dimensional factors (`factors`).  G is even
+     eqs. (I1FFT), (tensor), from the one-dimensional factors (`factors`).  G is even
      in every index, so it is formed on the octant k_j in [0, n] and extended.
   3. The Taylor constants A0, c2 of Section 2.3 (`taylor`).
 Actual computation (evaluate):
-  1. rho~ = DFT(pad(rho))                                (eqs. (2.10)-(2.11))
-  2. I1   = (1/M) crop(IDFT(G . rho~))                   (eq. (2.12))
+  1. rho~ = DFT(pad(rho))                                (eqs. (FourSeriB3), (rho_hat))
+  2. I1   = (1/M) crop(IDFT(G . rho~))                   (eq. (I1FFT))
   3. Lap  = (1/M) crop(IDFT(-|xi|^2 . rho~))             (spectral Laplacian)
-  4. I21~ = A0 rho + c2 Lap                              (eq. (2.19))
+  4. I21~ = A0 rho + c2 Lap                              (eq. (taylor))
   5. u    = I1 + I21~
 with M = (2n)^d.  The Laplacian is taken on the padded grid with the Nyquist
 mode kept (|xi| = pi/h there).

@@ -1,9 +1,9 @@
 """One-dimensional factor integrals of the kernel coefficients (Section 2.2).
 
-The tensor-product coefficient of eq. (2.13) is, per axis and per Gaussian,
+The tensor-product coefficient of eq. (tensor) is, per axis and per Gaussian,
     g(tau, xi) = int_{-c}^{c} exp(-tau^2 y^2) cos(xi y) dy,   c = 2L,
 taken at the padded-grid frequencies xi_k = pi k / (2L) = pi k / c (padding to
-the box [-2L, 2L], the Remark after eq. (2.13)).  The paper evaluates these by
+the box [-2L, 2L], the Remark after eq. (tensor)).  The paper evaluates these by
 adaptive quadrature; the oracle writes the integral out as a composite
 Gauss-Legendre rule on [0, c] with P = max(n, 8) equal panels of 20 nodes (at
 most one half-period of cos(xi_k y) per panel for every k <= n), with two exact

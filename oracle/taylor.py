@@ -1,4 +1,4 @@
-"""Near-field Taylor correction constants (Section 2.3, eq. (2.19)).
+"""Near-field Taylor correction constants (Section 2.3, eq. (taylor)).
 
 In the ball |y| < delta the density rho(x - y) is replaced by its third-order
 Taylor polynomial.  Integrating against the radial weight (U - U_GS)(|y|), the

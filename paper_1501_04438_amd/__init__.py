@@ -1,0 +1,253 @@
+"""Gaussian-sum nonlocal potentials on AMD MI355X (Exl, Mauser, Zhang).
+
+Python binding of the C ABI in include/gs.h.  Every step of an evaluation
+runs in the HIP library libgs.so; this module only marshals arguments
+(torch tensors give device pointers and the current stream).  Importing
+works without a GPU; evaluating needs one, and fails loudly without the
+built library.
+
+    plan = Plan("coulomb3d", n=256, L=10.0, eps=1e-14)
+    u = plan.eval(rho)                    # rho: (n, n, n) float64 CUDA tensor
+    u = potential(rho, plan)              # autograd: backward runs the adjoint chain
+    E = energy(rho, plan)                 # 1/2 h^d sum rho u
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+
+from ._lib import (KERNEL_DIM, KERNELS, PLAN_HOST_ASSEMBLY, PLAN_HOST_ONLY, GSError, GSOptions, GSPlanInfo,
+                   check, lib)
+
+__all__ = ["Plan", "potential", "energy", "eval_batch", "GSError", "device_count", "supported_sizes",
+           "mixture_density"]
+
+
+def device_count() -> int:
+    return int(lib().gs_device_count())
+
+
+def supported_sizes(d: int) -> list[int]:
+    buf = (C.c_int64 * 64)()
+    c = lib().gs_supported_sizes(d, buf, 64)
+    return [int(buf[i]) for i in range(min(c, 64))]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """Precomputed state for one grid and kernel (Algorithm 1, precomputation).
+
+    kernel: "coulomb3d" | "coulomb2d" | "poisson2d" | "dipolar3d" | "gaussian_sum"
+    n, L:   points per axis and box half-width (cubic box [-L, L]^d)
+    eps:    Gaussian-sum accuracy; delta_rel: near-field radius / L
+    dipole: (n_vec, m_vec) for "dipolar3d"; custom: (w, tau) for "gaussian_sum"
+    """
+
+    def __init__(self, kernel: str, n: int, L: float, eps: float = 1e-14, d: int | None = None,
+                 delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
+                 host_only: bool = False, host_assembly: bool = False, stream=None):
+        if kernel not in KERNELS:
+            raise ValueError(f"unknown kernel {kernel!r}")
+        d = KERNEL_DIM.get(kernel, d)
+        if d is None:
+            raise ValueError("gaussian_sum plans need d")
+        self.kernel, self.d, self.n, self.L, self.eps = kernel, int(d), int(n), float(L), float(eps)
+        opt = GSOptions()
+        lib().gs_options_default(C.byref(opt))
+        opt.delta_rel = float(delta_rel)
+        opt.device = int(device)
+        opt.flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_HOST_ASSEMBLY if host_assembly else 0)
+        if stream is not None:
+            opt.stream = C.c_void_p(int(stream))
+        keep = []
+        if dipole is not None:
+            for i in range(3):
+                opt.dipole_n[i] = float(dipole[0][i])
+                opt.dipole_m[i] = float(dipole[1][i])
+        if custom is not None:
+            w = np.ascontiguousarray(custom[0], dtype=np.float64)
+            tau = np.ascontiguousarray(custom[1], dtype=np.float64)
+            keep += [w, tau]
+            opt.gs_w = w.ctypes.data_as(C.POINTER(C.c_double))
+            opt.gs_tau = tau.ctypes.data_as(C.POINTER(C.c_double))
+            opt.gs_q = len(w)
+        nn = (C.c_int64 * self.d)(*([self.n] * self.d))
+        LL = (C.c_double * self.d)(*([self.L] * self.d))
+        h = C.c_void_p()
+        check(lib().gs_plan_create(C.byref(h), KERNELS[kernel], self.d, nn, LL, self.eps, C.byref(opt)))
+        self._h = h
+        self.host_only = host_only
+        self.info = self.query()
+
+    # ------------------------------------------------------------- plan data
+    def query(self) -> dict:
+        info = GSPlanInfo()
+        check(lib().gs_plan_query(self._h, C.byref(info)))
+        return {f: getattr(info, f) for f, _ in GSPlanInfo._fields_}
+
+    @property
+    def h(self) -> float:
+        return 2.0 * self.L / self.n
+
+    @property
+    def shape(self):
+        return (self.n,) * self.d
+
+    def table(self):
+        Q = self.info["Q"]
+        w, tau = np.empty(Q), np.empty(Q)
+        check(lib().gs_plan_table(self._h, w.ctypes.data_as(C.POINTER(C.c_double)),
+                                  tau.ctypes.data_as(C.POINTER(C.c_double)), Q))
+        return w, tau
+
+    def factors(self) -> np.ndarray:
+        F = np.empty((self.n + 1, self.info["Q"]))
+        check(lib().gs_plan_factors(self._h, F.ctypes.data_as(C.POINTER(C.c_double)), F.size))
+        return F
+
+    def spectrum(self) -> np.ndarray:
+        S = np.empty((self.n + 1,) * self.d)
+        check(lib().gs_plan_spectrum(self._h, S.ctypes.data_as(C.POINTER(C.c_double)), S.size))
+        return S
+
+    # ------------------------------------------------------------- evaluation
+    def _check_tensor(self, t, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != torch.float64 or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape {self.shape}")
+
+    def _stream(self):
+        torch = _torch()
+        check(lib().gs_plan_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def eval(self, rho, out=None):
+        """u = U * rho on the grid (Algorithm 1, actual computation)."""
+        torch = _torch()
+        self._check_tensor(rho, "rho")
+        u = torch.empty_like(rho) if out is None else out
+        self._check_tensor(u, "out")
+        self._stream()
+        check(lib().gs_eval(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr())))
+        return u
+
+    def eval_backward(self, grad_u, out=None):
+        """grad_rho = A^T grad_u (the transposed chain)."""
+        torch = _torch()
+        self._check_tensor(grad_u, "grad_u")
+        g = torch.empty_like(grad_u) if out is None else out
+        self._check_tensor(g, "out")
+        self._stream()
+        check(lib().gs_eval_backward(self._h, C.c_void_p(grad_u.data_ptr()), C.c_void_p(g.data_ptr())))
+        return g
+
+    def eval_pass(self, rho, u, p: int):
+        self._stream()
+        check(lib().gs_eval_pass(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()), int(p)))
+
+    def buffer(self, which: int, value=None):
+        """Read (value None) or write a plan buffer: 1 = X1, 2 = X2 (complex), 3 = spectrum."""
+        n, d = self.n, self.d
+        if which == 1:
+            shape, cplx = ((n, n + 1, n) if d == 3 else (n + 1, n)), True
+        elif which == 2:
+            shape, cplx = (n + 1, 2 * n, n), True
+        else:
+            shape, cplx = (n + 1,) * d, False
+        if value is None:
+            a = np.empty(shape, np.complex128 if cplx else np.float64)
+            check(lib().gs_plan_buffer(self._h, which, 0, a.ctypes.data_as(C.POINTER(C.c_double)),
+                                       a.size * (2 if cplx else 1)))
+            return a
+        a = np.ascontiguousarray(value, np.complex128 if cplx else np.float64).reshape(shape)
+        check(lib().gs_plan_buffer(self._h, which, 1, a.ctypes.data_as(C.POINTER(C.c_double)),
+                                   a.size * (2 if cplx else 1)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_batch(plans, rhos, outs=None):
+    """Evaluate independent problems (one plan each) in one batched launch."""
+    torch = _torch()
+    if outs is None:
+        outs = [torch.empty_like(r) for r in rhos]
+    for p, r, o in zip(plans, rhos, outs):
+        p._check_tensor(r, "rho")
+        p._check_tensor(o, "out")
+    n = len(plans)
+    hs = (C.c_void_p * n)(*[p._h for p in plans])
+    rs = (C.c_void_p * n)(*[r.data_ptr() for r in rhos])
+    us = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    plans[0]._stream()
+    check(lib().gs_eval_batch(n, hs, rs, us))
+    return outs
+
+
+# ------------------------------------------------------------------ autograd
+
+def _make_function():
+    torch = _torch()
+
+    class GSPotential(torch.autograd.Function):
+        """u = A rho with A the discrete Gaussian-sum convolution; backward applies A^T."""
+
+        @staticmethod
+        def forward(ctx, rho, plan):
+            ctx.plan = plan
+            return plan.eval(rho.contiguous())
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            return ctx.plan.eval_backward(grad_u.contiguous()), None
+
+    return GSPotential
+
+
+_GSPotential = None
+
+
+def potential(rho, plan: Plan):
+    global _GSPotential
+    if _GSPotential is None:
+        _GSPotential = _make_function()
+    return _GSPotential.apply(rho, plan)
+
+
+def energy(rho, plan: Plan):
+    """Hartree-type energy E = 1/2 int rho u, by the grid sum 1/2 h^d sum rho u."""
+    u = potential(rho, plan)
+    return 0.5 * plan.h ** plan.d * (rho * u).sum()
+
+
+def mixture_density(a, mu, sigma, n: int, L: float):
+    """Gaussian mixture sum_c a_c exp(-|x - mu_c|^2/sigma_c^2) on the [z][y][x] grid as a
+    differentiable torch expression (input construction for parameter gradients)."""
+    torch = _torch()
+    d = mu.shape[1]
+    ax = -L + (2.0 * L / n) * torch.arange(n, dtype=torch.float64, device=mu.device)
+    if d == 3:
+        X = (ax.view(1, 1, n), ax.view(1, n, 1), ax.view(n, 1, 1))
+    else:
+        X = (ax.view(1, n), ax.view(n, 1))
+    out = 0.0
+    for c in range(mu.shape[0]):
+        r2 = sum((X[i] - mu[c, i]) ** 2 for i in range(d))
+        out = out + a[c] * torch.exp(-r2 / sigma[c] ** 2)
+    return out

@@ -1,0 +1,44 @@
+// device_api.hpp -- host-side entry points of the device code (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace gsk {
+
+struct DipoleArgs;
+
+// Everything one evaluation needs.  Device pointers; X1 holds (n+1) n^(d-1)
+// complex values, X2 (3D only) 2 n^2 (n+1).
+struct EvalArgs {
+    int d = 3, n = 0;
+    const double* rho = nullptr;
+    double* u = nullptr;
+    double2* X1 = nullptr;
+    double2* X2 = nullptr;
+    const double* spec = nullptr;     // octant (n+1)^d, 1/M folded in
+    const double2* tw = nullptr;      // exp(-i pi m / n), m < 2n
+    int dipolar = 0;
+    double dxi = 0.0;                 // pi / (2L)
+    double cdiag[3] = {0, 0, 0};
+    double ccross[3] = {0, 0, 0};
+    double nm_over_M = 0.0;
+};
+
+// Passes: 1 x_r2c, 2 y_fwd, 3 fused, 4 y_inv, 5 x_c2r.  `which` < 0 runs the full chain.
+hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which = -1);
+bool eval_size_supported(int d, int n);
+int eval_sizes(int d, long long* out, int cap);
+
+struct AssemblyArgs {
+    int d = 3, n1 = 0, Qp = 0, ldk = 0;
+    const double* AT = nullptr;       // [Qp][ldk]
+    const double* FT = nullptr;       // [Qp][ldk]
+    double* out = nullptr;
+    double A0 = 0, c2 = 0, dxi = 0, invM = 0;
+};
+// Row blocks per wave chosen for n1; returns the padded k length the operands need.
+int assembly_ldk(int n1);
+hipError_t launch_assembly(const AssemblyArgs& a, hipStream_t s);
+
+}  // namespace gsk

@@ -1,0 +1,86 @@
+// device_dispatch.hip -- size dispatch of the evaluation passes and the
+// spectrum-assembly launcher.
+#include "assembly.hpp"
+#include "device_api.hpp"
+#include "sizes.hpp"
+
+namespace gsk {
+
+#define GS_DECL(N) hipError_t launch_eval_##N(const EvalArgs&, hipStream_t, int);
+GS_SIZE_LIST(GS_DECL)
+#undef GS_DECL
+
+hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which) {
+    switch (a.n) {
+#define GS_CASE(N) \
+    case N: return launch_eval_##N(a, s, which);
+        GS_SIZE_LIST(GS_CASE)
+#undef GS_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool eval_size_supported(int d, int n) {
+    if (d == 3 && n > GS_MAX_N_3D) return false;
+    switch (n) {
+#define GS_CASE(N) \
+    case N: return true;
+        GS_SIZE_LIST(GS_CASE)
+#undef GS_CASE
+        default: return false;
+    }
+}
+
+int eval_sizes(int d, long long* out, int cap) {
+    int c = 0;
+#define GS_ADD(N)                                                   \
+    if (!(d == 3 && N > GS_MAX_N_3D)) {                             \
+        if (c < cap && out) out[c] = N;                             \
+        ++c;                                                        \
+    }
+    GS_SIZE_LIST(GS_ADD)
+#undef GS_ADD
+    return c;
+}
+
+// Row blocks of 16 per wave: at most 9, with as few k1 chunks as possible.
+static int assembly_mb(int n1) {
+    const int blocks = (n1 + 15) / 16;
+    const int chunks = (blocks + 8) / 9;
+    return (blocks + chunks - 1) / chunks;
+}
+
+int assembly_ldk(int n1) {
+    const int mb = assembly_mb(n1);
+    const int chunks = ((n1 + 15) / 16 + mb - 1) / mb;
+    return chunks * mb * 16;
+}
+
+template <int MB>
+static hipError_t launch_mb(const AssemblyArgs& a, hipStream_t s) {
+    const long ncols = (a.d == 3) ? (long)a.n1 * a.n1 : a.n1;
+    const int chunks = a.ldk / (MB * 16);
+    dim3 grid((unsigned)((ncols + 63) / 64), chunks);
+    if (a.d == 3)
+        k_assemble<MB, 3><<<grid, 256, 0, s>>>(a.AT, a.FT, a.ldk, a.n1, a.Qp, a.out, a.A0, a.c2, a.dxi, a.invM);
+    else
+        k_assemble<MB, 2><<<grid, 256, 0, s>>>(a.AT, a.FT, a.ldk, a.n1, a.Qp, a.out, a.A0, a.c2, a.dxi, a.invM);
+    return hipGetLastError();
+}
+
+hipError_t launch_assembly(const AssemblyArgs& a, hipStream_t s) {
+    switch (assembly_mb(a.n1)) {
+        case 1: return launch_mb<1>(a, s);
+        case 2: return launch_mb<2>(a, s);
+        case 3: return launch_mb<3>(a, s);
+        case 4: return launch_mb<4>(a, s);
+        case 5: return launch_mb<5>(a, s);
+        case 6: return launch_mb<6>(a, s);
+        case 7: return launch_mb<7>(a, s);
+        case 8: return launch_mb<8>(a, s);
+        case 9: return launch_mb<9>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gsk

@@ -1,0 +1,56 @@
+// eval_instance.hip -- launchers of the evaluation passes for one transform length.
+// Compiled once per supported n with -DGS_N=<n>; the build lists the sizes.
+#include "device_api.hpp"
+#include "passes.hpp"
+#include "sizes.hpp"
+
+#ifndef GS_N
+#error "GS_N must be defined"
+#endif
+
+#define GS_CAT2(a, b) a##b
+#define GS_CAT(a, b) GS_CAT2(a, b)
+
+namespace gsk {
+
+hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int which) {
+    constexpr int N = GS_N;
+    using Gm = Geo<N>;
+    DipoleArgs dip;
+    dip.dxi = a.dxi;
+    for (int i = 0; i < 3; ++i) {
+        dip.cdiag[i] = a.cdiag[i];
+        dip.ccross[i] = a.ccross[i];
+    }
+    dip.nm_over_M = a.nm_over_M;
+    const int nz = (a.d == 3) ? N : 1;
+    const dim3 gx((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX), nz);
+    auto run = [&](int p) { return which < 0 || which == p; };
+    if (run(1)) k_x_r2c<N><<<gx, Gm::TX, 0, s>>>(a.rho, a.X1, a.tw);
+    if constexpr (N <= GS_MAX_N_3D) {
+      if (a.d == 3) {
+        const dim3 gy((N + Gm::PPY - 1) / Gm::PPY, N + 1);
+        const int np = (N + 1) * 2 * N;
+        if (run(2)) k_y_fwd<N><<<gy, Gm::TY, 0, s>>>(a.X1, a.X2, a.tw);
+        if (run(3)) {
+            const unsigned nb = (np + Gm::PPZ - 1) / Gm::PPZ;
+            if (a.dipolar)
+                k_fused<N, 3, SPEC_DIPOLAR><<<nb, Gm::TZ, 0, s>>>(a.X2, a.spec, a.tw, np, dip);
+            else
+                k_fused<N, 3, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(a.X2, a.spec, a.tw, np, dip);
+        }
+        if (run(4)) k_y_inv<N><<<gy, Gm::TY, 0, s>>>(a.X2, a.X1, a.tw);
+        if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(a.X1, a.u, a.tw);
+        return hipGetLastError();
+      }
+    }
+    {
+        const int np = N + 1;
+        const unsigned nb = (np + Gm::PPZ - 1) / Gm::PPZ;
+        if (run(3)) k_fused<N, 2, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(a.X1, a.spec, a.tw, np, dip);
+    }
+    if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(a.X1, a.u, a.tw);
+    return hipGetLastError();
+}
+
+}  // namespace gsk

@@ -1,0 +1,514 @@
+// gs_api.cpp -- the C ABI declared in include/gs.h.
+//
+// A plan owns the Gaussian-sum table, the factor matrix, the Taylor constants,
+// the stored spectrum octant (device), the FFT twiddle table (device) and the
+// evaluation workspace (device): X1 = (n+1) n^(d-1) complex values, and in 3D
+// X2 = 2n n (n+1) complex values.  Nothing is allocated per evaluation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/gs.h"
+#include "device_api.hpp"
+#include "host_plan.hpp"
+
+struct gs_plan_s {
+    int kernel = 0, d = 0, n = 0;
+    double L = 0, eps = 0, delta_rel = 0;
+    gsh::Table table;
+    std::vector<double> F;
+    double A0 = 0, c2 = 0;
+    std::vector<double> spec_host;
+    double dn[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
+    int device = 0, flags = 0;
+    bool host_only = false;
+    hipStream_t stream = nullptr;
+    double* spec = nullptr;
+    double2* X1 = nullptr;
+    double2* X2 = nullptr;
+    double2* tw = nullptr;
+    size_t spec_bytes = 0, work_bytes = 0;
+    double assembly_ms = 0.0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_live_mu;
+std::unordered_set<gs_plan_s*> g_live;
+
+gs_status fail(gs_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+gs_status hip_fail(hipError_t e, const char* what) {
+    return fail(GS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool is_live(gs_plan p) {
+    std::lock_guard<std::mutex> g(g_live_mu);
+    return p && g_live.count(p);
+}
+
+// Makes the plan's device current for the scope and restores the caller's.
+struct DeviceScope {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int visible_devices() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+void free_device(gs_plan_s* p) {
+    if (p->host_only) return;
+    DeviceScope ds(p->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    else (void)hipDeviceSynchronize();
+    if (p->spec) (void)hipFree(p->spec);
+    if (p->X1) (void)hipFree(p->X1);
+    if (p->X2) (void)hipFree(p->X2);
+    if (p->tw) (void)hipFree(p->tw);
+    p->spec = nullptr;
+    p->X1 = p->X2 = p->tw = nullptr;
+}
+
+gs_status device_assembly(gs_plan_s* p) {
+    const int n1 = p->n + 1, Q = (int)p->table.w.size();
+    const int Qp = (Q + 3) / 4 * 4;
+    const int ldk = gsk::assembly_ldk(n1);
+    std::vector<double> AT((size_t)Qp * ldk, 0.0), FT((size_t)Qp * ldk, 0.0);
+    for (int q = 0; q < Q; ++q)
+        for (int k = 0; k < n1; ++k) {
+            const double f = p->F[(size_t)k * Q + q];
+            FT[(size_t)q * ldk + k] = f;
+            AT[(size_t)q * ldk + k] = p->table.w[q] * f;
+        }
+    double *dA = nullptr, *dF = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc(&dA, AT.size() * 8)) != hipSuccess) return hip_fail(e, "hipMalloc(assembly)");
+    if ((e = hipMalloc(&dF, FT.size() * 8)) != hipSuccess) {
+        (void)hipFree(dA);
+        return hip_fail(e, "hipMalloc(assembly)");
+    }
+    gs_status st = GS_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    do {
+        if ((e = hipMemcpyAsync(dA, AT.data(), AT.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(dF, FT.data(), FT.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess) {
+            st = hip_fail(e, "hipMemcpy(assembly)");
+            break;
+        }
+        gsk::AssemblyArgs a;
+        a.d = p->d;
+        a.n1 = n1;
+        a.Qp = Qp;
+        a.ldk = ldk;
+        a.AT = dA;
+        a.FT = dF;
+        a.out = p->spec;
+        a.A0 = p->A0;
+        a.c2 = p->c2;
+        a.dxi = M_PI / (2.0 * p->L);
+        a.invM = 1.0 / std::pow(2.0 * p->n, p->d);
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, p->stream);
+        if ((e = gsk::launch_assembly(a, p->stream)) != hipSuccess) {
+            st = hip_fail(e, "spectrum assembly launch");
+            break;
+        }
+        (void)hipEventRecord(e1, p->stream);
+        if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) {
+            st = hip_fail(e, "spectrum assembly");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        p->assembly_ms = ms;
+    } while (false);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(dA);
+    (void)hipFree(dF);
+    return st;
+}
+
+size_t workspace_cap() {
+    const char* s = std::getenv("GS_MAX_WORKSPACE_BYTES");
+    if (!s || !*s) return (size_t)-1;
+    return (size_t)std::strtoull(s, nullptr, 10);
+}
+
+}  // namespace
+
+extern "C" {
+
+void gs_options_default(gs_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->delta_rel = 1e-4;
+    opt->device = -1;
+}
+
+const char* gs_status_string(gs_status s) {
+    switch (s) {
+        case GS_OK: return "GS_OK";
+        case GS_ERR_INVALID_ARG: return "GS_ERR_INVALID_ARG";
+        case GS_ERR_UNSUPPORTED_SIZE: return "GS_ERR_UNSUPPORTED_SIZE";
+        case GS_ERR_ACCURACY: return "GS_ERR_ACCURACY";
+        case GS_ERR_OUT_OF_MEMORY: return "GS_ERR_OUT_OF_MEMORY";
+        case GS_ERR_NO_DEVICE: return "GS_ERR_NO_DEVICE";
+        case GS_ERR_HIP: return "GS_ERR_HIP";
+    }
+    return "GS_UNKNOWN_STATUS";
+}
+
+const char* gs_last_error(void) { return g_err.c_str(); }
+
+int gs_device_count(void) { return visible_devices(); }
+
+int gs_supported_sizes(int d, int64_t* out, int capacity) {
+    if (d != 2 && d != 3) return 0;
+    std::vector<long long> tmp(64);
+    const int c = gsk::eval_sizes(d, tmp.data(), 64);
+    for (int i = 0; i < c && i < capacity && out; ++i) out[i] = tmp[i];
+    return c;
+}
+
+gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, const double* L, double eps,
+                         const gs_options* opt_in) {
+    if (!out) return fail(GS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    gs_options opt;
+    gs_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    if (opt.delta_rel == 0.0) opt.delta_rel = 1e-4;
+    if (d != 2 && d != 3) return fail(GS_ERR_INVALID_ARG, "d must be 2 or 3");
+    if (!n || !L) return fail(GS_ERR_INVALID_ARG, "n or L is NULL");
+    const int want_d = (k == GS_COULOMB_3D || k == GS_DIPOLAR_3D) ? 3
+                     : (k == GS_COULOMB_2D || k == GS_POISSON_2D) ? 2 : d;
+    if (k < GS_COULOMB_3D || k > GS_GAUSSIAN_SUM) return fail(GS_ERR_INVALID_ARG, "unknown kernel");
+    if (want_d != d) return fail(GS_ERR_INVALID_ARG, "kernel and dimension disagree");
+    for (int i = 0; i < d; ++i) {
+        if (n[i] != n[0] || L[i] != L[0]) return fail(GS_ERR_INVALID_ARG, "grids must be cubic (equal n and L)");
+    }
+    if (!(L[0] > 0.0) || !std::isfinite(L[0])) return fail(GS_ERR_INVALID_ARG, "L must be positive");
+    if (n[0] < 2 || n[0] > 1 << 20) return fail(GS_ERR_INVALID_ARG, "n out of range");
+    if (!(opt.delta_rel > 0.0 && opt.delta_rel < 0.5)) return fail(GS_ERR_INVALID_ARG, "delta_rel out of (0, 0.5)");
+    if (k != GS_GAUSSIAN_SUM && !(eps > 0.0 && eps < 1.0)) return fail(GS_ERR_INVALID_ARG, "eps out of (0, 1)");
+    if (k != GS_GAUSSIAN_SUM && eps < 1e-15)
+        return fail(GS_ERR_ACCURACY, "eps below the double-precision floor of the Gaussian-sum tables");
+    const int nn = (int)n[0];
+    if (!gsk::eval_size_supported(d, nn)) return fail(GS_ERR_UNSUPPORTED_SIZE, "no kernels compiled for this n");
+    const bool host_only = (opt.flags & GS_PLAN_HOST_ONLY) != 0;
+    if (k == GS_GAUSSIAN_SUM) {
+        if (!opt.gs_w || !opt.gs_tau || opt.gs_q <= 0) return fail(GS_ERR_INVALID_ARG, "custom Gaussian sum missing");
+        for (int q = 0; q < opt.gs_q; ++q)
+            if (!(opt.gs_tau[q] >= 0.0) || !std::isfinite(opt.gs_w[q]))
+                return fail(GS_ERR_INVALID_ARG, "custom Gaussian sum: tau must be >= 0, w finite");
+    }
+    if (k == GS_DIPOLAR_3D) {
+        // The dipolar operator is bilinear in (n, m); vectors are used as given
+        // (printed orientations are unit only to their printed digits).
+        double a = 0, b = 0;
+        for (int i = 0; i < 3; ++i) {
+            a += opt.dipole_n[i] * opt.dipole_n[i];
+            b += opt.dipole_m[i] * opt.dipole_m[i];
+        }
+        if (!std::isfinite(a) || !std::isfinite(b) || a == 0.0 || b == 0.0)
+            return fail(GS_ERR_INVALID_ARG, "dipole vectors must be finite and non-zero");
+    }
+    {
+        const size_t n1 = (size_t)n[0] + 1, nn0 = (size_t)n[0];
+        const size_t bytes = (d == 3 ? n1 * n1 * n1 * 8 + (n1 * nn0 * nn0 + 2 * nn0 * nn0 * n1) * 16
+                                     : n1 * n1 * 8 + n1 * nn0 * 16) + 2 * nn0 * 16;
+        if (!host_only && bytes > workspace_cap())
+            return fail(GS_ERR_OUT_OF_MEMORY, "plan exceeds GS_MAX_WORKSPACE_BYTES");
+    }
+    int ndev = 0;
+    if (!host_only) {
+        ndev = visible_devices();
+        if (ndev <= 0) return fail(GS_ERR_NO_DEVICE, "no HIP device visible");
+        if (opt.device >= ndev) return fail(GS_ERR_INVALID_ARG, "device ordinal out of range");
+    }
+
+    auto* p = new gs_plan_s();
+    p->kernel = k;
+    p->d = d;
+    p->n = nn;
+    p->L = L[0];
+    p->eps = eps;
+    p->delta_rel = opt.delta_rel;
+    p->flags = opt.flags;
+    p->host_only = host_only;
+    p->stream = (hipStream_t)opt.stream;
+    for (int i = 0; i < 3; ++i) {
+        p->dn[i] = opt.dipole_n[i];
+        p->dm[i] = opt.dipole_m[i];
+    }
+
+    bool ok = true;
+    if (k == GS_COULOMB_3D || k == GS_DIPOLAR_3D || k == GS_COULOMB_2D) {
+        ok = gsh::coulomb_table(d, p->L, p->delta_rel, eps, p->table);
+    } else if (k == GS_POISSON_2D) {
+        ok = gsh::poisson_table(p->L, p->delta_rel, eps, p->table);
+    } else {
+        p->table.w.assign(opt.gs_w, opt.gs_w + opt.gs_q);
+        p->table.tau.assign(opt.gs_tau, opt.gs_tau + opt.gs_q);
+        p->table.S = opt.gs_q - 1;
+        p->table.delta = 0.0;
+    }
+    if (!ok) {
+        delete p;
+        return fail(GS_ERR_ACCURACY, "eps not reachable by the sinc Gaussian sum");
+    }
+    gsh::factors_1d(p->table.tau, p->L, nn, p->F);
+    gsh::taylor_constants(k, d, p->table, p->A0, p->c2);
+
+    const size_t n1 = (size_t)nn + 1;
+    p->spec_bytes = (d == 3 ? n1 * n1 * n1 : n1 * n1) * sizeof(double);
+    const size_t x1 = n1 * (d == 3 ? (size_t)nn * nn : (size_t)nn);
+    const size_t x2 = (d == 3) ? 2 * (size_t)nn * nn * n1 : 0;
+    p->work_bytes = (x1 + x2) * sizeof(double2) + 2 * (size_t)nn * sizeof(double2);
+
+    if (host_only) {
+        gsh::assemble_spectrum(d, nn, p->L, p->table, p->F, p->A0, p->c2, p->spec_host);
+        std::lock_guard<std::mutex> g(g_live_mu);
+        g_live.insert(p);
+        *out = p;
+        return GS_OK;
+    }
+
+    if (opt.device < 0) {
+        if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
+    } else {
+        p->device = opt.device;
+    }
+    gs_status st = GS_OK;
+    {
+        DeviceScope ds(p->device);
+        hipError_t e = ds.err;
+        if (e != hipSuccess) st = hip_fail(e, "hipSetDevice");
+        if (st == GS_OK && (e = hipMalloc(&p->spec, p->spec_bytes)) != hipSuccess)
+            st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(spectrum) failed");
+        if (st == GS_OK && (e = hipMalloc(&p->X1, x1 * sizeof(double2))) != hipSuccess)
+            st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace X1) failed");
+        if (st == GS_OK && x2 && (e = hipMalloc(&p->X2, x2 * sizeof(double2))) != hipSuccess)
+            st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace X2) failed");
+        if (st == GS_OK && (e = hipMalloc(&p->tw, 2 * (size_t)nn * sizeof(double2))) != hipSuccess)
+            st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(twiddles) failed");
+        if (st == GS_OK) {
+            std::vector<double> tw;
+            gsh::twiddles(nn, tw);
+            if ((e = hipMemcpy(p->tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+                st = hip_fail(e, "hipMemcpy(twiddles)");
+        }
+        if (st == GS_OK) {
+            if (opt.flags & GS_PLAN_HOST_ASSEMBLY) {
+                gsh::assemble_spectrum(d, nn, p->L, p->table, p->F, p->A0, p->c2, p->spec_host);
+                if ((e = hipMemcpy(p->spec, p->spec_host.data(), p->spec_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+                    st = hip_fail(e, "hipMemcpy(spectrum)");
+            } else {
+                st = device_assembly(p);
+            }
+        }
+    }
+    if (st != GS_OK) {
+        free_device(p);
+        delete p;
+        (void)hipGetLastError();
+        return st;
+    }
+    std::lock_guard<std::mutex> g(g_live_mu);
+    g_live.insert(p);
+    *out = p;
+    return GS_OK;
+}
+
+gs_status gs_plan_destroy(gs_plan p) {
+    if (!p) return GS_OK;
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        if (!g_live.count(p)) return GS_OK;          // already destroyed: no-op
+        g_live.erase(p);
+    }
+    free_device(p);
+    delete p;
+    return GS_OK;
+}
+
+gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
+    if (!is_live(p) || !info) return fail(GS_ERR_INVALID_ARG, "invalid plan or info");
+    std::memset(info, 0, sizeof(*info));
+    info->kernel = p->kernel;
+    info->d = p->d;
+    info->n = p->n;
+    info->L = p->L;
+    info->eps = p->eps;
+    info->delta = p->table.delta;
+    info->S = p->table.S;
+    info->Q = (int)p->table.w.size();
+    info->A0 = p->A0;
+    info->c2 = p->c2;
+    info->spectrum_bytes = p->spec_bytes;
+    info->workspace_bytes = p->work_bytes;
+    info->assembly_ms = p->assembly_ms;
+    info->assembly_gflop = 2.0 * info->Q * std::pow((double)p->n + 1, p->d) * 1e-9;
+    info->host_only = p->host_only ? 1 : 0;
+    return GS_OK;
+}
+
+gs_status gs_plan_table(gs_plan p, double* w, double* tau, int capacity) {
+    if (!is_live(p) || !w || !tau) return fail(GS_ERR_INVALID_ARG, "invalid plan or pointer");
+    const int Q = (int)p->table.w.size();
+    if (capacity < Q) return fail(GS_ERR_INVALID_ARG, "capacity too small");
+    std::memcpy(w, p->table.w.data(), Q * sizeof(double));
+    std::memcpy(tau, p->table.tau.data(), Q * sizeof(double));
+    return GS_OK;
+}
+
+gs_status gs_plan_factors(gs_plan p, double* F, size_t capacity) {
+    if (!is_live(p) || !F) return fail(GS_ERR_INVALID_ARG, "invalid plan or pointer");
+    if (capacity < p->F.size()) return fail(GS_ERR_INVALID_ARG, "capacity too small");
+    std::memcpy(F, p->F.data(), p->F.size() * sizeof(double));
+    return GS_OK;
+}
+
+gs_status gs_plan_spectrum(gs_plan p, double* host_out, size_t capacity) {
+    if (!is_live(p) || !host_out) return fail(GS_ERR_INVALID_ARG, "invalid plan or pointer");
+    const size_t cnt = p->spec_bytes / sizeof(double);
+    if (capacity < cnt) return fail(GS_ERR_INVALID_ARG, "capacity too small");
+    if (p->host_only) {
+        std::memcpy(host_out, p->spec_host.data(), p->spec_bytes);
+        return GS_OK;
+    }
+    DeviceScope ds(p->device);
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess) e = hipMemcpy(host_out, p->spec, p->spec_bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(spectrum)");
+    return GS_OK;
+}
+
+gs_status gs_plan_buffer(gs_plan p, int which, int to_device, double* host, size_t count) {
+    if (!is_live(p) || !host) return fail(GS_ERR_INVALID_ARG, "invalid plan or pointer");
+    if (p->host_only) return fail(GS_ERR_INVALID_ARG, "host-only plan has no device buffers");
+    const size_t n = p->n, n1 = n + 1;
+    void* buf = nullptr;
+    size_t doubles = 0;
+    if (which == 1) {
+        buf = p->X1;
+        doubles = 2 * n1 * (p->d == 3 ? n * n : n);
+    } else if (which == 2 && p->d == 3) {
+        buf = p->X2;
+        doubles = 2 * 2 * n * n * n1;
+    } else if (which == 3) {
+        buf = p->spec;
+        doubles = p->spec_bytes / sizeof(double);
+    } else {
+        return fail(GS_ERR_INVALID_ARG, "unknown buffer");
+    }
+    if (count != doubles) return fail(GS_ERR_INVALID_ARG, "count does not match the buffer size");
+    DeviceScope ds(p->device);
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess)
+        e = to_device ? hipMemcpy(buf, host, count * sizeof(double), hipMemcpyHostToDevice)
+                      : hipMemcpy(host, buf, count * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan buffer)");
+    return GS_OK;
+}
+
+gs_status gs_plan_set_stream(gs_plan p, void* stream) {
+    if (!is_live(p)) return fail(GS_ERR_INVALID_ARG, "invalid plan");
+    p->stream = (hipStream_t)stream;
+    return GS_OK;
+}
+
+static gs_status eval_chain(gs_plan p, const double* in, double* out, int which) {
+    if (!is_live(p)) return fail(GS_ERR_INVALID_ARG, "invalid plan");
+    if (p->host_only) return fail(GS_ERR_INVALID_ARG, "host-only plan cannot evaluate");
+    if (!in || !out) return fail(GS_ERR_INVALID_ARG, "NULL device pointer");
+    DeviceScope ds(p->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    gsk::EvalArgs a;
+    a.d = p->d;
+    a.n = p->n;
+    a.rho = in;
+    a.u = out;
+    a.X1 = p->X1;
+    a.X2 = p->X2;
+    a.spec = p->spec;
+    a.tw = p->tw;
+    a.dxi = M_PI / (2.0 * p->L);
+    if (p->kernel == GS_DIPOLAR_3D) {
+        a.dipolar = 1;
+        for (int i = 0; i < 3; ++i) a.cdiag[i] = 3.0 * p->dn[i] * p->dm[i];
+        a.ccross[0] = 3.0 * (p->dn[0] * p->dm[1] + p->dn[1] * p->dm[0]);
+        a.ccross[1] = 3.0 * (p->dn[0] * p->dm[2] + p->dn[2] * p->dm[0]);
+        a.ccross[2] = 3.0 * (p->dn[1] * p->dm[2] + p->dn[2] * p->dm[1]);
+        const double nm = p->dn[0] * p->dm[0] + p->dn[1] * p->dm[1] + p->dn[2] * p->dm[2];
+        a.nm_over_M = nm / std::pow(2.0 * p->n, 3);
+    }
+    hipError_t e = gsk::launch_eval(a, p->stream, which);
+    if (e != hipSuccess) return hip_fail(e, "evaluation launch");
+    return GS_OK;
+}
+
+gs_status gs_eval(gs_plan p, const double* rho_dev, double* u_dev) { return eval_chain(p, rho_dev, u_dev, -1); }
+
+gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho_dev) {
+    // The transposed chain: zero-pad <-> crop exchanged and the transform signs
+    // flipped.  With an even spectrum (every supported kernel) the sign flip is
+    // the index reversal k -> -k, under which the spectrum is invariant, so the
+    // transposed chain is the same sequence of passes.
+    return eval_chain(p, grad_u_dev, grad_rho_dev, -1);
+}
+
+// Internal: run one pass of the chain (1..5) on the plan's workspace; used by
+// the benchmark to time passes separately.
+gs_status gs_eval_pass(gs_plan p, const double* rho_dev, double* u_dev, int pass) {
+    if (pass < 1 || pass > 5) return fail(GS_ERR_INVALID_ARG, "pass must be 1..5");
+    return eval_chain(p, rho_dev, u_dev, pass);
+}
+
+gs_status gs_eval_batch(int count, const gs_plan* plans, const double* const* rho_dev, double* const* u_dev) {
+    if (count <= 0 || !plans || !rho_dev || !u_dev) return fail(GS_ERR_INVALID_ARG, "invalid batch arguments");
+    std::unordered_set<gs_plan> seen;
+    for (int i = 0; i < count; ++i) {
+        if (!is_live(plans[i]) || plans[i]->host_only) return fail(GS_ERR_INVALID_ARG, "invalid plan in batch");
+        if (!rho_dev[i] || !u_dev[i]) return fail(GS_ERR_INVALID_ARG, "NULL device pointer in batch");
+        if (!seen.insert(plans[i]).second) return fail(GS_ERR_INVALID_ARG, "a plan appears twice in the batch");
+        if (plans[i]->device != plans[0]->device) return fail(GS_ERR_INVALID_ARG, "batch spans devices");
+    }
+    hipStream_t s0 = plans[0]->stream;
+    for (int i = 0; i < count; ++i) {
+        hipStream_t keep = plans[i]->stream;
+        plans[i]->stream = s0;
+        gs_status st = eval_chain(plans[i], rho_dev[i], u_dev[i], -1);
+        plans[i]->stream = keep;
+        if (st != GS_OK) return st;
+    }
+    return GS_OK;
+}
+
+}  // extern "C"

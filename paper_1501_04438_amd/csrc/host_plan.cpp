@@ -1,0 +1,450 @@
+// host_plan.cpp -- plan-time host computations (Algorithm 1, "Precomputation").
+//
+//  * Gaussian-sum tables by sinc quadrature (Section 3): 1/r from its Gaussian
+//    integral with tau = sinh(t) (Section 3.2), ln r from Frullani's integral with
+//    s = ln(1 + exp(sinh t)) (Section 3.3, read as described at poisson_table),
+//    step theta = c0 ln(S)/S with c0 = 2.1 and 1 (Remark in Section 3.1), and S the
+//    smallest value meeting eps on the fit interval.
+//  * One-dimensional factor integrals of the tensor-product coefficients
+//    (Section 2.2, eq. (tensor)) on the box [-2L, 2L] at xi_k = pi k/(2L).
+//  * Taylor constants A0, c2 of the near-field correction (Section 2.3).
+//  * A host assembly of the stored spectrum (used for host-only plans and as
+//    the reference of the device assembly), and the FFT twiddle table.
+#include "host_plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+
+namespace gsh {
+
+static const double PI = 3.14159265358979323846;
+
+static void parallel_for(int count, const std::function<void(int, int)>& body) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int nt = (int)std::min<unsigned>(hw ? hw : 1, 16);
+    nt = std::max(1, std::min(nt, count));
+    if (nt == 1) {
+        body(0, count);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int chunk = (count + nt - 1) / nt;
+    for (int i = 0; i < nt; ++i) {
+        const int lo = i * chunk, hi = std::min(count, lo + chunk);
+        if (lo >= hi) break;
+        th.emplace_back(body, lo, hi);
+    }
+    for (auto& t : th) t.join();
+}
+
+// ------------------------------------------------------------------ sinc tables
+
+static const int NPTS = 100001;   // check points on the fit interval (log spaced)
+
+static std::vector<double> log_points(double lo, double hi) {
+    std::vector<double> p(NPTS);
+    const double a = std::log(lo), b = std::log(hi);
+    for (int i = 0; i < NPTS; ++i) p[i] = std::exp(a + (b - a) * ((double)i / (NPTS - 1)));
+    p[0] = lo;
+    p[NPTS - 1] = hi;
+    return p;
+}
+
+// max over the points with index multiple of `step` of f(point); threads for the full set
+static double max_err(const std::vector<double>& pts, int step, const std::function<double(double)>& f) {
+    const int cnt = (NPTS - 1) / step + 1;
+    if (cnt < 4096) {
+        double m = 0.0;
+        for (int i = 0; i < cnt; ++i) m = std::max(m, f(pts[(size_t)i * step]));
+        return m;
+    }
+    double best = 0.0;
+    std::mutex mu;
+    parallel_for(cnt, [&](int lo, int hi) {
+        double m = 0.0;
+        for (int i = lo; i < hi; ++i) m = std::max(m, f(pts[(size_t)i * step]));
+        std::lock_guard<std::mutex> g(mu);
+        best = std::max(best, m);
+    });
+    return best;
+}
+
+static void coulomb_nodes(int S, std::vector<double>& w, std::vector<double>& tau) {
+    const double th = 2.1 * std::log((double)S) / S;
+    w.assign(S + 1, 0.0);
+    tau.assign(S + 1, 0.0);
+    w[0] = th / std::sqrt(PI);
+    for (int k = 1; k <= S; ++k) {
+        w[k] = 2.0 * th * std::cosh(k * th) / std::sqrt(PI);
+        tau[k] = std::sinh(k * th);
+    }
+}
+
+static double coulomb_err_at(const std::vector<double>& w, const std::vector<double>& tau, double r) {
+    double acc = 0.0;
+    for (int q = (int)w.size() - 1; q >= 0; --q) acc += w[q] * std::exp(-(tau[q] * r) * (tau[q] * r));
+    return std::fabs(1.0 - r * acc);
+}
+
+double coulomb_table_error(int S, double lo, double hi) {
+    std::vector<double> w, tau;
+    coulomb_nodes(S, w, tau);
+    auto pts = log_points(lo, hi);
+    return max_err(pts, 1, [&](double r) { return coulomb_err_at(w, tau, r); });
+}
+
+static const int S_MAX = 4000;
+
+// Smallest S whose error on all NPTS points is <= eps: two cheap necessary
+// tests on point subsets (every 1000th, every 50th) before the full check.
+// Gives up (-1) once the coarse error has not improved for 200 consecutive S
+// past S = 100: the rounding floor of the table lies above eps.
+template <class ErrFn>
+static int smallest_S(const std::vector<double>& pts, double eps, ErrFn err_for_S) {
+    double best = 1e300;
+    int best_at = 0;
+    for (int S = 2; S <= S_MAX; ++S) {
+        const double coarse = err_for_S(S, 1000);
+        if (coarse < best) {
+            best = coarse;
+            best_at = S;
+        } else if (S > 100 && S - best_at > 200) {
+            break;
+        }
+        if (coarse > eps) continue;
+        if (err_for_S(S, 50) > eps) continue;
+        if (err_for_S(S, 1) <= eps) return S;
+    }
+    (void)pts;
+    return -1;
+}
+
+struct TableKey {
+    int kind, d;
+    double delta_rel, eps;
+    bool operator<(const TableKey& o) const {
+        return std::tie(kind, d, delta_rel, eps) < std::tie(o.kind, o.d, o.delta_rel, o.eps);
+    }
+};
+static std::mutex g_cache_mu;
+static std::map<TableKey, int> g_S_cache;
+
+bool coulomb_table(int d, double L, double delta_rel, double eps, Table& out) {
+    const double lo = delta_rel, hi = 2.0 * std::sqrt((double)d);
+    int S;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        auto it = g_S_cache.find({0, d, delta_rel, eps});
+        S = (it == g_S_cache.end()) ? 0 : it->second;
+    }
+    if (S == 0) {
+        auto pts = log_points(lo, hi);
+        std::vector<double> w, tau;
+        S = smallest_S(pts, eps, [&](int s, int step) {
+            coulomb_nodes(s, w, tau);
+            return max_err(pts, step, [&](double r) { return coulomb_err_at(w, tau, r); });
+        });
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        g_S_cache[{0, d, delta_rel, eps}] = S;
+    }
+    if (S < 0) return false;
+    std::vector<double> w, tau;
+    coulomb_nodes(S, w, tau);
+    const double kappa = (d == 3) ? 1.0 / (4.0 * PI) : 1.0 / (2.0 * PI);
+    out.S = S;
+    out.delta = delta_rel * L;
+    out.w.resize(w.size());
+    out.tau.resize(w.size());
+    for (size_t q = 0; q < w.size(); ++q) {
+        out.w[q] = kappa * w[q] / L;
+        out.tau[q] = tau[q] / L;
+    }
+    return true;
+}
+
+// ln x ~= C0 - sum_k wh_k exp(-s_k x^2) on x in [1, X] (rescaled), nodes k = -S..S
+// with negligible contributions (a_k X^2/2 <= 1e-3 eps) dropped.
+static void poisson_nodes(int S, double X, double eps, double& C0, std::vector<double>& wh,
+                          std::vector<double>& s) {
+    const double th = 1.0 * std::log((double)S) / S;
+    wh.clear();
+    s.clear();
+    for (int k = -S; k <= S; ++k) {
+        const double t = k * th, sh = std::sinh(t);
+        const double e = std::exp(-std::fabs(sh));
+        const double sk = (sh > 0) ? sh + std::log1p(e) : std::log1p(e);
+        const double sig = (sh >= 0) ? 1.0 / (1.0 + e) : e / (1.0 + e);
+        const double a = th * std::cosh(t) * sig;
+        if (!(a * X * X / 2.0 > 1e-3 * eps)) continue;
+        wh.push_back(a / (2.0 * sk));
+        s.push_back(sk);
+    }
+    C0 = 0.0;
+    for (size_t q = 0; q < wh.size(); ++q) C0 += wh[q] * std::exp(-s[q]);
+}
+
+// |ln x - (C0 - sum_k wh_k exp(-s_k x^2))| summed as sum_k wh_k (exp(-s_k) - exp(-s_k x^2)):
+// positive terms without cancellation against C0, so S follows the quadrature error.
+static double poisson_err_at(double C0, const std::vector<double>& wh, const std::vector<double>& s, double x) {
+    (void)C0;
+    const double x2m1 = x * x - 1.0;
+    double acc = 0.0;
+    for (int q = (int)wh.size() - 1; q >= 0; --q) acc += wh[q] * (-std::exp(-s[q]) * std::expm1(-s[q] * x2m1));
+    return std::fabs(std::log(x) - acc);
+}
+
+bool poisson_table(double L, double delta_rel, double eps, Table& out) {
+    const double X = 2.0 * std::sqrt(2.0) / delta_rel;
+    int S;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        auto it = g_S_cache.find({1, 2, delta_rel, eps});
+        S = (it == g_S_cache.end()) ? 0 : it->second;
+    }
+    if (S == 0) {
+        auto pts = log_points(1.0, X);
+        double C0;
+        std::vector<double> wh, s;
+        S = smallest_S(pts, eps, [&](int ss, int step) {
+            poisson_nodes(ss, X, eps, C0, wh, s);
+            return max_err(pts, step, [&](double x) { return poisson_err_at(C0, wh, s, x); });
+        });
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        g_S_cache[{1, 2, delta_rel, eps}] = S;
+    }
+    if (S < 0) return false;
+    double C0;
+    std::vector<double> wh, s;
+    poisson_nodes(S, X, eps, C0, wh, s);
+    const double delta = delta_rel * L;
+    out.S = S;
+    out.delta = delta;
+    out.w.assign(1, -(std::log(delta) + C0) / (2.0 * PI));
+    out.tau.assign(1, 0.0);
+    for (size_t q = 0; q < wh.size(); ++q) {
+        out.w.push_back(wh[q] / (2.0 * PI));
+        out.tau.push_back(std::sqrt(s[q]) / delta);
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------ factor integrals
+
+static const int GL_M = 16;
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration in long double.
+static void gauss_legendre(int m, std::vector<double>& x, std::vector<double>& w) {
+    x.resize(m);
+    w.resize(m);
+    for (int i = 0; i < m; ++i) {
+        long double z = std::cos(PI * (i + 0.75) / (m + 0.5)), dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = z;
+            for (int k = 2; k <= m; ++k) {
+                long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = m * (z * p1 - p0) / (z * z - 1);
+            long double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs((double)dz) < 1e-19) break;
+        }
+        long double p0 = 1, p1 = z;
+        for (int k = 2; k <= m; ++k) {
+            long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = m * (z * p1 - p0) / (z * z - 1);
+        x[i] = (double)z;
+        w[i] = (double)(2.0L / ((1 - z * z) * dp * dp));
+    }
+}
+
+// tau c >= 6.5: the truncation of the Gaussian at |y| = c is below 1e-19 relative
+static const double TAU_C_CLOSED = 6.5;
+
+void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<double>& F) {
+    const int Q = (int)tau.size();
+    const double c = 2.0 * L;
+    F.assign((size_t)(n + 1) * Q, 0.0);
+    std::vector<int> mid;
+    for (int q = 0; q < Q; ++q) {
+        const double t = tau[q];
+        if (t == 0.0) {
+            F[q] = 2.0 * c;                      // k = 0 only: xi_k c = pi k
+        } else if (t * c >= TAU_C_CLOSED) {
+            for (int k = 0; k <= n; ++k) {
+                const double xi = PI * k / c;
+                F[(size_t)k * Q + q] = std::sqrt(PI) / t * std::exp(-(xi * xi) / (4.0 * t * t));
+            }
+        } else {
+            mid.push_back(q);
+        }
+    }
+    if (mid.empty()) return;
+    // Composite Gauss-Legendre on [0, c] (even integrand, factor 2): P panels of
+    // GL_M nodes, at most one half-period of cos(xi_k y) per panel.  At node
+    // y = c (p + s)/P the phase pi k (p + s)/P is split into an exactly reduced
+    // integer part pi ((k p) mod 2P)/P and a part pi k s/P <= pi.
+    const int P = std::max(n, 8);
+    const int Qm = (int)mid.size();
+    std::vector<double> xg, wg;
+    gauss_legendre(GL_M, xg, wg);
+    std::vector<double> s(GL_M);
+    for (int i = 0; i < GL_M; ++i) s[i] = 0.5 * (xg[i] + 1.0);
+    const double hp = c / P;
+    std::vector<double> gw((size_t)P * Qm * GL_M);    // [p][q][i]
+    for (int p = 0; p < P; ++p)
+        for (int qi = 0; qi < Qm; ++qi) {
+            const double t = tau[mid[qi]];
+            for (int i = 0; i < GL_M; ++i) {
+                const double y = hp * (p + s[i]);
+                gw[((size_t)p * Qm + qi) * GL_M + i] = hp * wg[i] * std::exp(-(t * y) * (t * y));
+            }
+        }
+    std::vector<double> cosA(2 * P), sinA(2 * P);
+    for (int m = 0; m < 2 * P; ++m) {
+        cosA[m] = std::cos(PI * m / P);
+        sinA[m] = std::sin(PI * m / P);
+    }
+    parallel_for(n + 1, [&](int k0, int k1) {
+        std::vector<double> acc(Qm), cb(GL_M), sb(GL_M);
+        for (int k = k0; k < k1; ++k) {
+            for (int i = 0; i < GL_M; ++i) {
+                const double B = PI * (k * s[i]) / P;
+                cb[i] = std::cos(B);
+                sb[i] = std::sin(B);
+            }
+            std::fill(acc.begin(), acc.end(), 0.0);
+            for (int p = 0; p < P; ++p) {
+                const int m = (int)(((long long)k * p) % (2 * P));
+                const double ca = cosA[m], sa = sinA[m];
+                const double* g = &gw[(size_t)p * Qm * GL_M];
+                for (int qi = 0; qi < Qm; ++qi) {
+                    double dc = 0.0, ds = 0.0;
+                    for (int i = 0; i < GL_M; ++i) {
+                        dc += g[qi * GL_M + i] * cb[i];
+                        ds += g[qi * GL_M + i] * sb[i];
+                    }
+                    acc[qi] += ca * dc - sa * ds;
+                }
+            }
+            for (int qi = 0; qi < Qm; ++qi) F[(size_t)k * Q + mid[qi]] = acc[qi];
+        }
+    });
+}
+
+// ------------------------------------------------------------------ Taylor constants
+
+// gamma_m(tau) = int_0^delta r^m exp(-tau^2 r^2) dr, m = 1..4, without cancellation:
+// a power series in u = tau delta for u <= 1, the closed recurrences otherwise.
+static double gamma_moment(int m, double tau, double delta) {
+    const double u = tau * delta;
+    if (u <= 1.0) {
+        // delta^{m+1} sum_i (-u^2)^i / (i! (m + 1 + 2i))
+        double term = 1.0, sum = 0.0;
+        const double u2 = u * u;
+        for (int i = 0; i < 40; ++i) {
+            sum += term / (m + 1 + 2 * i);
+            term *= -u2 / (i + 1);
+        }
+        return std::pow(delta, m + 1) * sum;
+    }
+    const double t2 = tau * tau, e = std::exp(-u * u);
+    const double I0 = std::sqrt(PI) * std::erf(u) / (2.0 * tau);
+    const double I1 = -std::expm1(-u * u) / (2.0 * t2);
+    switch (m) {
+        case 1: return I1;
+        case 2: return I0 / (2.0 * t2) - delta * e / (2.0 * t2);
+        case 3: return I1 / t2 - delta * delta * e / (2.0 * t2);
+        case 4: {
+            const double I2 = I0 / (2.0 * t2) - delta * e / (2.0 * t2);
+            return 3.0 * I2 / (2.0 * t2) - delta * delta * delta * e / (2.0 * t2);
+        }
+    }
+    return 0.0;
+}
+
+// int_0^delta r^m U(r) dr for the kernel (constants included)
+static double u_moment(int kernel, int m, double delta) {
+    switch (kernel) {
+        case COULOMB_3D:
+        case DIPOLAR_3D: return std::pow(delta, m) / (4.0 * PI * m);
+        case COULOMB_2D: return std::pow(delta, m) / (2.0 * PI * m);
+        case POISSON_2D: {
+            const double a = m + 1;
+            return -std::pow(delta, a) * (std::log(delta) / a - 1.0 / (a * a)) / (2.0 * PI);
+        }
+    }
+    return 0.0;
+}
+
+void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2) {
+    if (kernel == GAUSSIAN_SUM) {
+        A0 = c2 = 0.0;
+        return;
+    }
+    const double area = (d == 3) ? 4.0 * PI : 2.0 * PI;
+    const int m0 = d - 1, m2 = d + 1;
+    double s0 = u_moment(kernel, m0, t.delta), s2 = u_moment(kernel, m2, t.delta);
+    for (size_t q = 0; q < t.w.size(); ++q) {
+        s0 -= t.w[q] * gamma_moment(m0, t.tau[q], t.delta);
+        s2 -= t.w[q] * gamma_moment(m2, t.tau[q], t.delta);
+    }
+    A0 = area * s0;
+    c2 = area * s2 / (2.0 * d);
+}
+
+// ------------------------------------------------------------------ host assembly
+
+void assemble_spectrum(int d, int n, double L, const Table& t, const std::vector<double>& F, double A0,
+                       double c2, std::vector<double>& S) {
+    const int n1 = n + 1, Q = (int)t.w.size();
+    const double dxi = PI / (2.0 * L);
+    const double invM = 1.0 / std::pow(2.0 * n, d);
+    S.assign(d == 3 ? (size_t)n1 * n1 * n1 : (size_t)n1 * n1, 0.0);
+    parallel_for(n1, [&](int a0, int a1) {
+        std::vector<double> wa(Q);
+        for (int a = a0; a < a1; ++a) {
+            for (int q = 0; q < Q; ++q) wa[q] = t.w[q] * F[(size_t)a * Q + q];
+            const double xa = a * dxi;
+            if (d == 2) {
+                for (int b = 0; b < n1; ++b) {
+                    double acc = 0.0;
+                    for (int q = 0; q < Q; ++q) acc += wa[q] * F[(size_t)b * Q + q];
+                    const double xb = b * dxi;
+                    S[(size_t)a * n1 + b] = (acc + A0 - c2 * (xa * xa + xb * xb)) * invM;
+                }
+                continue;
+            }
+            for (int b = 0; b < n1; ++b) {
+                const double xb = b * dxi;
+                for (int cc = 0; cc < n1; ++cc) {
+                    double acc = 0.0;
+                    for (int q = 0; q < Q; ++q) acc += wa[q] * F[(size_t)b * Q + q] * F[(size_t)cc * Q + q];
+                    const double xc = cc * dxi;
+                    S[((size_t)a * n1 + b) * n1 + cc] = (acc + A0 - c2 * (xa * xa + xb * xb + xc * xc)) * invM;
+                }
+            }
+        }
+    });
+}
+
+void twiddles(int n, std::vector<double>& tw) {
+    tw.resize(4 * (size_t)n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int m = 0; m < 2 * n; ++m) {
+        const long double a = pi * (long double)m / (long double)n;
+        tw[2 * m] = (double)cosl(a);
+        tw[2 * m + 1] = (double)(-sinl(a));
+    }
+}
+
+}  // namespace gsh

@@ -1,0 +1,39 @@
+// host_plan.hpp -- plan-time host computations (Algorithm 1, "Precomputation").
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace gsh {
+
+enum Kernel { COULOMB_3D = 0, COULOMB_2D = 1, POISSON_2D = 2, DIPOLAR_3D = 3, GAUSSIAN_SUM = 4 };
+
+// Gaussian sum U_GS(r) = sum_q w[q] exp(-tau[q]^2 r^2) in physical units; q = 0 is tau = 0.
+struct Table {
+    std::vector<double> w, tau;
+    int S = 0;
+    double delta = 0.0;   // physical near-field radius
+};
+
+// Sinc-quadrature tables (Section 3).  Return false when eps is not reachable.
+bool coulomb_table(int d, double L, double delta_rel, double eps, Table& out);
+bool poisson_table(double L, double delta_rel, double eps, Table& out);
+
+// Max error of the rescaled tables on their fit interval (for tests and reports).
+double coulomb_table_error(int S, double lo, double hi);
+
+// F[k*Q + q] = int_{-2L}^{2L} exp(-tau_q^2 y^2) cos(pi k y / (2L)) dy, k = 0..n.
+void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<double>& F);
+
+// Taylor constants of the near-field correction (Section 2.3).
+void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2);
+
+// Host assembly of the stored octant (n+1)^d, 1/(2n)^d folded in.
+void assemble_spectrum(int d, int n, double L, const Table& t, const std::vector<double>& F,
+                       double A0, double c2, std::vector<double>& S);
+
+// exp(-i pi m / n), m = 0..2n-1, as interleaved (re, im).
+void twiddles(int n, std::vector<double>& tw);
+
+}  // namespace gsh

@@ -1,0 +1,319 @@
+// passes.hpp -- the evaluation passes of the Gaussian-sum convolution on gfx950.
+//
+// The evaluation is one aperiodic convolution, u = (1/M) crop(IDFT(S . DFT(pad rho)))
+// on the grid zero-padded from n to 2n points per axis (Section 2.2 with the
+// padding of its Remark; the Taylor terms A0 rho + c2 Lap rho of Section 2.3 are
+// folded into the stored spectrum S, which also carries 1/M).  Pruned passes,
+// 3D (arrays C-ordered, x fastest; complex FP64):
+//
+//   P1 x_r2c : rho[z][y][x] (real)      -> X1[z][kx][y],  kx = 0..n   (two real rows per FFT)
+//   P2 y_fwd : X1[z][kx][y]             -> X2[kx][ky][z], ky = 0..2n-1
+//   P3 fused : X2[kx][ky][z] -> forward z (n -> 2n), * S[kx][|ky|][|kz|], inverse z
+//              (2n -> n), in place
+//   P4 y_inv : X2[kx][ky][z]            -> X1[z][kx][y]   (2n -> n)
+//   P5 x_c2r : X1[z][kx][y]             -> u[z][y][x]     (Hermitian n+1 -> 2n real -> n)
+//
+// 2D is P1, P3 along y on X1[kx][y] with S[kx][|ky|], and P5.  Every pass reads
+// its input once and writes its output once; the zero padding is never stored.
+// Each pass that changes the contiguous axis does so through the LDS exchange of
+// its FFT: the first stage runs with the load-side thread mapping, the later
+// stages with the store-side mapping, so both global sides move 256-byte runs.
+#pragma once
+
+#include "fft_core.hpp"
+
+namespace gsk {
+
+// spectrum mode of the fused pass
+enum { SPEC_PLAIN = 0, SPEC_DIPOLAR = 1 };
+
+struct DipoleArgs {
+    double dxi;          // pi / (2L): xi_k = k * dxi
+    double cdiag[3];     // 3 n_i m_i                    (x, y, z)
+    double ccross[3];    // 3 (n_i m_j + n_j m_i)        (xy, xz, yz)
+    double nm_over_M;    // (n.m) / (2n)^3
+};
+
+// ---------------------------------------------------------------------------
+// Launch geometry per transform length.
+// ---------------------------------------------------------------------------
+template <int N> struct Geo {
+    static constexpr int E = FftCfg<N>::E, G = FftCfg<N>::G, A = LdsArea<N>::size;
+    // P1/P5: pairs of real rows per block (2*PPX rows of y, 16-byte complex each)
+    static constexpr int PPX = (N <= 256) ? 8 : (N <= 512 ? 4 : (N <= 1024 ? 2 : 1));
+    // P2/P4: z-pencils per block
+    static constexpr int PPY = (N <= 256) ? 16 : 8;
+    // P3: pencils per block (two half-transforms each)
+    static constexpr int PPZ = (2 * G >= 128) ? 1 : 128 / (2 * G);
+    static constexpr int TX = PPX * G, TY = PPY * G, TZ = PPZ * 2 * G;
+};
+
+// ---------------------------------------------------------------------------
+// P1: x-direction real-to-complex of zero-padded rows.  Block = one z, 2*PPX rows.
+// Two real rows a, b form c = a + i b; its padded transform C is split into the
+// Hermitian spectra A = (C[m] + conj C[2n-m])/2, B = (C[m] - conj C[2n-m])/(2i).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
+                                                      const cpx* __restrict__ tw) {
+    using Gm = Geo<N>;
+    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPX, A = Gm::A;
+    __shared__ cpx lds[PP * A];
+    const int tid = threadIdx.x;
+    const int tA = tid % G, pA = tid / G;      // load role: consecutive x
+    const int pB = tid % PP, tB = tid / PP;    // store role: consecutive y
+    const int z = blockIdx.y;
+    const int y0 = blockIdx.x * 2 * PP;
+    const bool okA = (y0 + 2 * pA) < N, okB = (y0 + 2 * pB) < N;
+
+    cpx x[E];
+    {
+        const double* ra = rho + ((size_t)z * N + (y0 + 2 * pA)) * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = tA + G * e;
+            x[e] = okA ? cmk(ra[j], ra[N + j]) : cmk(0.0, 0.0);
+        }
+    }
+    cpx* out = X1 + (size_t)z * (N + 1) * N + y0 + 2 * pB;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cpx v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = h ? cmul(x[e], tw[tA + G * e]) : x[e];
+        fft<N, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds[pB * A + lds_pad(tB + G * e)] = v[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tB + G * e;
+            const bool keep = h ? (k <= N / 2 - 1) : (k <= N / 2);
+            if (keep && okB) {
+                const int kp = h ? (N - 1 - k) : ((N - k) % N);
+                const cpx zk = v[e], zp = lds[pB * A + lds_pad(kp)];
+                const cpx sa = cmk(0.5 * (zk.x + zp.x), 0.5 * (zk.y - zp.y));       // (Z + conj P)/2
+                const cpx df = cmk(zk.x - zp.x, zk.y + zp.y);                        //  Z - conj P
+                const cpx sb = cmk(0.5 * df.y, -0.5 * df.x);                         // /(2i)
+                const int m = 2 * k + h;
+                cpx* o = out + (size_t)m * N;
+                o[0] = sa;
+                o[1] = sb;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P5: x-direction complex-to-real with cropping.  Inverse of P1 (unnormalised).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
+                                                      const cpx* __restrict__ tw) {
+    using Gm = Geo<N>;
+    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPX, A = Gm::A;
+    __shared__ cpx lds[PP * A];
+    const int tid = threadIdx.x;
+    const int tA = tid % G, pA = tid / G;      // store role: consecutive x
+    const int pB = tid % PP, tB = tid / PP;    // load role: consecutive y
+    const int z = blockIdx.y;
+    const int y0 = blockIdx.x * 2 * PP;
+    const bool okA = (y0 + 2 * pA) < N, okB = (y0 + 2 * pB) < N;
+    const cpx* in = X1 + (size_t)z * (N + 1) * N + y0 + 2 * pB;
+
+    cpx acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = cmk(0.0, 0.0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cpx v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int m = 2 * (tB + G * e) + h;       // padded index 0..2n-1
+            const bool direct = m <= N;
+            const int mm = direct ? m : 2 * N - m;
+            cpx a = cmk(0.0, 0.0), b = cmk(0.0, 0.0);
+            if (okB) {
+                const cpx* p = in + (size_t)mm * N;
+                a = p[0];
+                b = p[1];
+            }
+            if (!direct) { a.y = -a.y; b.y = -b.y; }
+            v[e] = cmk(a.x - b.y, a.y + b.x);          // a + i b
+        }
+        fft<N, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], h ? cmulc(v[e], tw[tA + G * e]) : v[e]);
+        __syncthreads();
+    }
+    if (okA) {
+        double* ua = u + ((size_t)z * N + (y0 + 2 * pA)) * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = tA + G * e;
+            ua[j] = acc[e].x;
+            ua[N + j] = acc[e].y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P2: y-direction forward with zero padding.  Block = one kx, PPY consecutive z.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1, cpx* __restrict__ X2,
+                                                      const cpx* __restrict__ tw) {
+    using Gm = Geo<N>;
+    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
+    __shared__ cpx lds[PP * A];
+    const int tid = threadIdx.x;
+    const int tA = tid % G, pA = tid / G;      // load role: consecutive y
+    const int pB = tid % PP, tB = tid / PP;    // store role: consecutive z
+    const int kx = blockIdx.y;
+    const int z0 = blockIdx.x * PP;
+    const bool okA = (z0 + pA) < N, okB = (z0 + pB) < N;
+
+    cpx x[E];
+    {
+        const cpx* src = X1 + ((size_t)(z0 + pA) * (N + 1) + kx) * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = okA ? src[tA + G * e] : cmk(0.0, 0.0);
+    }
+    cpx* dst = X2 + (size_t)kx * 2 * N * N + z0 + pB;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cpx v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = h ? cmul(x[e], tw[tA + G * e]) : x[e];
+        fft<N, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
+        if (okB) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) dst[(size_t)(2 * (tB + G * e) + h) * N] = v[e];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P4: y-direction inverse with cropping.  Block = one kx, PPY consecutive z.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2, cpx* __restrict__ X1,
+                                                      const cpx* __restrict__ tw) {
+    using Gm = Geo<N>;
+    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
+    __shared__ cpx lds[PP * A];
+    const int tid = threadIdx.x;
+    const int tA = tid % G, pA = tid / G;      // store role: consecutive y
+    const int pB = tid % PP, tB = tid / PP;    // load role: consecutive z
+    const int kx = blockIdx.y;
+    const int z0 = blockIdx.x * PP;
+    const bool okA = (z0 + pA) < N, okB = (z0 + pB) < N;
+    const cpx* src = X2 + (size_t)kx * 2 * N * N + z0 + pB;
+
+    cpx acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = cmk(0.0, 0.0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cpx v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            v[e] = okB ? src[(size_t)(2 * (tB + G * e) + h) * N] : cmk(0.0, 0.0);
+        fft<N, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], h ? cmulc(v[e], tw[tA + G * e]) : v[e]);
+        __syncthreads();
+    }
+    if (okA) {
+        cpx* dst = X1 + ((size_t)(z0 + pA) * (N + 1) + kx) * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) dst[tA + G * e] = acc[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P3: fused forward transform along the contiguous axis, multiplication by the
+// stored spectrum (folded Taylor terms and 1/M included), inverse transform.
+// Each pencil is carried by two thread groups: the even (h = 0) and the odd
+// (h = 1) half of the padded spectrum.  DIM = 3: pencils X2[kx][ky][:],
+// spectrum row S[kx][|ky|][:]; DIM = 2: pencils X1[kx][:], row S[kx][:].
+// ---------------------------------------------------------------------------
+template <int N, int DIM, int MODE>
+__global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ X, const double* __restrict__ spec,
+                                                      const cpx* __restrict__ tw, int npencils,
+                                                      DipoleArgs dip) {
+    using Gm = Geo<N>;
+    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPZ, A = Gm::A;
+    __shared__ cpx lds[PP * 2 * A];
+    const int tid = threadIdx.x;
+    const int t = tid % G, h = (tid / G) & 1, pl = tid / (2 * G);
+    const int pencil = blockIdx.x * PP + pl;
+    const bool ok = pencil < npencils;
+    cpx* area = lds + (pl * 2 + h) * A;
+
+    int kx, ky = 0;
+    const double* srow;
+    if constexpr (DIM == 3) {
+        kx = pencil / (2 * N);
+        ky = pencil % (2 * N);
+        const int aky = ky <= N ? ky : 2 * N - ky;
+        srow = spec + ((size_t)kx * (N + 1) + aky) * (N + 1);
+    } else {
+        kx = pencil;
+        srow = spec + (size_t)kx * (N + 1);
+    }
+    cpx* base = X + (size_t)pencil * N;
+
+    cpx v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = t + G * e;
+        const cpx xv = ok ? base[j] : cmk(0.0, 0.0);
+        v[e] = h ? cmul(xv, tw[j]) : xv;
+    }
+    fft<N, false>(v, t, area, t, area, tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = 2 * (t + G * e) + h;          // padded index along the pencil
+        const int am = m <= N ? m : 2 * N - m;
+        double s = ok ? srow[am] : 0.0;
+        if constexpr (MODE == SPEC_DIPOLAR) {
+            // (n.xi)(m.xi) with Nyquist taken as 0 in the odd (cross) factors
+            const double xe = kx * dip.dxi;
+            const int sy = ky < N ? ky : ky - 2 * N;
+            const int sz = m < N ? m : m - 2 * N;
+            const double ye = sy * dip.dxi, ze = sz * dip.dxi;
+            const double xo = (kx == N) ? 0.0 : xe;
+            const double yo = (ky == N) ? 0.0 : ye;
+            const double zo = (m == N) ? 0.0 : ze;
+            const double f = dip.cdiag[0] * xe * xe + dip.cdiag[1] * ye * ye + dip.cdiag[2] * ze * ze +
+                             dip.ccross[0] * xo * yo + dip.ccross[1] * xo * zo + dip.ccross[2] * yo * zo;
+            s = f * s - dip.nm_over_M;
+        }
+        v[e] = cscale(v[e], s);
+    }
+    __syncthreads();
+    fft<N, true>(v, t, area, t, area, tw);
+    if (h) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cmulc(v[e], tw[t + G * e]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) area[lds_pad(t + G * e)] = v[e];
+    __syncthreads();
+    if (ok) {
+        const cpx* a0 = lds + (pl * 2) * A;
+        const cpx* a1 = a0 + A;
+#pragma unroll
+        for (int ee = 0; ee < E / 2; ++ee) {
+            const int j = t + G * (h * (E / 2) + ee);
+            base[j] = cadd(a0[lds_pad(j)], a1[lds_pad(j)]);
+        }
+    }
+}
+
+}  // namespace gsk

@@ -1,0 +1,115 @@
+"""Each evaluation pass on its own, against a NumPy DFT of the same layout.
+
+The plan's workspace is filled from the host (gs_plan_buffer), one pass runs
+(gs_eval_pass), and its output is read back.  Layouts (complex FP64):
+  X1[z][kx][y] (2D: X1[kx][y]), X2[kx][ky][z], spectrum octant S[k][k][k].
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1501_04438_amd as gs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-13
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def crandn(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def fold(n):
+    k = np.arange(2 * n)
+    return np.minimum(k, 2 * n - k)
+
+
+@pytest.mark.parametrize("n", [8, 12, 24, 64, 256])
+def test_3d_passes(n):
+    rng = np.random.default_rng(n)
+    plan = gs.Plan("coulomb3d", n=n, L=5.0)
+    dev = "cuda:0"
+    rho = rng.standard_normal((n, n, n))
+    rt = torch.from_numpy(rho).to(dev)
+    ut = torch.empty_like(rt)
+
+    # P1: rho[z][y][x] -> X1[z][kx][y]
+    plan.eval_pass(rt, ut, 1)
+    got = plan.buffer(1)
+    ref = np.fft.fft(rho, n=2 * n, axis=2)[:, :, : n + 1].transpose(0, 2, 1)
+    assert rel(got, ref) < TOL, "P1"
+
+    # P2: X1[z][kx][y] -> X2[kx][ky][z]
+    x1 = crandn(rng, (n, n + 1, n))
+    plan.buffer(1, x1)
+    plan.eval_pass(rt, ut, 2)
+    got = plan.buffer(2)
+    ref = np.fft.fft(x1, n=2 * n, axis=2).transpose(1, 2, 0)
+    assert rel(got, ref) < TOL, "P2"
+
+    # P3: along z, forward (padded), times S[kx][|ky|][|kz|], inverse (cropped)
+    S = plan.buffer(3)
+    x2 = crandn(rng, (n + 1, 2 * n, n))
+    plan.buffer(2, x2)
+    plan.eval_pass(rt, ut, 3)
+    got = plan.buffer(2)
+    f = fold(n)
+    Sf = S[:, f][:, :, f]                                   # [kx][ky][kz] over the padded ky, kz
+    ref = (np.fft.ifft(np.fft.fft(x2, n=2 * n, axis=2) * Sf, axis=2) * 2 * n)[:, :, :n]
+    assert rel(got, ref) < TOL, "P3"
+
+    # P4: X2[kx][ky][z] -> X1[z][kx][y], y < n
+    x3 = crandn(rng, (n + 1, 2 * n, n))
+    plan.buffer(2, x3)
+    plan.eval_pass(rt, ut, 4)
+    got = plan.buffer(1)
+    ref = (np.fft.ifft(x3, axis=1) * 2 * n)[:, :n, :].transpose(2, 0, 1)
+    assert rel(got, ref) < TOL, "P4"
+
+    # P5: X1[z][kx][y] (Hermitian half, DC and Nyquist real) -> u[z][y][x]
+    x4 = crandn(rng, (n, n + 1, n))
+    x4[:, 0, :] = x4[:, 0, :].real
+    x4[:, n, :] = x4[:, n, :].real
+    plan.buffer(1, x4)
+    plan.eval_pass(rt, ut, 5)
+    torch.cuda.synchronize()
+    got = ut.cpu().numpy()
+    ref = (np.fft.irfft(x4.transpose(0, 2, 1), n=2 * n, axis=2) * 2 * n)[:, :, :n]
+    assert rel(got, ref) < TOL, "P5"
+
+
+@pytest.mark.parametrize("n", [8, 48, 1024])
+def test_2d_passes(n):
+    rng = np.random.default_rng(n)
+    plan = gs.Plan("coulomb2d", n=n, L=5.0)
+    rho = rng.standard_normal((n, n))
+    rt = torch.from_numpy(rho).to("cuda:0")
+    ut = torch.empty_like(rt)
+    plan.eval_pass(rt, ut, 1)
+    ref = np.fft.fft(rho, n=2 * n, axis=1)[:, : n + 1].T
+    assert rel(plan.buffer(1), ref) < TOL, "P1"
+    S = plan.buffer(3)
+    x = crandn(rng, (n + 1, n))
+    plan.buffer(1, x)
+    plan.eval_pass(rt, ut, 3)
+    ref = (np.fft.ifft(np.fft.fft(x, n=2 * n, axis=1) * S[:, fold(n)], axis=1) * 2 * n)[:, :n]
+    assert rel(plan.buffer(1), ref) < TOL, "P3"
+    x4 = crandn(rng, (n + 1, n))
+    x4[0] = x4[0].real
+    x4[n] = x4[n].real
+    plan.buffer(1, x4)
+    plan.eval_pass(rt, ut, 5)
+    torch.cuda.synchronize()
+    ref = (np.fft.irfft(x4.T, n=2 * n, axis=1) * 2 * n)[:, :n]
+    assert rel(ut.cpu().numpy(), ref) < TOL, "P5"

@@ -65,23 +65,29 @@ def draw_mixture(rng: np.random.Generator, K: int, d: int, mu_range: float = 2.0
 
 
 def sample_mixture(m: Mixture, n: int, L: float) -> np.ndarray:
+    """Each component is a product of one-dimensional Gaussians (outer products)."""
     d = m.d
-    X = mesh(n, L, d)
+    ax = axis(n, L)
     out = np.zeros((n,) * d)
     for c in range(len(m.a)):
-        r2 = sum((X[i] - m.mu[c, i]) ** 2 for i in range(d))
-        out += m.a[c] * np.exp(-r2 / m.sigma[c] ** 2)
+        f = [np.exp(-((ax - m.mu[c, i]) ** 2) / m.sigma[c] ** 2) for i in range(d)]   # (x, y[, z])
+        if d == 3:
+            out += m.a[c] * (f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :])
+        else:
+            out += m.a[c] * (f[1][:, None] * f[0][None, :])
     return out
 
 
 def gaussian(n: int, L: float, d: int, sigma: float = 1.0, center=None,
              gammas=None, scale: float = 1.0) -> np.ndarray:
     """``scale * exp(-sum_i gamma_i^2 (x_i - c_i)^2 / sigma^2)`` on the grid."""
-    X = mesh(n, L, d)
+    ax = axis(n, L)
     center = np.zeros(d) if center is None else np.asarray(center, float)
     gammas = np.ones(d) if gammas is None else np.asarray(gammas, float)
-    r2 = sum((gammas[i] * (X[i] - center[i])) ** 2 for i in range(d))
-    return scale * np.exp(-r2 / sigma ** 2)
+    f = [np.exp(-((gammas[i] * (ax - center[i])) ** 2) / sigma ** 2) for i in range(d)]
+    if d == 3:
+        return scale * (f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :])
+    return scale * (f[1][:, None] * f[0][None, :])
 
 
 # --------------------------------------------------------------------------
