@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the Gaussian-sum potential evaluation on one MI355X.
+
+Metric: Mpts/s per potential evaluation, 3D Coulomb, n = 256 per axis, FP64,
+accuracy <= 1e-12 against the oracle.  Workload: the triaxial Gaussian
+exp(-(x^2 + 4y^2 + 16z^2)) plus an 8-component seeded Gaussian mixture on
+[-10, 10]^3 (workloads.config2), density resident in HBM, plan (tables,
+factors, spectrum assembly) built before the timed region, as the paper times
+evaluations only.  One step = one evaluation (all five passes).
+
+The timed loop launches the five passes separately with HIP events between
+them on the launching stream, which gives every pass's device time; the
+dominant pass is reported against the HBM roofline with its algorithmic bytes.
+Also reported: the oracle on a bounded sample of the same workload on the host
+cores (cpu_baseline), the batched (64 uneven problems) and adjoint figures.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
+PASS_NAMES = {1: "k_x_r2c", 2: "k_y_fwd", 3: "k_fused", 4: "k_y_inv", 5: "k_x_c2r"}
+KERNEL_SOURCES = ["paper_1501_04438_amd/csrc/passes.hpp", "paper_1501_04438_amd/csrc/fft_core.hpp",
+                  "paper_1501_04438_amd/csrc/eval_instance.hip"]
+
+
+def pass_bytes(n: int) -> dict:
+    """Algorithmic HBM bytes per launch of each 3D pass (each input read once,
+    each output written once, spectrum octant read once)."""
+    n1 = n + 1
+    x1 = 16 * n1 * n * n          # [z][kx][y] complex
+    x2 = 32 * n1 * n * n          # [kx][ky][z] complex
+    real = 8 * n ** 3
+    return {1: real + x1, 2: x1 + x2, 3: 2 * x2 + 8 * n1 ** 3, 4: x2 + x1, 5: x1 + real}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_coulomb3d_256.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
+
+
+def cpu_baseline(n_sample: int) -> dict:
+    """The oracle, as it stands, on the same workload at a smaller grid."""
+    import oracle
+    import workloads
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:
+        threads = os.cpu_count() or 1
+    p = workloads.config2(n_sample)
+    plan = oracle.make_plan("coulomb3d", 3, n_sample, p.L, eps=1e-14)
+    t0 = time.perf_counter()
+    oracle.evaluate(plan, p.rho)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample ** 3 / dt / 1e6, "unit": "Mpts/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one evaluation of the same workload at {n_sample}^3 (plan excluded), {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--cpu-sample-n", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint measurements")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE={world}) is not supported: "
+              "the evaluation runs on a single MI355X and has no multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1501_04438_amd as gs
+    import workloads
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    n = args.n
+    prob = workloads.config2(n)
+    plan = gs.Plan("coulomb3d", n=n, L=prob.L, eps=1e-14)
+    rho = torch.from_numpy(prob.rho).to(dev)
+    u = torch.empty_like(rho)
+    print(f"# plan: n={n} Q={plan.info['Q']} spectrum assembly {plan.info['assembly_ms']:.3f} ms "
+          f"({plan.info['assembly_gflop']:.2f} GFLOP)", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        plan.eval(rho, out=u)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(K):
+        ev[s][0].record()
+        for p in range(1, 6):
+            plan.eval_pass(rho, u, p)
+            ev[s][p].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_step = wall / K * 1e3
+    pass_ms = {p: float(np.mean([ev[s][p - 1].elapsed_time(ev[s][p]) for s in range(K)])) for p in range(1, 6)}
+    gpu_ms = float(np.mean([ev[s][0].elapsed_time(ev[s][5]) for s in range(K)]))
+    value = n ** 3 / (wall / K) / 1e6
+
+    nb = pass_bytes(n)
+    dom = max(pass_ms, key=pass_ms.get)
+    achieved = nb[dom] / (pass_ms[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(PASS_NAMES[dom])
+    passes = {PASS_NAMES[p]: {"ms": round(pass_ms[p], 5), "alg_bytes": nb[p],
+                              "GB_s": round(nb[p] / (pass_ms[p] * 1e-3) / 1e9, 1)} for p in range(1, 6)}
+    total_bytes = sum(nb.values())
+
+    # accuracy of this very output against stored oracle samples
+    acc = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"oracle_c2_coulomb3d_{n}.npz")
+    if os.path.exists(gpath):
+        g = np.load(gpath)
+        plan.eval(rho, out=u)
+        uh = u.cpu().numpy()
+        acc = float(np.max(np.abs(uh[tuple(g["idx"].T)] - g["u"])) / float(g["umax"]))
+
+    out = {
+        "metric": "Mpts/s per potential eval, 3D Coulomb 256^3 FP64 @<=1e-12",
+        "value": round(value, 1), "unit": "Mpts/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"coulomb3d_{n}_triaxial_plus_8_gaussian_mixture_L10", "n": n, "L": prob.L,
+                   "kernel": "coulomb3d", "eps": 1e-14, "delta_rel": 1e-4, "Q": plan.info["Q"]},
+        "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "gpu_ms_per_eval_events": round(gpu_ms, 5),
+        "eval_alg_bytes": total_bytes,
+        "eval_GB_s": round(total_bytes / (gpu_ms * 1e-3) / 1e9, 1),
+        "eval_frac_hbm": round(total_bytes / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "passes": passes,
+        "max_rel_err_vs_oracle_samples": acc,
+        "assembly": {"ms": round(plan.info["assembly_ms"], 4), "gflop": round(plan.info["assembly_gflop"], 3),
+                     "tflops": round(plan.info["assembly_gflop"] / max(plan.info["assembly_ms"], 1e-9), 2),
+                     "frac_fp64_mfma": round(plan.info["assembly_gflop"] / max(plan.info["assembly_ms"], 1e-9)
+                                             / FP64_MFMA_PEAK_TFLOPS, 4)},
+        "paper_context": {"value": 0.850, "unit": "Mpts/s", "hardware": "Xeon E5540 2.53 GHz, Fortran, ifort -O3",
+                          "workload": "3D Coulomb 256^3, isotropic Gaussian sigma=1.2 on [-8,8]^3 (Table 1)"},
+    }
+
+    if not args.no_extras:
+        out["adjoint"] = adjoint_figures(gs, torch, plan, rho, K)
+        out["batched"] = batched_figures(gs, torch, workloads)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def adjoint_figures(gs, torch, plan, rho, K):
+    """The adjoint chain alone, and energy + rho-gradient through autograd."""
+    g = torch.empty_like(rho)
+    for _ in range(2):
+        plan.eval_backward(rho, out=g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        plan.eval_backward(rho, out=g)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / K
+    r = rho.clone().requires_grad_(True)
+    E = gs.energy(r, plan)
+    E.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(3, K // 5)
+    for _ in range(reps):
+        r.grad = None
+        E = gs.energy(r, plan)
+        E.backward()
+    torch.cuda.synchronize()
+    dte = (time.perf_counter() - t0) / reps
+    n3 = rho.numel()
+    return {"backward_Mpts_s": round(n3 / dt / 1e6, 1), "backward_ms": round(dt * 1e3, 4),
+            "energy_and_grad_Mpts_s": round(n3 / dte / 1e6, 1), "energy_and_grad_ms": round(dte * 1e3, 4)}
+
+
+def batched_figures(gs, torch, workloads, reps: int = 5):
+    """64 seeded mixtures on uneven grids: one batched call versus 64 single solves."""
+    probs = [workloads.materialise(p) for p in workloads.config4(64)]
+    plans = [gs.Plan("coulomb3d", n=p.n, L=p.L, eps=1e-14) for p in probs]
+    rhos = [torch.from_numpy(p.rho).to("cuda:0") for p in probs]
+    outs = [torch.empty_like(r) for r in rhos]
+    pts = sum(p.n ** 3 for p in probs)
+    gs.eval_batch(plans, rhos, outs)
+    for pl, r, o in zip(plans, rhos, outs):
+        pl.eval(r, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        gs.eval_batch(plans, rhos, outs)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for pl, r, o in zip(plans, rhos, outs):
+            pl.eval(r, out=o)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / reps
+    return {"problems": len(probs), "points": pts, "batched_Mpts_s": round(pts / tb / 1e6, 1),
+            "batched_ms": round(tb * 1e3, 3), "single_solves_Mpts_s": round(pts / ts / 1e6, 1),
+            "single_solves_ms": round(ts * 1e3, 3)}
+
+
+if __name__ == "__main__":
+    sys.exit(main())
