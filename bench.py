@@ -85,6 +85,24 @@ def cpu_baseline(n_sample: int) -> dict:
             "sample": f"one evaluation of the same workload at {n_sample}^3 (plan excluded), {dt:.1f} s"}
 
 
+def copy_bandwidth(torch, mib: int = 2048, reps: int = 20) -> float:
+    """Device-to-device copy of a 2 GiB buffer (read + write bytes / time): the
+    practical HBM ceiling on this machine, reported next to the datasheet peak."""
+    a = torch.empty(mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * mib * 2 ** 20 / (ms * 1e-3) / 1e9
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +197,7 @@ def main() -> int:
                           "workload": "3D Coulomb 256^3, isotropic Gaussian sigma=1.2 on [-8,8]^3 (Table 1)"},
     }
 
+    out["copy_GB_s"] = round(copy_bandwidth(torch), 1)
     if not args.no_extras:
         out["adjoint"] = adjoint_figures(gs, torch, plan, rho, K)
         out["batched"] = batched_figures(gs, torch, workloads)

@@ -23,6 +23,7 @@ struct EvalArgs {
     double cdiag[3] = {0, 0, 0};
     double ccross[3] = {0, 0, 0};
     double nm_over_M = 0.0;
+    int max_blocks_fused = 0;         // persistent grid size of the fused pass (0 = no cap)
 };
 
 // Passes: 1 x_r2c, 2 y_fwd, 3 fused, 4 y_inv, 5 x_c2r.  `which` < 0 runs the full chain.

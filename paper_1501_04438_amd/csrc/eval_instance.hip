@@ -13,6 +13,20 @@
 
 namespace gsk {
 
+// persistent grid of the fused pass: at most `cap` blocks (0 = one per group)
+static inline unsigned fused_grid(int groups, int cap) {
+    return (unsigned)((cap > 0 && groups > cap) ? cap : groups);
+}
+
+// Co-resident blocks of a kernel on the whole device (CUs x blocks per CU), computed once.
+static int resident_blocks(const void* fn, int threads) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, 0) != hipSuccess) return 0;
+    return cus * (per > 0 ? per : 1);
+}
+
 hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int which) {
     constexpr int N = GS_N;
     using Gm = Geo<N>;
@@ -24,6 +38,9 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
     }
     dip.nm_over_M = a.nm_over_M;
     const int nz = (a.d == 3) ? N : 1;
+    static const int cap3 = resident_blocks((const void*)k_fused<N, 3, SPEC_PLAIN>, Gm::TZ);
+    static const int cap2 = resident_blocks((const void*)k_fused<N, 2, SPEC_PLAIN>, Gm::TZ);
+    const int capf = a.max_blocks_fused > 0 ? a.max_blocks_fused : (a.d == 3 ? cap3 : cap2);
     const dim3 gx((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX), nz);
     auto run = [&](int p) { return which < 0 || which == p; };
     if (run(1)) k_x_r2c<N><<<gx, Gm::TX, 0, s>>>(a.rho, a.X1, a.tw);
@@ -33,7 +50,7 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
         const int np = (N + 1) * 2 * N;
         if (run(2)) k_y_fwd<N><<<gy, Gm::TY, 0, s>>>(a.X1, a.X2, a.tw);
         if (run(3)) {
-            const unsigned nb = (np + Gm::PPZ - 1) / Gm::PPZ;
+            const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf);
             if (a.dipolar)
                 k_fused<N, 3, SPEC_DIPOLAR><<<nb, Gm::TZ, 0, s>>>(a.X2, a.spec, a.tw, np, dip);
             else
@@ -46,7 +63,7 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
     }
     {
         const int np = N + 1;
-        const unsigned nb = (np + Gm::PPZ - 1) / Gm::PPZ;
+        const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf);
         if (run(3)) k_fused<N, 2, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(a.X1, a.spec, a.tw, np, dip);
     }
     if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(a.X1, a.u, a.tw);

@@ -44,26 +44,37 @@ template <bool INV> __device__ __forceinline__ cpx mul_mi(cpx a) {
 }
 
 // ---------------------------------------------------------------------------
-// Exact unit roots exp(-2 pi i e / R) for R dividing 48 (radices 2,3,4,6,8,12,16).
+// Exact unit roots exp(-2 pi i e / R) for R dividing 96 (radices 2,3,4,6,8,12,16
+// and the padding twists of 16, 24, 32 and 48 points).
 // ---------------------------------------------------------------------------
 struct CS { double c, s; };
 
-// cos and sin of a*pi/24 for a = 0..12 (only multiples of 3 or 4 occur)
+// cos and sin of a*pi/48 for the a in [0, 24] that occur
 constexpr CS first_quadrant(int a) {
     return a == 0  ? CS{1.0, 0.0}
-         : a == 3  ? CS{0.92387953251128675613, 0.38268343236508977173}
-         : a == 4  ? CS{0.86602540378443864676, 0.5}
-         : a == 6  ? CS{0.70710678118654752440, 0.70710678118654752440}
-         : a == 8  ? CS{0.5, 0.86602540378443864676}
-         : a == 9  ? CS{0.38268343236508977173, 0.92387953251128675613}
-         : a == 12 ? CS{0.0, 1.0}
+         : a == 2  ? CS{0.991444861373810411145, 0.130526192220051591548}
+         : a == 3  ? CS{0.980785280403230449126, 0.195090322016128267848}
+         : a == 4  ? CS{0.96592582628906828675, 0.258819045102520762349}
+         : a == 6  ? CS{0.923879532511286756128, 0.382683432365089771728}
+         : a == 8  ? CS{0.866025403784438646764, 0.5}
+         : a == 9  ? CS{0.831469612302545237079, 0.555570233019602224743}
+         : a == 10 ? CS{0.79335334029123516458, 0.608761429008720639416}
+         : a == 12 ? CS{0.707106781186547524401, 0.707106781186547524401}
+         : a == 14 ? CS{0.608761429008720639416, 0.79335334029123516458}
+         : a == 15 ? CS{0.555570233019602224743, 0.831469612302545237079}
+         : a == 16 ? CS{0.5, 0.866025403784438646764}
+         : a == 18 ? CS{0.382683432365089771728, 0.923879532511286756128}
+         : a == 20 ? CS{0.258819045102520762349, 0.96592582628906828675}
+         : a == 21 ? CS{0.195090322016128267848, 0.980785280403230449126}
+         : a == 22 ? CS{0.130526192220051591548, 0.991444861373810411145}
+         : a == 24 ? CS{0.0, 1.0}
                    : CS{2.0, 2.0};   // unreachable for the supported radices
 }
 
 // cos/sin of 2 pi e / R
 constexpr CS unit_root(int e, int R) {
-    int a = ((e % R + R) % R) * (48 / R);     // angle = a * pi / 24, a in [0, 48)
-    int q = a / 12, r = a % 12;
+    int a = ((e % R + R) % R) * (96 / R);     // angle = a * pi / 48, a in [0, 96)
+    int q = a / 24, r = a % 24;
     CS b = first_quadrant(r);
     return q == 0 ? CS{b.c, b.s} : q == 1 ? CS{-b.s, b.c} : q == 2 ? CS{-b.c, -b.s} : CS{b.s, -b.c};
 }
@@ -168,36 +179,84 @@ template <int S, bool INV> struct Dft<16, S, INV> {
 };
 
 // ---------------------------------------------------------------------------
-// Per-size plans: E values per thread and the stage radices (product = N).
+// Transform plans: length N carried by G = N/E threads with E values each, the
+// stage radices R[0..NS-1] (product N, each dividing E).
 // ---------------------------------------------------------------------------
+template <int N_, int E_, int NS_, int R0_, int R1_ = 1, int R2_ = 1, int R3_ = 1>
+struct FftPlan {
+    static constexpr int N = N_, E = E_, NS = NS_, G = N_ / E_;
+    static constexpr int R[4] = {R0_, R1_, R2_, R3_};
+};
+
+// Default plans (few stages: one LDS exchange for n <= 256).
 template <int N> struct FftCfg;
-#define GSK_FFT_CFG(N_, E_, NS_, R0_, R1_, R2_, R3_)                              \
-    template <> struct FftCfg<N_> {                                               \
-        static constexpr int E = E_, NS = NS_, G = N_ / E_;                       \
-        static constexpr int R[4] = {R0_, R1_, R2_, R3_};                         \
-    };
-GSK_FFT_CFG(8, 8, 1, 8, 1, 1, 1)
-GSK_FFT_CFG(12, 12, 2, 4, 3, 1, 1)
-GSK_FFT_CFG(16, 16, 1, 16, 1, 1, 1)
-GSK_FFT_CFG(24, 24, 2, 8, 3, 1, 1)
-GSK_FFT_CFG(32, 8, 2, 4, 8, 1, 1)
-GSK_FFT_CFG(48, 12, 3, 4, 4, 3, 1)
-GSK_FFT_CFG(64, 8, 2, 8, 8, 1, 1)
-GSK_FFT_CFG(96, 12, 4, 4, 4, 2, 3)
-GSK_FFT_CFG(128, 16, 2, 16, 8, 1, 1)
-GSK_FFT_CFG(192, 12, 4, 4, 4, 4, 3)
-GSK_FFT_CFG(256, 16, 2, 16, 16, 1, 1)
-GSK_FFT_CFG(512, 8, 3, 8, 8, 8, 1)
-GSK_FFT_CFG(1024, 16, 3, 16, 16, 4, 1)
-GSK_FFT_CFG(2048, 16, 3, 16, 16, 8, 1)
-#undef GSK_FFT_CFG
+template <> struct FftCfg<8> : FftPlan<8, 8, 1, 8> {};
+template <> struct FftCfg<12> : FftPlan<12, 12, 2, 4, 3> {};
+template <> struct FftCfg<16> : FftPlan<16, 16, 1, 16> {};
+template <> struct FftCfg<24> : FftPlan<24, 24, 2, 8, 3> {};
+template <> struct FftCfg<32> : FftPlan<32, 8, 2, 4, 8> {};
+template <> struct FftCfg<48> : FftPlan<48, 12, 3, 4, 4, 3> {};
+template <> struct FftCfg<64> : FftPlan<64, 8, 2, 8, 8> {};
+template <> struct FftCfg<96> : FftPlan<96, 12, 4, 4, 4, 2, 3> {};
+template <> struct FftCfg<128> : FftPlan<128, 16, 2, 16, 8> {};
+template <> struct FftCfg<192> : FftPlan<192, 12, 4, 4, 4, 4, 3> {};
+template <> struct FftCfg<256> : FftPlan<256, 16, 2, 16, 16> {};
+template <> struct FftCfg<512> : FftPlan<512, 8, 3, 8, 8, 8> {};
+template <> struct FftCfg<1024> : FftPlan<1024, 16, 3, 16, 16, 4> {};
+template <> struct FftCfg<2048> : FftPlan<2048, 16, 3, 16, 16, 8> {};
+
+// Plans for the fused spectrum pass, which keeps a prefetch buffer live through
+// its transforms: fewer values per thread where that matters (n = 256: 8 values,
+// radices 8, 8, 4, a 32-thread transform).
+template <int N> struct FftCfgFused : FftCfg<N> {};
+template <> struct FftCfgFused<256> : FftPlan<256, 8, 3, 8, 8, 4> {};
+
+// Block barrier ordering LDS only: global loads in flight (prefetches) are not
+// drained, unlike __syncthreads(), whose workgroup fence covers global memory.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// LDS ordering among the lanes of one wave (LDS operations of a wave execute in
+// order; this keeps the compiler from reordering across it).
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+template <bool WAVE> __device__ __forceinline__ void lds_sync() {
+    if constexpr (WAVE) lds_wave_sync();
+    else lds_barrier();
+}
 
 // LDS area of one transform: one 16-byte pad slot after every 16 elements so that
 // the strided Stockham scatters spread over the banks.
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 template <int N> struct LdsArea { static constexpr int size = N + N / 16 + 1; };
 
+// v[r S] *= w^r (conj for INV), r = 1..R-1, with w^{4a+c} = (w^4)^a w^c formed from
+// w1 = w and w4 = w^4: at most three multiplications deep.
+template <int R, int S, bool INV>
+__device__ __forceinline__ void mul_powers(cpx* v, cpx w1, cpx w4) {
+    const cpx p2 = cmul(w1, w1);
+    const cpx p3 = cmul(p2, w1);
+    const cpx q2 = cmul(w4, w4);
+    const cpx q3 = cmul(q2, w4);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        const int a = r / 4, c = r % 4;
+        const cpx pc = c == 1 ? w1 : (c == 2 ? p2 : p3);
+        const cpx qa = a == 1 ? w4 : (a == 2 ? q2 : q3);
+        const cpx w = (a == 0) ? pc : (c == 0 ? qa : cmul(qa, pc));
+        v[r * S] = INV ? cmulc(v[r * S], w) : cmul(v[r * S], w);
+    }
+}
+
 // One Stockham stage on registers: twiddles (unless first) and E/R DFTs of radix R.
+// The twiddles W_N^{base r} are powers of W_N^{base} (two table reads per butterfly).
 template <int N, int E, int R, int NSPRE, bool INV>
 __device__ __forceinline__ void stage_compute(cpx (&v)[E], int t, const cpx* __restrict__ tw) {
     constexpr int G = N / E, B = E / R;
@@ -206,14 +265,33 @@ __device__ __forceinline__ void stage_compute(cpx (&v)[E], int t, const cpx* __r
         if constexpr (NSPRE > 1) {
             const int j = t + b * G;
             const int base = (j % NSPRE) * (N / (NSPRE * R));
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                const cpx w = tw[2 * base * r];     // W_N^{base r} = W_{2N}^{2 base r}
-                v[b + r * B] = INV ? cmulc(v[b + r * B], w) : cmul(v[b + r * B], w);
-            }
+            const cpx w1 = tw[2 * base];                          // W_N^base = W_2N^{2 base}
+            const cpx w4 = (R > 4) ? tw[8 * base] : w1;           // W_N^{4 base}, 4 base < N
+            mul_powers<R, B, INV>(&v[b], w1, w4);
         }
         Dft<R, B, INV>::run(&v[b]);
     }
+}
+
+// Padding twist before a forward transform: x[j] *= W_2N^j for j = t + G e, as
+// W_2N^t (one table read) times the constant W_2E^e.
+template <class P>
+__device__ __forceinline__ void twist_in(cpx (&v)[P::E], int t, const cpx* __restrict__ tw) {
+    constexpr int E = P::E;
+    const cpx c = tw[t];
+    [&]<int... I>(std::integer_sequence<int, I...>) {
+        ((v[I] = cmul(twiddle_const<I, 2 * E, false>(v[I]), c)), ...);
+    }(std::make_integer_sequence<int, E>{});
+}
+
+// Cropping twist after an inverse transform: y[j] *= conj(W_2N^j), j = t + G e.
+template <class P>
+__device__ __forceinline__ void twist_out(cpx (&v)[P::E], int t, const cpx* __restrict__ tw) {
+    constexpr int E = P::E;
+    const cpx c = tw[t];
+    [&]<int... I>(std::integer_sequence<int, I...>) {
+        ((v[I] = cmulc(twiddle_const<I, 2 * E, true>(v[I]), c)), ...);
+    }(std::make_integer_sequence<int, E>{});
 }
 
 template <int N, int E, int R, int NSPRE>
@@ -237,32 +315,34 @@ __device__ __forceinline__ void stage_gather(cpx (&v)[E], int t, const cpx* lds)
 
 // Full length-N transform.  On entry thread t1 holds x[t1 + G e]; on exit thread t2
 // holds X[t2 + G e].  lds1/lds2 are the LDS areas of the transform as seen by the
-// two thread roles.  Contains block barriers: every thread of the block must call
-// it, and the areas must not be in use by other threads when it is entered.
-template <int N, bool INV>
-__device__ __forceinline__ void fft(cpx (&v)[FftCfg<N>::E], int t1, cpx* lds1, int t2, cpx* lds2,
+// two thread roles.  WAVE = true when both roles coincide and the G threads of a
+// transform lie in one wave (only wave-level ordering is then needed); otherwise
+// it contains block barriers and every thread of the block must call it.  The
+// areas must not be in use by other threads when it is entered.
+template <class C, bool INV, bool WAVE = false>
+__device__ __forceinline__ void fft(cpx (&v)[C::E], int t1, cpx* lds1, int t2, cpx* lds2,
                                     const cpx* __restrict__ tw) {
-    using C = FftCfg<N>;
+    constexpr int N = C::N;
     constexpr int E = C::E;
     constexpr int R0 = C::R[0], R1 = C::R[1], R2 = C::R[2], R3 = C::R[3];
     stage_compute<N, E, R0, 1, INV>(v, t1, tw);
     if constexpr (C::NS >= 2) {
         stage_scatter<N, E, R0, 1>(v, t1, lds1);
-        __syncthreads();
+        lds_sync<WAVE>();
         stage_gather<N, E>(v, t2, lds2);
         stage_compute<N, E, R1, R0, INV>(v, t2, tw);
     }
     if constexpr (C::NS >= 3) {
-        __syncthreads();
+        lds_sync<WAVE>();
         stage_scatter<N, E, R1, R0>(v, t2, lds2);
-        __syncthreads();
+        lds_sync<WAVE>();
         stage_gather<N, E>(v, t2, lds2);
         stage_compute<N, E, R2, R0 * R1, INV>(v, t2, tw);
     }
     if constexpr (C::NS >= 4) {
-        __syncthreads();
+        lds_sync<WAVE>();
         stage_scatter<N, E, R2, R0 * R1>(v, t2, lds2);
-        __syncthreads();
+        lds_sync<WAVE>();
         stage_gather<N, E>(v, t2, lds2);
         stage_compute<N, E, R3, R0 * R1 * R2, INV>(v, t2, tw);
     }

@@ -38,14 +38,17 @@ struct DipoleArgs {
 // Launch geometry per transform length.
 // ---------------------------------------------------------------------------
 template <int N> struct Geo {
-    static constexpr int E = FftCfg<N>::E, G = FftCfg<N>::G, A = LdsArea<N>::size;
+    using F = FftCfg<N>;          // transforms of the x and y passes
+    using FZ = FftCfgFused<N>;    // transforms of the fused pass
+    static constexpr int E = F::E, G = F::G, A = LdsArea<N>::size;
+    static constexpr int EZ = FZ::E, GZ = FZ::G;
     // P1/P5: pairs of real rows per block (2*PPX rows of y, 16-byte complex each)
     static constexpr int PPX = (N <= 256) ? 8 : (N <= 512 ? 4 : (N <= 1024 ? 2 : 1));
     // P2/P4: z-pencils per block
     static constexpr int PPY = (N <= 256) ? 16 : 8;
     // P3: pencils per block (two half-transforms each)
-    static constexpr int PPZ = (2 * G >= 128) ? 1 : 128 / (2 * G);
-    static constexpr int TX = PPX * G, TY = PPY * G, TZ = PPZ * 2 * G;
+    static constexpr int PPZ = (2 * GZ >= 128) ? 1 : 128 / (2 * GZ);
+    static constexpr int TX = PPX * G, TY = PPY * G, TZ = PPZ * 2 * GZ;
 };
 
 // ---------------------------------------------------------------------------
@@ -80,12 +83,13 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c(const double* __restrict__
     for (int h = 0; h < 2; ++h) {
         cpx v[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = h ? cmul(x[e], tw[tA + G * e]) : x[e];
-        fft<N, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
-        __syncthreads();
+        for (int e = 0; e < E; ++e) v[e] = x[e];
+        if (h) twist_in<typename Gm::F>(v, tA, tw);
+        fft<typename Gm::F, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
+        lds_barrier();
 #pragma unroll
         for (int e = 0; e < E; ++e) lds[pB * A + lds_pad(tB + G * e)] = v[e];
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = tB + G * e;
@@ -102,7 +106,7 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c(const double* __restrict__
                 o[1] = sb;
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -143,10 +147,11 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1
             if (!direct) { a.y = -a.y; b.y = -b.y; }
             v[e] = cmk(a.x - b.y, a.y + b.x);          // a + i b
         }
-        fft<N, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
+        fft<typename Gm::F, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
+        if (h) twist_out<typename Gm::F>(v, tA, tw);
 #pragma unroll
-        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], h ? cmulc(v[e], tw[tA + G * e]) : v[e]);
-        __syncthreads();
+        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], v[e]);
+        lds_barrier();
     }
     if (okA) {
         double* ua = u + ((size_t)z * N + (y0 + 2 * pA)) * N;
@@ -186,13 +191,14 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1
     for (int h = 0; h < 2; ++h) {
         cpx v[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = h ? cmul(x[e], tw[tA + G * e]) : x[e];
-        fft<N, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
+        for (int e = 0; e < E; ++e) v[e] = x[e];
+        if (h) twist_in<typename Gm::F>(v, tA, tw);
+        fft<typename Gm::F, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
         if (okB) {
 #pragma unroll
             for (int e = 0; e < E; ++e) dst[(size_t)(2 * (tB + G * e) + h) * N] = v[e];
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -222,10 +228,11 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2
 #pragma unroll
         for (int e = 0; e < E; ++e)
             v[e] = okB ? src[(size_t)(2 * (tB + G * e) + h) * N] : cmk(0.0, 0.0);
-        fft<N, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
+        fft<typename Gm::F, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
+        if (h) twist_out<typename Gm::F>(v, tA, tw);
 #pragma unroll
-        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], h ? cmulc(v[e], tw[tA + G * e]) : v[e]);
-        __syncthreads();
+        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], v[e]);
+        lds_barrier();
     }
     if (okA) {
         cpx* dst = X1 + ((size_t)(z0 + pA) * (N + 1) + kx) * N;
@@ -240,79 +247,145 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2
 // Each pencil is carried by two thread groups: the even (h = 0) and the odd
 // (h = 1) half of the padded spectrum.  DIM = 3: pencils X2[kx][ky][:],
 // spectrum row S[kx][|ky|][:]; DIM = 2: pencils X1[kx][:], row S[kx][:].
+//
+// Persistent: a block walks pencil groups g = blockIdx.x, + gridDim.x, ...
+// and issues the global loads of the next group (pencil data and spectrum
+// values) before transforming the current one, so that every wave keeps memory
+// requests in flight through its FFT arithmetic.  In 3D the pencils of a kx
+// plane are visited in the order ky = 0, n, 1, 2n-1, 2, 2n-2, ...: the two
+// pencils +ky and -ky that share a spectrum row sit in the same block.
 // ---------------------------------------------------------------------------
+template <int N, int DIM>
+__device__ __forceinline__ int fused_pencil(int slot) {
+    if constexpr (DIM == 2) {
+        return slot;
+    } else {
+        const int kx = slot / (2 * N), s = slot % (2 * N);
+        const int i = s >> 1;
+        const int ky = (s == 0) ? 0 : (s == 1) ? N : ((s & 1) ? 2 * N - i : i);
+        return kx * 2 * N + ky;
+    }
+}
+
+template <int N, int DIM>
+__device__ __forceinline__ const double* fused_row(const double* spec, int pencil) {
+    if constexpr (DIM == 3) {
+        const int kx = pencil / (2 * N), ky = pencil % (2 * N);
+        const int aky = ky <= N ? ky : 2 * N - ky;
+        return spec + ((size_t)kx * (N + 1) + aky) * (N + 1);
+    } else {
+        return spec + (size_t)pencil * (N + 1);
+    }
+}
+
+template <int N, int DIM>
+__device__ __forceinline__ void fused_load(const cpx* X, int pencil, bool ok, int t, cpx (&v)[FftCfgFused<N>::E]) {
+    constexpr int E = FftCfgFused<N>::E, G = FftCfgFused<N>::G;
+    const cpx* base = X + (size_t)pencil * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = ok ? base[t + G * e] : cmk(0.0, 0.0);
+}
+
+template <int N, int DIM>
+__device__ __forceinline__ void fused_spec(const double* spec, int pencil, bool ok, int t, int h,
+                                           double (&sv)[FftCfgFused<N>::E]) {
+    constexpr int E = FftCfgFused<N>::E, G = FftCfgFused<N>::G;
+    const double* srow = fused_row<N, DIM>(spec, ok ? pencil : 0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = 2 * (t + G * e) + h;          // padded index along the pencil
+        sv[e] = ok ? srow[m <= N ? m : 2 * N - m] : 0.0;
+    }
+}
+
 template <int N, int DIM, int MODE>
 __global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ X, const double* __restrict__ spec,
                                                       const cpx* __restrict__ tw, int npencils,
                                                       DipoleArgs dip) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPZ, A = Gm::A;
+    using FZ = typename Gm::FZ;
+    constexpr int E = Gm::EZ, G = Gm::GZ, PP = Gm::PPZ, A = Gm::A;
+    // a transform's G threads within one wave: wave-level LDS ordering suffices;
+    // the even/odd combine needs both halves (2G threads) within one wave
+    constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
     __shared__ cpx lds[PP * 2 * A];
     const int tid = threadIdx.x;
     const int t = tid % G, h = (tid / G) & 1, pl = tid / (2 * G);
-    const int pencil = blockIdx.x * PP + pl;
-    const bool ok = pencil < npencils;
     cpx* area = lds + (pl * 2 + h) * A;
+    const int ngroups = (npencils + PP - 1) / PP;
 
-    int kx, ky = 0;
-    const double* srow;
-    if constexpr (DIM == 3) {
-        kx = pencil / (2 * N);
-        ky = pencil % (2 * N);
-        const int aky = ky <= N ? ky : 2 * N - ky;
-        srow = spec + ((size_t)kx * (N + 1) + aky) * (N + 1);
-    } else {
-        kx = pencil;
-        srow = spec + (size_t)kx * (N + 1);
+    int g = blockIdx.x;
+    cpx nv[E];
+    double ns[E];
+    {
+        const int slot = g * PP + pl;
+        const bool ok0 = slot < npencils;
+        const int p0 = ok0 ? fused_pencil<N, DIM>(slot) : 0;
+        fused_load<N, DIM>(X, p0, ok0, t, nv);
+        fused_spec<N, DIM>(spec, p0, ok0, t, h, ns);
     }
-    cpx* base = X + (size_t)pencil * N;
-
-    cpx v[E];
+    for (; g < ngroups; g += gridDim.x) {
+        const int slot = g * PP + pl;
+        const bool ok = slot < npencils;
+        const int pencil = ok ? fused_pencil<N, DIM>(slot) : 0;
+        cpx v[E];
+        double sv[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int j = t + G * e;
-        const cpx xv = ok ? base[j] : cmk(0.0, 0.0);
-        v[e] = h ? cmul(xv, tw[j]) : xv;
-    }
-    fft<N, false>(v, t, area, t, area, tw);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int m = 2 * (t + G * e) + h;          // padded index along the pencil
-        const int am = m <= N ? m : 2 * N - m;
-        double s = ok ? srow[am] : 0.0;
+        for (int e = 0; e < E; ++e) {
+            v[e] = nv[e];
+            sv[e] = ns[e];
+        }
+        {   // prefetch the next group's pencils and spectrum values while this one is transformed
+            const int gn = g + gridDim.x;
+            const int sn = gn * PP + pl;
+            const bool okn = gn < ngroups && sn < npencils;
+            const int pn = okn ? fused_pencil<N, DIM>(sn) : 0;
+            fused_load<N, DIM>(X, pn, okn, t, nv);
+            fused_spec<N, DIM>(spec, pn, okn, t, h, ns);
+        }
+        if (h) twist_in<FZ>(v, t, tw);
+        fft<FZ, false, FW>(v, t, area, t, area, tw);
         if constexpr (MODE == SPEC_DIPOLAR) {
             // (n.xi)(m.xi) with Nyquist taken as 0 in the odd (cross) factors
+            const int kx = (DIM == 3) ? pencil / (2 * N) : pencil;
+            const int ky = (DIM == 3) ? pencil % (2 * N) : 0;
             const double xe = kx * dip.dxi;
             const int sy = ky < N ? ky : ky - 2 * N;
-            const int sz = m < N ? m : m - 2 * N;
-            const double ye = sy * dip.dxi, ze = sz * dip.dxi;
+            const double ye = sy * dip.dxi;
             const double xo = (kx == N) ? 0.0 : xe;
             const double yo = (ky == N) ? 0.0 : ye;
-            const double zo = (m == N) ? 0.0 : ze;
-            const double f = dip.cdiag[0] * xe * xe + dip.cdiag[1] * ye * ye + dip.cdiag[2] * ze * ze +
-                             dip.ccross[0] * xo * yo + dip.ccross[1] * xo * zo + dip.ccross[2] * yo * zo;
-            s = f * s - dip.nm_over_M;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int m = 2 * (t + G * e) + h;
+                const int sz = m < N ? m : m - 2 * N;
+                const double ze = sz * dip.dxi;
+                const double zo = (m == N) ? 0.0 : ze;
+                const double f = dip.cdiag[0] * xe * xe + dip.cdiag[1] * ye * ye + dip.cdiag[2] * ze * ze +
+                                 dip.ccross[0] * xo * yo + dip.ccross[1] * xo * zo + dip.ccross[2] * yo * zo;
+                v[e] = cscale(v[e], f * sv[e] - dip.nm_over_M);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sv[e]);
         }
-        v[e] = cscale(v[e], s);
-    }
-    __syncthreads();
-    fft<N, true>(v, t, area, t, area, tw);
-    if (h) {
+        lds_sync<FW>();
+        fft<FZ, true, FW>(v, t, area, t, area, tw);
+        if (h) twist_out<FZ>(v, t, tw);
+        lds_sync<FW>();
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cmulc(v[e], tw[t + G * e]);
-    }
-    __syncthreads();
+        for (int e = 0; e < E; ++e) area[lds_pad(t + G * e)] = v[e];
+        lds_sync<CW>();
+        if (ok) {
+            cpx* base = X + (size_t)pencil * N;
+            const cpx* a0 = lds + (pl * 2) * A;
+            const cpx* a1 = a0 + A;
 #pragma unroll
-    for (int e = 0; e < E; ++e) area[lds_pad(t + G * e)] = v[e];
-    __syncthreads();
-    if (ok) {
-        const cpx* a0 = lds + (pl * 2) * A;
-        const cpx* a1 = a0 + A;
-#pragma unroll
-        for (int ee = 0; ee < E / 2; ++ee) {
-            const int j = t + G * (h * (E / 2) + ee);
-            base[j] = cadd(a0[lds_pad(j)], a1[lds_pad(j)]);
+            for (int ee = 0; ee < E / 2; ++ee) {
+                const int j = t + G * (h * (E / 2) + ee);
+                base[j] = cadd(a0[lds_pad(j)], a1[lds_pad(j)]);
+            }
         }
+        lds_sync<CW>();
     }
 }
 
