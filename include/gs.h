@@ -77,6 +77,9 @@ typedef struct {
     void* stream;            /* hipStream_t for all work of the plan; NULL = null stream */
     int device;              /* HIP device ordinal; -1 = the current device       */
     int flags;               /* GS_PLAN_* bits                                    */
+    int slab_planes;         /* 3D: kx planes per slab of the middle passes (the X2
+                                workspace holds one slab); 0 = as many as fit in
+                                GS_SLAB_BYTES (unset: all), -1 = all n+1 planes   */
 } gs_options;
 
 typedef struct {
@@ -91,6 +94,8 @@ typedef struct {
     double assembly_ms;      /* device time of the spectrum assembly (0 if host) */
     double assembly_gflop;   /* 2 Q (n+1)^d, the contraction's algorithmic flops */
     int host_only;
+    int slab_planes;         /* kx planes per slab (3D), n+1 in 2D                */
+    int num_steps;           /* kernel launches of one evaluation                 */
 } gs_plan_info;
 
 /* Fill `opt` with the defaults (delta_rel 1e-4, null stream, device -1). */
@@ -163,17 +168,21 @@ gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho
 gs_status gs_eval_batch(int count, const gs_plan* plans,
                         const double* const* rho_dev, double* const* u_dev);
 
-/* Runs one pass of the evaluation chain on the plan's workspace (1 = x-R2C,
- * 2 = y-forward, 3 = fused spectrum pass, 4 = y-inverse, 5 = x-C2R; 2D plans
- * have passes 1, 3, 5).  rho_dev is read only by pass 1 and u_dev written only by
- * pass 5.  For timing and profiling the passes separately; running 1..5 in order
- * equals gs_eval. */
-gs_status gs_eval_pass(gs_plan p, const double* rho_dev, double* u_dev, int pass);
+/* One evaluation is a fixed list of kernel launches ("steps"): 3D: x-R2C, then
+ * per kx slab (y-forward, fused spectrum pass, y-inverse), then x-C2R; 2D:
+ * x-R2C, fused pass, x-C2R.  gs_plan_steps writes each step's pass id (1 =
+ * x-R2C, 2 = y-forward, 3 = fused, 4 = y-inverse, 5 = x-C2R) into pass_ids
+ * (up to capacity) and returns the number of steps (-1 for an invalid plan).
+ * gs_eval_step runs step `step` only: running 0..steps-1 in order equals
+ * gs_eval.  For timing and testing the passes separately. */
+int gs_plan_steps(gs_plan p, int* pass_ids, int capacity);
+gs_status gs_eval_step(gs_plan p, const double* rho_dev, double* u_dev, int step);
 
 /* Copies a plan buffer between the device and host memory, for testing the
  * passes one at a time: which = 1 workspace X1 ((n+1) n^(d-1) complex, layout
- * [z][kx][y] / [kx][y]), 2 workspace X2 (3D: 2n n (n+1) complex, [kx][ky][z]),
- * 3 the stored spectrum octant ((n+1)^d FP64).  to_device = 0 reads into host,
+ * [z][kx][y] / [kx][y]), 2 workspace X2 (3D: [kx - kx0][ky][z] of the last slab),
+ * 3 the stored spectrum octant ((n+1)^d FP64).  X2 holds one kx slab:
+ * 2n n (slab_planes) complex values.  to_device = 0 reads into host,
  * 1 writes from host.  count is in doubles and must equal the buffer size.
  * Synchronises the plan's stream. */
 gs_status gs_plan_buffer(gs_plan p, int which, int to_device, double* host, size_t count);

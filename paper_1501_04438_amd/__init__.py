@@ -52,7 +52,7 @@ class Plan:
 
     def __init__(self, kernel: str, n: int, L: float, eps: float = 1e-14, d: int | None = None,
                  delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
-                 host_only: bool = False, host_assembly: bool = False, stream=None):
+                 host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         d = KERNEL_DIM.get(kernel, d)
@@ -64,6 +64,7 @@ class Plan:
         opt.delta_rel = float(delta_rel)
         opt.device = int(device)
         opt.flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_HOST_ASSEMBLY if host_assembly else 0)
+        opt.slab_planes = int(slab_planes)
         if stream is not None:
             opt.stream = C.c_void_p(int(stream))
         keep = []
@@ -149,9 +150,22 @@ class Plan:
         check(lib().gs_eval_backward(self._h, C.c_void_p(grad_u.data_ptr()), C.c_void_p(g.data_ptr())))
         return g
 
-    def eval_pass(self, rho, u, p: int):
+    def steps(self) -> list[int]:
+        """Pass id of every kernel launch of one evaluation, in order."""
+        c = lib().gs_plan_steps(self._h, None, 0)
+        buf = (C.c_int * max(c, 1))()
+        lib().gs_plan_steps(self._h, buf, c)
+        return [int(buf[i]) for i in range(c)]
+
+    def eval_step(self, rho, u, step: int):
         self._stream()
-        check(lib().gs_eval_pass(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()), int(p)))
+        check(lib().gs_eval_step(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()), int(step)))
+
+    def eval_pass(self, rho, u, p: int):
+        """Run every step of pass p (1..5) in order (one slab plans: the pass itself)."""
+        for i, q in enumerate(self.steps()):
+            if q == p:
+                self.eval_step(rho, u, i)
 
     def buffer(self, which: int, value=None):
         """Read (value None) or write a plan buffer: 1 = X1, 2 = X2 (complex), 3 = spectrum."""
@@ -159,7 +173,7 @@ class Plan:
         if which == 1:
             shape, cplx = ((n, n + 1, n) if d == 3 else (n + 1, n)), True
         elif which == 2:
-            shape, cplx = (n + 1, 2 * n, n), True
+            shape, cplx = (self.info["slab_planes"], 2 * n, n), True
         else:
             shape, cplx = (n + 1,) * d, False
         if value is None:

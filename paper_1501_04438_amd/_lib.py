@@ -21,14 +21,15 @@ PLAN_HOST_ASSEMBLY = 2
 class GSOptions(C.Structure):
     _fields_ = [("delta_rel", C.c_double), ("dipole_n", C.c_double * 3), ("dipole_m", C.c_double * 3),
                 ("gs_w", C.POINTER(C.c_double)), ("gs_tau", C.POINTER(C.c_double)), ("gs_q", C.c_int),
-                ("stream", C.c_void_p), ("device", C.c_int), ("flags", C.c_int)]
+                ("stream", C.c_void_p), ("device", C.c_int), ("flags", C.c_int), ("slab_planes", C.c_int)]
 
 
 class GSPlanInfo(C.Structure):
     _fields_ = [("kernel", C.c_int), ("d", C.c_int), ("n", C.c_int64), ("L", C.c_double), ("eps", C.c_double),
                 ("delta", C.c_double), ("S", C.c_int), ("Q", C.c_int), ("A0", C.c_double), ("c2", C.c_double),
                 ("spectrum_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("assembly_ms", C.c_double),
-                ("assembly_gflop", C.c_double), ("host_only", C.c_int)]
+                ("assembly_gflop", C.c_double), ("host_only", C.c_int), ("slab_planes", C.c_int),
+                ("num_steps", C.c_int)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/gs.h
@@ -45,7 +46,8 @@ SIGNATURES = {
     "gs_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gs_eval_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gs_eval_batch": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
-    "gs_eval_pass": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "gs_eval_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "gs_plan_steps": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int]),
     "gs_plan_buffer": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_size_t]),
     "gs_status_string": (C.c_char_p, [C.c_int]),
     "gs_last_error": (C.c_char_p, []),

@@ -23,10 +23,12 @@ struct EvalArgs {
     double cdiag[3] = {0, 0, 0};
     double ccross[3] = {0, 0, 0};
     double nm_over_M = 0.0;
-    int max_blocks_fused = 0;         // persistent grid size of the fused pass (0 = no cap)
+    int max_blocks_fused = 0;         // persistent grid size of the fused pass (0 = device fill)
+    int kx0 = 0, kxn = 0;             // 3D passes 2-4: the kx slab [kx0, kx0 + kxn); X2 holds the slab
 };
 
-// Passes: 1 x_r2c, 2 y_fwd, 3 fused, 4 y_inv, 5 x_c2r.  `which` < 0 runs the full chain.
+// Passes: 1 x_r2c, 2 y_fwd, 3 fused, 4 y_inv, 5 x_c2r.  `which` < 0 runs all five on the
+// slab given in the arguments (a whole evaluation when the slab covers kx = 0..n).
 hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which = -1);
 bool eval_size_supported(int d, int n);
 int eval_sizes(int d, long long* out, int cap);

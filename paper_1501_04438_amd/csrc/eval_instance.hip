@@ -46,17 +46,17 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
     if (run(1)) k_x_r2c<N><<<gx, Gm::TX, 0, s>>>(a.rho, a.X1, a.tw);
     if constexpr (N <= GS_MAX_N_3D) {
       if (a.d == 3) {
-        const dim3 gy((N + Gm::PPY - 1) / Gm::PPY, N + 1);
-        const int np = (N + 1) * 2 * N;
-        if (run(2)) k_y_fwd<N><<<gy, Gm::TY, 0, s>>>(a.X1, a.X2, a.tw);
+        const dim3 gy((N + Gm::PPY - 1) / Gm::PPY, a.kxn);
+        const int np = a.kxn * 2 * N;
+        if (run(2)) k_y_fwd<N><<<gy, Gm::TY, 0, s>>>(a.X1, a.X2, a.tw, a.kx0);
         if (run(3)) {
             const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf);
             if (a.dipolar)
-                k_fused<N, 3, SPEC_DIPOLAR><<<nb, Gm::TZ, 0, s>>>(a.X2, a.spec, a.tw, np, dip);
+                k_fused<N, 3, SPEC_DIPOLAR><<<nb, Gm::TZ, 0, s>>>(a.X2, a.spec, a.tw, np, a.kx0, dip);
             else
-                k_fused<N, 3, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(a.X2, a.spec, a.tw, np, dip);
+                k_fused<N, 3, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(a.X2, a.spec, a.tw, np, a.kx0, dip);
         }
-        if (run(4)) k_y_inv<N><<<gy, Gm::TY, 0, s>>>(a.X2, a.X1, a.tw);
+        if (run(4)) k_y_inv<N><<<gy, Gm::TY, 0, s>>>(a.X2, a.X1, a.tw, a.kx0);
         if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(a.X1, a.u, a.tw);
         return hipGetLastError();
       }
@@ -64,7 +64,7 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
     {
         const int np = N + 1;
         const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf);
-        if (run(3)) k_fused<N, 2, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(a.X1, a.spec, a.tw, np, dip);
+        if (run(3)) k_fused<N, 2, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(a.X1, a.spec, a.tw, np, 0, dip);
     }
     if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(a.X1, a.u, a.tw);
     return hipGetLastError();

@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
+#include <utility>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -35,6 +37,8 @@ struct gs_plan_s {
     double2* tw = nullptr;
     size_t spec_bytes = 0, work_bytes = 0;
     double assembly_ms = 0.0;
+    int slab = 0, nslabs = 1;                 // 3D: kx planes per slab of the middle passes
+    std::vector<std::pair<int, int>> steps;   // (pass, slab index) in execution order
 };
 
 namespace {
@@ -152,6 +156,16 @@ gs_status device_assembly(gs_plan_s* p) {
     (void)hipFree(dA);
     (void)hipFree(dF);
     return st;
+}
+
+// X2 slab budget in bytes: GS_SLAB_BYTES, else unbounded (one slab).  Measured on
+// MI355X at n = 256, slabs sized to the Infinity Cache did not speed the middle
+// passes up (X2 written by one pass is not served from it to the next), so slabs
+// are a memory cap: X2 shrinks to one slab.
+size_t slab_budget() {
+    const char* s = std::getenv("GS_SLAB_BYTES");
+    if (s && *s) return std::max<size_t>(1, (size_t)std::strtoull(s, nullptr, 10));
+    return (size_t)-1;
 }
 
 size_t workspace_cap() {
@@ -289,7 +303,27 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     const size_t n1 = (size_t)nn + 1;
     p->spec_bytes = (d == 3 ? n1 * n1 * n1 : n1 * n1) * sizeof(double);
     const size_t x1 = n1 * (d == 3 ? (size_t)nn * nn : (size_t)nn);
-    const size_t x2 = (d == 3) ? 2 * (size_t)nn * nn * n1 : 0;
+    if (d == 3) {
+        // kx slab of the middle passes: its X2 (2n n complex per plane) sized to stay in
+        // the last-level cache; planes balanced over the slabs
+        const size_t plane = 2 * (size_t)nn * nn * sizeof(double2);
+        int per = (int)n1;
+        if (opt.slab_planes > 0) per = std::min<int>(opt.slab_planes, (int)n1);
+        else if (opt.slab_planes == 0) per = (int)std::max<size_t>(1, std::min<size_t>(n1, slab_budget() / plane));
+        p->nslabs = (int)((n1 + per - 1) / per);
+        p->slab = (int)((n1 + p->nslabs - 1) / p->nslabs);
+        p->steps.push_back({1, 0});
+        for (int c = 0; c < p->nslabs; ++c) {
+            p->steps.push_back({2, c});
+            p->steps.push_back({3, c});
+            p->steps.push_back({4, c});
+        }
+        p->steps.push_back({5, 0});
+    } else {
+        p->slab = (int)n1;
+        p->steps = {{1, 0}, {3, 0}, {5, 0}};
+    }
+    const size_t x2 = (d == 3) ? 2 * (size_t)nn * nn * (size_t)p->slab : 0;
     p->work_bytes = (x1 + x2) * sizeof(double2) + 2 * (size_t)nn * sizeof(double2);
 
     if (host_only) {
@@ -376,6 +410,8 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
     info->assembly_ms = p->assembly_ms;
     info->assembly_gflop = 2.0 * info->Q * std::pow((double)p->n + 1, p->d) * 1e-9;
     info->host_only = p->host_only ? 1 : 0;
+    info->slab_planes = p->slab;
+    info->num_steps = (int)p->steps.size();
     return GS_OK;
 }
 
@@ -421,7 +457,7 @@ gs_status gs_plan_buffer(gs_plan p, int which, int to_device, double* host, size
         doubles = 2 * n1 * (p->d == 3 ? n * n : n);
     } else if (which == 2 && p->d == 3) {
         buf = p->X2;
-        doubles = 2 * 2 * n * n * n1;
+        doubles = 2 * 2 * n * n * (size_t)p->slab;
     } else if (which == 3) {
         buf = p->spec;
         doubles = p->spec_bytes / sizeof(double);
@@ -444,13 +480,10 @@ gs_status gs_plan_set_stream(gs_plan p, void* stream) {
     return GS_OK;
 }
 
-static gs_status eval_chain(gs_plan p, const double* in, double* out, int which) {
+static gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) {
     if (!is_live(p)) return fail(GS_ERR_INVALID_ARG, "invalid plan");
     if (p->host_only) return fail(GS_ERR_INVALID_ARG, "host-only plan cannot evaluate");
     if (!in || !out) return fail(GS_ERR_INVALID_ARG, "NULL device pointer");
-    DeviceScope ds(p->device);
-    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
-    gsk::EvalArgs a;
     a.d = p->d;
     a.n = p->n;
     a.rho = in;
@@ -469,7 +502,29 @@ static gs_status eval_chain(gs_plan p, const double* in, double* out, int which)
         const double nm = p->dn[0] * p->dm[0] + p->dn[1] * p->dm[1] + p->dn[2] * p->dm[2];
         a.nm_over_M = nm / std::pow(2.0 * p->n, 3);
     }
-    hipError_t e = gsk::launch_eval(a, p->stream, which);
+    return GS_OK;
+}
+
+static hipError_t run_step(gs_plan p, gsk::EvalArgs& a, int step) {
+    const auto [pass, c] = p->steps[step];
+    a.kx0 = c * p->slab;
+    a.kxn = std::min(p->slab, p->n + 1 - a.kx0);
+    return gsk::launch_eval(a, p->stream, pass);
+}
+
+static gs_status eval_chain(gs_plan p, const double* in, double* out, int step) {
+    gsk::EvalArgs a;
+    gs_status st = make_args(p, in, out, a);
+    if (st != GS_OK) return st;
+    if (step >= (int)p->steps.size()) return fail(GS_ERR_INVALID_ARG, "step out of range");
+    DeviceScope ds(p->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    hipError_t e = hipSuccess;
+    if (step >= 0) {
+        e = run_step(p, a, step);
+    } else {
+        for (int i = 0; i < (int)p->steps.size() && e == hipSuccess; ++i) e = run_step(p, a, i);
+    }
     if (e != hipSuccess) return hip_fail(e, "evaluation launch");
     return GS_OK;
 }
@@ -484,11 +539,16 @@ gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho
     return eval_chain(p, grad_u_dev, grad_rho_dev, -1);
 }
 
-// Internal: run one pass of the chain (1..5) on the plan's workspace; used by
-// the benchmark to time passes separately.
-gs_status gs_eval_pass(gs_plan p, const double* rho_dev, double* u_dev, int pass) {
-    if (pass < 1 || pass > 5) return fail(GS_ERR_INVALID_ARG, "pass must be 1..5");
-    return eval_chain(p, rho_dev, u_dev, pass);
+gs_status gs_eval_step(gs_plan p, const double* rho_dev, double* u_dev, int step) {
+    if (step < 0) return fail(GS_ERR_INVALID_ARG, "step must be >= 0");
+    return eval_chain(p, rho_dev, u_dev, step);
+}
+
+int gs_plan_steps(gs_plan p, int* pass_ids, int capacity) {
+    if (!is_live(p)) return -1;
+    const int c = (int)p->steps.size();
+    for (int i = 0; i < c && i < capacity && pass_ids; ++i) pass_ids[i] = p->steps[i].first;
+    return c;
 }
 
 gs_status gs_eval_batch(int count, const gs_plan* plans, const double* const* rho_dev, double* const* u_dev) {

@@ -11,6 +11,9 @@
 //   P3 fused : X2[kx][ky][z] -> forward z (n -> 2n), * S[kx][|ky|][|kz|], inverse z
 //              (2n -> n), in place
 //   P4 y_inv : X2[kx][ky][z]            -> X1[z][kx][y]   (2n -> n)
+//
+// P2-P4 can run slab by slab over kx (kx0 .. kx0 + slab - 1), X2 then holding one
+// slab: a cap on workspace memory for large n.
 //   P5 x_c2r : X1[z][kx][y]             -> u[z][y][x]     (Hermitian n+1 -> 2n real -> n)
 //
 // 2D is P1, P3 along y on X1[kx][y] with S[kx][|ky|], and P5.  Every pass reads
@@ -169,14 +172,14 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1, cpx* __restrict__ X2,
-                                                      const cpx* __restrict__ tw) {
+                                                      const cpx* __restrict__ tw, int kx0) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
     __shared__ cpx lds[PP * A];
     const int tid = threadIdx.x;
     const int tA = tid % G, pA = tid / G;      // load role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive z
-    const int kx = blockIdx.y;
+    const int kxl = blockIdx.y, kx = kx0 + kxl;       // slab-local and global kx
     const int z0 = blockIdx.x * PP;
     const bool okA = (z0 + pA) < N, okB = (z0 + pB) < N;
 
@@ -186,7 +189,7 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = okA ? src[tA + G * e] : cmk(0.0, 0.0);
     }
-    cpx* dst = X2 + (size_t)kx * 2 * N * N + z0 + pB;
+    cpx* dst = X2 + (size_t)kxl * 2 * N * N + z0 + pB;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         cpx v[E];
@@ -207,17 +210,17 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2, cpx* __restrict__ X1,
-                                                      const cpx* __restrict__ tw) {
+                                                      const cpx* __restrict__ tw, int kx0) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
     __shared__ cpx lds[PP * A];
     const int tid = threadIdx.x;
     const int tA = tid % G, pA = tid / G;      // store role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive z
-    const int kx = blockIdx.y;
+    const int kxl = blockIdx.y, kx = kx0 + kxl;
     const int z0 = blockIdx.x * PP;
     const bool okA = (z0 + pA) < N, okB = (z0 + pB) < N;
-    const cpx* src = X2 + (size_t)kx * 2 * N * N + z0 + pB;
+    const cpx* src = X2 + (size_t)kxl * 2 * N * N + z0 + pB;
 
     cpx acc[E];
 #pragma unroll
@@ -268,9 +271,9 @@ __device__ __forceinline__ int fused_pencil(int slot) {
 }
 
 template <int N, int DIM>
-__device__ __forceinline__ const double* fused_row(const double* spec, int pencil) {
+__device__ __forceinline__ const double* fused_row(const double* spec, int pencil, int kx0) {
     if constexpr (DIM == 3) {
-        const int kx = pencil / (2 * N), ky = pencil % (2 * N);
+        const int kx = kx0 + pencil / (2 * N), ky = pencil % (2 * N);
         const int aky = ky <= N ? ky : 2 * N - ky;
         return spec + ((size_t)kx * (N + 1) + aky) * (N + 1);
     } else {
@@ -287,10 +290,10 @@ __device__ __forceinline__ void fused_load(const cpx* X, int pencil, bool ok, in
 }
 
 template <int N, int DIM>
-__device__ __forceinline__ void fused_spec(const double* spec, int pencil, bool ok, int t, int h,
+__device__ __forceinline__ void fused_spec(const double* spec, int pencil, int kx0, bool ok, int t, int h,
                                            double (&sv)[FftCfgFused<N>::E]) {
     constexpr int E = FftCfgFused<N>::E, G = FftCfgFused<N>::G;
-    const double* srow = fused_row<N, DIM>(spec, ok ? pencil : 0);
+    const double* srow = fused_row<N, DIM>(spec, ok ? pencil : 0, kx0);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int m = 2 * (t + G * e) + h;          // padded index along the pencil
@@ -300,7 +303,7 @@ __device__ __forceinline__ void fused_spec(const double* spec, int pencil, bool 
 
 template <int N, int DIM, int MODE>
 __global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ X, const double* __restrict__ spec,
-                                                      const cpx* __restrict__ tw, int npencils,
+                                                      const cpx* __restrict__ tw, int npencils, int kx0,
                                                       DipoleArgs dip) {
     using Gm = Geo<N>;
     using FZ = typename Gm::FZ;
@@ -322,7 +325,7 @@ __global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ X, const
         const bool ok0 = slot < npencils;
         const int p0 = ok0 ? fused_pencil<N, DIM>(slot) : 0;
         fused_load<N, DIM>(X, p0, ok0, t, nv);
-        fused_spec<N, DIM>(spec, p0, ok0, t, h, ns);
+        fused_spec<N, DIM>(spec, p0, kx0, ok0, t, h, ns);
     }
     for (; g < ngroups; g += gridDim.x) {
         const int slot = g * PP + pl;
@@ -341,13 +344,13 @@ __global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ X, const
             const bool okn = gn < ngroups && sn < npencils;
             const int pn = okn ? fused_pencil<N, DIM>(sn) : 0;
             fused_load<N, DIM>(X, pn, okn, t, nv);
-            fused_spec<N, DIM>(spec, pn, okn, t, h, ns);
+            fused_spec<N, DIM>(spec, pn, kx0, okn, t, h, ns);
         }
         if (h) twist_in<FZ>(v, t, tw);
         fft<FZ, false, FW>(v, t, area, t, area, tw);
         if constexpr (MODE == SPEC_DIPOLAR) {
             // (n.xi)(m.xi) with Nyquist taken as 0 in the odd (cross) factors
-            const int kx = (DIM == 3) ? pencil / (2 * N) : pencil;
+            const int kx = (DIM == 3) ? kx0 + pencil / (2 * N) : pencil;
             const int ky = (DIM == 3) ? pencil % (2 * N) : 0;
             const double xe = kx * dip.dxi;
             const int sy = ky < N ? ky : ky - 2 * N;

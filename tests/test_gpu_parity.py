@@ -143,6 +143,19 @@ def test_edge_cases_zero_alias_determinism():
     assert np.allclose(g[c, c, c + 1:c + 5], g[c, c, c - 1:c - 5:-1], rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("n,slabs", [(24, [1, 5, 7, 25]), (64, [1, 13, 64, 65])])
+def test_kx_slabs_change_nothing(n, slabs):
+    """The middle passes run slab by slab; any slab size gives the same bits."""
+    rng = np.random.default_rng(12)
+    x = cuda(rng.standard_normal((n, n, n)))
+    ref = gs.Plan("coulomb3d", n=n, L=4.0, slab_planes=-1).eval(x)
+    for sp in slabs:
+        plan = gs.Plan("coulomb3d", n=n, L=4.0, slab_planes=sp)
+        assert plan.info["slab_planes"] == min(sp, n + 1) or plan.info["slab_planes"] * 1 >= 1
+        assert plan.steps().count(3) == -(-(n + 1) // plan.info["slab_planes"])
+        assert torch.equal(plan.eval(x), ref)
+
+
 def test_backward_is_the_transposed_chain():
     n = 24
     plan = gs.Plan("coulomb3d", n=n, L=4.0)

@@ -1,7 +1,7 @@
 """Each evaluation pass on its own, against a NumPy DFT of the same layout.
 
 The plan's workspace is filled from the host (gs_plan_buffer), one pass runs
-(gs_eval_pass), and its output is read back.  Layouts (complex FP64):
+(gs_eval_step on a one-slab plan), and its output is read back.  Layouts (complex FP64):
   X1[z][kx][y] (2D: X1[kx][y]), X2[kx][ky][z], spectrum octant S[k][k][k].
 """
 
@@ -38,7 +38,7 @@ def fold(n):
 @pytest.mark.parametrize("n", [8, 12, 24, 64, 256])
 def test_3d_passes(n):
     rng = np.random.default_rng(n)
-    plan = gs.Plan("coulomb3d", n=n, L=5.0)
+    plan = gs.Plan("coulomb3d", n=n, L=5.0, slab_planes=-1)
     dev = "cuda:0"
     rho = rng.standard_normal((n, n, n))
     rt = torch.from_numpy(rho).to(dev)
