@@ -240,31 +240,53 @@ def adjoint_figures(gs, torch, plan, rho, K):
             "energy_and_grad_Mpts_s": round(n3 / dte / 1e6, 1), "energy_and_grad_ms": round(dte * 1e3, 4)}
 
 
-def batched_figures(gs, torch, workloads, reps: int = 5):
-    """64 seeded mixtures on uneven grids: one batched call versus 64 single solves."""
+def batched_figures(gs, torch, workloads, reps: int = 10):
+    """64 seeded mixtures on uneven grids (32..128 points per axis): the batch
+    schedules against 64 plain solves (plan.eval one after the other)."""
     probs = [workloads.materialise(p) for p in workloads.config4(64)]
     plans = [gs.Plan("coulomb3d", n=p.n, L=p.L, eps=1e-14) for p in probs]
     rhos = [torch.from_numpy(p.rho).to("cuda:0") for p in probs]
-    outs = [torch.empty_like(r) for r in rhos]
     pts = sum(p.n ** 3 for p in probs)
-    gs.eval_batch(plans, rhos, outs)
-    for pl, r, o in zip(plans, rhos, outs):
-        pl.eval(r, out=o)
+    ref = [pl.eval(r) for pl, r in zip(plans, rhos)]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        gs.eval_batch(plans, rhos, outs)
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        for pl, r, o in zip(plans, rhos, outs):
-            pl.eval(r, out=o)
-    torch.cuda.synchronize()
-    ts = (time.perf_counter() - t0) / reps
-    return {"problems": len(probs), "points": pts, "batched_Mpts_s": round(pts / tb / 1e6, 1),
-            "batched_ms": round(tb * 1e3, 3), "single_solves_Mpts_s": round(pts / ts / 1e6, 1),
-            "single_solves_ms": round(ts * 1e3, 3)}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    outs = [torch.empty_like(r) for r in rhos]
+    res = {"problems": len(probs), "points": pts, "sizes": sorted({p.n for p in probs}), "reps": reps}
+    ms = timed(lambda: [pl.eval(r, out=o) for pl, r, o in zip(plans, rhos, outs)])
+    res["single_solves"] = {"ms": round(ms, 4), "Mpts_s": round(pts / ms / 1e3, 1)}
+    equal = all(torch.equal(o, r) for o, r in zip(outs, ref))
+    for name, kw in [("sequential", dict(schedule="sequential")),
+                     ("sequential_graph", dict(schedule="sequential", graph=True)),
+                     ("phased", dict(schedule="phased")),
+                     ("queue", dict(schedule="queue")),
+                     ("queue_graph", dict(schedule="queue", graph=True)),
+                     ("auto_graph", dict(schedule="auto", graph=True))]:
+        b = gs.Batch(plans, **kw)
+        outs = [torch.empty_like(r) for r in rhos]
+        ms = timed(lambda: b.eval(rhos, outs))
+        equal = equal and all(torch.equal(o, r) for o, r in zip(outs, ref))
+        info = b.info
+        res[name] = {"ms": round(ms, 4), "Mpts_s": round(pts / ms / 1e3, 1), "schedule": info["schedule"],
+                     "tiles_per_task": info["tiles_per_task"], "tasks": info["num_tasks"]}
+        if name.startswith("auto"):
+            res[name]["candidates_timed"] = info["candidates"]
+        b.close()
+    best = min((v["ms"], k) for k, v in res.items() if isinstance(v, dict) and k != "single_solves")
+    res["best"] = best[1]
+    res["speedup_vs_single_solves"] = round(res["single_solves"]["ms"] / best[0], 2)
+    res["bitwise_equal_to_single"] = bool(equal)
+    return res
 
 
 if __name__ == "__main__":

@@ -160,11 +160,89 @@ gs_status gs_eval(gs_plan p, const double* rho_dev, double* u_dev);
 gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho_dev);
 
 /*
- * Batched evaluation of `count` independent problems (each with its own plan,
- * possibly of different sizes) in one persistent launch.  plans must be
- * distinct device plans on one device; the first plan's stream is used.
- * rho[i], u[i] are device arrays of plans[i]'s shape.
+ * Batched evaluation: many independent problems, each with its own plan (any
+ * kernel, d = 2 or 3, sizes n <= 128 of the compiled list, possibly all
+ * different).  The method is the per-problem evaluation of gs_eval unchanged;
+ * batching only schedules the tiles of all problems together, and every
+ * problem's result is bitwise the one gs_eval gives.
+ *
+ * Schedules:
+ *   GS_SCHED_QUEUE      one persistent launch walks a pass-major task list of
+ *                       every problem; a task waits for the preceding pass of
+ *                       its own problem through per-problem counters.
+ *   GS_SCHED_PHASED     one launch per pass type over the tasks of all problems.
+ *   GS_SCHED_SEQUENTIAL each plan's own gs_eval launches, one problem after the
+ *                       other (the unbatched baseline).
+ *   GS_SCHED_AUTO       the fastest of the above (and of their task sizes) for
+ *                       this device and multiset of problem shapes, measured on
+ *                       the first gs_batch_eval and cached in the process and,
+ *                       if the environment variable GS_AUTOTUNE_CACHE names a
+ *                       file, in that JSON file across processes.
  */
+typedef enum {
+    GS_SCHED_AUTO = 0,
+    GS_SCHED_QUEUE = 1,
+    GS_SCHED_PHASED = 2,
+    GS_SCHED_SEQUENTIAL = 3
+} gs_schedule;
+
+typedef struct gs_batch_s* gs_batch;
+
+typedef struct {
+    int schedule;        /* gs_schedule                                               */
+    int tiles_per_task;  /* block-fulls of tiles per task (>= 1); 0 = 1, or tuned       */
+    int grid;            /* persistent blocks; 0 = as many as can be co-resident        */
+    int use_graph;       /* 1: capture the launch sequence in a hipGraph on the first
+                            evaluation and replay it afterwards                         */
+    void* stream;        /* hipStream_t the evaluations are ordered on; NULL = null stream */
+} gs_batch_options;
+
+typedef struct {
+    int count;              /* problems                                        */
+    double points;          /* sum of n^d over the problems                    */
+    int schedule;           /* resolved schedule (never GS_SCHED_AUTO once run) */
+    int tiles_per_task;
+    int grid;
+    int use_graph;
+    int num_tasks;          /* tasks of the queue / phased schedules           */
+    int tasks_per_pass[6];  /* index = pass id 1..5                             */
+    int autotuned;          /* 1 if the schedule came from a measurement        */
+    int candidates;         /* schedules timed by the autotuner for this batch  */
+    double tuned_ms;        /* best measured evaluation time (ms), 0 if none    */
+    int wait_timeouts;      /* 1 if a queue-schedule dependency wait ever gave up
+                               (results of that call invalid; never expected)  */
+} gs_batch_info;
+
+/* Defaults: GS_SCHED_AUTO, tiles_per_task 0, grid 0, no graph, null stream. */
+void gs_batch_options_default(gs_batch_options* opt);
+
+/*
+ * Creates a batch over `count` distinct device plans on one device.  The plans
+ * must outlive the batch and must not be evaluated elsewhere while a batch
+ * evaluation is in flight (the batch uses their workspaces).  Allocates the
+ * batch's device descriptors and synchronises once.  Errors:
+ * GS_ERR_INVALID_ARG (count < 1, NULL or duplicate or host-only plan, plans on
+ * several devices, a plan whose middle passes run in kx slabs),
+ * GS_ERR_UNSUPPORTED_SIZE (n > 128), GS_ERR_HIP.
+ */
+gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const gs_batch_options* opt);
+
+/* Evaluates u[i] = U * rho[i] for every problem i; rho[i], u[i] are device
+ * arrays of plans[i]'s shape (u[i] may alias rho[i]).  Asynchronous on the
+ * batch's stream, except for the first call of a GS_SCHED_AUTO batch whose
+ * shapes are not in the cache: that call times the candidates (each produces
+ * the same result) and synchronises.  Calls on one batch must not overlap. */
+gs_status gs_batch_eval(gs_batch b, const double* const* rho_dev, double* const* u_dev);
+
+/* Fills info; waits for the batch's stream (it reads the error flag). */
+gs_status gs_batch_query(gs_batch b, gs_batch_info* info);
+
+/* Waits for the batch's stream and frees its device memory; NULL or an already
+ * destroyed batch is a no-op. */
+gs_status gs_batch_destroy(gs_batch b);
+
+/* One-shot form: creates a GS_SCHED_QUEUE batch on the first plan's stream,
+ * evaluates once, waits for it and destroys the batch. */
 gs_status gs_eval_batch(int count, const gs_plan* plans,
                         const double* const* rho_dev, double* const* u_dev);
 

@@ -19,10 +19,10 @@ import math
 
 import numpy as np
 
-from ._lib import (KERNEL_DIM, KERNELS, PLAN_HOST_ASSEMBLY, PLAN_HOST_ONLY, GSError, GSOptions, GSPlanInfo,
-                   check, lib)
+from ._lib import (KERNEL_DIM, KERNELS, PLAN_HOST_ASSEMBLY, PLAN_HOST_ONLY, SCHEDULES, GSBatchInfo,
+                   GSBatchOptions, GSError, GSOptions, GSPlanInfo, check, lib)
 
-__all__ = ["Plan", "potential", "energy", "eval_batch", "GSError", "device_count", "supported_sizes",
+__all__ = ["Plan", "Batch", "SCHEDULES", "potential", "energy", "eval_batch", "GSError", "device_count", "supported_sizes",
            "mixture_density"]
 
 
@@ -212,6 +212,70 @@ def eval_batch(plans, rhos, outs=None):
     plans[0]._stream()
     check(lib().gs_eval_batch(n, hs, rs, us))
     return outs
+
+
+class Batch:
+    """Many independent problems (one plan each, sizes may differ) evaluated together.
+
+    schedule: "auto" (measured on the first eval, cached; GS_AUTOTUNE_CACHE names a
+    JSON file to keep it across processes), "queue" (one persistent launch),
+    "phased" (one launch per pass type) or "sequential" (each plan's own eval).
+    graph=True captures the launch sequence in a hipGraph and replays it.
+    Every schedule gives each problem bitwise the result of plan.eval.
+    """
+
+    def __init__(self, plans, schedule: str = "auto", graph: bool = False, tiles_per_task: int = 0,
+                 grid: int = 0):
+        torch = _torch()
+        self.plans = list(plans)
+        opt = GSBatchOptions()
+        lib().gs_batch_options_default(C.byref(opt))
+        opt.schedule = SCHEDULES[schedule]
+        opt.tiles_per_task = int(tiles_per_task)
+        opt.grid = int(grid)
+        opt.use_graph = 1 if graph else 0
+        opt.stream = torch.cuda.current_stream().cuda_stream
+        n = len(self.plans)
+        hs = (C.c_void_p * n)(*[p._h for p in self.plans])
+        h = C.c_void_p()
+        check(lib().gs_batch_create(C.byref(h), n, hs, C.byref(opt)))
+        self._h = h
+
+    def eval(self, rhos, outs=None):
+        torch = _torch()
+        if outs is None:
+            outs = [torch.empty_like(r) for r in rhos]
+        if len(rhos) != len(self.plans) or len(outs) != len(self.plans):
+            raise ValueError("one rho and one out per plan")
+        for p, r, o in zip(self.plans, rhos, outs):
+            p._check_tensor(r, "rho")
+            p._check_tensor(o, "out")
+        n = len(self.plans)
+        rs = (C.c_void_p * n)(*[r.data_ptr() for r in rhos])
+        us = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        check(lib().gs_batch_eval(self._h, rs, us))
+        return outs
+
+    @property
+    def info(self) -> dict:
+        i = GSBatchInfo()
+        check(lib().gs_batch_query(self._h, C.byref(i)))
+        names = {v: k for k, v in SCHEDULES.items()}
+        out = {f: getattr(i, f) for f, _ in GSBatchInfo._fields_ if f != "tasks_per_pass"}
+        out["schedule"] = names[out["schedule"]]
+        out["tasks_per_pass"] = [int(i.tasks_per_pass[p]) for p in range(6)]
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ autograd

@@ -32,6 +32,21 @@ class GSPlanInfo(C.Structure):
                 ("num_steps", C.c_int)]
 
 
+SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3}
+
+
+class GSBatchOptions(C.Structure):
+    _fields_ = [("schedule", C.c_int), ("tiles_per_task", C.c_int), ("grid", C.c_int), ("use_graph", C.c_int),
+                ("stream", C.c_void_p)]
+
+
+class GSBatchInfo(C.Structure):
+    _fields_ = [("count", C.c_int), ("points", C.c_double), ("schedule", C.c_int), ("tiles_per_task", C.c_int),
+                ("grid", C.c_int), ("use_graph", C.c_int), ("num_tasks", C.c_int), ("tasks_per_pass", C.c_int * 6),
+                ("autotuned", C.c_int), ("candidates", C.c_int), ("tuned_ms", C.c_double),
+                ("wait_timeouts", C.c_int)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/gs.h
 SIGNATURES = {
     "gs_options_default": (None, [C.POINTER(GSOptions)]),
@@ -46,6 +61,12 @@ SIGNATURES = {
     "gs_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gs_eval_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gs_eval_batch": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    "gs_batch_options_default": (None, [C.POINTER(GSBatchOptions)]),
+    "gs_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p),
+                                  C.POINTER(GSBatchOptions)]),
+    "gs_batch_eval": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    "gs_batch_query": (C.c_int, [C.c_void_p, C.POINTER(GSBatchInfo)]),
+    "gs_batch_destroy": (C.c_int, [C.c_void_p]),
     "gs_eval_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "gs_plan_steps": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int]),
     "gs_plan_buffer": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_size_t]),

@@ -55,7 +55,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for n in sizes():
         units.append([cc, *FLAGS, f"-DGS_N={n}", "-c", os.path.join(CSRC, "eval_instance.hip"),
                       "-o", os.path.join(BUILD, f"eval_{n}.o")])
-    for src in ("device_dispatch.hip", "host_plan.cpp", "gs_api.cpp"):
+    for src in ("device_dispatch.hip", "batch.hip", "host_plan.cpp", "gs_api.cpp", "batch_api.cpp",
+                "autotune.cpp"):
         units.append([cc, *FLAGS, "-c", os.path.join(CSRC, src),
                       "-o", os.path.join(BUILD, os.path.splitext(src)[0] + ".o")])
     with cf.ThreadPoolExecutor(jobs) as ex:

@@ -1,0 +1,62 @@
+// api_internal.hpp -- the plan object and helpers shared by the C ABI sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/gs.h"
+#include "device_api.hpp"
+#include "host_plan.hpp"
+
+struct gs_plan_s {
+    int kernel = 0, d = 0, n = 0;
+    double L = 0, eps = 0, delta_rel = 0;
+    gsh::Table table;
+    std::vector<double> F;
+    double A0 = 0, c2 = 0;
+    std::vector<double> spec_host;
+    double dn[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
+    int device = 0, flags = 0;
+    bool host_only = false;
+    hipStream_t stream = nullptr;
+    double* spec = nullptr;
+    double2* X1 = nullptr;
+    double2* X2 = nullptr;
+    double2* tw = nullptr;
+    size_t spec_bytes = 0, work_bytes = 0;
+    double assembly_ms = 0.0;
+    int slab = 0, nslabs = 1;                 // 3D: kx planes per slab of the middle passes
+    std::vector<std::pair<int, int>> steps;   // (pass, slab index) in execution order
+};
+
+namespace gsapi {
+
+// Records msg as this thread's last error and returns s.
+gs_status fail(gs_status s, const std::string& msg);
+gs_status hip_fail(hipError_t e, const char* what);
+// true while p is a plan created and not yet destroyed
+bool is_live(gs_plan p);
+
+// Makes the plan's device current for the scope and restores the caller's.
+struct DeviceScope {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Device arguments of one evaluation of plan p on (in, out).
+gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a);
+// Queues the evaluation steps of p on its stream: all of them (step < 0) or one.
+gs_status eval_chain(gs_plan p, const double* in, double* out, int step);
+
+}  // namespace gsapi

@@ -1,0 +1,152 @@
+// batch.hip -- host side of the batched evaluation: descriptors, task lists, launches.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "batch.hpp"
+#include "device_api.hpp"
+
+namespace gsk {
+
+static_assert(sizeof(BatchTask) == BATCH_TASK_INTS * sizeof(int), "task layout");
+
+bool batch_size_supported(int d, int n) {
+    if (d != 2 && d != 3) return false;
+    switch (n) {
+#define GS_CASE(N) \
+    case N: return true;
+        GS_BATCH_SIZES(GS_CASE)
+#undef GS_CASE
+        default: return false;
+    }
+}
+
+static int threads_for(int n, int pass) {
+    switch (n) {
+#define GS_CASE(N) \
+    case N: return tile_threads<N>(pass);
+        GS_BATCH_SIZES(GS_CASE)
+#undef GS_CASE
+    }
+    return 0;
+}
+
+static int tiles_for(int n, int pass, int d) {
+    switch (n) {
+#define GS_CASE(N) \
+    case N: return tile_count<N>(pass, d);
+        GS_BATCH_SIZES(GS_CASE)
+#undef GS_CASE
+    }
+    return 0;
+}
+
+void batch_problems(const std::vector<BatchMember>& m, std::vector<unsigned char>& out) {
+    out.assign(m.size() * sizeof(BatchProblem), 0);
+    for (size_t b = 0; b < m.size(); ++b) {
+        const BatchMember& a = m[b];
+        BatchProblem P;
+        P.n = a.n;
+        P.d = a.d;
+        P.mode = a.dipolar ? SPEC_DIPOLAR : SPEC_PLAIN;
+        P.rho = a.rho;
+        P.u = a.u;
+        P.X1 = reinterpret_cast<cpx*>(a.X1);
+        P.X2 = reinterpret_cast<cpx*>(a.X2);
+        P.spec = a.spec;
+        P.tw = reinterpret_cast<const cpx*>(a.tw);
+        P.dip.dxi = a.dxi;
+        for (int i = 0; i < 3; ++i) {
+            P.dip.cdiag[i] = a.cdiag[i];
+            P.dip.ccross[i] = a.ccross[i];
+        }
+        P.dip.nm_over_M = a.nm_over_M;
+        std::memcpy(out.data() + b * sizeof(BatchProblem), &P, sizeof(P));
+    }
+}
+
+void batch_tasks(const std::vector<BatchMember>& m, int mult, bool largest_first, std::vector<int>& tasks,
+                 int pass_off[6], int pass_cnt[6]) {
+    const int nb = (int)m.size();
+    std::vector<int> order(nb);
+    std::iota(order.begin(), order.end(), 0);
+    if (largest_first)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return (double)m[a].n * (m[a].d == 3 ? m[a].n : 1) > (double)m[b].n * (m[b].d == 3 ? m[b].n : 1);
+        });
+    std::vector<int> ntask(nb * 6, 0);      // tasks of pass p of member b
+    std::vector<BatchTask> T;
+    for (int p = 1; p <= 5; ++p) {
+        pass_off[p] = (int)T.size();
+        for (int b : order) {
+            const int d = m[b].d, n = m[b].n;
+            if (d == 2 && (p == 2 || p == 4)) continue;
+            const int dep = (p == 1) ? 0 : (d == 2 ? p - 2 : p - 1);
+            const int step = (BATCH_THREADS / threads_for(n, p)) * std::max(1, mult);
+            const int nt = tiles_for(n, p, d);
+            for (int t = 0; t < nt; t += step) {
+                BatchTask k;
+                k.prob = b;
+                k.pass = p;
+                k.tile0 = t;
+                k.tile1 = std::min(nt, t + step);
+                k.dep_pass = dep;
+                k.dep_count = dep ? ntask[b * 6 + dep] : 0;
+                T.push_back(k);
+                ntask[b * 6 + p]++;
+            }
+        }
+        pass_cnt[p] = (int)T.size() - pass_off[p];
+    }
+    pass_off[0] = pass_cnt[0] = 0;
+    tasks.resize(T.size() * BATCH_TASK_INTS);
+    std::memcpy(tasks.data(), T.data(), T.size() * sizeof(BatchTask));
+}
+
+int batch_counters(int nprob) { return batch_counter(nprob, 0); }
+
+int batch_resident_blocks() {
+    int dev = 0, cus = 0, a = 0, b = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)k_batch_queue, BATCH_THREADS, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)k_batch_pass<3>, BATCH_THREADS, 0);
+    const int per = std::max(1, std::min(a > 0 ? a : 1, b > 0 ? b : 1));
+    return cus * per;
+}
+
+hipError_t launch_batch_queue(const void* probs, const void* tasks, int ntasks, unsigned* ctr, int nctr, int grid,
+                              unsigned spin_limit, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    if (grid <= 0) return hipErrorInvalidValue;
+    k_batch_queue<<<std::min(grid, ntasks), BATCH_THREADS, 0, s>>>(static_cast<const BatchProblem*>(probs),
+                                                                  static_cast<const BatchTask*>(tasks), ntasks, ctr,
+                                                                  nctr, spin_limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_phased(const void* probs, const void* tasks, const int pass_off[6], const int pass_cnt[6],
+                               int grid, hipStream_t s) {
+    if (grid <= 0) return hipErrorInvalidValue;
+    auto P = static_cast<const BatchProblem*>(probs);
+    auto T = static_cast<const BatchTask*>(tasks);
+    for (int p = 1; p <= 5; ++p) {
+        const int c = pass_cnt[p];
+        if (c <= 0) continue;
+        const int g = std::min(grid, c);
+        const BatchTask* tp = T + pass_off[p];
+        switch (p) {
+            case 1: k_batch_pass<1><<<g, BATCH_THREADS, 0, s>>>(P, tp, c); break;
+            case 2: k_batch_pass<2><<<g, BATCH_THREADS, 0, s>>>(P, tp, c); break;
+            case 3: k_batch_pass<3><<<g, BATCH_THREADS, 0, s>>>(P, tp, c); break;
+            case 4: k_batch_pass<4><<<g, BATCH_THREADS, 0, s>>>(P, tp, c); break;
+            case 5: k_batch_pass<5><<<g, BATCH_THREADS, 0, s>>>(P, tp, c); break;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace gsk

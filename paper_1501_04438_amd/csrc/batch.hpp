@@ -1,0 +1,240 @@
+// batch.hpp -- batched evaluation of many independent problems of uneven sizes.
+//
+// The work of a batch is a list of tasks: a task is a run of consecutive tiles
+// (blocks of the single-problem launches) of one pass of one problem, grouped so
+// that one 256-thread block carries several small tiles at once.  The list is
+// pass-major (all P1 tasks, then all P2 tasks, ...), so every task depends only
+// on tasks before it.
+//
+//   queue schedule : ONE persistent launch.  Blocks pop tasks in list order from
+//                    a device counter; before a task of pass p a block waits until
+//                    every task of the preceding pass of the same problem has
+//                    published its writes (agent-scope release/acquire on a
+//                    per-problem counter).  A block only waits on tasks popped
+//                    earlier by running blocks, so the launch cannot deadlock
+//                    whatever the number of resident blocks.  The last block to
+//                    leave clears the counters for the next launch.
+//   phased schedule: one launch per pass type over the tasks of that pass; kernel
+//                    boundaries carry the dependencies.
+//
+// The tile code is the single-problem code, so every problem's result is bitwise
+// that of its own evaluation, under either schedule.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "passes.hpp"
+
+namespace gsk {
+
+constexpr int BATCH_THREADS = 256;
+
+struct BatchProblem {
+    int n, d, mode;            // mode: SPEC_PLAIN / SPEC_DIPOLAR
+    const double* rho;
+    double* u;
+    cpx* X1;
+    cpx* X2;
+    const double* spec;
+    const cpx* tw;
+    DipoleArgs dip;
+};
+
+struct BatchTask {
+    int prob, pass;            // problem index, pass 1..5
+    int tile0, tile1;          // tiles tile0 .. tile1 - 1 of that pass
+    int dep_pass, dep_count;   // wait until dep_count tasks of pass dep_pass of this problem are done (0: none)
+};
+
+// Counters of the queue schedule: [0] next task, [1] blocks that left,
+// [2 + 8 b + p] tasks of pass p of problem b that are done; one more word after
+// them is the error flag (a dependency wait gave up), which launches do not clear.
+__host__ __device__ constexpr int batch_counter(int prob, int pass) { return 2 + 8 * prob + pass; }
+
+// Threads and LDS slots of one tile of pass p at size N; tiles per problem.
+template <int N> __host__ __device__ constexpr int tile_threads(int pass) {
+    return (pass == 1 || pass == 5) ? Geo<N>::TX : (pass == 3 ? Geo<N>::TZ : Geo<N>::TY);
+}
+template <int N> __host__ __device__ constexpr int tile_lds(int pass) {
+    return ((pass == 1 || pass == 5) ? Geo<N>::PPX : (pass == 3 ? 2 * Geo<N>::PPZ : Geo<N>::PPY)) * Geo<N>::A;
+}
+template <int N> __host__ __device__ inline int tile_count(int pass, int d) {
+    using Gm = Geo<N>;
+    if (pass == 1 || pass == 5) return ((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX)) * (d == 3 ? N : 1);
+    if (pass == 2 || pass == 4) return ((N + Gm::PPY - 1) / Gm::PPY) * (N + 1);
+    const int np = (d == 3) ? (N + 1) * 2 * N : N + 1;
+    return (np + Gm::PPZ - 1) / Gm::PPZ;
+}
+
+// sizes a batch may hold
+#define GS_BATCH_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
+
+template <int N> constexpr int batch_lds_of() {
+    int m = 0;
+    for (int p = 1; p <= 5; ++p) {
+        const int s = tile_lds<N>(p) * (BATCH_THREADS / tile_threads<N>(p));
+        m = s > m ? s : m;
+    }
+    return m;
+}
+#define GS_LDS_OF(N) batch_lds_of<N>(),
+constexpr int batch_lds_slots() {
+    constexpr int v[] = {GS_BATCH_SIZES(GS_LDS_OF) 0};
+    int m = 0;
+    for (int x : v) m = x > m ? x : m;
+    return m;
+}
+#undef GS_LDS_OF
+
+// Tiles tile0 .. tile0 + (block / tile threads) - 1 of pass PASS of one problem.
+template <int N, int PASS>
+__device__ __forceinline__ void batch_tile(const BatchProblem& P, int tile0, int tile1, cpx* lds) {
+    constexpr int T = tile_threads<N>(PASS);
+    static_assert(BATCH_THREADS % T == 0, "tile threads must divide the block");
+    // the thread index is laundered so that nothing derived from it is hoisted out
+    // of the task loop (kept live across every size and pass, that would spill)
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
+    const int sub = lane / T, tid = lane % T;
+    const int tile = tile0 + sub;
+    const bool active = tile < tile1;
+    cpx* l = lds + sub * tile_lds<N>(PASS);
+    using Gm = Geo<N>;
+    // descriptor pointers typed as global memory (global, not flat, accesses)
+    const gp<const double> rho = (gp<const double>)P.rho;
+    const gp<double> u = (gp<double>)P.u;
+    const gp<cpx> X1 = (gp<cpx>)P.X1;
+    const gp<cpx> X2 = (gp<cpx>)P.X2;
+    const gp<const double> spec = (gp<const double>)P.spec;
+    const gp<const cpx> tw = (gp<const cpx>)P.tw;
+    if constexpr (PASS == 1 || PASS == 5) {
+        constexpr int nbx = (N + 2 * Gm::PPX - 1) / (2 * Gm::PPX);
+        const int bx = tile % nbx, z = tile / nbx;
+        if constexpr (PASS == 1) x_r2c_tile<N>(rho, X1, tw, bx, z, tid, active, l);
+        else x_c2r_tile<N>(X1, u, tw, bx, z, tid, active, l);
+    } else if constexpr (PASS == 2 || PASS == 4) {
+        constexpr int nbz = (N + Gm::PPY - 1) / Gm::PPY;
+        const int bx = tile % nbz, kxl = tile / nbz;
+        if constexpr (PASS == 2) y_fwd_tile<N>(X1, X2, tw, 0, bx, kxl, tid, active, l);
+        else y_inv_tile<N>(X2, X1, tw, 0, bx, kxl, tid, active, l);
+    } else {
+        if (P.d == 3) {
+            const int np = (N + 1) * 2 * N;
+            if (P.mode == SPEC_DIPOLAR)
+                fused_group<N, 3, SPEC_DIPOLAR>(X2, spec, tw, np, 0, P.dip, tile, tid, active, l);
+            else
+                fused_group<N, 3, SPEC_PLAIN>(X2, spec, tw, np, 0, P.dip, tile, tid, active, l);
+        } else {
+            fused_group<N, 2, SPEC_PLAIN>(X1, spec, tw, N + 1, 0, P.dip, tile, tid, active, l);
+        }
+    }
+}
+
+// All tiles of one task, one block-full at a time.
+template <int N, int PASS>
+__device__ __forceinline__ void batch_run(const BatchProblem& P, int tile0, int tile1, cpx* lds) {
+    constexpr int sub = BATCH_THREADS / tile_threads<N>(PASS);
+    for (int j = tile0; j < tile1; j += sub) {
+        batch_tile<N, PASS>(P, j, tile1, lds);
+        lds_barrier();      // the next tiles reuse the LDS
+    }
+}
+
+template <int PASS>
+__device__ __forceinline__ void batch_task_pass(const BatchProblem& P, const BatchTask& t, cpx* lds) {
+    switch (P.n) {
+#define GS_CASE(N) \
+    case N: batch_run<N, PASS>(P, t.tile0, t.tile1, lds); break;
+        GS_BATCH_SIZES(GS_CASE)
+#undef GS_CASE
+        default: break;
+    }
+}
+
+__device__ __forceinline__ void batch_task(const BatchProblem& P, const BatchTask& t, cpx* lds) {
+    switch (t.pass) {
+        case 1: batch_task_pass<1>(P, t, lds); break;
+        case 2: batch_task_pass<2>(P, t, lds); break;
+        case 3: batch_task_pass<3>(P, t, lds); break;
+        case 4: batch_task_pass<4>(P, t, lds); break;
+        case 5: batch_task_pass<5>(P, t, lds); break;
+        default: break;
+    }
+}
+
+// Phased schedule: the tasks of one pass, block-strided.
+template <int PASS>
+__global__ void __launch_bounds__(BATCH_THREADS) k_batch_pass(const BatchProblem* __restrict__ probs,
+                                                              const BatchTask* __restrict__ tasks, int ntasks) {
+    __shared__ cpx lds[batch_lds_slots()];
+    for (int k = blockIdx.x; k < ntasks; k += gridDim.x) {
+        const BatchTask t = tasks[k];
+        batch_task_pass<PASS>(probs[t.prob], t, lds);
+    }
+}
+
+// Queue schedule: one persistent launch over every task of the batch.
+//
+// Every branch of the task loop is wave-uniform (conditions pass through
+// readfirstlane): wave 0 of the block does the counter work with all its lanes,
+// lane 0 contributing the increment and the others zero.  A lane-0-only branch at
+// the loop boundary would let the compiler park lane 0 outside the loop while the
+// other lanes of its wave run on through the barriers with a stale task index.
+//
+// A dependency wait gives up after spin_limit polls (far beyond any task's
+// duration): it raises the error flag ctr[nctr] and carries on, so every wave
+// reaches the end of the launch whatever happens; the host reads the flag.
+__global__ void __launch_bounds__(BATCH_THREADS) k_batch_queue(const BatchProblem* __restrict__ probs,
+                                                               const BatchTask* __restrict__ tasks, int ntasks,
+                                                               unsigned* __restrict__ ctr, int nctr,
+                                                               unsigned spin_limit) {
+    __shared__ cpx lds[batch_lds_slots()];
+    __shared__ int s_task;
+    const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64u;
+    const unsigned one = (threadIdx.x == 0) ? 1u : 0u;      // the increment of lane 0
+    for (;;) {
+        if (wave0) {
+            const unsigned k = __hip_atomic_fetch_add(&ctr[0], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_task = (int)__builtin_amdgcn_readfirstlane(k);
+        }
+        __syncthreads();
+        const int k = __builtin_amdgcn_readfirstlane(s_task);
+        __syncthreads();
+        if (k >= ntasks) break;
+        const BatchTask t = tasks[k];
+        if (t.dep_count > 0) {
+            if (wave0) {
+                unsigned* c = &ctr[batch_counter(t.prob, t.dep_pass)];
+                for (unsigned polls = 0;; ++polls) {
+                    const unsigned done =
+                        __builtin_amdgcn_readfirstlane(__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (done >= (unsigned)t.dep_count) break;
+                    if (polls >= spin_limit) {
+                        __hip_atomic_store(&ctr[nctr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+        }
+        batch_task(probs[t.prob], t, lds);
+        __syncthreads();                       // every wave's stores are issued and complete
+        if (wave0)
+            __hip_atomic_fetch_add(&ctr[batch_counter(t.prob, t.pass)], one, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the last block to leave clears the counters (the next launch starts after this one ends)
+    if (wave0) {
+        const unsigned e = __hip_atomic_fetch_add(&ctr[1], one, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_task = (__builtin_amdgcn_readfirstlane(e) == gridDim.x - 1u) ? 1 : 0;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_task)) {
+        for (int i = threadIdx.x; i < nctr; i += BATCH_THREADS)
+            __hip_atomic_store(&ctr[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+}  // namespace gsk

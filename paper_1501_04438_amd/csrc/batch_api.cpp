@@ -1,0 +1,451 @@
+// batch_api.cpp -- the batch object of the C ABI (include/gs.h): descriptors and
+// task lists in device memory, schedule resolution (fixed or autotuned), and
+// replay of the launch sequence through a hipGraph.
+//
+// All work of a batch runs on a stream the batch owns, ordered after the
+// caller's stream by an event and waited for by the caller's stream in turn, so
+// the launch sequence can be captured whatever the caller's stream is.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "api_internal.hpp"
+#include "autotune.hpp"
+
+using namespace gsapi;
+
+struct gs_batch_s {
+    std::vector<gs_plan> plans;
+    int device = 0;
+    hipStream_t user = nullptr, own = nullptr;
+    gs_batch_options req{};
+    TuneEntry cfg;
+    bool resolved = false, autotuned = false, kernels_ok = true;
+    int candidates = 0;
+    double tuned_ms = 0.0, points = 0.0;
+    int resident = 0;
+    // device memory
+    void* d_probs = nullptr;
+    size_t probs_bytes = 0;
+    int* d_tasks = nullptr;
+    size_t tasks_cap = 0;                 // ints
+    unsigned* d_ctr = nullptr;
+    int nctr = 0;
+    unsigned char* h_stage = nullptr;     // pinned staging of the descriptors
+    std::vector<unsigned char> probs_dev; // descriptors now in device memory
+    int ntasks = 0, pass_off[6] = {}, pass_cnt[6] = {};
+    int tasks_mult = -1, tasks_lf = -1;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_staged = nullptr;
+    bool staged_pending = false;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> graph_sig;   // what the captured launches baked in
+};
+
+namespace {
+
+// Polls of a dependency wait before it gives up (about 2 us each: seconds in all,
+// orders of magnitude beyond the longest task).
+constexpr unsigned kSpinLimit = 1u << 22;
+
+std::mutex g_batch_mu;
+std::unordered_set<gs_batch_s*> g_batches;
+
+bool batch_live(gs_batch b) {
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    return b && g_batches.count(b);
+}
+
+void release(gs_batch_s* b) {
+    DeviceScope ds(b->device);
+    if (b->own) (void)hipStreamSynchronize(b->own);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->d_probs) (void)hipFree(b->d_probs);
+    if (b->d_tasks) (void)hipFree(b->d_tasks);
+    if (b->d_ctr) (void)hipFree(b->d_ctr);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->ev_staged) (void)hipEventDestroy(b->ev_staged);
+    if (b->own) (void)hipStreamDestroy(b->own);
+    delete b;
+}
+
+gs_status members(gs_batch_s* b, const double* const* rho, double* const* u, std::vector<gsk::BatchMember>& m) {
+    m.resize(b->plans.size());
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        gsk::EvalArgs a;
+        const gs_status st = make_args(b->plans[i], rho[i], u[i], a);
+        if (st != GS_OK) return st;
+        gsk::BatchMember& x = m[i];
+        x.d = a.d;
+        x.n = a.n;
+        x.dipolar = a.dipolar;
+        x.rho = a.rho;
+        x.u = a.u;
+        x.X1 = a.X1;
+        x.X2 = a.X2;
+        x.spec = a.spec;
+        x.tw = a.tw;
+        x.dxi = a.dxi;
+        for (int k = 0; k < 3; ++k) {
+            x.cdiag[k] = a.cdiag[k];
+            x.ccross[k] = a.ccross[k];
+        }
+        x.nm_over_M = a.nm_over_M;
+    }
+    return GS_OK;
+}
+
+// The task list of (mult, largest_first) in device memory (synchronous: rare).
+gs_status upload_tasks(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, int mult, int lf) {
+    if (b->tasks_mult == mult && b->tasks_lf == lf) return GS_OK;
+    std::vector<int> t;
+    gsk::batch_tasks(m, mult, lf != 0, t, b->pass_off, b->pass_cnt);
+    hipError_t e = hipStreamSynchronize(b->own);
+    if (e != hipSuccess) return hip_fail(e, "batch stream");
+    if (t.size() > b->tasks_cap) {
+        if (b->d_tasks) (void)hipFree(b->d_tasks);
+        b->d_tasks = nullptr;
+        b->tasks_cap = 0;
+        if ((e = hipMalloc(&b->d_tasks, t.size() * sizeof(int))) != hipSuccess)
+            return fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(batch tasks) failed");
+        b->tasks_cap = t.size();
+    }
+    if ((e = hipMemcpy(b->d_tasks, t.data(), t.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(batch tasks)");
+    b->ntasks = (int)(t.size() / gsk::BATCH_TASK_INTS);
+    b->tasks_mult = mult;
+    b->tasks_lf = lf;
+    return GS_OK;
+}
+
+// Descriptors (they carry the rho / u pointers) to device memory when they changed.
+gs_status upload_probs(gs_batch_s* b, const std::vector<gsk::BatchMember>& m) {
+    std::vector<unsigned char> bytes;
+    gsk::batch_problems(m, bytes);
+    if (bytes == b->probs_dev) return GS_OK;
+    hipError_t e = hipSuccess;
+    if (b->staged_pending && (e = hipEventSynchronize(b->ev_staged)) != hipSuccess)
+        return hip_fail(e, "batch staging");
+    std::memcpy(b->h_stage, bytes.data(), bytes.size());
+    if ((e = hipMemcpyAsync(b->d_probs, b->h_stage, bytes.size(), hipMemcpyHostToDevice, b->own)) != hipSuccess ||
+        (e = hipEventRecord(b->ev_staged, b->own)) != hipSuccess)
+        return hip_fail(e, "batch descriptor upload");
+    b->staged_pending = true;
+    b->probs_dev.swap(bytes);
+    return GS_OK;
+}
+
+// Queues one evaluation of the whole batch on the batch stream under cfg.
+gs_status launch(gs_batch_s* b, const TuneEntry& c, const double* const* rho, double* const* u) {
+    hipError_t e = hipSuccess;
+    const int grid = c.grid > 0 ? c.grid : b->resident;
+    if (c.schedule == GS_SCHED_QUEUE) {
+        e = gsk::launch_batch_queue(b->d_probs, b->d_tasks, b->ntasks, b->d_ctr, b->nctr, grid, kSpinLimit, b->own);
+    } else if (c.schedule == GS_SCHED_PHASED) {
+        e = gsk::launch_batch_phased(b->d_probs, b->d_tasks, b->pass_off, b->pass_cnt, grid, b->own);
+    } else {
+        for (size_t i = 0; i < b->plans.size(); ++i) {
+            gs_plan p = b->plans[i];
+            const hipStream_t keep = p->stream;
+            p->stream = b->own;
+            const gs_status st = eval_chain(p, rho[i], u[i], -1);
+            p->stream = keep;
+            if (st != GS_OK) return st;
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return GS_OK;
+}
+
+std::string shape_key(const gs_batch_s* b) {
+    std::map<std::string, int> c;
+    for (gs_plan p : b->plans)
+        c[std::to_string(p->d) + "d" + std::to_string(p->n) + (p->kernel == GS_DIPOLAR_3D ? "dip" : "")]++;
+    std::string k;
+    for (const auto& [s, cnt] : c) k += (k.empty() ? "" : ",") + s + "x" + std::to_string(cnt);
+    return k;
+}
+
+gs_status time_candidate(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const TuneEntry& c,
+                         const double* const* rho, double* const* u, double& ms) {
+    if (c.schedule != GS_SCHED_SEQUENTIAL) {
+        const gs_status st = upload_tasks(b, m, c.tiles_per_task, c.largest_first);
+        if (st != GS_OK) return st;
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    gs_status st = launch(b, c, rho, u);          // warm-up
+    ms = 1e300;
+    for (int r = 0; r < 3 && st == GS_OK; ++r) {
+        (void)hipEventRecord(t0, b->own);
+        st = launch(b, c, rho, u);
+        (void)hipEventRecord(t1, b->own);
+        const hipError_t e = hipEventSynchronize(t1);
+        if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+        float f = 0.f;
+        (void)hipEventElapsedTime(&f, t0, t1);
+        ms = std::min(ms, (double)f);
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return st;
+}
+
+gs_status autotune(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const double* const* rho,
+                   double* const* u) {
+    const std::string key = tune_device_key(b->device) + "|batch|" + shape_key(b);
+    TuneEntry best;
+    if (tune_lookup(key, best) && (best.schedule == GS_SCHED_SEQUENTIAL || b->kernels_ok)) {
+        b->cfg = best;
+        b->autotuned = true;
+        b->tuned_ms = best.ms;
+        return GS_OK;
+    }
+    std::vector<TuneEntry> cand;
+    if (b->kernels_ok) {
+        for (int mult : {1, 2, 4}) cand.push_back({GS_SCHED_QUEUE, mult, 1, 0, 0.0});
+        cand.push_back({GS_SCHED_QUEUE, 1, 0, 0, 0.0});
+        for (int mult : {1, 4}) cand.push_back({GS_SCHED_PHASED, mult, 1, 0, 0.0});
+    }
+    cand.push_back({GS_SCHED_SEQUENTIAL, 1, 1, 0, 0.0});
+    best.ms = 1e300;
+    for (TuneEntry c : cand) {
+        double ms = 0.0;
+        const gs_status st = time_candidate(b, m, c, rho, u, ms);
+        if (st != GS_OK) return st;
+        b->candidates++;
+        if (ms < best.ms) {
+            best = c;
+            best.ms = ms;
+        }
+    }
+    tune_store(key, best);
+    b->cfg = best;
+    b->autotuned = true;
+    b->tuned_ms = best.ms;
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gs_batch_options_default(gs_batch_options* opt) {
+    if (opt) std::memset(opt, 0, sizeof(*opt));
+}
+
+gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const gs_batch_options* opt_in) {
+    if (!out) return fail(GS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    gs_batch_options opt;
+    gs_batch_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    if (count < 1 || !plans) return fail(GS_ERR_INVALID_ARG, "invalid batch arguments");
+    if (opt.schedule < GS_SCHED_AUTO || opt.schedule > GS_SCHED_SEQUENTIAL || opt.tiles_per_task < 0 || opt.grid < 0)
+        return fail(GS_ERR_INVALID_ARG, "invalid batch options");
+    std::unordered_set<gs_plan> seen;
+    bool kernels_ok = true;
+    for (int i = 0; i < count; ++i) {
+        gs_plan p = plans[i];
+        if (!is_live(p) || p->host_only) return fail(GS_ERR_INVALID_ARG, "invalid plan in batch");
+        if (!seen.insert(p).second) return fail(GS_ERR_INVALID_ARG, "a plan appears twice in the batch");
+        if (p->device != plans[0]->device) return fail(GS_ERR_INVALID_ARG, "batch spans devices");
+        if (!gsk::batch_size_supported(p->d, p->n)) {
+            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED)
+                return fail(GS_ERR_UNSUPPORTED_SIZE, "batched kernels cover n <= 128 of the compiled list");
+            kernels_ok = false;
+        }
+        if (p->nslabs != 1) {
+            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED)
+                return fail(GS_ERR_INVALID_ARG, "a batched plan must run its middle passes in one slab");
+            kernels_ok = false;
+        }
+    }
+    auto* b = new gs_batch_s();
+    b->plans.assign(plans, plans + count);
+    b->device = plans[0]->device;
+    b->user = (hipStream_t)opt.stream;
+    b->req = opt;
+    b->kernels_ok = kernels_ok;
+    for (gs_plan p : b->plans) b->points += std::pow((double)p->n, p->d);
+    DeviceScope ds(b->device);
+    hipError_t e = ds.err;
+    gs_status st = GS_OK;
+    std::vector<gsk::BatchMember> m;
+    {
+        std::vector<const double*> r(count, nullptr);
+        std::vector<double*> w(count, nullptr);
+        std::vector<double> dummy(1);
+        for (int i = 0; i < count; ++i) {
+            r[i] = dummy.data();
+            w[i] = dummy.data();
+        }
+        st = members(b, r.data(), w.data(), m);
+    }
+    std::vector<unsigned char> bytes;
+    gsk::batch_problems(m, bytes);
+    b->probs_bytes = bytes.size();
+    b->nctr = gsk::batch_counters(count);
+    if (st == GS_OK && e != hipSuccess) st = hip_fail(e, "hipSetDevice");
+    if (st == GS_OK && (e = hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking)) != hipSuccess)
+        st = hip_fail(e, "hipStreamCreate");
+    if (st == GS_OK && ((e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) != hipSuccess ||
+                        (e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming)) != hipSuccess ||
+                        (e = hipEventCreateWithFlags(&b->ev_staged, hipEventDisableTiming)) != hipSuccess))
+        st = hip_fail(e, "hipEventCreate");
+    if (st == GS_OK && (hipMalloc(&b->d_probs, b->probs_bytes) != hipSuccess ||
+                        hipMalloc(&b->d_ctr, (b->nctr + 1) * sizeof(unsigned)) != hipSuccess ||
+                        hipHostMalloc(&b->h_stage, b->probs_bytes) != hipSuccess))
+        st = fail(GS_ERR_OUT_OF_MEMORY, "batch allocation failed");
+    if (st == GS_OK) {
+        // the queue counters and the error flag start at zero; each queue launch
+        // leaves the counters at zero
+        std::vector<unsigned> zero(b->nctr + 1, 0u);
+        if ((e = hipMemcpy(b->d_ctr, zero.data(), zero.size() * sizeof(unsigned), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            st = hip_fail(e, "hipMemcpy(batch counters)");
+    }
+    if (st == GS_OK) b->resident = gsk::batch_resident_blocks();
+    if (st == GS_OK && opt.schedule != GS_SCHED_AUTO) {
+        b->cfg = {opt.schedule, std::max(1, opt.tiles_per_task), 1, opt.grid, 0.0};
+        if (opt.schedule != GS_SCHED_SEQUENTIAL) st = upload_tasks(b, m, b->cfg.tiles_per_task, 1);
+        b->resolved = true;
+    }
+    if (st != GS_OK) {
+        (void)hipGetLastError();
+        release(b);
+        return st;
+    }
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    g_batches.insert(b);
+    *out = b;
+    return GS_OK;
+}
+
+gs_status gs_batch_eval(gs_batch b, const double* const* rho, double* const* u) {
+    if (!batch_live(b)) return fail(GS_ERR_INVALID_ARG, "invalid batch");
+    if (!rho || !u) return fail(GS_ERR_INVALID_ARG, "NULL pointer array");
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        if (!is_live(b->plans[i])) return fail(GS_ERR_INVALID_ARG, "a plan of the batch was destroyed");
+        if (!rho[i] || !u[i]) return fail(GS_ERR_INVALID_ARG, "NULL device pointer in batch");
+    }
+    DeviceScope ds(b->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    std::vector<gsk::BatchMember> m;
+    gs_status st = members(b, rho, u, m);
+    if (st != GS_OK) return st;
+    hipError_t e;
+    if ((e = hipEventRecord(b->ev_in, b->user)) != hipSuccess || (e = hipStreamWaitEvent(b->own, b->ev_in, 0)) != hipSuccess)
+        return hip_fail(e, "batch stream ordering");
+    if ((st = upload_probs(b, m)) != GS_OK) return st;
+    if (!b->resolved) {
+        if ((st = autotune(b, m, rho, u)) != GS_OK) return st;
+        b->resolved = true;
+    }
+    if (b->cfg.schedule != GS_SCHED_SEQUENTIAL &&
+        (st = upload_tasks(b, m, b->cfg.tiles_per_task, b->cfg.largest_first)) != GS_OK)
+        return st;
+    if (b->req.use_graph) {
+        // what the captured launches bake in: the task list, and for the sequential
+        // schedule the rho / u pointers themselves
+        std::vector<const void*> sig = {b->d_tasks, (const void*)(intptr_t)b->ntasks,
+                                        (const void*)(intptr_t)b->cfg.schedule};
+        if (b->cfg.schedule == GS_SCHED_SEQUENTIAL)
+            for (size_t i = 0; i < b->plans.size(); ++i) {
+                sig.push_back(rho[i]);
+                sig.push_back(u[i]);
+            }
+        if (!b->exec || sig != b->graph_sig) {
+            if (b->exec) {
+                (void)hipStreamSynchronize(b->own);
+                (void)hipGraphExecDestroy(b->exec);
+                b->exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            if ((e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(e, "hipStreamBeginCapture");
+            st = launch(b, b->cfg, rho, u);
+            e = hipStreamEndCapture(b->own, &g);
+            if (st != GS_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                b->exec = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            b->graph_sig = sig;
+        }
+        if ((e = hipGraphLaunch(b->exec, b->own)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else {
+        if ((st = launch(b, b->cfg, rho, u)) != GS_OK) return st;
+    }
+    if ((e = hipEventRecord(b->ev_out, b->own)) != hipSuccess || (e = hipStreamWaitEvent(b->user, b->ev_out, 0)) != hipSuccess)
+        return hip_fail(e, "batch stream ordering");
+    return GS_OK;
+}
+
+gs_status gs_batch_query(gs_batch b, gs_batch_info* info) {
+    if (!batch_live(b) || !info) return fail(GS_ERR_INVALID_ARG, "invalid batch or info");
+    std::memset(info, 0, sizeof(*info));
+    info->count = (int)b->plans.size();
+    info->points = b->points;
+    info->schedule = b->resolved ? b->cfg.schedule : GS_SCHED_AUTO;
+    info->tiles_per_task = b->cfg.tiles_per_task;
+    info->grid = b->cfg.grid > 0 ? b->cfg.grid : b->resident;
+    info->use_graph = b->req.use_graph;
+    info->num_tasks = b->ntasks;
+    for (int p = 0; p < 6; ++p) info->tasks_per_pass[p] = b->pass_cnt[p];
+    info->autotuned = b->autotuned ? 1 : 0;
+    info->candidates = b->candidates;
+    info->tuned_ms = b->tuned_ms;
+    DeviceScope ds(b->device);
+    unsigned flag = 0;
+    hipError_t e = hipStreamSynchronize(b->own);
+    if (e == hipSuccess)
+        e = hipMemcpy(&flag, b->d_ctr + b->nctr, sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "batch query");
+    info->wait_timeouts = flag ? 1 : 0;
+    return GS_OK;
+}
+
+gs_status gs_batch_destroy(gs_batch b) {
+    if (!b) return GS_OK;
+    {
+        std::lock_guard<std::mutex> g(g_batch_mu);
+        if (!g_batches.count(b)) return GS_OK;
+        g_batches.erase(b);
+    }
+    release(b);
+    return GS_OK;
+}
+
+gs_status gs_eval_batch(int count, const gs_plan* plans, const double* const* rho_dev, double* const* u_dev) {
+    if (count <= 0 || !plans || !rho_dev || !u_dev) return fail(GS_ERR_INVALID_ARG, "invalid batch arguments");
+    for (int i = 0; i < count; ++i)
+        if (!is_live(plans[i])) return fail(GS_ERR_INVALID_ARG, "invalid plan in batch");
+    gs_batch_options opt;
+    gs_batch_options_default(&opt);
+    opt.schedule = GS_SCHED_QUEUE;
+    opt.stream = plans[0]->stream;
+    gs_batch b = nullptr;
+    gs_status st = gs_batch_create(&b, count, plans, &opt);
+    if (st != GS_OK) return st;
+    st = gs_batch_eval(b, rho_dev, u_dev);
+    const gs_status st2 = gs_batch_destroy(b);
+    return st != GS_OK ? st : st2;
+}
+
+}  // extern "C"

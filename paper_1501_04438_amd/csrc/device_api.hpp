@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <vector>
 
 namespace gsk {
 
@@ -43,5 +44,33 @@ struct AssemblyArgs {
 // Row blocks per wave chosen for n1; returns the padded k length the operands need.
 int assembly_ldk(int n1);
 hipError_t launch_assembly(const AssemblyArgs& a, hipStream_t s);
+
+// Batched evaluation of independent problems (sizes up to 128, batch.hpp).
+struct BatchMember {
+    int d = 3, n = 0, dipolar = 0;
+    const double* rho = nullptr;
+    double* u = nullptr;
+    double2* X1 = nullptr;
+    double2* X2 = nullptr;
+    const double* spec = nullptr;
+    const double2* tw = nullptr;
+    double dxi = 0.0, cdiag[3] = {0, 0, 0}, ccross[3] = {0, 0, 0}, nm_over_M = 0.0;
+};
+bool batch_size_supported(int d, int n);
+// packed device descriptors of the members (copy to device memory as is)
+void batch_problems(const std::vector<BatchMember>& m, std::vector<unsigned char>& out);
+constexpr int BATCH_TASK_INTS = 6;
+// Pass-major task list; mult = block-fulls of tiles per task; largest_first orders the
+// members of each pass by size.  pass_off/pass_cnt: the tasks of pass p (index p).
+void batch_tasks(const std::vector<BatchMember>& m, int mult, bool largest_first, std::vector<int>& tasks,
+                 int pass_off[6], int pass_cnt[6]);
+// unsigned counters of the queue schedule (start zeroed); the error flag is the word after them
+int batch_counters(int nprob);
+int batch_resident_blocks();              // co-resident blocks of the batch kernels on this device
+// spin_limit: polls after which a dependency wait raises the error flag and goes on
+hipError_t launch_batch_queue(const void* probs, const void* tasks, int ntasks, unsigned* ctr, int nctr, int grid,
+                              unsigned spin_limit, hipStream_t s);
+hipError_t launch_batch_phased(const void* probs, const void* tasks, const int pass_off[6], const int pass_cnt[6],
+                               int grid, hipStream_t s);
 
 }  // namespace gsk

@@ -38,35 +38,38 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
     }
     dip.nm_over_M = a.nm_over_M;
     const int nz = (a.d == 3) ? N : 1;
+    cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
+    cpx* const X2 = reinterpret_cast<cpx*>(a.X2);
+    const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
     static const int cap3 = resident_blocks((const void*)k_fused<N, 3, SPEC_PLAIN>, Gm::TZ);
     static const int cap2 = resident_blocks((const void*)k_fused<N, 2, SPEC_PLAIN>, Gm::TZ);
     const int capf = a.max_blocks_fused > 0 ? a.max_blocks_fused : (a.d == 3 ? cap3 : cap2);
     const dim3 gx((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX), nz);
     auto run = [&](int p) { return which < 0 || which == p; };
-    if (run(1)) k_x_r2c<N><<<gx, Gm::TX, 0, s>>>(a.rho, a.X1, a.tw);
+    if (run(1)) k_x_r2c<N><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw);
     if constexpr (N <= GS_MAX_N_3D) {
       if (a.d == 3) {
         const dim3 gy((N + Gm::PPY - 1) / Gm::PPY, a.kxn);
         const int np = a.kxn * 2 * N;
-        if (run(2)) k_y_fwd<N><<<gy, Gm::TY, 0, s>>>(a.X1, a.X2, a.tw, a.kx0);
+        if (run(2)) k_y_fwd<N><<<gy, Gm::TY, 0, s>>>(X1, X2, tw, a.kx0);
         if (run(3)) {
             const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf);
             if (a.dipolar)
-                k_fused<N, 3, SPEC_DIPOLAR><<<nb, Gm::TZ, 0, s>>>(a.X2, a.spec, a.tw, np, a.kx0, dip);
+                k_fused<N, 3, SPEC_DIPOLAR><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
             else
-                k_fused<N, 3, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(a.X2, a.spec, a.tw, np, a.kx0, dip);
+                k_fused<N, 3, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
         }
-        if (run(4)) k_y_inv<N><<<gy, Gm::TY, 0, s>>>(a.X2, a.X1, a.tw, a.kx0);
-        if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(a.X1, a.u, a.tw);
+        if (run(4)) k_y_inv<N><<<gy, Gm::TY, 0, s>>>(X2, X1, tw, a.kx0);
+        if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
         return hipGetLastError();
       }
     }
     {
         const int np = N + 1;
         const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf);
-        if (run(3)) k_fused<N, 2, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(a.X1, a.spec, a.tw, np, 0, dip);
+        if (run(3)) k_fused<N, 2, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
     }
-    if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(a.X1, a.u, a.tw);
+    if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
     return hipGetLastError();
 }
 

@@ -24,9 +24,19 @@
 
 namespace gsk {
 
-typedef double2 cpx;
+// Global-memory pointer.  Device functions take global data through this type so
+// that every access compiles to a global (not flat) instruction, also where the
+// pointer was read from memory rather than passed as a kernel argument.
+template <class T> using gp = __attribute__((address_space(1))) T*;
 
-__device__ __forceinline__ cpx cmk(double a, double b) { return make_double2(a, b); }
+// complex FP64 as a native two-lane vector: copies from any address space are
+// plain loads and stores
+typedef double cpx __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ cpx cmk(double a, double b) {
+    cpx r = {a, b};
+    return r;
+}
 __device__ __forceinline__ cpx cadd(cpx a, cpx b) { return cmk(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ cpx csub(cpx a, cpx b) { return cmk(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ cpx cscale(cpx a, double s) { return cmk(a.x * s, a.y * s); }
@@ -192,13 +202,13 @@ struct FftPlan {
 template <int N> struct FftCfg;
 template <> struct FftCfg<8> : FftPlan<8, 8, 1, 8> {};
 template <> struct FftCfg<12> : FftPlan<12, 12, 2, 4, 3> {};
-template <> struct FftCfg<16> : FftPlan<16, 16, 1, 16> {};
-template <> struct FftCfg<24> : FftPlan<24, 24, 2, 8, 3> {};
+template <> struct FftCfg<16> : FftPlan<16, 8, 2, 4, 4> {};
+template <> struct FftCfg<24> : FftPlan<24, 12, 2, 4, 6> {};
 template <> struct FftCfg<32> : FftPlan<32, 8, 2, 4, 8> {};
 template <> struct FftCfg<48> : FftPlan<48, 12, 3, 4, 4, 3> {};
 template <> struct FftCfg<64> : FftPlan<64, 8, 2, 8, 8> {};
 template <> struct FftCfg<96> : FftPlan<96, 12, 4, 4, 4, 2, 3> {};
-template <> struct FftCfg<128> : FftPlan<128, 16, 2, 16, 8> {};
+template <> struct FftCfg<128> : FftPlan<128, 8, 3, 8, 4, 4> {};
 template <> struct FftCfg<192> : FftPlan<192, 12, 4, 4, 4, 4, 3> {};
 template <> struct FftCfg<256> : FftPlan<256, 16, 2, 16, 16> {};
 template <> struct FftCfg<512> : FftPlan<512, 8, 3, 8, 8, 8> {};
@@ -258,7 +268,7 @@ __device__ __forceinline__ void mul_powers(cpx* v, cpx w1, cpx w4) {
 // One Stockham stage on registers: twiddles (unless first) and E/R DFTs of radix R.
 // The twiddles W_N^{base r} are powers of W_N^{base} (two table reads per butterfly).
 template <int N, int E, int R, int NSPRE, bool INV>
-__device__ __forceinline__ void stage_compute(cpx (&v)[E], int t, const cpx* __restrict__ tw) {
+__device__ __forceinline__ void stage_compute(cpx (&v)[E], int t, gp<const cpx> __restrict__ tw) {
     constexpr int G = N / E, B = E / R;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -276,7 +286,7 @@ __device__ __forceinline__ void stage_compute(cpx (&v)[E], int t, const cpx* __r
 // Padding twist before a forward transform: x[j] *= W_2N^j for j = t + G e, as
 // W_2N^t (one table read) times the constant W_2E^e.
 template <class P>
-__device__ __forceinline__ void twist_in(cpx (&v)[P::E], int t, const cpx* __restrict__ tw) {
+__device__ __forceinline__ void twist_in(cpx (&v)[P::E], int t, gp<const cpx> __restrict__ tw) {
     constexpr int E = P::E;
     const cpx c = tw[t];
     [&]<int... I>(std::integer_sequence<int, I...>) {
@@ -286,7 +296,7 @@ __device__ __forceinline__ void twist_in(cpx (&v)[P::E], int t, const cpx* __res
 
 // Cropping twist after an inverse transform: y[j] *= conj(W_2N^j), j = t + G e.
 template <class P>
-__device__ __forceinline__ void twist_out(cpx (&v)[P::E], int t, const cpx* __restrict__ tw) {
+__device__ __forceinline__ void twist_out(cpx (&v)[P::E], int t, gp<const cpx> __restrict__ tw) {
     constexpr int E = P::E;
     const cpx c = tw[t];
     [&]<int... I>(std::integer_sequence<int, I...>) {
@@ -321,7 +331,7 @@ __device__ __forceinline__ void stage_gather(cpx (&v)[E], int t, const cpx* lds)
 // areas must not be in use by other threads when it is entered.
 template <class C, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft(cpx (&v)[C::E], int t1, cpx* lds1, int t2, cpx* lds2,
-                                    const cpx* __restrict__ tw) {
+                                    gp<const cpx> __restrict__ tw) {
     constexpr int N = C::N;
     constexpr int E = C::E;
     constexpr int R0 = C::R[0], R1 = C::R[1], R2 = C::R[2], R3 = C::R[3];

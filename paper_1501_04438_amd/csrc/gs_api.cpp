@@ -19,29 +19,10 @@
 #include "../../include/gs.h"
 #include "device_api.hpp"
 #include "host_plan.hpp"
+#include "api_internal.hpp"
 
-struct gs_plan_s {
-    int kernel = 0, d = 0, n = 0;
-    double L = 0, eps = 0, delta_rel = 0;
-    gsh::Table table;
-    std::vector<double> F;
-    double A0 = 0, c2 = 0;
-    std::vector<double> spec_host;
-    double dn[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
-    int device = 0, flags = 0;
-    bool host_only = false;
-    hipStream_t stream = nullptr;
-    double* spec = nullptr;
-    double2* X1 = nullptr;
-    double2* X2 = nullptr;
-    double2* tw = nullptr;
-    size_t spec_bytes = 0, work_bytes = 0;
-    double assembly_ms = 0.0;
-    int slab = 0, nslabs = 1;                 // 3D: kx planes per slab of the middle passes
-    std::vector<std::pair<int, int>> steps;   // (pass, slab index) in execution order
-};
 
-namespace {
+namespace gsapi {
 
 thread_local std::string g_err;
 std::mutex g_live_mu;
@@ -61,19 +42,11 @@ bool is_live(gs_plan p) {
     return p && g_live.count(p);
 }
 
-// Makes the plan's device current for the scope and restores the caller's.
-struct DeviceScope {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit DeviceScope(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) err = hipSetDevice(dev);
-    }
-    ~DeviceScope() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
+}  // namespace gsapi
+
+using namespace gsapi;
+
+namespace {
 
 int visible_devices() {
     int n = 0;
@@ -175,6 +148,59 @@ size_t workspace_cap() {
 }
 
 }  // namespace
+
+namespace gsapi {
+
+gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) {
+    if (!is_live(p)) return fail(GS_ERR_INVALID_ARG, "invalid plan");
+    if (p->host_only) return fail(GS_ERR_INVALID_ARG, "host-only plan cannot evaluate");
+    if (!in || !out) return fail(GS_ERR_INVALID_ARG, "NULL device pointer");
+    a.d = p->d;
+    a.n = p->n;
+    a.rho = in;
+    a.u = out;
+    a.X1 = p->X1;
+    a.X2 = p->X2;
+    a.spec = p->spec;
+    a.tw = p->tw;
+    a.dxi = M_PI / (2.0 * p->L);
+    if (p->kernel == GS_DIPOLAR_3D) {
+        a.dipolar = 1;
+        for (int i = 0; i < 3; ++i) a.cdiag[i] = 3.0 * p->dn[i] * p->dm[i];
+        a.ccross[0] = 3.0 * (p->dn[0] * p->dm[1] + p->dn[1] * p->dm[0]);
+        a.ccross[1] = 3.0 * (p->dn[0] * p->dm[2] + p->dn[2] * p->dm[0]);
+        a.ccross[2] = 3.0 * (p->dn[1] * p->dm[2] + p->dn[2] * p->dm[1]);
+        const double nm = p->dn[0] * p->dm[0] + p->dn[1] * p->dm[1] + p->dn[2] * p->dm[2];
+        a.nm_over_M = nm / std::pow(2.0 * p->n, 3);
+    }
+    return GS_OK;
+}
+
+static hipError_t run_step(gs_plan p, gsk::EvalArgs& a, int step) {
+    const auto [pass, c] = p->steps[step];
+    a.kx0 = c * p->slab;
+    a.kxn = std::min(p->slab, p->n + 1 - a.kx0);
+    return gsk::launch_eval(a, p->stream, pass);
+}
+
+gs_status eval_chain(gs_plan p, const double* in, double* out, int step) {
+    gsk::EvalArgs a;
+    gs_status st = make_args(p, in, out, a);
+    if (st != GS_OK) return st;
+    if (step >= (int)p->steps.size()) return fail(GS_ERR_INVALID_ARG, "step out of range");
+    DeviceScope ds(p->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    hipError_t e = hipSuccess;
+    if (step >= 0) {
+        e = run_step(p, a, step);
+    } else {
+        for (int i = 0; i < (int)p->steps.size() && e == hipSuccess; ++i) e = run_step(p, a, i);
+    }
+    if (e != hipSuccess) return hip_fail(e, "evaluation launch");
+    return GS_OK;
+}
+
+}  // namespace gsapi
 
 extern "C" {
 
@@ -480,55 +506,6 @@ gs_status gs_plan_set_stream(gs_plan p, void* stream) {
     return GS_OK;
 }
 
-static gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) {
-    if (!is_live(p)) return fail(GS_ERR_INVALID_ARG, "invalid plan");
-    if (p->host_only) return fail(GS_ERR_INVALID_ARG, "host-only plan cannot evaluate");
-    if (!in || !out) return fail(GS_ERR_INVALID_ARG, "NULL device pointer");
-    a.d = p->d;
-    a.n = p->n;
-    a.rho = in;
-    a.u = out;
-    a.X1 = p->X1;
-    a.X2 = p->X2;
-    a.spec = p->spec;
-    a.tw = p->tw;
-    a.dxi = M_PI / (2.0 * p->L);
-    if (p->kernel == GS_DIPOLAR_3D) {
-        a.dipolar = 1;
-        for (int i = 0; i < 3; ++i) a.cdiag[i] = 3.0 * p->dn[i] * p->dm[i];
-        a.ccross[0] = 3.0 * (p->dn[0] * p->dm[1] + p->dn[1] * p->dm[0]);
-        a.ccross[1] = 3.0 * (p->dn[0] * p->dm[2] + p->dn[2] * p->dm[0]);
-        a.ccross[2] = 3.0 * (p->dn[1] * p->dm[2] + p->dn[2] * p->dm[1]);
-        const double nm = p->dn[0] * p->dm[0] + p->dn[1] * p->dm[1] + p->dn[2] * p->dm[2];
-        a.nm_over_M = nm / std::pow(2.0 * p->n, 3);
-    }
-    return GS_OK;
-}
-
-static hipError_t run_step(gs_plan p, gsk::EvalArgs& a, int step) {
-    const auto [pass, c] = p->steps[step];
-    a.kx0 = c * p->slab;
-    a.kxn = std::min(p->slab, p->n + 1 - a.kx0);
-    return gsk::launch_eval(a, p->stream, pass);
-}
-
-static gs_status eval_chain(gs_plan p, const double* in, double* out, int step) {
-    gsk::EvalArgs a;
-    gs_status st = make_args(p, in, out, a);
-    if (st != GS_OK) return st;
-    if (step >= (int)p->steps.size()) return fail(GS_ERR_INVALID_ARG, "step out of range");
-    DeviceScope ds(p->device);
-    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
-    hipError_t e = hipSuccess;
-    if (step >= 0) {
-        e = run_step(p, a, step);
-    } else {
-        for (int i = 0; i < (int)p->steps.size() && e == hipSuccess; ++i) e = run_step(p, a, i);
-    }
-    if (e != hipSuccess) return hip_fail(e, "evaluation launch");
-    return GS_OK;
-}
-
 gs_status gs_eval(gs_plan p, const double* rho_dev, double* u_dev) { return eval_chain(p, rho_dev, u_dev, -1); }
 
 gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho_dev) {
@@ -549,26 +526,6 @@ int gs_plan_steps(gs_plan p, int* pass_ids, int capacity) {
     const int c = (int)p->steps.size();
     for (int i = 0; i < c && i < capacity && pass_ids; ++i) pass_ids[i] = p->steps[i].first;
     return c;
-}
-
-gs_status gs_eval_batch(int count, const gs_plan* plans, const double* const* rho_dev, double* const* u_dev) {
-    if (count <= 0 || !plans || !rho_dev || !u_dev) return fail(GS_ERR_INVALID_ARG, "invalid batch arguments");
-    std::unordered_set<gs_plan> seen;
-    for (int i = 0; i < count; ++i) {
-        if (!is_live(plans[i]) || plans[i]->host_only) return fail(GS_ERR_INVALID_ARG, "invalid plan in batch");
-        if (!rho_dev[i] || !u_dev[i]) return fail(GS_ERR_INVALID_ARG, "NULL device pointer in batch");
-        if (!seen.insert(plans[i]).second) return fail(GS_ERR_INVALID_ARG, "a plan appears twice in the batch");
-        if (plans[i]->device != plans[0]->device) return fail(GS_ERR_INVALID_ARG, "batch spans devices");
-    }
-    hipStream_t s0 = plans[0]->stream;
-    for (int i = 0; i < count; ++i) {
-        hipStream_t keep = plans[i]->stream;
-        plans[i]->stream = s0;
-        gs_status st = eval_chain(plans[i], rho_dev[i], u_dev[i], -1);
-        plans[i]->stream = keep;
-        if (st != GS_OK) return st;
-    }
-    return GS_OK;
 }
 
 }  // extern "C"

@@ -60,28 +60,26 @@ template <int N> struct Geo {
 // Hermitian spectra A = (C[m] + conj C[2n-m])/2, B = (C[m] - conj C[2n-m])/(2i).
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
-                                                      const cpx* __restrict__ tw) {
+__device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp<cpx> __restrict__ X1,
+                                           gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
+                                           cpx* lds) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPX, A = Gm::A;
-    __shared__ cpx lds[PP * A];
-    const int tid = threadIdx.x;
     const int tA = tid % G, pA = tid / G;      // load role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive y
-    const int z = blockIdx.y;
-    const int y0 = blockIdx.x * 2 * PP;
-    const bool okA = (y0 + 2 * pA) < N, okB = (y0 + 2 * pB) < N;
+    const int y0 = bx * 2 * PP;
+    const bool okA = active && (y0 + 2 * pA) < N, okB = active && (y0 + 2 * pB) < N;
 
     cpx x[E];
     {
-        const double* ra = rho + ((size_t)z * N + (y0 + 2 * pA)) * N;
+        gp<const double> ra = rho + ((size_t)z * N + (y0 + 2 * pA)) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = tA + G * e;
             x[e] = okA ? cmk(ra[j], ra[N + j]) : cmk(0.0, 0.0);
         }
     }
-    cpx* out = X1 + (size_t)z * (N + 1) * N + y0 + 2 * pB;
+    gp<cpx> out = X1 + (size_t)z * (N + 1) * N + y0 + 2 * pB;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         cpx v[E];
@@ -104,7 +102,7 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c(const double* __restrict__
                 const cpx df = cmk(zk.x - zp.x, zk.y + zp.y);                        //  Z - conj P
                 const cpx sb = cmk(0.5 * df.y, -0.5 * df.x);                         // /(2i)
                 const int m = 2 * k + h;
-                cpx* o = out + (size_t)m * N;
+                gp<cpx> o = out + (size_t)m * N;
                 o[0] = sa;
                 o[1] = sb;
             }
@@ -113,22 +111,28 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c(const double* __restrict__
     }
 }
 
+template <int N>
+__global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
+                                                      const cpx* __restrict__ tw) {
+    __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
+    x_r2c_tile<N>((gp<const double>)rho, (gp<cpx>)X1, (gp<const cpx>)tw, blockIdx.x, blockIdx.y, threadIdx.x, true,
+                  lds);
+}
+
 // ---------------------------------------------------------------------------
 // P5: x-direction complex-to-real with cropping.  Inverse of P1 (unnormalised).
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
-                                                      const cpx* __restrict__ tw) {
+__device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> __restrict__ u,
+                                           gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
+                                           cpx* lds) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPX, A = Gm::A;
-    __shared__ cpx lds[PP * A];
-    const int tid = threadIdx.x;
     const int tA = tid % G, pA = tid / G;      // store role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive y
-    const int z = blockIdx.y;
-    const int y0 = blockIdx.x * 2 * PP;
-    const bool okA = (y0 + 2 * pA) < N, okB = (y0 + 2 * pB) < N;
-    const cpx* in = X1 + (size_t)z * (N + 1) * N + y0 + 2 * pB;
+    const int y0 = bx * 2 * PP;
+    const bool okA = active && (y0 + 2 * pA) < N, okB = active && (y0 + 2 * pB) < N;
+    gp<const cpx> in = X1 + (size_t)z * (N + 1) * N + y0 + 2 * pB;
 
     cpx acc[E];
 #pragma unroll
@@ -143,7 +147,7 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1
             const int mm = direct ? m : 2 * N - m;
             cpx a = cmk(0.0, 0.0), b = cmk(0.0, 0.0);
             if (okB) {
-                const cpx* p = in + (size_t)mm * N;
+                gp<const cpx> p = in + (size_t)mm * N;
                 a = p[0];
                 b = p[1];
             }
@@ -157,7 +161,7 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1
         lds_barrier();
     }
     if (okA) {
-        double* ua = u + ((size_t)z * N + (y0 + 2 * pA)) * N;
+        gp<double> ua = u + ((size_t)z * N + (y0 + 2 * pA)) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = tA + G * e;
@@ -167,29 +171,36 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1
     }
 }
 
+template <int N>
+__global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
+                                                      const cpx* __restrict__ tw) {
+    __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
+    x_c2r_tile<N>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x, blockIdx.y, threadIdx.x, true,
+                  lds);
+}
+
 // ---------------------------------------------------------------------------
 // P2: y-direction forward with zero padding.  Block = one kx, PPY consecutive z.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1, cpx* __restrict__ X2,
-                                                      const cpx* __restrict__ tw, int kx0) {
+__device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx> __restrict__ X2,
+                                           gp<const cpx> __restrict__ tw, int kx0, int bx, int kxl, int tid,
+                                           bool active, cpx* lds) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
-    __shared__ cpx lds[PP * A];
-    const int tid = threadIdx.x;
     const int tA = tid % G, pA = tid / G;      // load role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive z
-    const int kxl = blockIdx.y, kx = kx0 + kxl;       // slab-local and global kx
-    const int z0 = blockIdx.x * PP;
-    const bool okA = (z0 + pA) < N, okB = (z0 + pB) < N;
+    const int kx = kx0 + kxl;                         // slab-local and global kx
+    const int z0 = bx * PP;
+    const bool okA = active && (z0 + pA) < N, okB = active && (z0 + pB) < N;
 
     cpx x[E];
     {
-        const cpx* src = X1 + ((size_t)(z0 + pA) * (N + 1) + kx) * N;
+        gp<const cpx> src = X1 + ((size_t)(z0 + pA) * (N + 1) + kx) * N;
 #pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = okA ? src[tA + G * e] : cmk(0.0, 0.0);
+        for (int e = 0; e < E; ++e) x[e] = okA ? cpx(src[tA + G * e]) : cmk(0.0, 0.0);
     }
-    cpx* dst = X2 + (size_t)kxl * 2 * N * N + z0 + pB;
+    gp<cpx> dst = X2 + (size_t)kxl * 2 * N * N + z0 + pB;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         cpx v[E];
@@ -205,22 +216,29 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1
     }
 }
 
+template <int N>
+__global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1, cpx* __restrict__ X2,
+                                                      const cpx* __restrict__ tw, int kx0) {
+    __shared__ cpx lds[Geo<N>::PPY * Geo<N>::A];
+    y_fwd_tile<N>((gp<const cpx>)X1, (gp<cpx>)X2, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y, threadIdx.x, true,
+                  lds);
+}
+
 // ---------------------------------------------------------------------------
 // P4: y-direction inverse with cropping.  Block = one kx, PPY consecutive z.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2, cpx* __restrict__ X1,
-                                                      const cpx* __restrict__ tw, int kx0) {
+__device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx> __restrict__ X1,
+                                           gp<const cpx> __restrict__ tw, int kx0, int bx, int kxl, int tid,
+                                           bool active, cpx* lds) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
-    __shared__ cpx lds[PP * A];
-    const int tid = threadIdx.x;
     const int tA = tid % G, pA = tid / G;      // store role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive z
-    const int kxl = blockIdx.y, kx = kx0 + kxl;
-    const int z0 = blockIdx.x * PP;
-    const bool okA = (z0 + pA) < N, okB = (z0 + pB) < N;
-    const cpx* src = X2 + (size_t)kxl * 2 * N * N + z0 + pB;
+    const int kx = kx0 + kxl;
+    const int z0 = bx * PP;
+    const bool okA = active && (z0 + pA) < N, okB = active && (z0 + pB) < N;
+    gp<const cpx> src = X2 + (size_t)kxl * 2 * N * N + z0 + pB;
 
     cpx acc[E];
 #pragma unroll
@@ -230,7 +248,7 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2
         cpx v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            v[e] = okB ? src[(size_t)(2 * (tB + G * e) + h) * N] : cmk(0.0, 0.0);
+            v[e] = okB ? cpx(src[(size_t)(2 * (tB + G * e) + h) * N]) : cmk(0.0, 0.0);
         fft<typename Gm::F, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
         if (h) twist_out<typename Gm::F>(v, tA, tw);
 #pragma unroll
@@ -238,10 +256,18 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2
         lds_barrier();
     }
     if (okA) {
-        cpx* dst = X1 + ((size_t)(z0 + pA) * (N + 1) + kx) * N;
+        gp<cpx> dst = X1 + ((size_t)(z0 + pA) * (N + 1) + kx) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) dst[tA + G * e] = acc[e];
     }
+}
+
+template <int N>
+__global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2, cpx* __restrict__ X1,
+                                                      const cpx* __restrict__ tw, int kx0) {
+    __shared__ cpx lds[Geo<N>::PPY * Geo<N>::A];
+    y_inv_tile<N>((gp<const cpx>)X2, (gp<cpx>)X1, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y, threadIdx.x, true,
+                  lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -271,7 +297,7 @@ __device__ __forceinline__ int fused_pencil(int slot) {
 }
 
 template <int N, int DIM>
-__device__ __forceinline__ const double* fused_row(const double* spec, int pencil, int kx0) {
+__device__ __forceinline__ gp<const double> fused_row(gp<const double> spec, int pencil, int kx0) {
     if constexpr (DIM == 3) {
         const int kx = kx0 + pencil / (2 * N), ky = pencil % (2 * N);
         const int aky = ky <= N ? ky : 2 * N - ky;
@@ -282,18 +308,18 @@ __device__ __forceinline__ const double* fused_row(const double* spec, int penci
 }
 
 template <int N, int DIM>
-__device__ __forceinline__ void fused_load(const cpx* X, int pencil, bool ok, int t, cpx (&v)[FftCfgFused<N>::E]) {
+__device__ __forceinline__ void fused_load(gp<const cpx> X, int pencil, bool ok, int t, cpx (&v)[FftCfgFused<N>::E]) {
     constexpr int E = FftCfgFused<N>::E, G = FftCfgFused<N>::G;
-    const cpx* base = X + (size_t)pencil * N;
+    gp<const cpx> base = X + (size_t)pencil * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = ok ? base[t + G * e] : cmk(0.0, 0.0);
+    for (int e = 0; e < E; ++e) v[e] = ok ? cpx(base[t + G * e]) : cmk(0.0, 0.0);
 }
 
 template <int N, int DIM>
-__device__ __forceinline__ void fused_spec(const double* spec, int pencil, int kx0, bool ok, int t, int h,
+__device__ __forceinline__ void fused_spec(gp<const double> spec, int pencil, int kx0, bool ok, int t, int h,
                                            double (&sv)[FftCfgFused<N>::E]) {
     constexpr int E = FftCfgFused<N>::E, G = FftCfgFused<N>::G;
-    const double* srow = fused_row<N, DIM>(spec, ok ? pencil : 0, kx0);
+    gp<const double> srow = fused_row<N, DIM>(spec, ok ? pencil : 0, kx0);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int m = 2 * (t + G * e) + h;          // padded index along the pencil
@@ -301,10 +327,90 @@ __device__ __forceinline__ void fused_spec(const double* spec, int pencil, int k
     }
 }
 
+// Transform, spectrum multiplication, inverse transform and even/odd combination
+// of one pencil held in v (spectrum values in sv); stores the pencil if ok.
 template <int N, int DIM, int MODE>
-__global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ X, const double* __restrict__ spec,
-                                                      const cpx* __restrict__ tw, int npencils, int kx0,
+__device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx> __restrict__ tw, int pencil, int kx0,
+                                           bool ok, const DipoleArgs& dip, int t, int h, int pl,
+                                           cpx (&v)[FftCfgFused<N>::E], const double (&sv)[FftCfgFused<N>::E],
+                                           cpx* lds, cpx* area) {
+    using Gm = Geo<N>;
+    using FZ = typename Gm::FZ;
+    constexpr int E = Gm::EZ, G = Gm::GZ, A = Gm::A;
+    constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
+    if (h) twist_in<FZ>(v, t, tw);
+    fft<FZ, false, FW>(v, t, area, t, area, tw);
+    if constexpr (MODE == SPEC_DIPOLAR) {
+        // (n.xi)(m.xi) with Nyquist taken as 0 in the odd (cross) factors
+        const int kx = (DIM == 3) ? kx0 + pencil / (2 * N) : pencil;
+        const int ky = (DIM == 3) ? pencil % (2 * N) : 0;
+        const double xe = kx * dip.dxi;
+        const int sy = ky < N ? ky : ky - 2 * N;
+        const double ye = sy * dip.dxi;
+        const double xo = (kx == N) ? 0.0 : xe;
+        const double yo = (ky == N) ? 0.0 : ye;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int m = 2 * (t + G * e) + h;
+            const int sz = m < N ? m : m - 2 * N;
+            const double ze = sz * dip.dxi;
+            const double zo = (m == N) ? 0.0 : ze;
+            const double f = dip.cdiag[0] * xe * xe + dip.cdiag[1] * ye * ye + dip.cdiag[2] * ze * ze +
+                             dip.ccross[0] * xo * yo + dip.ccross[1] * xo * zo + dip.ccross[2] * yo * zo;
+            v[e] = cscale(v[e], f * sv[e] - dip.nm_over_M);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sv[e]);
+    }
+    lds_sync<FW>();
+    fft<FZ, true, FW>(v, t, area, t, area, tw);
+    if (h) twist_out<FZ>(v, t, tw);
+    lds_sync<FW>();
+#pragma unroll
+    for (int e = 0; e < E; ++e) area[lds_pad(t + G * e)] = v[e];
+    lds_sync<CW>();
+    if (ok) {
+        gp<cpx> base = X + (size_t)pencil * N;
+        const cpx* a0 = lds + (pl * 2) * A;
+        const cpx* a1 = a0 + A;
+#pragma unroll
+        for (int ee = 0; ee < E / 2; ++ee) {
+            const int j = t + G * (h * (E / 2) + ee);
+            base[j] = cadd(a0[lds_pad(j)], a1[lds_pad(j)]);
+        }
+    }
+    lds_sync<CW>();
+}
+
+// One pencil group of the fused pass without prefetch (the batched launches).
+template <int N, int DIM, int MODE>
+__device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const double> __restrict__ spec,
+                                            gp<const cpx> __restrict__ tw, int npencils, int kx0,
+                                            const DipoleArgs& dip, int g, int tid, bool active, cpx* lds) {
+    using Gm = Geo<N>;
+    using FZ = typename Gm::FZ;
+    constexpr int E = Gm::EZ, G = Gm::GZ, PP = Gm::PPZ, A = Gm::A;
+    constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
+    const int t = tid % G, h = (tid / G) & 1, pl = tid / (2 * G);
+    cpx* area = lds + (pl * 2 + h) * A;
+    const int slot = g * PP + pl;
+    const bool ok = active && slot < npencils;
+    const int pencil = ok ? fused_pencil<N, DIM>(slot) : 0;
+    cpx v[E];
+    double sv[E];
+    fused_load<N, DIM>(X, pencil, ok, t, v);
+    fused_spec<N, DIM>(spec, pencil, kx0, ok, t, h, sv);
+    fused_body<N, DIM, MODE>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area);
+}
+
+template <int N, int DIM, int MODE>
+__global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ Xg, const double* __restrict__ specg,
+                                                      const cpx* __restrict__ twg, int npencils, int kx0,
                                                       DipoleArgs dip) {
+    const gp<cpx> X = (gp<cpx>)Xg;
+    const gp<const double> spec = (gp<const double>)specg;
+    const gp<const cpx> tw = (gp<const cpx>)twg;
     using Gm = Geo<N>;
     using FZ = typename Gm::FZ;
     constexpr int E = Gm::EZ, G = Gm::GZ, PP = Gm::PPZ, A = Gm::A;
@@ -346,49 +452,7 @@ __global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ X, const
             fused_load<N, DIM>(X, pn, okn, t, nv);
             fused_spec<N, DIM>(spec, pn, kx0, okn, t, h, ns);
         }
-        if (h) twist_in<FZ>(v, t, tw);
-        fft<FZ, false, FW>(v, t, area, t, area, tw);
-        if constexpr (MODE == SPEC_DIPOLAR) {
-            // (n.xi)(m.xi) with Nyquist taken as 0 in the odd (cross) factors
-            const int kx = (DIM == 3) ? kx0 + pencil / (2 * N) : pencil;
-            const int ky = (DIM == 3) ? pencil % (2 * N) : 0;
-            const double xe = kx * dip.dxi;
-            const int sy = ky < N ? ky : ky - 2 * N;
-            const double ye = sy * dip.dxi;
-            const double xo = (kx == N) ? 0.0 : xe;
-            const double yo = (ky == N) ? 0.0 : ye;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int m = 2 * (t + G * e) + h;
-                const int sz = m < N ? m : m - 2 * N;
-                const double ze = sz * dip.dxi;
-                const double zo = (m == N) ? 0.0 : ze;
-                const double f = dip.cdiag[0] * xe * xe + dip.cdiag[1] * ye * ye + dip.cdiag[2] * ze * ze +
-                                 dip.ccross[0] * xo * yo + dip.ccross[1] * xo * zo + dip.ccross[2] * yo * zo;
-                v[e] = cscale(v[e], f * sv[e] - dip.nm_over_M);
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sv[e]);
-        }
-        lds_sync<FW>();
-        fft<FZ, true, FW>(v, t, area, t, area, tw);
-        if (h) twist_out<FZ>(v, t, tw);
-        lds_sync<FW>();
-#pragma unroll
-        for (int e = 0; e < E; ++e) area[lds_pad(t + G * e)] = v[e];
-        lds_sync<CW>();
-        if (ok) {
-            cpx* base = X + (size_t)pencil * N;
-            const cpx* a0 = lds + (pl * 2) * A;
-            const cpx* a1 = a0 + A;
-#pragma unroll
-            for (int ee = 0; ee < E / 2; ++ee) {
-                const int j = t + G * (h * (E / 2) + ee);
-                base[j] = cadd(a0[lds_pad(j)], a1[lds_pad(j)]);
-            }
-        }
-        lds_sync<CW>();
+        fused_body<N, DIM, MODE>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area);
     }
 }
 
