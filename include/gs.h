@@ -190,7 +190,8 @@ typedef struct gs_batch_s* gs_batch;
 
 typedef struct {
     int schedule;        /* gs_schedule                                               */
-    int tiles_per_task;  /* block-fulls of tiles per task (>= 1); 0 = 1, or tuned       */
+    int tiles_per_task;  /* block-fulls of tiles per task (>= 1); 0 = default (queue 16,
+                            phased 4) or tuned                                        */
     int grid;            /* persistent blocks; 0 = as many as can be co-resident        */
     int use_graph;       /* 1: capture the launch sequence in a hipGraph on the first
                             evaluation and replay it afterwards                         */

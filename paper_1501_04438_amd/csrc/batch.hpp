@@ -189,21 +189,24 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_queue(const BatchProble
                                                                unsigned* __restrict__ ctr, int nctr,
                                                                unsigned spin_limit) {
     __shared__ cpx lds[batch_lds_slots()];
-    __shared__ int s_task;
+    __shared__ int s_task, s_next;
     const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64u;
     const unsigned one = (threadIdx.x == 0) ? 1u : 0u;      // the increment of lane 0
+    if (wave0) {
+        const unsigned k0 = __hip_atomic_fetch_add(&ctr[0], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_task = (int)__builtin_amdgcn_readfirstlane(k0);
+    }
+    __syncthreads();
     for (;;) {
-        if (wave0) {
-            const unsigned k = __hip_atomic_fetch_add(&ctr[0], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_task = (int)__builtin_amdgcn_readfirstlane(k);
-        }
-        __syncthreads();
         const int k = __builtin_amdgcn_readfirstlane(s_task);
-        __syncthreads();
         if (k >= ntasks) break;
         const BatchTask t = tasks[k];
-        if (t.dep_count > 0) {
-            if (wave0) {
+        if (wave0) {
+            // claim the next task now: its index arrives while this one waits and runs
+            // (a claimed task depends only on tasks before it, so claiming early
+            // cannot deadlock)
+            const unsigned nx = __hip_atomic_fetch_add(&ctr[0], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t.dep_count > 0) {
                 unsigned* c = &ctr[batch_counter(t.prob, t.dep_pass)];
                 for (unsigned polls = 0;; ++polls) {
                     const unsigned done =
@@ -217,13 +220,17 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_queue(const BatchProble
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
-            __syncthreads();
+            s_next = (int)__builtin_amdgcn_readfirstlane(nx);
         }
+        __syncthreads();
         batch_task(probs[t.prob], t, lds);
         __syncthreads();                       // every wave's stores are issued and complete
-        if (wave0)
+        if (wave0) {
             __hip_atomic_fetch_add(&ctr[batch_counter(t.prob, t.pass)], one, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
+            s_task = s_next;
+        }
+        __syncthreads();
     }
     // the last block to leave clears the counters (the next launch starts after this one ends)
     if (wave0) {

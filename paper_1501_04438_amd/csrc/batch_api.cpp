@@ -53,6 +53,8 @@ namespace {
 // Polls of a dependency wait before it gives up (about 2 us each: seconds in all,
 // orders of magnitude beyond the longest task).
 constexpr unsigned kSpinLimit = 1u << 22;
+// Default block-fulls of tiles per task of the queue schedule.
+constexpr int kQueueTilesPerTask = 16;
 
 std::mutex g_batch_mu;
 std::unordered_set<gs_batch_s*> g_batches;
@@ -212,9 +214,8 @@ gs_status autotune(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const 
     }
     std::vector<TuneEntry> cand;
     if (b->kernels_ok) {
-        for (int mult : {1, 2, 4}) cand.push_back({GS_SCHED_QUEUE, mult, 1, 0, 0.0});
-        cand.push_back({GS_SCHED_QUEUE, 1, 0, 0, 0.0});
-        for (int mult : {1, 4}) cand.push_back({GS_SCHED_PHASED, mult, 1, 0, 0.0});
+        for (int mult : {4, 16, 64}) cand.push_back({GS_SCHED_QUEUE, mult, 1, 0, 0.0});
+        for (int mult : {1, 4, 16}) cand.push_back({GS_SCHED_PHASED, mult, 1, 0, 0.0});
     }
     cand.push_back({GS_SCHED_SEQUENTIAL, 1, 1, 0, 0.0});
     best.ms = 1e300;
@@ -316,7 +317,10 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
     }
     if (st == GS_OK) b->resident = gsk::batch_resident_blocks();
     if (st == GS_OK && opt.schedule != GS_SCHED_AUTO) {
-        b->cfg = {opt.schedule, std::max(1, opt.tiles_per_task), 1, opt.grid, 0.0};
+        // default task sizes: the queue schedule pays an agent-scope release and
+        // acquire per task, so its tasks are larger
+        const int def = opt.schedule == GS_SCHED_QUEUE ? kQueueTilesPerTask : 4;
+        b->cfg = {opt.schedule, opt.tiles_per_task > 0 ? opt.tiles_per_task : def, 1, opt.grid, 0.0};
         if (opt.schedule != GS_SCHED_SEQUENTIAL) st = upload_tasks(b, m, b->cfg.tiles_per_task, 1);
         b->resolved = true;
     }
