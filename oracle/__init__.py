@@ -23,13 +23,13 @@ from .gs_table import coulomb_table, poisson_table, physical_table, GSTable
 from .factors import factor_1d
 from .taylor import taylor_constants
 from .evaluate import (OraclePlan, make_plan, evaluate, adjoint, energy,
-                       energy_gradient_rho, full_spectrum, padded_frequencies,
-                       laplacian_symbol, dipolar_symbol)
+                       energy_gradient_rho, energy_gradient_params, mixture_grid,
+                       full_spectrum, padded_frequencies, laplacian_symbol, dipolar_symbol)
 from . import closed_forms, dft
 
 __all__ = [
     "coulomb_table", "poisson_table", "physical_table", "GSTable", "factor_1d",
     "taylor_constants", "OraclePlan", "make_plan", "evaluate", "adjoint", "energy",
-    "energy_gradient_rho", "full_spectrum", "padded_frequencies",
+    "energy_gradient_rho", "energy_gradient_params", "mixture_grid", "full_spectrum", "padded_frequencies",
     "laplacian_symbol", "dipolar_symbol", "closed_forms", "dft",
 ]

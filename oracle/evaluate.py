@@ -23,6 +23,8 @@ no value there that keeps the result real); squares keep (pi/h)^2.
 The operator is real, linear and, the kernel being even, symmetric.  `adjoint`
 applies the transposed steps literally (pad and crop exchanged, DFT signs
 flipped), `energy` is 1/2 h^d sum rho u, and its rho-gradient is h^d u.
+`energy_gradient_params` carries that gradient to the parameters of a Gaussian
+mixture density by the chain rule.
 """
 
 from __future__ import annotations
@@ -203,3 +205,51 @@ def energy(plan: OraclePlan, rho: np.ndarray, u: np.ndarray | None = None) -> fl
 def energy_gradient_rho(plan: OraclePlan, rho: np.ndarray) -> np.ndarray:
     """dE/drho = 1/2 h^d (A + A^T) rho."""
     return 0.5 * plan.h ** plan.d * (evaluate(plan, rho) + adjoint(plan, rho))
+
+
+def mixture_grid(n: int, L: float, a, mu, sigma):
+    """rho = sum_c a_c exp(-|x - mu_c|^2 / sigma_c^2) on the grid x_j = -L + j h
+    ([z][y][x] / [y][x] order, mu columns (x, y[, z])), with the per-component
+    Gaussians g_c and squared distances r2_c and offsets x_i - mu_ci it is made of."""
+    a = np.asarray(a, float)
+    mu = np.asarray(mu, float)
+    sigma = np.asarray(sigma, float)
+    d = mu.shape[1]
+    h = 2.0 * L / n
+    ax = -L + h * np.arange(n)
+    if d == 3:
+        X = (ax[None, None, :], ax[:, None][None], ax[:, None, None])     # x, y, z
+    else:
+        X = (ax[None, :], ax[:, None])
+    shape = (n,) * d
+    rho = np.zeros(shape)
+    comps = []
+    for c in range(len(a)):
+        off = [np.broadcast_to(X[i] - mu[c, i], shape) for i in range(d)]
+        r2 = sum(o * o for o in off)
+        g = np.exp(-r2 / sigma[c] ** 2)
+        rho += a[c] * g
+        comps.append((g, r2, off))
+    return rho, comps
+
+
+def energy_gradient_params(plan: OraclePlan, a, mu, sigma):
+    """E = 1/2 h^d sum rho u for the mixture density and its gradient with respect
+    to (a, mu, sigma): dE/dtheta = sum_i (dE/drho_i) (drho_i/dtheta) with
+      drho/da_c      = g_c
+      drho/dmu_ci    = a_c g_c 2 (x_i - mu_ci) / sigma_c^2
+      drho/dsigma_c  = a_c g_c 2 |x - mu_c|^2 / sigma_c^3.
+    Returns (E, dE/da (K,), dE/dmu (K, d), dE/dsigma (K,))."""
+    a = np.asarray(a, float)
+    sigma = np.asarray(sigma, float)
+    rho, comps = mixture_grid(plan.n, plan.L, a, mu, sigma)
+    gr = energy_gradient_rho(plan, rho)
+    E = energy(plan, rho)
+    K, d = len(a), plan.d
+    ga, gmu, gs = np.zeros(K), np.zeros((K, d)), np.zeros(K)
+    for c, (g, r2, off) in enumerate(comps):
+        ga[c] = np.sum(gr * g)
+        for i in range(d):
+            gmu[c, i] = np.sum(gr * a[c] * g * 2.0 * off[i] / sigma[c] ** 2)
+        gs[c] = np.sum(gr * a[c] * g * 2.0 * r2 / sigma[c] ** 3)
+    return E, ga, gmu, gs

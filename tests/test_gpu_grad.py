@@ -1,0 +1,89 @@
+"""Differentiation on the GPU: the energy E = 1/2 h^d sum rho u of a Gaussian
+mixture and its gradient with respect to the mixture's amplitudes, centres and
+widths, through torch autograd over the adjoint chain (gs.potential).  Checked
+against the oracle's chain-rule gradient and against central differences."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import paper_1501_04438_amd as gs
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def params(m):
+    t = lambda x: torch.tensor(x, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    return t(m.a), t(m.mu), t(m.sigma)
+
+
+def energy_and_grad(plan, a, mu, s):
+    rho = gs.mixture_density(a, mu, s, plan.n, plan.L)
+    E = gs.energy(rho, plan)
+    ga, gmu, gsig = torch.autograd.grad(E, (a, mu, s))
+    return float(E), np.concatenate([ga.cpu().numpy(), gmu.cpu().numpy().ravel(), gsig.cpu().numpy()])
+
+
+@pytest.mark.parametrize("n", [32, 48])
+def test_parameter_gradients_match_oracle(n):
+    m = workloads.config5_mixture()
+    plan = gs.Plan("coulomb3d", n=n, L=10.0)
+    E, g = energy_and_grad(plan, *params(m))
+    Eo, ga, gmu, gsig = oracle.energy_gradient_params(oracle.make_plan("coulomb3d", 3, n, 10.0), m.a, m.mu, m.sigma)
+    go = np.concatenate([ga, gmu.ravel(), gsig])
+    assert abs(E - Eo) <= 1e-12 * abs(Eo)
+    assert np.max(np.abs(g - go)) <= 1e-12 * np.max(np.abs(go))
+
+
+def test_parameter_gradients_central_differences_256():
+    """All 40 parameters of the 8-component mixture on 256^3, h = 1e-6: 80 more
+    energy evaluations.  E is smooth in the parameters; the agreement is limited by
+    rounding (about 1e-16 |E| / h)."""
+    m = workloads.config5_mixture()
+    plan = gs.Plan("coulomb3d", n=256, L=10.0)
+    a, mu, s = params(m)
+    _, g = energy_and_grad(plan, a, mu, s)
+    hh = 1e-6
+
+    def E_of(av, muv, sv):
+        with torch.no_grad():
+            rho = gs.mixture_density(av, muv, sv, 256, 10.0)
+            return float(gs.energy(rho, plan))
+
+    base = [a.detach().clone(), mu.detach().clone(), s.detach().clone()]
+    fd = []
+    for which in range(3):
+        for idx in np.ndindex(tuple(base[which].shape)):
+            vals = [b.clone() for b in base]
+            vals[which][idx] += hh
+            ep = E_of(*vals)
+            vals[which][idx] -= 2 * hh
+            em = E_of(*vals)
+            fd.append((ep - em) / (2 * hh))
+    fd = np.array(fd)
+    assert len(fd) == 40
+    assert np.max(np.abs(g - fd)) <= 1e-7 * np.max(np.abs(fd))
+
+
+def test_rho_gradient_is_h3_u_and_dot_test_256():
+    p = workloads.config5(256)
+    plan = gs.Plan("coulomb3d", n=256, L=p.L)
+    rho = torch.from_numpy(p.rho).to("cuda:0").requires_grad_(True)
+    E = gs.energy(rho, plan)
+    E.backward()
+    u = plan.eval(rho.detach())
+    assert torch.allclose(rho.grad, plan.h ** 3 * u, rtol=1e-13, atol=0)
+    rng = np.random.default_rng(8)
+    v = torch.from_numpy(rng.standard_normal(rho.shape)).to("cuda:0")
+    lhs = float((u * v).sum())
+    rhs = float((rho.detach() * plan.eval_backward(v)).sum())
+    assert abs(lhs - rhs) <= 1e-14 * float(u.norm() * v.norm())

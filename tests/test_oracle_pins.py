@@ -416,3 +416,63 @@ def test_dipolar_closed_form_against_mpmath_hessian():
     # u(0) = 0: D(0) = -I/3
     z = cf.dipolar3d_gaussian(np.zeros(1), np.zeros(1), np.zeros(1), nv, mv, 1.2)
     assert abs(z[0]) < 1e-15
+
+
+# ------------------------------------------------------------ parameter gradients
+
+def _concat_grad(ga, gmu, gs):
+    return np.concatenate([np.ravel(ga), np.ravel(gmu), np.ravel(gs)])
+
+
+def test_mixture_parameter_gradient_matches_closed_form_energy():
+    """On a resolving grid the discrete energy is the continuum mixture energy (closed
+    form: pairwise erf interactions), so the chain-rule gradient must match a central
+    difference of the closed form in every amplitude, centre and width."""
+    m = workloads.config5_mixture()
+    pl = oracle.make_plan("coulomb3d", 3, 64, 10.0)
+    E, ga, gmu, gs = oracle.energy_gradient_params(pl, m.a, m.mu, m.sigma)
+    Ec = oracle.closed_forms.mixture_energy_coulomb3d(m.a, m.mu, m.sigma)
+    assert abs(E - Ec) <= 1e-10 * abs(Ec)
+    hh = 1e-6
+
+    def fd(f, x):
+        out = np.zeros_like(x)
+        for idx in np.ndindex(x.shape):
+            xp, xm = x.copy(), x.copy()
+            xp[idx] += hh
+            xm[idx] -= hh
+            out[idx] = (f(xp) - f(xm)) / (2 * hh)
+        return out
+
+    cf = oracle.closed_forms.mixture_energy_coulomb3d
+    ref = _concat_grad(fd(lambda v: cf(v, m.mu, m.sigma), m.a), fd(lambda v: cf(m.a, v, m.sigma), m.mu),
+                       fd(lambda v: cf(m.a, m.mu, v), m.sigma))
+    got = _concat_grad(ga, gmu, gs)
+    assert np.max(np.abs(got - ref)) <= 1e-8 * np.max(np.abs(ref))
+
+
+def test_mixture_parameter_gradient_matches_discrete_difference():
+    """On an under-resolved grid (no closed form) the chain rule must still be the
+    derivative of the discrete energy: central differences of oracle energies."""
+    rng = np.random.default_rng(3)
+    mix = workloads.draw_mixture(rng, 3, 3)
+    pl = oracle.make_plan("coulomb3d", 3, 12, 4.0)
+    _, ga, gmu, gs = oracle.energy_gradient_params(pl, mix.a, mix.mu, mix.sigma)
+
+    def E(a, mu, s):
+        rho, _ = oracle.mixture_grid(12, 4.0, a, mu, s)
+        return oracle.energy(pl, rho)
+
+    hh = 1e-5
+    got = _concat_grad(ga, gmu, gs)
+    ref = []
+    for which, x in (("a", mix.a), ("mu", mix.mu), ("s", mix.sigma)):
+        for idx in np.ndindex(x.shape):
+            args = {"a": mix.a.copy(), "mu": mix.mu.copy(), "s": mix.sigma.copy()}
+            args[which][idx] += hh
+            ep = E(args["a"], args["mu"], args["s"])
+            args[which][idx] -= 2 * hh
+            em = E(args["a"], args["mu"], args["s"])
+            ref.append((ep - em) / (2 * hh))
+    ref = np.array(ref)
+    assert np.max(np.abs(got - ref)) <= 1e-7 * np.max(np.abs(ref))
