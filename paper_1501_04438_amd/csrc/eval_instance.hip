@@ -14,8 +14,11 @@
 namespace gsk {
 
 // persistent grid of the fused pass: at most `cap` blocks (0 = one per group)
+// Persistent grid of the fused pass: two rounds of co-resident blocks (measured at
+// n = 256 marginally ahead of one round and of one block per pencil group).
 static inline unsigned fused_grid(int groups, int cap) {
-    return (unsigned)((cap > 0 && groups > cap) ? cap : groups);
+    const long long c = 2LL * cap;
+    return (unsigned)((cap > 0 && groups > c) ? c : groups);
 }
 
 // Co-resident blocks of a kernel on the whole device (CUs x blocks per CU), computed once.

@@ -277,13 +277,46 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2
 // (h = 1) half of the padded spectrum.  DIM = 3: pencils X2[kx][ky][:],
 // spectrum row S[kx][|ky|][:]; DIM = 2: pencils X1[kx][:], row S[kx][:].
 //
-// Persistent: a block walks pencil groups g = blockIdx.x, + gridDim.x, ...
-// and issues the global loads of the next group (pencil data and spectrum
-// values) before transforming the current one, so that every wave keeps memory
-// requests in flight through its FFT arithmetic.  In 3D the pencils of a kx
-// plane are visited in the order ky = 0, n, 1, 2n-1, 2, 2n-2, ...: the two
-// pencils +ky and -ky that share a spectrum row sit in the same block.
+// Lane roles: a pencil's G-thread halves sit in one wave at lanes l and l + 32
+// (G <= 32), so the even/odd combination after the inverse is a cross-half lane
+// swap (v_permlane32_swap) and an add, with no LDS round trip; for G > 32 the
+// halves are combined through LDS.  Persistent: a block walks pencil groups
+// g = blockIdx.x, + gridDim.x, ...  (No register prefetch: the registers it needs
+// cost a wave per SIMD, which hides more latency than the prefetch did.)  In 3D
+// the pencils of a kx plane are visited in the order ky = 0, n, 1, 2n-1, 2,
+// 2n-2, ...: the two pencils +ky and -ky that share a spectrum row sit in the
+// same block.
 // ---------------------------------------------------------------------------
+template <int N> struct FusedRoles {
+    static constexpr int G = Geo<N>::GZ;
+    static constexpr bool SWAP = (G <= 32);
+    // t: thread within its half-transform, h: half (0 even, 1 odd), pl: pencil in the block
+    __device__ __forceinline__ static void get(int tid, int& t, int& h, int& pl) {
+        if constexpr (SWAP) {
+            const int w = tid >> 6, l = tid & 63;
+            h = l >> 5;
+            t = l % G;
+            pl = w * (32 / G) + (l & 31) / G;
+        } else {
+            t = tid % G;
+            h = (tid / G) & 1;
+            pl = tid / (2 * G);
+        }
+    }
+};
+
+// Exchanges the upper 32 lanes of a with the lower 32 lanes of b (all four words).
+__device__ __forceinline__ void swap_halves(cpx& a, cpx& b) {
+    unsigned* pa = reinterpret_cast<unsigned*>(&a);
+    unsigned* pb = reinterpret_cast<unsigned*>(&b);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(pa[i], pb[i], false, false);
+        pa[i] = r[0];
+        pb[i] = r[1];
+    }
+}
+
 template <int N, int DIM>
 __device__ __forceinline__ int fused_pencil(int slot) {
     if constexpr (DIM == 2) {
@@ -366,21 +399,34 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
     lds_sync<FW>();
     fft<FZ, true, FW>(v, t, area, t, area, tw);
     if (h) twist_out<FZ>(v, t, tw);
-    lds_sync<FW>();
+    gp<cpx> base = X + (size_t)pencil * N;
+    if constexpr (FusedRoles<N>::SWAP) {
+        // lanes l < 32 (even half) take the odd half's values e < E/2 from lane l + 32,
+        // which takes the even half's values e >= E/2: each lane then holds the sums
+        // for its own store slots
 #pragma unroll
-    for (int e = 0; e < E; ++e) area[lds_pad(t + G * e)] = v[e];
-    lds_sync<CW>();
-    if (ok) {
-        gp<cpx> base = X + (size_t)pencil * N;
-        const cpx* a0 = lds + (pl * 2) * A;
-        const cpx* a1 = a0 + A;
-#pragma unroll
-        for (int ee = 0; ee < E / 2; ++ee) {
-            const int j = t + G * (h * (E / 2) + ee);
-            base[j] = cadd(a0[lds_pad(j)], a1[lds_pad(j)]);
+        for (int e = 0; e < E / 2; ++e) {
+            cpx a = v[e], b = v[e + E / 2];
+            swap_halves(a, b);
+            if (ok) base[t + G * (h * (E / 2) + e)] = cadd(a, b);
         }
+        lds_sync<FW>();
+    } else {
+        lds_sync<FW>();
+#pragma unroll
+        for (int e = 0; e < E; ++e) area[lds_pad(t + G * e)] = v[e];
+        lds_sync<CW>();
+        if (ok) {
+            const cpx* a0 = lds + (pl * 2) * A;
+            const cpx* a1 = a0 + A;
+#pragma unroll
+            for (int ee = 0; ee < E / 2; ++ee) {
+                const int j = t + G * (h * (E / 2) + ee);
+                base[j] = cadd(a0[lds_pad(j)], a1[lds_pad(j)]);
+            }
+        }
+        lds_sync<CW>();
     }
-    lds_sync<CW>();
 }
 
 // One pencil group of the fused pass without prefetch (the batched launches).
@@ -392,7 +438,8 @@ __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const dou
     using FZ = typename Gm::FZ;
     constexpr int E = Gm::EZ, G = Gm::GZ, PP = Gm::PPZ, A = Gm::A;
     constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
-    const int t = tid % G, h = (tid / G) & 1, pl = tid / (2 * G);
+    int t, h, pl;
+    FusedRoles<N>::get(tid, t, h, pl);
     cpx* area = lds + (pl * 2 + h) * A;
     const int slot = g * PP + pl;
     const bool ok = active && slot < npencils;
@@ -408,52 +455,11 @@ template <int N, int DIM, int MODE>
 __global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ Xg, const double* __restrict__ specg,
                                                       const cpx* __restrict__ twg, int npencils, int kx0,
                                                       DipoleArgs dip) {
-    const gp<cpx> X = (gp<cpx>)Xg;
-    const gp<const double> spec = (gp<const double>)specg;
-    const gp<const cpx> tw = (gp<const cpx>)twg;
-    using Gm = Geo<N>;
-    using FZ = typename Gm::FZ;
-    constexpr int E = Gm::EZ, G = Gm::GZ, PP = Gm::PPZ, A = Gm::A;
-    // a transform's G threads within one wave: wave-level LDS ordering suffices;
-    // the even/odd combine needs both halves (2G threads) within one wave
-    constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
-    __shared__ cpx lds[PP * 2 * A];
-    const int tid = threadIdx.x;
-    const int t = tid % G, h = (tid / G) & 1, pl = tid / (2 * G);
-    cpx* area = lds + (pl * 2 + h) * A;
-    const int ngroups = (npencils + PP - 1) / PP;
-
-    int g = blockIdx.x;
-    cpx nv[E];
-    double ns[E];
-    {
-        const int slot = g * PP + pl;
-        const bool ok0 = slot < npencils;
-        const int p0 = ok0 ? fused_pencil<N, DIM>(slot) : 0;
-        fused_load<N, DIM>(X, p0, ok0, t, nv);
-        fused_spec<N, DIM>(spec, p0, kx0, ok0, t, h, ns);
-    }
-    for (; g < ngroups; g += gridDim.x) {
-        const int slot = g * PP + pl;
-        const bool ok = slot < npencils;
-        const int pencil = ok ? fused_pencil<N, DIM>(slot) : 0;
-        cpx v[E];
-        double sv[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            v[e] = nv[e];
-            sv[e] = ns[e];
-        }
-        {   // prefetch the next group's pencils and spectrum values while this one is transformed
-            const int gn = g + gridDim.x;
-            const int sn = gn * PP + pl;
-            const bool okn = gn < ngroups && sn < npencils;
-            const int pn = okn ? fused_pencil<N, DIM>(sn) : 0;
-            fused_load<N, DIM>(X, pn, okn, t, nv);
-            fused_spec<N, DIM>(spec, pn, kx0, okn, t, h, ns);
-        }
-        fused_body<N, DIM, MODE>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area);
-    }
+    __shared__ cpx lds[Geo<N>::PPZ * 2 * Geo<N>::A];
+    const int ngroups = (npencils + Geo<N>::PPZ - 1) / Geo<N>::PPZ;
+    for (int g = blockIdx.x; g < ngroups; g += gridDim.x)
+        fused_group<N, DIM, MODE>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg, npencils, kx0, dip, g,
+                                  threadIdx.x, true, lds);
 }
 
 }  // namespace gsk
