@@ -67,6 +67,94 @@ def measured_traffic(kernel: str):
     return t.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
 
 
+PROFILE_CMD = ("cd /tmp && export TMPDIR=/tmp && cd $GRAFT_REPO_ROOT && "
+               "timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o run --output-format csv "
+               "-- python3 bench.py --steps 5 --warmup 1 --no-extras --no-cpu-baseline && "
+               "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o run --output-format csv "
+               "-- python3 bench.py --steps 5 --warmup 1 --no-extras --no-cpu-baseline && "
+               "timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d gpurun_out/ktrace -o run --output-format csv "
+               "-- python3 bench.py --steps 20 --warmup 3 --no-extras --no-cpu-baseline")
+
+
+def _csv_rows(directory: str, suffix: str):
+    import csv
+    import glob
+    paths = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    if not paths:
+        raise FileNotFoundError(f"no *{suffix} under {directory}")
+    with open(paths[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_profiles(fetch_dir: str, write_dir: str, trace_dir: str, n: int = 256) -> int:
+    """HBM traffic per launch of each pass from two rocprofv3 counter runs (FETCH_SIZE,
+    WRITE_SIZE in KiB per dispatch) and the kernel-duration table from a kernel-trace
+    run, all of `python3 bench.py --no-extras --no-cpu-baseline` (PROFILE_CMD).  Each
+    counter is scaled by what it reads for the bench's 2 GiB device-to-device copies
+    (2 GiB read and 2 GiB written by definition)."""
+    import statistics
+    copy_bytes = 2048 * 2 ** 20
+    names = list(PASS_NAMES.values())
+
+    def per_kernel(rows, counter):
+        out = {k: [] for k in names}
+        copies = []
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0          # KiB -> bytes
+            kn = r["Kernel_Name"]
+            for k in names:
+                if k in kn:
+                    out[k].append(v)
+            if "copyBuffer" in kn and v > 0.25 * 2 ** 30:
+                copies.append(v)
+        return out, copies
+
+    fetch, fcopies = per_kernel(_csv_rows(fetch_dir, "counter_collection.csv"), "FETCH_SIZE")
+    write, wcopies = per_kernel(_csv_rows(write_dir, "counter_collection.csv"), "WRITE_SIZE")
+    fscale = copy_bytes / statistics.median(fcopies)
+    wscale = copy_bytes / statistics.median(wcopies)
+    nb = pass_bytes(n)
+    kern = {}
+    for p, k in PASS_NAMES.items():
+        if not fetch[k] or not write[k]:
+            continue
+        fb = statistics.mean(fetch[k]) * fscale
+        wb = statistics.mean(write[k]) * wscale
+        kern[k] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "bytes_per_launch": round(fb + wb),
+                   "alg_bytes": nb[p], "ratio_to_alg": round((fb + wb) / nb[p], 3)}
+    traffic = {"source_hash": source_hash(), "n": n, "command": PROFILE_CMD,
+               "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+               "calibration": "median FETCH_SIZE / WRITE_SIZE of the bench's 2 GiB device-to-device copies",
+               "kernels": kern}
+    with open(os.path.join(ROOT, "profiles", f"traffic_coulomb3d_{n}.json"), "w") as f:
+        json.dump(traffic, f, indent=1)
+
+    rows = _csv_rows(trace_dir, "kernel_stats.csv")
+    lines = [f"# Kernel durations: 3D Coulomb {n}^3 evaluation", "",
+             "Command (repo root on the GPU box):", "", "    " + PROFILE_CMD.split(" && ")[-1], "",
+             f"Source: {trace_dir}/.../run_kernel_stats.csv.  k_assemble is the plan-time spectrum assembly;",
+             "__amd_rocclr_copyBuffer are the density upload and the bench's copy-bandwidth probe.", "",
+             "| kernel | calls | average ns | min ns | max ns | share % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r.get("Name", r.get("Kernel_Name", "?"))
+        short = name.split("(")[0].replace("void ", "").replace("gsk::", "")
+        lines.append(f"| {short[:60]} | {r.get('Calls')} | {float(r.get('AverageNs', 0)):.0f} | "
+                     f"{float(r.get('MinNs', 0)):.0f} | {float(r.get('MaxNs', 0)):.0f} | "
+                     f"{float(r.get('Percentage', 0)):.1f} |")
+    lines += ["", "HBM traffic per launch (FETCH_SIZE x %.3f + WRITE_SIZE x %.3f, bytes):" % (fscale, wscale), "",
+              "| kernel | fetch | write | total | algorithmic | ratio |", "|---|---|---|---|---|---|"]
+    for k, v in kern.items():
+        lines.append(f"| {k} | {v['fetch_bytes']} | {v['write_bytes']} | {v['bytes_per_launch']} | "
+                     f"{v['alg_bytes']} | {v['ratio_to_alg']} |")
+    lines += ["", "Counter commands:", ""] + ["    " + c for c in PROFILE_CMD.split(" && ")[3:5]]
+    with open(os.path.join(ROOT, "profiles", f"eval_coulomb3d_{n}_kernel_stats.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps(traffic, indent=1))
+    return 0
+
+
 def cpu_baseline(n_sample: int, min_seconds: float = 10.0) -> dict:
     """The oracle, as it stands, on the same workload: whole evaluations repeated
     until at least min_seconds of host time (plan construction excluded)."""
@@ -116,7 +204,11 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint measurements")
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR"),
+                    help="write profiles/ summaries from rocprofv3 runs of this script (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        return summarize_profiles(*args.summarize_profiles, n=args.n)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE={world}) is not supported: "
