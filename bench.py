@@ -365,6 +365,8 @@ def batched_figures(gs, torch, workloads, reps: int = 10):
     for name, kw in [("sequential", dict(schedule="sequential")),
                      ("sequential_graph", dict(schedule="sequential", graph=True)),
                      ("phased", dict(schedule="phased")),
+                     ("sized", dict(schedule="sized")),
+                     ("sized_graph", dict(schedule="sized", graph=True)),
                      ("queue", dict(schedule="queue")),
                      ("queue_graph", dict(schedule="queue", graph=True)),
                      ("auto_graph", dict(schedule="auto", graph=True))]:

@@ -171,9 +171,11 @@ gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho
  *                       every problem; a task waits for the preceding pass of
  *                       its own problem through per-problem counters.
  *   GS_SCHED_PHASED     one launch per pass type over the tasks of all problems.
+ *   GS_SCHED_SIZED      one launch per pass type and grid size (each launch
+ *                       specialised to its size).
  *   GS_SCHED_SEQUENTIAL each plan's own gs_eval launches, one problem after the
  *                       other (the unbatched baseline).
- *   GS_SCHED_AUTO       the fastest of the above (and of their task sizes) for
+ *   GS_SCHED_AUTO       the fastest of the others (and of their task sizes) for
  *                       this device and multiset of problem shapes, measured on
  *                       the first gs_batch_eval and cached in the process and,
  *                       if the environment variable GS_AUTOTUNE_CACHE names a
@@ -183,7 +185,8 @@ typedef enum {
     GS_SCHED_AUTO = 0,
     GS_SCHED_QUEUE = 1,
     GS_SCHED_PHASED = 2,
-    GS_SCHED_SEQUENTIAL = 3
+    GS_SCHED_SEQUENTIAL = 3,
+    GS_SCHED_SIZED = 4
 } gs_schedule;
 
 typedef struct gs_batch_s* gs_batch;

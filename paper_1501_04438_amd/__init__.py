@@ -219,7 +219,8 @@ class Batch:
 
     schedule: "auto" (measured on the first eval, cached; GS_AUTOTUNE_CACHE names a
     JSON file to keep it across processes), "queue" (one persistent launch),
-    "phased" (one launch per pass type) or "sequential" (each plan's own eval).
+    "phased" (one launch per pass type), "sized" (one launch per pass type and grid
+    size) or "sequential" (each plan's own eval).
     graph=True captures the launch sequence in a hipGraph and replays it.
     Every schedule gives each problem bitwise the result of plan.eval.
     """

@@ -32,7 +32,7 @@ class GSPlanInfo(C.Structure):
                 ("num_steps", C.c_int)]
 
 
-SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3}
+SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3, "sized": 4}
 
 
 class GSBatchOptions(C.Structure):

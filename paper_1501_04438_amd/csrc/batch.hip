@@ -149,4 +149,66 @@ hipError_t launch_batch_phased(const void* probs, const void* tasks, const int p
     return hipSuccess;
 }
 
+template <int N, int PASS> static int size_grid() {
+    static const int g = [] {
+        int dev = 0, cus = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch_size<N, PASS>, BATCH_THREADS, 0);
+        return cus * (per > 0 ? per : 1);
+    }();
+    return g;
+}
+
+template <int PASS>
+static hipError_t launch_size(int n, const BatchProblem* P, const BatchTask* T, int cnt, int mult_grid, hipStream_t s) {
+    switch (n) {
+#define GS_CASE(N)                                                                            \
+    case N: {                                                                                 \
+        const int g = std::min(cnt, std::max(1, size_grid<N, PASS>() * mult_grid));          \
+        k_batch_size<N, PASS><<<g, BATCH_THREADS, 0, s>>>(P, T, cnt);                         \
+        break;                                                                                \
+    }
+        GS_BATCH_SIZES(GS_CASE)
+#undef GS_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sized(const void* probs, const void* tasks, const std::vector<int>& runs, hipStream_t s) {
+    auto P = static_cast<const BatchProblem*>(probs);
+    auto T = static_cast<const BatchTask*>(tasks);
+    for (size_t i = 0; i + 3 < runs.size(); i += 4) {
+        const int pass = runs[i], n = runs[i + 1], off = runs[i + 2], cnt = runs[i + 3];
+        hipError_t e = hipSuccess;
+        switch (pass) {
+            case 1: e = launch_size<1>(n, P, T + off, cnt, 2, s); break;
+            case 2: e = launch_size<2>(n, P, T + off, cnt, 2, s); break;
+            case 3: e = launch_size<3>(n, P, T + off, cnt, 2, s); break;
+            case 4: e = launch_size<4>(n, P, T + off, cnt, 2, s); break;
+            case 5: e = launch_size<5>(n, P, T + off, cnt, 2, s); break;
+            default: e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void batch_size_runs(const std::vector<BatchMember>& m, const std::vector<int>& tasks, std::vector<int>& runs) {
+    runs.clear();
+    const BatchTask* T = reinterpret_cast<const BatchTask*>(tasks.data());
+    const int nt = (int)(tasks.size() / BATCH_TASK_INTS);
+    for (int k = 0; k < nt;) {
+        const int pass = T[k].pass, n = m[T[k].prob].n;
+        int j = k;
+        while (j < nt && T[j].pass == pass && m[T[j].prob].n == n) ++j;
+        runs.push_back(pass);
+        runs.push_back(n);
+        runs.push_back(k);
+        runs.push_back(j - k);
+        k = j;
+    }
+}
+
 }  // namespace gsk

@@ -173,6 +173,18 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_pass(const BatchProblem
     }
 }
 
+// Phased-by-size schedule: one launch per pass and per grid size over that size's
+// tasks (each launch gets the register allocation of its own tile code).
+template <int N, int PASS>
+__global__ void __launch_bounds__(BATCH_THREADS) k_batch_size(const BatchProblem* __restrict__ probs,
+                                                              const BatchTask* __restrict__ tasks, int ntasks) {
+    __shared__ cpx lds[batch_lds_of<N>()];
+    for (int k = blockIdx.x; k < ntasks; k += gridDim.x) {
+        const BatchTask t = tasks[k];
+        batch_run<N, PASS>(probs[t.prob], t.tile0, t.tile1, lds);
+    }
+}
+
 // Queue schedule: one persistent launch over every task of the batch.
 //
 // Every branch of the task loop is wave-uniform (conditions pass through

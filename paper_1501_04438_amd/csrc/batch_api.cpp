@@ -41,6 +41,7 @@ struct gs_batch_s {
     unsigned char* h_stage = nullptr;     // pinned staging of the descriptors
     std::vector<unsigned char> probs_dev; // descriptors now in device memory
     int ntasks = 0, pass_off[6] = {}, pass_cnt[6] = {};
+    std::vector<int> runs;                // (pass, n, first task, count) of the sized schedule
     int tasks_mult = -1, tasks_lf = -1;
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_staged = nullptr;
     bool staged_pending = false;
@@ -110,6 +111,7 @@ gs_status upload_tasks(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, in
     if (b->tasks_mult == mult && b->tasks_lf == lf) return GS_OK;
     std::vector<int> t;
     gsk::batch_tasks(m, mult, lf != 0, t, b->pass_off, b->pass_cnt);
+    gsk::batch_size_runs(m, t, b->runs);
     hipError_t e = hipStreamSynchronize(b->own);
     if (e != hipSuccess) return hip_fail(e, "batch stream");
     if (t.size() > b->tasks_cap) {
@@ -153,6 +155,8 @@ gs_status launch(gs_batch_s* b, const TuneEntry& c, const double* const* rho, do
         e = gsk::launch_batch_queue(b->d_probs, b->d_tasks, b->ntasks, b->d_ctr, b->nctr, grid, kSpinLimit, b->own);
     } else if (c.schedule == GS_SCHED_PHASED) {
         e = gsk::launch_batch_phased(b->d_probs, b->d_tasks, b->pass_off, b->pass_cnt, grid, b->own);
+    } else if (c.schedule == GS_SCHED_SIZED) {
+        e = gsk::launch_batch_sized(b->d_probs, b->d_tasks, b->runs, b->own);
     } else {
         for (size_t i = 0; i < b->plans.size(); ++i) {
             gs_plan p = b->plans[i];
@@ -216,6 +220,7 @@ gs_status autotune(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const 
     if (b->kernels_ok) {
         for (int mult : {4, 16, 64}) cand.push_back({GS_SCHED_QUEUE, mult, 1, 0, 0.0});
         for (int mult : {1, 4, 16}) cand.push_back({GS_SCHED_PHASED, mult, 1, 0, 0.0});
+        for (int mult : {1, 4}) cand.push_back({GS_SCHED_SIZED, mult, 1, 0, 0.0});
     }
     cand.push_back({GS_SCHED_SEQUENTIAL, 1, 1, 0, 0.0});
     best.ms = 1e300;
@@ -251,7 +256,7 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
     gs_batch_options_default(&opt);
     if (opt_in) opt = *opt_in;
     if (count < 1 || !plans) return fail(GS_ERR_INVALID_ARG, "invalid batch arguments");
-    if (opt.schedule < GS_SCHED_AUTO || opt.schedule > GS_SCHED_SEQUENTIAL || opt.tiles_per_task < 0 || opt.grid < 0)
+    if (opt.schedule < GS_SCHED_AUTO || opt.schedule > GS_SCHED_SIZED || opt.tiles_per_task < 0 || opt.grid < 0)
         return fail(GS_ERR_INVALID_ARG, "invalid batch options");
     std::unordered_set<gs_plan> seen;
     bool kernels_ok = true;
@@ -261,12 +266,12 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
         if (!seen.insert(p).second) return fail(GS_ERR_INVALID_ARG, "a plan appears twice in the batch");
         if (p->device != plans[0]->device) return fail(GS_ERR_INVALID_ARG, "batch spans devices");
         if (!gsk::batch_size_supported(p->d, p->n)) {
-            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED)
+            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED)
                 return fail(GS_ERR_UNSUPPORTED_SIZE, "batched kernels cover n <= 128 of the compiled list");
             kernels_ok = false;
         }
         if (p->nslabs != 1) {
-            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED)
+            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED)
                 return fail(GS_ERR_INVALID_ARG, "a batched plan must run its middle passes in one slab");
             kernels_ok = false;
         }

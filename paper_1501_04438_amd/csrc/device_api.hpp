@@ -73,4 +73,9 @@ hipError_t launch_batch_queue(const void* probs, const void* tasks, int ntasks, 
 hipError_t launch_batch_phased(const void* probs, const void* tasks, const int pass_off[6], const int pass_cnt[6],
                                int grid, hipStream_t s);
 
+// Phased-by-size schedule: (pass, n, first task, count) runs of a task list whose
+// tasks of one pass are grouped by size (largest_first), one launch per run.
+void batch_size_runs(const std::vector<BatchMember>& m, const std::vector<int>& tasks, std::vector<int>& runs);
+hipError_t launch_batch_sized(const void* probs, const void* tasks, const std::vector<int>& runs, hipStream_t s);
+
 }  // namespace gsk

@@ -61,8 +61,8 @@ def mixed():
     return plans, rhos, refs
 
 
-@pytest.mark.parametrize("schedule,tpt", [("sequential", 1), ("phased", 1), ("phased", 2), ("queue", 1),
-                                          ("queue", 3)])
+@pytest.mark.parametrize("schedule,tpt", [("sequential", 1), ("phased", 1), ("phased", 2), ("sized", 1),
+                                          ("sized", 3), ("queue", 1), ("queue", 3)])
 @pytest.mark.parametrize("graph", [False, True])
 def test_schedules_bitwise_equal_single(mixed, schedule, tpt, graph):
     plans, rhos, refs = mixed
@@ -85,7 +85,7 @@ def test_schedules_bitwise_equal_single(mixed, schedule, tpt, graph):
 def test_new_pointers_and_alias(mixed):
     """A second call with other tensors (descriptors re-uploaded, graph kept), then u aliasing rho."""
     plans, rhos, refs = mixed
-    for schedule in ("queue", "phased"):
+    for schedule in ("queue", "phased", "sized"):
         b = gs.Batch(plans, schedule=schedule, graph=True)
         b.eval(rhos)
         copies = [r.clone() for r in rhos]
