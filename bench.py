@@ -225,7 +225,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     n = args.n
     prob = workloads.config2(n)
-    plan = gs.Plan("coulomb3d", n=n, L=prob.L, eps=1e-14)
+    plan = gs.Plan("coulomb3d", n=n, L=prob.L, eps=1e-14, autotune=True)
     rho = torch.from_numpy(prob.rho).to(dev)
     u = torch.empty_like(rho)
     print(f"# plan: n={n} Q={plan.info['Q']} spectrum assembly {plan.info['assembly_ms']:.3f} ms "
@@ -280,7 +280,10 @@ def main() -> int:
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"coulomb3d_{n}_triaxial_plus_8_gaussian_mixture_L10", "n": n, "L": prob.L,
                    "kernel": "coulomb3d", "eps": 1e-14, "delta_rel": 1e-4, "Q": plan.info["Q"],
-                   "slab_planes": plan.info["slab_planes"], "launches": S},
+                   "slab_planes": plan.info["slab_planes"], "launches": S,
+                   "launch_variants": {"hint_bits": plan.info["hint_bits"],
+                                       "fused_grid_mult": plan.info["fused_grid_mult"],
+                                       "autotuned": plan.info["tuned"]}},
         "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
@@ -302,10 +305,51 @@ def main() -> int:
     if not args.no_extras:
         out["adjoint"] = adjoint_figures(gs, torch, plan, rho, K)
         out["batched"] = batched_figures(gs, torch, workloads)
+        out["other_workloads"] = other_figures(gs, torch, workloads)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def other_workloads_bytes(d: int, n: int) -> int:
+    """Algorithmic bytes of one evaluation (2D: P1, fused P3 along y, P5)."""
+    if d == 3:
+        return sum(pass_bytes(n).values())
+    return 16 * n * n + 64 * (n + 1) * n + 8 * (n + 1) ** 2
+
+
+def other_figures(gs, torch, workloads, reps: int = 20):
+    """Evaluation throughput of the other workloads: 2D Poisson and Coulomb at 2048^2,
+    3D dipolar at 128^3, 3D Coulomb at 128^3 (working sets partly resident in the
+    Infinity Cache, so their bandwidth fraction can exceed what HBM alone allows)."""
+    res = {}
+    cases = [("poisson2d_2048", workloads.config3_2d("poisson2d", 2048), {"eps": 1e-13}),
+             ("coulomb2d_2048", workloads.config3_2d("coulomb2d", 2048), {}),
+             ("dipolar3d_128", workloads.config3_dipolar(128), None),
+             ("coulomb3d_128", workloads.config2(128), {})]
+    for name, p, kw in cases:
+        if kw is None:
+            kw = {"dipole": (p.extra["n"], p.extra["m"])}
+        plan = gs.Plan(p.kernel, n=p.n, L=p.L, autotune=True, **kw)
+        rho = torch.from_numpy(p.rho).to("cuda:0")
+        u = torch.empty_like(rho)
+        for _ in range(3):
+            plan.eval(rho, out=u)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            plan.eval(rho, out=u)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        pts = p.n ** p.d
+        b = other_workloads_bytes(p.d, p.n)
+        res[name] = {"ms": round(ms, 4), "Mpts_s": round(pts / ms / 1e3, 1), "alg_GB_s": round(b / ms / 1e6, 1),
+                     "hint_bits": plan.info["hint_bits"], "fused_grid_mult": plan.info["fused_grid_mult"]}
+        plan.close()
+    return res
 
 
 def adjoint_figures(gs, torch, plan, rho, K):

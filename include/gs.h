@@ -66,6 +66,12 @@ typedef enum {
                                      calls (gs_eval* return GS_ERR_INVALID_ARG) */
 #define GS_PLAN_HOST_ASSEMBLY  2  /* assemble the spectrum on the host and upload it
                                      instead of the MFMA assembly kernel */
+#define GS_PLAN_AUTOTUNE       4  /* pick the launch variants of the evaluation (cache
+                                     hints per pass, persistent grid of the fused pass)
+                                     by timing whole evaluations at plan creation, or
+                                     take them from the autotune cache (see
+                                     GS_SCHED_AUTO); results are bitwise the same for
+                                     every variant */
 
 typedef struct {
     double delta_rel;        /* near-field radius delta / L; 0 selects 1e-4      */
@@ -96,6 +102,11 @@ typedef struct {
     int host_only;
     int slab_planes;         /* kx planes per slab (3D), n+1 in 2D                */
     int num_steps;           /* kernel launches of one evaluation                 */
+    int tuned;               /* 1 if the launch variants came from the autotuner  */
+    int hint_bits;           /* bit p-1 set: pass p uses its cache-hint variant   */
+    int fused_grid_mult;     /* rounds of co-resident blocks of the fused pass    */
+    int tune_candidates;     /* variants timed when this plan was created         */
+    double tuned_ms;         /* measured evaluation time of the chosen variant    */
 } gs_plan_info;
 
 /* Fill `opt` with the defaults (delta_rel 1e-4, null stream, device -1). */

@@ -19,7 +19,7 @@ import math
 
 import numpy as np
 
-from ._lib import (KERNEL_DIM, KERNELS, PLAN_HOST_ASSEMBLY, PLAN_HOST_ONLY, SCHEDULES, GSBatchInfo,
+from ._lib import (KERNEL_DIM, KERNELS, PLAN_AUTOTUNE, PLAN_HOST_ASSEMBLY, PLAN_HOST_ONLY, SCHEDULES, GSBatchInfo,
                    GSBatchOptions, GSError, GSOptions, GSPlanInfo, check, lib)
 
 __all__ = ["Plan", "Batch", "SCHEDULES", "potential", "energy", "eval_batch", "GSError", "device_count", "supported_sizes",
@@ -48,11 +48,15 @@ class Plan:
     n, L:   points per axis and box half-width (cubic box [-L, L]^d)
     eps:    Gaussian-sum accuracy; delta_rel: near-field radius / L
     dipole: (n_vec, m_vec) for "dipolar3d"; custom: (w, tau) for "gaussian_sum"
+    autotune: time the launch variants (cache hints per pass, fused-pass grid) at plan
+              creation and keep the fastest (cached per device and size; the results
+              are bitwise the same for every variant)
     """
 
     def __init__(self, kernel: str, n: int, L: float, eps: float = 1e-14, d: int | None = None,
                  delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
-                 host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0):
+                 host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0,
+                 autotune: bool = False):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         d = KERNEL_DIM.get(kernel, d)
@@ -63,7 +67,8 @@ class Plan:
         lib().gs_options_default(C.byref(opt))
         opt.delta_rel = float(delta_rel)
         opt.device = int(device)
-        opt.flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_HOST_ASSEMBLY if host_assembly else 0)
+        opt.flags = ((PLAN_HOST_ONLY if host_only else 0) | (PLAN_HOST_ASSEMBLY if host_assembly else 0)
+                     | (PLAN_AUTOTUNE if autotune else 0))
         opt.slab_planes = int(slab_planes)
         if stream is not None:
             opt.stream = C.c_void_p(int(stream))

@@ -16,6 +16,7 @@ STATUS = {0: "GS_OK", 1: "GS_ERR_INVALID_ARG", 2: "GS_ERR_UNSUPPORTED_SIZE", 3: 
           4: "GS_ERR_OUT_OF_MEMORY", 5: "GS_ERR_NO_DEVICE", 6: "GS_ERR_HIP"}
 PLAN_HOST_ONLY = 1
 PLAN_HOST_ASSEMBLY = 2
+PLAN_AUTOTUNE = 4
 
 
 class GSOptions(C.Structure):
@@ -29,7 +30,8 @@ class GSPlanInfo(C.Structure):
                 ("delta", C.c_double), ("S", C.c_int), ("Q", C.c_int), ("A0", C.c_double), ("c2", C.c_double),
                 ("spectrum_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("assembly_ms", C.c_double),
                 ("assembly_gflop", C.c_double), ("host_only", C.c_int), ("slab_planes", C.c_int),
-                ("num_steps", C.c_int)]
+                ("num_steps", C.c_int), ("tuned", C.c_int), ("hint_bits", C.c_int), ("fused_grid_mult", C.c_int),
+                ("tune_candidates", C.c_int), ("tuned_ms", C.c_double)]
 
 
 SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3, "sized": 4}

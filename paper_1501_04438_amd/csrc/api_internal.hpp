@@ -29,6 +29,10 @@ struct gs_plan_s {
     size_t spec_bytes = 0, work_bytes = 0;
     double assembly_ms = 0.0;
     int slab = 0, nslabs = 1;                 // 3D: kx planes per slab of the middle passes
+    int hint_bits = 31, fused_mult = 2;       // launch variants (see gsk::EvalArgs)
+    bool tuned = false;
+    int tune_candidates = 0;
+    double tuned_ms = 0.0;
     std::vector<std::pair<int, int>> steps;   // (pass, slab index) in execution order
 };
 

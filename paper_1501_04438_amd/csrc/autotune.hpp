@@ -10,6 +10,9 @@
 
 namespace gsapi {
 
+// Batch entries: the schedule, task size, task order and grid.  Plan entries reuse
+// the fields: schedule = cache-hint bits of the passes, tiles_per_task = rounds of
+// co-resident blocks of the fused pass.
 struct TuneEntry {
     int schedule = 0, tiles_per_task = 1, largest_first = 1, grid = 0;
     double ms = 0.0;

@@ -26,6 +26,11 @@ struct EvalArgs {
     double nm_over_M = 0.0;
     int max_blocks_fused = 0;         // persistent grid size of the fused pass (0 = device fill)
     int kx0 = 0, kxn = 0;             // 3D passes 2-4: the kx slab [kx0, kx0 + kxn); X2 holds the slab
+    // Launch variants (none changes a single bit of the result): bit p-1 clear selects
+    // plain (cached) memory accesses for pass p instead of its cache-hint default;
+    // fused_grid_mult = rounds of co-resident blocks in the persistent fused pass.
+    int hint_bits = 31;
+    int fused_grid_mult = 2;
 };
 
 // Passes: 1 x_r2c, 2 y_fwd, 3 fused, 4 y_inv, 5 x_c2r.  `which` < 0 runs all five on the

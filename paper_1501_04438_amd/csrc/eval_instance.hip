@@ -13,11 +13,11 @@
 
 namespace gsk {
 
-// persistent grid of the fused pass: at most `cap` blocks (0 = one per group)
-// Persistent grid of the fused pass: two rounds of co-resident blocks (measured at
-// n = 256 marginally ahead of one round and of one block per pencil group).
-static inline unsigned fused_grid(int groups, int cap) {
-    const long long c = 2LL * cap;
+// Persistent grid of the fused pass: `mult` rounds of co-resident blocks, at most one
+// block per pencil group (default two rounds: measured at n = 256 marginally ahead of
+// one round and of one block per group).
+static inline unsigned fused_grid(int groups, int cap, int mult) {
+    const long long c = (long long)(mult > 0 ? mult : 2) * cap;
     return (unsigned)((cap > 0 && groups > c) ? c : groups);
 }
 
@@ -49,30 +49,51 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
     const int capf = a.max_blocks_fused > 0 ? a.max_blocks_fused : (a.d == 3 ? cap3 : cap2);
     const dim3 gx((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX), nz);
     auto run = [&](int p) { return which < 0 || which == p; };
-    if (run(1)) k_x_r2c<N><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw);
+    auto hint = [&](int p) { return (a.hint_bits >> (p - 1)) & 1; };
+    const int fm = a.fused_grid_mult;
+    if (run(1)) {
+        if (hint(1)) k_x_r2c<N, NT_P1><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw);
+        else k_x_r2c<N, 0><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw);
+    }
     if constexpr (N <= GS_MAX_N_3D) {
       if (a.d == 3) {
         const dim3 gy((N + Gm::PPY - 1) / Gm::PPY, a.kxn);
         const int np = a.kxn * 2 * N;
-        if (run(2)) k_y_fwd<N><<<gy, Gm::TY, 0, s>>>(X1, X2, tw, a.kx0);
-        if (run(3)) {
-            const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf);
-            if (a.dipolar)
-                k_fused<N, 3, SPEC_DIPOLAR><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
-            else
-                k_fused<N, 3, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+        if (run(2)) {
+            if (hint(2)) k_y_fwd<N, NT_P2><<<gy, Gm::TY, 0, s>>>(X1, X2, tw, a.kx0);
+            else k_y_fwd<N, 0><<<gy, Gm::TY, 0, s>>>(X1, X2, tw, a.kx0);
         }
-        if (run(4)) k_y_inv<N><<<gy, Gm::TY, 0, s>>>(X2, X1, tw, a.kx0);
-        if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
+        if (run(3)) {
+            const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf, fm);
+            if (a.dipolar) {
+                if (hint(3)) k_fused<N, 3, SPEC_DIPOLAR, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+                else k_fused<N, 3, SPEC_DIPOLAR, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+            } else {
+                if (hint(3)) k_fused<N, 3, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+                else k_fused<N, 3, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+            }
+        }
+        if (run(4)) {
+            if (hint(4)) k_y_inv<N, NT_P4><<<gy, Gm::TY, 0, s>>>(X2, X1, tw, a.kx0);
+            else k_y_inv<N, 0><<<gy, Gm::TY, 0, s>>>(X2, X1, tw, a.kx0);
+        }
+        if (run(5)) {
+            if (hint(5)) k_x_c2r<N, NT_P5><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
+            else k_x_c2r<N, 0><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
+        }
         return hipGetLastError();
       }
     }
-    {
+    if (run(3)) {
         const int np = N + 1;
-        const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf);
-        if (run(3)) k_fused<N, 2, SPEC_PLAIN><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
+        const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf, fm);
+        if (hint(3)) k_fused<N, 2, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
+        else k_fused<N, 2, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
     }
-    if (run(5)) k_x_c2r<N><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
+    if (run(5)) {
+        if (hint(5)) k_x_c2r<N, NT_P5><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
+        else k_x_c2r<N, 0><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
+    }
     return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@
 #include "device_api.hpp"
 #include "host_plan.hpp"
 #include "api_internal.hpp"
+#include "autotune.hpp"
 
 
 namespace gsapi {
@@ -147,6 +148,8 @@ size_t workspace_cap() {
     return (size_t)std::strtoull(s, nullptr, 10);
 }
 
+gs_status plan_autotune(gs_plan_s* p);
+
 }  // namespace
 
 namespace gsapi {
@@ -164,6 +167,8 @@ gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) 
     a.spec = p->spec;
     a.tw = p->tw;
     a.dxi = M_PI / (2.0 * p->L);
+    a.hint_bits = p->hint_bits;
+    a.fused_grid_mult = p->fused_mult;
     if (p->kernel == GS_DIPOLAR_3D) {
         a.dipolar = 1;
         for (int i = 0; i < 3; ++i) a.cdiag[i] = 3.0 * p->dn[i] * p->dm[i];
@@ -400,8 +405,19 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         (void)hipGetLastError();
         return st;
     }
-    std::lock_guard<std::mutex> g(g_live_mu);
-    g_live.insert(p);
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        g_live.insert(p);
+    }
+    if (opt.flags & GS_PLAN_AUTOTUNE) {
+        // the plan is complete: the autotuner times it through the ordinary eval path
+        st = plan_autotune(p);
+        if (st != GS_OK) {
+            (void)gs_plan_destroy(p);
+            (void)hipGetLastError();
+            return st;
+        }
+    }
     *out = p;
     return GS_OK;
 }
@@ -438,6 +454,11 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
     info->host_only = p->host_only ? 1 : 0;
     info->slab_planes = p->slab;
     info->num_steps = (int)p->steps.size();
+    info->tuned = p->tuned ? 1 : 0;
+    info->hint_bits = p->hint_bits;
+    info->fused_grid_mult = p->fused_mult;
+    info->tune_candidates = p->tune_candidates;
+    info->tuned_ms = p->tuned_ms;
     return GS_OK;
 }
 
@@ -529,3 +550,94 @@ int gs_plan_steps(gs_plan p, int* pass_ids, int capacity) {
 }
 
 }  // extern "C"
+
+namespace {
+
+// Times whole evaluations of p (launch variants in p) on scratch buffers: best of 3
+// after one warm-up, in ms.
+gs_status time_plan(gs_plan_s* p, const double* rho, double* u, double& ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    gs_status st = eval_chain(p, rho, u, -1);
+    ms = 1e300;
+    for (int r = 0; r < 3 && st == GS_OK; ++r) {
+        (void)hipEventRecord(e0, p->stream);
+        st = eval_chain(p, rho, u, -1);
+        (void)hipEventRecord(e1, p->stream);
+        const hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+        float f = 0.f;
+        (void)hipEventElapsedTime(&f, e0, e1);
+        ms = std::min(ms, (double)f);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+// Greedy search over the launch variants (none changes the result): starting from
+// the compiled defaults, flip each pass's cache-hint variant in turn and keep what is
+// faster, then try one and four rounds of co-resident blocks in the fused pass.
+gs_status plan_autotune(gs_plan_s* p) {
+    const std::string key = tune_device_key(p->device) + "|plan|d" + std::to_string(p->d) + "|n" +
+                            std::to_string(p->n) + (p->kernel == GS_DIPOLAR_3D ? "|dip" : "") + "|slab" +
+                            std::to_string(p->slab);
+    TuneEntry te;
+    if (tune_lookup(key, te)) {
+        p->hint_bits = te.schedule;
+        p->fused_mult = te.tiles_per_task;
+        p->tuned = true;
+        p->tuned_ms = te.ms;
+        return GS_OK;
+    }
+    const size_t pts = (size_t)std::pow((double)p->n, p->d);
+    double *rho = nullptr, *u = nullptr;
+    if (hipMalloc(&rho, pts * sizeof(double)) != hipSuccess || hipMalloc(&u, pts * sizeof(double)) != hipSuccess) {
+        if (rho) (void)hipFree(rho);
+        (void)hipGetLastError();
+        return fail(GS_ERR_OUT_OF_MEMORY, "autotune scratch allocation failed");
+    }
+    gs_status st = GS_OK;
+    hipError_t e = hipMemsetAsync(rho, 0, pts * sizeof(double), p->stream);
+    if (e != hipSuccess) st = hip_fail(e, "autotune scratch");
+    double best = 1e300;
+    if (st == GS_OK) st = time_plan(p, rho, u, best);
+    const int passes[5] = {1, 2, 3, 4, 5};
+    for (int pass : passes) {
+        if (st != GS_OK) break;
+        if (p->d == 2 && (pass == 2 || pass == 4)) continue;
+        const int keep = p->hint_bits;
+        p->hint_bits ^= 1 << (pass - 1);
+        double ms = 0;
+        st = time_plan(p, rho, u, ms);
+        p->tune_candidates++;
+        if (st == GS_OK && ms < best) best = ms;
+        else p->hint_bits = keep;
+    }
+    for (int m : {1, 4}) {
+        if (st != GS_OK) break;
+        const int keep = p->fused_mult;
+        p->fused_mult = m;
+        double ms = 0;
+        st = time_plan(p, rho, u, ms);
+        p->tune_candidates++;
+        if (st == GS_OK && ms < best) best = ms;
+        else p->fused_mult = keep;
+    }
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipFree(rho);
+    (void)hipFree(u);
+    if (st != GS_OK) return st;
+    p->tuned = true;
+    p->tuned_ms = best;
+    te.schedule = p->hint_bits;          // plan entries: schedule = hint bits,
+    te.tiles_per_task = p->fused_mult;   // tiles_per_task = fused grid rounds
+    te.largest_first = 0;
+    te.grid = 0;
+    te.ms = best;
+    tune_store(key, te);
+    return GS_OK;
+}
+
+}  // namespace

@@ -248,3 +248,26 @@ def test_max_size_3d_1024_against_closed_form():
     del u, rho, plan
     torch.cuda.empty_cache()
     assert np.max(np.abs(got - ref)) <= 1e-12 * umax
+
+
+@pytest.mark.parametrize("kernel,n", [("coulomb3d", 64), ("coulomb2d", 256), ("dipolar3d", 32)])
+def test_plan_autotune_changes_no_bit(kernel, n, tmp_path, monkeypatch):
+    """The plan autotuner picks launch variants (cache hints, fused-pass grid) by timing;
+    every variant computes the same bits, and the choice is cached per device and size."""
+    import json
+    monkeypatch.setenv("GS_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    d = 2 if kernel == "coulomb2d" else 3
+    rng = np.random.default_rng(77)
+    x = cuda(rng.standard_normal((n,) * d))
+    ref = gs.Plan(kernel, n=n, L=5.0, **kw).eval(x)
+    tuned = gs.Plan(kernel, n=n, L=5.0, autotune=True, **kw)
+    info = tuned.query()
+    assert info["tuned"] == 1 and info["tune_candidates"] >= 3 and info["tuned_ms"] > 0
+    assert torch.equal(tuned.eval(x), ref)
+    entries = json.loads((tmp_path / "tune.json").read_text())
+    assert any("|plan|" in k for k in entries)
+    again = gs.Plan(kernel, n=n, L=5.0, autotune=True, **kw)
+    assert again.query()["tune_candidates"] == 0
+    assert again.query()["hint_bits"] == info["hint_bits"]
+    assert torch.equal(again.eval(x), ref)
