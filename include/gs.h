@@ -178,9 +178,10 @@ gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho
  * problem's result is bitwise the one gs_eval gives.
  *
  * Schedules:
- *   GS_SCHED_QUEUE      one persistent launch walks a pass-major task list of
- *                       every problem; a task waits for the preceding pass of
- *                       its own problem through per-problem counters.
+ *   GS_SCHED_QUEUE      one persistent launch; each die (XCD) of the device
+ *                       walks a pass-major task list of the problems pinned to
+ *                       it, a task waiting for the preceding pass of its own
+ *                       problem through per-problem counters.
  *   GS_SCHED_PHASED     one launch per pass type over the tasks of all problems.
  *   GS_SCHED_SIZED      one launch per pass type and grid size (each launch
  *                       specialised to its size).
@@ -225,7 +226,10 @@ typedef struct {
     int candidates;         /* schedules timed by the autotuner for this batch  */
     double tuned_ms;        /* best measured evaluation time (ms), 0 if none    */
     int wait_timeouts;      /* 1 if a queue-schedule dependency wait ever gave up
-                               (results of that call invalid; never expected)  */
+                               or a queue was left unfinished (results of that
+                               call invalid; never expected)                    */
+    int num_queues;         /* queue schedule: task queues (one per die in use)  */
+    int local_queues;       /* 1: each problem pinned to one die's queue         */
 } gs_batch_info;
 
 /* Defaults: GS_SCHED_AUTO, tiles_per_task 0, grid 0, no graph, null stream. */

@@ -46,7 +46,7 @@ class GSBatchInfo(C.Structure):
     _fields_ = [("count", C.c_int), ("points", C.c_double), ("schedule", C.c_int), ("tiles_per_task", C.c_int),
                 ("grid", C.c_int), ("use_graph", C.c_int), ("num_tasks", C.c_int), ("tasks_per_pass", C.c_int * 6),
                 ("autotuned", C.c_int), ("candidates", C.c_int), ("tuned_ms", C.c_double),
-                ("wait_timeouts", C.c_int)]
+                ("wait_timeouts", C.c_int), ("num_queues", C.c_int), ("local_queues", C.c_int)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/gs.h

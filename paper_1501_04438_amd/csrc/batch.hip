@@ -1,5 +1,9 @@
 // batch.hip -- host side of the batched evaluation: descriptors, task lists, launches.
 #include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <set>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -66,17 +70,10 @@ void batch_problems(const std::vector<BatchMember>& m, std::vector<unsigned char
     }
 }
 
-void batch_tasks(const std::vector<BatchMember>& m, int mult, bool largest_first, std::vector<int>& tasks,
-                 int pass_off[6], int pass_cnt[6]) {
-    const int nb = (int)m.size();
-    std::vector<int> order(nb);
-    std::iota(order.begin(), order.end(), 0);
-    if (largest_first)
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return (double)m[a].n * (m[a].d == 3 ? m[a].n : 1) > (double)m[b].n * (m[b].d == 3 ? m[b].n : 1);
-        });
-    std::vector<int> ntask(nb * 6, 0);      // tasks of pass p of member b
-    std::vector<BatchTask> T;
+// Pass-major tasks of the members listed in `order` (indices into m), appended to T.
+static void build_tasks(const std::vector<BatchMember>& m, const std::vector<int>& order, int mult,
+                        std::vector<BatchTask>& T, int pass_off[6], int pass_cnt[6]) {
+    std::vector<int> ntask(m.size() * 6, 0);      // tasks of pass p of member b
     for (int p = 1; p <= 5; ++p) {
         pass_off[p] = (int)T.size();
         for (int b : order) {
@@ -100,8 +97,79 @@ void batch_tasks(const std::vector<BatchMember>& m, int mult, bool largest_first
         pass_cnt[p] = (int)T.size() - pass_off[p];
     }
     pass_off[0] = pass_cnt[0] = 0;
+}
+
+static double member_work(const BatchMember& x) { return std::pow((double)x.n, x.d) * (x.d == 3 ? 2.5 : 1.0); }
+
+static std::vector<int> size_order(const std::vector<BatchMember>& m, bool largest_first) {
+    std::vector<int> order(m.size());
+    std::iota(order.begin(), order.end(), 0);
+    if (largest_first)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return member_work(m[a]) > member_work(m[b]); });
+    return order;
+}
+
+void batch_tasks(const std::vector<BatchMember>& m, int mult, bool largest_first, std::vector<int>& tasks,
+                 int pass_off[6], int pass_cnt[6]) {
+    std::vector<BatchTask> T;
+    build_tasks(m, size_order(m, largest_first), mult, T, pass_off, pass_cnt);
     tasks.resize(T.size() * BATCH_TASK_INTS);
     std::memcpy(tasks.data(), T.data(), T.size() * sizeof(BatchTask));
+}
+
+void batch_queue_tasks(const std::vector<BatchMember>& m, int mult, int nq, std::vector<int>& tasks,
+                       std::vector<int>& qoff) {
+    nq = std::max(1, nq);
+    // members dealt to queues by decreasing work, each to the least loaded queue
+    std::vector<std::vector<int>> part(nq);
+    std::vector<double> load(nq, 0.0);
+    for (int b : size_order(m, true)) {
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        part[q].push_back(b);
+        load[q] += member_work(m[b]);
+    }
+    std::vector<BatchTask> T;
+    qoff.assign(nq + 1, 0);
+    for (int q = 0; q < nq; ++q) {
+        int off[6], cnt[6];
+        build_tasks(m, part[q], mult, T, off, cnt);
+        qoff[q + 1] = (int)T.size();
+    }
+    tasks.resize(T.size() * BATCH_TASK_INTS);
+    std::memcpy(tasks.data(), T.data(), T.size() * sizeof(BatchTask));
+}
+
+__global__ void k_xcc_probe(int* out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = hw_xcc_id();
+}
+
+int batch_xcc_ids(int* ids, int cap) {
+    static std::mutex mu;
+    static std::map<int, std::vector<int>> cache;      // device -> sorted ids
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it == cache.end()) {
+        constexpr int NB = 2048;
+        int* d = nullptr;
+        std::vector<int> h(NB, -1), found;
+        if (hipMalloc(&d, NB * sizeof(int)) == hipSuccess) {
+            k_xcc_probe<<<NB, 64>>>(d);
+            if (hipGetLastError() == hipSuccess &&
+                hipMemcpy(h.data(), d, NB * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess) {
+                std::set<int> s(h.begin(), h.end());
+                found.assign(s.begin(), s.end());
+            }
+            (void)hipFree(d);
+        }
+        (void)hipGetLastError();
+        it = cache.emplace(dev, found).first;
+    }
+    const int c = (int)it->second.size();
+    for (int i = 0; i < c && i < cap; ++i) ids[i] = it->second[i];
+    return c;
 }
 
 int batch_counters(int nprob) { return batch_counter(nprob, 0); }
@@ -116,13 +184,20 @@ int batch_resident_blocks() {
     return cus * per;
 }
 
-hipError_t launch_batch_queue(const void* probs, const void* tasks, int ntasks, unsigned* ctr, int nctr, int grid,
-                              unsigned spin_limit, hipStream_t s) {
-    if (ntasks <= 0) return hipSuccess;
+hipError_t launch_batch_queue(const void* probs, const void* tasks, const BatchQueueSpec& spec, unsigned* ctr,
+                              int nctr, int grid, unsigned spin_limit, hipStream_t s) {
+    if (spec.nq < 1 || spec.nq > BATCH_MAX_QUEUES || (int)spec.qoff.size() != spec.nq + 1) return hipErrorInvalidValue;
+    if (spec.qoff[spec.nq] <= 0) return hipSuccess;
     if (grid <= 0) return hipErrorInvalidValue;
-    k_batch_queue<<<std::min(grid, ntasks), BATCH_THREADS, 0, s>>>(static_cast<const BatchProblem*>(probs),
-                                                                  static_cast<const BatchTask*>(tasks), ntasks, ctr,
-                                                                  nctr, spin_limit);
+    BatchQueues Q;
+    Q.nq = spec.nq;
+    Q.local = spec.local;
+    for (int i = 0; i < BATCH_MAX_QUEUES; ++i) Q.qmap[i] = spec.qmap[i];
+    for (int i = 0; i <= BATCH_MAX_QUEUES; ++i) Q.qoff[i] = i <= spec.nq ? spec.qoff[i] : spec.qoff[spec.nq];
+    // local queues need blocks on every die: the whole co-resident grid
+    const int g = spec.local ? grid : std::min(grid, spec.qoff[spec.nq]);
+    k_batch_queue<<<g, BATCH_THREADS, 0, s>>>(static_cast<const BatchProblem*>(probs),
+                                               static_cast<const BatchTask*>(tasks), Q, ctr, nctr, spin_limit);
     return hipGetLastError();
 }
 

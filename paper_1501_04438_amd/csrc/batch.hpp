@@ -46,10 +46,26 @@ struct BatchTask {
     int dep_pass, dep_count;   // wait until dep_count tasks of pass dep_pass of this problem are done (0: none)
 };
 
-// Counters of the queue schedule: [0] next task, [1] blocks that left,
-// [2 + 8 b + p] tasks of pass p of problem b that are done; one more word after
-// them is the error flag (a dependency wait gave up), which launches do not clear.
-__host__ __device__ constexpr int batch_counter(int prob, int pass) { return 2 + 8 * prob + pass; }
+// Task queues of the queue schedule: one per XCD (accelerator die) in use.  qmap maps
+// a hardware XCC id (0..15) to its queue (-1: none); queue q holds tasks
+// qoff[q] .. qoff[q+1]-1.  local: every problem's tasks sit in one queue, so a
+// producer and its consumers share one L2 and the dependencies need no L2
+// write-back; otherwise (one queue for all dies) agent-scope release/acquire.
+constexpr int BATCH_MAX_QUEUES = 16;
+struct BatchQueues {
+    int nq, local;
+    int qmap[BATCH_MAX_QUEUES];
+    int qoff[BATCH_MAX_QUEUES + 1];
+};
+
+// Counters of the queue schedule: [0] blocks that left, [1 + q] next task of queue q,
+// [1 + BATCH_MAX_QUEUES + 8 b + p] tasks of pass p of problem b that are done; one
+// more word after them is the error flag (a dependency wait gave up, or a queue was
+// left unfinished because no block ran on its die), which launches do not clear.
+__host__ __device__ constexpr int batch_counter(int prob, int pass) { return 1 + BATCH_MAX_QUEUES + 8 * prob + pass; }
+
+// Hardware id of the XCD the calling wave runs on (HW_REG_XCC_ID, bits 3:0).
+__device__ __forceinline__ int hw_xcc_id() { return (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
 
 // Threads and LDS slots of one tile of pass p at size N; tiles per problem.
 template <int N> __host__ __device__ constexpr int tile_threads(int pass) {
@@ -187,37 +203,51 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_size(const BatchProblem
 
 // Queue schedule: one persistent launch over every task of the batch.
 //
-// Every branch of the task loop is wave-uniform (conditions pass through
-// readfirstlane): wave 0 of the block does the counter work with all its lanes,
-// lane 0 contributing the increment and the others zero.  A lane-0-only branch at
-// the loop boundary would let the compiler park lane 0 outside the loop while the
-// other lanes of its wave run on through the barriers with a stale task index.
+// A block serves the queue of the die it runs on.  Every branch of the task loop is
+// wave-uniform (conditions pass through readfirstlane): wave 0 of the block does the
+// counter work with all its lanes, lane 0 contributing the increment and the others
+// zero.  A lane-0-only branch at the loop boundary would let the compiler park lane
+// 0 outside the loop while the other lanes of its wave run on through the barriers
+// with a stale task index.
+//
+// Memory ordering, local queues: the producer's stores reach the die's L2 before
+// its counter increment (every wave waits for its stores before the block barrier;
+// the vector L1 is write through), and a consumer invalidates its own L1 after
+// observing the counter.
+// Otherwise agent-scope release (L2 write-back) and acquire (L2 invalidate).
 //
 // A dependency wait gives up after spin_limit polls (far beyond any task's
 // duration): it raises the error flag ctr[nctr] and carries on, so every wave
 // reaches the end of the launch whatever happens; the host reads the flag.
 __global__ void __launch_bounds__(BATCH_THREADS) k_batch_queue(const BatchProblem* __restrict__ probs,
-                                                               const BatchTask* __restrict__ tasks, int ntasks,
+                                                               const BatchTask* __restrict__ tasks, BatchQueues Q,
                                                                unsigned* __restrict__ ctr, int nctr,
                                                                unsigned spin_limit) {
     __shared__ cpx lds[batch_lds_slots()];
     __shared__ int s_task, s_next;
     const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64u;
     const unsigned one = (threadIdx.x == 0) ? 1u : 0u;      // the increment of lane 0
+    const int q = Q.nq == 1 && !Q.local ? 0 : Q.qmap[hw_xcc_id() & (BATCH_MAX_QUEUES - 1)];
+    const int base = q >= 0 ? Q.qoff[q] : 0;
+    const int count = q >= 0 ? Q.qoff[q + 1] - base : 0;
+    unsigned* head = &ctr[1 + (q >= 0 ? q : 0)];
     if (wave0) {
-        const unsigned k0 = __hip_atomic_fetch_add(&ctr[0], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_task = (int)__builtin_amdgcn_readfirstlane(k0);
+        int k0 = count;
+        if (count > 0)
+            k0 = (int)__builtin_amdgcn_readfirstlane(
+                __hip_atomic_fetch_add(head, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        s_task = k0;
     }
     __syncthreads();
     for (;;) {
         const int k = __builtin_amdgcn_readfirstlane(s_task);
-        if (k >= ntasks) break;
-        const BatchTask t = tasks[k];
+        if (k >= count) break;
+        const BatchTask t = tasks[base + k];
         if (wave0) {
             // claim the next task now: its index arrives while this one waits and runs
-            // (a claimed task depends only on tasks before it, so claiming early
-            // cannot deadlock)
-            const unsigned nx = __hip_atomic_fetch_add(&ctr[0], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // (a claimed task depends only on tasks before it in its queue, so claiming
+            // early cannot deadlock)
+            const unsigned nx = __hip_atomic_fetch_add(head, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (t.dep_count > 0) {
                 unsigned* c = &ctr[batch_counter(t.prob, t.dep_pass)];
                 for (unsigned polls = 0;; ++polls) {
@@ -230,27 +260,41 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_queue(const BatchProble
                     }
                     __builtin_amdgcn_s_sleep(2);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (Q.local) asm volatile("buffer_inv sc0" ::: "memory");        // this CU's L1
+                else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             s_next = (int)__builtin_amdgcn_readfirstlane(nx);
         }
         __syncthreads();
         batch_task(probs[t.prob], t, lds);
-        __syncthreads();                       // every wave's stores are issued and complete
+        // every wave waits until its stores are complete (in the die's L2; the block
+        // barrier alone orders LDS only), then the barrier
+        __builtin_amdgcn_s_waitcnt(0x0F70);    // vmcnt(0)
+        __syncthreads();
         if (wave0) {
-            __hip_atomic_fetch_add(&ctr[batch_counter(t.prob, t.pass)], one, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            unsigned* c = &ctr[batch_counter(t.prob, t.pass)];
+            if (Q.local) __hip_atomic_fetch_add(c, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else __hip_atomic_fetch_add(c, one, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             s_task = s_next;
         }
         __syncthreads();
     }
-    // the last block to leave clears the counters (the next launch starts after this one ends)
+    // the last block to leave checks that every queue was drained and clears the
+    // counters (the next launch starts after this one ends)
     if (wave0) {
-        const unsigned e = __hip_atomic_fetch_add(&ctr[1], one, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned e = __hip_atomic_fetch_add(&ctr[0], one, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         s_task = (__builtin_amdgcn_readfirstlane(e) == gridDim.x - 1u) ? 1 : 0;
     }
     __syncthreads();
     if (__builtin_amdgcn_readfirstlane(s_task)) {
+        if (wave0) {
+            bool drained = true;
+            for (int i = 0; i < Q.nq; ++i)
+                drained = drained && __hip_atomic_load(&ctr[1 + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                                         (unsigned)(Q.qoff[i + 1] - Q.qoff[i]);
+            if (!__builtin_amdgcn_readfirstlane(drained ? 1u : 0u))
+                __hip_atomic_store(&ctr[nctr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         for (int i = threadIdx.x; i < nctr; i += BATCH_THREADS)
             __hip_atomic_store(&ctr[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }

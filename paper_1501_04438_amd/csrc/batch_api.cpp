@@ -42,7 +42,8 @@ struct gs_batch_s {
     std::vector<unsigned char> probs_dev; // descriptors now in device memory
     int ntasks = 0, pass_off[6] = {}, pass_cnt[6] = {};
     std::vector<int> runs;                // (pass, n, first task, count) of the sized schedule
-    int tasks_mult = -1, tasks_lf = -1;
+    int tasks_mult = -1, tasks_lf = -1, tasks_queue = -1;
+    gsk::BatchQueueSpec queues;           // the queue schedule's per-die queues
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_staged = nullptr;
     bool staged_pending = false;
     hipGraphExec_t exec = nullptr;
@@ -106,12 +107,41 @@ gs_status members(gs_batch_s* b, const double* const* rho, double* const* u, std
     return GS_OK;
 }
 
-// The task list of (mult, largest_first) in device memory (synchronous: rare).
-gs_status upload_tasks(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, int mult, int lf) {
-    if (b->tasks_mult == mult && b->tasks_lf == lf) return GS_OK;
+// Queues of the queue schedule: one per die the device's blocks run on (problems
+// pinned to a die), or a single shared queue if the dies cannot be identified.
+void plan_queues(gs_batch_s* b) {
+    int ids[32];
+    const int c = gsk::batch_xcc_ids(ids, 32);
+    gsk::BatchQueueSpec& q = b->queues;
+    bool ok = c >= 1 && c <= 16;
+    for (int i = 0; i < c && ok; ++i) ok = ids[i] >= 0 && ids[i] < 16;
+    for (int i = 0; i < 16; ++i) q.qmap[i] = ok ? -1 : 0;
+    if (ok) {
+        q.nq = c;
+        q.local = 1;
+        for (int i = 0; i < c; ++i) q.qmap[ids[i]] = i;
+    } else {
+        q.nq = 1;
+        q.local = 0;
+    }
+}
+
+// The task list of (schedule, mult, largest_first) in device memory (synchronous: rare).
+gs_status upload_tasks(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, int mult, int lf, int schedule) {
+    const int queue = schedule == GS_SCHED_QUEUE ? 1 : 0;
+    if (b->tasks_mult == mult && b->tasks_lf == lf && b->tasks_queue == queue) return GS_OK;
     std::vector<int> t;
-    gsk::batch_tasks(m, mult, lf != 0, t, b->pass_off, b->pass_cnt);
-    gsk::batch_size_runs(m, t, b->runs);
+    if (queue) {
+        plan_queues(b);
+        gsk::batch_queue_tasks(m, mult, b->queues.nq, t, b->queues.qoff);
+        for (int p = 0; p < 6; ++p) b->pass_off[p] = b->pass_cnt[p] = 0;
+        for (size_t k = 0; k < t.size() / gsk::BATCH_TASK_INTS; ++k)      // field 1 of a task: its pass
+            b->pass_cnt[t[k * gsk::BATCH_TASK_INTS + 1]]++;
+        b->runs.clear();
+    } else {
+        gsk::batch_tasks(m, mult, lf != 0, t, b->pass_off, b->pass_cnt);
+        gsk::batch_size_runs(m, t, b->runs);
+    }
     hipError_t e = hipStreamSynchronize(b->own);
     if (e != hipSuccess) return hip_fail(e, "batch stream");
     if (t.size() > b->tasks_cap) {
@@ -127,6 +157,7 @@ gs_status upload_tasks(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, in
     b->ntasks = (int)(t.size() / gsk::BATCH_TASK_INTS);
     b->tasks_mult = mult;
     b->tasks_lf = lf;
+    b->tasks_queue = queue;
     return GS_OK;
 }
 
@@ -152,7 +183,7 @@ gs_status launch(gs_batch_s* b, const TuneEntry& c, const double* const* rho, do
     hipError_t e = hipSuccess;
     const int grid = c.grid > 0 ? c.grid : b->resident;
     if (c.schedule == GS_SCHED_QUEUE) {
-        e = gsk::launch_batch_queue(b->d_probs, b->d_tasks, b->ntasks, b->d_ctr, b->nctr, grid, kSpinLimit, b->own);
+        e = gsk::launch_batch_queue(b->d_probs, b->d_tasks, b->queues, b->d_ctr, b->nctr, grid, kSpinLimit, b->own);
     } else if (c.schedule == GS_SCHED_PHASED) {
         e = gsk::launch_batch_phased(b->d_probs, b->d_tasks, b->pass_off, b->pass_cnt, grid, b->own);
     } else if (c.schedule == GS_SCHED_SIZED) {
@@ -183,7 +214,7 @@ std::string shape_key(const gs_batch_s* b) {
 gs_status time_candidate(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const TuneEntry& c,
                          const double* const* rho, double* const* u, double& ms) {
     if (c.schedule != GS_SCHED_SEQUENTIAL) {
-        const gs_status st = upload_tasks(b, m, c.tiles_per_task, c.largest_first);
+        const gs_status st = upload_tasks(b, m, c.tiles_per_task, c.largest_first, c.schedule);
         if (st != GS_OK) return st;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -326,7 +357,7 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
         // acquire per task, so its tasks are larger
         const int def = opt.schedule == GS_SCHED_QUEUE ? kQueueTilesPerTask : 4;
         b->cfg = {opt.schedule, opt.tiles_per_task > 0 ? opt.tiles_per_task : def, 1, opt.grid, 0.0};
-        if (opt.schedule != GS_SCHED_SEQUENTIAL) st = upload_tasks(b, m, b->cfg.tiles_per_task, 1);
+        if (opt.schedule != GS_SCHED_SEQUENTIAL) st = upload_tasks(b, m, b->cfg.tiles_per_task, 1, opt.schedule);
         b->resolved = true;
     }
     if (st != GS_OK) {
@@ -361,7 +392,7 @@ gs_status gs_batch_eval(gs_batch b, const double* const* rho, double* const* u) 
         b->resolved = true;
     }
     if (b->cfg.schedule != GS_SCHED_SEQUENTIAL &&
-        (st = upload_tasks(b, m, b->cfg.tiles_per_task, b->cfg.largest_first)) != GS_OK)
+        (st = upload_tasks(b, m, b->cfg.tiles_per_task, b->cfg.largest_first, b->cfg.schedule)) != GS_OK)
         return st;
     if (b->req.use_graph) {
         // what the captured launches bake in: the task list, and for the sequential
@@ -427,6 +458,8 @@ gs_status gs_batch_query(gs_batch b, gs_batch_info* info) {
         e = hipMemcpy(&flag, b->d_ctr + b->nctr, sizeof(unsigned), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "batch query");
     info->wait_timeouts = flag ? 1 : 0;
+    info->num_queues = b->queues.nq;
+    info->local_queues = b->queues.local;
     return GS_OK;
 }
 

@@ -72,9 +72,23 @@ void batch_tasks(const std::vector<BatchMember>& m, int mult, bool largest_first
 // unsigned counters of the queue schedule (start zeroed); the error flag is the word after them
 int batch_counters(int nprob);
 int batch_resident_blocks();              // co-resident blocks of the batch kernels on this device
+// Queue schedule: nq task queues (tasks qoff[q] .. qoff[q+1]-1 of a concatenated list),
+// qmap[hardware die id] = queue or -1; local = every problem's tasks in one queue
+// served only by blocks on one die.
+struct BatchQueueSpec {
+    int nq = 1, local = 0;
+    int qmap[16] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    std::vector<int> qoff = {0, 0};
+};
+// Per-queue pass-major task lists: members dealt to nq queues by decreasing work,
+// each to the least loaded queue.
+void batch_queue_tasks(const std::vector<BatchMember>& m, int mult, int nq, std::vector<int>& tasks,
+                       std::vector<int>& qoff);
+// Hardware ids of the dies (XCDs) blocks run on, sorted; probed once per device.
+int batch_xcc_ids(int* ids, int cap);
 // spin_limit: polls after which a dependency wait raises the error flag and goes on
-hipError_t launch_batch_queue(const void* probs, const void* tasks, int ntasks, unsigned* ctr, int nctr, int grid,
-                              unsigned spin_limit, hipStream_t s);
+hipError_t launch_batch_queue(const void* probs, const void* tasks, const BatchQueueSpec& spec, unsigned* ctr,
+                              int nctr, int grid, unsigned spin_limit, hipStream_t s);
 hipError_t launch_batch_phased(const void* probs, const void* tasks, const int pass_off[6], const int pass_cnt[6],
                                int grid, hipStream_t s);
 

@@ -79,6 +79,9 @@ def test_schedules_bitwise_equal_single(mixed, schedule, tpt, graph):
     assert info["wait_timeouts"] == 0
     if schedule != "sequential":
         assert info["num_tasks"] == sum(info["tasks_per_pass"])
+    if schedule == "queue":
+        # one queue per die of the device, problems pinned to a die
+        assert info["num_queues"] >= 1 and info["local_queues"] == (1 if info["num_queues"] >= 1 else 0)
     b.close()
 
 
