@@ -86,6 +86,10 @@ typedef struct {
     int slab_planes;         /* 3D: kx planes per slab of the middle passes (the X2
                                 workspace holds one slab); 0 = as many as fit in
                                 GS_SLAB_BYTES (unset: all), -1 = all n+1 planes   */
+    int slab_streams;        /* 3D: streams the slabs' middle-pass chains run on
+                                concurrently (>= 2: X2 holds every slab, each at
+                                its own planes; the results are the same bits);
+                                0 or 1 = in order on the plan's stream           */
 } gs_options;
 
 typedef struct {
@@ -102,6 +106,8 @@ typedef struct {
     int host_only;
     int slab_planes;         /* kx planes per slab (3D), n+1 in 2D                */
     int num_steps;           /* kernel launches of one evaluation                 */
+    int slab_streams;        /* concurrent slab chains (1 = in order)             */
+    int x2_planes;           /* kx planes the X2 workspace holds                  */
     int tuned;               /* 1 if the launch variants came from the autotuner  */
     int hint_bits;           /* bit p-1 set: pass p uses its cache-hint variant   */
     int fused_grid_mult;     /* rounds of co-resident blocks of the fused pass    */

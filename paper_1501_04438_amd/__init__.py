@@ -56,7 +56,7 @@ class Plan:
     def __init__(self, kernel: str, n: int, L: float, eps: float = 1e-14, d: int | None = None,
                  delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
                  host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0,
-                 autotune: bool = False):
+                 slab_streams: int = 0, autotune: bool = False):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         d = KERNEL_DIM.get(kernel, d)
@@ -70,6 +70,7 @@ class Plan:
         opt.flags = ((PLAN_HOST_ONLY if host_only else 0) | (PLAN_HOST_ASSEMBLY if host_assembly else 0)
                      | (PLAN_AUTOTUNE if autotune else 0))
         opt.slab_planes = int(slab_planes)
+        opt.slab_streams = int(slab_streams)
         if stream is not None:
             opt.stream = C.c_void_p(int(stream))
         keep = []
@@ -178,7 +179,7 @@ class Plan:
         if which == 1:
             shape, cplx = ((n, n + 1, n) if d == 3 else (n + 1, n)), True
         elif which == 2:
-            shape, cplx = (self.info["slab_planes"], 2 * n, n), True
+            shape, cplx = (self.query()["x2_planes"], 2 * n, n), True
         else:
             shape, cplx = (n + 1,) * d, False
         if value is None:

@@ -22,7 +22,8 @@ PLAN_AUTOTUNE = 4
 class GSOptions(C.Structure):
     _fields_ = [("delta_rel", C.c_double), ("dipole_n", C.c_double * 3), ("dipole_m", C.c_double * 3),
                 ("gs_w", C.POINTER(C.c_double)), ("gs_tau", C.POINTER(C.c_double)), ("gs_q", C.c_int),
-                ("stream", C.c_void_p), ("device", C.c_int), ("flags", C.c_int), ("slab_planes", C.c_int)]
+                ("stream", C.c_void_p), ("device", C.c_int), ("flags", C.c_int), ("slab_planes", C.c_int),
+                ("slab_streams", C.c_int)]
 
 
 class GSPlanInfo(C.Structure):
@@ -30,7 +31,7 @@ class GSPlanInfo(C.Structure):
                 ("delta", C.c_double), ("S", C.c_int), ("Q", C.c_int), ("A0", C.c_double), ("c2", C.c_double),
                 ("spectrum_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("assembly_ms", C.c_double),
                 ("assembly_gflop", C.c_double), ("host_only", C.c_int), ("slab_planes", C.c_int),
-                ("num_steps", C.c_int), ("tuned", C.c_int), ("hint_bits", C.c_int), ("fused_grid_mult", C.c_int),
+                ("num_steps", C.c_int), ("slab_streams", C.c_int), ("x2_planes", C.c_int), ("tuned", C.c_int), ("hint_bits", C.c_int), ("fused_grid_mult", C.c_int),
                 ("tune_candidates", C.c_int), ("tuned_ms", C.c_double)]
 
 

@@ -30,6 +30,10 @@ struct gs_plan_s {
     double assembly_ms = 0.0;
     int slab = 0, nslabs = 1;                 // 3D: kx planes per slab of the middle passes
     int hint_bits = 31, fused_mult = 2;       // launch variants (see gsk::EvalArgs)
+    int x2_planes = 0;                        // kx planes X2 holds (n+1: every slab at its own planes)
+    int nstreams = 1;                         // concurrent slab chains of the middle passes
+    std::vector<hipStream_t> sstreams;        // their streams (created on demand)
+    std::vector<hipEvent_t> sevents;          // one per stream, plus the fork event last
     bool tuned = false;
     int tune_candidates = 0;
     double tuned_ms = 0.0;
@@ -62,5 +66,8 @@ struct DeviceScope {
 gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a);
 // Queues the evaluation steps of p on its stream: all of them (step < 0) or one.
 gs_status eval_chain(gs_plan p, const double* in, double* out, int step);
+// Rebuilds p's step list for `planes` kx planes per slab (3D), run on `streams` streams
+// (X2 must hold every plane when streams > 1 or planes exceed x2_planes: returns false).
+bool set_slabs(gs_plan p, int planes, int streams);
 
 }  // namespace gsapi

@@ -67,6 +67,10 @@ void free_device(gs_plan_s* p) {
     if (p->X1) (void)hipFree(p->X1);
     if (p->X2) (void)hipFree(p->X2);
     if (p->tw) (void)hipFree(p->tw);
+    for (hipStream_t st : p->sstreams) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : p->sevents) (void)hipEventDestroy(ev);
+    p->sstreams.clear();
+    p->sevents.clear();
     p->spec = nullptr;
     p->X1 = p->X2 = p->tw = nullptr;
 }
@@ -181,11 +185,67 @@ gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) 
     return GS_OK;
 }
 
-static hipError_t run_step(gs_plan p, gsk::EvalArgs& a, int step) {
+bool set_slabs(gs_plan p, int planes, int streams) {
+    if (p->d != 3) return planes >= p->n + 1 && streams <= 1;
+    const int n1 = p->n + 1;
+    planes = std::max(1, std::min(planes, n1));
+    const int nsl = (n1 + planes - 1) / planes;
+    const int slab = (n1 + nsl - 1) / nsl;
+    streams = std::max(1, std::min(streams, nsl));
+    if (slab > p->x2_planes || (streams > 1 && p->x2_planes < n1)) return false;
+    p->nslabs = nsl;
+    p->slab = slab;
+    p->nstreams = streams;
+    p->steps.clear();
+    p->steps.push_back({1, 0});
+    for (int c = 0; c < nsl; ++c) {
+        p->steps.push_back({2, c});
+        p->steps.push_back({3, c});
+        p->steps.push_back({4, c});
+    }
+    p->steps.push_back({5, 0});
+    return true;
+}
+
+static hipError_t run_step(gs_plan p, gsk::EvalArgs& a, int step, hipStream_t s) {
     const auto [pass, c] = p->steps[step];
     a.kx0 = c * p->slab;
     a.kxn = std::min(p->slab, p->n + 1 - a.kx0);
-    return gsk::launch_eval(a, p->stream, pass);
+    gsk::EvalArgs b = a;
+    // X2 holding every plane: the slab's planes sit at its own offset
+    if (p->d == 3 && p->x2_planes == p->n + 1 && p->nslabs > 1) b.X2 = a.X2 + (size_t)a.kx0 * 2 * p->n * p->n;
+    return gsk::launch_eval(b, s, pass);
+}
+
+// The slab chains (y-forward, fused, y-inverse of one kx slab) on p->nstreams streams:
+// forked from the plan's stream after the x pass, joined before the x-inverse pass.
+static hipError_t run_concurrent(gs_plan p, gsk::EvalArgs& a) {
+    const int k = p->nstreams;
+    hipError_t e = hipSuccess;
+    if ((int)p->sstreams.size() < k) {
+        for (hipStream_t st : p->sstreams) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : p->sevents) (void)hipEventDestroy(ev);
+        p->sstreams.assign(k, nullptr);
+        p->sevents.assign(k + 1, nullptr);
+        for (int i = 0; i < k && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&p->sstreams[i], hipStreamNonBlocking);
+        for (int i = 0; i <= k && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&p->sevents[i], hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    const int last = (int)p->steps.size() - 1;
+    if ((e = run_step(p, a, 0, p->stream)) != hipSuccess) return e;
+    if ((e = hipEventRecord(p->sevents[k], p->stream)) != hipSuccess) return e;
+    for (int i = 0; i < k; ++i)
+        if ((e = hipStreamWaitEvent(p->sstreams[i], p->sevents[k], 0)) != hipSuccess) return e;
+    for (int c = 0; c < p->nslabs; ++c) {
+        hipStream_t s = p->sstreams[c % k];
+        for (int j = 0; j < 3; ++j)
+            if ((e = run_step(p, a, 1 + 3 * c + j, s)) != hipSuccess) return e;
+    }
+    for (int i = 0; i < k; ++i) {
+        if ((e = hipEventRecord(p->sevents[i], p->sstreams[i])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(p->stream, p->sevents[i], 0)) != hipSuccess) return e;
+    }
+    return run_step(p, a, last, p->stream);
 }
 
 gs_status eval_chain(gs_plan p, const double* in, double* out, int step) {
@@ -197,9 +257,11 @@ gs_status eval_chain(gs_plan p, const double* in, double* out, int step) {
     if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
     hipError_t e = hipSuccess;
     if (step >= 0) {
-        e = run_step(p, a, step);
+        e = run_step(p, a, step, p->stream);
+    } else if (p->d == 3 && p->nstreams > 1 && p->nslabs > 1) {
+        e = run_concurrent(p, a);
     } else {
-        for (int i = 0; i < (int)p->steps.size() && e == hipSuccess; ++i) e = run_step(p, a, i);
+        for (int i = 0; i < (int)p->steps.size() && e == hipSuccess; ++i) e = run_step(p, a, i, p->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "evaluation launch");
     return GS_OK;
@@ -334,27 +396,23 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     const size_t n1 = (size_t)nn + 1;
     p->spec_bytes = (d == 3 ? n1 * n1 * n1 : n1 * n1) * sizeof(double);
     const size_t x1 = n1 * (d == 3 ? (size_t)nn * nn : (size_t)nn);
+    size_t x2 = 0;
     if (d == 3) {
-        // kx slab of the middle passes: its X2 (2n n complex per plane) sized to stay in
-        // the last-level cache; planes balanced over the slabs
+        // kx slab of the middle passes; X2 (2n n complex per plane) holds one slab, or
+        // every plane when slab chains run concurrently
         const size_t plane = 2 * (size_t)nn * nn * sizeof(double2);
         int per = (int)n1;
         if (opt.slab_planes > 0) per = std::min<int>(opt.slab_planes, (int)n1);
         else if (opt.slab_planes == 0) per = (int)std::max<size_t>(1, std::min<size_t>(n1, slab_budget() / plane));
-        p->nslabs = (int)((n1 + per - 1) / per);
-        p->slab = (int)((n1 + p->nslabs - 1) / p->nslabs);
-        p->steps.push_back({1, 0});
-        for (int c = 0; c < p->nslabs; ++c) {
-            p->steps.push_back({2, c});
-            p->steps.push_back({3, c});
-            p->steps.push_back({4, c});
-        }
-        p->steps.push_back({5, 0});
+        const int nsl = (int)((n1 + per - 1) / per);
+        const int slab = (int)((n1 + nsl - 1) / nsl);
+        p->x2_planes = opt.slab_streams > 1 ? (int)n1 : slab;
+        (void)set_slabs(p, slab, std::max(1, opt.slab_streams));
+        x2 = plane / sizeof(double2) * (size_t)p->x2_planes;
     } else {
         p->slab = (int)n1;
         p->steps = {{1, 0}, {3, 0}, {5, 0}};
     }
-    const size_t x2 = (d == 3) ? 2 * (size_t)nn * nn * (size_t)p->slab : 0;
     p->work_bytes = (x1 + x2) * sizeof(double2) + 2 * (size_t)nn * sizeof(double2);
 
     if (host_only) {
@@ -454,6 +512,8 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
     info->host_only = p->host_only ? 1 : 0;
     info->slab_planes = p->slab;
     info->num_steps = (int)p->steps.size();
+    info->slab_streams = p->nstreams;
+    info->x2_planes = p->d == 3 ? p->x2_planes : 0;
     info->tuned = p->tuned ? 1 : 0;
     info->hint_bits = p->hint_bits;
     info->fused_grid_mult = p->fused_mult;
@@ -504,7 +564,7 @@ gs_status gs_plan_buffer(gs_plan p, int which, int to_device, double* host, size
         doubles = 2 * n1 * (p->d == 3 ? n * n : n);
     } else if (which == 2 && p->d == 3) {
         buf = p->X2;
-        doubles = 2 * 2 * n * n * (size_t)p->slab;
+        doubles = 2 * 2 * n * n * (size_t)p->x2_planes;
     } else if (which == 3) {
         buf = p->spec;
         doubles = p->spec_bytes / sizeof(double);

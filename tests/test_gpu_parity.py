@@ -271,3 +271,19 @@ def test_plan_autotune_changes_no_bit(kernel, n, tmp_path, monkeypatch):
     assert again.query()["tune_candidates"] == 0
     assert again.query()["hint_bits"] == info["hint_bits"]
     assert torch.equal(again.eval(x), ref)
+
+
+@pytest.mark.parametrize("planes,streams", [(13, 2), (9, 3), (65, 2)])
+def test_concurrent_slab_chains_change_nothing(planes, streams):
+    """Slab chains of the middle passes on several streams (forked after the x pass,
+    joined before the x-inverse) give the same bits as the in-order evaluation."""
+    n = 64
+    rng = np.random.default_rng(13)
+    x = cuda(rng.standard_normal((n, n, n)))
+    ref = gs.Plan("coulomb3d", n=n, L=4.0, slab_planes=-1).eval(x)
+    plan = gs.Plan("coulomb3d", n=n, L=4.0, slab_planes=planes, slab_streams=streams)
+    info = plan.query()
+    assert info["x2_planes"] == n + 1 and info["slab_streams"] == min(streams, -(-(n + 1) // info["slab_planes"]))
+    for _ in range(3):
+        assert torch.equal(plan.eval(x), ref)
+    assert torch.equal(plan.eval_backward(x), ref)
