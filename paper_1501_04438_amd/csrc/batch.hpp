@@ -2,23 +2,22 @@
 //
 // The work of a batch is a list of tasks: a task is a run of consecutive tiles
 // (blocks of the single-problem launches) of one pass of one problem, grouped so
-// that one 256-thread block carries several small tiles at once.  The list is
+// that one 256-thread block carries several small tiles at once.  Task lists are
 // pass-major (all P1 tasks, then all P2 tasks, ...), so every task depends only
 // on tasks before it.
 //
-//   queue schedule : ONE persistent launch.  Blocks pop tasks in list order from
-//                    a device counter; before a task of pass p a block waits until
-//                    every task of the preceding pass of the same problem has
-//                    published its writes (agent-scope release/acquire on a
-//                    per-problem counter).  A block only waits on tasks popped
-//                    earlier by running blocks, so the launch cannot deadlock
-//                    whatever the number of resident blocks.  The last block to
-//                    leave clears the counters for the next launch.
+//   queue schedule : ONE persistent launch.  Each die (XCD) serves a task queue of
+//                    the problems pinned to it; before a task of pass p a block
+//                    waits until every task of the preceding pass of the same
+//                    problem is done (per-problem counters).  A block only waits on
+//                    tasks claimed earlier by running blocks of its die, so the
+//                    launch cannot deadlock whatever the number of resident blocks.
+//                    The last block to leave clears the counters for the next launch.
 //   phased schedule: one launch per pass type over the tasks of that pass; kernel
-//                    boundaries carry the dependencies.
+//                    boundaries carry the dependencies (also per pass and size).
 //
 // The tile code is the single-problem code, so every problem's result is bitwise
-// that of its own evaluation, under either schedule.
+// that of its own evaluation, under any schedule.
 #pragma once
 
 #include <hip/hip_runtime.h>
