@@ -23,14 +23,16 @@ const char* cache_path() {
     return (p && *p) ? p : nullptr;
 }
 
-// Merges the entries of the file GS_AUTOTUNE_CACHE names (when it names another
-// file than last time) as written by save(): one per line,
+// When GS_AUTOTUNE_CACHE names another file than last time (or none), the cache
+// switches to it: the entries held so far are dropped and those of the file are
+// read, as written by save(): one per line,
 //   "key": {"schedule": S, "tiles_per_task": T, "largest_first": F, "grid": G, "ms": M},
 void load() {
     const char* path = cache_path();
     const std::string now = path ? path : "";
     if (now == g_loaded_from) return;
     g_loaded_from = now;
+    g_cache.clear();
     if (!path) return;
     std::ifstream in(path);
     std::string line;

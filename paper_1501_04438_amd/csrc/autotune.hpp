@@ -3,7 +3,9 @@
 // Entries map a key (device, then the shapes of the work) to the schedule that
 // measured fastest.  The cache lives in the process; if GS_AUTOTUNE_CACHE names
 // a file, it is read from there on first use and rewritten after every new entry
-// (a flat JSON object, written by this file only).
+// (a flat JSON object, written by this file only).  Pointing GS_AUTOTUNE_CACHE at
+// another file (or unsetting it) switches to that file's entries (or to an empty
+// cache in the process).
 #pragma once
 
 #include <string>

@@ -71,7 +71,7 @@ template <int N> __host__ __device__ constexpr int tile_threads(int pass) {
     return (pass == 1 || pass == 5) ? Geo<N>::TX : (pass == 3 ? Geo<N>::TZ : Geo<N>::TY);
 }
 template <int N> __host__ __device__ constexpr int tile_lds(int pass) {
-    return ((pass == 1 || pass == 5) ? Geo<N>::PPX : (pass == 3 ? 2 * Geo<N>::PPZ : Geo<N>::PPY)) * Geo<N>::A;
+    return pass == 3 ? 2 * Geo<N>::PPZ * Geo<N>::AZ : ((pass == 1 || pass == 5) ? Geo<N>::PPX : Geo<N>::PPY) * Geo<N>::A;
 }
 template <int N> __host__ __device__ inline int tile_count(int pass, int d) {
     using Gm = Geo<N>;

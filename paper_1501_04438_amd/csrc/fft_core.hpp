@@ -190,11 +190,13 @@ template <int S, bool INV> struct Dft<16, S, INV> {
 
 // ---------------------------------------------------------------------------
 // Transform plans: length N carried by G = N/E threads with E values each, the
-// stage radices R[0..NS-1] (product N, each dividing E).
+// stage radices R[0..NS-1] (product N, each dividing E).  SLOTS selects the LDS
+// layout of the exchanges (see lds_slot).
 // ---------------------------------------------------------------------------
-template <int N_, int E_, int NS_, int R0_, int R1_ = 1, int R2_ = 1, int R3_ = 1>
+enum { SLOTS_PAD16 = 0, SLOTS_PAD8 = 1 };
+template <int N_, int E_, int NS_, int R0_, int R1_ = 1, int R2_ = 1, int R3_ = 1, int SLOTS_ = SLOTS_PAD16>
 struct FftPlan {
-    static constexpr int N = N_, E = E_, NS = NS_, G = N_ / E_;
+    static constexpr int N = N_, E = E_, NS = NS_, G = N_ / E_, SLOTS = SLOTS_;
     static constexpr int R[4] = {R0_, R1_, R2_, R3_};
 };
 
@@ -215,11 +217,11 @@ template <> struct FftCfg<512> : FftPlan<512, 8, 3, 8, 8, 8> {};
 template <> struct FftCfg<1024> : FftPlan<1024, 16, 3, 16, 16, 4> {};
 template <> struct FftCfg<2048> : FftPlan<2048, 16, 3, 16, 16, 8> {};
 
-// Plans for the fused spectrum pass, which keeps a prefetch buffer live through
-// its transforms: fewer values per thread where that matters (n = 256: 8 values,
-// radices 8, 8, 4, a 32-thread transform).
+// Plans for the fused spectrum pass, whose registers also hold the spectrum row:
+// fewer values per thread where that matters (n = 256: 8 values, radices 8, 8, 4,
+// a 32-thread transform, one LDS pad slot per 8 elements).
 template <int N> struct FftCfgFused : FftCfg<N> {};
-template <> struct FftCfgFused<256> : FftPlan<256, 8, 3, 8, 8, 4> {};
+template <> struct FftCfgFused<256> : FftPlan<256, 8, 3, 8, 8, 4, 1, SLOTS_PAD8> {};
 
 // Block barrier ordering LDS only: global loads in flight (prefetches) are not
 // drained, unlike __syncthreads(), whose workgroup fence covers global memory.
@@ -246,6 +248,22 @@ template <bool WAVE> __device__ __forceinline__ void lds_sync() {
 // the strided Stockham scatters spread over the banks.
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 template <int N> struct LdsArea { static constexpr int size = N + N / 16 + 1; };
+// Slot of element i in the LDS area of a plan C (SLOTS_PAD8: one pad slot per 8).
+// Bank rules measured on gfx950: a 16-byte LDS store serves 8 consecutive lanes per
+// cycle, which must hit distinct slots mod 8 (128 bytes); a 16-byte LDS load serves
+// 16 lanes per cycle (the lane sets of equal bit 5 and equal parity of bits 2-4),
+// which must hit distinct slots mod 16 (256 bytes).  For the 8 x 8 x 4 plan of 256
+// points (32-thread transforms, two per wave) the radix-8 scatter of the first
+// stage is then conflict-free with PAD8 and takes two cycles per lane group with
+// PAD16.  (A XOR swizzle removes the gather conflicts as well, but its addresses
+// cost registers or instructions that the fused pass cannot spare: measured slower.)
+template <class C> __host__ __device__ constexpr int lds_slot(int i) {
+    if constexpr (C::SLOTS == SLOTS_PAD8) return i + (i >> 3);
+    else return lds_pad(i);
+}
+template <class C> struct LdsAreaOf {
+    static constexpr int size = (C::SLOTS == SLOTS_PAD8) ? C::N + C::N / 8 + 1 : LdsArea<C::N>::size;
+};
 
 // v[r S] *= w^r (conj for INV), r = 1..R-1, with w^{4a+c} = (w^4)^a w^c formed from
 // w1 = w and w4 = w^4: at most three multiplications deep.
@@ -304,23 +322,23 @@ __device__ __forceinline__ void twist_out(cpx (&v)[P::E], int t, gp<const cpx> _
     }(std::make_integer_sequence<int, E>{});
 }
 
-template <int N, int E, int R, int NSPRE>
-__device__ __forceinline__ void stage_scatter(const cpx (&v)[E], int t, cpx* lds) {
-    constexpr int G = N / E, B = E / R;
+template <class C, int R, int NSPRE>
+__device__ __forceinline__ void stage_scatter(const cpx (&v)[C::E], int t, cpx* lds) {
+    constexpr int E = C::E, G = C::G, B = E / R;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int j = t + b * G;
         const int base = (j / NSPRE) * NSPRE * R + (j % NSPRE);
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NSPRE)] = v[b + r * B];
+        for (int r = 0; r < R; ++r) lds[lds_slot<C>(base + r * NSPRE)] = v[b + r * B];
     }
 }
 
-template <int N, int E>
-__device__ __forceinline__ void stage_gather(cpx (&v)[E], int t, const cpx* lds) {
-    constexpr int G = N / E;
+template <class C>
+__device__ __forceinline__ void stage_gather(cpx (&v)[C::E], int t, const cpx* lds) {
+    constexpr int E = C::E, G = C::G;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(t + G * e)];
+    for (int e = 0; e < E; ++e) v[e] = lds[lds_slot<C>(t + G * e)];
 }
 
 // Full length-N transform.  On entry thread t1 holds x[t1 + G e]; on exit thread t2
@@ -337,23 +355,23 @@ __device__ __forceinline__ void fft(cpx (&v)[C::E], int t1, cpx* lds1, int t2, c
     constexpr int R0 = C::R[0], R1 = C::R[1], R2 = C::R[2], R3 = C::R[3];
     stage_compute<N, E, R0, 1, INV>(v, t1, tw);
     if constexpr (C::NS >= 2) {
-        stage_scatter<N, E, R0, 1>(v, t1, lds1);
+        stage_scatter<C, R0, 1>(v, t1, lds1);
         lds_sync<WAVE>();
-        stage_gather<N, E>(v, t2, lds2);
+        stage_gather<C>(v, t2, lds2);
         stage_compute<N, E, R1, R0, INV>(v, t2, tw);
     }
     if constexpr (C::NS >= 3) {
         lds_sync<WAVE>();
-        stage_scatter<N, E, R1, R0>(v, t2, lds2);
+        stage_scatter<C, R1, R0>(v, t2, lds2);
         lds_sync<WAVE>();
-        stage_gather<N, E>(v, t2, lds2);
+        stage_gather<C>(v, t2, lds2);
         stage_compute<N, E, R2, R0 * R1, INV>(v, t2, tw);
     }
     if constexpr (C::NS >= 4) {
         lds_sync<WAVE>();
-        stage_scatter<N, E, R2, R0 * R1>(v, t2, lds2);
+        stage_scatter<C, R2, R0 * R1>(v, t2, lds2);
         lds_sync<WAVE>();
-        stage_gather<N, E>(v, t2, lds2);
+        stage_gather<C>(v, t2, lds2);
         stage_compute<N, E, R3, R0 * R1 * R2, INV>(v, t2, tw);
     }
 }

@@ -63,7 +63,7 @@ template <int N> struct Geo {
     using F = FftCfg<N>;          // transforms of the x and y passes
     using FZ = FftCfgFused<N>;    // transforms of the fused pass
     static constexpr int E = F::E, G = F::G, A = LdsArea<N>::size;
-    static constexpr int EZ = FZ::E, GZ = FZ::G;
+    static constexpr int EZ = FZ::E, GZ = FZ::G, AZ = LdsAreaOf<FZ>::size;
     // P1/P5: pairs of real rows per block (2*PPX rows of y, 16-byte complex each)
     static constexpr int PPX = (N <= 256) ? 8 : (N <= 512 ? 4 : (N <= 1024 ? 2 : 1));
     // P2/P4: z-pencils per block
@@ -388,7 +388,7 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
                                            cpx* lds, cpx* area) {
     using Gm = Geo<N>;
     using FZ = typename Gm::FZ;
-    constexpr int E = Gm::EZ, G = Gm::GZ, A = Gm::A;
+    constexpr int E = Gm::EZ, G = Gm::GZ, A = Gm::AZ;
     constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
     if (h) twist_in<FZ>(v, t, tw);
     fft<FZ, false, FW>(v, t, area, t, area, tw);
@@ -433,7 +433,7 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
     } else {
         lds_sync<FW>();
 #pragma unroll
-        for (int e = 0; e < E; ++e) area[lds_pad(t + G * e)] = v[e];
+        for (int e = 0; e < E; ++e) area[lds_slot<FZ>(t + G * e)] = v[e];
         lds_sync<CW>();
         if (ok) {
             const cpx* a0 = lds + (pl * 2) * A;
@@ -441,7 +441,7 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
 #pragma unroll
             for (int ee = 0; ee < E / 2; ++ee) {
                 const int j = t + G * (h * (E / 2) + ee);
-                stg<(NT & 2) != 0>(base + j, cadd(a0[lds_pad(j)], a1[lds_pad(j)]));
+                stg<(NT & 2) != 0>(base + j, cadd(a0[lds_slot<FZ>(j)], a1[lds_slot<FZ>(j)]));
             }
         }
         lds_sync<CW>();
@@ -455,7 +455,7 @@ __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const dou
                                             const DipoleArgs& dip, int g, int tid, bool active, cpx* lds) {
     using Gm = Geo<N>;
     using FZ = typename Gm::FZ;
-    constexpr int E = Gm::EZ, G = Gm::GZ, PP = Gm::PPZ, A = Gm::A;
+    constexpr int E = Gm::EZ, G = Gm::GZ, PP = Gm::PPZ, A = Gm::AZ;
     constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
     int t, h, pl;
     FusedRoles<N>::get(tid, t, h, pl);
@@ -474,7 +474,7 @@ template <int N, int DIM, int MODE, int NT = NT_P3>
 __global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ Xg, const double* __restrict__ specg,
                                                       const cpx* __restrict__ twg, int npencils, int kx0,
                                                       DipoleArgs dip) {
-    __shared__ cpx lds[Geo<N>::PPZ * 2 * Geo<N>::A];
+    __shared__ cpx lds[Geo<N>::PPZ * 2 * Geo<N>::AZ];
     const int ngroups = (npencils + Geo<N>::PPZ - 1) / Geo<N>::PPZ;
     for (int g = blockIdx.x; g < ngroups; g += gridDim.x)
         fused_group<N, DIM, MODE, NT>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg, npencils, kx0, dip,
