@@ -8,6 +8,7 @@ These are the checks the method must hit, independent of the method itself:
     a = (1, 1, gamma^2)/sigma^2 gives the anisotropic case of eq. (DensGaus).
   * 2D Coulomb of exp(-r^2/sigma^2): (sqrt(pi) sigma/2) I0(r^2/(2 sigma^2)) exp(-r^2/(2 sigma^2))
   * 2D Coulomb of exp(-(x^2 + gamma^2 y^2)/sigma^2): the integral of eq. (2.5D-clb-exact)
+    (its maximum at the origin, and its values anywhere)
   * 2D Poisson of exp(-r^2/sigma^2): -(sigma^2/4)[E1(r^2/sigma^2) + 2 ln r],
     (sigma^2/4)(gamma_e - ln sigma^2) at r = 0                                 (eq. (eg-2d-Exact))
   * 3D dipolar of exp(-r^2/sigma^2): -(n.m) rho - 3 n^T D m with the Hessian D
@@ -98,6 +99,33 @@ def anisotropic2d_max(sigma: float, gamma: float) -> float:
         g2 = mp.mpf(1) / mp.mpf(gamma) ** 2
         v = mp.quad(lambda t: 1 / (mp.sqrt(t * t + 1) * mp.sqrt(t * t + g2)), [0, 1, mp.inf])
         return float(mp.mpf(sigma) / (mp.mpf(gamma) * mp.sqrt(mp.pi)) * v)
+
+
+def coulomb2d_anisotropic(x, y, sigma: float, gamma: float, step: float = 0.1, vmax: float = 45.0):
+    """2D Coulomb potential of exp(-(x^2 + gamma^2 y^2)/sigma^2), eq. (2.5D-clb-exact):
+    (sigma/(gamma sqrt(pi))) int_0^inf exp(-x^2/(sigma^2(t^2+1)) - y^2/(sigma^2(t^2+gamma^-2)))
+    / (sqrt(t^2+1) sqrt(t^2+gamma^-2)) dt.  With t = exp(v) the integrand decays
+    exponentially at both ends and is analytic in the strip |Im v| < pi/2, so the
+    trapezoidal rule in v converges geometrically (error about exp(-pi^2/step))."""
+    x, y = (np.asarray(v, dtype=np.float64).ravel() for v in (x, y))
+    g2 = 1.0 / (gamma * gamma)
+    out = np.zeros_like(x)
+    for k in range(int(round(2.0 * vmax / step)) + 1):
+        t = math.exp(-vmax + k * step)          # nodes formed directly: no drift of the spacing
+        t2 = t * t
+        f = step * t / (math.sqrt(t2 + 1.0) * math.sqrt(t2 + g2))
+        out += f * np.exp(-x * x / (sigma * sigma * (t2 + 1.0)) - y * y / (sigma * sigma * (t2 + g2)))
+    return out * sigma / (gamma * math.sqrt(math.pi))
+
+
+def coulomb2d_anisotropic_mp(x: float, y: float, sigma: float, gamma: float) -> float:
+    """Same integral at one point by mpmath quadrature (reference for the above)."""
+    with mp.workdps(30):
+        g2 = mp.mpf(1) / mp.mpf(gamma) ** 2
+        s2 = mp.mpf(sigma) ** 2
+        f = lambda t: mp.exp(-x * x / (s2 * (t * t + 1)) - y * y / (s2 * (t * t + g2))) / (
+            mp.sqrt(t * t + 1) * mp.sqrt(t * t + g2))
+        return float(mp.mpf(sigma) / (mp.mpf(gamma) * mp.sqrt(mp.pi)) * mp.quad(f, [0, 1, 10, mp.inf]))
 
 
 def poisson2d_gaussian(r, sigma: float = 1.0):

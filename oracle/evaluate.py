@@ -15,6 +15,15 @@ Actual computation (evaluate):
 with M = (2n)^d.  The Laplacian is taken on the padded grid with the Nyquist
 mode kept (|xi| = pi/h there).
 
+Rectangular boxes (Section 2.5): the box is prod_j [-L_j, L_j] with n points on
+every axis, so h_j = 2 L_j / n and xi^(j)_k = pi k / (2 L_j); the factors of
+eq. (tensor_ani) are the one-dimensional integrals over [-2 L_j, 2 L_j] at those
+frequencies, the Laplacian symbol is sum_j (xi^(j))^2, and the Gaussian-sum
+table is fitted on the rescaled distances of that box (`gs_table`).  The
+printed phase factor of eq. (tensor_ani)'s companion formula carries a stray
+epsilon where the axis ratio eta is meant; with eta the short axis is simply an
+axis of half-width eta L, which is what per-axis half-widths express.
+
 Dipolar potential (Section 2.4): u = -(n.m) rho - 3 Coul3D(d_n d_m rho), the
 source d_n d_m rho having padded coefficients -(n.xi)(m.xi) rho~.  In the cross
 terms xi_i xi_j (i != j) the Nyquist frequency is taken as 0 (an odd symbol has
@@ -36,7 +45,7 @@ import numpy as np
 
 from . import dft
 from .factors import factor_1d
-from .gs_table import GSTable, custom_table, physical_table
+from .gs_table import GSTable, box_half_widths, custom_table, physical_table
 from .taylor import taylor_constants
 
 COULOMB_LIKE = ("coulomb3d", "coulomb2d", "poisson2d", "dipolar3d")
@@ -47,41 +56,58 @@ class OraclePlan:
     kernel: str
     d: int
     n: int
-    L: float
+    L: float                # largest half-width (the table's length unit)
     table: GSTable
-    F: np.ndarray           # (n+1, Q) one-dimensional factors
-    G_oct: np.ndarray       # (n+1)^d regular-part coefficients
+    F: np.ndarray           # (n+1, Q) one-dimensional factors of the last axis (x)
+    G_oct: np.ndarray       # (n+1)^d regular-part coefficients, array axis order
     A0: float
     c2: float
     dipole_n: tuple | None = None
     dipole_m: tuple | None = None
+    Ls: tuple = ()          # per-axis half-widths, C order (z, y, x / y, x)
+    Fs: tuple = ()          # per-axis factor matrices, C order
 
     @property
     def h(self) -> float:
+        """Grid step of a cubic box (use `hs` for rectangular ones)."""
+        if len(set(self.Ls)) > 1:
+            raise ValueError("rectangular box: the grid step differs per axis")
         return 2.0 * self.L / self.n
+
+    @property
+    def hs(self) -> tuple:
+        return tuple(2.0 * v / self.n for v in self.Ls)
+
+    @property
+    def cell(self) -> float:
+        """Volume of a grid cell, prod_j h_j."""
+        return float(np.prod(self.hs))
 
     @property
     def M(self) -> int:
         return (2 * self.n) ** self.d
 
 
-def make_plan(kernel: str, d: int, n: int, L: float, eps: float = 1e-14,
+def make_plan(kernel: str, d: int, n: int, L, eps: float = 1e-14,
               delta_rel: float = 1e-4, custom=None, dipole=None) -> OraclePlan:
+    """L: one half-width for the cube [-L, L]^d, or one per axis in C order."""
+    Ls = box_half_widths(L, d)
     if kernel == "gaussian_sum":
         w, tau = custom
-        table = custom_table(w, tau, d, L)
+        table = custom_table(w, tau, d, Ls)
     else:
-        table = physical_table(kernel, d, L, eps, delta_rel)
+        table = physical_table(kernel, d, Ls, eps, delta_rel)
         if table.d != d:
             raise ValueError("kernel and dimension disagree")
-    F = factor_1d(table.tau, 2.0 * L, n)
-    Fw = F * table.w[None, :]
+    Fs = tuple(factor_1d(table.tau, 2.0 * Lj, n) for Lj in Ls)
+    # G[i0][i1]([i2]) = sum_q w_q F_0[i0, q] F_1[i1, q] (F_2[i2, q]), array axes
+    Fw = Fs[0] * table.w[None, :]
     if d == 2:
-        G = Fw @ F.T
+        G = Fw @ Fs[1].T
     else:
         G = np.empty((n + 1,) * 3)
         for a in range(n + 1):
-            G[a] = (Fw * F[a][None, :]) @ F.T
+            G[a] = (Fw[a][None, :] * Fs[1]) @ Fs[2].T
     if kernel == "gaussian_sum":
         A0, c2 = 0.0, 0.0
     else:
@@ -89,7 +115,7 @@ def make_plan(kernel: str, d: int, n: int, L: float, eps: float = 1e-14,
     dn = dm = None
     if kernel == "dipolar3d":
         dn, dm = dipole
-    return OraclePlan(kernel, d, n, L, table, F, G, A0, c2, dn, dm)
+    return OraclePlan(kernel, d, n, table.L, table, Fs[-1], G, A0, c2, dn, dm, Ls, Fs)
 
 
 def padded_frequencies(n: int, L: float, odd: bool = False) -> np.ndarray:
@@ -118,11 +144,11 @@ def full_spectrum(plan: OraclePlan) -> np.ndarray:
 def _axes_vectors(plan: OraclePlan, odd: bool):
     """Per-axis xi arrays shaped to broadcast over the [z][y][x] (or [y][x]) grid,
     returned in vector-component order (x, y[, z])."""
-    xi = padded_frequencies(plan.n, plan.L, odd)
     d = plan.d
     out = []
     for comp in range(d):
         ax = d - 1 - comp                       # x is the last array axis
+        xi = padded_frequencies(plan.n, plan.Ls[ax], odd)
         shape = [1] * d
         shape[ax] = 2 * plan.n
         out.append(xi.reshape(shape))
@@ -199,28 +225,29 @@ def energy(plan: OraclePlan, rho: np.ndarray, u: np.ndarray | None = None) -> fl
     """Hartree-type energy 1/2 int rho u, by the grid (trapezoidal) sum."""
     if u is None:
         u = evaluate(plan, rho)
-    return 0.5 * plan.h ** plan.d * float(np.sum(rho * u))
+    return 0.5 * plan.cell * float(np.sum(rho * u))
 
 
 def energy_gradient_rho(plan: OraclePlan, rho: np.ndarray) -> np.ndarray:
     """dE/drho = 1/2 h^d (A + A^T) rho."""
-    return 0.5 * plan.h ** plan.d * (evaluate(plan, rho) + adjoint(plan, rho))
+    return 0.5 * plan.cell * (evaluate(plan, rho) + adjoint(plan, rho))
 
 
-def mixture_grid(n: int, L: float, a, mu, sigma):
+def mixture_grid(n: int, L, a, mu, sigma):
     """rho = sum_c a_c exp(-|x - mu_c|^2 / sigma_c^2) on the grid x_j = -L + j h
-    ([z][y][x] / [y][x] order, mu columns (x, y[, z])), with the per-component
-    Gaussians g_c and squared distances r2_c and offsets x_i - mu_ci it is made of."""
+    ([z][y][x] / [y][x] order, mu columns (x, y[, z]); L one half-width or one per
+    axis in C order), with the per-component Gaussians g_c and squared distances
+    r2_c and offsets x_i - mu_ci it is made of."""
     a = np.asarray(a, float)
     mu = np.asarray(mu, float)
     sigma = np.asarray(sigma, float)
     d = mu.shape[1]
-    h = 2.0 * L / n
-    ax = -L + h * np.arange(n)
+    Ls = box_half_widths(L, d)
+    axes = [-Lj + (2.0 * Lj / n) * np.arange(n) for Lj in Ls]     # array-axis order
     if d == 3:
-        X = (ax[None, None, :], ax[:, None][None], ax[:, None, None])     # x, y, z
+        X = (axes[2][None, None, :], axes[1][None, :, None], axes[0][:, None, None])   # x, y, z
     else:
-        X = (ax[None, :], ax[:, None])
+        X = (axes[1][None, :], axes[0][:, None])
     shape = (n,) * d
     rho = np.zeros(shape)
     comps = []
@@ -242,7 +269,7 @@ def energy_gradient_params(plan: OraclePlan, a, mu, sigma):
     Returns (E, dE/da (K,), dE/dmu (K, d), dE/dsigma (K,))."""
     a = np.asarray(a, float)
     sigma = np.asarray(sigma, float)
-    rho, comps = mixture_grid(plan.n, plan.L, a, mu, sigma)
+    rho, comps = mixture_grid(plan.n, plan.Ls, a, mu, sigma)
     gr = energy_gradient_rho(plan, rho)
     E = energy(plan, rho)
     K, d = len(a), plan.d

@@ -21,10 +21,13 @@ on x in [1, X], X = R/delta.  Nodes whose whole contribution on [1, X]
 the paper asks for (otherwise s_k underflows and wh_k becomes 0/0).
 
 S is the smallest value whose maximum error on 100001 log-spaced points of the
-fit interval is <= eps: relative error of 1/r on [delta, 2 sqrt(d)] (the
-paper's E_rel), absolute error of ln on [delta, 2 sqrt(2)] (E_abs), both in
-box-rescaled units (Section 2.1).  The paper writes [delta, 2]; the distance
-|y| over the box [-2,2]^d reaches 2 sqrt(d), so the interval is widened to it.
+fit interval is <= eps: relative error of 1/r on [delta, R] (the paper's E_rel),
+absolute error of ln on [delta, R] (E_abs), both in box-rescaled units
+(Section 2.1, lengths in units of the largest half-width L).  R is the largest
+distance |y| between two points of the box: 2 sqrt(d) for the cube (the paper
+writes [delta, 2]; |y| over [-2,2]^d reaches 2 sqrt(d), so the interval is
+widened to it) and 2 sqrt(sum_j (L_j/L)^2) for a rectangular box (Section 2.5,
+where the short axis is eta times the others).
 """
 
 from __future__ import annotations
@@ -81,9 +84,10 @@ def _smallest_S(err_fn, pts_full) -> int:
 _EPS_BOX = [0.0]
 
 
-def coulomb_table(d: int, delta_rel: float, eps: float, c0: float = 2.1):
-    """Smallest-S 1/r table meeting E_rel <= eps on [delta_rel, 2 sqrt(d)]."""
-    pts = np.geomspace(delta_rel, 2.0 * math.sqrt(d), NPTS)
+def coulomb_table(d: int, delta_rel: float, eps: float, c0: float = 2.1, hi: float | None = None):
+    """Smallest-S 1/r table meeting E_rel <= eps on [delta_rel, hi] (default 2 sqrt(d))."""
+    hi = 2.0 * math.sqrt(d) if hi is None else hi
+    pts = np.geomspace(delta_rel, hi, NPTS)
     _EPS_BOX[0] = eps
     S = _smallest_S(lambda S, p: coulomb_error(S, 0, 0, c0, pts=p), pts)
     w, tau = coulomb_nodes(S, c0)
@@ -120,8 +124,11 @@ def poisson_error(S: int, X: float, eps: float, c0: float = 1.0, pts=None) -> fl
     return float(np.max(np.abs(np.log(pts) - acc)))
 
 
-def poisson_table(delta_rel: float, eps: float, c0: float = 1.0):
-    X = 2.0 * math.sqrt(2.0) / delta_rel
+def poisson_table(delta_rel: float, eps: float, c0: float = 1.0, hi: float | None = None):
+    """Smallest-S ln table meeting E_abs <= eps for r in [delta_rel, hi] (default
+    2 sqrt(2)), i.e. x = r/delta_rel in [1, hi/delta_rel]."""
+    hi = 2.0 * math.sqrt(2.0) if hi is None else hi
+    X = hi / delta_rel
     pts = np.geomspace(1.0, X, NPTS)
     _EPS_BOX[0] = eps
     S = _smallest_S(lambda S, p: poisson_error(S, X, eps, c0, pts=p), pts)
@@ -139,31 +146,56 @@ class GSTable:
     delta: float         # physical near-field radius delta_rel * L
     kernel: str
     d: int
-    L: float
+    L: float             # length unit: the largest half-width of the box
 
 
-def physical_table(kernel: str, d: int, L: float, eps: float, delta_rel: float = 1e-4) -> GSTable:
-    """Table for U in physical units on the box [-L, L]^d (Section 2.1 rescaling).
+def box_half_widths(L, d: int) -> tuple:
+    """Per-axis half-widths (C order: z, y, x in 3D; y, x in 2D) from a scalar or a sequence."""
+    if np.ndim(L) == 0:
+        return (float(L),) * d
+    Ls = tuple(float(v) for v in L)
+    if len(Ls) != d:
+        raise ValueError("one half-width per axis")
+    return Ls
+
+
+def fit_interval_end(Ls) -> float:
+    """R = largest |y| over the difference box, in units of the largest half-width."""
+    Lu = max(Ls)
+    return 2.0 * math.sqrt(sum((v / Lu) ** 2 for v in Ls))
+
+
+def physical_table(kernel: str, d: int, L, eps: float, delta_rel: float = 1e-4) -> GSTable:
+    """Table for U in physical units on the box prod_j [-L_j, L_j] (Section 2.1
+    rescaling, with the largest half-width L as the length unit; Section 2.5 for
+    rectangular boxes).
 
     Coulomb: 1/r = (1/L)(1/r~) with r~ = r/L, so w = kappa w~/L, tau = tau~/L,
     kappa = 1/(4 pi) (3D) or 1/(2 pi) (2D).  Poisson: -ln(r)/(2 pi) with
     r = delta x, delta = delta_rel L: w_0 = -(ln delta + C0)/(2 pi), tau_0 = 0,
-    w_k = wh_k/(2 pi), tau_k = sqrt(s_k)/delta.
+    w_k = wh_k/(2 pi), tau_k = sqrt(s_k)/delta.  The near-field ball must fit the
+    shortest axis (Section 2.5: delta below eta): delta_rel < min_j L_j / L.
     """
+    dd = 3 if kernel in ("coulomb3d", "dipolar3d") else (2 if kernel in ("coulomb2d", "poisson2d") else d)
+    Ls = box_half_widths(L, dd)
+    L = max(Ls)
+    if not delta_rel < min(Ls) / L:
+        raise ValueError("delta_rel must be below the shortest half-width over the largest")
+    hi = fit_interval_end(Ls)
     delta = delta_rel * L
     if kernel in ("coulomb3d", "coulomb2d", "dipolar3d"):
-        dd = 3 if kernel != "coulomb2d" else 2
         kappa = 1.0 / (4.0 * math.pi) if dd == 3 else 1.0 / (2.0 * math.pi)
-        wt, tt, S = coulomb_table(dd, delta_rel, eps)
+        wt, tt, S = coulomb_table(dd, delta_rel, eps, hi=hi)
         return GSTable(kappa * wt / L, tt / L, S, delta, kernel, dd, L)
     if kernel == "poisson2d":
-        C0, wh, s, S = poisson_table(delta_rel, eps)
+        C0, wh, s, S = poisson_table(delta_rel, eps, hi=hi)
         w = np.concatenate([[-(math.log(delta) + C0) / (2.0 * math.pi)], wh / (2.0 * math.pi)])
         tau = np.concatenate([[0.0], np.sqrt(s) / delta])
         return GSTable(w, tau, S, delta, kernel, 2, L)
     raise ValueError(kernel)
 
 
-def custom_table(w, tau, d: int, L: float, kernel: str = "gaussian_sum") -> GSTable:
+def custom_table(w, tau, d: int, L, kernel: str = "gaussian_sum") -> GSTable:
     """A user-given Gaussian sum (test hook): no Taylor correction is applied."""
-    return GSTable(np.asarray(w, float), np.asarray(tau, float), len(w) - 1, 0.0, kernel, d, L)
+    return GSTable(np.asarray(w, float), np.asarray(tau, float), len(w) - 1, 0.0, kernel, d,
+                   max(box_half_widths(L, d)))

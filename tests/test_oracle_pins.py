@@ -476,3 +476,112 @@ def test_mixture_parameter_gradient_matches_discrete_difference():
             ref.append((ep - em) / (2 * hh))
     ref = np.array(ref)
     assert np.max(np.abs(got - ref)) <= 1e-7 * np.max(np.abs(ref))
+
+
+# --------------------------------------------------------------------------
+# Rectangular boxes (Section 2.5): one half-width per axis, n points per axis.
+# --------------------------------------------------------------------------
+
+def _rect_exact(p):
+    X = workloads.mesh(p.n, p.L, p.d)
+    s, g = p.extra["sigma"], p.extra["gamma"]
+    if p.d == 3:
+        x, y, z = np.broadcast_arrays(*X)
+        return cf.coulomb3d_triaxial(x, y, z, a=(1 / s ** 2, 1 / s ** 2, g * g / s ** 2)).reshape(p.rho.shape)
+    x, y = np.broadcast_arrays(X[0], X[1])
+    return cf.coulomb2d_anisotropic(x, y, s, g).reshape(p.rho.shape)
+
+
+@pytest.mark.parametrize("d,gamma,n", [(3, 2.0, 48), (3, 8.0, 48), (2, 4.0, 96), (2, 16.0, 96)])
+def test_rectangular_box_against_closed_form(d, gamma, n):
+    """Tables 3 and 5 setups (sigma = 2, box [-12,12]^(d-1) x [-12,12]/gamma): the
+    oracle meets the closed-form potential of the anisotropic Gaussian at every
+    grid point (the paper reports 5.6e-16 .. 2.6e-14 for these rows)."""
+    p = workloads.rect_box(d, gamma, n=n)
+    plan = oracle.make_plan(p.kernel, d, n, p.L)
+    u = oracle.evaluate(plan, p.rho)
+    assert relmax(u, _rect_exact(p)) < 1e-13
+
+
+def test_rectangular_box_max_norms(golden_dir):
+    """max|u| on the rectangular boxes reproduces the printed column of Tables 3 and 5."""
+    for row in _rows(os.path.join(golden_dir, "paper_max_norms.csv")):
+        d = 3 if row["kernel"] == "coulomb3d" else 2
+        g = float(row["gamma"])
+        if g == 1.0 or g == 16.0:
+            continue
+        p = workloads.rect_box(d, g, n=48 if d == 3 else 96)
+        u = oracle.evaluate(oracle.make_plan(p.kernel, d, p.n, p.L), p.rho)
+        um = float(row["umax"])
+        digits = len(row["umax"].replace("0.", "").replace(".", "").lstrip("0"))
+        assert abs(np.max(np.abs(u)) - um) <= 0.6 * 10 ** (math.floor(math.log10(um)) - digits + 1), row
+
+
+def test_anisotropic_2d_closed_form_against_mpmath():
+    for x, y, g in [(0.7, -0.3, 4.0), (0.0, 0.0, 16.0), (2.5, 0.4, 2.0), (-1.0, 1.5, 1.0)]:
+        v = cf.coulomb2d_anisotropic(np.array([x]), np.array([y]), 2.0, g)[0]
+        assert abs(v - cf.coulomb2d_anisotropic_mp(x, y, 2.0, g)) < 1e-14 * max(1.0, abs(v))
+    # gamma = 1 is the isotropic Bessel form
+    r = np.array([0.0, 0.8, 3.0])
+    v = cf.coulomb2d_anisotropic(r, np.zeros(3), 1.5, 1.0)
+    assert np.max(np.abs(v - cf.coulomb2d_gaussian(r, 1.5))) < 1e-14
+
+
+@pytest.mark.parametrize("kernel,d,eps", [("coulomb3d", 3, 1e-14), ("poisson2d", 2, 1e-12)])
+def test_rectangular_box_with_equal_sides_is_the_cube(kernel, d, eps):
+    rng = np.random.default_rng(5)
+    rho = rng.standard_normal((12,) * d)
+    a = oracle.make_plan(kernel, d, 12, 5.0, eps=eps)
+    b = oracle.make_plan(kernel, d, 12, (5.0,) * d, eps=eps)
+    assert a.table.S == b.table.S and np.array_equal(a.G_oct, b.G_oct)
+    assert np.array_equal(oracle.evaluate(a, rho), oracle.evaluate(b, rho))
+
+
+@pytest.mark.parametrize("kernel", ["coulomb3d", "dipolar3d"])
+def test_rectangular_box_axis_permutation(kernel):
+    """Reversing the axes of box and density reverses the potential (with the
+    dipole vectors' components permuted alike): a per-axis factor, frequency or
+    Laplacian term attached to the wrong axis breaks it."""
+    rng = np.random.default_rng(6)
+    n = 16
+    rho = rng.standard_normal((n,) * 3)
+    dip = ((0.3, -0.5, 0.8), (0.6, 0.2, -0.4))
+    a = oracle.make_plan(kernel, 3, n, (3.0, 4.0, 5.0), dipole=dip)
+    rdip = (tuple(dip[0][::-1]), tuple(dip[1][::-1]))
+    b = oracle.make_plan(kernel, 3, n, (5.0, 4.0, 3.0), dipole=rdip)
+    ua = oracle.evaluate(a, rho)
+    ub = oracle.evaluate(b, rho.transpose(2, 1, 0))
+    assert relmax(ub.transpose(2, 1, 0), ua) < 1e-14
+
+
+def test_rectangular_box_isotropic_gaussians():
+    """An isotropic density in a rectangular box: 3D Coulomb and dipolar (per-axis
+    frequencies in the dipolar symbol) and 2D Poisson against their closed forms."""
+    n, Ls, s = 64, (7.0, 8.0, 9.0), 1.2
+    rho = workloads.gaussian(n, Ls, 3, sigma=s)
+    X = workloads.mesh(n, Ls, 3)
+    r = np.sqrt(X[0] ** 2 + X[1] ** 2 + X[2] ** 2)
+    u = oracle.evaluate(oracle.make_plan("coulomb3d", 3, n, Ls), rho)
+    assert relmax(u, np.broadcast_to(cf.coulomb3d_gaussian(r, s), u.shape)) < 1e-13
+    dn, dm = workloads.PAPER_DIPOLE_N, workloads.PAPER_DIPOLE_M
+    u = oracle.evaluate(oracle.make_plan("dipolar3d", 3, n, Ls, dipole=(dn, dm)), rho)
+    ex = cf.dipolar3d_gaussian(X[0], X[1], X[2], dn, dm, s)
+    assert relmax(u, np.broadcast_to(ex, u.shape)) < 1e-12
+    n2, L2 = 96, (9.0, 12.0)
+    rho2 = workloads.gaussian(n2, L2, 2, sigma=s)
+    Y = workloads.mesh(n2, L2, 2)
+    r2 = np.sqrt(Y[0] ** 2 + Y[1] ** 2)
+    u2 = oracle.evaluate(oracle.make_plan("poisson2d", 2, n2, L2, eps=1e-13), rho2)
+    assert relmax(u2, np.broadcast_to(cf.poisson2d_gaussian(r2, s), u2.shape)) < 1e-13
+
+
+def test_rectangular_box_table_and_near_field_rule():
+    """The table is fitted on the distances of the box (R = 2 |L| / max L) and the
+    near-field ball must fit the short axis (delta below eta)."""
+    t = gs_table.physical_table("coulomb3d", 3, (1.5, 12.0, 12.0), 1e-14)
+    hi = 2.0 * math.sqrt(2.0 + (1.5 / 12.0) ** 2)
+    r = np.geomspace(1e-4, hi, 20001) * 12.0
+    approx = sum(wq * np.exp(-(tq * r) ** 2) for wq, tq in zip(t.w, t.tau))
+    assert np.max(np.abs(1.0 - 4.0 * math.pi * r * approx)) <= 1e-14
+    with pytest.raises(ValueError):
+        gs_table.physical_table("coulomb3d", 3, (1e-3, 12.0, 12.0), 1e-14, delta_rel=1e-4)

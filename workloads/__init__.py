@@ -9,7 +9,9 @@ Grid convention (one axis): ``x_j = -L + j*h`` with ``h = 2L/n`` and
 x the last, fastest-varying index.
 
 Workloads follow the experiments of the paper (Section 4): Gaussian densities,
-shifted and anisotropic Gaussians, and Gaussian mixtures on cubic boxes.
+shifted and anisotropic Gaussians, and Gaussian mixtures on cubic boxes, and
+anisotropic Gaussians on rectangular boxes (one half-width per axis, given in
+C order: ``(Lz, Ly, Lx)`` in 3D, ``(Ly, Lx)`` in 2D; n points on every axis).
 Random draws use ``numpy.random.default_rng(150104438 + config_id)``.
 """
 
@@ -32,14 +34,24 @@ def axis(n: int, L: float) -> np.ndarray:
     return -L + (2.0 * L / n) * np.arange(n, dtype=np.float64)
 
 
-def mesh(n: int, L: float, d: int):
+def half_widths(L, d: int) -> tuple:
+    """``(L,)*d`` for a cube, else the given per-axis half-widths (C order)."""
+    if np.ndim(L) == 0:
+        return (float(L),) * d
+    Ls = tuple(float(v) for v in L)
+    if len(Ls) != d:
+        raise ValueError("one half-width per axis")
+    return Ls
+
+
+def mesh(n: int, L, d: int):
     """Coordinate arrays (x, y[, z]) broadcastable to the ``[z][y][x]`` grid."""
-    a = axis(n, L)
+    if d not in (2, 3):
+        raise ValueError("d must be 2 or 3")
+    Ls = half_widths(L, d)
     if d == 2:
-        return a[None, :], a[:, None]
-    if d == 3:
-        return a[None, None, :], a[None, :, None], a[:, None, None]
-    raise ValueError("d must be 2 or 3")
+        return axis(n, Ls[1])[None, :], axis(n, Ls[0])[:, None]
+    return axis(n, Ls[2])[None, None, :], axis(n, Ls[1])[None, :, None], axis(n, Ls[0])[:, None, None]
 
 
 @dataclass
@@ -78,13 +90,14 @@ def sample_mixture(m: Mixture, n: int, L: float) -> np.ndarray:
     return out
 
 
-def gaussian(n: int, L: float, d: int, sigma: float = 1.0, center=None,
+def gaussian(n: int, L, d: int, sigma: float = 1.0, center=None,
              gammas=None, scale: float = 1.0) -> np.ndarray:
-    """``scale * exp(-sum_i gamma_i^2 (x_i - c_i)^2 / sigma^2)`` on the grid."""
-    ax = axis(n, L)
+    """``scale * exp(-sum_i gamma_i^2 (x_i - c_i)^2 / sigma^2)`` on the grid
+    (center and gammas in (x, y[, z]) order; L scalar or per axis in C order)."""
+    Ls = half_widths(L, d)
     center = np.zeros(d) if center is None else np.asarray(center, float)
     gammas = np.ones(d) if gammas is None else np.asarray(gammas, float)
-    f = [np.exp(-((gammas[i] * (ax - center[i])) ** 2) / sigma ** 2) for i in range(d)]
+    f = [np.exp(-((gammas[i] * (axis(n, Ls[d - 1 - i]) - center[i])) ** 2) / sigma ** 2) for i in range(d)]
     if d == 3:
         return scale * (f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :])
     return scale * (f[1][:, None] * f[0][None, :])
@@ -99,7 +112,7 @@ class Problem:
     kernel: str          # "coulomb3d" | "coulomb2d" | "poisson2d" | "dipolar3d"
     d: int
     n: int
-    L: float
+    L: float             # half-width of the cube, or per-axis half-widths (C order)
     rho: np.ndarray
     mixture: Mixture | None = None
     extra: dict = field(default_factory=dict)
@@ -156,6 +169,23 @@ def config3_dipolar(n: int = 128, paper_vectors: bool = False) -> Problem:
         dn, dm = config3_dipoles()
     rho = gaussian(n, 8.0, 3, sigma=1.2)
     return Problem("dipolar3d", 3, n, 8.0, rho, extra={"n": dn, "m": dm, "sigma": 1.2})
+
+
+def rect_box(d: int, gamma: float, n: int | None = None) -> Problem:
+    """Anisotropic examples of Section 4 on rectangular boxes: sigma = 2 and
+      3D Coulomb, exp(-(x^2 + y^2 + gamma^2 z^2)/sigma^2) on [-12,12]^2 x [-12,12]/gamma,
+         n = 96 per axis (h_x = h_y = 1/4, h_z = h_x/gamma; Table 3);
+      2D Coulomb, exp(-(x^2 + gamma^2 y^2)/sigma^2) on [-12,12] x [-12,12]/gamma,
+         n = 192 per axis (h_x = 1/8, h_y = h_x/gamma; Table 5)."""
+    if d == 3:
+        n = 96 if n is None else n
+        Ls = (12.0 / gamma, 12.0, 12.0)
+        rho = gaussian(n, Ls, 3, sigma=2.0, gammas=(1.0, 1.0, gamma))
+        return Problem("coulomb3d", 3, n, Ls, rho, extra={"sigma": 2.0, "gamma": gamma})
+    n = 192 if n is None else n
+    Ls = (12.0 / gamma, 12.0)
+    rho = gaussian(n, Ls, 2, sigma=2.0, gammas=(1.0, gamma))
+    return Problem("coulomb2d", 2, n, Ls, rho, extra={"sigma": 2.0, "gamma": gamma})
 
 
 BATCH_SIZES = (32, 48, 64, 96, 128)
