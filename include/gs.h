@@ -3,7 +3,7 @@
  *
  * The library evaluates u = U * rho (convolution over R^d, free-space
  * boundary conditions) for a density rho sampled on a uniform grid over the
- * box [-L, L]^d, with the method of Exl, Mauser and Zhang, "Accurate and
+ * box prod_j [-L_j, L_j], with the method of Exl, Mauser and Zhang, "Accurate and
  * efficient computation of nonlocal potentials based on Gaussian-sum
  * approximation": the kernel is split as U = U_GS + (U - U_GS) (Section 2.1,
  * eqs. (key_form), (GS-Gene)); the regular part is a zero-padded aperiodic FFT
@@ -13,11 +13,12 @@
  * evaluation split of Algorithm 1 is the plan / eval split below.
  *
  * Conventions shared by every entry point
- *   - Grids are cubic: n points per axis, box [-L, L]^d, spacing h = 2L/n,
- *     sample j on an axis at x_j = -L + j h, j = 0..n-1.
+ *   - Grids have n points on every axis over a box prod_j [-L_j, L_j] (a cube
+ *     when the L_j are equal; a rectangular box as in Section 2.5 otherwise):
+ *     spacing h_j = 2 L_j / n, sample i on axis j at -L_j + i h_j, i = 0..n-1.
  *   - Arrays are dense, C-ordered FP64: [z][y][x] in 3D, [y][x] in 2D, x the
  *     last (fastest) index.  `n` and `L` arguments are arrays of length d in
- *     that same order; all entries must currently be equal.
+ *     that same order; the entries of `n` must be equal.
  *   - Device pointers are HIP device memory on the plan's device, owned by the
  *     caller, and must stay valid until the work queued on the plan's stream
  *     has completed.  Calls are asynchronous with respect to the host.
@@ -74,7 +75,8 @@ typedef enum {
                                      every variant */
 
 typedef struct {
-    double delta_rel;        /* near-field radius delta / L; 0 selects 1e-4      */
+    double delta_rel;        /* near-field radius delta / max_j L_j; 0 selects 1e-4;
+                                must be below min_j L_j / max_j L_j              */
     double dipole_n[3];      /* GS_DIPOLAR_3D: orientations (x, y, z), non-zero; used as given */
     double dipole_m[3];
     const double* gs_w;      /* GS_GAUSSIAN_SUM: weights w_q (host), length gs_q  */
@@ -113,6 +115,8 @@ typedef struct {
     int fused_grid_mult;     /* rounds of co-resident blocks of the fused pass    */
     int tune_candidates;     /* variants timed when this plan was created         */
     double tuned_ms;         /* measured evaluation time of the chosen variant    */
+    double L_axes[3];        /* half-widths as given, C order (first d entries);
+                                L above is their maximum, the table's length unit */
 } gs_plan_info;
 
 /* Fill `opt` with the defaults (delta_rel 1e-4, null stream, device -1). */
@@ -120,17 +124,21 @@ void gs_options_default(gs_options* opt);
 
 /*
  * Precomputation (Algorithm 1, "Precomputation"): Gaussian-sum table by sinc
- * quadrature with the smallest S meeting `eps` on [delta, 2 sqrt(d)] in box
- * units (Section 3; relative error of 1/r, absolute error of ln r), the
- * one-dimensional factor integrals of eq. (tensor) at the padded frequencies
- * pi k/(2L), k = 0..n, the Taylor constants A0, c2 (Section 2.3), and the
- * stored spectrum octant
+ * quadrature with the smallest S meeting `eps` on [delta, R] in units of the
+ * largest half-width L (Section 3; relative error of 1/r, absolute error of
+ * ln r; R = 2 sqrt(sum_j (L_j/L)^2), the largest distance in the box: 2 sqrt(d)
+ * for a cube), the one-dimensional factor integrals of eq. (tensor) (eq.
+ * (tensor_ani) for rectangular boxes) at the padded frequencies
+ * xi = pi k/(2 L_j), k = 0..n, of every axis, the Taylor constants A0, c2
+ * (Section 2.3), and the stored spectrum octant
  *     S[k] = ( sum_q w_q prod_j g_q(xi_kj) + A0 - c2 |xi_k|^2 ) / (2n)^d,
  * assembled on the device by an FP64 matrix-core contraction.  Allocates the
  * spectrum and the evaluation workspace on the device.
  *   out     receives the plan (NULL on error).
  *   k, d    kernel family and dimension (2 or 3).
- *   n, L    length-d arrays, [z][y][x] order; equal entries; L > 0.
+ *   n, L    length-d arrays, [z][y][x] order; equal n; every L_j > 0, and
+ *           delta_rel below min_j L_j / max_j L_j (the near-field ball must fit
+ *           the shortest axis, Section 2.5).
  *   eps     target accuracy of the Gaussian sum (1e-15 <= eps < 1).
  *   opt     NULL for defaults.
  * Errors: INVALID_ARG, UNSUPPORTED_SIZE, ACCURACY, OUT_OF_MEMORY, NO_DEVICE, HIP.
@@ -148,8 +156,13 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info);
 /* Copies the Gaussian-sum table (physical units) into w[0..Q-1], tau[0..Q-1]. */
 gs_status gs_plan_table(gs_plan p, double* w, double* tau, int capacity);
 
-/* Copies the factor matrix F[k][q] = g_q(pi k/(2L)), k = 0..n, row-major (n+1) x Q. */
+/* Copies the factor matrix F[k][q] = g_q(pi k/(2L)), k = 0..n, row-major (n+1) x Q,
+ * of the x axis (the last array axis). */
 gs_status gs_plan_factors(gs_plan p, double* F, size_t capacity);
+
+/* As gs_plan_factors for array axis `axis` (0 .. d-1, C order), whose half-width
+ * L_axis gives the frequencies pi k/(2 L_axis).  INVALID_ARG for another axis. */
+gs_status gs_plan_factors_axis(gs_plan p, int axis, double* F, size_t capacity);
 
 /* Copies the stored spectrum octant ((n+1)^d FP64, scaled by 1/(2n)^d) to host
  * memory: from the device for device plans, the host assembly otherwise. */

@@ -45,15 +45,16 @@ class Plan:
     """Precomputed state for one grid and kernel (Algorithm 1, precomputation).
 
     kernel: "coulomb3d" | "coulomb2d" | "poisson2d" | "dipolar3d" | "gaussian_sum"
-    n, L:   points per axis and box half-width (cubic box [-L, L]^d)
-    eps:    Gaussian-sum accuracy; delta_rel: near-field radius / L
+    n, L:   points per axis and box half-width: one value for the cube [-L, L]^d, or
+            one per axis in array order ((Lz, Ly, Lx) / (Ly, Lx)) for a rectangular box
+    eps:    Gaussian-sum accuracy; delta_rel: near-field radius / max L (below min L / max L)
     dipole: (n_vec, m_vec) for "dipolar3d"; custom: (w, tau) for "gaussian_sum"
     autotune: time the launch variants (cache hints per pass, fused-pass grid) at plan
               creation and keep the fastest (cached per device and size; the results
               are bitwise the same for every variant)
     """
 
-    def __init__(self, kernel: str, n: int, L: float, eps: float = 1e-14, d: int | None = None,
+    def __init__(self, kernel: str, n: int, L, eps: float = 1e-14, d: int | None = None,
                  delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
                  host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0,
                  slab_streams: int = 0, autotune: bool = False):
@@ -62,7 +63,9 @@ class Plan:
         d = KERNEL_DIM.get(kernel, d)
         if d is None:
             raise ValueError("gaussian_sum plans need d")
-        self.kernel, self.d, self.n, self.L, self.eps = kernel, int(d), int(n), float(L), float(eps)
+        self.kernel, self.d, self.n, self.eps = kernel, int(d), int(n), float(eps)
+        self.Ls = _half_widths(L, self.d)
+        self.L = max(self.Ls)
         opt = GSOptions()
         lib().gs_options_default(C.byref(opt))
         opt.delta_rel = float(delta_rel)
@@ -86,7 +89,7 @@ class Plan:
             opt.gs_tau = tau.ctypes.data_as(C.POINTER(C.c_double))
             opt.gs_q = len(w)
         nn = (C.c_int64 * self.d)(*([self.n] * self.d))
-        LL = (C.c_double * self.d)(*([self.L] * self.d))
+        LL = (C.c_double * self.d)(*self.Ls)
         h = C.c_void_p()
         check(lib().gs_plan_create(C.byref(h), KERNELS[kernel], self.d, nn, LL, self.eps, C.byref(opt)))
         self._h = h
@@ -97,11 +100,25 @@ class Plan:
     def query(self) -> dict:
         info = GSPlanInfo()
         check(lib().gs_plan_query(self._h, C.byref(info)))
-        return {f: getattr(info, f) for f, _ in GSPlanInfo._fields_}
+        out = {f: getattr(info, f) for f, _ in GSPlanInfo._fields_}
+        out["L_axes"] = tuple(out["L_axes"][:self.d])
+        return out
 
     @property
     def h(self) -> float:
+        """Grid step of a cubic box (`hs` holds the per-axis steps)."""
+        if len(set(self.Ls)) > 1:
+            raise ValueError("rectangular box: the grid step differs per axis")
         return 2.0 * self.L / self.n
+
+    @property
+    def hs(self) -> tuple:
+        return tuple(2.0 * v / self.n for v in self.Ls)
+
+    @property
+    def cell(self) -> float:
+        """Grid cell volume prod_j h_j."""
+        return float(np.prod(self.hs))
 
     @property
     def shape(self):
@@ -114,9 +131,11 @@ class Plan:
                                   tau.ctypes.data_as(C.POINTER(C.c_double)), Q))
         return w, tau
 
-    def factors(self) -> np.ndarray:
+    def factors(self, axis: int | None = None) -> np.ndarray:
+        """Factor matrix (n+1, Q) of array axis `axis` (default: the last, x)."""
         F = np.empty((self.n + 1, self.info["Q"]))
-        check(lib().gs_plan_factors(self._h, F.ctypes.data_as(C.POINTER(C.c_double)), F.size))
+        ax = self.d - 1 if axis is None else int(axis)
+        check(lib().gs_plan_factors_axis(self._h, ax, F.ctypes.data_as(C.POINTER(C.c_double)), F.size))
         return F
 
     def spectrum(self) -> np.ndarray:
@@ -316,21 +335,32 @@ def potential(rho, plan: Plan):
 
 
 def energy(rho, plan: Plan):
-    """Hartree-type energy E = 1/2 int rho u, by the grid sum 1/2 h^d sum rho u."""
+    """Hartree-type energy E = 1/2 int rho u, by the grid sum 1/2 (prod_j h_j) sum rho u."""
     u = potential(rho, plan)
-    return 0.5 * plan.h ** plan.d * (rho * u).sum()
+    return 0.5 * plan.cell * (rho * u).sum()
 
 
-def mixture_density(a, mu, sigma, n: int, L: float):
+def _half_widths(L, d: int) -> tuple:
+    if np.ndim(L) == 0:
+        return (float(L),) * d
+    Ls = tuple(float(v) for v in L)
+    if len(Ls) != d:
+        raise ValueError("L: one half-width, or one per axis")
+    return Ls
+
+
+def mixture_density(a, mu, sigma, n: int, L):
     """Gaussian mixture sum_c a_c exp(-|x - mu_c|^2/sigma_c^2) on the [z][y][x] grid as a
-    differentiable torch expression (input construction for parameter gradients)."""
+    differentiable torch expression (input construction for parameter gradients).
+    L: one half-width or one per axis in array order."""
     torch = _torch()
     d = mu.shape[1]
-    ax = -L + (2.0 * L / n) * torch.arange(n, dtype=torch.float64, device=mu.device)
+    Ls = _half_widths(L, d)
+    ax = [-Lj + (2.0 * Lj / n) * torch.arange(n, dtype=torch.float64, device=mu.device) for Lj in Ls]
     if d == 3:
-        X = (ax.view(1, 1, n), ax.view(1, n, 1), ax.view(n, 1, 1))
+        X = (ax[2].view(1, 1, n), ax[1].view(1, n, 1), ax[0].view(n, 1, 1))
     else:
-        X = (ax.view(1, n), ax.view(n, 1))
+        X = (ax[1].view(1, n), ax[0].view(n, 1))
     out = 0.0
     for c in range(mu.shape[0]):
         r2 = sum((X[i] - mu[c, i]) ** 2 for i in range(d))

@@ -32,7 +32,7 @@ class GSPlanInfo(C.Structure):
                 ("spectrum_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("assembly_ms", C.c_double),
                 ("assembly_gflop", C.c_double), ("host_only", C.c_int), ("slab_planes", C.c_int),
                 ("num_steps", C.c_int), ("slab_streams", C.c_int), ("x2_planes", C.c_int), ("tuned", C.c_int), ("hint_bits", C.c_int), ("fused_grid_mult", C.c_int),
-                ("tune_candidates", C.c_int), ("tuned_ms", C.c_double)]
+                ("tune_candidates", C.c_int), ("tuned_ms", C.c_double), ("L_axes", C.c_double * 3)]
 
 
 SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3, "sized": 4}
@@ -59,6 +59,7 @@ SIGNATURES = {
     "gs_plan_query": (C.c_int, [C.c_void_p, C.POINTER(GSPlanInfo)]),
     "gs_plan_table": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int]),
     "gs_plan_factors": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_size_t]),
+    "gs_plan_factors_axis": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_size_t]),
     "gs_plan_spectrum": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_size_t]),
     "gs_plan_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gs_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

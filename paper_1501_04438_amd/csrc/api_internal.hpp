@@ -13,9 +13,11 @@
 
 struct gs_plan_s {
     int kernel = 0, d = 0, n = 0;
-    double L = 0, eps = 0, delta_rel = 0;
+    double L = 0, eps = 0, delta_rel = 0;     // L: largest half-width (the table's length unit)
+    double Lc[3] = {0, 0, 0};                 // half-widths as given, C order (z, y, x / y, x)
+    double Lk[3] = {0, 0, 0};                 // half-widths of the octant axes x, y[, z]
     gsh::Table table;
-    std::vector<double> F;
+    std::vector<double> Fk[3];                // factors (n+1) x Q of the octant axes x, y[, z]
     double A0 = 0, c2 = 0;
     std::vector<double> spec_host;
     double dn[3] = {0, 0, 0}, dm[3] = {0, 0, 0};

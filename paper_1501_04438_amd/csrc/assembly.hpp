@@ -1,13 +1,14 @@
 // assembly.hpp -- stored-spectrum assembly on the FP64 matrix cores (gfx950).
 //
 // The coefficient sums of Section 2.2 (eq. (tensor) summed with the weights as
-// in eq. (I1FFT)), with the Taylor terms of Section 2.3 folded in, on the octant
-// k_j = 0..n of the padded frequencies xi_k = pi k / (2L):
-//     S[k1][k2][k3] = ( sum_q (w_q F[k1][q]) F[k2][q] F[k3][q]
+// in eq. (I1FFT); eq. (tensor_ani) for rectangular boxes), with the Taylor terms
+// of Section 2.3 folded in, on the octant k_j = 0..n of the padded frequencies
+// xi_k = pi k / (2 L_j) of each axis:
+//     S[k1][k2][k3] = ( sum_q (w_q Fx[k1][q]) Fy[k2][q] Fz[k3][q]
 //                       + A0 - c2 (xi_k1^2 + xi_k2^2 + xi_k3^2) ) / (2n)^3
 // is a rank-Q contraction whose right operand is the Khatri-Rao product
-// B[q][(k2,k3)] = F[k2][q] F[k3][q]: a GEMM of shape (n+1) x Q x (n+1)^2 with
-// B formed in registers.  2D: S[k1][k2] with B[q][k2] = F[k2][q].
+// B[q][(k2,k3)] = Fy[k2][q] Fz[k3][q]: a GEMM of shape (n+1) x Q x (n+1)^2 with
+// B formed in registers.  2D: S[k1][k3] with B[q][k3] = Fy[k3][q] (passed as FC).
 //
 // v_mfma_f64_16x16x4f64 operand layout (one wave, lane l = 0..63):
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
@@ -24,10 +25,12 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // One wave computes a (16*MB) x 16 tile: MB row blocks of k1 against 16 columns.
 template <int MB, int DIM>
-__global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,   // [Qp][ldk]: w_q F[k][q]
-                                                  const double* __restrict__ FT,   // [Qp][ldk]: F[k][q]
+__global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,   // [Qp][ldk]: w_q Fx[k][q]
+                                                  const double* __restrict__ FB,   // [Qp][ldk]: factor of k2
+                                                  const double* __restrict__ FC,   // [Qp][ldk]: factor of k3
                                                   int ldk, int n1, int Qp, double* __restrict__ out,
-                                                  double A0, double c2, double dxi, double invM) {
+                                                  double A0, double c2, double dx1, double dx2, double dx3,
+                                                  double invM) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long ncols = (DIM == 3) ? (long)n1 * n1 : (long)n1;
     const long col0 = ((long)blockIdx.x * 4 + wave) * 16;
@@ -45,8 +48,7 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
 
     for (int q0 = 0; q0 < Qp; q0 += 4) {
         const size_t row = (size_t)(q0 + kk) * ldk;
-        const double* fq = FT + row;
-        const double b = (DIM == 3) ? fq[k2] * fq[k3] : fq[k3];
+        const double b = (DIM == 3) ? FB[row + k2] * FC[row + k3] : FC[row + k3];
         const double* aq = AT + row + k1base + i;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -57,11 +59,11 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
     if (c < ncols) {
         double xs;
         if constexpr (DIM == 3) {
-            const double x2 = (double)(c / n1) * dxi, x3 = (double)(c % n1) * dxi;
+            const double x2 = (double)(c / n1) * dx2, x3 = (double)(c % n1) * dx3;
             xs = x2 * x2 + x3 * x3;
         } else {
-            const double x2 = (double)c * dxi;
-            xs = x2 * x2;
+            const double x3 = (double)c * dx3;
+            xs = x3 * x3;
         }
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
@@ -69,7 +71,7 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
             for (int r = 0; r < 4; ++r) {
                 const int k1 = k1base + mb * 16 + kk + 4 * r;
                 if (k1 < n1) {
-                    const double x1 = (double)k1 * dxi;
+                    const double x1 = (double)k1 * dx1;
                     out[(size_t)k1 * ncols + c] = (acc[mb][r] + A0 - c2 * (x1 * x1 + xs)) * invM;
                 }
             }

@@ -60,7 +60,7 @@ void batch_problems(const std::vector<BatchMember>& m, std::vector<unsigned char
         P.X2 = reinterpret_cast<cpx*>(a.X2);
         P.spec = a.spec;
         P.tw = reinterpret_cast<const cpx*>(a.tw);
-        P.dip.dxi = a.dxi;
+        for (int i = 0; i < 3; ++i) P.dip.dxi[i] = a.dxi[i];
         for (int i = 0; i < 3; ++i) {
             P.dip.cdiag[i] = a.cdiag[i];
             P.dip.ccross[i] = a.ccross[i];

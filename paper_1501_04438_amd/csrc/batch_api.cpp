@@ -97,7 +97,7 @@ gs_status members(gs_batch_s* b, const double* const* rho, double* const* u, std
         x.X2 = a.X2;
         x.spec = a.spec;
         x.tw = a.tw;
-        x.dxi = a.dxi;
+        for (int i = 0; i < 3; ++i) x.dxi[i] = a.dxi[i];
         for (int k = 0; k < 3; ++k) {
             x.cdiag[k] = a.cdiag[k];
             x.ccross[k] = a.ccross[k];

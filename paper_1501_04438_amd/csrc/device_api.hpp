@@ -20,7 +20,7 @@ struct EvalArgs {
     const double* spec = nullptr;     // octant (n+1)^d, 1/M folded in
     const double2* tw = nullptr;      // exp(-i pi m / n), m < 2n
     int dipolar = 0;
-    double dxi = 0.0;                 // pi / (2L)
+    double dxi[3] = {0, 0, 0};        // pi / (2 L_j) of the x, y, z axes
     double cdiag[3] = {0, 0, 0};
     double ccross[3] = {0, 0, 0};
     double nm_over_M = 0.0;
@@ -39,12 +39,15 @@ hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which = -1);
 bool eval_size_supported(int d, int n);
 int eval_sizes(int d, long long* out, int cap);
 
+// Octant indices (k1, k2, k3) = (kx, ky, kz) in 3D and (k1, k3) = (kx, ky) in 2D.
 struct AssemblyArgs {
     int d = 3, n1 = 0, Qp = 0, ldk = 0;
-    const double* AT = nullptr;       // [Qp][ldk]
-    const double* FT = nullptr;       // [Qp][ldk]
+    const double* AT = nullptr;       // [Qp][ldk]: w_q F_x[k][q]
+    const double* FB = nullptr;       // [Qp][ldk]: F_y[k][q] (3D)
+    const double* FC = nullptr;       // [Qp][ldk]: F_z[k][q] (3D), F_y[k][q] (2D)
     double* out = nullptr;
-    double A0 = 0, c2 = 0, dxi = 0, invM = 0;
+    double A0 = 0, c2 = 0, invM = 0;
+    double dxi[3] = {0, 0, 0};        // pi / (2 L) of the axes of k1, k2, k3 (2D: k1, -, k3)
 };
 // Row blocks per wave chosen for n1; returns the padded k length the operands need.
 int assembly_ldk(int n1);
@@ -59,7 +62,7 @@ struct BatchMember {
     double2* X2 = nullptr;
     const double* spec = nullptr;
     const double2* tw = nullptr;
-    double dxi = 0.0, cdiag[3] = {0, 0, 0}, ccross[3] = {0, 0, 0}, nm_over_M = 0.0;
+    double dxi[3] = {0, 0, 0}, cdiag[3] = {0, 0, 0}, ccross[3] = {0, 0, 0}, nm_over_M = 0.0;
 };
 bool batch_size_supported(int d, int n);
 // packed device descriptors of the members (copy to device memory as is)

@@ -34,7 +34,7 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
     constexpr int N = GS_N;
     using Gm = Geo<N>;
     DipoleArgs dip;
-    dip.dxi = a.dxi;
+    for (int i = 0; i < 3; ++i) dip.dxi[i] = a.dxi[i];
     for (int i = 0; i < 3; ++i) {
         dip.cdiag[i] = a.cdiag[i];
         dip.ccross[i] = a.ccross[i];

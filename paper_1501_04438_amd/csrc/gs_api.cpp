@@ -79,25 +79,22 @@ gs_status device_assembly(gs_plan_s* p) {
     const int n1 = p->n + 1, Q = (int)p->table.w.size();
     const int Qp = (Q + 3) / 4 * 4;
     const int ldk = gsk::assembly_ldk(n1);
-    std::vector<double> AT((size_t)Qp * ldk, 0.0), FT((size_t)Qp * ldk, 0.0);
+    const size_t sz = (size_t)Qp * ldk;
+    // operands [Qp][ldk], transposed factors: w_q Fx (AT), then Fy, then (3D) Fz
+    const int nf = p->d - 1;                   // factor blocks after AT: y (and z)
+    std::vector<double> ops(sz * (1 + nf), 0.0);
     for (int q = 0; q < Q; ++q)
         for (int k = 0; k < n1; ++k) {
-            const double f = p->F[(size_t)k * Q + q];
-            FT[(size_t)q * ldk + k] = f;
-            AT[(size_t)q * ldk + k] = p->table.w[q] * f;
+            ops[(size_t)q * ldk + k] = p->table.w[q] * p->Fk[0][(size_t)k * Q + q];
+            for (int j = 1; j <= nf; ++j) ops[sz * j + (size_t)q * ldk + k] = p->Fk[j][(size_t)k * Q + q];
         }
-    double *dA = nullptr, *dF = nullptr;
+    double* dops = nullptr;
     hipError_t e;
-    if ((e = hipMalloc(&dA, AT.size() * 8)) != hipSuccess) return hip_fail(e, "hipMalloc(assembly)");
-    if ((e = hipMalloc(&dF, FT.size() * 8)) != hipSuccess) {
-        (void)hipFree(dA);
-        return hip_fail(e, "hipMalloc(assembly)");
-    }
+    if ((e = hipMalloc(&dops, ops.size() * 8)) != hipSuccess) return hip_fail(e, "hipMalloc(assembly)");
     gs_status st = GS_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     do {
-        if ((e = hipMemcpyAsync(dA, AT.data(), AT.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
-            (e = hipMemcpyAsync(dF, FT.data(), FT.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess) {
+        if ((e = hipMemcpyAsync(dops, ops.data(), ops.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess) {
             st = hip_fail(e, "hipMemcpy(assembly)");
             break;
         }
@@ -106,12 +103,15 @@ gs_status device_assembly(gs_plan_s* p) {
         a.n1 = n1;
         a.Qp = Qp;
         a.ldk = ldk;
-        a.AT = dA;
-        a.FT = dF;
+        a.AT = dops;
+        a.FB = dops + sz;                          // Fy
+        a.FC = dops + sz * nf;                     // Fz (3D), Fy (2D)
         a.out = p->spec;
         a.A0 = p->A0;
         a.c2 = p->c2;
-        a.dxi = M_PI / (2.0 * p->L);
+        a.dxi[0] = M_PI / (2.0 * p->Lk[0]);
+        a.dxi[1] = M_PI / (2.0 * p->Lk[1]);
+        a.dxi[2] = M_PI / (2.0 * p->Lk[p->d - 1]);
         a.invM = 1.0 / std::pow(2.0 * p->n, p->d);
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
@@ -131,8 +131,7 @@ gs_status device_assembly(gs_plan_s* p) {
     } while (false);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(dA);
-    (void)hipFree(dF);
+    (void)hipFree(dops);
     return st;
 }
 
@@ -170,7 +169,7 @@ gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) 
     a.X2 = p->X2;
     a.spec = p->spec;
     a.tw = p->tw;
-    a.dxi = M_PI / (2.0 * p->L);
+    for (int i = 0; i < 3; ++i) a.dxi[i] = p->Lk[i] > 0.0 ? M_PI / (2.0 * p->Lk[i]) : 0.0;
     a.hint_bits = p->hint_bits;
     a.fused_grid_mult = p->fused_mult;
     if (p->kernel == GS_DIPOLAR_3D) {
@@ -317,10 +316,17 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
                      : (k == GS_COULOMB_2D || k == GS_POISSON_2D) ? 2 : d;
     if (k < GS_COULOMB_3D || k > GS_GAUSSIAN_SUM) return fail(GS_ERR_INVALID_ARG, "unknown kernel");
     if (want_d != d) return fail(GS_ERR_INVALID_ARG, "kernel and dimension disagree");
+    double Lmax = 0.0, Lmin = 0.0, sum2 = 0.0;
     for (int i = 0; i < d; ++i) {
-        if (n[i] != n[0] || L[i] != L[0]) return fail(GS_ERR_INVALID_ARG, "grids must be cubic (equal n and L)");
+        if (n[i] != n[0]) return fail(GS_ERR_INVALID_ARG, "every axis must have the same n");
+        if (!(L[i] > 0.0) || !std::isfinite(L[i])) return fail(GS_ERR_INVALID_ARG, "L must be positive");
+        Lmax = std::max(Lmax, L[i]);
+        Lmin = (i == 0) ? L[i] : std::min(Lmin, L[i]);
     }
-    if (!(L[0] > 0.0) || !std::isfinite(L[0])) return fail(GS_ERR_INVALID_ARG, "L must be positive");
+    for (int i = 0; i < d; ++i) sum2 += (L[i] / Lmax) * (L[i] / Lmax);
+    // the near-field ball of the Taylor correction must fit the shortest axis
+    if (k != GS_GAUSSIAN_SUM && !(opt.delta_rel < Lmin / Lmax))
+        return fail(GS_ERR_INVALID_ARG, "delta_rel must be below the shortest half-width over the largest");
     if (n[0] < 2 || n[0] > 1 << 20) return fail(GS_ERR_INVALID_ARG, "n out of range");
     if (!(opt.delta_rel > 0.0 && opt.delta_rel < 0.5)) return fail(GS_ERR_INVALID_ARG, "delta_rel out of (0, 0.5)");
     if (k != GS_GAUSSIAN_SUM && !(eps > 0.0 && eps < 1.0)) return fail(GS_ERR_INVALID_ARG, "eps out of (0, 1)");
@@ -364,7 +370,11 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->kernel = k;
     p->d = d;
     p->n = nn;
-    p->L = L[0];
+    p->L = Lmax;
+    for (int i = 0; i < d; ++i) {
+        p->Lc[i] = L[i];
+        p->Lk[i] = L[d - 1 - i];               // octant axes x, y[, z]: C order reversed
+    }
     p->eps = eps;
     p->delta_rel = opt.delta_rel;
     p->flags = opt.flags;
@@ -376,10 +386,11 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     }
 
     bool ok = true;
+    const double hi = 2.0 * std::sqrt(sum2);   // largest distance in the box, in units of L
     if (k == GS_COULOMB_3D || k == GS_DIPOLAR_3D || k == GS_COULOMB_2D) {
-        ok = gsh::coulomb_table(d, p->L, p->delta_rel, eps, p->table);
+        ok = gsh::coulomb_table(d, p->L, hi, p->delta_rel, eps, p->table);
     } else if (k == GS_POISSON_2D) {
-        ok = gsh::poisson_table(p->L, p->delta_rel, eps, p->table);
+        ok = gsh::poisson_table(p->L, hi, p->delta_rel, eps, p->table);
     } else {
         p->table.w.assign(opt.gs_w, opt.gs_w + opt.gs_q);
         p->table.tau.assign(opt.gs_tau, opt.gs_tau + opt.gs_q);
@@ -390,7 +401,13 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         delete p;
         return fail(GS_ERR_ACCURACY, "eps not reachable by the sinc Gaussian sum");
     }
-    gsh::factors_1d(p->table.tau, p->L, nn, p->F);
+    for (int i = 0; i < d; ++i) {
+        int same = -1;
+        for (int j = 0; j < i; ++j)
+            if (p->Lk[j] == p->Lk[i]) same = j;
+        if (same >= 0) p->Fk[i] = p->Fk[same];
+        else gsh::factors_1d(p->table.tau, p->Lk[i], nn, p->Fk[i]);
+    }
     gsh::taylor_constants(k, d, p->table, p->A0, p->c2);
 
     const size_t n1 = (size_t)nn + 1;
@@ -416,7 +433,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->work_bytes = (x1 + x2) * sizeof(double2) + 2 * (size_t)nn * sizeof(double2);
 
     if (host_only) {
-        gsh::assemble_spectrum(d, nn, p->L, p->table, p->F, p->A0, p->c2, p->spec_host);
+        gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, p->spec_host);
         std::lock_guard<std::mutex> g(g_live_mu);
         g_live.insert(p);
         *out = p;
@@ -449,7 +466,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         }
         if (st == GS_OK) {
             if (opt.flags & GS_PLAN_HOST_ASSEMBLY) {
-                gsh::assemble_spectrum(d, nn, p->L, p->table, p->F, p->A0, p->c2, p->spec_host);
+                gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, p->spec_host);
                 if ((e = hipMemcpy(p->spec, p->spec_host.data(), p->spec_bytes, hipMemcpyHostToDevice)) != hipSuccess)
                     st = hip_fail(e, "hipMemcpy(spectrum)");
             } else {
@@ -499,6 +516,7 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
     info->d = p->d;
     info->n = p->n;
     info->L = p->L;
+    for (int i = 0; i < p->d; ++i) info->L_axes[i] = p->Lc[i];
     info->eps = p->eps;
     info->delta = p->table.delta;
     info->S = p->table.S;
@@ -531,11 +549,18 @@ gs_status gs_plan_table(gs_plan p, double* w, double* tau, int capacity) {
     return GS_OK;
 }
 
-gs_status gs_plan_factors(gs_plan p, double* F, size_t capacity) {
+gs_status gs_plan_factors_axis(gs_plan p, int axis, double* F, size_t capacity) {
     if (!is_live(p) || !F) return fail(GS_ERR_INVALID_ARG, "invalid plan or pointer");
-    if (capacity < p->F.size()) return fail(GS_ERR_INVALID_ARG, "capacity too small");
-    std::memcpy(F, p->F.data(), p->F.size() * sizeof(double));
+    if (axis < 0 || axis >= p->d) return fail(GS_ERR_INVALID_ARG, "axis out of range");
+    const std::vector<double>& Fa = p->Fk[p->d - 1 - axis];
+    if (capacity < Fa.size()) return fail(GS_ERR_INVALID_ARG, "capacity too small");
+    std::memcpy(F, Fa.data(), Fa.size() * sizeof(double));
     return GS_OK;
+}
+
+gs_status gs_plan_factors(gs_plan p, double* F, size_t capacity) {
+    if (!is_live(p)) return fail(GS_ERR_INVALID_ARG, "invalid plan or pointer");
+    return gs_plan_factors_axis(p, p->d - 1, F, capacity);
 }
 
 gs_status gs_plan_spectrum(gs_plan p, double* host_out, size_t capacity) {

@@ -125,21 +125,21 @@ static int smallest_S(const std::vector<double>& pts, double eps, ErrFn err_for_
 }
 
 struct TableKey {
-    int kind, d;
-    double delta_rel, eps;
+    int kind;
+    double hi, delta_rel, eps;
     bool operator<(const TableKey& o) const {
-        return std::tie(kind, d, delta_rel, eps) < std::tie(o.kind, o.d, o.delta_rel, o.eps);
+        return std::tie(kind, hi, delta_rel, eps) < std::tie(o.kind, o.hi, o.delta_rel, o.eps);
     }
 };
 static std::mutex g_cache_mu;
 static std::map<TableKey, int> g_S_cache;
 
-bool coulomb_table(int d, double L, double delta_rel, double eps, Table& out) {
-    const double lo = delta_rel, hi = 2.0 * std::sqrt((double)d);
+bool coulomb_table(int d, double L, double hi, double delta_rel, double eps, Table& out) {
+    const double lo = delta_rel;
     int S;
     {
         std::lock_guard<std::mutex> g(g_cache_mu);
-        auto it = g_S_cache.find({0, d, delta_rel, eps});
+        auto it = g_S_cache.find({0, hi, delta_rel, eps});
         S = (it == g_S_cache.end()) ? 0 : it->second;
     }
     if (S == 0) {
@@ -150,7 +150,7 @@ bool coulomb_table(int d, double L, double delta_rel, double eps, Table& out) {
             return max_err(pts, step, [&](double r) { return coulomb_err_at(w, tau, r); });
         });
         std::lock_guard<std::mutex> g(g_cache_mu);
-        g_S_cache[{0, d, delta_rel, eps}] = S;
+        g_S_cache[{0, hi, delta_rel, eps}] = S;
     }
     if (S < 0) return false;
     std::vector<double> w, tau;
@@ -198,12 +198,12 @@ static double poisson_err_at(double C0, const std::vector<double>& wh, const std
     return std::fabs(std::log(x) - acc);
 }
 
-bool poisson_table(double L, double delta_rel, double eps, Table& out) {
-    const double X = 2.0 * std::sqrt(2.0) / delta_rel;
+bool poisson_table(double L, double hi, double delta_rel, double eps, Table& out) {
+    const double X = hi / delta_rel;
     int S;
     {
         std::lock_guard<std::mutex> g(g_cache_mu);
-        auto it = g_S_cache.find({1, 2, delta_rel, eps});
+        auto it = g_S_cache.find({1, hi, delta_rel, eps});
         S = (it == g_S_cache.end()) ? 0 : it->second;
     }
     if (S == 0) {
@@ -215,7 +215,7 @@ bool poisson_table(double L, double delta_rel, double eps, Table& out) {
             return max_err(pts, step, [&](double x) { return poisson_err_at(C0, wh, s, x); });
         });
         std::lock_guard<std::mutex> g(g_cache_mu);
-        g_S_cache[{1, 2, delta_rel, eps}] = S;
+        g_S_cache[{1, hi, delta_rel, eps}] = S;
     }
     if (S < 0) return false;
     double C0;
@@ -404,32 +404,35 @@ void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2)
 
 // ------------------------------------------------------------------ host assembly
 
-void assemble_spectrum(int d, int n, double L, const Table& t, const std::vector<double>& F, double A0,
+void assemble_spectrum(int d, int n, const double* Lk, const Table& t, const std::vector<double>* Fk, double A0,
                        double c2, std::vector<double>& S) {
     const int n1 = n + 1, Q = (int)t.w.size();
-    const double dxi = PI / (2.0 * L);
+    const double dxa = PI / (2.0 * Lk[0]), dxb = PI / (2.0 * Lk[1]), dxc = PI / (2.0 * Lk[d - 1]);
+    const std::vector<double>& Fa = Fk[0];
+    const std::vector<double>& Fb = Fk[1];
+    const std::vector<double>& Fc = Fk[d - 1];
     const double invM = 1.0 / std::pow(2.0 * n, d);
     S.assign(d == 3 ? (size_t)n1 * n1 * n1 : (size_t)n1 * n1, 0.0);
     parallel_for(n1, [&](int a0, int a1) {
         std::vector<double> wa(Q);
         for (int a = a0; a < a1; ++a) {
-            for (int q = 0; q < Q; ++q) wa[q] = t.w[q] * F[(size_t)a * Q + q];
-            const double xa = a * dxi;
+            for (int q = 0; q < Q; ++q) wa[q] = t.w[q] * Fa[(size_t)a * Q + q];
+            const double xa = a * dxa;
             if (d == 2) {
                 for (int b = 0; b < n1; ++b) {
                     double acc = 0.0;
-                    for (int q = 0; q < Q; ++q) acc += wa[q] * F[(size_t)b * Q + q];
-                    const double xb = b * dxi;
+                    for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q];
+                    const double xb = b * dxb;
                     S[(size_t)a * n1 + b] = (acc + A0 - c2 * (xa * xa + xb * xb)) * invM;
                 }
                 continue;
             }
             for (int b = 0; b < n1; ++b) {
-                const double xb = b * dxi;
+                const double xb = b * dxb;
                 for (int cc = 0; cc < n1; ++cc) {
                     double acc = 0.0;
-                    for (int q = 0; q < Q; ++q) acc += wa[q] * F[(size_t)b * Q + q] * F[(size_t)cc * Q + q];
-                    const double xc = cc * dxi;
+                    for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q] * Fc[(size_t)cc * Q + q];
+                    const double xc = cc * dxc;
                     S[((size_t)a * n1 + b) * n1 + cc] = (acc + A0 - c2 * (xa * xa + xb * xb + xc * xc)) * invM;
                 }
             }

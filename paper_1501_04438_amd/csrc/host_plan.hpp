@@ -16,9 +16,11 @@ struct Table {
     double delta = 0.0;   // physical near-field radius
 };
 
-// Sinc-quadrature tables (Section 3).  Return false when eps is not reachable.
-bool coulomb_table(int d, double L, double delta_rel, double eps, Table& out);
-bool poisson_table(double L, double delta_rel, double eps, Table& out);
+// Sinc-quadrature tables (Section 3) fitted on [delta_rel, hi] in units of the
+// length Lu (the largest half-width of the box; hi = 2 |L| / Lu, the largest
+// distance in the box: 2 sqrt(d) for a cube).  False when eps is not reachable.
+bool coulomb_table(int d, double Lu, double hi, double delta_rel, double eps, Table& out);
+bool poisson_table(double Lu, double hi, double delta_rel, double eps, Table& out);
 
 // Max error of the rescaled tables on their fit interval (for tests and reports).
 double coulomb_table_error(int S, double lo, double hi);
@@ -29,8 +31,9 @@ void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<dou
 // Taylor constants of the near-field correction (Section 2.3).
 void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2);
 
-// Host assembly of the stored octant (n+1)^d, 1/(2n)^d folded in.
-void assemble_spectrum(int d, int n, double L, const Table& t, const std::vector<double>& F,
+// Host assembly of the stored octant (n+1)^d, 1/(2n)^d folded in.  Octant axes
+// (kx, ky[, kz]): Lk[i] and Fk[i] are the half-width and factors of axis x, y[, z].
+void assemble_spectrum(int d, int n, const double* Lk, const Table& t, const std::vector<double>* Fk,
                        double A0, double c2, std::vector<double>& S);
 
 // exp(-i pi m / n), m = 0..2n-1, as interleaved (re, im).

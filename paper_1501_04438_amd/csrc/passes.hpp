@@ -31,7 +31,7 @@ namespace gsk {
 enum { SPEC_PLAIN = 0, SPEC_DIPOLAR = 1 };
 
 struct DipoleArgs {
-    double dxi;          // pi / (2L): xi_k = k * dxi
+    double dxi[3];       // pi / (2 L_j) of the x, y, z axes: xi_k = k * dxi[j]
     double cdiag[3];     // 3 n_i m_i                    (x, y, z)
     double ccross[3];    // 3 (n_i m_j + n_j m_i)        (xy, xz, yz)
     double nm_over_M;    // (n.m) / (2n)^3
@@ -396,16 +396,16 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
         // (n.xi)(m.xi) with Nyquist taken as 0 in the odd (cross) factors
         const int kx = (DIM == 3) ? kx0 + pencil / (2 * N) : pencil;
         const int ky = (DIM == 3) ? pencil % (2 * N) : 0;
-        const double xe = kx * dip.dxi;
+        const double xe = kx * dip.dxi[0];
         const int sy = ky < N ? ky : ky - 2 * N;
-        const double ye = sy * dip.dxi;
+        const double ye = sy * dip.dxi[1];
         const double xo = (kx == N) ? 0.0 : xe;
         const double yo = (ky == N) ? 0.0 : ye;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int m = 2 * (t + G * e) + h;
             const int sz = m < N ? m : m - 2 * N;
-            const double ze = sz * dip.dxi;
+            const double ze = sz * dip.dxi[2];
             const double zo = (m == N) ? 0.0 : ze;
             const double f = dip.cdiag[0] * xe * xe + dip.cdiag[1] * ye * ye + dip.cdiag[2] * ze * ze +
                              dip.ccross[0] * xo * yo + dip.ccross[1] * xo * zo + dip.ccross[2] * yo * zo;

@@ -37,15 +37,15 @@ def test_nm_exports_c_symbols():
     assert set(header_functions()) <= exported
 
 
-def _create(kernel=0, d=3, n=16, L=4.0, eps=1e-14, flags=_lib.PLAN_HOST_ONLY, **kw):
+def _create(kernel=0, d=3, n=16, L=4.0, eps=1e-14, flags=_lib.PLAN_HOST_ONLY, nlist=None, **kw):
     opt = _lib.GSOptions()
     _lib.lib().gs_options_default(C.byref(opt))
     opt.flags = flags
     for k, v in kw.items():
         setattr(opt, k, v)
     h = C.c_void_p()
-    nn = (C.c_int64 * d)(*([n] * d))
-    LL = (C.c_double * d)(*([L] * d))
+    nn = (C.c_int64 * d)(*(nlist if nlist is not None else [n] * d))
+    LL = (C.c_double * d)(*(L if isinstance(L, (tuple, list)) else [L] * d))
     st = _lib.lib().gs_plan_create(C.byref(h), kernel, d, nn, LL, eps, C.byref(opt))
     return st, h
 
@@ -69,6 +69,19 @@ def test_argument_validation_statuses():
     assert _create(kernel=4, d=3)[0] == 1                # custom sum missing
     msg = _lib.lib().gs_last_error().decode()
     assert "custom" in msg
+    assert _create(nlist=[16, 16, 32])[0] == 1           # n must agree on every axis
+    assert _create(L=(4.0, 4.0, -1.0))[0] == 1
+    assert _create(L=(1e-4, 4.0, 4.0))[0] == 1           # near-field ball wider than the short axis
+    assert "shortest" in _lib.lib().gs_last_error().decode()
+    st, h = _create(L=(1.0, 2.0, 4.0))                   # rectangular box
+    assert st == 0
+    info = _lib.GSPlanInfo()
+    assert _lib.lib().gs_plan_query(h, C.byref(info)) == 0
+    assert info.L == 4.0 and tuple(info.L_axes) == (1.0, 2.0, 4.0)
+    F = (C.c_double * (17 * info.Q))()
+    assert _lib.lib().gs_plan_factors_axis(h, 3, F, len(F)) == 1
+    assert _lib.lib().gs_plan_factors_axis(h, 0, F, len(F)) == 0
+    assert _lib.lib().gs_plan_destroy(h) == 0
 
 
 def test_no_device_and_workspace_cap():

@@ -287,3 +287,84 @@ def test_concurrent_slab_chains_change_nothing(planes, streams):
     for _ in range(3):
         assert torch.equal(plan.eval(x), ref)
     assert torch.equal(plan.eval_backward(x), ref)
+
+
+# --------------------------------------------------------------------------
+# Rectangular boxes (Section 2.5): one half-width per axis (array order).
+# --------------------------------------------------------------------------
+
+RECT_3D = [("coulomb3d", 12, (2.0, 3.0, 5.0)), ("coulomb3d", 48, (1.5, 12.0, 12.0)),
+           ("coulomb3d", 24, (6.0, 4.0, 2.5)), ("dipolar3d", 16, (5.0, 4.0, 3.0)),
+           ("dipolar3d", 32, (8.0, 8.0, 2.0))]
+
+
+@pytest.mark.parametrize("kernel,n,Ls", RECT_3D)
+def test_rectangular_box_3d_random_input(kernel, n, Ls):
+    rng = np.random.default_rng(300 + n)
+    rho = rng.standard_normal((n, n, n))
+    dip = ((0.3, -0.5, 0.8), (0.6, 0.2, -0.4)) if kernel == "dipolar3d" else None
+    plan = gs.Plan(kernel, n=n, L=Ls, dipole=dip)
+    assert plan.query()["L_axes"] == Ls
+    ref = oracle.evaluate(oracle.make_plan(kernel, 3, n, Ls, dipole=dip), rho)
+    assert relmax(gpu_eval(plan, rho), ref) <= TOL
+
+
+@pytest.mark.parametrize("kernel,n,Ls", [("coulomb2d", 96, (0.75, 12.0)), ("poisson2d", 64, (9.0, 6.0)),
+                                          ("coulomb2d", 48, (3.0, 5.0))])
+def test_rectangular_box_2d_random_input(kernel, n, Ls):
+    rng = np.random.default_rng(400 + n)
+    rho = rng.standard_normal((n, n))
+    eps = 1e-13 if kernel == "poisson2d" else 1e-14
+    plan = gs.Plan(kernel, n=n, L=Ls, eps=eps)
+    ref = oracle.evaluate(oracle.make_plan(kernel, 2, n, Ls, eps=eps), rho)
+    assert relmax(gpu_eval(plan, rho), ref) <= TOL
+
+
+@pytest.mark.parametrize("d,gamma", [(3, 2.0), (3, 4.0), (3, 8.0), (2, 2.0), (2, 8.0), (2, 16.0)])
+def test_rectangular_box_paper_setups(d, gamma):
+    """Tables 3 (96^3) and 5 (192^2) at full size: the oracle at sampled planes,
+    the closed form at every grid point, and the printed max|u|."""
+    from oracle import closed_forms as cf
+    p = workloads.rect_box(d, gamma)
+    plan = gs.Plan(p.kernel, n=p.n, L=p.L)
+    u = gpu_eval(plan, p.rho)
+    ref = oracle.evaluate(oracle.make_plan(p.kernel, d, p.n, p.L), p.rho)
+    assert relmax(u, ref) <= TOL
+    X = np.broadcast_arrays(*workloads.mesh(p.n, p.L, d))
+    s = p.extra["sigma"]
+    if d == 3:
+        ex = cf.coulomb3d_triaxial(X[0], X[1], X[2], a=(1 / s ** 2, 1 / s ** 2, gamma ** 2 / s ** 2))
+        umax = cf.anisotropic3d_max(s, gamma)
+    else:
+        ex = cf.coulomb2d_anisotropic(X[0], X[1], s, gamma)
+        umax = cf.anisotropic2d_max(s, gamma)
+    assert relmax(u, ex.reshape(u.shape)) <= 1e-13
+    assert abs(np.max(np.abs(u)) - umax) <= 1e-13 * umax
+
+
+def test_rectangular_box_device_assembly_equals_host():
+    for kernel, n, Ls in [("coulomb3d", 24, (1.5, 6.0, 4.0)), ("coulomb2d", 64, (2.0, 9.0))]:
+        d = len(Ls)
+        dev = gs.Plan(kernel, n=n, L=Ls).spectrum()
+        host = gs.Plan(kernel, n=n, L=Ls, host_only=True).spectrum()
+        assert np.max(np.abs(dev - host)) <= 1e-14 * np.max(np.abs(host))
+
+
+def test_rectangular_box_gradient_and_batch():
+    """Autograd on a rectangular box (grad of 1/2 sum cell rho u is cell * u) and a
+    rectangular plan inside a batch (bitwise equal to its own evaluation)."""
+    Ls = (2.0, 3.0, 4.0)
+    rng = np.random.default_rng(9)
+    plan = gs.Plan("coulomb3d", n=24, L=Ls)
+    rho = cuda(rng.standard_normal((24, 24, 24))).requires_grad_(True)
+    E = gs.energy(rho, plan)
+    E.backward()
+    u = plan.eval(rho.detach())
+    torch.cuda.synchronize()
+    # signed input: compare in the max norm (elementwise ratios are ill-posed near zeros)
+    assert relmax(rho.grad.cpu().numpy(), (plan.cell * u).cpu().numpy()) <= 1e-13
+    other = gs.Plan("coulomb3d", n=32, L=5.0)
+    rho2 = cuda(rng.standard_normal((32, 32, 32)))
+    outs = gs.eval_batch([plan, other], [rho.detach(), rho2])
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], u) and torch.equal(outs[1], other.eval(rho2))

@@ -9,14 +9,23 @@ import paper_1501_04438_amd as gs
 
 
 def _octant_ref(op):
-    n, L, d = op.n, op.L, op.d
-    xi = oracle.padded_frequencies(n, L)[: n + 1]
-    lap = sum(np.expand_dims(xi ** 2, tuple(j for j in range(d) if j != i)) for i in range(d))
-    return (op.G_oct + op.A0 - op.c2 * lap) / (2 * n) ** d
+    """The library's stored octant, indexed [kx][ky]([kz]) (axes reversed from the
+    oracle's array-order G), with the Taylor terms and 1/M folded in."""
+    n, d = op.n, op.d
+    lap = 0.0
+    for i in range(d):                          # octant axis i = array axis d-1-i
+        xi = oracle.padded_frequencies(n, op.Ls[d - 1 - i])[: n + 1]
+        lap = lap + np.expand_dims(xi ** 2, tuple(j for j in range(d) if j != i))
+    G = op.G_oct.transpose(tuple(range(d - 1, -1, -1)))
+    return (G + op.A0 - op.c2 * lap) / (2 * n) ** d
 
 
 CASES = [("coulomb3d", 3, 16, 8.0, 1e-14), ("coulomb3d", 3, 24, 10.0, 1e-14), ("coulomb2d", 2, 64, 12.0, 1e-14),
-         ("poisson2d", 2, 64, 12.0, 1e-13), ("poisson2d", 2, 48, 3.0, 1e-13), ("dipolar3d", 3, 12, 8.0, 1e-14)]
+         ("poisson2d", 2, 64, 12.0, 1e-13), ("poisson2d", 2, 48, 3.0, 1e-13), ("dipolar3d", 3, 12, 8.0, 1e-14),
+         # rectangular boxes (Section 2.5), half-widths in array order
+         ("coulomb3d", 3, 16, (1.5, 12.0, 12.0), 1e-14), ("coulomb3d", 3, 12, (3.0, 4.0, 5.0), 1e-14),
+         ("coulomb2d", 2, 48, (0.75, 12.0), 1e-14), ("poisson2d", 2, 32, (6.0, 9.0), 1e-13),
+         ("dipolar3d", 3, 12, (5.0, 4.0, 3.0), 1e-14)]
 
 
 @pytest.mark.parametrize("kernel,d,n,L,eps", CASES)
@@ -27,9 +36,12 @@ def test_host_plan_matches_oracle(kernel, d, n, L, eps):
     assert p.info["S"] == op.table.S
     w, tau = p.table()
     assert np.max(np.abs(w - op.table.w)) <= 2e-15 * np.max(np.abs(w))
-    assert np.max(np.abs(tau - op.table.tau)) <= 2e-16 * np.max(tau)
-    F = p.factors()
-    assert np.max(np.abs(F - op.F)) <= 5e-14 * 4 * L
+    # tau = sqrt(s)/delta rounds independently on both sides: two ulps of the largest
+    assert np.max(np.abs(tau - op.table.tau)) <= 4.5e-16 * np.max(tau)
+    for ax in range(d):
+        F = p.factors(ax)
+        assert np.max(np.abs(F - op.Fs[ax])) <= 5e-14 * 4 * op.Ls[ax]
+    assert np.array_equal(p.factors(), p.factors(d - 1))
     # A0 and c2 are differences of moments of size delta^2 and delta^4 (physical
     # delta); compare on that scale (their effect on u is A0 rho + c2 Lap rho)
     dl = p.info["delta"]
