@@ -11,6 +11,7 @@ These are the checks the method must hit, independent of the method itself:
     (its maximum at the origin, and its values anywhere)
   * 2D Poisson of exp(-r^2/sigma^2): -(sigma^2/4)[E1(r^2/sigma^2) + 2 ln r],
     (sigma^2/4)(gamma_e - ln sigma^2) at r = 0                                 (eq. (eg-2d-Exact))
+  * Davey-Stewartson potential of pi exp(-pi^2 r^2) (Example 4.5)
   * 3D dipolar of exp(-r^2/sigma^2): -(n.m) rho - 3 n^T D m with the Hessian D
     of the Coulomb potential (Example 4.4)
   * the 1-D factor integral in closed form, (sqrt(pi)/tau) exp(-xi^2/4tau^2)
@@ -126,6 +127,31 @@ def coulomb2d_anisotropic_mp(x: float, y: float, sigma: float, gamma: float) -> 
         f = lambda t: mp.exp(-x * x / (s2 * (t * t + 1)) - y * y / (s2 * (t * t + g2))) / (
             mp.sqrt(t * t + 1) * mp.sqrt(t * t + g2))
         return float(mp.mpf(sigma) / (mp.mpf(gamma) * mp.sqrt(mp.pi)) * mp.quad(f, [0, 1, 10, mp.inf]))
+
+
+def davey_stewartson_gaussian(x, y):
+    """Davey-Stewartson potential (-ln|x|/(2 pi)) * d_xx rho of rho = pi exp(-pi^2 (x^2+y^2))
+    (Example 4.5): -(pi/2) e^{-a} - cos(2 theta) e^{-a} (1 + a - e^a)/(2 pi r^2), a = pi^2 r^2,
+    with cos(2 theta) = (x^2 - y^2)/r^2.  Near r = 0, (1 + a - e^a)/r^2 is summed as a series
+    (-pi^2 a (1/2 + a/6 + a^2/24 + ...))."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    r2 = x * x + y * y
+    a = math.pi ** 2 * r2
+    small = a < 0.5
+    eq = np.empty_like(a)                              # e^{-a} (1 + a - e^a) / r^2
+    big = ~small
+    eq[big] = ((1.0 + a[big]) * np.exp(-a[big]) - 1.0) / r2[big]
+    asm = a[small]
+    ser = np.zeros_like(asm)
+    term = np.full_like(asm, 0.5)                      # a^k / (k+2)!
+    for k in range(1, 30):
+        ser += term
+        term = term * asm / (k + 2)
+    eq[small] = -math.pi ** 2 * asm * ser * np.exp(-asm)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        c2t = np.where(r2 > 0, (x * x - y * y) / np.where(r2 > 0, r2, 1.0), 0.0)
+    return -(0.5 * math.pi * np.exp(-a) + c2t * eq / (2.0 * math.pi))
 
 
 def poisson2d_gaussian(r, sigma: float = 1.0):

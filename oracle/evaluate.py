@@ -25,7 +25,10 @@ epsilon where the axis ratio eta is meant; with eta the short axis is simply an
 axis of half-width eta L, which is what per-axis half-widths express.
 
 Dipolar potential (Section 2.4): u = -(n.m) rho - 3 Coul3D(d_n d_m rho), the
-source d_n d_m rho having padded coefficients -(n.xi)(m.xi) rho~.  In the cross
+source d_n d_m rho having padded coefficients -(n.xi)(m.xi) rho~.  Davey-Stewartson
+potential (the remark closing Section 2.4 and Example 4.5): u = Poisson2D(d_xx rho),
+the source having padded coefficients -xi_x^2 rho~ (an even symbol: the Nyquist
+frequency keeps pi/h_x).  In the cross
 terms xi_i xi_j (i != j) the Nyquist frequency is taken as 0 (an odd symbol has
 no value there that keeps the result real); squares keep (pi/h)^2.
 
@@ -48,7 +51,7 @@ from .factors import factor_1d
 from .gs_table import GSTable, box_half_widths, custom_table, physical_table
 from .taylor import taylor_constants
 
-COULOMB_LIKE = ("coulomb3d", "coulomb2d", "poisson2d", "dipolar3d")
+COULOMB_LIKE = ("coulomb3d", "coulomb2d", "poisson2d", "dipolar3d", "davey_stewartson2d")
 
 
 @dataclass
@@ -186,10 +189,20 @@ def _coulomb_steps(plan: OraclePlan, rt: np.ndarray, f: np.ndarray, sign: int = 
     return I1 + plan.A0 * f + plan.c2 * lap
 
 
+def ds_symbol(plan: OraclePlan) -> np.ndarray:
+    """-xi_x^2 on the padded grid: the symbol of d_xx (x the last array axis)."""
+    xs = _axes_vectors(plan, odd=False)
+    return -(xs[0] * xs[0])
+
+
 def evaluate(plan: OraclePlan, rho: np.ndarray) -> np.ndarray:
     rho = np.asarray(rho, dtype=np.float64)
     assert rho.shape == (plan.n,) * plan.d
     rt = dft.forward(rho)
+    if plan.kernel == "davey_stewartson2d":
+        src_t = ds_symbol(plan) * rt
+        src = dft.inverse(src_t).real / plan.M
+        return _coulomb_steps(plan, src_t, src)
     if plan.kernel != "dipolar3d":
         return _coulomb_steps(plan, rt, rho)
     src_t = -dipolar_symbol(plan) * rt
@@ -204,6 +217,10 @@ def adjoint(plan: OraclePlan, v: np.ndarray) -> np.ndarray:
     v = np.asarray(v, dtype=np.float64)
     vt = dft.forward(v, sign=+1)                  # transpose of the crop-inverse
     M = plan.M
+    if plan.kernel == "davey_stewartson2d":
+        # transpose of rho -> [I1 + A0 f + c2 Lap f](f = d_xx rho)
+        w1 = full_spectrum(plan) * vt - plan.c2 * laplacian_symbol(plan) * vt + plan.A0 * vt
+        return dft.inverse(ds_symbol(plan) * w1, sign=-1).real / M
     if plan.kernel != "dipolar3d":
         G = full_spectrum(plan)
         out = dft.inverse(G * vt, sign=-1).real / M

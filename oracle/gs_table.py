@@ -176,7 +176,8 @@ def physical_table(kernel: str, d: int, L, eps: float, delta_rel: float = 1e-4) 
     w_k = wh_k/(2 pi), tau_k = sqrt(s_k)/delta.  The near-field ball must fit the
     shortest axis (Section 2.5: delta below eta): delta_rel < min_j L_j / L.
     """
-    dd = 3 if kernel in ("coulomb3d", "dipolar3d") else (2 if kernel in ("coulomb2d", "poisson2d") else d)
+    dd = 3 if kernel in ("coulomb3d", "dipolar3d") else (
+        2 if kernel in ("coulomb2d", "poisson2d", "davey_stewartson2d") else d)
     Ls = box_half_widths(L, dd)
     L = max(Ls)
     if not delta_rel < min(Ls) / L:
@@ -187,7 +188,8 @@ def physical_table(kernel: str, d: int, L, eps: float, delta_rel: float = 1e-4) 
         kappa = 1.0 / (4.0 * math.pi) if dd == 3 else 1.0 / (2.0 * math.pi)
         wt, tt, S = coulomb_table(dd, delta_rel, eps, hi=hi)
         return GSTable(kappa * wt / L, tt / L, S, delta, kernel, dd, L)
-    if kernel == "poisson2d":
+    if kernel in ("poisson2d", "davey_stewartson2d"):
+        # the Davey-Stewartson potential convolves the same logarithmic kernel
         C0, wh, s, S = poisson_table(delta_rel, eps, hi=hi)
         w = np.concatenate([[-(math.log(delta) + C0) / (2.0 * math.pi)], wh / (2.0 * math.pi)])
         tau = np.concatenate([[0.0], np.sqrt(s) / delta])

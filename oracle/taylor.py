@@ -40,7 +40,7 @@ def _u_moment(kernel: str, m: int, delta):
         return dl ** m / (4 * mp.pi * m)                 # int r^{m-1}/(4 pi) dr
     if kernel == "coulomb2d":
         return dl ** m / (2 * mp.pi * m)
-    if kernel == "poisson2d":
+    if kernel in ("poisson2d", "davey_stewartson2d"):
         # -(1/2pi) int_0^delta r^m ln r dr = -(1/2pi) [delta^{m+1}(ln delta/(m+1) - 1/(m+1)^2)]
         a = m + 1
         return -(dl ** a) * (mp.log(dl) / a - mp.mpf(1) / a ** 2) / (2 * mp.pi)

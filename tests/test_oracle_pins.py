@@ -36,6 +36,8 @@ def _exact(kernel, n, L, sigma, x0):
     if kernel == "dipolar3d":
         return cf.dipolar3d_gaussian(X[0], X[1], X[2], workloads.PAPER_DIPOLE_N,
                                      workloads.PAPER_DIPOLE_M, sigma)
+    if kernel == "davey_stewartson2d":
+        return cf.davey_stewartson_gaussian(*np.broadcast_arrays(X[0] - x0[0], X[1] - x0[1]))
     r = np.sqrt(sum((X[i] - x0[i]) ** 2 for i in range(d)))
     return {"coulomb3d": cf.coulomb3d_gaussian, "coulomb2d": cf.coulomb2d_gaussian,
             "poisson2d": cf.poisson2d_gaussian}[kernel](r, sigma)
@@ -53,10 +55,11 @@ def test_paper_table_error(row):
     kernel, L, n, sigma = row["kernel"], float(row["L"]), int(row["n"]), float(row["sigma"])
     d = 3 if kernel.endswith("3d") else 2
     x0 = [float(row["x0"]), float(row["y0"]), float(row["z0"])][:d]
-    eps = 1e-13 if kernel == "poisson2d" else 1e-14
+    eps = 1e-13 if kernel in ("poisson2d", "davey_stewartson2d") else 1e-14
     dip = (workloads.PAPER_DIPOLE_N, workloads.PAPER_DIPOLE_M) if kernel == "dipolar3d" else None
     plan = oracle.make_plan(kernel, d, n, L, eps=eps, dipole=dip)
-    rho = workloads.gaussian(n, L, d, sigma=sigma, center=x0)
+    scale = math.pi if kernel == "davey_stewartson2d" else 1.0
+    rho = workloads.gaussian(n, L, d, sigma=sigma, center=x0, scale=scale)
     E = relmax(oracle.evaluate(plan, rho), _exact(kernel, n, L, sigma, x0))
     Ep = float(row["E_paper"])
     if row["check"] == "rel":
@@ -585,3 +588,44 @@ def test_rectangular_box_table_and_near_field_rule():
     assert np.max(np.abs(1.0 - 4.0 * math.pi * r * approx)) <= 1e-14
     with pytest.raises(ValueError):
         gs_table.physical_table("coulomb3d", 3, (1e-3, 12.0, 12.0), 1e-14, delta_rel=1e-4)
+
+
+# --------------------------------------------------------------------------
+# Davey-Stewartson potential (Example 4.5): Poisson kernel convolved with d_xx rho.
+# --------------------------------------------------------------------------
+
+def test_davey_stewartson_closed_form_against_mpmath():
+    def direct(x, y):
+        with mp.workdps(40):
+            x, y = mp.mpf(x), mp.mpf(y)
+            r2 = x * x + y * y
+            if r2 == 0:
+                return float(-mp.pi / 2)
+            a = mp.pi ** 2 * r2
+            return float(-(mp.pi / 2 * mp.e ** (-a)
+                           + (x * x - y * y) / r2 * mp.e ** (-a) * (1 + a - mp.e ** a) / (2 * mp.pi * r2)))
+    for x, y in [(0.0, 0.0), (0.05, 0.02), (0.1, 0.12), (0.3, -0.4), (0.7, 0.1), (1.2, 0.9), (3.0, 0.5), (-6.0, 2.0)]:
+        v = cf.davey_stewartson_gaussian(np.array([x]), np.array([y]))[0]
+        assert abs(v - direct(x, y)) <= 1e-15 * max(1.0, abs(v)), (x, y)
+
+
+def test_davey_stewartson_xx_plus_yy_is_minus_rho():
+    """d_xx + d_yy = Laplacian and -Laplacian of the Poisson kernel is the delta function:
+    DS(rho) + (the same with x and y exchanged) = -rho, independently of the closed form
+    (a wrong sign or axis of the symbol, or a lost Taylor term, breaks it)."""
+    n, L = 128, 6.0
+    rho = workloads.gaussian(n, L, 2, sigma=0.8, center=(0.3, -0.5)) - 0.5 * workloads.gaussian(n, L, 2, sigma=0.6)
+    plan = oracle.make_plan("davey_stewartson2d", 2, n, L, eps=1e-13)
+    uxx = oracle.evaluate(plan, rho)
+    uyy = oracle.evaluate(plan, rho.T.copy()).T
+    assert relmax(uxx + uyy, -rho) < 1e-12
+
+
+def test_davey_stewartson_adjoint_and_symmetry():
+    rng = np.random.default_rng(11)
+    n = 16
+    plan = oracle.make_plan("davey_stewartson2d", 2, n, 4.0, eps=1e-13)
+    a, b = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    Aa, ATb = oracle.evaluate(plan, a), oracle.adjoint(plan, b)
+    assert abs(np.sum(Aa * b) - np.sum(a * ATb)) <= 1e-13 * np.sqrt(np.sum(Aa ** 2) * np.sum(b ** 2))
+    assert relmax(oracle.adjoint(plan, a), Aa) < 1e-13
