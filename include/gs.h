@@ -41,14 +41,18 @@ extern "C" {
 
 typedef struct gs_plan_s* gs_plan;
 
-/* Kernel families (Section 1, eq. (kernelPhy); dipolar kernel, Section 2.4). */
+/* Kernel families (Section 1, eq. (kernelPhy); dipolar kernel, Section 2.4;
+ * Davey-Stewartson potential, the remark closing Section 2.4 and Example 4.5). */
 typedef enum {
     GS_COULOMB_3D = 0,    /* U = 1/(4 pi |x|),                       d = 3 */
     GS_COULOMB_2D = 1,    /* U = 1/(2 pi |x|),                       d = 2 */
     GS_POISSON_2D = 2,    /* U = -ln|x| / (2 pi),                    d = 2 */
     GS_DIPOLAR_3D = 3,    /* u = -(n.m) rho - 3 Coulomb3D(d_n d_m rho), d = 3 */
-    GS_GAUSSIAN_SUM = 4   /* U = sum_q w_q exp(-tau_q^2 |x|^2) from gs_options,
+    GS_GAUSSIAN_SUM = 4,  /* U = sum_q w_q exp(-tau_q^2 |x|^2) from gs_options,
                              no near-field term (test hook), d = 2 or 3 */
+    GS_DAVEY_STEWARTSON_2D = 5  /* u = (-ln|x| / (2 pi)) * d_xx rho, d = 2: the Poisson
+                             table and Taylor terms, the d_xx symbol -xi_x^2 (even,
+                             Nyquist kept) folded into the stored spectrum */
 } gs_kernel;
 
 typedef enum {

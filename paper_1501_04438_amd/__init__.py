@@ -44,7 +44,7 @@ def _torch():
 class Plan:
     """Precomputed state for one grid and kernel (Algorithm 1, precomputation).
 
-    kernel: "coulomb3d" | "coulomb2d" | "poisson2d" | "dipolar3d" | "gaussian_sum"
+    kernel: "coulomb3d" | "coulomb2d" | "poisson2d" | "dipolar3d" | "davey_stewartson2d" | "gaussian_sum"
     n, L:   points per axis and box half-width: one value for the cube [-L, L]^d, or
             one per axis in array order ((Lz, Ly, Lx) / (Ly, Lx)) for a rectangular box
     eps:    Gaussian-sum accuracy; delta_rel: near-field radius / max L (below min L / max L)

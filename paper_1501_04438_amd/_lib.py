@@ -8,8 +8,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs.so")
 
-KERNELS = {"coulomb3d": 0, "coulomb2d": 1, "poisson2d": 2, "dipolar3d": 3, "gaussian_sum": 4}
-KERNEL_DIM = {"coulomb3d": 3, "coulomb2d": 2, "poisson2d": 2, "dipolar3d": 3}
+KERNELS = {"coulomb3d": 0, "coulomb2d": 1, "poisson2d": 2, "dipolar3d": 3, "gaussian_sum": 4,
+           "davey_stewartson2d": 5}
+KERNEL_DIM = {"coulomb3d": 3, "coulomb2d": 2, "poisson2d": 2, "dipolar3d": 3, "davey_stewartson2d": 2}
 
 GS_OK = 0
 STATUS = {0: "GS_OK", 1: "GS_ERR_INVALID_ARG", 2: "GS_ERR_UNSUPPORTED_SIZE", 3: "GS_ERR_ACCURACY",

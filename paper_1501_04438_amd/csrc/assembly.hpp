@@ -9,6 +9,8 @@
 // is a rank-Q contraction whose right operand is the Khatri-Rao product
 // B[q][(k2,k3)] = Fy[k2][q] Fz[k3][q]: a GEMM of shape (n+1) x Q x (n+1)^2 with
 // B formed in registers.  2D: S[k1][k3] with B[q][k3] = Fy[k3][q] (passed as FC).
+// dxx != 0 multiplies the result by -xi_k1^2, the symbol of d_xx (Davey-Stewartson
+// potential: the Poisson spectrum applied to the second x-derivative of rho).
 //
 // v_mfma_f64_16x16x4f64 operand layout (one wave, lane l = 0..63):
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
@@ -30,7 +32,7 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
                                                   const double* __restrict__ FC,   // [Qp][ldk]: factor of k3
                                                   int ldk, int n1, int Qp, double* __restrict__ out,
                                                   double A0, double c2, double dx1, double dx2, double dx3,
-                                                  double invM) {
+                                                  double invM, int dxx) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long ncols = (DIM == 3) ? (long)n1 * n1 : (long)n1;
     const long col0 = ((long)blockIdx.x * 4 + wave) * 16;
@@ -72,7 +74,8 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
                 const int k1 = k1base + mb * 16 + kk + 4 * r;
                 if (k1 < n1) {
                     const double x1 = (double)k1 * dx1;
-                    out[(size_t)k1 * ncols + c] = (acc[mb][r] + A0 - c2 * (x1 * x1 + xs)) * invM;
+                    const double f = dxx ? -(x1 * x1) * invM : invM;
+                    out[(size_t)k1 * ncols + c] = (acc[mb][r] + A0 - c2 * (x1 * x1 + xs)) * f;
                 }
             }
         }

@@ -113,6 +113,7 @@ gs_status device_assembly(gs_plan_s* p) {
         a.dxi[1] = M_PI / (2.0 * p->Lk[1]);
         a.dxi[2] = M_PI / (2.0 * p->Lk[p->d - 1]);
         a.invM = 1.0 / std::pow(2.0 * p->n, p->d);
+        a.dxx = p->kernel == GS_DAVEY_STEWARTSON_2D ? 1 : 0;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
         (void)hipEventRecord(e0, p->stream);
@@ -313,8 +314,8 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     if (d != 2 && d != 3) return fail(GS_ERR_INVALID_ARG, "d must be 2 or 3");
     if (!n || !L) return fail(GS_ERR_INVALID_ARG, "n or L is NULL");
     const int want_d = (k == GS_COULOMB_3D || k == GS_DIPOLAR_3D) ? 3
-                     : (k == GS_COULOMB_2D || k == GS_POISSON_2D) ? 2 : d;
-    if (k < GS_COULOMB_3D || k > GS_GAUSSIAN_SUM) return fail(GS_ERR_INVALID_ARG, "unknown kernel");
+                     : (k == GS_COULOMB_2D || k == GS_POISSON_2D || k == GS_DAVEY_STEWARTSON_2D) ? 2 : d;
+    if (k < GS_COULOMB_3D || k > GS_DAVEY_STEWARTSON_2D) return fail(GS_ERR_INVALID_ARG, "unknown kernel");
     if (want_d != d) return fail(GS_ERR_INVALID_ARG, "kernel and dimension disagree");
     double Lmax = 0.0, Lmin = 0.0, sum2 = 0.0;
     for (int i = 0; i < d; ++i) {
@@ -389,7 +390,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     const double hi = 2.0 * std::sqrt(sum2);   // largest distance in the box, in units of L
     if (k == GS_COULOMB_3D || k == GS_DIPOLAR_3D || k == GS_COULOMB_2D) {
         ok = gsh::coulomb_table(d, p->L, hi, p->delta_rel, eps, p->table);
-    } else if (k == GS_POISSON_2D) {
+    } else if (k == GS_POISSON_2D || k == GS_DAVEY_STEWARTSON_2D) {
         ok = gsh::poisson_table(p->L, hi, p->delta_rel, eps, p->table);
     } else {
         p->table.w.assign(opt.gs_w, opt.gs_w + opt.gs_q);
@@ -433,7 +434,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->work_bytes = (x1 + x2) * sizeof(double2) + 2 * (size_t)nn * sizeof(double2);
 
     if (host_only) {
-        gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, p->spec_host);
+        gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D, p->spec_host);
         std::lock_guard<std::mutex> g(g_live_mu);
         g_live.insert(p);
         *out = p;
@@ -466,7 +467,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         }
         if (st == GS_OK) {
             if (opt.flags & GS_PLAN_HOST_ASSEMBLY) {
-                gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, p->spec_host);
+                gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D, p->spec_host);
                 if ((e = hipMemcpy(p->spec, p->spec_host.data(), p->spec_bytes, hipMemcpyHostToDevice)) != hipSuccess)
                     st = hip_fail(e, "hipMemcpy(spectrum)");
             } else {

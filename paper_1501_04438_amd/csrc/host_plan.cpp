@@ -378,7 +378,8 @@ static double u_moment(int kernel, int m, double delta) {
         case COULOMB_3D:
         case DIPOLAR_3D: return std::pow(delta, m) / (4.0 * PI * m);
         case COULOMB_2D: return std::pow(delta, m) / (2.0 * PI * m);
-        case POISSON_2D: {
+        case POISSON_2D:
+        case DAVEY_STEWARTSON_2D: {
             const double a = m + 1;
             return -std::pow(delta, a) * (std::log(delta) / a - 1.0 / (a * a)) / (2.0 * PI);
         }
@@ -405,7 +406,7 @@ void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2)
 // ------------------------------------------------------------------ host assembly
 
 void assemble_spectrum(int d, int n, const double* Lk, const Table& t, const std::vector<double>* Fk, double A0,
-                       double c2, std::vector<double>& S) {
+                       double c2, bool dxx, std::vector<double>& S) {
     const int n1 = n + 1, Q = (int)t.w.size();
     const double dxa = PI / (2.0 * Lk[0]), dxb = PI / (2.0 * Lk[1]), dxc = PI / (2.0 * Lk[d - 1]);
     const std::vector<double>& Fa = Fk[0];
@@ -418,12 +419,13 @@ void assemble_spectrum(int d, int n, const double* Lk, const Table& t, const std
         for (int a = a0; a < a1; ++a) {
             for (int q = 0; q < Q; ++q) wa[q] = t.w[q] * Fa[(size_t)a * Q + q];
             const double xa = a * dxa;
+            const double fa = dxx ? -(xa * xa) * invM : invM;
             if (d == 2) {
                 for (int b = 0; b < n1; ++b) {
                     double acc = 0.0;
                     for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q];
                     const double xb = b * dxb;
-                    S[(size_t)a * n1 + b] = (acc + A0 - c2 * (xa * xa + xb * xb)) * invM;
+                    S[(size_t)a * n1 + b] = (acc + A0 - c2 * (xa * xa + xb * xb)) * fa;
                 }
                 continue;
             }
@@ -433,7 +435,7 @@ void assemble_spectrum(int d, int n, const double* Lk, const Table& t, const std
                     double acc = 0.0;
                     for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q] * Fc[(size_t)cc * Q + q];
                     const double xc = cc * dxc;
-                    S[((size_t)a * n1 + b) * n1 + cc] = (acc + A0 - c2 * (xa * xa + xb * xb + xc * xc)) * invM;
+                    S[((size_t)a * n1 + b) * n1 + cc] = (acc + A0 - c2 * (xa * xa + xb * xb + xc * xc)) * fa;
                 }
             }
         }

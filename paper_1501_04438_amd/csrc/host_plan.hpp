@@ -7,7 +7,7 @@
 
 namespace gsh {
 
-enum Kernel { COULOMB_3D = 0, COULOMB_2D = 1, POISSON_2D = 2, DIPOLAR_3D = 3, GAUSSIAN_SUM = 4 };
+enum Kernel { COULOMB_3D = 0, COULOMB_2D = 1, POISSON_2D = 2, DIPOLAR_3D = 3, GAUSSIAN_SUM = 4, DAVEY_STEWARTSON_2D = 5 };
 
 // Gaussian sum U_GS(r) = sum_q w[q] exp(-tau[q]^2 r^2) in physical units; q = 0 is tau = 0.
 struct Table {
@@ -33,8 +33,9 @@ void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2)
 
 // Host assembly of the stored octant (n+1)^d, 1/(2n)^d folded in.  Octant axes
 // (kx, ky[, kz]): Lk[i] and Fk[i] are the half-width and factors of axis x, y[, z].
+// dxx: multiply by -xi_x^2, the symbol of d_xx (Davey-Stewartson).
 void assemble_spectrum(int d, int n, const double* Lk, const Table& t, const std::vector<double>* Fk,
-                       double A0, double c2, std::vector<double>& S);
+                       double A0, double c2, bool dxx, std::vector<double>& S);
 
 // exp(-i pi m / n), m = 0..2n-1, as interleaved (re, im).
 void twiddles(int n, std::vector<double>& tw);

@@ -368,3 +368,44 @@ def test_rectangular_box_gradient_and_batch():
     outs = gs.eval_batch([plan, other], [rho.detach(), rho2])
     torch.cuda.synchronize()
     assert torch.equal(outs[0], u) and torch.equal(outs[1], other.eval(rho2))
+
+
+# --------------------------------------------------------------------------
+# Davey-Stewartson potential (Example 4.5).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [8, 24, 64, 192, 512])
+def test_davey_stewartson_random_input(n):
+    rng = np.random.default_rng(500 + n)
+    rho = rng.standard_normal((n, n))
+    plan = gs.Plan("davey_stewartson2d", n=n, L=6.0, eps=1e-13)
+    ref = oracle.evaluate(oracle.make_plan("davey_stewartson2d", 2, n, 6.0, eps=1e-13), rho)
+    assert relmax(gpu_eval(plan, rho), ref) <= TOL
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_davey_stewartson_paper_example(n):
+    """Example 4.5 on [-8,8]^2: oracle parity, and the closed form within the printed
+    Table 8 error (3.974e-9 at 128^2, 4.536e-13 at 256^2)."""
+    from oracle import closed_forms as cf
+    p = workloads.ds_example(n)
+    plan = gs.Plan(p.kernel, n=n, L=p.L, eps=1e-13)
+    u = gpu_eval(plan, p.rho)
+    assert relmax(u, oracle.evaluate(oracle.make_plan(p.kernel, 2, n, p.L, eps=1e-13), p.rho)) <= TOL
+    X = np.broadcast_arrays(*workloads.mesh(n, p.L, 2))
+    assert relmax(u, cf.davey_stewartson_gaussian(X[0], X[1])) <= {128: 3.974e-9, 256: 4.536e-13}[n]
+
+
+def test_davey_stewartson_rectangle_mixture_gradient():
+    """A rectangular box, the seeded mixture, autograd (the operator is symmetric)."""
+    Ls = (9.0, 12.0)
+    n = 96
+    rho = workloads.gaussian(n, Ls, 2, sigma=1.1, center=(0.5, -1.0)) - workloads.gaussian(n, Ls, 2, sigma=0.7)
+    plan = gs.Plan("davey_stewartson2d", n=n, L=Ls, eps=1e-13)
+    ref = oracle.evaluate(oracle.make_plan("davey_stewartson2d", 2, n, Ls, eps=1e-13), rho)
+    assert relmax(gpu_eval(plan, rho), ref) <= TOL
+    r = cuda(rho).requires_grad_(True)
+    gs.energy(r, plan).backward()
+    u = plan.eval(r.detach())
+    torch.cuda.synchronize()
+    assert relmax(r.grad.cpu().numpy(), (plan.cell * u).cpu().numpy()) <= 1e-13

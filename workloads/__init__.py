@@ -145,8 +145,9 @@ def config3_mixture() -> Mixture:
 
 
 def config3_2d(kernel: str, n: int = 1024) -> Problem:
-    """2D Poisson or 2D Coulomb of a seeded 16-Gaussian mixture on [-12,12]^2."""
-    assert kernel in ("poisson2d", "coulomb2d")
+    """2D Poisson, 2D Coulomb or Davey-Stewartson potential of a seeded 16-Gaussian
+    mixture on [-12,12]^2."""
+    assert kernel in ("poisson2d", "coulomb2d", "davey_stewartson2d")
     L = 12.0
     mix = config3_mixture()
     return Problem(kernel, 2, n, L, sample_mixture(mix, n, L), mixture=mix)
@@ -186,6 +187,12 @@ def rect_box(d: int, gamma: float, n: int | None = None) -> Problem:
     Ls = (12.0 / gamma, 12.0)
     rho = gaussian(n, Ls, 2, sigma=2.0, gammas=(1.0, gamma))
     return Problem("coulomb2d", 2, n, Ls, rho, extra={"sigma": 2.0, "gamma": gamma})
+
+
+def ds_example(n: int = 256) -> Problem:
+    """Davey-Stewartson example (Example 4.5): rho = pi exp(-pi^2 |x|^2) on [-8,8]^2."""
+    rho = gaussian(n, 8.0, 2, sigma=1.0 / math.pi, scale=math.pi)
+    return Problem("davey_stewartson2d", 2, n, 8.0, rho)
 
 
 BATCH_SIZES = (32, 48, 64, 96, 128)
