@@ -12,6 +12,8 @@ These are the checks the method must hit, independent of the method itself:
   * 2D Poisson of exp(-r^2/sigma^2): -(sigma^2/4)[E1(r^2/sigma^2) + 2 ln r],
     (sigma^2/4)(gamma_e - ln sigma^2) at r = 0                                 (eq. (eg-2d-Exact))
   * Davey-Stewartson potential of pi exp(-pi^2 r^2) (Example 4.5)
+  * inverse-power kernel |x|^-beta of exp(-r^2/sigma^2): a 1-D integral, and its value
+    at the origin in Gamma functions
   * 3D dipolar of exp(-r^2/sigma^2): -(n.m) rho - 3 n^T D m with the Hessian D
     of the Coulomb potential (Example 4.4)
   * the 1-D factor integral in closed form, (sqrt(pi)/tau) exp(-xi^2/4tau^2)
@@ -127,6 +129,41 @@ def coulomb2d_anisotropic_mp(x: float, y: float, sigma: float, gamma: float) -> 
         f = lambda t: mp.exp(-x * x / (s2 * (t * t + 1)) - y * y / (s2 * (t * t + g2))) / (
             mp.sqrt(t * t + 1) * mp.sqrt(t * t + g2))
         return float(mp.mpf(sigma) / (mp.mpf(gamma) * mp.sqrt(mp.pi)) * mp.quad(f, [0, 1, 10, mp.inf]))
+
+
+def power_gaussian(r, beta: float, sigma: float, d: int, step: float = 0.05, vmax: float = 90.0):
+    """Potential of exp(-|x|^2/sigma^2) under the kernel |x|^-beta (0 < beta < d) at
+    distances r: with r^-beta = (2/Gamma(beta/2)) int tau^(beta-1) e^(-r^2 tau^2) dtau and the
+    Gaussian convolution, u(r) = (2/Gamma(beta/2)) int_0^inf tau^(beta-1) (pi/(a+tau^2))^(d/2)
+    exp(-a tau^2 r^2/(a+tau^2)) dtau, a = 1/sigma^2.  With tau = exp(v) the integrand decays
+    exponentially at both ends (rates beta and d-beta) and is analytic in |Im v| < pi/2:
+    trapezoidal rule in v."""
+    r = np.asarray(r, dtype=np.float64)
+    a = 1.0 / (sigma * sigma)
+    out = np.zeros_like(r)
+    r2 = r * r
+    for k in range(int(round(2.0 * vmax / step)) + 1):
+        v = -vmax + k * step
+        t2 = math.exp(2.0 * v)
+        f = step * math.exp(beta * v) * (math.pi / (a + t2)) ** (d / 2.0)
+        if f == 0.0:
+            continue
+        out += f * np.exp(-a * t2 * r2 / (a + t2))
+    return out * 2.0 / math.gamma(beta / 2.0)
+
+
+def power_gaussian_mp(r: float, beta: float, sigma: float, d: int) -> float:
+    """Same integral at one distance by mpmath quadrature (reference for the above)."""
+    with mp.workdps(30):
+        a = 1 / mp.mpf(sigma) ** 2
+        f = lambda t: t ** (beta - 1) * (mp.pi / (a + t * t)) ** (mp.mpf(d) / 2) * mp.e ** (-a * t * t * r * r / (a + t * t))
+        return float(2 / mp.gamma(mp.mpf(beta) / 2) * mp.quad(f, [0, 1, 10, mp.inf]))
+
+
+def power_gaussian_origin(beta: float, sigma: float, d: int) -> float:
+    """u(0) = |S^(d-1)| int_0^inf r^(d-1-beta) e^(-r^2/sigma^2) dr
+            = pi^(d/2) sigma^(d-beta) Gamma((d-beta)/2) / Gamma(d/2)."""
+    return math.pi ** (d / 2.0) * sigma ** (d - beta) * math.gamma((d - beta) / 2.0) / math.gamma(d / 2.0)
 
 
 def davey_stewartson_gaussian(x, y):

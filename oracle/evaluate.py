@@ -51,7 +51,7 @@ from .factors import factor_1d
 from .gs_table import GSTable, box_half_widths, custom_table, physical_table
 from .taylor import taylor_constants
 
-COULOMB_LIKE = ("coulomb3d", "coulomb2d", "poisson2d", "dipolar3d", "davey_stewartson2d")
+COULOMB_LIKE = ("coulomb3d", "coulomb2d", "poisson2d", "dipolar3d", "davey_stewartson2d", "inverse_power")
 
 
 @dataclass
@@ -69,6 +69,7 @@ class OraclePlan:
     dipole_m: tuple | None = None
     Ls: tuple = ()          # per-axis half-widths, C order (z, y, x / y, x)
     Fs: tuple = ()          # per-axis factor matrices, C order
+    beta: float | None = None   # exponent of the inverse-power kernel r^-beta
 
     @property
     def h(self) -> float:
@@ -92,14 +93,15 @@ class OraclePlan:
 
 
 def make_plan(kernel: str, d: int, n: int, L, eps: float = 1e-14,
-              delta_rel: float = 1e-4, custom=None, dipole=None) -> OraclePlan:
-    """L: one half-width for the cube [-L, L]^d, or one per axis in C order."""
+              delta_rel: float = 1e-4, custom=None, dipole=None, beta: float | None = None) -> OraclePlan:
+    """L: one half-width for the cube [-L, L]^d, or one per axis in C order;
+    beta: the exponent of kernel "inverse_power" (U = |x|^-beta, 0 < beta < d)."""
     Ls = box_half_widths(L, d)
     if kernel == "gaussian_sum":
         w, tau = custom
         table = custom_table(w, tau, d, Ls)
     else:
-        table = physical_table(kernel, d, Ls, eps, delta_rel)
+        table = physical_table(kernel, d, Ls, eps, delta_rel, beta=beta)
         if table.d != d:
             raise ValueError("kernel and dimension disagree")
     Fs = tuple(factor_1d(table.tau, 2.0 * Lj, n) for Lj in Ls)
@@ -114,11 +116,11 @@ def make_plan(kernel: str, d: int, n: int, L, eps: float = 1e-14,
     if kernel == "gaussian_sum":
         A0, c2 = 0.0, 0.0
     else:
-        A0, c2 = taylor_constants(kernel, d, table.delta, table.w, table.tau)
+        A0, c2 = taylor_constants(kernel, d, table.delta, table.w, table.tau, beta)
     dn = dm = None
     if kernel == "dipolar3d":
         dn, dm = dipole
-    return OraclePlan(kernel, d, n, table.L, table, Fs[-1], G, A0, c2, dn, dm, Ls, Fs)
+    return OraclePlan(kernel, d, n, table.L, table, Fs[-1], G, A0, c2, dn, dm, Ls, Fs, beta)
 
 
 def padded_frequencies(n: int, L: float, odd: bool = False) -> np.ndarray:

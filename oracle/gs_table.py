@@ -20,6 +20,19 @@ on x in [1, X], X = R/delta.  Nodes whose whole contribution on [1, X]
 (about a_k X^2 / 2) is below 1e-3 eps are dropped: that is the stable evaluation
 the paper asks for (otherwise s_k underflows and wh_k becomes 0/0).
 
+Inverse powers 1/r^beta, 0 < beta < d (the Remark after eq. (GauInte)): the same
+Gaussian integral with alpha = beta - 1,
+    r^-beta = (2/Gamma(beta/2)) int_0^inf tau^(beta-1) exp(-r^2 tau^2) dtau
+(eq. (Gauss_int) as printed lacks the factor 1/2 of int_0^inf; with alpha = 0 it
+must give eq. (GauInte), which fixes it).  For beta != 1 the integrand is not even
+in tau, so the sinh substitution does not apply; the reading taken is the double-
+exponential substitution tau = exp(t - e^-t) (decay exp(-beta e^-t) as t -> -inf,
+exp(-r^2 e^2t) as t -> inf), sinc rule with step theta = c0 ln(S)/S, c0 = 2, over
+k = -S..S:
+    w_k = (2/Gamma(beta/2)) theta tau_k^beta (1 + e^-t_k),   tau_k = exp(t_k - e^-t_k),
+keeping the nodes whose largest contribution r^beta w_k exp(-tau_k^2 r^2) on the
+fit interval exceeds 1e-3 eps.
+
 S is the smallest value whose maximum error on 100001 log-spaced points of the
 fit interval is <= eps: relative error of 1/r on [delta, R] (the paper's E_rel),
 absolute error of ln on [delta, R] (E_abs), both in box-rescaled units
@@ -94,6 +107,33 @@ def coulomb_table(d: int, delta_rel: float, eps: float, c0: float = 2.1, hi: flo
     return w, tau, S
 
 
+def power_nodes(beta: float, S: int, lo: float, hi: float, eps: float, c0: float = 2.0):
+    """Rescaled 1/r^beta table (w~, tau~) on [lo, hi] with the negligible nodes dropped."""
+    th = _theta(S, c0)
+    t = np.arange(-S, S + 1, dtype=np.float64) * th
+    tau = np.exp(t - np.exp(-t))
+    w = (2.0 / math.gamma(beta / 2.0)) * th * tau ** beta * (1.0 + np.exp(-t))
+    with np.errstate(divide="ignore", over="ignore"):
+        rstar = np.clip(math.sqrt(beta / 2.0) / tau, lo, hi)   # where r^beta e^(-tau^2 r^2) peaks
+    keep = w * rstar ** beta * np.exp(-(tau * rstar) ** 2) > 1e-3 * eps
+    return w[keep], tau[keep]
+
+
+def power_error(beta: float, S: int, lo: float, hi: float, eps: float, c0: float = 2.0, pts=None) -> float:
+    w, tau = power_nodes(beta, S, lo, hi, eps, c0)
+    r = np.geomspace(lo, hi, NPTS) if pts is None else pts
+    return float(np.max(np.abs(1.0 - r ** beta * _sum_gauss(w[np.argsort(tau)], np.sort(tau) ** 2, r * r))))
+
+
+def power_table(beta: float, delta_rel: float, eps: float, hi: float, c0: float = 2.0):
+    """Smallest-S 1/r^beta table meeting the relative error eps on [delta_rel, hi]."""
+    pts = np.geomspace(delta_rel, hi, NPTS)
+    _EPS_BOX[0] = eps
+    S = _smallest_S(lambda S, p: power_error(beta, S, delta_rel, hi, eps, c0, pts=p), pts)
+    w, tau = power_nodes(beta, S, delta_rel, hi, eps, c0)
+    return w, tau, S
+
+
 def poisson_nodes(S: int, X: float, eps: float, c0: float = 1.0):
     """Rescaled ln table: returns (C0, wh, s) with the negligible nodes dropped."""
     th = _theta(S, c0)
@@ -165,7 +205,7 @@ def fit_interval_end(Ls) -> float:
     return 2.0 * math.sqrt(sum((v / Lu) ** 2 for v in Ls))
 
 
-def physical_table(kernel: str, d: int, L, eps: float, delta_rel: float = 1e-4) -> GSTable:
+def physical_table(kernel: str, d: int, L, eps: float, delta_rel: float = 1e-4, beta: float | None = None) -> GSTable:
     """Table for U in physical units on the box prod_j [-L_j, L_j] (Section 2.1
     rescaling, with the largest half-width L as the length unit; Section 2.5 for
     rectangular boxes).
@@ -173,7 +213,8 @@ def physical_table(kernel: str, d: int, L, eps: float, delta_rel: float = 1e-4) 
     Coulomb: 1/r = (1/L)(1/r~) with r~ = r/L, so w = kappa w~/L, tau = tau~/L,
     kappa = 1/(4 pi) (3D) or 1/(2 pi) (2D).  Poisson: -ln(r)/(2 pi) with
     r = delta x, delta = delta_rel L: w_0 = -(ln delta + C0)/(2 pi), tau_0 = 0,
-    w_k = wh_k/(2 pi), tau_k = sqrt(s_k)/delta.  The near-field ball must fit the
+    w_k = wh_k/(2 pi), tau_k = sqrt(s_k)/delta.  Inverse power r^-beta = L^-beta r~^-beta:
+    w = w~/L^beta, tau = tau~/L.  The near-field ball must fit the
     shortest axis (Section 2.5: delta below eta): delta_rel < min_j L_j / L.
     """
     dd = 3 if kernel in ("coulomb3d", "dipolar3d") else (
@@ -188,6 +229,11 @@ def physical_table(kernel: str, d: int, L, eps: float, delta_rel: float = 1e-4) 
         kappa = 1.0 / (4.0 * math.pi) if dd == 3 else 1.0 / (2.0 * math.pi)
         wt, tt, S = coulomb_table(dd, delta_rel, eps, hi=hi)
         return GSTable(kappa * wt / L, tt / L, S, delta, kernel, dd, L)
+    if kernel == "inverse_power":
+        if beta is None or not 0.0 < beta < dd:
+            raise ValueError("inverse_power needs 0 < beta < d")
+        wt, tt, S = power_table(beta, delta_rel, eps, hi)
+        return GSTable(wt / L ** beta, tt / L, S, delta, kernel, dd, L)
     if kernel in ("poisson2d", "davey_stewartson2d"):
         # the Davey-Stewartson potential convolves the same logarithmic kernel
         C0, wh, s, S = poisson_table(delta_rel, eps, hi=hi)

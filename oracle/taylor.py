@@ -13,6 +13,7 @@ constants; the expressions above follow from its derivation.
 The U parts are elementary (kernel constants included):
     3D Coulomb 1/(4 pi r):      int r^2 U = delta^2/(8 pi),   int r^4 U = delta^4/(16 pi)
     2D Coulomb 1/(2 pi r):      int r U   = delta/(2 pi),     int r^3 U = delta^3/(6 pi)
+    inverse power r^-beta:      int r^m U = delta^(m+1-beta)/(m+1-beta)    (m = d-1, d+1)
     2D Poisson -ln r/(2 pi):    int r U   = (delta^2/4 - delta^2 ln(delta)/2)/(2 pi),
                                 int r^3 U = (delta^4/16 - delta^4 ln(delta)/4)/(2 pi)
 and the Gaussian parts are lower incomplete gamma functions,
@@ -33,9 +34,12 @@ def sphere_area(d: int) -> float:
     return float(2 * mp.pi ** (mp.mpf(d) / 2) / mp.gamma(mp.mpf(d) / 2))
 
 
-def _u_moment(kernel: str, m: int, delta):
+def _u_moment(kernel: str, m: int, delta, beta=None):
     """int_0^delta r^m U(r) dr (mpmath)."""
     dl = mp.mpf(delta)
+    if kernel == "inverse_power":                        # int_0^delta r^(m - beta) dr
+        e = m + 1 - mp.mpf(beta)
+        return dl ** e / e
     if kernel in ("coulomb3d", "dipolar3d"):
         return dl ** m / (4 * mp.pi * m)                 # int r^{m-1}/(4 pi) dr
     if kernel == "coulomb2d":
@@ -56,13 +60,14 @@ def gamma_moment(m: int, tau, delta):
     return mp.gammainc(a, 0, (t * dl) ** 2) / (2 * t ** (m + 1))
 
 
-def taylor_constants(kernel: str, d: int, delta: float, w, tau):
-    """(A0, c2) for the table (w, tau) and the physical radius delta."""
+def taylor_constants(kernel: str, d: int, delta: float, w, tau, beta=None):
+    """(A0, c2) for the table (w, tau) and the physical radius delta (beta: the exponent
+    of the inverse-power kernel r^-beta, whose moments need beta < d)."""
     with mp.workdps(40):
         area = 2 * mp.pi ** (mp.mpf(d) / 2) / mp.gamma(mp.mpf(d) / 2)
         m0, m2 = d - 1, d + 1
-        s0 = _u_moment(kernel, m0, delta)
-        s2 = _u_moment(kernel, m2, delta)
+        s0 = _u_moment(kernel, m0, delta, beta)
+        s2 = _u_moment(kernel, m2, delta, beta)
         for wq, tq in zip(w, tau):
             s0 -= mp.mpf(float(wq)) * gamma_moment(m0, float(tq), delta)
             s2 -= mp.mpf(float(wq)) * gamma_moment(m2, float(tq), delta)

@@ -629,3 +629,73 @@ def test_davey_stewartson_adjoint_and_symmetry():
     Aa, ATb = oracle.evaluate(plan, a), oracle.adjoint(plan, b)
     assert abs(np.sum(Aa * b) - np.sum(a * ATb)) <= 1e-13 * np.sqrt(np.sum(Aa ** 2) * np.sum(b ** 2))
     assert relmax(oracle.adjoint(plan, a), Aa) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Inverse-power kernels |x|^-beta (the Remark after eq. (GauInte)).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("beta,d", [(0.5, 3), (2.0, 3), (2.5, 3), (1.5, 2)])
+def test_power_closed_form_against_mpmath(beta, d):
+    r = np.array([0.0, 0.3, 1.7, 5.0])
+    v = cf.power_gaussian(r, beta, 1.3, d)
+    for ri, vi in zip(r, v):
+        assert abs(vi - cf.power_gaussian_mp(float(ri), beta, 1.3, d)) <= 1e-14 * abs(vi)
+    assert abs(v[0] - cf.power_gaussian_origin(beta, 1.3, d)) <= 1e-14 * v[0]
+
+
+@pytest.mark.parametrize("beta,d,n", [(0.5, 3, 48), (2.0, 3, 48), (2.5, 3, 48), (0.5, 2, 96), (1.5, 2, 96)])
+def test_power_kernel_against_closed_form(beta, d, n):
+    L, s = 8.0, 1.2
+    rho = workloads.gaussian(n, L, d, sigma=s)
+    X = np.broadcast_arrays(*workloads.mesh(n, L, d))
+    r = np.sqrt(sum(x * x for x in X))
+    u = oracle.evaluate(oracle.make_plan("inverse_power", d, n, L, beta=beta), rho)
+    assert relmax(u, cf.power_gaussian(r, beta, s, d)) < 1e-13
+
+
+@pytest.mark.parametrize("d,kernel,kappa", [(3, "coulomb3d", 4 * math.pi), (2, "coulomb2d", 2 * math.pi)])
+def test_power_kernel_beta_one_is_coulomb(d, kernel, kappa):
+    """beta = 1 is the Coulomb kernel without its constant, through a different table."""
+    rng = np.random.default_rng(12)
+    n = 16 if d == 3 else 48
+    rho = rng.standard_normal((n,) * d)
+    a = oracle.evaluate(oracle.make_plan("inverse_power", d, n, 5.0, beta=1.0), rho)
+    b = oracle.evaluate(oracle.make_plan(kernel, d, n, 5.0), rho)
+    assert relmax(a, kappa * b) < 1e-13
+
+
+@pytest.mark.parametrize("beta,d", [(0.7, 3), (2.2, 3), (1.3, 2)])
+def test_power_kernel_box_scaling(beta, d):
+    """|s x|^-beta = s^-beta |x|^-beta: u_{sL}(s x) = s^(d - beta) u_L(x)."""
+    rng = np.random.default_rng(13)
+    n, L, s = 12, 3.0, 2.5
+    rho = rng.standard_normal((n,) * d)
+    u1 = oracle.evaluate(oracle.make_plan("inverse_power", d, n, L, beta=beta), rho)
+    u2 = oracle.evaluate(oracle.make_plan("inverse_power", d, n, s * L, beta=beta), rho)
+    assert relmax(u2, s ** (d - beta) * u1) < 1e-13
+
+
+@pytest.mark.parametrize("beta,d", [(0.5, 3), (2.5, 3), (1.5, 2)])
+def test_power_table_and_taylor_constants(beta, d):
+    """The table meets eps on its fit interval; A0, c2 against a direct quadrature of
+    int_0^delta r^m (r^-beta - U_GS) dr; beta outside (0, d) is refused."""
+    hi = 2 * math.sqrt(d)
+    w, tau, S = gs_table.power_table(beta, 1e-3, 1e-13, hi)
+    assert gs_table.power_error(beta, S, 1e-3, hi, 1e-13) <= 1e-13
+    t = gs_table.physical_table("inverse_power", d, 9.0, 1e-13, delta_rel=1e-3, beta=beta)
+    A0, c2 = taylor_constants("inverse_power", d, t.delta, t.w, t.tau, beta)
+    with mp.workdps(30):
+        area = 2 * mp.pi ** (mp.mpf(d) / 2) / mp.gamma(mp.mpf(d) / 2)
+        ws = [mp.mpf(float(x)) for x in t.w]
+        ts = [mp.mpf(float(x)) for x in t.tau]
+
+        def diff(r):
+            return r ** (-mp.mpf(beta)) - mp.fsum(wq * mp.exp(-(tq * r) ** 2) for wq, tq in zip(ws, ts))
+        pts = [0] + [t.delta * 10 ** (-k) for k in range(8, 0, -1)] + [t.delta]
+        q0 = area * mp.quad(lambda r: r ** (d - 1) * diff(r), pts)
+        q2 = area * mp.quad(lambda r: r ** (d + 1) * diff(r), pts) / (2 * d)
+    assert abs(A0 - float(q0)) <= 1e-12 * abs(float(q0))
+    assert abs(c2 - float(q2)) <= 1e-12 * abs(float(q2))
+    with pytest.raises(ValueError):
+        gs_table.physical_table("inverse_power", d, 9.0, 1e-13, beta=float(d))
