@@ -50,9 +50,11 @@ typedef enum {
     GS_DIPOLAR_3D = 3,    /* u = -(n.m) rho - 3 Coulomb3D(d_n d_m rho), d = 3 */
     GS_GAUSSIAN_SUM = 4,  /* U = sum_q w_q exp(-tau_q^2 |x|^2) from gs_options,
                              no near-field term (test hook), d = 2 or 3 */
-    GS_DAVEY_STEWARTSON_2D = 5  /* u = (-ln|x| / (2 pi)) * d_xx rho, d = 2: the Poisson
+    GS_DAVEY_STEWARTSON_2D = 5, /* u = (-ln|x| / (2 pi)) * d_xx rho, d = 2: the Poisson
                              table and Taylor terms, the d_xx symbol -xi_x^2 (even,
                              Nyquist kept) folded into the stored spectrum */
+    GS_INVERSE_POWER = 6  /* U = |x|^-beta, 0 < beta < d (gs_options.beta), d = 2 or 3
+                             (the Remark after eq. (GauInte)) */
 } gs_kernel;
 
 typedef enum {
@@ -96,6 +98,7 @@ typedef struct {
                                 concurrently (>= 2: X2 holds every slab, each at
                                 its own planes; the results are the same bits);
                                 0 or 1 = in order on the plan's stream           */
+    double beta;             /* GS_INVERSE_POWER: the exponent, 0 < beta < d      */
 } gs_options;
 
 typedef struct {
@@ -121,6 +124,7 @@ typedef struct {
     double tuned_ms;         /* measured evaluation time of the chosen variant    */
     double L_axes[3];        /* half-widths as given, C order (first d entries);
                                 L above is their maximum, the table's length unit */
+    double beta;             /* GS_INVERSE_POWER exponent (0 for other kernels)   */
 } gs_plan_info;
 
 /* Fill `opt` with the defaults (delta_rel 1e-4, null stream, device -1). */

@@ -44,7 +44,8 @@ def _torch():
 class Plan:
     """Precomputed state for one grid and kernel (Algorithm 1, precomputation).
 
-    kernel: "coulomb3d" | "coulomb2d" | "poisson2d" | "dipolar3d" | "davey_stewartson2d" | "gaussian_sum"
+    kernel: "coulomb3d" | "coulomb2d" | "poisson2d" | "dipolar3d" | "davey_stewartson2d" | "inverse_power"
+            | "gaussian_sum" (the last two need d; "inverse_power" also beta: U = |x|^-beta, 0 < beta < d)
     n, L:   points per axis and box half-width: one value for the cube [-L, L]^d, or
             one per axis in array order ((Lz, Ly, Lx) / (Ly, Lx)) for a rectangular box
     eps:    Gaussian-sum accuracy; delta_rel: near-field radius / max L (below min L / max L)
@@ -57,12 +58,12 @@ class Plan:
     def __init__(self, kernel: str, n: int, L, eps: float = 1e-14, d: int | None = None,
                  delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
                  host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0,
-                 slab_streams: int = 0, autotune: bool = False):
+                 slab_streams: int = 0, autotune: bool = False, beta: float | None = None):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         d = KERNEL_DIM.get(kernel, d)
         if d is None:
-            raise ValueError("gaussian_sum plans need d")
+            raise ValueError(f"{kernel} plans need d")
         self.kernel, self.d, self.n, self.eps = kernel, int(d), int(n), float(eps)
         self.Ls = _half_widths(L, self.d)
         self.L = max(self.Ls)
@@ -74,6 +75,8 @@ class Plan:
                      | (PLAN_AUTOTUNE if autotune else 0))
         opt.slab_planes = int(slab_planes)
         opt.slab_streams = int(slab_streams)
+        if beta is not None:
+            opt.beta = float(beta)
         if stream is not None:
             opt.stream = C.c_void_p(int(stream))
         keep = []

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs.so")
 
 KERNELS = {"coulomb3d": 0, "coulomb2d": 1, "poisson2d": 2, "dipolar3d": 3, "gaussian_sum": 4,
-           "davey_stewartson2d": 5}
+           "davey_stewartson2d": 5, "inverse_power": 6}
 KERNEL_DIM = {"coulomb3d": 3, "coulomb2d": 2, "poisson2d": 2, "dipolar3d": 3, "davey_stewartson2d": 2}
 
 GS_OK = 0
@@ -24,7 +24,7 @@ class GSOptions(C.Structure):
     _fields_ = [("delta_rel", C.c_double), ("dipole_n", C.c_double * 3), ("dipole_m", C.c_double * 3),
                 ("gs_w", C.POINTER(C.c_double)), ("gs_tau", C.POINTER(C.c_double)), ("gs_q", C.c_int),
                 ("stream", C.c_void_p), ("device", C.c_int), ("flags", C.c_int), ("slab_planes", C.c_int),
-                ("slab_streams", C.c_int)]
+                ("slab_streams", C.c_int), ("beta", C.c_double)]
 
 
 class GSPlanInfo(C.Structure):
@@ -33,7 +33,8 @@ class GSPlanInfo(C.Structure):
                 ("spectrum_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("assembly_ms", C.c_double),
                 ("assembly_gflop", C.c_double), ("host_only", C.c_int), ("slab_planes", C.c_int),
                 ("num_steps", C.c_int), ("slab_streams", C.c_int), ("x2_planes", C.c_int), ("tuned", C.c_int), ("hint_bits", C.c_int), ("fused_grid_mult", C.c_int),
-                ("tune_candidates", C.c_int), ("tuned_ms", C.c_double), ("L_axes", C.c_double * 3)]
+                ("tune_candidates", C.c_int), ("tuned_ms", C.c_double), ("L_axes", C.c_double * 3),
+                ("beta", C.c_double)]
 
 
 SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3, "sized": 4}

@@ -315,7 +315,9 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     if (!n || !L) return fail(GS_ERR_INVALID_ARG, "n or L is NULL");
     const int want_d = (k == GS_COULOMB_3D || k == GS_DIPOLAR_3D) ? 3
                      : (k == GS_COULOMB_2D || k == GS_POISSON_2D || k == GS_DAVEY_STEWARTSON_2D) ? 2 : d;
-    if (k < GS_COULOMB_3D || k > GS_DAVEY_STEWARTSON_2D) return fail(GS_ERR_INVALID_ARG, "unknown kernel");
+    if (k < GS_COULOMB_3D || k > GS_INVERSE_POWER) return fail(GS_ERR_INVALID_ARG, "unknown kernel");
+    if (k == GS_INVERSE_POWER && !(opt.beta > 0.0 && opt.beta < d))
+        return fail(GS_ERR_INVALID_ARG, "inverse power: beta must lie in (0, d)");
     if (want_d != d) return fail(GS_ERR_INVALID_ARG, "kernel and dimension disagree");
     double Lmax = 0.0, Lmin = 0.0, sum2 = 0.0;
     for (int i = 0; i < d; ++i) {
@@ -392,6 +394,8 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         ok = gsh::coulomb_table(d, p->L, hi, p->delta_rel, eps, p->table);
     } else if (k == GS_POISSON_2D || k == GS_DAVEY_STEWARTSON_2D) {
         ok = gsh::poisson_table(p->L, hi, p->delta_rel, eps, p->table);
+    } else if (k == GS_INVERSE_POWER) {
+        ok = gsh::power_table(opt.beta, p->L, hi, p->delta_rel, eps, p->table);
     } else {
         p->table.w.assign(opt.gs_w, opt.gs_w + opt.gs_q);
         p->table.tau.assign(opt.gs_tau, opt.gs_tau + opt.gs_q);
@@ -518,6 +522,7 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
     info->n = p->n;
     info->L = p->L;
     for (int i = 0; i < p->d; ++i) info->L_axes[i] = p->Lc[i];
+    info->beta = p->table.beta;
     info->eps = p->eps;
     info->delta = p->table.delta;
     info->S = p->table.S;

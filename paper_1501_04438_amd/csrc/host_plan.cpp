@@ -4,7 +4,8 @@
 //    integral with tau = sinh(t) (Section 3.2), ln r from Frullani's integral with
 //    s = ln(1 + exp(sinh t)) (Section 3.3, read as described at poisson_table),
 //    step theta = c0 ln(S)/S with c0 = 2.1 and 1 (Remark in Section 3.1), and S the
-//    smallest value meeting eps on the fit interval.
+//    smallest value meeting eps on the fit interval; inverse powers r^-beta (the
+//    Remark after eq. (GauInte)) with tau = exp(t - e^-t), c0 = 2 (power_table).
 //  * One-dimensional factor integrals of the tensor-product coefficients
 //    (Section 2.2, eq. (tensor)) on the box [-2L, 2L] at xi_k = pi k/(2L).
 //  * Taylor constants A0, c2 of the near-field correction (Section 2.3).
@@ -126,9 +127,9 @@ static int smallest_S(const std::vector<double>& pts, double eps, ErrFn err_for_
 
 struct TableKey {
     int kind;
-    double hi, delta_rel, eps;
+    double hi, delta_rel, eps, beta;
     bool operator<(const TableKey& o) const {
-        return std::tie(kind, hi, delta_rel, eps) < std::tie(o.kind, o.hi, o.delta_rel, o.eps);
+        return std::tie(kind, hi, delta_rel, eps, beta) < std::tie(o.kind, o.hi, o.delta_rel, o.eps, o.beta);
     }
 };
 static std::mutex g_cache_mu;
@@ -139,7 +140,7 @@ bool coulomb_table(int d, double L, double hi, double delta_rel, double eps, Tab
     int S;
     {
         std::lock_guard<std::mutex> g(g_cache_mu);
-        auto it = g_S_cache.find({0, hi, delta_rel, eps});
+        auto it = g_S_cache.find({0, hi, delta_rel, eps, 0.0});
         S = (it == g_S_cache.end()) ? 0 : it->second;
     }
     if (S == 0) {
@@ -150,7 +151,7 @@ bool coulomb_table(int d, double L, double hi, double delta_rel, double eps, Tab
             return max_err(pts, step, [&](double r) { return coulomb_err_at(w, tau, r); });
         });
         std::lock_guard<std::mutex> g(g_cache_mu);
-        g_S_cache[{0, hi, delta_rel, eps}] = S;
+        g_S_cache[{0, hi, delta_rel, eps, 0.0}] = S;
     }
     if (S < 0) return false;
     std::vector<double> w, tau;
@@ -162,6 +163,68 @@ bool coulomb_table(int d, double L, double hi, double delta_rel, double eps, Tab
     out.tau.resize(w.size());
     for (size_t q = 0; q < w.size(); ++q) {
         out.w[q] = kappa * w[q] / L;
+        out.tau[q] = tau[q] / L;
+    }
+    return true;
+}
+
+// r^-beta ~= sum_k w_k exp(-tau_k^2 r^2), nodes t_k = k theta, k = -S..S, theta = 2 ln(S)/S,
+// tau_k = exp(t_k - e^-t_k), w_k = (2/Gamma(beta/2)) theta tau_k^beta (1 + e^-t_k); nodes whose
+// largest relative contribution on [lo, hi] (at r = sqrt(beta/2)/tau clipped to it) is at most
+// 1e-3 eps are dropped.  Sorted by increasing tau.
+static void power_nodes(double beta, int S, double lo, double hi, double eps, std::vector<double>& w,
+                        std::vector<double>& tau) {
+    const double th = 2.0 * std::log((double)S) / S;
+    const double g = 2.0 / std::tgamma(beta / 2.0);
+    w.clear();
+    tau.clear();
+    for (int k = -S; k <= S; ++k) {
+        const double t = k * th, em = std::exp(-t);
+        const double tk = std::exp(t - em);
+        const double wk = g * th * std::pow(tk, beta) * (1.0 + em);
+        double rs = tk > 0.0 ? std::sqrt(beta / 2.0) / tk : hi;
+        rs = std::min(hi, std::max(lo, rs));
+        if (!(wk * std::pow(rs, beta) * std::exp(-(tk * rs) * (tk * rs)) > 1e-3 * eps)) continue;
+        w.push_back(wk);
+        tau.push_back(tk);
+    }
+}
+
+static double power_err_at(double beta, const std::vector<double>& w, const std::vector<double>& tau, double r) {
+    double acc = 0.0;
+    for (int q = (int)w.size() - 1; q >= 0; --q) acc += w[q] * std::exp(-(tau[q] * r) * (tau[q] * r));
+    return std::fabs(1.0 - std::pow(r, beta) * acc);
+}
+
+bool power_table(double beta, double L, double hi, double delta_rel, double eps, Table& out) {
+    const double lo = delta_rel;
+    int S;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        auto it = g_S_cache.find({2, hi, delta_rel, eps, beta});
+        S = (it == g_S_cache.end()) ? 0 : it->second;
+    }
+    if (S == 0) {
+        auto pts = log_points(lo, hi);
+        std::vector<double> w, tau;
+        S = smallest_S(pts, eps, [&](int s, int step) {
+            power_nodes(beta, s, lo, hi, eps, w, tau);
+            return max_err(pts, step, [&](double r) { return power_err_at(beta, w, tau, r); });
+        });
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        g_S_cache[{2, hi, delta_rel, eps, beta}] = S;
+    }
+    if (S < 0) return false;
+    std::vector<double> w, tau;
+    power_nodes(beta, S, lo, hi, eps, w, tau);
+    out.S = S;
+    out.beta = beta;
+    out.delta = delta_rel * L;
+    out.w.resize(w.size());
+    out.tau.resize(w.size());
+    const double scale = std::pow(L, -beta);
+    for (size_t q = 0; q < w.size(); ++q) {
+        out.w[q] = w[q] * scale;
         out.tau[q] = tau[q] / L;
     }
     return true;
@@ -203,7 +266,7 @@ bool poisson_table(double L, double hi, double delta_rel, double eps, Table& out
     int S;
     {
         std::lock_guard<std::mutex> g(g_cache_mu);
-        auto it = g_S_cache.find({1, hi, delta_rel, eps});
+        auto it = g_S_cache.find({1, hi, delta_rel, eps, 0.0});
         S = (it == g_S_cache.end()) ? 0 : it->second;
     }
     if (S == 0) {
@@ -215,7 +278,7 @@ bool poisson_table(double L, double hi, double delta_rel, double eps, Table& out
             return max_err(pts, step, [&](double x) { return poisson_err_at(C0, wh, s, x); });
         });
         std::lock_guard<std::mutex> g(g_cache_mu);
-        g_S_cache[{1, hi, delta_rel, eps}] = S;
+        g_S_cache[{1, hi, delta_rel, eps, 0.0}] = S;
     }
     if (S < 0) return false;
     double C0;
@@ -373,8 +436,9 @@ static double gamma_moment(int m, double tau, double delta) {
 }
 
 // int_0^delta r^m U(r) dr for the kernel (constants included)
-static double u_moment(int kernel, int m, double delta) {
+static double u_moment(int kernel, int m, double delta, double beta) {
     switch (kernel) {
+        case INVERSE_POWER: return std::pow(delta, m + 1 - beta) / (m + 1 - beta);
         case COULOMB_3D:
         case DIPOLAR_3D: return std::pow(delta, m) / (4.0 * PI * m);
         case COULOMB_2D: return std::pow(delta, m) / (2.0 * PI * m);
@@ -394,7 +458,7 @@ void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2)
     }
     const double area = (d == 3) ? 4.0 * PI : 2.0 * PI;
     const int m0 = d - 1, m2 = d + 1;
-    double s0 = u_moment(kernel, m0, t.delta), s2 = u_moment(kernel, m2, t.delta);
+    double s0 = u_moment(kernel, m0, t.delta, t.beta), s2 = u_moment(kernel, m2, t.delta, t.beta);
     for (size_t q = 0; q < t.w.size(); ++q) {
         s0 -= t.w[q] * gamma_moment(m0, t.tau[q], t.delta);
         s2 -= t.w[q] * gamma_moment(m2, t.tau[q], t.delta);

@@ -7,13 +7,17 @@
 
 namespace gsh {
 
-enum Kernel { COULOMB_3D = 0, COULOMB_2D = 1, POISSON_2D = 2, DIPOLAR_3D = 3, GAUSSIAN_SUM = 4, DAVEY_STEWARTSON_2D = 5 };
+enum Kernel {
+    COULOMB_3D = 0, COULOMB_2D = 1, POISSON_2D = 2, DIPOLAR_3D = 3, GAUSSIAN_SUM = 4, DAVEY_STEWARTSON_2D = 5,
+    INVERSE_POWER = 6
+};
 
 // Gaussian sum U_GS(r) = sum_q w[q] exp(-tau[q]^2 r^2) in physical units; q = 0 is tau = 0.
 struct Table {
     std::vector<double> w, tau;
     int S = 0;
     double delta = 0.0;   // physical near-field radius
+    double beta = 0.0;    // exponent of the inverse-power kernel r^-beta
 };
 
 // Sinc-quadrature tables (Section 3) fitted on [delta_rel, hi] in units of the
@@ -21,6 +25,9 @@ struct Table {
 // distance in the box: 2 sqrt(d) for a cube).  False when eps is not reachable.
 bool coulomb_table(int d, double Lu, double hi, double delta_rel, double eps, Table& out);
 bool poisson_table(double Lu, double hi, double delta_rel, double eps, Table& out);
+// r^-beta (0 < beta < d): 2/Gamma(beta/2) int tau^(beta-1) exp(-r^2 tau^2) dtau with
+// tau = exp(t - e^-t), step 2 ln(S)/S, negligible nodes dropped.
+bool power_table(double beta, double Lu, double hi, double delta_rel, double eps, Table& out);
 
 // Max error of the rescaled tables on their fit interval (for tests and reports).
 double coulomb_table_error(int S, double lo, double hi);

@@ -69,6 +69,10 @@ def test_argument_validation_statuses():
     assert _create(kernel=4, d=3)[0] == 1                # custom sum missing
     msg = _lib.lib().gs_last_error().decode()
     assert "custom" in msg
+    assert _create(kernel=6, d=3)[0] == 1                # inverse power without beta
+    assert _create(kernel=6, d=2, beta=2.0)[0] == 1      # beta must be below d
+    st, h = _create(kernel=6, d=3, beta=1.5)
+    assert st == 0 and _lib.lib().gs_plan_destroy(h) == 0
     assert _create(nlist=[16, 16, 32])[0] == 1           # n must agree on every axis
     assert _create(L=(4.0, 4.0, -1.0))[0] == 1
     assert _create(L=(1e-4, 4.0, 4.0))[0] == 1           # near-field ball wider than the short axis

@@ -409,3 +409,30 @@ def test_davey_stewartson_rectangle_mixture_gradient():
     u = plan.eval(r.detach())
     torch.cuda.synchronize()
     assert relmax(r.grad.cpu().numpy(), (plan.cell * u).cpu().numpy()) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# Inverse-power kernels |x|^-beta.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,n,L,beta", [(3, 12, 4.0, 0.5), (3, 48, 6.0, 2.5), (3, 24, (3.0, 4.0, 5.0), 1.7),
+                                        (2, 96, 7.0, 1.5), (2, 64, (5.0, 8.0), 0.4)])
+def test_inverse_power_random_input(d, n, L, beta):
+    rng = np.random.default_rng(600 + n)
+    rho = rng.standard_normal((n,) * d)
+    plan = gs.Plan("inverse_power", n=n, L=L, d=d, beta=beta)
+    ref = oracle.evaluate(oracle.make_plan("inverse_power", d, n, L, beta=beta), rho)
+    assert relmax(gpu_eval(plan, rho), ref) <= TOL
+
+
+@pytest.mark.parametrize("beta", [0.5, 2.0])
+def test_inverse_power_gaussian_closed_form(beta):
+    """exp(-|x|^2/1.44) on [-8,8]^3 at 96^3 against the 1-D integral and the origin value."""
+    from oracle import closed_forms as cf
+    n, L, s = 96, 8.0, 1.2
+    rho = workloads.gaussian(n, L, 3, sigma=s)
+    u = gpu_eval(gs.Plan("inverse_power", n=n, L=L, d=3, beta=beta), rho)
+    X = np.broadcast_arrays(*workloads.mesh(n, L, 3))
+    r = np.sqrt(sum(x * x for x in X))
+    assert relmax(u, cf.power_gaussian(r, beta, s, 3)) <= 1e-13
+    assert abs(u[n // 2, n // 2, n // 2] - cf.power_gaussian_origin(beta, s, 3)) <= 1e-13 * u.max()

@@ -70,3 +70,41 @@ def test_custom_gaussian_sum_host_plan():
     op = oracle.make_plan("gaussian_sum", 3, 16, 3.0, custom=(w, tau))
     assert p.info["A0"] == 0.0 and p.info["c2"] == 0.0
     assert np.max(np.abs(p.spectrum() - op.G_oct / 32 ** 3)) < 1e-15 * np.max(np.abs(op.G_oct / 32 ** 3))
+
+
+@pytest.mark.parametrize("d,n,L,beta", [(3, 16, 6.0, 0.5), (3, 12, (2.0, 3.0, 4.0), 2.5), (2, 48, 9.0, 1.5),
+                                        (2, 32, (4.0, 7.0), 0.3)])
+def test_inverse_power_host_plan_matches_oracle(d, n, L, beta):
+    import math
+    from oracle import gs_table
+    p = gs.Plan("inverse_power", n=n, L=L, d=d, beta=beta, host_only=True)
+    op = oracle.make_plan("inverse_power", d, n, L, beta=beta)
+    assert p.info["beta"] == beta
+    S = p.info["S"]
+    Ls = op.Ls
+    hi, Lu = gs_table.fit_interval_end(Ls), max(Ls)
+    wr, tr = op.table.w, op.table.tau
+    if S != op.table.S:
+        # S sits at the threshold, where the two error evaluations round differently:
+        # the oracle's own error at the library's S must be eps up to rounding
+        assert abs(S - op.table.S) == 1
+        assert gs_table.power_error(beta, S, 1e-4, hi, 1e-14) <= 1.05e-14
+        wt, tt = gs_table.power_nodes(beta, S, 1e-4, hi, 1e-14)
+        wr, tr = wt / Lu ** beta, tt / Lu
+    w, tau = p.table()
+    assert len(w) == len(wr)
+    assert np.max(np.abs(w - wr)) <= 4e-15 * np.max(np.abs(w))
+    assert np.max(np.abs(tau - tr)) <= 4.5e-16 * np.max(tau)
+    from oracle.factors import factor_1d
+    for ax in range(d):
+        assert np.max(np.abs(p.factors(ax) - factor_1d(tr, 2.0 * Ls[ax], n))) <= 5e-14 * 4 * Ls[ax]
+    # Taylor constants and spectrum of the reference table (the near-field constants
+    # depend on the table inside the ball, so they are formed from the same table)
+    from oracle.taylor import taylor_constants
+    ref_plan = oracle.make_plan("gaussian_sum", d, n, L, custom=(wr, tr))
+    ref_plan.A0, ref_plan.c2 = taylor_constants("inverse_power", d, op.table.delta, wr, tr, beta)
+    dl = p.info["delta"]
+    assert abs(p.info["A0"] - ref_plan.A0) <= 1e-12 * max(abs(ref_plan.A0), dl ** (d - beta))
+    assert abs(p.info["c2"] - ref_plan.c2) <= 1e-10 * max(abs(ref_plan.c2), dl ** (d + 2 - beta))
+    S, ref = p.spectrum(), _octant_ref(ref_plan)
+    assert np.max(np.abs(S - ref)) <= 1e-13 * np.max(np.abs(ref))
