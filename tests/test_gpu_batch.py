@@ -36,19 +36,25 @@ def relmax(a, b):
 MIXED = [("coulomb3d", 32, 10.0), ("coulomb3d", 48, 10.0), ("coulomb3d", 24, 6.0), ("coulomb3d", 64, 10.0),
          ("coulomb3d", 12, 3.0), ("coulomb3d", 96, 8.0), ("coulomb3d", 128, 10.0), ("coulomb3d", 8, 2.0),
          ("coulomb3d", 16, 4.0), ("dipolar3d", 16, 4.0), ("dipolar3d", 24, 5.0), ("coulomb2d", 48, 7.0),
-         ("poisson2d", 128, 7.0), ("coulomb2d", 8, 2.0)]
+         ("poisson2d", 128, 7.0), ("coulomb2d", 8, 2.0),
+         # the other kernel families and rectangular boxes share the batch path
+         ("davey_stewartson2d", 24, 6.0), ("inverse_power", 16, 5.0), ("coulomb3d", 24, (3.0, 5.0, 8.0)),
+         ("dipolar3d", 16, (4.0, 5.0, 6.0)), ("inverse_power", 48, (4.0, 4.0, 6.0))]
+
+
+def member_kw(k):
+    """Options of a member kernel, the same for the library and the oracle."""
+    if k == "dipolar3d":
+        return {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))}
+    if k in ("poisson2d", "davey_stewartson2d"):
+        return {"eps": 1e-13}
+    if k == "inverse_power":
+        return {"beta": 0.7}
+    return {}
 
 
 def make_plans(specs):
-    plans = []
-    for k, n, L in specs:
-        kw = {}
-        if k == "dipolar3d":
-            kw["dipole"] = ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))
-        if k == "poisson2d":
-            kw["eps"] = 1e-13
-        plans.append(gs.Plan(k, n=n, L=L, **kw))
-    return plans
+    return [gs.Plan(k, n=n, L=L, d=3 if k == "inverse_power" else None, **member_kw(k)) for k, n, L in specs]
 
 
 @pytest.fixture(scope="module")
@@ -106,8 +112,7 @@ def test_small_members_against_oracle(mixed):
     for (k, n, L), p, r, o in zip(MIXED, plans, rhos, outs):
         if n > 24:
             continue
-        kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if k == "dipolar3d" else {}
-        ref = oracle.evaluate(oracle.make_plan(k, p.d, n, L, **kw), r.cpu().numpy())
+        ref = oracle.evaluate(oracle.make_plan(k, p.d, n, L, **member_kw(k)), r.cpu().numpy())
         assert relmax(o.cpu().numpy(), ref) <= TOL, (k, n)
 
 
