@@ -87,7 +87,9 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
     const int tA = tid % G, pA = tid / G;      // load role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive y
     const int y0 = bx * 2 * PP;
-    const bool okA = active && (y0 + 2 * pA) < N, okB = active && (y0 + 2 * pB) < N;
+    // rows beyond n exist only when 2 PPX does not divide n
+    constexpr bool FULL = (N % (2 * PP) == 0);
+    const bool okA = active && (FULL || (y0 + 2 * pA) < N), okB = active && (FULL || (y0 + 2 * pB) < N);
 
     cpx x[E];
     {
@@ -150,7 +152,9 @@ __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<dou
     const int tA = tid % G, pA = tid / G;      // store role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive y
     const int y0 = bx * 2 * PP;
-    const bool okA = active && (y0 + 2 * pA) < N, okB = active && (y0 + 2 * pB) < N;
+    // rows beyond n exist only when 2 PPX does not divide n
+    constexpr bool FULL = (N % (2 * PP) == 0);
+    const bool okA = active && (FULL || (y0 + 2 * pA) < N), okB = active && (FULL || (y0 + 2 * pB) < N);
     gp<const cpx> in = X1 + (size_t)z * (N + 1) * N + y0 + 2 * pB;
 
     cpx acc[E];
@@ -211,7 +215,9 @@ __device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive z
     const int kx = kx0 + kxl;                         // slab-local and global kx
     const int z0 = bx * PP;
-    const bool okA = active && (z0 + pA) < N, okB = active && (z0 + pB) < N;
+    // z beyond n exists only when PPY does not divide n
+    constexpr bool FULL = (N % PP == 0);
+    const bool okA = active && (FULL || (z0 + pA) < N), okB = active && (FULL || (z0 + pB) < N);
 
     cpx x[E];
     {
@@ -256,7 +262,9 @@ __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive z
     const int kx = kx0 + kxl;
     const int z0 = bx * PP;
-    const bool okA = active && (z0 + pA) < N, okB = active && (z0 + pB) < N;
+    // z beyond n exists only when PPY does not divide n
+    constexpr bool FULL = (N % PP == 0);
+    const bool okA = active && (FULL || (z0 + pA) < N), okB = active && (FULL || (z0 + pB) < N);
     gp<const cpx> src = X2 + (size_t)kxl * 2 * N * N + z0 + pB;
 
     cpx acc[E];
@@ -461,7 +469,10 @@ __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const dou
     FusedRoles<N>::get(tid, t, h, pl);
     cpx* area = lds + (pl * 2 + h) * A;
     const int slot = g * PP + pl;
-    const bool ok = active && slot < npencils;
+    // in 3D the pencil count is a multiple of 2n, so groups of PP pencils never run past it
+    // when PP divides 2n; 2D has n + 1 pencils
+    constexpr bool FULL = (DIM == 3 && (2 * N) % PP == 0);
+    const bool ok = active && (FULL || slot < npencils);
     const int pencil = ok ? fused_pencil<N, DIM>(slot) : 0;
     cpx v[E];
     double sv[E];
