@@ -112,11 +112,13 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
 #pragma unroll
         for (int e = 0; e < E; ++e) lds[pB * A + lds_pad(tB + G * e)] = v[e];
         lds_barrier();
+        // k = tB + G e is below n/2 for e < E/2 (kept by both halves); at e = E/2 it is
+        // n/2 + tB, kept only by the even half's thread tB = 0; beyond it is never kept
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
+        for (int e = 0; e <= E / 2; ++e) {
+            if (e == E / 2 && !(h == 0 && tB == 0)) continue;
             const int k = tB + G * e;
-            const bool keep = h ? (k <= N / 2 - 1) : (k <= N / 2);
-            if (keep && okB) {
+            if (okB) {
                 const int kp = h ? (N - 1 - k) : ((N - k) % N);
                 const cpx zk = v[e], zp = lds[pB * A + lds_pad(kp)];
                 const cpx sa = cmk(0.5 * (zk.x + zp.x), 0.5 * (zk.y - zp.y));       // (Z + conj P)/2
