@@ -29,8 +29,8 @@ struct EvalArgs {
     // Launch variants (none changes a single bit of the result): bit p-1 clear selects
     // plain (cached) memory accesses for pass p instead of its cache-hint default;
     // fused_grid_mult = rounds of co-resident blocks in the persistent fused pass.
-    int hint_bits = 31;
-    int fused_grid_mult = 2;
+    int hint_bits = 27;
+    int fused_grid_mult = 4;
 };
 
 // Passes: 1 x_r2c, 2 y_fwd, 3 fused, 4 y_inv, 5 x_c2r.  `which` < 0 runs all five on the

@@ -49,11 +49,13 @@ template <bool NT, class T> __device__ __forceinline__ void stg(gp<T> p, T v) {
     if constexpr (NT) __builtin_nontemporal_store(v, p);
     else *p = v;
 }
-// chosen by measurement at n = 256 over whole five-pass chains (the fused pass keeps
-// its spectrum loads cached: the +ky and -ky pencils of a block read the same row): non-temporal loads
-// where the input is streamed once (P1, P3, P4), non-temporal stores where the
-// output is scattered in short runs (P2) or real (P5); P5 keeps its loads cached
-// because each Hermitian row is read twice (direct and mirrored)
+// Each pass is compiled with these hints and without (plain accesses); the launch picks per
+// pass (hint bits of the plan, default: hints for P1, P2, P4, P5 and plain P3, chosen by
+// measurement at n = 256 over whole five-pass chains): non-temporal loads where the input is
+// streamed once (P1, P4; P3's variant), non-temporal stores where the output is scattered in
+// short runs (P2) or real (P5); P5 keeps its loads cached because each Hermitian row is read
+// twice (direct and mirrored), and the fused pass its spectrum loads, because the +ky and
+// -ky pencils of a block read the same row
 constexpr int NT_P1 = 1, NT_P2 = 2, NT_P3 = 1, NT_P4 = 1, NT_P5 = 2;
 
 // ---------------------------------------------------------------------------
