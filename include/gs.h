@@ -133,8 +133,10 @@ void gs_options_default(gs_options* opt);
 /*
  * Precomputation (Algorithm 1, "Precomputation"): Gaussian-sum table by sinc
  * quadrature with the smallest S meeting `eps` on [delta, R] in units of the
- * largest half-width L (Section 3; relative error of 1/r, absolute error of
- * ln r; R = 2 sqrt(sum_j (L_j/L)^2), the largest distance in the box: 2 sqrt(d)
+ * largest half-width L (Section 3; relative error of 1/r and of r^-beta, absolute
+ * error of ln r; r^-beta through its Gaussian integral, eq. (Gauss_int) with the
+ * factor 1/2 of the half line, under tau = exp(t - e^-t);
+ * R = 2 sqrt(sum_j (L_j/L)^2), the largest distance in the box: 2 sqrt(d)
  * for a cube), the one-dimensional factor integrals of eq. (tensor) (eq.
  * (tensor_ani) for rectangular boxes) at the padded frequencies
  * xi = pi k/(2 L_j), k = 0..n, of every axis, the Taylor constants A0, c2
