@@ -28,6 +28,8 @@
  *     later call.  gs_last_error() returns a thread-local message.
  *   - A plan is used by one stream at a time.  Plans are independent: several
  *     plans may run concurrently on different streams.
+ *   - The environment variable GS_LOG_LEVEL (1: plan and batch decisions, 2: also
+ *     every error status) makes the library write one line per event to stderr.
  */
 #ifndef GS_H
 #define GS_H

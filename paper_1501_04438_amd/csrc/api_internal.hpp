@@ -46,6 +46,9 @@ namespace gsapi {
 
 // Records msg as this thread's last error and returns s.
 gs_status fail(gs_status s, const std::string& msg);
+// Writes one line "[gs] ..." to stderr when the environment variable GS_LOG_LEVEL is at
+// least `level` (1: plan and batch decisions, 2: also every error status).
+void log(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 gs_status hip_fail(hipError_t e, const char* what);
 // true while p is a plan created and not yet destroyed
 bool is_live(gs_plan p);

@@ -245,6 +245,8 @@ gs_status autotune(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const 
         b->cfg = best;
         b->autotuned = true;
         b->tuned_ms = best.ms;
+        log(1, "batch autotune (cached): schedule %d, %d tiles per task, %.4f ms", best.schedule,
+            best.tiles_per_task, best.ms);
         return GS_OK;
     }
     std::vector<TuneEntry> cand;
@@ -269,6 +271,8 @@ gs_status autotune(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const 
     b->cfg = best;
     b->autotuned = true;
     b->tuned_ms = best.ms;
+    log(1, "batch autotune: schedule %d, %d tiles per task, %.4f ms (%zu candidates timed)", best.schedule,
+        best.tiles_per_task, best.ms, cand.size());
     return GS_OK;
 }
 

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
@@ -31,7 +33,19 @@ std::unordered_set<gs_plan_s*> g_live;
 
 gs_status fail(gs_status s, const std::string& msg) {
     g_err = msg;
+    log(2, "error %d: %s", (int)s, msg.c_str());
     return s;
+}
+
+void log(int level, const char* fmt, ...) {
+    const char* env = std::getenv("GS_LOG_LEVEL");
+    if (!env || std::atoi(env) < level) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[gs] %s\n", buf);
 }
 
 gs_status hip_fail(hipError_t e, const char* what) {
@@ -439,6 +453,8 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
 
     if (host_only) {
         gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D, p->spec_host);
+        log(1, "host-only plan kernel=%d d=%d n=%d L=(%g, %g, %g) S=%d Q=%zu delta=%.3g A0=%.6g c2=%.6g", (int)k, d,
+            nn, p->Lc[0], p->Lc[1], p->Lc[2], p->table.S, p->table.w.size(), p->table.delta, p->A0, p->c2);
         std::lock_guard<std::mutex> g(g_live_mu);
         g_live.insert(p);
         *out = p;
@@ -489,6 +505,9 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         std::lock_guard<std::mutex> g(g_live_mu);
         g_live.insert(p);
     }
+    log(1, "plan kernel=%d d=%d n=%d L=(%g, %g, %g) S=%d Q=%zu delta=%.3g A0=%.6g c2=%.6g spectrum %zu B, "
+        "workspace %zu B, assembly %.3f ms", (int)k, d, nn, p->Lc[0], p->Lc[1], p->Lc[2], p->table.S,
+        p->table.w.size(), p->table.delta, p->A0, p->c2, p->spec_bytes, p->work_bytes, p->assembly_ms);
     if (opt.flags & GS_PLAN_AUTOTUNE) {
         // the plan is complete: the autotuner times it through the ordinary eval path
         st = plan_autotune(p);
@@ -722,6 +741,8 @@ gs_status plan_autotune(gs_plan_s* p) {
     if (st != GS_OK) return st;
     p->tuned = true;
     p->tuned_ms = best;
+    log(1, "plan autotune n=%d d=%d: hint bits %d, fused rounds %d, %.4f ms (%d variants timed)", p->n, p->d,
+        p->hint_bits, p->fused_mult, best, p->tune_candidates);
     te.schedule = p->hint_bits;          // plan entries: schedule = hint bits,
     te.tiles_per_task = p->fused_mult;   // tiles_per_task = fused grid rounds
     te.largest_first = 0;
