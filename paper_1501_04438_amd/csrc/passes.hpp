@@ -67,7 +67,9 @@ template <int N> struct Geo {
     static constexpr int E = F::E, G = F::G, A = LdsArea<N>::size;
     static constexpr int EZ = FZ::E, GZ = FZ::G, AZ = LdsAreaOf<FZ>::size;
     // P1/P5: pairs of real rows per block (2*PPX rows of y, 16-byte complex each)
-    static constexpr int PPX = (N <= 256) ? 8 : (N <= 512 ? 4 : (N <= 1024 ? 2 : 1));
+    // (at n = 2048 two pairs per block, not one: the transposed X1 accesses then move 64-byte
+    // runs instead of 32-byte ones; measured 0.069 -> 0.039 ms for the 2D x-inverse)
+    static constexpr int PPX = (N <= 256) ? 8 : (N <= 512 ? 4 : 2);
     // P2/P4: z-pencils per block
     static constexpr int PPY = (N <= 256) ? 16 : 8;
     // P3: pencils per block (two half-transforms each)
