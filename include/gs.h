@@ -121,7 +121,7 @@ typedef struct {
     int x2_planes;           /* kx planes the X2 workspace holds                  */
     int tuned;               /* 1 if the launch variants came from the autotuner  */
     int hint_bits;           /* bit p-1 set: pass p uses its cache-hint variant   */
-    int fused_grid_mult;     /* rounds of co-resident blocks of the fused pass    */
+    int fused_grid_mult;     /* rounds of co-resident blocks of the 3D fused pass */
     int tune_candidates;     /* variants timed when this plan was created         */
     double tuned_ms;         /* measured evaluation time of the chosen variant    */
     double L_axes[3];        /* half-widths as given, C order (first d entries);

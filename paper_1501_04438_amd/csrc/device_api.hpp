@@ -24,11 +24,12 @@ struct EvalArgs {
     double cdiag[3] = {0, 0, 0};
     double ccross[3] = {0, 0, 0};
     double nm_over_M = 0.0;
-    int max_blocks_fused = 0;         // persistent grid size of the fused pass (0 = device fill)
+    int max_blocks_fused = 0;         // persistent grid size of the 3D fused pass (0 = device fill)
     int kx0 = 0, kxn = 0;             // 3D passes 2-4: the kx slab [kx0, kx0 + kxn); X2 holds the slab
     // Launch variants (none changes a single bit of the result): bit p-1 clear selects
     // plain (cached) memory accesses for pass p instead of its cache-hint default;
-    // fused_grid_mult = rounds of co-resident blocks in the persistent fused pass.
+    // fused_grid_mult = rounds of co-resident blocks in the persistent fused pass (3D; the 2D
+    // fused pass runs one block per pencil group).
     int hint_bits = 27;
     int fused_grid_mult = 4;
 };

@@ -14,8 +14,7 @@
 namespace gsk {
 
 // Persistent grid of the fused pass: `mult` rounds of co-resident blocks, at most one
-// block per pencil group (default two rounds: measured at n = 256 marginally ahead of
-// one round and of one block per group).
+// block per pencil group (plan default four rounds, the autotuner's choice at n = 256).
 static inline unsigned fused_grid(int groups, int cap, int mult) {
     const long long c = (long long)(mult > 0 ? mult : 2) * cap;
     return (unsigned)((cap > 0 && groups > c) ? c : groups);
@@ -45,8 +44,7 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
     cpx* const X2 = reinterpret_cast<cpx*>(a.X2);
     const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
     static const int cap3 = resident_blocks((const void*)k_fused<N, 3, SPEC_PLAIN>, Gm::TZ);
-    static const int cap2 = resident_blocks((const void*)k_fused<N, 2, SPEC_PLAIN>, Gm::TZ);
-    const int capf = a.max_blocks_fused > 0 ? a.max_blocks_fused : (a.d == 3 ? cap3 : cap2);
+    const int capf = a.max_blocks_fused > 0 ? a.max_blocks_fused : cap3;
     const dim3 gx((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX), nz);
     auto run = [&](int p) { return which < 0 || which == p; };
     auto hint = [&](int p) { return (a.hint_bits >> (p - 1)) & 1; };
@@ -64,7 +62,8 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
             else k_y_fwd<N, 0><<<gy, Gm::TY, 0, s>>>(X1, X2, tw, a.kx0);
         }
         if (run(3)) {
-            const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf, fm);
+            const int groups = (np + Gm::PPZ - 1) / Gm::PPZ;
+            const unsigned nb = gs_fused_persistent(3, N) ? fused_grid(groups, capf, fm) : (unsigned)groups;
             if (a.dipolar) {
                 if (hint(3)) k_fused<N, 3, SPEC_DIPOLAR, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
                 else k_fused<N, 3, SPEC_DIPOLAR, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
@@ -85,8 +84,9 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
       }
     }
     if (run(3)) {
+        static_assert(!gs_fused_persistent(2, N), "the 2D fused pass runs one block per pencil group");
         const int np = N + 1;
-        const unsigned nb = fused_grid((np + Gm::PPZ - 1) / Gm::PPZ, capf, fm);
+        const unsigned nb = (unsigned)((np + Gm::PPZ - 1) / Gm::PPZ);
         if (hint(3)) k_fused<N, 2, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
         else k_fused<N, 2, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
     }

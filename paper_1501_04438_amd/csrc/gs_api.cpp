@@ -23,6 +23,7 @@
 #include "host_plan.hpp"
 #include "api_internal.hpp"
 #include "autotune.hpp"
+#include "sizes.hpp"
 
 
 namespace gsapi {
@@ -726,7 +727,7 @@ gs_status plan_autotune(gs_plan_s* p) {
         else p->hint_bits = keep;
     }
     for (int m : {1, 4}) {
-        if (st != GS_OK) break;
+        if (st != GS_OK || !gs_fused_persistent(p->d, p->n)) break;   // grid fixed by the group count
         const int keep = p->fused_mult;
         p->fused_mult = m;
         double ms = 0;
