@@ -224,13 +224,15 @@ def test_full_size_sampled_against_oracle(name):
     assert abs(E - float(g["energy"])) <= 1e-12 * scale
 
 
-def test_max_size_3d_1024_against_closed_form():
-    """The largest 3D grid (1024^3, 77 GB of device memory).  No oracle runs at this
-    size; the property checked is the method's accuracy against the exact potential
-    of a resolved Gaussian mixture well inside the box (closed form: the erf
-    potential of each Gaussian), at 2000 sampled points, to 1e-12 of the max norm."""
-    n, L = 1024, 10.0
-    rng = np.random.default_rng(1024)
+@pytest.mark.parametrize("n", [192, 512, 1024])
+def test_large_3d_against_closed_form(n):
+    """Large 3D grids up to the largest (1024^3, 77 GB of device memory), the fused pass
+    with one block per pencil group.  No oracle runs at these sizes; the property checked
+    is the method's accuracy against the exact potential of a resolved Gaussian mixture
+    well inside the box (closed form: the erf potential of each Gaussian), at 2000 sampled
+    points, to 1e-12 of the max norm."""
+    L = 10.0
+    rng = np.random.default_rng(n)
     K = 4
     a = rng.uniform(-1.0, 1.0, K)
     mu = rng.uniform(-1.0, 1.0, (K, 3))
