@@ -67,13 +67,19 @@ def measured_traffic(kernel: str):
     return t.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
 
 
-PROFILE_CMD = ("cd /tmp && export TMPDIR=/tmp && cd $GRAFT_REPO_ROOT && "
-               "timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o run --output-format csv "
-               "-- python3 bench.py --steps 5 --warmup 1 --no-extras --no-cpu-baseline && "
-               "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o run --output-format csv "
-               "-- python3 bench.py --steps 5 --warmup 1 --no-extras --no-cpu-baseline && "
-               "timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d gpurun_out/ktrace -o run --output-format csv "
-               "-- python3 bench.py --steps 20 --warmup 3 --no-extras --no-cpu-baseline")
+# The three profiled runs behind profiles/ (from the repository root, TMPDIR=/tmp, output
+# folders under {out}); each counter pass is its own run, bounded by a kill timeout.
+PROFILE_STEPS = (
+    "timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d {out}/pmc_fetch -o run --output-format csv "
+    "-- python3 bench.py --steps 5 --warmup 1 --no-extras --no-cpu-baseline",
+    "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d {out}/pmc_write -o run --output-format csv "
+    "-- python3 bench.py --steps 5 --warmup 1 --no-extras --no-cpu-baseline",
+    "timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d {out}/ktrace -o run --output-format csv "
+    "-- python3 bench.py --steps 20 --warmup 3 --no-extras --no-cpu-baseline")
+
+
+def profile_steps(out: str) -> list:
+    return [c.format(out=out) for c in PROFILE_STEPS]
 
 
 def _csv_rows(directory: str, suffix: str):
@@ -89,7 +95,7 @@ def _csv_rows(directory: str, suffix: str):
 def summarize_profiles(fetch_dir: str, write_dir: str, trace_dir: str, n: int = 256) -> int:
     """HBM traffic per launch of each pass from two rocprofv3 counter runs (FETCH_SIZE,
     WRITE_SIZE in KiB per dispatch) and the kernel-duration table from a kernel-trace
-    run, all of `python3 bench.py --no-extras --no-cpu-baseline` (PROFILE_CMD).  Each
+    run, all of `python3 bench.py --no-extras --no-cpu-baseline` (PROFILE_STEPS).  Each
     counter is scaled by what it reads for the bench's 2 GiB device-to-device copies
     (2 GiB read and 2 GiB written by definition)."""
     import statistics
@@ -124,7 +130,9 @@ def summarize_profiles(fetch_dir: str, write_dir: str, trace_dir: str, n: int = 
         wb = statistics.mean(write[k]) * wscale
         kern[k] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "bytes_per_launch": round(fb + wb),
                    "alg_bytes": nb[p], "ratio_to_alg": round((fb + wb) / nb[p], 3)}
-    traffic = {"source_hash": source_hash(), "n": n, "command": PROFILE_CMD,
+    out = os.path.dirname(os.path.normpath(fetch_dir)) or "."
+    steps = profile_steps(out)
+    traffic = {"source_hash": source_hash(), "n": n, "command": " && ".join(steps),
                "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
                "calibration": "median FETCH_SIZE / WRITE_SIZE of the bench's 2 GiB device-to-device copies",
                "kernels": kern}
@@ -133,7 +141,7 @@ def summarize_profiles(fetch_dir: str, write_dir: str, trace_dir: str, n: int = 
 
     rows = _csv_rows(trace_dir, "kernel_stats.csv")
     lines = [f"# Kernel durations: 3D Coulomb {n}^3 evaluation", "",
-             "Command (repo root on the GPU box):", "", "    " + PROFILE_CMD.split(" && ")[-1], "",
+             "Command (from the repository root on an MI355X, TMPDIR=/tmp):", "", "    " + steps[2], "",
              f"Source: {trace_dir}/.../run_kernel_stats.csv.  k_assemble is the plan-time spectrum assembly;",
              "__amd_rocclr_copyBuffer are the density upload and the bench's copy-bandwidth probe.", "",
              "| kernel | calls | average ns | min ns | max ns | share % |", "|---|---|---|---|---|---|"]
@@ -148,7 +156,7 @@ def summarize_profiles(fetch_dir: str, write_dir: str, trace_dir: str, n: int = 
     for k, v in kern.items():
         lines.append(f"| {k} | {v['fetch_bytes']} | {v['write_bytes']} | {v['bytes_per_launch']} | "
                      f"{v['alg_bytes']} | {v['ratio_to_alg']} |")
-    lines += ["", "Counter commands:", ""] + ["    " + c for c in PROFILE_CMD.split(" && ")[3:5]]
+    lines += ["", "Counter commands:", ""] + ["    " + c for c in steps[:2]]
     with open(os.path.join(ROOT, "profiles", f"eval_coulomb3d_{n}_kernel_stats.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print(json.dumps(traffic, indent=1))
