@@ -54,6 +54,7 @@ struct AssemblyArgs {
 // Row blocks per wave chosen for n1; returns the padded k length the operands need.
 int assembly_ldk(int n1);
 hipError_t launch_assembly(const AssemblyArgs& a, hipStream_t s);
+hipError_t load_assembly(const AssemblyArgs& a);   // loads the kernel's code object (no launch)
 
 // Batched evaluation of independent problems (sizes up to 128, batch.hpp).
 struct BatchMember {

@@ -70,6 +70,30 @@ static hipError_t launch_mb(const AssemblyArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Loads the code object of the assembly kernel that launch_assembly(a) will run (a kernel's
+// first launch in a process otherwise loads it on the host between the events that time it).
+template <int MB>
+static hipError_t load_mb(const AssemblyArgs& a) {
+    hipFuncAttributes attr;
+    return a.d == 3 ? hipFuncGetAttributes(&attr, (const void*)k_assemble<MB, 3>)
+                    : hipFuncGetAttributes(&attr, (const void*)k_assemble<MB, 2>);
+}
+
+hipError_t load_assembly(const AssemblyArgs& a) {
+    switch (assembly_mb(a.n1)) {
+        case 1: return load_mb<1>(a);
+        case 2: return load_mb<2>(a);
+        case 3: return load_mb<3>(a);
+        case 4: return load_mb<4>(a);
+        case 5: return load_mb<5>(a);
+        case 6: return load_mb<6>(a);
+        case 7: return load_mb<7>(a);
+        case 8: return load_mb<8>(a);
+        case 9: return load_mb<9>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_assembly(const AssemblyArgs& a, hipStream_t s) {
     switch (assembly_mb(a.n1)) {
         case 1: return launch_mb<1>(a, s);

@@ -129,6 +129,10 @@ gs_status device_assembly(gs_plan_s* p) {
         a.dxi[2] = M_PI / (2.0 * p->Lk[p->d - 1]);
         a.invM = 1.0 / std::pow(2.0 * p->n, p->d);
         a.dxx = p->kernel == GS_DAVEY_STEWARTSON_2D ? 1 : 0;
+        if ((e = gsk::load_assembly(a)) != hipSuccess) {
+            st = hip_fail(e, "spectrum assembly kernel load");
+            break;
+        }
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
         (void)hipEventRecord(e0, p->stream);
