@@ -48,13 +48,32 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[mb] = v4d{0.0, 0.0, 0.0, 0.0};
 
+    // operands of K step q0 + 4 are loaded while the MFMAs of step q0 run (the last
+    // step reloads its own rows)
+    double a[MB], fb, fc;
+    {
+        const size_t row = (size_t)kk * ldk;
+        fb = (DIM == 3) ? FB[row + k2] : 1.0;
+        fc = FC[row + k3];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) a[mb] = AT[row + k1base + i + mb * 16];
+    }
     for (int q0 = 0; q0 < Qp; q0 += 4) {
-        const size_t row = (size_t)(q0 + kk) * ldk;
-        const double b = (DIM == 3) ? FB[row + k2] * FC[row + k3] : FC[row + k3];
-        const double* aq = AT + row + k1base + i;
+        const int qn = (q0 + 4 < Qp) ? q0 + 4 : q0;
+        const size_t rown = (size_t)(qn + kk) * ldk;
+        double an[MB];
+        const double fbn = (DIM == 3) ? FB[rown + k2] : 1.0;
+        const double fcn = FC[rown + k3];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) an[mb] = AT[rown + k1base + i + mb * 16];
+        const double b = (DIM == 3) ? fb * fc : fc;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
-            acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[mb * 16], b, acc[mb], 0, 0, 0);
+            acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb], b, acc[mb], 0, 0, 0);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) a[mb] = an[mb];
+        fb = fbn;
+        fc = fcn;
     }
 
     const long c = col0 + (lane & 15);
