@@ -324,23 +324,48 @@ def _make_function():
         def backward(ctx, grad_u):
             return ctx.plan.eval_backward(grad_u.contiguous()), None
 
-    return GSPotential
+    class GSEnergy(torch.autograd.Function):
+        """E = 1/2 cell sum rho (A rho).  A is symmetric (the spectrum is real and even, and the
+        zero padding and the cropping are transposes of each other; the library's transposed
+        chain is the forward chain), so dE/drho = cell A rho = cell u: the backward reuses the
+        forward's potential instead of running the adjoint solve."""
+
+        @staticmethod
+        def forward(ctx, rho, plan):
+            rho = rho.contiguous()
+            u = plan.eval(rho)
+            ctx.save_for_backward(u)
+            ctx.cell = plan.cell
+            return 0.5 * plan.cell * (rho * u).sum()
+
+        @staticmethod
+        def backward(ctx, grad_e):
+            (u,) = ctx.saved_tensors
+            return (grad_e * ctx.cell) * u, None
+
+    return GSPotential, GSEnergy
 
 
 _GSPotential = None
+_GSEnergy = None
+
+
+def _functions():
+    global _GSPotential, _GSEnergy
+    if _GSPotential is None:
+        _GSPotential, _GSEnergy = _make_function()
+    return _GSPotential, _GSEnergy
 
 
 def potential(rho, plan: Plan):
-    global _GSPotential
-    if _GSPotential is None:
-        _GSPotential = _make_function()
-    return _GSPotential.apply(rho, plan)
+    """u = U * rho as a differentiable function of rho (backward: the adjoint solve)."""
+    return _functions()[0].apply(rho, plan)
 
 
 def energy(rho, plan: Plan):
-    """Hartree-type energy E = 1/2 int rho u, by the grid sum 1/2 (prod_j h_j) sum rho u."""
-    u = potential(rho, plan)
-    return 0.5 * plan.cell * (rho * u).sum()
+    """Hartree-type energy E = 1/2 int rho u, by the grid sum 1/2 (prod_j h_j) sum rho u;
+    differentiable in rho with one solve (dE/drho = prod_j h_j u, the operator being symmetric)."""
+    return _functions()[1].apply(rho, plan)
 
 
 def _half_widths(L, d: int) -> tuple:

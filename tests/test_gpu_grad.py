@@ -1,7 +1,8 @@
 """Differentiation on the GPU: the energy E = 1/2 h^d sum rho u of a Gaussian
 mixture and its gradient with respect to the mixture's amplitudes, centres and
-widths, through torch autograd over the adjoint chain (gs.potential).  Checked
-against the oracle's chain-rule gradient and against central differences."""
+widths, through torch autograd (gs.energy: one solve, its gradient prod_j h_j u; gs.potential:
+backward by the adjoint chain).  Checked against the oracle's chain-rule gradient, against
+central differences and the one-solve energy against the two-solve autograd path."""
 
 import numpy as np
 import pytest
@@ -89,3 +90,27 @@ def test_rho_gradient_is_h3_u_and_dot_test_256():
     lhs = float((u * v).sum())
     rhs = float((rho.detach() * plan.eval_backward(v)).sum())
     assert abs(lhs - rhs) <= 1e-14 * float(u.norm() * v.norm())
+
+
+@pytest.mark.parametrize("kernel,d,n", [("coulomb3d", 3, 48), ("dipolar3d", 3, 32), ("poisson2d", 2, 96),
+                                        ("davey_stewartson2d", 2, 64)])
+def test_one_solve_energy_equals_adjoint_path(kernel, d, n):
+    """gs.energy's backward uses the symmetry of the operator (gradient prod_j h_j u); the
+    generic path, 1/2 cell sum rho potential(rho) through autograd, runs the adjoint solve.
+    Both give the same energy and the same gradient to rounding."""
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    if d == 2:
+        kw["eps"] = 1e-13
+    plan = gs.Plan(kernel, n=n, L=6.0, **kw)
+    rng = np.random.default_rng(n + d)
+    x = torch.from_numpy(rng.standard_normal((n,) * d)).to("cuda:0")
+    r1 = x.clone().requires_grad_(True)
+    E1 = gs.energy(r1, plan)
+    E1.backward()
+    r2 = x.clone().requires_grad_(True)
+    E2 = 0.5 * plan.cell * (r2 * gs.potential(r2, plan)).sum()
+    E2.backward()
+    scale = float(0.5 * plan.cell * (x * plan.eval(x)).abs().sum())
+    assert abs(float(E1) - float(E2)) <= 1e-14 * scale
+    g2 = r2.grad
+    assert float((r1.grad - g2).abs().max()) <= 1e-13 * float(g2.abs().max())
