@@ -151,7 +151,9 @@ def test_kx_slabs_change_nothing(n, slabs):
     ref = gs.Plan("coulomb3d", n=n, L=4.0, slab_planes=-1).eval(x)
     for sp in slabs:
         plan = gs.Plan("coulomb3d", n=n, L=4.0, slab_planes=sp)
-        assert plan.info["slab_planes"] == min(sp, n + 1) or plan.info["slab_planes"] * 1 >= 1
+        # the requested planes per slab, balanced: ceil(n1 / number of slabs)
+        nsl = -(-(n + 1) // min(sp, n + 1))
+        assert plan.info["slab_planes"] == -(-(n + 1) // nsl)
         assert plan.steps().count(3) == -(-(n + 1) // plan.info["slab_planes"])
         assert torch.equal(plan.eval(x), ref)
 
