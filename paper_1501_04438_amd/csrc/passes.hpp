@@ -95,17 +95,23 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
     // rows beyond n exist only when 2 PPX does not divide n
     constexpr bool FULL = (N % (2 * PP) == 0);
     const bool okA = active && (FULL || (y0 + 2 * pA) < N), okB = active && (FULL || (y0 + 2 * pB) < N);
+    // the two real rows of pair p: y0 + p and y0 + PP + p when the tile divides the grid and
+    // holds 8 pairs (each 16-byte store instruction on the transposed X1 side then fills whole
+    // 128-byte lines: P1 at 256^3 0.0765 -> 0.0706 ms), else y0 + 2p and y0 + 2p + 1
+    constexpr bool SPLIT = FULL && PP >= 8;
+    constexpr int RS = SPLIT ? PP : 1;
+    const int rowA = SPLIT ? y0 + pA : y0 + 2 * pA, rowB = SPLIT ? y0 + pB : y0 + 2 * pB;
 
     cpx x[E];
     {
-        gp<const double> ra = rho + ((size_t)z * N + (y0 + 2 * pA)) * N;
+        gp<const double> ra = rho + ((size_t)z * N + rowA) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = tA + G * e;
-            x[e] = okA ? cmk(ldg<NT & 1>(ra + j), ldg<NT & 1>(ra + N + j)) : cmk(0.0, 0.0);
+            x[e] = okA ? cmk(ldg<NT & 1>(ra + j), ldg<NT & 1>(ra + (size_t)RS * N + j)) : cmk(0.0, 0.0);
         }
     }
-    gp<cpx> out = X1 + (size_t)z * (N + 1) * N + y0 + 2 * pB;
+    gp<cpx> out = X1 + (size_t)z * (N + 1) * N + rowB;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         cpx v[E];
@@ -132,7 +138,7 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
                 const int m = 2 * k + h;
                 gp<cpx> o = out + (size_t)m * N;
                 stg<(NT & 2) != 0>(o, sa);
-                stg<(NT & 2) != 0>(o + 1, sb);
+                stg<(NT & 2) != 0>(o + RS, sb);
             }
         }
         lds_barrier();
@@ -166,7 +172,12 @@ __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<dou
     // rows beyond n exist only when 2 PPX does not divide n
     constexpr bool FULL = (N % (2 * PP) == 0);
     const bool okA = active && (FULL || (y0 + 2 * pA) < N), okB = active && (FULL || (y0 + 2 * pB) < N);
-    gp<const cpx> in = X1 + (size_t)z * (N + 1) * N + y0 + 2 * pB;
+    // rows of pair p as in x_r2c_tile (y0 + p and y0 + PP + p when the tile divides the grid and
+    // holds 8 pairs: whole 128-byte lines per load instruction on the transposed X1 side)
+    constexpr bool SPLIT = FULL && PP >= 8;
+    constexpr int RS = SPLIT ? PP : 1;
+    const int rowA = SPLIT ? y0 + pA : y0 + 2 * pA, rowB = SPLIT ? y0 + pB : y0 + 2 * pB;
+    gp<const cpx> in = X1 + (size_t)z * (N + 1) * N + rowB;
 
     cpx acc[E];
 #pragma unroll
@@ -183,7 +194,7 @@ __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<dou
             if (okB) {
                 gp<const cpx> p = in + (size_t)mm * N;
                 a = ldg<NT & 1>(p);
-                b = ldg<NT & 1>(p + 1);
+                b = ldg<NT & 1>(p + RS);
             }
             if (!direct) { a.y = -a.y; b.y = -b.y; }
             v[e] = cmk(a.x - b.y, a.y + b.x);          // a + i b
@@ -195,12 +206,12 @@ __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<dou
         lds_barrier();
     }
     if (okA) {
-        gp<double> ua = u + ((size_t)z * N + (y0 + 2 * pA)) * N;
+        gp<double> ua = u + ((size_t)z * N + rowA) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = tA + G * e;
             stg<(NT & 2) != 0>(ua + j, acc[e].x);
-            stg<(NT & 2) != 0>(ua + N + j, acc[e].y);
+            stg<(NT & 2) != 0>(ua + (size_t)RS * N + j, acc[e].y);
         }
     }
 }
