@@ -238,7 +238,9 @@ typedef struct {
     int schedule;        /* gs_schedule                                               */
     int tiles_per_task;  /* block-fulls of tiles per task (>= 1); 0 = default (queue 16,
                             phased 4) or tuned                                        */
-    int grid;            /* persistent blocks; 0 = as many as can be co-resident        */
+    int grid;            /* persistent blocks; 0 = as many as can be co-resident.  The
+                            queue schedule with per-die queues raises a smaller grid to
+                            the co-resident count (every die must run blocks)          */
     int use_graph;       /* 1: capture the launch sequence in a hipGraph on the first
                             evaluation and replay it afterwards                         */
     void* stream;        /* hipStream_t the evaluations are ordered on; NULL = null stream */
@@ -281,8 +283,15 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
  * arrays of plans[i]'s shape (u[i] may alias rho[i]).  Asynchronous on the
  * batch's stream, except for the first call of a GS_SCHED_AUTO batch whose
  * shapes are not in the cache: that call times the candidates (each produces
- * the same result) and synchronises.  Calls on one batch must not overlap. */
+ * the same result) and synchronises.  Calls on one batch must not overlap.
+ * Returns GS_ERR_HIP when an earlier queue-schedule call of this batch, finished
+ * by now, raised the error flag that gs_batch_query reports (never expected). */
 gs_status gs_batch_eval(gs_batch b, const double* const* rho_dev, double* const* u_dev);
+
+/* Sets the stream later gs_batch_eval calls are ordered after (the caller's
+ * stream; NULL = null stream).  The batch's own work runs on a stream it owns,
+ * ordered between the caller's stream by events. */
+gs_status gs_batch_set_stream(gs_batch b, void* stream);
 
 /* Fills info; waits for the batch's stream (it reads the error flag). */
 gs_status gs_batch_query(gs_batch b, gs_batch_info* info);
@@ -292,7 +301,8 @@ gs_status gs_batch_query(gs_batch b, gs_batch_info* info);
 gs_status gs_batch_destroy(gs_batch b);
 
 /* One-shot form: creates a GS_SCHED_QUEUE batch on the first plan's stream,
- * evaluates once, waits for it and destroys the batch. */
+ * evaluates once, waits for it, checks the error flag (GS_ERR_HIP if it was
+ * raised) and destroys the batch. */
 gs_status gs_eval_batch(int count, const gs_plan* plans,
                         const double* const* rho_dev, double* const* u_dev);
 

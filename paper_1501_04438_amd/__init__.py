@@ -282,6 +282,8 @@ class Batch:
         n = len(self.plans)
         rs = (C.c_void_p * n)(*[r.data_ptr() for r in rhos])
         us = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        # ordered after the stream current at this call (as Plan.eval is)
+        check(lib().gs_batch_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
         check(lib().gs_batch_eval(self._h, rs, us))
         return outs
 

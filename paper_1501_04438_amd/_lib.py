@@ -72,6 +72,7 @@ SIGNATURES = {
                                   C.POINTER(GSBatchOptions)]),
     "gs_batch_eval": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "gs_batch_query": (C.c_int, [C.c_void_p, C.POINTER(GSBatchInfo)]),
+    "gs_batch_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gs_batch_destroy": (C.c_int, [C.c_void_p]),
     "gs_eval_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "gs_plan_steps": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int]),

@@ -39,6 +39,7 @@ struct gs_batch_s {
     unsigned* d_ctr = nullptr;
     int nctr = 0;
     unsigned char* h_stage = nullptr;     // pinned staging of the descriptors
+    unsigned* h_flag = nullptr;           // pinned copy of the error flag, refreshed after each queue launch
     std::vector<unsigned char> probs_dev; // descriptors now in device memory
     int ntasks = 0, pass_off[6] = {}, pass_cnt[6] = {};
     std::vector<int> runs;                // (pass, n, first task, count) of the sized schedule
@@ -74,6 +75,7 @@ void release(gs_batch_s* b) {
     if (b->d_tasks) (void)hipFree(b->d_tasks);
     if (b->d_ctr) (void)hipFree(b->d_ctr);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->h_flag) (void)hipHostFree(b->h_flag);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->ev_staged) (void)hipEventDestroy(b->ev_staged);
@@ -179,9 +181,19 @@ gs_status upload_probs(gs_batch_s* b, const std::vector<gsk::BatchMember>& m) {
 }
 
 // Queues one evaluation of the whole batch on the batch stream under cfg.
+// Persistent grid of a launch under c.  With per-die queues every die must run blocks of
+// the launch, or the queues of the dies without any are never drained: the grid is then
+// at least the co-resident block count (blocks of a full co-resident grid land on every
+// die).
+int launch_grid(const gs_batch_s* b, const TuneEntry& c) {
+    const int grid = c.grid > 0 ? c.grid : b->resident;
+    if (c.schedule == GS_SCHED_QUEUE && b->queues.local) return std::max(grid, b->resident);
+    return grid;
+}
+
 gs_status launch(gs_batch_s* b, const TuneEntry& c, const double* const* rho, double* const* u) {
     hipError_t e = hipSuccess;
-    const int grid = c.grid > 0 ? c.grid : b->resident;
+    const int grid = launch_grid(b, c);
     if (c.schedule == GS_SCHED_QUEUE) {
         e = gsk::launch_batch_queue(b->d_probs, b->d_tasks, b->queues, b->d_ctr, b->nctr, grid, kSpinLimit, b->own);
     } else if (c.schedule == GS_SCHED_PHASED) {
@@ -345,8 +357,10 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
         st = hip_fail(e, "hipEventCreate");
     if (st == GS_OK && (hipMalloc(&b->d_probs, b->probs_bytes) != hipSuccess ||
                         hipMalloc(&b->d_ctr, (b->nctr + 1) * sizeof(unsigned)) != hipSuccess ||
-                        hipHostMalloc(&b->h_stage, b->probs_bytes) != hipSuccess))
+                        hipHostMalloc(&b->h_stage, b->probs_bytes) != hipSuccess ||
+                        hipHostMalloc(&b->h_flag, sizeof(unsigned)) != hipSuccess))
         st = fail(GS_ERR_OUT_OF_MEMORY, "batch allocation failed");
+    if (st == GS_OK) *b->h_flag = 0u;
     if (st == GS_OK) {
         // the queue counters and the error flag start at zero; each queue launch
         // leaves the counters at zero
@@ -382,6 +396,11 @@ gs_status gs_batch_eval(gs_batch b, const double* const* rho, double* const* u) 
         if (!is_live(b->plans[i])) return fail(GS_ERR_INVALID_ARG, "a plan of the batch was destroyed");
         if (!rho[i] || !u[i]) return fail(GS_ERR_INVALID_ARG, "NULL device pointer in batch");
     }
+    // the error flag of an earlier queue launch, as far as its copy has arrived (the flag
+    // is sticky: once a launch raised it, every later check sees it)
+    if (*reinterpret_cast<volatile unsigned*>(b->h_flag))
+        return fail(GS_ERR_HIP, "an earlier queue-schedule evaluation of this batch left tasks unfinished "
+                                "(its results are invalid)");
     DeviceScope ds(b->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
     std::vector<gsk::BatchMember> m;
@@ -436,6 +455,10 @@ gs_status gs_batch_eval(gs_batch b, const double* const* rho, double* const* u) 
     } else {
         if ((st = launch(b, b->cfg, rho, u)) != GS_OK) return st;
     }
+    if (b->cfg.schedule == GS_SCHED_QUEUE &&
+        (e = hipMemcpyAsync(b->h_flag, b->d_ctr + b->nctr, sizeof(unsigned), hipMemcpyDeviceToHost, b->own)) !=
+            hipSuccess)
+        return hip_fail(e, "batch error flag copy");
     if ((e = hipEventRecord(b->ev_out, b->own)) != hipSuccess || (e = hipStreamWaitEvent(b->user, b->ev_out, 0)) != hipSuccess)
         return hip_fail(e, "batch stream ordering");
     return GS_OK;
@@ -448,7 +471,7 @@ gs_status gs_batch_query(gs_batch b, gs_batch_info* info) {
     info->points = b->points;
     info->schedule = b->resolved ? b->cfg.schedule : GS_SCHED_AUTO;
     info->tiles_per_task = b->cfg.tiles_per_task;
-    info->grid = b->cfg.grid > 0 ? b->cfg.grid : b->resident;
+    info->grid = launch_grid(b, b->cfg);
     info->use_graph = b->req.use_graph;
     info->num_tasks = b->ntasks;
     for (int p = 0; p < 6; ++p) info->tasks_per_pass[p] = b->pass_cnt[p];
@@ -490,8 +513,21 @@ gs_status gs_eval_batch(int count, const gs_plan* plans, const double* const* rh
     gs_status st = gs_batch_create(&b, count, plans, &opt);
     if (st != GS_OK) return st;
     st = gs_batch_eval(b, rho_dev, u_dev);
+    if (st == GS_OK) {
+        // waits for the evaluation and reads the error flag
+        gs_batch_info info;
+        st = gs_batch_query(b, &info);
+        if (st == GS_OK && info.wait_timeouts)
+            st = fail(GS_ERR_HIP, "batched evaluation left tasks unfinished (results invalid)");
+    }
     const gs_status st2 = gs_batch_destroy(b);
     return st != GS_OK ? st : st2;
+}
+
+gs_status gs_batch_set_stream(gs_batch b, void* stream) {
+    if (!batch_live(b)) return fail(GS_ERR_INVALID_ARG, "invalid batch");
+    b->user = (hipStream_t)stream;
+    return GS_OK;
 }
 
 }  // extern "C"

@@ -177,3 +177,37 @@ def test_config4_batch_of_64():
     i = min(range(64), key=lambda k: probs[k].n)
     ref = oracle.evaluate(oracle.make_plan("coulomb3d", 3, probs[i].n, probs[i].L), probs[i].rho)
     assert relmax(outs[i].cpu().numpy(), ref) <= TOL
+
+
+def test_queue_schedule_small_grid_is_raised(mixed):
+    """With per-die queues a grid below the co-resident block count would leave the
+    queues of dies without blocks undrained: the library raises it, the results stay
+    bitwise those of single evaluations and the error flag stays clear."""
+    plans, rhos, refs = mixed
+    b = gs.Batch(plans, schedule="queue", grid=3)
+    outs = b.eval(rhos)
+    torch.cuda.synchronize()
+    info = b.info
+    assert info["wait_timeouts"] == 0
+    if info["local_queues"]:
+        assert info["grid"] > 3
+    for o, r in zip(outs, refs):
+        assert torch.equal(o, r)
+    b.close()
+
+
+def test_batch_follows_the_current_stream(mixed):
+    """Batch.eval orders its work after the stream current at the call, not the one
+    current at creation: inputs written on a side stream are read after that write."""
+    plans, rhos, refs = mixed
+    b = gs.Batch(plans, schedule="phased")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        copies = [torch.empty_like(r) for r in rhos]
+        for c, r in zip(copies, rhos):
+            c.copy_(r)
+        outs = b.eval(copies)
+    side.synchronize()
+    for o, r in zip(outs, refs):
+        assert torch.equal(o, r)
+    b.close()
