@@ -332,6 +332,43 @@ static void gauss_legendre(int m, std::vector<double>& x, std::vector<double>& w
 
 // tau c >= 6.5: the truncation of the Gaussian at |y| = c is below 1e-19 relative
 static const double TAU_C_CLOSED = 6.5;
+// tau c <= 0.05: the power series of exp(-tau^2 y^2) in tau^2 with the exact cosine moments
+static const double TAU_C_SERIES = 0.05;
+
+// Neumaier's compensated summation: s + e carries the sum to about one rounding of s.
+struct CompSum {
+    double s = 0.0, e = 0.0;
+    void add(double x) {
+        const double t = s + x;
+        e += (std::fabs(s) >= std::fabs(x)) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    double value() const { return s + e; }
+};
+
+// Small tau c: g(tau, xi_k) = sum_i (-tau^2)^i / i! M_2i(k) with the exact moments
+// M_2i(k) = int_{-c}^{c} y^2i cos(pi k y / c) dy = c^(2i+1) m_2i(pi k),
+//   m_2i(0) = 2 / (2i + 1),
+//   m_0(a) = 0, m_2i(a) = (4i cos a - 2i (2i - 1) m_2i-2(a)) / a^2   (a = pi k, k >= 1),
+// by parts twice (sin a = 0).  For tau c <= 0.05 the recurrence's growth at small k,
+// (2i)!/(pi k)^2i, is outweighed by the series weight (tau c)^2i / i!: each term is
+// exact to a few roundings of itself, and ten terms reach below 1e-25 relative.
+static void factor_series(double t, double c, int n, int Q, int q, std::vector<double>& F) {
+    const long double tc2 = (long double)t * t * c * c;
+    for (int k = 0; k <= n; ++k) {
+        const long double a = (long double)PI * k, a2 = a * a;
+        const long double cosa = (k & 1) ? -1.0L : 1.0L;
+        long double m = (k == 0) ? 2.0L : 0.0L;          // m_0
+        long double coef = 1.0L, sum = 0.0L;             // (-tau^2 c^2)^i / i!
+        for (int i = 0; i < 10; ++i) {
+            sum += coef * m;
+            const int j = 2 * (i + 1);                  // next moment index
+            m = (k == 0) ? 2.0L / (j + 1) : (2.0L * j * cosa - (long double)j * (j - 1) * m) / a2;
+            coef *= -tc2 / (i + 1);
+        }
+        F[(size_t)k * Q + q] = (double)(sum * c);
+    }
+}
 
 void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<double>& F) {
     const int Q = (int)tau.size();
@@ -347,6 +384,8 @@ void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<dou
                 const double xi = PI * k / c;
                 F[(size_t)k * Q + q] = std::sqrt(PI) / t * std::exp(-(xi * xi) / (4.0 * t * t));
             }
+        } else if (t * c <= TAU_C_SERIES) {
+            factor_series(t, c, n, Q, q, F);
         } else {
             mid.push_back(q);
         }
@@ -355,7 +394,8 @@ void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<dou
     // Composite Gauss-Legendre on [0, c] (even integrand, factor 2): P panels of
     // GL_M nodes, at most one half-period of cos(xi_k y) per panel.  At node
     // y = c (p + s)/P the phase pi k (p + s)/P is split into an exactly reduced
-    // integer part pi ((k p) mod 2P)/P and a part pi k s/P <= pi.
+    // integer part pi ((k p) mod 2P)/P and a part pi k s/P <= pi.  The panel
+    // contributions are summed with compensation (up to 2048 panels).
     const int P = std::max(n, 8);
     const int Qm = (int)mid.size();
     std::vector<double> xg, wg;
@@ -374,18 +414,20 @@ void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<dou
         }
     std::vector<double> cosA(2 * P), sinA(2 * P);
     for (int m = 0; m < 2 * P; ++m) {
-        cosA[m] = std::cos(PI * m / P);
-        sinA[m] = std::sin(PI * m / P);
+        const long double a = 3.141592653589793238462643383279502884L * (long double)m / (long double)P;
+        cosA[m] = (double)cosl(a);
+        sinA[m] = (double)sinl(a);
     }
     parallel_for(n + 1, [&](int k0, int k1) {
-        std::vector<double> acc(Qm), cb(GL_M), sb(GL_M);
+        std::vector<CompSum> acc(Qm);
+        std::vector<double> cb(GL_M), sb(GL_M);
         for (int k = k0; k < k1; ++k) {
             for (int i = 0; i < GL_M; ++i) {
-                const double B = PI * (k * s[i]) / P;
-                cb[i] = std::cos(B);
-                sb[i] = std::sin(B);
+                const long double B = 3.141592653589793238462643383279502884L * ((long double)k * s[i]) / P;
+                cb[i] = (double)cosl(B);
+                sb[i] = (double)sinl(B);
             }
-            std::fill(acc.begin(), acc.end(), 0.0);
+            std::fill(acc.begin(), acc.end(), CompSum());
             for (int p = 0; p < P; ++p) {
                 const int m = (int)(((long long)k * p) % (2 * P));
                 const double ca = cosA[m], sa = sinA[m];
@@ -396,59 +438,71 @@ void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<dou
                         dc += g[qi * GL_M + i] * cb[i];
                         ds += g[qi * GL_M + i] * sb[i];
                     }
-                    acc[qi] += ca * dc - sa * ds;
+                    acc[qi].add(ca * dc - sa * ds);
                 }
             }
-            for (int qi = 0; qi < Qm; ++qi) F[(size_t)k * Q + mid[qi]] = acc[qi];
+            for (int qi = 0; qi < Qm; ++qi) F[(size_t)k * Q + mid[qi]] = acc[qi].value();
         }
     });
 }
 
 // ------------------------------------------------------------------ Taylor constants
 
+// A0 and c2 are small differences of moments (for the ln kernel c2 is about 1e-6 of the
+// moments it is formed from: the Gaussian sum follows U deep into the ball), so the
+// moments and their sums are formed in extended precision (x86 long double, 64-bit
+// significand) and rounded once.
+typedef long double ld;
+static const ld PI_L = 3.141592653589793238462643383279502884L;
+
 // gamma_m(tau) = int_0^delta r^m exp(-tau^2 r^2) dr, m = 1..4, without cancellation:
-// a power series in u = tau delta for u <= 1, the closed recurrences otherwise.
-static double gamma_moment(int m, double tau, double delta) {
-    const double u = tau * delta;
-    if (u <= 1.0) {
-        // delta^{m+1} sum_i (-u^2)^i / (i! (m + 1 + 2i))
-        double term = 1.0, sum = 0.0;
-        const double u2 = u * u;
-        for (int i = 0; i < 40; ++i) {
+// a power series in u = tau delta for u <= 3 (largest term e^9, four of the nineteen
+// digits), the closed forms through the incomplete gamma function otherwise
+// (gamma_m = gammainc((m+1)/2, u^2) / (2 tau^(m+1)); the subtracted terms are below
+// e^-9 of the first).
+static ld gamma_moment(int m, double tau, double delta) {
+    const ld t = tau, dl = delta, u = t * dl;
+    if (u <= 3.0L) {
+        // delta^(m+1) sum_i (-u^2)^i / (i! (m + 1 + 2i))
+        ld term = 1.0L, sum = 0.0L;
+        const ld u2 = u * u;
+        for (int i = 0; i < 80; ++i) {
             sum += term / (m + 1 + 2 * i);
             term *= -u2 / (i + 1);
         }
-        return std::pow(delta, m + 1) * sum;
+        return powl(dl, m + 1) * sum;
     }
-    const double t2 = tau * tau, e = std::exp(-u * u);
-    const double I0 = std::sqrt(PI) * std::erf(u) / (2.0 * tau);
-    const double I1 = -std::expm1(-u * u) / (2.0 * t2);
+    const ld u2 = u * u, e = expl(-u2);
+    const ld g12 = sqrtl(PI_L) * erfl(u);                 // gammainc(1/2, u^2)
+    const ld g1 = -expm1l(-u2);                           // gammainc(1, u^2)
+    const ld g32 = 0.5L * g12 - u * e;                    // gammainc(3/2, u^2)
+    const ld g2 = g1 - u2 * e;                            // gammainc(2, u^2)
+    const ld g52 = 1.5L * g32 - u2 * u * e;               // gammainc(5/2, u^2)
+    ld g = 0.0L;
     switch (m) {
-        case 1: return I1;
-        case 2: return I0 / (2.0 * t2) - delta * e / (2.0 * t2);
-        case 3: return I1 / t2 - delta * delta * e / (2.0 * t2);
-        case 4: {
-            const double I2 = I0 / (2.0 * t2) - delta * e / (2.0 * t2);
-            return 3.0 * I2 / (2.0 * t2) - delta * delta * delta * e / (2.0 * t2);
-        }
+        case 1: g = g1; break;
+        case 2: g = g32; break;
+        case 3: g = g2; break;
+        case 4: g = g52; break;
     }
-    return 0.0;
+    return g / (2.0L * powl(t, m + 1));
 }
 
 // int_0^delta r^m U(r) dr for the kernel (constants included)
-static double u_moment(int kernel, int m, double delta, double beta) {
+static ld u_moment(int kernel, int m, double delta, double beta) {
+    const ld dl = delta;
     switch (kernel) {
-        case INVERSE_POWER: return std::pow(delta, m + 1 - beta) / (m + 1 - beta);
+        case INVERSE_POWER: return powl(dl, m + 1 - (ld)beta) / (m + 1 - (ld)beta);
         case COULOMB_3D:
-        case DIPOLAR_3D: return std::pow(delta, m) / (4.0 * PI * m);
-        case COULOMB_2D: return std::pow(delta, m) / (2.0 * PI * m);
+        case DIPOLAR_3D: return powl(dl, m) / (4.0L * PI_L * m);
+        case COULOMB_2D: return powl(dl, m) / (2.0L * PI_L * m);
         case POISSON_2D:
         case DAVEY_STEWARTSON_2D: {
-            const double a = m + 1;
-            return -std::pow(delta, a) * (std::log(delta) / a - 1.0 / (a * a)) / (2.0 * PI);
+            const ld a = m + 1;
+            return -powl(dl, a) * (logl(dl) / a - 1.0L / (a * a)) / (2.0L * PI_L);
         }
     }
-    return 0.0;
+    return 0.0L;
 }
 
 void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2) {
@@ -456,15 +510,15 @@ void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2)
         A0 = c2 = 0.0;
         return;
     }
-    const double area = (d == 3) ? 4.0 * PI : 2.0 * PI;
+    const ld area = (d == 3) ? 4.0L * PI_L : 2.0L * PI_L;
     const int m0 = d - 1, m2 = d + 1;
-    double s0 = u_moment(kernel, m0, t.delta, t.beta), s2 = u_moment(kernel, m2, t.delta, t.beta);
+    ld s0 = u_moment(kernel, m0, t.delta, t.beta), s2 = u_moment(kernel, m2, t.delta, t.beta);
     for (size_t q = 0; q < t.w.size(); ++q) {
-        s0 -= t.w[q] * gamma_moment(m0, t.tau[q], t.delta);
-        s2 -= t.w[q] * gamma_moment(m2, t.tau[q], t.delta);
+        s0 -= (ld)t.w[q] * gamma_moment(m0, t.tau[q], t.delta);
+        s2 -= (ld)t.w[q] * gamma_moment(m2, t.tau[q], t.delta);
     }
-    A0 = area * s0;
-    c2 = area * s2 / (2.0 * d);
+    A0 = (double)(area * s0);
+    c2 = (double)(area * s2 / (2.0L * d));
 }
 
 // ------------------------------------------------------------------ host assembly

@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 import paper_1501_04438_amd as gs
+from oracle.factors import factor_1d
 
 
 def _octant_ref(op):
@@ -22,6 +23,26 @@ def _octant_ref(op):
         xi = oracle.padded_frequencies(n, op.Ls[d - 1])[: n + 1]
         S = S * -(xi ** 2)[:, None]
     return S
+
+
+def _factors_and_constants(p, kernel, d, n, beta=None):
+    """The factor integrals and the Taylor constants of the library against the oracle's,
+    formed from the library's own table (the tables are compared separately; a table
+    that differs by an ulp moves A0 and c2, small differences of moments, by far more).
+    Factors: 4e-16 of 4 L_j (two roundings).  A0, c2: 1e-14 relative, or of delta^2 and
+    delta^4 (physical delta) where the constant is smaller than that: the ln kernel's c2
+    is about 1e-6 delta^4, a difference of moments of size delta^4."""
+    from oracle.taylor import taylor_constants
+    w, tau = p.table()
+    for ax in range(d):
+        Lj = p.Ls[ax]
+        assert np.max(np.abs(p.factors(ax) - factor_1d(tau, 2.0 * Lj, n))) <= 4e-16 * 4 * Lj
+    if kernel == "gaussian_sum":
+        return
+    dl = p.info["delta"]
+    A0, c2 = taylor_constants(kernel, d, dl, w, tau, beta)
+    assert abs(p.info["A0"] - A0) <= 1e-14 * max(abs(A0), dl ** 2)
+    assert abs(p.info["c2"] - c2) <= 1e-14 * max(abs(c2), dl ** 4)
 
 
 CASES = [("coulomb3d", 3, 16, 8.0, 1e-14), ("coulomb3d", 3, 24, 10.0, 1e-14), ("coulomb2d", 2, 64, 12.0, 1e-14),
@@ -44,15 +65,8 @@ def test_host_plan_matches_oracle(kernel, d, n, L, eps):
     assert np.max(np.abs(w - op.table.w)) <= 2e-15 * np.max(np.abs(w))
     # tau = sqrt(s)/delta rounds independently on both sides: two ulps of the largest
     assert np.max(np.abs(tau - op.table.tau)) <= 4.5e-16 * np.max(tau)
-    for ax in range(d):
-        F = p.factors(ax)
-        assert np.max(np.abs(F - op.Fs[ax])) <= 5e-14 * 4 * op.Ls[ax]
+    _factors_and_constants(p, kernel, d, n)
     assert np.array_equal(p.factors(), p.factors(d - 1))
-    # A0 and c2 are differences of moments of size delta^2 and delta^4 (physical
-    # delta); compare on that scale (their effect on u is A0 rho + c2 Lap rho)
-    dl = p.info["delta"]
-    assert abs(p.info["A0"] - op.A0) <= 1e-12 * max(abs(op.A0), dl ** 2)
-    assert abs(p.info["c2"] - op.c2) <= 1e-10 * max(abs(op.c2), dl ** 4)
     S = p.spectrum()
     ref = _octant_ref(op)
     if kernel == "davey_stewartson2d":
@@ -95,16 +109,22 @@ def test_inverse_power_host_plan_matches_oracle(d, n, L, beta):
     assert len(w) == len(wr)
     assert np.max(np.abs(w - wr)) <= 4e-15 * np.max(np.abs(w))
     assert np.max(np.abs(tau - tr)) <= 4.5e-16 * np.max(tau)
-    from oracle.factors import factor_1d
-    for ax in range(d):
-        assert np.max(np.abs(p.factors(ax) - factor_1d(tr, 2.0 * Ls[ax], n))) <= 5e-14 * 4 * Ls[ax]
+    _factors_and_constants(p, "inverse_power", d, n, beta)
     # Taylor constants and spectrum of the reference table (the near-field constants
     # depend on the table inside the ball, so they are formed from the same table)
     from oracle.taylor import taylor_constants
     ref_plan = oracle.make_plan("gaussian_sum", d, n, L, custom=(wr, tr))
     ref_plan.A0, ref_plan.c2 = taylor_constants("inverse_power", d, op.table.delta, wr, tr, beta)
-    dl = p.info["delta"]
-    assert abs(p.info["A0"] - ref_plan.A0) <= 1e-12 * max(abs(ref_plan.A0), dl ** (d - beta))
-    assert abs(p.info["c2"] - ref_plan.c2) <= 1e-10 * max(abs(ref_plan.c2), dl ** (d + 2 - beta))
     S, ref = p.spectrum(), _octant_ref(ref_plan)
     assert np.max(np.abs(S - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("kernel,d,n,L,eps", [("poisson2d", 2, 512, 12.0, 1e-13), ("poisson2d", 2, 2048, 12.0, 1e-13),
+                                              ("coulomb3d", 3, 256, 10.0, 1e-14), ("coulomb2d", 2, 2048, 12.0, 1e-14)])
+def test_full_size_factors_and_constants(kernel, d, n, L, eps):
+    """The workload sizes (2D 512^2 and 2048^2: up to 2048 Gauss-Legendre panels per
+    factor; the ln table's tiny tau, tau c down to 1e-7, by the exact-moment series),
+    to the same bars."""
+    p = gs.Plan(kernel, n=n, L=L, eps=eps, host_only=True)
+    assert p.info["S"] == oracle.gs_table.physical_table(kernel, d, (L,) * d, eps, 1e-4).S
+    _factors_and_constants(p, kernel, d, n)

@@ -699,3 +699,75 @@ def test_power_table_and_taylor_constants(beta, d):
     assert abs(c2 - float(q2)) <= 1e-12 * abs(float(q2))
     with pytest.raises(ValueError):
         gs_table.physical_table("inverse_power", d, 9.0, 1e-13, beta=float(d))
+
+
+# --------------------------------------------------------------------------
+# Order of the near-field Taylor correction (Section 2.3, the bound after
+# eq. (taylor)): with the Taylor constants of the ball |y| < delta, the
+# remainder of the near-field integral is O(delta^(d+3)) for the Coulomb kernels
+# and O(delta^6 |ln delta|) for the logarithmic one.
+# --------------------------------------------------------------------------
+
+_U_MP = {"coulomb3d": lambda r: 1 / (4 * mp.pi * r), "coulomb2d": lambda r: 1 / (2 * mp.pi * r),
+         "poisson2d": lambda r: -mp.log(r) / (2 * mp.pi)}
+
+
+def _near_field_remainder(kernel, d, delta, w, tau, x=0.7):
+    """|N - (A0 rho(x) + c2 Lap rho(x))| for rho = exp(-|y|^2) at |x| = 0.7, where
+    N = int_{|y|<delta} (U - U_GS)(|y|) rho(x - y) dy by mpmath quadrature over the
+    radius of the exact spherical mean of the Gaussian (3D: e^{-(a^2+r^2)} sinh(2ar)/(2ar),
+    2D: e^{-(a^2+r^2)} I0(2ar)); A0, c2 from the oracle for the table (w, tau)."""
+    with mp.workdps(40):
+        a = mp.mpf(x)
+
+        def mean(r):
+            z = 2 * a * r
+            rad = mp.e ** (-(a * a + r * r))
+            return rad * (mp.sinh(z) / z if d == 3 else mp.besseli(0, z))
+
+        def ugs(r):
+            return sum(mp.mpf(wq) * mp.e ** (-(mp.mpf(tq) * r) ** 2) for wq, tq in zip(w, tau))
+
+        area = 4 * mp.pi if d == 3 else 2 * mp.pi
+        N = area * mp.quad(lambda r: r ** (d - 1) * (_U_MP[kernel](r) - ugs(r)) * mean(r), [0, delta])
+        A0, c2 = taylor_constants(kernel, d, delta, w, tau)
+        rho = mp.e ** (-a * a)
+        lap = rho * (4 * a * a - 2 * d)
+        return float(abs(N - (A0 * rho + c2 * lap)))
+
+
+@pytest.mark.parametrize("kernel,d", [("coulomb3d", 3), ("coulomb2d", 2), ("poisson2d", 2)])
+@pytest.mark.parametrize("table", ["none", "two_terms"])
+def test_taylor_remainder_delta_order(kernel, d, table):
+    """Halving delta divides the remainder by 2^(d+3) (Coulomb) or by 2^6 up to the
+    |ln delta| factor (ln kernel): a dropped or mis-scaled term of A0 or c2 leaves a
+    remainder of order delta^(d-1) or delta^(d+1) and fails the slope.  With a Gaussian
+    sum in the ball its smooth part only adds terms of higher order."""
+    w, tau = ([], []) if table == "none" else ([0.3, -0.1], [0.0, 2.5])
+    ds = [0.0125, 0.025, 0.05]
+    e = np.array([_near_field_remainder(kernel, d, dl, w, tau) for dl in ds])
+    if kernel == "poisson2d":
+        # delta^6 (a |ln delta| + b): local slopes 6 + 1/ln delta, about 5.7 here
+        slopes = np.diff(np.log(e)) / np.diff(np.log(ds))
+        assert np.all((slopes > 5.3) & (slopes < 6.1)), slopes
+        if table == "none":                    # the logarithmic factor itself
+            ratio = e / np.array([dl ** 6 * abs(math.log(dl)) for dl in ds])
+            assert np.max(ratio) / np.min(ratio) < 1.05, ratio
+    else:
+        slopes = np.diff(np.log(e)) / np.diff(np.log(ds))
+        assert np.all(np.abs(slopes - (d + 3)) < 0.1), slopes
+
+
+@pytest.mark.parametrize("tau", [1e-9, 1e-6, 1e-3, 0.004])
+def test_factors_small_tau_relative_to_their_size(tau):
+    """tau c <= 0.05 (the ln table's tiny exponents): the factors at k >= 1 are of the size
+    (tau c)^2 c, far below 4L; mpmath quadrature over half-periods fixes them to 1e-15 of
+    their own size, not only of 4L (the Davey-Stewartson symbol -xi_x^2 amplifies their
+    absolute error)."""
+    c, n = 12.0, 192
+    F = factor_1d(np.array([tau]), c, n)[:, 0]
+    with mp.workdps(40):
+        for k in (0, 1, 2, 7, 50, n // 2, n):
+            ex = mp.quad(lambda y: mp.e ** (-(tau * y) ** 2) * mp.cos(mp.pi * k * y / c),
+                         mp.linspace(-c, c, 2 * max(k, 1) + 1))
+            assert abs(F[k] - float(ex)) <= 1e-15 * abs(float(ex)), (k, F[k], ex)
