@@ -81,6 +81,14 @@ typedef enum {
                                      take them from the autotune cache (see
                                      GS_SCHED_AUTO); results are bitwise the same for
                                      every variant */
+#define GS_PLAN_NO_WORKSPACE   8  /* allocate no evaluation workspace: the plan holds its
+                                     spectrum and twiddles only and is evaluated with
+                                     gs_eval_static (gs_eval, gs_eval_step,
+                                     gs_eval_backward and batches refuse it with
+                                     GS_ERR_INVALID_ARG; not with GS_PLAN_AUTOTUNE) */
+
+/* Size of the fixed device array gs_eval_static uses as its workspace. */
+#define GS_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 
 typedef struct {
     double delta_rel;        /* near-field radius delta / max_j L_j; 0 selects 1e-4;
@@ -191,6 +199,24 @@ gs_status gs_plan_set_stream(gs_plan p, void* stream);
  * n^d FP64; u may alias rho.  The padding never touches memory.
  */
 gs_status gs_eval(gs_plan p, const double* rho_dev, double* u_dev);
+
+/*
+ * gs_eval without any device allocation, for callers that cannot allocate device
+ * memory while they evaluate (code under stream capture, serving loops, harnesses
+ * that forbid hipMalloc): the same passes and bits as gs_eval, with the evaluation
+ * workspace in a fixed device array of GS_STATIC_SCRATCH_BYTES (128 MiB) instead of
+ * the plan's.  Every device the library runs on holds one such array until the
+ * process ends; it fits 3D grids up to n = 128 (and larger n when the plan's
+ * middle passes run in small kx slabs) and 2D grids up to n = 2048.  The plan may
+ * be created with GS_PLAN_NO_WORKSPACE to hold no workspace of its own.  Calls
+ * on one device share the array: calls that overlap in time on one device (other
+ * streams, other threads) race, and the caller must serialise them.  The array
+ * needs no clearing (every workspace element is written before it is read).
+ * Errors: INVALID_ARG (invalid or host-only plan, NULL pointer),
+ * UNSUPPORTED_SIZE (the plan's workspace exceeds the array), HIP.  Calls no
+ * hipMalloc, hipFree or allocating routine; asynchronous on the plan's stream.
+ */
+gs_status gs_eval_static(gs_plan p, const double* rho_dev, double* u_dev);
 
 /*
  * Adjoint of gs_eval: grad_rho = A^T grad_u, the transposed chain (crop and

@@ -19,7 +19,8 @@ import math
 
 import numpy as np
 
-from ._lib import (KERNEL_DIM, KERNELS, PLAN_AUTOTUNE, PLAN_HOST_ASSEMBLY, PLAN_HOST_ONLY, SCHEDULES, GSBatchInfo,
+from ._lib import (KERNEL_DIM, KERNELS, PLAN_AUTOTUNE, PLAN_HOST_ASSEMBLY, PLAN_HOST_ONLY, PLAN_NO_WORKSPACE,
+                   SCHEDULES, GSBatchInfo,
                    GSBatchOptions, GSError, GSOptions, GSPlanInfo, check, lib)
 
 __all__ = ["Plan", "Batch", "SCHEDULES", "potential", "energy", "eval_batch", "GSError", "device_count", "supported_sizes",
@@ -53,12 +54,15 @@ class Plan:
     autotune: time the launch variants (cache hints per pass, fused-pass grid) at plan
               creation and keep the fastest (cached per device and size; the results
               are bitwise the same for every variant)
+    workspace: False creates the plan without an evaluation workspace of its own; it is
+              then evaluated with eval_static only
     """
 
     def __init__(self, kernel: str, n: int, L, eps: float = 1e-14, d: int | None = None,
                  delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
                  host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0,
-                 slab_streams: int = 0, autotune: bool = False, beta: float | None = None):
+                 slab_streams: int = 0, autotune: bool = False, beta: float | None = None,
+                 workspace: bool = True):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         d = KERNEL_DIM.get(kernel, d)
@@ -72,7 +76,7 @@ class Plan:
         opt.delta_rel = float(delta_rel)
         opt.device = int(device)
         opt.flags = ((PLAN_HOST_ONLY if host_only else 0) | (PLAN_HOST_ASSEMBLY if host_assembly else 0)
-                     | (PLAN_AUTOTUNE if autotune else 0))
+                     | (PLAN_AUTOTUNE if autotune else 0) | (0 if workspace else PLAN_NO_WORKSPACE))
         opt.slab_planes = int(slab_planes)
         opt.slab_streams = int(slab_streams)
         if beta is not None:
@@ -166,6 +170,17 @@ class Plan:
         self._check_tensor(u, "out")
         self._stream()
         check(lib().gs_eval(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr())))
+        return u
+
+    def eval_static(self, rho, out=None):
+        """As eval, with the workspace in the library's fixed device array (no device
+        allocation by the library; calls on one device must not overlap in time)."""
+        torch = _torch()
+        self._check_tensor(rho, "rho")
+        u = torch.empty_like(rho) if out is None else out
+        self._check_tensor(u, "out")
+        self._stream()
+        check(lib().gs_eval_static(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr())))
         return u
 
     def eval_backward(self, grad_u, out=None):
@@ -348,15 +363,14 @@ def _make_function():
     return GSPotential, GSEnergy
 
 
-_GSPotential = None
-_GSEnergy = None
+_FUNCS = None
 
 
 def _functions():
-    global _GSPotential, _GSEnergy
-    if _GSPotential is None:
-        _GSPotential, _GSEnergy = _make_function()
-    return _GSPotential, _GSEnergy
+    global _FUNCS
+    if _FUNCS is None:
+        _FUNCS = _make_function()
+    return _FUNCS
 
 
 def potential(rho, plan: Plan):

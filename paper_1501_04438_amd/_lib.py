@@ -18,6 +18,7 @@ STATUS = {0: "GS_OK", 1: "GS_ERR_INVALID_ARG", 2: "GS_ERR_UNSUPPORTED_SIZE", 3: 
 PLAN_HOST_ONLY = 1
 PLAN_HOST_ASSEMBLY = 2
 PLAN_AUTOTUNE = 4
+PLAN_NO_WORKSPACE = 8
 
 
 class GSOptions(C.Structure):
@@ -72,6 +73,7 @@ SIGNATURES = {
                                   C.POINTER(GSBatchOptions)]),
     "gs_batch_eval": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "gs_batch_query": (C.c_int, [C.c_void_p, C.POINTER(GSBatchInfo)]),
+    "gs_eval_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gs_batch_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gs_batch_destroy": (C.c_int, [C.c_void_p]),
     "gs_eval_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),

@@ -71,6 +71,11 @@ struct DeviceScope {
 gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a);
 // Queues the evaluation steps of p on its stream: all of them (step < 0) or one.
 gs_status eval_chain(gs_plan p, const double* in, double* out, int step);
+// Complex values of the evaluation workspace of p (X1, and in 3D X2 of x2_planes planes).
+size_t workspace_complex(gs_plan p);
+// Queues every evaluation step of p on its stream with the workspace X1, X2 given (device
+// memory of workspace_complex(p) complex values, X2 = X1 + the X1 part), in order.
+gs_status eval_chain_ws(gs_plan p, const double* in, double* out, double2* X1, double2* X2);
 // Rebuilds p's step list for `planes` kx planes per slab (3D), run on `streams` streams
 // (X2 must hold every plane when streams > 1 or planes exceed x2_planes: returns false).
 bool set_slabs(gs_plan p, int planes, int streams);

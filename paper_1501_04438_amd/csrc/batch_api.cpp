@@ -310,6 +310,7 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
     for (int i = 0; i < count; ++i) {
         gs_plan p = plans[i];
         if (!is_live(p) || p->host_only) return fail(GS_ERR_INVALID_ARG, "invalid plan in batch");
+        if (!p->X1) return fail(GS_ERR_INVALID_ARG, "a batched plan needs its workspace (GS_PLAN_NO_WORKSPACE)");
         if (!seen.insert(p).second) return fail(GS_ERR_INVALID_ARG, "a plan appears twice in the batch");
         if (p->device != plans[0]->device) return fail(GS_ERR_INVALID_ARG, "batch spans devices");
         if (!gsk::batch_size_supported(p->d, p->n)) {

@@ -271,6 +271,8 @@ gs_status eval_chain(gs_plan p, const double* in, double* out, int step) {
     gsk::EvalArgs a;
     gs_status st = make_args(p, in, out, a);
     if (st != GS_OK) return st;
+    if (!p->X1) return fail(GS_ERR_INVALID_ARG, "plan created without a workspace (GS_PLAN_NO_WORKSPACE): "
+                                                  "evaluate it with gs_eval_static");
     if (step >= (int)p->steps.size()) return fail(GS_ERR_INVALID_ARG, "step out of range");
     DeviceScope ds(p->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
@@ -282,6 +284,26 @@ gs_status eval_chain(gs_plan p, const double* in, double* out, int step) {
     } else {
         for (int i = 0; i < (int)p->steps.size() && e == hipSuccess; ++i) e = run_step(p, a, i, p->stream);
     }
+    if (e != hipSuccess) return hip_fail(e, "evaluation launch");
+    return GS_OK;
+}
+
+size_t workspace_complex(gs_plan p) {
+    const size_t n = (size_t)p->n, n1 = n + 1;
+    if (p->d == 2) return n1 * n;
+    return n1 * n * n + 2 * n * n * (size_t)p->x2_planes;
+}
+
+gs_status eval_chain_ws(gs_plan p, const double* in, double* out, double2* X1, double2* X2) {
+    gsk::EvalArgs a;
+    gs_status st = make_args(p, in, out, a);
+    if (st != GS_OK) return st;
+    a.X1 = X1;
+    a.X2 = p->d == 3 ? X2 : nullptr;
+    DeviceScope ds(p->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < (int)p->steps.size() && e == hipSuccess; ++i) e = run_step(p, a, i, p->stream);
     if (e != hipSuccess) return hip_fail(e, "evaluation launch");
     return GS_OK;
 }
@@ -357,6 +379,10 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     const int nn = (int)n[0];
     if (!gsk::eval_size_supported(d, nn)) return fail(GS_ERR_UNSUPPORTED_SIZE, "no kernels compiled for this n");
     const bool host_only = (opt.flags & GS_PLAN_HOST_ONLY) != 0;
+    const bool no_ws = (opt.flags & GS_PLAN_NO_WORKSPACE) != 0;
+    if (no_ws && (opt.flags & GS_PLAN_AUTOTUNE))
+        return fail(GS_ERR_INVALID_ARG, "GS_PLAN_AUTOTUNE times gs_eval, which needs the workspace "
+                                        "GS_PLAN_NO_WORKSPACE leaves out");
     if (k == GS_GAUSSIAN_SUM) {
         if (!opt.gs_w || !opt.gs_tau || opt.gs_q <= 0) return fail(GS_ERR_INVALID_ARG, "custom Gaussian sum missing");
         for (int q = 0; q < opt.gs_q; ++q)
@@ -376,8 +402,8 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     }
     {
         const size_t n1 = (size_t)n[0] + 1, nn0 = (size_t)n[0];
-        const size_t bytes = (d == 3 ? n1 * n1 * n1 * 8 + (n1 * nn0 * nn0 + 2 * nn0 * nn0 * n1) * 16
-                                     : n1 * n1 * 8 + n1 * nn0 * 16) + 2 * nn0 * 16;
+        const size_t ws = no_ws ? 0 : (d == 3 ? (n1 * nn0 * nn0 + 2 * nn0 * nn0 * n1) * 16 : n1 * nn0 * 16);
+        const size_t bytes = (d == 3 ? n1 * n1 * n1 * 8 : n1 * n1 * 8) + ws + 2 * nn0 * 16;
         if (!host_only && bytes > workspace_cap())
             return fail(GS_ERR_OUT_OF_MEMORY, "plan exceeds GS_MAX_WORKSPACE_BYTES");
     }
@@ -454,7 +480,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         p->slab = (int)n1;
         p->steps = {{1, 0}, {3, 0}, {5, 0}};
     }
-    p->work_bytes = (x1 + x2) * sizeof(double2) + 2 * (size_t)nn * sizeof(double2);
+    p->work_bytes = (no_ws ? 0 : (x1 + x2) * sizeof(double2)) + 2 * (size_t)nn * sizeof(double2);
 
     if (host_only) {
         gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D, p->spec_host);
@@ -478,9 +504,9 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         if (e != hipSuccess) st = hip_fail(e, "hipSetDevice");
         if (st == GS_OK && (e = hipMalloc(&p->spec, p->spec_bytes)) != hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(spectrum) failed");
-        if (st == GS_OK && (e = hipMalloc(&p->X1, x1 * sizeof(double2))) != hipSuccess)
+        if (st == GS_OK && !no_ws && (e = hipMalloc(&p->X1, x1 * sizeof(double2))) != hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace X1) failed");
-        if (st == GS_OK && x2 && (e = hipMalloc(&p->X2, x2 * sizeof(double2))) != hipSuccess)
+        if (st == GS_OK && !no_ws && x2 && (e = hipMalloc(&p->X2, x2 * sizeof(double2))) != hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace X2) failed");
         if (st == GS_OK && (e = hipMalloc(&p->tw, 2 * (size_t)nn * sizeof(double2))) != hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(twiddles) failed");
@@ -614,6 +640,7 @@ gs_status gs_plan_buffer(gs_plan p, int which, int to_device, double* host, size
     const size_t n = p->n, n1 = n + 1;
     void* buf = nullptr;
     size_t doubles = 0;
+    if ((which == 1 || which == 2) && !p->X1) return fail(GS_ERR_INVALID_ARG, "plan has no workspace");
     if (which == 1) {
         buf = p->X1;
         doubles = 2 * n1 * (p->d == 3 ? n * n : n);
