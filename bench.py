@@ -181,7 +181,17 @@ def cpu_baseline(n_sample: int, min_seconds: float = 10.0) -> dict:
         oracle.evaluate(plan, p.rho)
         dt += time.perf_counter() - t0
         evals += 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": evals * n_sample ** 3 / dt / 1e6, "unit": "Mpts/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": model,
             "sample": f"{evals} evaluation(s) of the same workload at {n_sample}^3 (plan excluded), {dt:.1f} s"}
 
 
@@ -313,7 +323,7 @@ def main() -> int:
 
     out["copy_GB_s"] = round(copy_bandwidth(torch), 1)
     if not args.no_extras:
-        out["adjoint"] = adjoint_figures(gs, torch, plan, rho, K)
+        out["adjoint"] = adjoint_figures(gs, torch, workloads, plan, rho, K, ms_step)
         out["batched"] = batched_figures(gs, torch, workloads)
         out["other_workloads"] = other_figures(gs, torch, workloads)
     if not args.no_cpu_baseline:
@@ -367,8 +377,12 @@ def other_figures(gs, torch, workloads, reps: int = 20):
     return res
 
 
-def adjoint_figures(gs, torch, plan, rho, K):
-    """The adjoint chain alone, and energy + rho-gradient through autograd."""
+def adjoint_figures(gs, torch, workloads, plan, rho, K, eval_ms):
+    """The adjoint chain alone; energy + rho-gradient through autograd (gs.energy: the energy
+    summed inside the evaluation's last pass, the gradient cell * u); and the differentiation
+    workload: the energy of the 8-component mixture on the same grid with its gradient with
+    respect to all 40 mixture parameters (gs.mixture_energy: density, evaluation with energy
+    and gradient reduction in library kernels), each against the plain evaluation."""
     g = torch.empty_like(rho)
     for _ in range(2):
         plan.eval_backward(rho, out=g)
@@ -390,9 +404,29 @@ def adjoint_figures(gs, torch, plan, rho, K):
         E.backward()
     torch.cuda.synchronize()
     dte = (time.perf_counter() - t0) / reps
+    m = workloads.config5_mixture()
+    t = lambda x: torch.tensor(x, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    a, mu, s = t(m.a), t(m.mu), t(m.sigma)
+
+    def mixture_step():
+        E = gs.mixture_energy(a, mu, s, plan)
+        return torch.autograd.grad(E, (a, mu, s))
+
+    for _ in range(2):
+        mixture_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mixture_step()
+    torch.cuda.synchronize()
+    dtm = (time.perf_counter() - t0) / reps
     n3 = rho.numel()
     return {"backward_Mpts_s": round(n3 / dt / 1e6, 1), "backward_ms": round(dt * 1e3, 4),
-            "energy_and_grad_Mpts_s": round(n3 / dte / 1e6, 1), "energy_and_grad_ms": round(dte * 1e3, 4)}
+            "energy_and_grad_Mpts_s": round(n3 / dte / 1e6, 1), "energy_and_grad_ms": round(dte * 1e3, 4),
+            "energy_and_grad_over_eval": round(dte * 1e3 / eval_ms, 3),
+            "mixture_energy_and_40_param_grads_ms": round(dtm * 1e3, 4),
+            "mixture_energy_and_40_param_grads_Mpts_s": round(n3 / dtm / 1e6, 1),
+            "mixture_over_eval": round(dtm * 1e3 / eval_ms, 3)}
 
 
 def batched_figures(gs, torch, workloads, reps: int = 10):
@@ -417,9 +451,12 @@ def batched_figures(gs, torch, workloads, reps: int = 10):
         return e0.elapsed_time(e1) / reps
 
     outs = [torch.empty_like(r) for r in rhos]
-    res = {"problems": len(probs), "points": pts, "sizes": sorted({p.n for p in probs}), "reps": reps}
+    alg = sum(sum(pass_bytes(p.n).values()) for p in probs)
+    res = {"problems": len(probs), "points": pts, "sizes": sorted({p.n for p in probs}), "reps": reps,
+           "alg_bytes": alg}
     ms = timed(lambda: [pl.eval(r, out=o) for pl, r, o in zip(plans, rhos, outs)])
-    res["single_solves"] = {"ms": round(ms, 4), "Mpts_s": round(pts / ms / 1e3, 1)}
+    res["single_solves"] = {"ms": round(ms, 4), "Mpts_s": round(pts / ms / 1e3, 1),
+                            "alg_GB_s": round(alg / ms / 1e6, 1), "frac_hbm": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
     equal = all(torch.equal(o, r) for o, r in zip(outs, ref))
     for name, kw in [("sequential", dict(schedule="sequential")),
                      ("sequential_graph", dict(schedule="sequential", graph=True)),
@@ -435,7 +472,8 @@ def batched_figures(gs, torch, workloads, reps: int = 10):
         equal = equal and all(torch.equal(o, r) for o, r in zip(outs, ref))
         info = b.info
         res[name] = {"ms": round(ms, 4), "Mpts_s": round(pts / ms / 1e3, 1), "schedule": info["schedule"],
-                     "tiles_per_task": info["tiles_per_task"], "tasks": info["num_tasks"]}
+                     "tiles_per_task": info["tiles_per_task"], "tasks": info["num_tasks"],
+                     "alg_GB_s": round(alg / ms / 1e6, 1), "frac_hbm": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
         if name.startswith("auto"):
             res[name]["candidates_timed"] = info["candidates"]
         b.close()

@@ -219,6 +219,38 @@ gs_status gs_eval(gs_plan p, const double* rho_dev, double* u_dev);
 gs_status gs_eval_static(gs_plan p, const double* rho_dev, double* u_dev);
 
 /*
+ * gs_eval plus the Hartree-type energy E = 1/2 int rho u by the grid sum
+ * E = 1/2 (prod_j h_j) sum_i rho_i u_i (the energy of the differentiation
+ * workload), formed inside the last pass: the x-inverse pass reads rho where it
+ * writes u and leaves one partial sum per block, and one more block adds them in
+ * a fixed order, so E is the same bits on every run.  energy_dev is device memory
+ * for one double, written asynchronously on the plan's stream; u may alias rho.
+ * The rho-gradient of E is (prod_j h_j) u (the operator is symmetric).
+ * Errors: as gs_eval; INVALID_ARG for a NULL energy_dev.
+ */
+gs_status gs_eval_energy(gs_plan p, const double* rho_dev, double* u_dev, double* energy_dev);
+
+/*
+ * Gaussian-mixture densities and the parameter gradient of a scalar through them (the
+ * chain rule of the differentiation workload): on the plan's grid,
+ *     rho_i = sum_c a_c exp(-|x_i - mu_c|^2 / sigma_c^2),   c = 0..K-1, 1 <= K <= 64.
+ * a (K), mu (K x d, row c = (x, y[, z]) of centre c) and sigma (K) are device arrays.
+ * gs_mixture_density writes rho (n^d FP64, device).  gs_mixture_gradient reads a grid
+ * gradient g = dE/drho (device, n^d) and writes out (device, K (d + 2) doubles):
+ *     out[c]               = scale sum_i g_i e_ci                               (dE/da_c)
+ *     out[K + c d + j]     = scale (2 a_c / sigma_c^2) sum_i g_i e_ci (x_ij - mu_cj)
+ *     out[K + K d + c]     = scale (2 a_c / sigma_c^3) sum_i g_i e_ci |x_i - mu_c|^2
+ * with e_ci = exp(-|x_i - mu_c|^2 / sigma_c^2); the sums are reduced in a fixed order
+ * (the same bits on every run) in the plan's own partial-sum buffer.  For the energy,
+ * g = (prod_j h_j) u: pass u and scale = prod_j h_j.  Asynchronous on the plan's
+ * stream; calls on one plan must not overlap.  Errors: INVALID_ARG (plan, K, pointers).
+ */
+gs_status gs_mixture_density(gs_plan p, int K, const double* a, const double* mu, const double* sigma,
+                             double* rho_dev);
+gs_status gs_mixture_gradient(gs_plan p, int K, const double* a, const double* mu, const double* sigma,
+                              const double* g_dev, double scale, double* out_dev);
+
+/*
  * Adjoint of gs_eval: grad_rho = A^T grad_u, the transposed chain (crop and
  * zero-padding exchanged, transform signs flipped).  The discrete operator is
  * a symmetric Toeplitz matrix because every kernel here is even, so the

@@ -24,7 +24,7 @@ from ._lib import (KERNEL_DIM, KERNELS, PLAN_AUTOTUNE, PLAN_HOST_ASSEMBLY, PLAN_
                    GSBatchOptions, GSError, GSOptions, GSPlanInfo, check, lib)
 
 __all__ = ["Plan", "Batch", "SCHEDULES", "potential", "energy", "eval_batch", "GSError", "device_count", "supported_sizes",
-           "mixture_density"]
+           "mixture_density", "mixture_energy"]
 
 
 def device_count() -> int:
@@ -182,6 +182,45 @@ class Plan:
         self._stream()
         check(lib().gs_eval_static(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr())))
         return u
+
+    def mixture_density(self, a, mu, sigma, out=None):
+        """rho = sum_c a_c exp(-|x - mu_c|^2 / sigma_c^2) on the plan's grid (a, sigma: (K,), mu: (K, d)
+        with columns (x, y[, z]); float64 device tensors), formed by the library."""
+        torch = _torch()
+        a, mu, sigma = (t.detach().contiguous() for t in (a, mu, sigma))
+        rho = torch.empty(self.shape, dtype=torch.float64, device=a.device) if out is None else out
+        self._check_tensor(rho, "out")
+        self._stream()
+        check(lib().gs_mixture_density(self._h, int(a.numel()), C.c_void_p(a.data_ptr()), C.c_void_p(mu.data_ptr()),
+                                       C.c_void_p(sigma.data_ptr()), C.c_void_p(rho.data_ptr())))
+        return rho
+
+    def mixture_gradient(self, a, mu, sigma, g, scale: float = 1.0):
+        """(d/da, d/dmu, d/dsigma) of a scalar whose grid gradient is scale * g, through the mixture
+        density (the library's fixed-order reduction)."""
+        torch = _torch()
+        a, mu, sigma = (t.detach().contiguous() for t in (a, mu, sigma))
+        self._check_tensor(g, "g")
+        K, d = int(a.numel()), self.d
+        out = torch.empty(K * (d + 2), dtype=torch.float64, device=a.device)
+        self._stream()
+        check(lib().gs_mixture_gradient(self._h, K, C.c_void_p(a.data_ptr()), C.c_void_p(mu.data_ptr()),
+                                        C.c_void_p(sigma.data_ptr()), C.c_void_p(g.data_ptr()), float(scale),
+                                        C.c_void_p(out.data_ptr())))
+        return out[:K], out[K:K + K * d].view(K, d), out[K + K * d:]
+
+    def eval_energy(self, rho, out=None):
+        """(u, E): the potential and E = 1/2 cell sum rho u (a 0-d device tensor), the sum
+        formed in the evaluation's last pass in a fixed order."""
+        torch = _torch()
+        self._check_tensor(rho, "rho")
+        u = torch.empty_like(rho) if out is None else out
+        self._check_tensor(u, "out")
+        E = torch.empty((), dtype=torch.float64, device=rho.device)
+        self._stream()
+        check(lib().gs_eval_energy(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()),
+                                   C.c_void_p(E.data_ptr())))
+        return u, E
 
     def eval_backward(self, grad_u, out=None):
         """grad_rho = A^T grad_u (the transposed chain)."""
@@ -350,17 +389,36 @@ def _make_function():
         @staticmethod
         def forward(ctx, rho, plan):
             rho = rho.contiguous()
-            u = plan.eval(rho)
+            u, E = plan.eval_energy(rho)
             ctx.save_for_backward(u)
             ctx.cell = plan.cell
-            return 0.5 * plan.cell * (rho * u).sum()
+            return E
 
         @staticmethod
         def backward(ctx, grad_e):
             (u,) = ctx.saved_tensors
             return (grad_e * ctx.cell) * u, None
 
-    return GSPotential, GSEnergy
+    class GSMixtureEnergy(torch.autograd.Function):
+        """E(a, mu, sigma) = 1/2 cell sum rho u for the Gaussian-mixture density: the density, the
+        evaluation with its energy and the parameter gradient (cell u through the density's
+        derivatives) all run in the library."""
+
+        @staticmethod
+        def forward(ctx, a, mu, sigma, plan):
+            rho = plan.mixture_density(a, mu, sigma)
+            u, E = plan.eval_energy(rho, out=rho)
+            ctx.save_for_backward(a, mu, sigma, u)
+            ctx.plan = plan
+            return E
+
+        @staticmethod
+        def backward(ctx, grad_e):
+            a, mu, sigma, u = ctx.saved_tensors
+            ga, gmu, gs_ = ctx.plan.mixture_gradient(a, mu, sigma, u, ctx.plan.cell)
+            return ga * grad_e, gmu * grad_e, gs_ * grad_e, None
+
+    return GSPotential, GSEnergy, GSMixtureEnergy
 
 
 _FUNCS = None
@@ -382,6 +440,13 @@ def energy(rho, plan: Plan):
     """Hartree-type energy E = 1/2 int rho u, by the grid sum 1/2 (prod_j h_j) sum rho u;
     differentiable in rho with one solve (dE/drho = prod_j h_j u, the operator being symmetric)."""
     return _functions()[1].apply(rho, plan)
+
+
+def mixture_energy(a, mu, sigma, plan: Plan):
+    """Energy 1/2 int rho u of the Gaussian mixture rho = sum_c a_c exp(-|x - mu_c|^2/sigma_c^2)
+    on the plan's grid, differentiable in (a, mu, sigma): the density, the evaluation with
+    its energy, and the gradient's reduction run in the library (one solve)."""
+    return _functions()[2].apply(a, mu, sigma, plan)
 
 
 def _half_widths(L, d: int) -> tuple:

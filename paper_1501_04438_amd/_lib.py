@@ -73,6 +73,10 @@ SIGNATURES = {
                                   C.POINTER(GSBatchOptions)]),
     "gs_batch_eval": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "gs_batch_query": (C.c_int, [C.c_void_p, C.POINTER(GSBatchInfo)]),
+    "gs_eval_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gs_mixture_density": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gs_mixture_gradient": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_double, C.c_void_p]),
     "gs_eval_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gs_batch_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gs_batch_destroy": (C.c_int, [C.c_void_p]),

@@ -61,7 +61,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     # 9 MFMAs); the VGPR form has none: 0.304 -> 0.245 ms at 256^3 (27.8 -> 34.5 TFLOP/s).
     extra = {"device_dispatch.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
     for src in ("device_dispatch.hip", "batch.hip", "host_plan.cpp", "gs_api.cpp", "batch_api.cpp",
-                "autotune.cpp", "static_eval.hip"):
+                "autotune.cpp", "static_eval.hip", "mixture.hip"):
         units.append([cc, *FLAGS, *extra.get(src, []), "-c", os.path.join(CSRC, src),
                       "-o", os.path.join(BUILD, os.path.splitext(src)[0] + ".o")])
     with cf.ThreadPoolExecutor(jobs) as ex:

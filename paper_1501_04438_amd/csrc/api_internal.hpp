@@ -28,6 +28,8 @@ struct gs_plan_s {
     double2* X1 = nullptr;
     double2* X2 = nullptr;
     double2* tw = nullptr;
+    double* epart = nullptr;                  // per-block energy sums of the x-inverse pass
+    double* mixpart = nullptr;                // per-block sums of the mixture gradient
     size_t spec_bytes = 0, work_bytes = 0;
     double assembly_ms = 0.0;
     int slab = 0, nslabs = 1;                 // 3D: kx planes per slab of the middle passes
@@ -69,8 +71,11 @@ struct DeviceScope {
 
 // Device arguments of one evaluation of plan p on (in, out).
 gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a);
-// Queues the evaluation steps of p on its stream: all of them (step < 0) or one.
-gs_status eval_chain(gs_plan p, const double* in, double* out, int step);
+// Queues the evaluation steps of p on its stream: all of them (step < 0) or one.  With
+// energy != nullptr the last pass also forms energy[0] = 1/2 cell sum in*out.
+gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double* energy = nullptr);
+// Doubles of the per-block partial sums the mixture gradient needs (plan-owned).
+size_t mixture_partial_doubles();
 // Complex values of the evaluation workspace of p (X1, and in 3D X2 of x2_planes planes).
 size_t workspace_complex(gs_plan p);
 // Queues every evaluation step of p on its stream with the workspace X1, X2 given (device

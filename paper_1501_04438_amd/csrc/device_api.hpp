@@ -32,7 +32,17 @@ struct EvalArgs {
     // fused pass runs one block per pencil group).
     int hint_bits = 27;
     int fused_grid_mult = 4;
+    // Energy (pass 5 only, when energy != nullptr): E = escale * sum_i rho_i u_i, per-block
+    // partial sums in epart (energy_blocks(d, n) doubles), their fixed-order total in *energy.
+    double* energy = nullptr;
+    double* epart = nullptr;
+    double escale = 0.0;
 };
+
+// Blocks of the x-inverse pass (the energy partial sums it writes).
+int energy_blocks(int d, int n);
+// energy[0] = scale * (part[0] + ... + part[count-1]) in a fixed order (one block).
+hipError_t launch_energy_finish(const double* part, int count, double scale, double* energy, hipStream_t s);
 
 // Passes: 1 x_r2c, 2 y_fwd, 3 fused, 4 y_inv, 5 x_c2r.  `which` < 0 runs all five on the
 // slab given in the arguments (a whole evaluation when the slab covers kx = 0..n).

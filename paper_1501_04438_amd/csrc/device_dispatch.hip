@@ -6,9 +6,38 @@
 
 namespace gsk {
 
-#define GS_DECL(N) hipError_t launch_eval_##N(const EvalArgs&, hipStream_t, int);
+#define GS_DECL(N) hipError_t launch_eval_##N(const EvalArgs&, hipStream_t, int); int energy_blocks_##N(int);
 GS_SIZE_LIST(GS_DECL)
 #undef GS_DECL
+
+int energy_blocks(int d, int n) {
+    switch (n) {
+#define GS_CASE(N) \
+    case N: return energy_blocks_##N(d);
+        GS_SIZE_LIST(GS_CASE)
+#undef GS_CASE
+        default: return 0;
+    }
+}
+
+// One block: thread t sums part[t], part[t + 256], ... in order, then the fixed-order block
+// sum; the same bits on every run.
+__global__ void __launch_bounds__(256) k_energy_finish(const double* __restrict__ part, int count, double scale,
+                                                       double* __restrict__ energy) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < count; i += 256) v += part[i];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) energy[0] = scale * (((red[0] + red[1]) + red[2]) + red[3]);
+}
+
+hipError_t launch_energy_finish(const double* part, int count, double scale, double* energy, hipStream_t s) {
+    k_energy_finish<<<1, 256, 0, s>>>(part, count, scale, energy);
+    return hipGetLastError();
+}
 
 hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which) {
     switch (a.n) {

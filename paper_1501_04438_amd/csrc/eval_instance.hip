@@ -29,6 +29,30 @@ static int resident_blocks(const void* fn, int threads) {
     return cus * (per > 0 ? per : 1);
 }
 
+// P5, with the energy sum when the arguments ask for it.
+static hipError_t launch_x_inverse(const EvalArgs& a, hipStream_t s, dim3 gx) {
+    constexpr int N = GS_N;
+    using Gm = Geo<N>;
+    const cpx* const X1 = reinterpret_cast<const cpx*>(a.X1);
+    const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
+    const bool hint = (a.hint_bits >> 4) & 1;
+    if (a.energy) {
+        if (hint) k_x_c2r_energy<N, NT_P5><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart);
+        else k_x_c2r_energy<N, 0><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_energy_finish(a.epart, (int)(gx.x * gx.y), a.escale, a.energy, s);
+    }
+    if (hint) k_x_c2r<N, NT_P5><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
+    else k_x_c2r<N, 0><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
+    return hipGetLastError();
+}
+
+int GS_CAT(energy_blocks_, GS_N)(int d) {
+    constexpr int N = GS_N;
+    return (N + 2 * Geo<N>::PPX - 1) / (2 * Geo<N>::PPX) * (d == 3 ? N : 1);
+}
+
 hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int which) {
     constexpr int N = GS_N;
     using Gm = Geo<N>;
@@ -76,10 +100,7 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
             if (hint(4)) k_y_inv<N, NT_P4><<<gy, Gm::TY, 0, s>>>(X2, X1, tw, a.kx0);
             else k_y_inv<N, 0><<<gy, Gm::TY, 0, s>>>(X2, X1, tw, a.kx0);
         }
-        if (run(5)) {
-            if (hint(5)) k_x_c2r<N, NT_P5><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
-            else k_x_c2r<N, 0><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
-        }
+        if (run(5)) return launch_x_inverse(a, s, gx);
         return hipGetLastError();
       }
     }
@@ -90,10 +111,7 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
         if (hint(3)) k_fused<N, 2, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
         else k_fused<N, 2, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
     }
-    if (run(5)) {
-        if (hint(5)) k_x_c2r<N, NT_P5><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
-        else k_x_c2r<N, 0><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
-    }
+    if (run(5)) return launch_x_inverse(a, s, gx);
     return hipGetLastError();
 }
 

@@ -82,6 +82,9 @@ void free_device(gs_plan_s* p) {
     if (p->X1) (void)hipFree(p->X1);
     if (p->X2) (void)hipFree(p->X2);
     if (p->tw) (void)hipFree(p->tw);
+    if (p->epart) (void)hipFree(p->epart);
+    if (p->mixpart) (void)hipFree(p->mixpart);
+    p->epart = p->mixpart = nullptr;
     for (hipStream_t st : p->sstreams) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : p->sevents) (void)hipEventDestroy(ev);
     p->sstreams.clear();
@@ -267,10 +270,17 @@ static hipError_t run_concurrent(gs_plan p, gsk::EvalArgs& a) {
     return run_step(p, a, last, p->stream);
 }
 
-gs_status eval_chain(gs_plan p, const double* in, double* out, int step) {
+gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double* energy) {
     gsk::EvalArgs a;
     gs_status st = make_args(p, in, out, a);
     if (st != GS_OK) return st;
+    if (energy) {
+        a.energy = energy;
+        a.epart = p->epart;
+        double cell = 1.0;
+        for (int i = 0; i < p->d; ++i) cell *= 2.0 * p->Lc[i] / p->n;
+        a.escale = 0.5 * cell;
+    }
     if (!p->X1) return fail(GS_ERR_INVALID_ARG, "plan created without a workspace (GS_PLAN_NO_WORKSPACE): "
                                                   "evaluate it with gs_eval_static");
     if (step >= (int)p->steps.size()) return fail(GS_ERR_INVALID_ARG, "step out of range");
@@ -510,6 +520,11 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace X2) failed");
         if (st == GS_OK && (e = hipMalloc(&p->tw, 2 * (size_t)nn * sizeof(double2))) != hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(twiddles) failed");
+        if (st == GS_OK && !no_ws &&
+            (e = hipMalloc(&p->epart, (size_t)gsk::energy_blocks(d, nn) * sizeof(double))) != hipSuccess)
+            st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(energy partial sums) failed");
+        if (st == GS_OK && (e = hipMalloc(&p->mixpart, mixture_partial_doubles() * sizeof(double))) != hipSuccess)
+            st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(mixture partial sums) failed");
         if (st == GS_OK) {
             std::vector<double> tw;
             gsh::twiddles(nn, tw);
@@ -670,6 +685,11 @@ gs_status gs_plan_set_stream(gs_plan p, void* stream) {
 }
 
 gs_status gs_eval(gs_plan p, const double* rho_dev, double* u_dev) { return eval_chain(p, rho_dev, u_dev, -1); }
+
+gs_status gs_eval_energy(gs_plan p, const double* rho_dev, double* u_dev, double* energy_dev) {
+    if (!energy_dev) return fail(GS_ERR_INVALID_ARG, "NULL energy pointer");
+    return eval_chain(p, rho_dev, u_dev, -1, energy_dev);
+}
 
 gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho_dev) {
     // The transposed chain: zero-pad <-> crop exchanged and the transform signs

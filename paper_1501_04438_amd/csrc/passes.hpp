@@ -160,10 +160,12 @@ k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
 // ---------------------------------------------------------------------------
 // P5: x-direction complex-to-real with cropping.  Inverse of P1 (unnormalised).
 // ---------------------------------------------------------------------------
-template <int N, int NT = NT_P5>
-__device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> __restrict__ u,
-                                           gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
-                                           cpx* lds) {
+// EN: also returns this thread's part of sum_i rho_i u_i over the outputs it stores (rho
+// read at those outputs before they are written, so u may alias rho), in a fixed order.
+template <int N, int NT = NT_P5, bool EN = false>
+__device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> u,
+                                             gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
+                                             cpx* lds, gp<const double> erho = nullptr) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPX, A = Gm::A;
     const int tA = tid % G, pA = tid / G;      // store role: consecutive x
@@ -205,8 +207,22 @@ __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<dou
         for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], v[e]);
         lds_barrier();
     }
+    double part = 0.0;
     if (okA) {
-        gp<double> ua = u + ((size_t)z * N + rowA) * N;
+        const size_t o = ((size_t)z * N + rowA) * N;
+        gp<double> ua = u + o;
+        if constexpr (EN) {
+            gp<const double> ra = erho + o;
+            double r0[E], r1[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int j = tA + G * e;
+                r0[e] = ra[j];
+                r1[e] = ra[(size_t)RS * N + j];
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) part += r0[e] * acc[e].x + r1[e] * acc[e].y;
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = tA + G * e;
@@ -214,6 +230,28 @@ __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<dou
             stg<(NT & 2) != 0>(ua + (size_t)RS * N + j, acc[e].y);
         }
     }
+    return part;
+}
+
+// Sum of one value per thread over a block of THREADS (a power of two) in a fixed order:
+// a xor butterfly within each wave, then the waves in index order (red: THREADS/64 slots).
+// Every thread of the block must call it; the result is valid in thread 0.
+template <int THREADS>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    constexpr int W = THREADS < 64 ? THREADS : 64;
+#pragma unroll
+    for (int o = W / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, W);
+    if constexpr (THREADS > 64) {
+        const int tid = threadIdx.x;
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) {
+            v = red[0];
+#pragma unroll
+            for (int w = 1; w < THREADS / 64; ++w) v += red[w];
+        }
+    }
+    return v;
 }
 
 template <int N, int NT = NT_P5>
@@ -222,6 +260,20 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1
     __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
     x_c2r_tile<N, NT>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x, blockIdx.y, threadIdx.x, true,
                   lds);
+}
+
+// P5 with the energy sum: as k_x_c2r, plus sum rho u over the block's outputs into
+// part[block] (rho may alias u: each thread reads rho where it then writes u).
+template <int N, int NT = NT_P5>
+__global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r_energy(const cpx* __restrict__ X1, double* u,
+                                                             const cpx* __restrict__ tw, const double* rho,
+                                                             double* __restrict__ part) {
+    __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
+    __shared__ double red[Geo<N>::TX / 64 + 1];
+    const double v = x_c2r_tile<N, NT, true>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                             blockIdx.y, threadIdx.x, true, lds, (gp<const double>)rho);
+    const double s = block_sum<Geo<N>::TX>(v, red);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------------------

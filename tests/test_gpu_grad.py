@@ -47,18 +47,22 @@ def test_parameter_gradients_match_oracle(n):
 
 def test_parameter_gradients_central_differences_256():
     """All 40 parameters of the 8-component mixture on 256^3, h = 1e-6: 80 more
-    energy evaluations.  E is smooth in the parameters; the agreement is limited by
-    rounding (about 1e-16 |E| / h)."""
+    energy evaluations, through the library's mixture path (density, evaluation with
+    its energy, gradient reduction).  E is smooth in the parameters; the agreement is
+    limited by rounding (about 1e-16 |E| / h).  The gradient also equals the one of the
+    torch-expression density through autograd."""
     m = workloads.config5_mixture()
     plan = gs.Plan("coulomb3d", n=256, L=10.0)
     a, mu, s = params(m)
-    _, g = energy_and_grad(plan, a, mu, s)
+    E = gs.mixture_energy(a, mu, s, plan)
+    g = np.concatenate([t.cpu().numpy().ravel() for t in torch.autograd.grad(E, (a, mu, s))])
+    _, g_torch = energy_and_grad(plan, a, mu, s)
+    assert np.max(np.abs(g - g_torch)) <= 1e-12 * np.max(np.abs(g_torch))
     hh = 1e-6
 
     def E_of(av, muv, sv):
         with torch.no_grad():
-            rho = gs.mixture_density(av, muv, sv, 256, 10.0)
-            return float(gs.energy(rho, plan))
+            return float(gs.mixture_energy(av, muv, sv, plan))
 
     base = [a.detach().clone(), mu.detach().clone(), s.detach().clone()]
     fd = []
@@ -148,3 +152,74 @@ def test_adjoint_against_oracle_transpose(kernel, d, n, L, kw):
     lhs = float((Aa * v).sum())
     rhs = float((a * Atv).sum())
     assert abs(lhs - rhs) <= 1e-14 * float(Aa.norm() * v.norm())
+
+
+@pytest.mark.parametrize("kernel,d,n,L", [("coulomb3d", 3, 12, 4.0), ("coulomb3d", 3, 24, (3.0, 4.0, 5.0)),
+                                          ("dipolar3d", 3, 96, 8.0), ("coulomb3d", 3, 256, 10.0),
+                                          ("poisson2d", 2, 48, 7.0), ("coulomb2d", 2, 2048, 12.0)])
+def test_energy_formed_in_the_last_pass(kernel, d, n, L):
+    """gs_eval_energy: u bitwise that of gs_eval; E = 1/2 cell sum rho u against a float64
+    sum of the same product (1e-14 of sum |1/2 cell rho u|) and against the oracle's energy
+    (small grids); the same bits on repeated calls and with u aliasing rho."""
+    print(f"energy: {kernel} n={n} L={L}", flush=True)
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    if kernel == "poisson2d":
+        kw["eps"] = 1e-13
+    plan = gs.Plan(kernel, n=n, L=L, **kw)
+    rng = np.random.default_rng(800 + n)
+    x = rng.standard_normal((n,) * d)
+    rho = torch.from_numpy(x).to("cuda:0")
+    u_ref = plan.eval(rho)
+    u, E = plan.eval_energy(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(u, u_ref)
+    prod = 0.5 * plan.cell * (rho * u_ref)
+    assert abs(float(E) - float(prod.sum())) <= 1e-14 * float(prod.abs().sum())
+    for _ in range(2):
+        _, E2 = plan.eval_energy(rho)
+        assert torch.equal(E2, E)
+    y = rho.clone()
+    _, E3 = plan.eval_energy(y, out=y)
+    torch.cuda.synchronize()
+    assert torch.equal(y, u_ref) and torch.equal(E3, E)
+    if n <= 48:
+        Eo = oracle.energy(oracle.make_plan(kernel, d, n, L, **kw), x)
+        assert abs(float(E) - Eo) <= 1e-13 * float(prod.abs().sum())
+
+
+MIX_CASES = [("coulomb3d", 3, 32, 10.0, 8), ("coulomb3d", 3, 48, (6.0, 8.0, 10.0), 11),
+             ("poisson2d", 2, 96, 12.0, 16), ("dipolar3d", 3, 24, 8.0, 3)]
+
+
+def _mixture(d, K, seed):
+    rng = np.random.default_rng(seed)
+    t = lambda x: torch.tensor(x, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    return (t(rng.uniform(-1, 1, K)), t(rng.uniform(-2, 2, (K, d))), t(rng.uniform(0.5, 2.0, K)))
+
+
+@pytest.mark.parametrize("kernel,d,n,L,K", MIX_CASES)
+def test_mixture_path_against_oracle(kernel, d, n, L, K):
+    """The library's mixture density against the torch expression (1e-15), and the energy
+    and its 40-odd parameter derivatives against the oracle's chain rule (1e-12), K beyond
+    one 8-component chunk and rectangular boxes included; two calls give the same bits."""
+    print(f"mixture: {kernel} n={n} K={K}", flush=True)
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    if kernel == "poisson2d":
+        kw["eps"] = 1e-13
+    plan = gs.Plan(kernel, n=n, L=L, **kw)
+    a, mu, s = _mixture(d, K, 40 + n)
+    rho = plan.mixture_density(a, mu, s)
+    ref = gs.mixture_density(a.detach(), mu.detach(), s.detach(), n, L)
+    assert float((rho - ref).abs().max()) <= 1e-15 * float(ref.abs().max())
+    E = gs.mixture_energy(a, mu, s, plan)
+    g = torch.autograd.grad(E, (a, mu, s))
+    E2 = gs.mixture_energy(a, mu, s, plan)
+    g2 = torch.autograd.grad(E2, (a, mu, s))
+    assert torch.equal(E, E2) and all(torch.equal(x, y) for x, y in zip(g, g2))
+    op = oracle.make_plan(kernel, d, n, L, **kw)
+    Eo, ga, gmu, gsig = oracle.energy_gradient_params(op, a.detach().cpu().numpy(), mu.detach().cpu().numpy(),
+                                                      s.detach().cpu().numpy())
+    got = np.concatenate([x.cpu().numpy().ravel() for x in g])
+    go = np.concatenate([ga, gmu.ravel(), gsig])
+    assert abs(float(E) - Eo) <= 1e-12 * abs(Eo)
+    assert np.max(np.abs(got - go)) <= 1e-12 * np.max(np.abs(go))
