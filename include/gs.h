@@ -13,12 +13,14 @@
  * evaluation split of Algorithm 1 is the plan / eval split below.
  *
  * Conventions shared by every entry point
- *   - Grids have n points on every axis over a box prod_j [-L_j, L_j] (a cube
- *     when the L_j are equal; a rectangular box as in Section 2.5 otherwise):
- *     spacing h_j = 2 L_j / n, sample i on axis j at -L_j + i h_j, i = 0..n-1.
+ *   - Grids have n_j points on axis j over a box prod_j [-L_j, L_j] (a cube
+ *     when the L_j and n_j are equal; a rectangular box or grid as in Section
+ *     2.5 otherwise): spacing h_j = 2 L_j / n_j, sample i on axis j at
+ *     -L_j + i h_j, i = 0..n_j - 1.  A rectangular box with one spacing on every
+ *     axis has unequal n_j.
  *   - Arrays are dense, C-ordered FP64: [z][y][x] in 3D, [y][x] in 2D, x the
  *     last (fastest) index.  `n` and `L` arguments are arrays of length d in
- *     that same order; the entries of `n` must be equal.
+ *     that same order.
  *   - Device pointers are HIP device memory on the plan's device, owned by the
  *     caller, and must stay valid until the work queued on the plan's stream
  *     has completed.  Calls are asynchronous with respect to the host.
@@ -135,6 +137,9 @@ typedef struct {
     double L_axes[3];        /* half-widths as given, C order (first d entries);
                                 L above is their maximum, the table's length unit */
     double beta;             /* GS_INVERSE_POWER exponent (0 for other kernels)   */
+    int64_t n_axes[3];       /* points per axis, C order (first d entries); n above is
+                                their common value, or their largest on a grid whose
+                                axes differ                                      */
 } gs_plan_info;
 
 /* Fill `opt` with the defaults (delta_rel 1e-4, null stream, device -1). */
@@ -149,14 +154,17 @@ void gs_options_default(gs_options* opt);
  * R = 2 sqrt(sum_j (L_j/L)^2), the largest distance in the box: 2 sqrt(d)
  * for a cube), the one-dimensional factor integrals of eq. (tensor) (eq.
  * (tensor_ani) for rectangular boxes) at the padded frequencies
- * xi = pi k/(2 L_j), k = 0..n, of every axis, the Taylor constants A0, c2
- * (Section 2.3), and the stored spectrum octant
- *     S[k] = ( sum_q w_q prod_j g_q(xi_kj) + A0 - c2 |xi_k|^2 ) / (2n)^d,
+ * xi = pi k/(2 L_j), k = 0..n_j, of every axis, the Taylor constants A0, c2
+ * (Section 2.3), and the stored spectrum octant [kx][ky][kz] (x first)
+ *     S[k] = ( sum_q w_q prod_j g_q(xi_kj) + A0 - c2 |xi_k|^2 ) / prod_j (2 n_j),
  * assembled on the device by an FP64 matrix-core contraction.  Allocates the
  * spectrum and the evaluation workspace on the device.
  *   out     receives the plan (NULL on error).
  *   k, d    kernel family and dimension (2 or 3).
- *   n, L    length-d arrays, [z][y][x] order; equal n; every L_j > 0, and
+ *   n, L    length-d arrays, [z][y][x] order; every n_j in the compiled size
+ *           list (gs_supported_sizes; UNSUPPORTED_SIZE otherwise); a cubic grid
+ *           (equal n_j) runs the cubic passes, a grid with unequal n_j runs each
+ *           pass at the length of the axis it transforms; every L_j > 0, and
  *           delta_rel below min_j L_j / max_j L_j (the near-field ball must fit
  *           the shortest axis, Section 2.5).
  *   eps     target accuracy of the Gaussian sum (1e-15 <= eps < 1).

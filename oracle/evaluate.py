@@ -12,14 +12,16 @@ Actual computation (evaluate):
   3. Lap  = (1/M) crop(IDFT(-|xi|^2 . rho~))             (spectral Laplacian)
   4. I21~ = A0 rho + c2 Lap                              (eq. (taylor))
   5. u    = I1 + I21~
-with M = (2n)^d.  The Laplacian is taken on the padded grid with the Nyquist
+with M = prod_j 2 n_j.  The Laplacian is taken on the padded grid with the Nyquist
 mode kept (|xi| = pi/h there).
 
-Rectangular boxes (Section 2.5): the box is prod_j [-L_j, L_j] with n points on
-every axis, so h_j = 2 L_j / n and xi^(j)_k = pi k / (2 L_j); the factors of
+Rectangular boxes (Section 2.5): the box is prod_j [-L_j, L_j] with n_j points on
+axis j (one n for every axis, or one per axis), so h_j = 2 L_j / n_j, the padded
+grid has 2 n_j points and xi^(j)_k = pi k / (2 L_j); the factors of
 eq. (tensor_ani) are the one-dimensional integrals over [-2 L_j, 2 L_j] at those
-frequencies, the Laplacian symbol is sum_j (xi^(j))^2, and the Gaussian-sum
-table is fitted on the rescaled distances of that box (`gs_table`).  The
+frequencies (k = 0..n_j), the Laplacian symbol is sum_j (xi^(j))^2,
+M = prod_j 2 n_j, and the Gaussian-sum table is fitted on the rescaled distances
+of that box (`gs_table`).  The
 printed phase factor of eq. (tensor_ani)'s companion formula carries a stray
 epsilon where the axis ratio eta is meant; with eta the short axis is simply an
 axis of half-width eta L, which is what per-axis half-widths express.
@@ -58,7 +60,7 @@ COULOMB_LIKE = ("coulomb3d", "coulomb2d", "poisson2d", "dipolar3d", "davey_stewa
 class OraclePlan:
     kernel: str
     d: int
-    n: int
+    n: int                  # points per axis (the largest, when the axes differ)
     L: float                # largest half-width (the table's length unit)
     table: GSTable
     F: np.ndarray           # (n+1, Q) one-dimensional factors of the last axis (x)
@@ -70,17 +72,18 @@ class OraclePlan:
     Ls: tuple = ()          # per-axis half-widths, C order (z, y, x / y, x)
     Fs: tuple = ()          # per-axis factor matrices, C order
     beta: float | None = None   # exponent of the inverse-power kernel r^-beta
+    ns: tuple = ()          # points per axis, C order
 
     @property
     def h(self) -> float:
         """Grid step of a cubic box (use `hs` for rectangular ones)."""
-        if len(set(self.Ls)) > 1:
+        if len(set(self.hs)) > 1:
             raise ValueError("rectangular box: the grid step differs per axis")
-        return 2.0 * self.L / self.n
+        return self.hs[0]
 
     @property
     def hs(self) -> tuple:
-        return tuple(2.0 * v / self.n for v in self.Ls)
+        return tuple(2.0 * v / m for v, m in zip(self.Ls, self.ns))
 
     @property
     def cell(self) -> float:
@@ -89,14 +92,15 @@ class OraclePlan:
 
     @property
     def M(self) -> int:
-        return (2 * self.n) ** self.d
+        return int(np.prod([2 * m for m in self.ns]))
 
 
-def make_plan(kernel: str, d: int, n: int, L, eps: float = 1e-14,
+def make_plan(kernel: str, d: int, n, L, eps: float = 1e-14,
               delta_rel: float = 1e-4, custom=None, dipole=None, beta: float | None = None) -> OraclePlan:
-    """L: one half-width for the cube [-L, L]^d, or one per axis in C order;
-    beta: the exponent of kernel "inverse_power" (U = |x|^-beta, 0 < beta < d)."""
+    """n, L: one value for every axis (the cube [-L, L]^d with n^d points), or one per axis
+    in C order; beta: the exponent of kernel "inverse_power" (U = |x|^-beta, 0 < beta < d)."""
     Ls = box_half_widths(L, d)
+    ns = grid_points(n, d)
     if kernel == "gaussian_sum":
         w, tau = custom
         table = custom_table(w, tau, d, Ls)
@@ -104,14 +108,14 @@ def make_plan(kernel: str, d: int, n: int, L, eps: float = 1e-14,
         table = physical_table(kernel, d, Ls, eps, delta_rel, beta=beta)
         if table.d != d:
             raise ValueError("kernel and dimension disagree")
-    Fs = tuple(factor_1d(table.tau, 2.0 * Lj, n) for Lj in Ls)
+    Fs = tuple(factor_1d(table.tau, 2.0 * Lj, m) for Lj, m in zip(Ls, ns))
     # G[i0][i1]([i2]) = sum_q w_q F_0[i0, q] F_1[i1, q] (F_2[i2, q]), array axes
     Fw = Fs[0] * table.w[None, :]
     if d == 2:
         G = Fw @ Fs[1].T
     else:
-        G = np.empty((n + 1,) * 3)
-        for a in range(n + 1):
+        G = np.empty(tuple(m + 1 for m in ns))
+        for a in range(ns[0] + 1):
             G[a] = (Fw[a][None, :] * Fs[1]) @ Fs[2].T
     if kernel == "gaussian_sum":
         A0, c2 = 0.0, 0.0
@@ -120,7 +124,17 @@ def make_plan(kernel: str, d: int, n: int, L, eps: float = 1e-14,
     dn = dm = None
     if kernel == "dipolar3d":
         dn, dm = dipole
-    return OraclePlan(kernel, d, n, table.L, table, Fs[-1], G, A0, c2, dn, dm, Ls, Fs, beta)
+    return OraclePlan(kernel, d, max(ns), table.L, table, Fs[-1], G, A0, c2, dn, dm, Ls, Fs, beta, ns)
+
+
+def grid_points(n, d: int) -> tuple:
+    """Points per axis (C order) from one value or a sequence."""
+    if np.ndim(n) == 0:
+        return (int(n),) * d
+    ns = tuple(int(v) for v in n)
+    if len(ns) != d:
+        raise ValueError("one n per axis")
+    return ns
 
 
 def padded_frequencies(n: int, L: float, odd: bool = False) -> np.ndarray:
@@ -140,10 +154,7 @@ def _fold_index(n: int) -> np.ndarray:
 
 
 def full_spectrum(plan: OraclePlan) -> np.ndarray:
-    idx = _fold_index(plan.n)
-    if plan.d == 2:
-        return plan.G_oct[np.ix_(idx, idx)]
-    return plan.G_oct[np.ix_(idx, idx, idx)]
+    return plan.G_oct[np.ix_(*[_fold_index(m) for m in plan.ns])]
 
 
 def _axes_vectors(plan: OraclePlan, odd: bool):
@@ -153,9 +164,9 @@ def _axes_vectors(plan: OraclePlan, odd: bool):
     out = []
     for comp in range(d):
         ax = d - 1 - comp                       # x is the last array axis
-        xi = padded_frequencies(plan.n, plan.Ls[ax], odd)
+        xi = padded_frequencies(plan.ns[ax], plan.Ls[ax], odd)
         shape = [1] * d
-        shape[ax] = 2 * plan.n
+        shape[ax] = 2 * plan.ns[ax]
         out.append(xi.reshape(shape))
     return out
 
@@ -199,7 +210,7 @@ def ds_symbol(plan: OraclePlan) -> np.ndarray:
 
 def evaluate(plan: OraclePlan, rho: np.ndarray) -> np.ndarray:
     rho = np.asarray(rho, dtype=np.float64)
-    assert rho.shape == (plan.n,) * plan.d
+    assert rho.shape == tuple(plan.ns)
     rt = dft.forward(rho)
     if plan.kernel == "davey_stewartson2d":
         src_t = ds_symbol(plan) * rt
@@ -252,9 +263,9 @@ def energy_gradient_rho(plan: OraclePlan, rho: np.ndarray) -> np.ndarray:
     return 0.5 * plan.cell * (evaluate(plan, rho) + adjoint(plan, rho))
 
 
-def mixture_grid(n: int, L, a, mu, sigma):
+def mixture_grid(n, L, a, mu, sigma):
     """rho = sum_c a_c exp(-|x - mu_c|^2 / sigma_c^2) on the grid x_j = -L + j h
-    ([z][y][x] / [y][x] order, mu columns (x, y[, z]); L one half-width or one per
+    ([z][y][x] / [y][x] order, mu columns (x, y[, z]); n and L one value or one per
     axis in C order), with the per-component Gaussians g_c and squared distances
     r2_c and offsets x_i - mu_ci it is made of."""
     a = np.asarray(a, float)
@@ -262,12 +273,13 @@ def mixture_grid(n: int, L, a, mu, sigma):
     sigma = np.asarray(sigma, float)
     d = mu.shape[1]
     Ls = box_half_widths(L, d)
-    axes = [-Lj + (2.0 * Lj / n) * np.arange(n) for Lj in Ls]     # array-axis order
+    ns = grid_points(n, d)
+    axes = [-Lj + (2.0 * Lj / m) * np.arange(m) for Lj, m in zip(Ls, ns)]     # array-axis order
     if d == 3:
         X = (axes[2][None, None, :], axes[1][None, :, None], axes[0][:, None, None])   # x, y, z
     else:
         X = (axes[1][None, :], axes[0][:, None])
-    shape = (n,) * d
+    shape = ns
     rho = np.zeros(shape)
     comps = []
     for c in range(len(a)):
@@ -288,7 +300,7 @@ def energy_gradient_params(plan: OraclePlan, a, mu, sigma):
     Returns (E, dE/da (K,), dE/dmu (K, d), dE/dsigma (K,))."""
     a = np.asarray(a, float)
     sigma = np.asarray(sigma, float)
-    rho, comps = mixture_grid(plan.n, plan.Ls, a, mu, sigma)
+    rho, comps = mixture_grid(plan.ns, plan.Ls, a, mu, sigma)
     gr = energy_gradient_rho(plan, rho)
     E = energy(plan, rho)
     K, d = len(a), plan.d

@@ -47,8 +47,9 @@ class Plan:
 
     kernel: "coulomb3d" | "coulomb2d" | "poisson2d" | "dipolar3d" | "davey_stewartson2d" | "inverse_power"
             | "gaussian_sum" (the last two need d; "inverse_power" also beta: U = |x|^-beta, 0 < beta < d)
-    n, L:   points per axis and box half-width: one value for the cube [-L, L]^d, or
-            one per axis in array order ((Lz, Ly, Lx) / (Ly, Lx)) for a rectangular box
+    n, L:   points per axis and box half-width: one value each for the cube [-L, L]^d with
+            n^d points, or one per axis in array order ((nz, ny, nx), (Lz, Ly, Lx) / (ny, nx),
+            (Ly, Lx)) for a rectangular box or grid (Section 2.5)
     eps:    Gaussian-sum accuracy; delta_rel: near-field radius / max L (below min L / max L)
     dipole: (n_vec, m_vec) for "dipolar3d"; custom: (w, tau) for "gaussian_sum"
     autotune: time the launch variants (cache hints per pass, fused-pass grid) at plan
@@ -68,7 +69,9 @@ class Plan:
         d = KERNEL_DIM.get(kernel, d)
         if d is None:
             raise ValueError(f"{kernel} plans need d")
-        self.kernel, self.d, self.n, self.eps = kernel, int(d), int(n), float(eps)
+        self.kernel, self.d, self.eps = kernel, int(d), float(eps)
+        self.ns = _points(n, self.d)
+        self.n = max(self.ns)
         self.Ls = _half_widths(L, self.d)
         self.L = max(self.Ls)
         opt = GSOptions()
@@ -95,7 +98,7 @@ class Plan:
             opt.gs_w = w.ctypes.data_as(C.POINTER(C.c_double))
             opt.gs_tau = tau.ctypes.data_as(C.POINTER(C.c_double))
             opt.gs_q = len(w)
-        nn = (C.c_int64 * self.d)(*([self.n] * self.d))
+        nn = (C.c_int64 * self.d)(*self.ns)
         LL = (C.c_double * self.d)(*self.Ls)
         h = C.c_void_p()
         check(lib().gs_plan_create(C.byref(h), KERNELS[kernel], self.d, nn, LL, self.eps, C.byref(opt)))
@@ -109,18 +112,20 @@ class Plan:
         check(lib().gs_plan_query(self._h, C.byref(info)))
         out = {f: getattr(info, f) for f, _ in GSPlanInfo._fields_}
         out["L_axes"] = tuple(out["L_axes"][:self.d])
+        out["n_axes"] = tuple(int(v) for v in out["n_axes"][:self.d])
         return out
 
     @property
     def h(self) -> float:
         """Grid step of a cubic box (`hs` holds the per-axis steps)."""
-        if len(set(self.Ls)) > 1:
+        hs = self.hs
+        if len(set(hs)) > 1:
             raise ValueError("rectangular box: the grid step differs per axis")
-        return 2.0 * self.L / self.n
+        return hs[0]
 
     @property
     def hs(self) -> tuple:
-        return tuple(2.0 * v / self.n for v in self.Ls)
+        return tuple(2.0 * v / m for v, m in zip(self.Ls, self.ns))
 
     @property
     def cell(self) -> float:
@@ -129,7 +134,7 @@ class Plan:
 
     @property
     def shape(self):
-        return (self.n,) * self.d
+        return tuple(self.ns)
 
     def table(self):
         Q = self.info["Q"]
@@ -140,13 +145,14 @@ class Plan:
 
     def factors(self, axis: int | None = None) -> np.ndarray:
         """Factor matrix (n+1, Q) of array axis `axis` (default: the last, x)."""
-        F = np.empty((self.n + 1, self.info["Q"]))
         ax = self.d - 1 if axis is None else int(axis)
+        F = np.empty((self.ns[ax] + 1, self.info["Q"]))
         check(lib().gs_plan_factors_axis(self._h, ax, F.ctypes.data_as(C.POINTER(C.c_double)), F.size))
         return F
 
     def spectrum(self) -> np.ndarray:
-        S = np.empty((self.n + 1,) * self.d)
+        """The stored octant, indexed [kx][ky]([kz]) (x the first index)."""
+        S = np.empty(tuple(m + 1 for m in reversed(self.ns)))
         check(lib().gs_plan_spectrum(self._h, S.ctypes.data_as(C.POINTER(C.c_double)), S.size))
         return S
 
@@ -251,13 +257,15 @@ class Plan:
 
     def buffer(self, which: int, value=None):
         """Read (value None) or write a plan buffer: 1 = X1, 2 = X2 (complex), 3 = spectrum."""
-        n, d = self.n, self.d
+        d = self.d
+        nx, ny = self.ns[-1], self.ns[-2]
+        nz = self.ns[0] if d == 3 else 1
         if which == 1:
-            shape, cplx = ((n, n + 1, n) if d == 3 else (n + 1, n)), True
+            shape, cplx = ((nz, nx + 1, ny) if d == 3 else (nx + 1, ny)), True
         elif which == 2:
-            shape, cplx = (self.query()["x2_planes"], 2 * n, n), True
+            shape, cplx = (self.query()["x2_planes"], 2 * ny, nz), True
         else:
-            shape, cplx = (n + 1,) * d, False
+            shape, cplx = tuple(m + 1 for m in reversed(self.ns)), False
         if value is None:
             a = np.empty(shape, np.complex128 if cplx else np.float64)
             check(lib().gs_plan_buffer(self._h, which, 0, a.ctypes.data_as(C.POINTER(C.c_double)),
@@ -449,6 +457,15 @@ def mixture_energy(a, mu, sigma, plan: Plan):
     return _functions()[2].apply(a, mu, sigma, plan)
 
 
+def _points(n, d: int) -> tuple:
+    if np.ndim(n) == 0:
+        return (int(n),) * d
+    ns = tuple(int(v) for v in n)
+    if len(ns) != d:
+        raise ValueError("n: one value, or one per axis")
+    return ns
+
+
 def _half_widths(L, d: int) -> tuple:
     if np.ndim(L) == 0:
         return (float(L),) * d
@@ -458,18 +475,19 @@ def _half_widths(L, d: int) -> tuple:
     return Ls
 
 
-def mixture_density(a, mu, sigma, n: int, L):
+def mixture_density(a, mu, sigma, n, L):
     """Gaussian mixture sum_c a_c exp(-|x - mu_c|^2/sigma_c^2) on the [z][y][x] grid as a
     differentiable torch expression (input construction for parameter gradients).
-    L: one half-width or one per axis in array order."""
+    n, L: one value or one per axis in array order."""
     torch = _torch()
     d = mu.shape[1]
     Ls = _half_widths(L, d)
-    ax = [-Lj + (2.0 * Lj / n) * torch.arange(n, dtype=torch.float64, device=mu.device) for Lj in Ls]
+    ns = _points(n, d)
+    ax = [-Lj + (2.0 * Lj / m) * torch.arange(m, dtype=torch.float64, device=mu.device) for Lj, m in zip(Ls, ns)]
     if d == 3:
-        X = (ax[2].view(1, 1, n), ax[1].view(1, n, 1), ax[0].view(n, 1, 1))
+        X = (ax[2].view(1, 1, -1), ax[1].view(1, -1, 1), ax[0].view(-1, 1, 1))
     else:
-        X = (ax[1].view(1, n), ax[0].view(n, 1))
+        X = (ax[1].view(1, -1), ax[0].view(-1, 1))
     out = 0.0
     for c in range(mu.shape[0]):
         r2 = sum((X[i] - mu[c, i]) ** 2 for i in range(d))

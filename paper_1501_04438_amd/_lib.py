@@ -35,7 +35,7 @@ class GSPlanInfo(C.Structure):
                 ("assembly_gflop", C.c_double), ("host_only", C.c_int), ("slab_planes", C.c_int),
                 ("num_steps", C.c_int), ("slab_streams", C.c_int), ("x2_planes", C.c_int), ("tuned", C.c_int), ("hint_bits", C.c_int), ("fused_grid_mult", C.c_int),
                 ("tune_candidates", C.c_int), ("tuned_ms", C.c_double), ("L_axes", C.c_double * 3),
-                ("beta", C.c_double)]
+                ("beta", C.c_double), ("n_axes", C.c_int64 * 3)]
 
 
 SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3, "sized": 4}

@@ -12,7 +12,10 @@
 #include "host_plan.hpp"
 
 struct gs_plan_s {
-    int kernel = 0, d = 0, n = 0;
+    int kernel = 0, d = 0, n = 0;             // n: points per axis of a cubic grid, else the largest
+    int nc[3] = {0, 0, 0};                    // points per axis, C order (z, y, x / y, x)
+    int nk[3] = {0, 0, 0};                    // points of the octant axes x, y[, z]
+    bool cube = true;                         // every axis has the same n
     double L = 0, eps = 0, delta_rel = 0;     // L: largest half-width (the table's length unit)
     double Lc[3] = {0, 0, 0};                 // half-widths as given, C order (z, y, x / y, x)
     double Lk[3] = {0, 0, 0};                 // half-widths of the octant axes x, y[, z]
@@ -27,7 +30,8 @@ struct gs_plan_s {
     double* spec = nullptr;
     double2* X1 = nullptr;
     double2* X2 = nullptr;
-    double2* tw = nullptr;
+    double2* tw = nullptr;                    // twiddles of length n (cubic grids)
+    double2* twk[3] = {nullptr, nullptr, nullptr};   // per octant axis (rectangular grids; may alias)
     double* epart = nullptr;                  // per-block energy sums of the x-inverse pass
     double* mixpart = nullptr;                // per-block sums of the mixture gradient
     size_t spec_bytes = 0, work_bytes = 0;

@@ -5,9 +5,9 @@
 // of Section 2.3 folded in, on the octant k_j = 0..n of the padded frequencies
 // xi_k = pi k / (2 L_j) of each axis:
 //     S[k1][k2][k3] = ( sum_q (w_q Fx[k1][q]) Fy[k2][q] Fz[k3][q]
-//                       + A0 - c2 (xi_k1^2 + xi_k2^2 + xi_k3^2) ) / (2n)^3
+//                       + A0 - c2 (xi_k1^2 + xi_k2^2 + xi_k3^2) ) / prod_j (2 n_j)
 // is a rank-Q contraction whose right operand is the Khatri-Rao product
-// B[q][(k2,k3)] = Fy[k2][q] Fz[k3][q]: a GEMM of shape (n+1) x Q x (n+1)^2 with
+// B[q][(k2,k3)] = Fy[k2][q] Fz[k3][q]: a GEMM of shape (nx+1) x Q x (ny+1)(nz+1) with
 // B formed in registers.  2D: S[k1][k3] with B[q][k3] = Fy[k3][q] (passed as FC).
 // dxx != 0 multiplies the result by -xi_k1^2, the symbol of d_xx (Davey-Stewartson
 // potential: the Poisson spectrum applied to the second x-derivative of rho).
@@ -25,24 +25,26 @@ namespace gsk {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// One wave computes a (16*MB) x 16 tile: MB row blocks of k1 against 16 columns.
+// One wave computes a (16*MB) x 16 tile: MB row blocks of k1 against 16 columns.  n1, n1b,
+// n1c: the octant extents of k1, k2, k3 (each axis its own n on rectangular grids).
 template <int MB, int DIM>
 __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,   // [Qp][ldk]: w_q Fx[k][q]
                                                   const double* __restrict__ FB,   // [Qp][ldk]: factor of k2
                                                   const double* __restrict__ FC,   // [Qp][ldk]: factor of k3
-                                                  int ldk, int n1, int Qp, double* __restrict__ out,
+                                                  int ldk, int n1, int n1b, int n1c, int Qp,
+                                                  double* __restrict__ out,
                                                   double A0, double c2, double dx1, double dx2, double dx3,
                                                   double invM, int dxx) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long ncols = (DIM == 3) ? (long)n1 * n1 : (long)n1;
+    const long ncols = (DIM == 3) ? (long)n1b * n1c : (long)n1c;
     const long col0 = ((long)blockIdx.x * 4 + wave) * 16;
     if (col0 >= ncols) return;                              // whole wave idle: uniform exit
     const int k1base = blockIdx.y * MB * 16;
     const int i = lane & 15, kk = lane >> 4;
 
     const long colb = (col0 + i < ncols) ? col0 + i : ncols - 1;
-    const int k2 = (DIM == 3) ? (int)(colb / n1) : 0;
-    const int k3 = (DIM == 3) ? (int)(colb % n1) : (int)colb;
+    const int k2 = (DIM == 3) ? (int)(colb / n1c) : 0;
+    const int k3 = (DIM == 3) ? (int)(colb % n1c) : (int)colb;
 
     v4d acc[MB];
 #pragma unroll
@@ -80,7 +82,7 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
     if (c < ncols) {
         double xs;
         if constexpr (DIM == 3) {
-            const double x2 = (double)(c / n1) * dx2, x3 = (double)(c % n1) * dx3;
+            const double x2 = (double)(c / n1c) * dx2, x3 = (double)(c % n1c) * dx3;
             xs = x2 * x2 + x3 * x3;
         } else {
             const double x3 = (double)c * dx3;

@@ -217,7 +217,11 @@ gs_status launch(gs_batch_s* b, const TuneEntry& c, const double* const* rho, do
 std::string shape_key(const gs_batch_s* b) {
     std::map<std::string, int> c;
     for (gs_plan p : b->plans)
-        c[std::to_string(p->d) + "d" + std::to_string(p->n) + (p->kernel == GS_DIPOLAR_3D ? "dip" : "")]++;
+    {
+        std::string dims = std::to_string(p->nc[0]);
+        for (int i = 1; i < p->d; ++i) dims += "x" + std::to_string(p->nc[i]);
+        c[std::to_string(p->d) + "d" + dims + (p->kernel == GS_DIPOLAR_3D ? "dip" : "")]++;
+    }
     std::string k;
     for (const auto& [s, cnt] : c) k += (k.empty() ? "" : ",") + s + "x" + std::to_string(cnt);
     return k;
@@ -313,9 +317,10 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
         if (!p->X1) return fail(GS_ERR_INVALID_ARG, "a batched plan needs its workspace (GS_PLAN_NO_WORKSPACE)");
         if (!seen.insert(p).second) return fail(GS_ERR_INVALID_ARG, "a plan appears twice in the batch");
         if (p->device != plans[0]->device) return fail(GS_ERR_INVALID_ARG, "batch spans devices");
-        if (!gsk::batch_size_supported(p->d, p->n)) {
+        if (!p->cube || !gsk::batch_size_supported(p->d, p->n)) {
             if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED)
-                return fail(GS_ERR_UNSUPPORTED_SIZE, "batched kernels cover n <= 128 of the compiled list");
+                return fail(GS_ERR_UNSUPPORTED_SIZE,
+                            "batched kernels cover grids with the same n <= 128 of the compiled list on every axis");
             kernels_ok = false;
         }
         if (p->nslabs != 1) {
@@ -330,7 +335,7 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
     b->user = (hipStream_t)opt.stream;
     b->req = opt;
     b->kernels_ok = kernels_ok;
-    for (gs_plan p : b->plans) b->points += std::pow((double)p->n, p->d);
+    for (gs_plan p : b->plans) b->points += (double)p->nc[0] * p->nc[1] * (p->d == 3 ? p->nc[2] : 1);
     DeviceScope ds(b->device);
     hipError_t e = ds.err;
     gs_status st = GS_OK;

@@ -37,15 +37,23 @@ struct EvalArgs {
     double* energy = nullptr;
     double* epart = nullptr;
     double escale = 0.0;
+    // Grids whose axes have their own n (rectangular grids): the extents of the x, y, z axes
+    // (n above is unused unless nx = ny (= nz) = n) and each axis' twiddle table.
+    int nx = 0, ny = 0, nz = 0;
+    const double2* twx = nullptr;
+    const double2* twy = nullptr;
+    const double2* twz = nullptr;
 };
 
-// Blocks of the x-inverse pass (the energy partial sums it writes).
-int energy_blocks(int d, int n);
+// Blocks of the x-inverse pass (the energy partial sums it writes) of an (nx, ny, nz) grid
+// (2D: nz = 1).
+int energy_blocks(int d, int nx, int ny, int nz);
 // energy[0] = scale * (part[0] + ... + part[count-1]) in a fixed order (one block).
 hipError_t launch_energy_finish(const double* part, int count, double scale, double* energy, hipStream_t s);
 
 // Passes: 1 x_r2c, 2 y_fwd, 3 fused, 4 y_inv, 5 x_c2r.  `which` < 0 runs all five on the
-// slab given in the arguments (a whole evaluation when the slab covers kx = 0..n).
+// slab given in the arguments (a whole evaluation when the slab covers kx = 0..n).  A grid
+// whose extents nx, ny (, nz) differ runs each pass at the length of the axis it transforms.
 hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which = -1);
 bool eval_size_supported(int d, int n);
 int eval_sizes(int d, long long* out, int cap);
@@ -53,6 +61,7 @@ int eval_sizes(int d, long long* out, int cap);
 // Octant indices (k1, k2, k3) = (kx, ky, kz) in 3D and (k1, k3) = (kx, ky) in 2D.
 struct AssemblyArgs {
     int d = 3, n1 = 0, Qp = 0, ldk = 0;
+    int n1b = 0, n1c = 0;             // extents of k2, k3 (0: n1, a cubic octant)
     const double* AT = nullptr;       // [Qp][ldk]: w_q F_x[k][q]
     const double* FB = nullptr;       // [Qp][ldk]: F_y[k][q] (3D)
     const double* FC = nullptr;       // [Qp][ldk]: F_z[k][q] (3D), F_y[k][q] (2D)

@@ -6,17 +6,46 @@
 
 namespace gsk {
 
-#define GS_DECL(N) hipError_t launch_eval_##N(const EvalArgs&, hipStream_t, int); int energy_blocks_##N(int);
+#define GS_DECL(N)                                                   \
+    hipError_t launch_eval_##N(const EvalArgs&, hipStream_t, int);   \
+    hipError_t launch_eval_g_##N(const EvalArgs&, hipStream_t, int); \
+    int energy_blocks_##N(int);                                      \
+    int energy_blocks_g_##N(int, int);
 GS_SIZE_LIST(GS_DECL)
 #undef GS_DECL
 
-int energy_blocks(int d, int n) {
-    switch (n) {
+static bool cubic(const EvalArgs& a) {
+    return a.nx == a.n && a.ny == a.n && (a.d == 2 || a.nz == a.n);
+}
+
+int energy_blocks(int d, int nx, int ny, int nz) {
+    if (nx == ny && (d == 2 || nz == nx)) {
+        switch (nx) {
 #define GS_CASE(N) \
     case N: return energy_blocks_##N(d);
+            GS_SIZE_LIST(GS_CASE)
+#undef GS_CASE
+            default: return 0;
+        }
+    }
+    switch (nx) {
+#define GS_CASE(N) \
+    case N: return energy_blocks_g_##N(ny, d == 3 ? nz : 1);
         GS_SIZE_LIST(GS_CASE)
 #undef GS_CASE
         default: return 0;
+    }
+}
+
+// One pass of a rectangular grid at the length of the axis it transforms.
+static hipError_t launch_pass_g(const EvalArgs& a, hipStream_t s, int pass) {
+    const int len = (pass == 1 || pass == 5) ? a.nx : (pass == 3 && a.d == 3) ? a.nz : a.ny;
+    switch (len) {
+#define GS_CASE(N) \
+    case N: return launch_eval_g_##N(a, s, pass);
+        GS_SIZE_LIST(GS_CASE)
+#undef GS_CASE
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -40,6 +69,15 @@ hipError_t launch_energy_finish(const double* part, int count, double scale, dou
 }
 
 hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which) {
+    if (!cubic(a)) {
+        for (int p = 1; p <= 5; ++p) {
+            if (which >= 0 && which != p) continue;
+            if (a.d == 2 && (p == 2 || p == 4)) continue;
+            const hipError_t e = launch_pass_g(a, s, p);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     switch (a.n) {
 #define GS_CASE(N) \
     case N: return launch_eval_##N(a, s, which);
@@ -87,15 +125,16 @@ int assembly_ldk(int n1) {
 
 template <int MB>
 static hipError_t launch_mb(const AssemblyArgs& a, hipStream_t s) {
-    const long ncols = (a.d == 3) ? (long)a.n1 * a.n1 : a.n1;
-    const int chunks = a.ldk / (MB * 16);
+    const int n1b = a.n1b > 0 ? a.n1b : a.n1, n1c = a.n1c > 0 ? a.n1c : a.n1;
+    const long ncols = (a.d == 3) ? (long)n1b * n1c : n1c;
+    const int chunks = (a.n1 + MB * 16 - 1) / (MB * 16);
     dim3 grid((unsigned)((ncols + 63) / 64), chunks);
     if (a.d == 3)
-        k_assemble<MB, 3><<<grid, 256, 0, s>>>(a.AT, a.FB, a.FC, a.ldk, a.n1, a.Qp, a.out, a.A0, a.c2, a.dxi[0],
-                                               a.dxi[1], a.dxi[2], a.invM, a.dxx);
+        k_assemble<MB, 3><<<grid, 256, 0, s>>>(a.AT, a.FB, a.FC, a.ldk, a.n1, n1b, n1c, a.Qp, a.out, a.A0, a.c2,
+                                               a.dxi[0], a.dxi[1], a.dxi[2], a.invM, a.dxx);
     else
-        k_assemble<MB, 2><<<grid, 256, 0, s>>>(a.AT, a.FC, a.FC, a.ldk, a.n1, a.Qp, a.out, a.A0, a.c2, a.dxi[0],
-                                               a.dxi[2], a.dxi[2], a.invM, a.dxx);
+        k_assemble<MB, 2><<<grid, 256, 0, s>>>(a.AT, a.FC, a.FC, a.ldk, a.n1, n1b, n1c, a.Qp, a.out, a.A0, a.c2,
+                                               a.dxi[0], a.dxi[2], a.dxi[2], a.invM, a.dxx);
     return hipGetLastError();
 }
 

@@ -53,6 +53,87 @@ int GS_CAT(energy_blocks_, GS_N)(int d) {
     return (N + 2 * Geo<N>::PPX - 1) / (2 * Geo<N>::PPX) * (d == 3 ? N : 1);
 }
 
+// Rectangular grids (each axis its own n): x-pass blocks when N is the x length.
+int GS_CAT(energy_blocks_g_, GS_N)(int ny, int nz) {
+    constexpr int N = GS_N;
+    return (ny + 2 * Geo<N>::PPX - 1) / (2 * Geo<N>::PPX) * nz;
+}
+
+// Pass `pass` of a grid whose axes have their own n, N being the length the pass transforms
+// (x for passes 1 and 5, y for 2 and 4, the fused axis for 3: z in 3D, y in 2D).  One block
+// per tile or pencil group; the cache-hint variants as in the cubic launches.
+hipError_t GS_CAT(launch_eval_g_, GS_N)(const EvalArgs& a, hipStream_t s, int pass) {
+    constexpr int N = GS_N;
+    using Gm = Geo<N>;
+    Ext ext;
+    ext.nx = a.nx;
+    ext.ny = a.ny;
+    ext.nz = a.d == 3 ? a.nz : 1;
+    cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
+    cpx* const X2 = reinterpret_cast<cpx*>(a.X2);
+    const bool hint = (a.hint_bits >> (pass - 1)) & 1;
+    if (pass == 1 || pass == 5) {
+        const cpx* const tw = reinterpret_cast<const cpx*>(a.twx);
+        const dim3 gx((ext.ny + 2 * Gm::PPX - 1) / (2 * Gm::PPX), ext.nz);
+        if (pass == 1) {
+            if (hint) k_x_r2c_g<N, NT_P1><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw, ext);
+            else k_x_r2c_g<N, 0><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw, ext);
+            return hipGetLastError();
+        }
+        if (a.energy) {
+            if (hint) k_x_c2r_g<N, NT_P5, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart, ext);
+            else k_x_c2r_g<N, 0, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart, ext);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return launch_energy_finish(a.epart, (int)(gx.x * gx.y), a.escale, a.energy, s);
+        }
+        if (hint) k_x_c2r_g<N, NT_P5, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, nullptr, nullptr, ext);
+        else k_x_c2r_g<N, 0, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, nullptr, nullptr, ext);
+        return hipGetLastError();
+    }
+    DipoleArgs dip;
+    for (int i = 0; i < 3; ++i) {
+        dip.dxi[i] = a.dxi[i];
+        dip.cdiag[i] = a.cdiag[i];
+        dip.ccross[i] = a.ccross[i];
+    }
+    dip.nm_over_M = a.nm_over_M;
+    if constexpr (N <= GS_MAX_N_3D) {
+      if (a.d == 3) {
+        const cpx* const twy = reinterpret_cast<const cpx*>(a.twy);
+        const dim3 gy((ext.nz + Gm::PPY - 1) / Gm::PPY, a.kxn);
+        if (pass == 2) {
+            if (hint) k_y_fwd_g<N, NT_P2><<<gy, Gm::TY, 0, s>>>(X1, X2, twy, a.kx0, ext);
+            else k_y_fwd_g<N, 0><<<gy, Gm::TY, 0, s>>>(X1, X2, twy, a.kx0, ext);
+        } else if (pass == 4) {
+            if (hint) k_y_inv_g<N, NT_P4><<<gy, Gm::TY, 0, s>>>(X2, X1, twy, a.kx0, ext);
+            else k_y_inv_g<N, 0><<<gy, Gm::TY, 0, s>>>(X2, X1, twy, a.kx0, ext);
+        } else if (pass == 3) {
+            const cpx* const twz = reinterpret_cast<const cpx*>(a.twz);
+            const int np = a.kxn * 2 * ext.ny;
+            const unsigned nb = (unsigned)((np + Gm::PPZ - 1) / Gm::PPZ);
+            if (a.dipolar) {
+                if (hint) k_fused_g<N, 3, SPEC_DIPOLAR, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+                else k_fused_g<N, 3, SPEC_DIPOLAR, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+            } else {
+                if (hint) k_fused_g<N, 3, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+                else k_fused_g<N, 3, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+            }
+        } else {
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+      }
+    }
+    if (pass != 3 || a.d != 2) return hipErrorInvalidValue;
+    const cpx* const twy = reinterpret_cast<const cpx*>(a.twy);
+    const int np = ext.nx + 1;
+    const unsigned nb = (unsigned)((np + Gm::PPZ - 1) / Gm::PPZ);
+    if (hint) k_fused_g<N, 2, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, twy, np, 0, dip, ext);
+    else k_fused_g<N, 2, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, twy, np, 0, dip, ext);
+    return hipGetLastError();
+}
+
 hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int which) {
     constexpr int N = GS_N;
     using Gm = Geo<N>;

@@ -82,6 +82,12 @@ void free_device(gs_plan_s* p) {
     if (p->X1) (void)hipFree(p->X1);
     if (p->X2) (void)hipFree(p->X2);
     if (p->tw) (void)hipFree(p->tw);
+    for (int i = 0; i < 3; ++i) {
+        bool shared = p->twk[i] == p->tw;
+        for (int j = 0; j < i; ++j) shared = shared || p->twk[j] == p->twk[i];
+        if (p->twk[i] && !shared) (void)hipFree(p->twk[i]);
+        p->twk[i] = nullptr;
+    }
     if (p->epart) (void)hipFree(p->epart);
     if (p->mixpart) (void)hipFree(p->mixpart);
     p->epart = p->mixpart = nullptr;
@@ -94,18 +100,19 @@ void free_device(gs_plan_s* p) {
 }
 
 gs_status device_assembly(gs_plan_s* p) {
-    const int n1 = p->n + 1, Q = (int)p->table.w.size();
+    const int Q = (int)p->table.w.size();
+    const int n1 = p->nk[0] + 1, n1b = p->nk[1] + 1, n1c = p->nk[p->d - 1] + 1;
     const int Qp = (Q + 3) / 4 * 4;
-    const int ldk = gsk::assembly_ldk(n1);
+    const int ldk = std::max(gsk::assembly_ldk(n1), std::max(n1b, n1c));
     const size_t sz = (size_t)Qp * ldk;
     // operands [Qp][ldk], transposed factors: w_q Fx (AT), then Fy, then (3D) Fz
     const int nf = p->d - 1;                   // factor blocks after AT: y (and z)
     std::vector<double> ops(sz * (1 + nf), 0.0);
-    for (int q = 0; q < Q; ++q)
-        for (int k = 0; k < n1; ++k) {
-            ops[(size_t)q * ldk + k] = p->table.w[q] * p->Fk[0][(size_t)k * Q + q];
-            for (int j = 1; j <= nf; ++j) ops[sz * j + (size_t)q * ldk + k] = p->Fk[j][(size_t)k * Q + q];
-        }
+    for (int q = 0; q < Q; ++q) {
+        for (int k = 0; k < n1; ++k) ops[(size_t)q * ldk + k] = p->table.w[q] * p->Fk[0][(size_t)k * Q + q];
+        for (int j = 1; j <= nf; ++j)
+            for (int k = 0; k <= p->nk[j]; ++k) ops[sz * j + (size_t)q * ldk + k] = p->Fk[j][(size_t)k * Q + q];
+    }
     double* dops = nullptr;
     hipError_t e;
     if ((e = hipMalloc(&dops, ops.size() * 8)) != hipSuccess) return hip_fail(e, "hipMalloc(assembly)");
@@ -119,6 +126,8 @@ gs_status device_assembly(gs_plan_s* p) {
         gsk::AssemblyArgs a;
         a.d = p->d;
         a.n1 = n1;
+        a.n1b = p->d == 3 ? n1b : 0;
+        a.n1c = n1c;
         a.Qp = Qp;
         a.ldk = ldk;
         a.AT = dops;
@@ -130,7 +139,9 @@ gs_status device_assembly(gs_plan_s* p) {
         a.dxi[0] = M_PI / (2.0 * p->Lk[0]);
         a.dxi[1] = M_PI / (2.0 * p->Lk[1]);
         a.dxi[2] = M_PI / (2.0 * p->Lk[p->d - 1]);
-        a.invM = 1.0 / std::pow(2.0 * p->n, p->d);
+        double M = 1.0;
+        for (int j = 0; j < p->d; ++j) M *= 2.0 * p->nk[j];
+        a.invM = 1.0 / M;
         a.dxx = p->kernel == GS_DAVEY_STEWARTSON_2D ? 1 : 0;
         if ((e = gsk::load_assembly(a)) != hipSuccess) {
             st = hip_fail(e, "spectrum assembly kernel load");
@@ -186,6 +197,12 @@ gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) 
     if (!in || !out) return fail(GS_ERR_INVALID_ARG, "NULL device pointer");
     a.d = p->d;
     a.n = p->n;
+    a.nx = p->nk[0];
+    a.ny = p->nk[1];
+    a.nz = p->d == 3 ? p->nk[2] : 1;
+    a.twx = p->twk[0];
+    a.twy = p->twk[1];
+    a.twz = p->d == 3 ? p->twk[2] : nullptr;
     a.rho = in;
     a.u = out;
     a.X1 = p->X1;
@@ -202,14 +219,14 @@ gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) 
         a.ccross[1] = 3.0 * (p->dn[0] * p->dm[2] + p->dn[2] * p->dm[0]);
         a.ccross[2] = 3.0 * (p->dn[1] * p->dm[2] + p->dn[2] * p->dm[1]);
         const double nm = p->dn[0] * p->dm[0] + p->dn[1] * p->dm[1] + p->dn[2] * p->dm[2];
-        a.nm_over_M = nm / std::pow(2.0 * p->n, 3);
+        a.nm_over_M = nm / (8.0 * p->nk[0] * p->nk[1] * p->nk[2]);
     }
     return GS_OK;
 }
 
 bool set_slabs(gs_plan p, int planes, int streams) {
-    if (p->d != 3) return planes >= p->n + 1 && streams <= 1;
-    const int n1 = p->n + 1;
+    if (p->d != 3) return planes >= p->nk[0] + 1 && streams <= 1;
+    const int n1 = p->nk[0] + 1;
     planes = std::max(1, std::min(planes, n1));
     const int nsl = (n1 + planes - 1) / planes;
     const int slab = (n1 + nsl - 1) / nsl;
@@ -232,10 +249,11 @@ bool set_slabs(gs_plan p, int planes, int streams) {
 static hipError_t run_step(gs_plan p, gsk::EvalArgs& a, int step, hipStream_t s) {
     const auto [pass, c] = p->steps[step];
     a.kx0 = c * p->slab;
-    a.kxn = std::min(p->slab, p->n + 1 - a.kx0);
+    a.kxn = std::min(p->slab, p->nk[0] + 1 - a.kx0);
     gsk::EvalArgs b = a;
     // X2 holding every plane: the slab's planes sit at its own offset
-    if (p->d == 3 && p->x2_planes == p->n + 1 && p->nslabs > 1) b.X2 = a.X2 + (size_t)a.kx0 * 2 * p->n * p->n;
+    if (p->d == 3 && p->x2_planes == p->nk[0] + 1 && p->nslabs > 1)
+        b.X2 = a.X2 + (size_t)a.kx0 * 2 * p->nk[1] * p->nk[2];
     return gsk::launch_eval(b, s, pass);
 }
 
@@ -278,7 +296,7 @@ gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double*
         a.energy = energy;
         a.epart = p->epart;
         double cell = 1.0;
-        for (int i = 0; i < p->d; ++i) cell *= 2.0 * p->Lc[i] / p->n;
+        for (int i = 0; i < p->d; ++i) cell *= 2.0 * p->Lc[i] / p->nc[i];
         a.escale = 0.5 * cell;
     }
     if (!p->X1) return fail(GS_ERR_INVALID_ARG, "plan created without a workspace (GS_PLAN_NO_WORKSPACE): "
@@ -299,9 +317,9 @@ gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double*
 }
 
 size_t workspace_complex(gs_plan p) {
-    const size_t n = (size_t)p->n, n1 = n + 1;
-    if (p->d == 2) return n1 * n;
-    return n1 * n * n + 2 * n * n * (size_t)p->x2_planes;
+    const size_t nx = p->nk[0], ny = p->nk[1], nz = p->d == 3 ? p->nk[2] : 1;
+    if (p->d == 2) return (nx + 1) * ny;
+    return (nx + 1) * ny * nz + 2 * ny * nz * (size_t)p->x2_planes;
 }
 
 gs_status eval_chain_ws(gs_plan p, const double* in, double* out, double2* X1, double2* X2) {
@@ -372,7 +390,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     if (want_d != d) return fail(GS_ERR_INVALID_ARG, "kernel and dimension disagree");
     double Lmax = 0.0, Lmin = 0.0, sum2 = 0.0;
     for (int i = 0; i < d; ++i) {
-        if (n[i] != n[0]) return fail(GS_ERR_INVALID_ARG, "every axis must have the same n");
+        if (n[i] < 2 || n[i] > 1 << 20) return fail(GS_ERR_INVALID_ARG, "n out of range");
         if (!(L[i] > 0.0) || !std::isfinite(L[i])) return fail(GS_ERR_INVALID_ARG, "L must be positive");
         Lmax = std::max(Lmax, L[i]);
         Lmin = (i == 0) ? L[i] : std::min(Lmin, L[i]);
@@ -381,13 +399,20 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     // the near-field ball of the Taylor correction must fit the shortest axis
     if (k != GS_GAUSSIAN_SUM && !(opt.delta_rel < Lmin / Lmax))
         return fail(GS_ERR_INVALID_ARG, "delta_rel must be below the shortest half-width over the largest");
-    if (n[0] < 2 || n[0] > 1 << 20) return fail(GS_ERR_INVALID_ARG, "n out of range");
     if (!(opt.delta_rel > 0.0 && opt.delta_rel < 0.5)) return fail(GS_ERR_INVALID_ARG, "delta_rel out of (0, 0.5)");
     if (k != GS_GAUSSIAN_SUM && !(eps > 0.0 && eps < 1.0)) return fail(GS_ERR_INVALID_ARG, "eps out of (0, 1)");
     if (k != GS_GAUSSIAN_SUM && eps < 1e-15)
         return fail(GS_ERR_ACCURACY, "eps below the double-precision floor of the Gaussian-sum tables");
-    const int nn = (int)n[0];
-    if (!gsk::eval_size_supported(d, nn)) return fail(GS_ERR_UNSUPPORTED_SIZE, "no kernels compiled for this n");
+    int nc[3] = {1, 1, 1}, nk[3] = {1, 1, 1};
+    bool cube = true;
+    for (int i = 0; i < d; ++i) {
+        nc[i] = (int)n[i];
+        nk[i] = (int)n[d - 1 - i];
+        cube = cube && n[i] == n[0];
+        if (!gsk::eval_size_supported(d, nc[i]))
+            return fail(GS_ERR_UNSUPPORTED_SIZE, "no kernels compiled for n = " + std::to_string(nc[i]));
+    }
+    const int nn = *std::max_element(nc, nc + d);
     const bool host_only = (opt.flags & GS_PLAN_HOST_ONLY) != 0;
     const bool no_ws = (opt.flags & GS_PLAN_NO_WORKSPACE) != 0;
     if (no_ws && (opt.flags & GS_PLAN_AUTOTUNE))
@@ -411,9 +436,10 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
             return fail(GS_ERR_INVALID_ARG, "dipole vectors must be finite and non-zero");
     }
     {
-        const size_t n1 = (size_t)n[0] + 1, nn0 = (size_t)n[0];
-        const size_t ws = no_ws ? 0 : (d == 3 ? (n1 * nn0 * nn0 + 2 * nn0 * nn0 * n1) * 16 : n1 * nn0 * 16);
-        const size_t bytes = (d == 3 ? n1 * n1 * n1 * 8 : n1 * n1 * 8) + ws + 2 * nn0 * 16;
+        const size_t nx = nk[0], ny = nk[1], nz = d == 3 ? nk[2] : 1;
+        const size_t ws = no_ws ? 0 : (d == 3 ? 3 * (nx + 1) * ny * nz * 16 : (nx + 1) * ny * 16);
+        const size_t spec = (nx + 1) * (ny + 1) * (d == 3 ? nz + 1 : 1) * 8;
+        const size_t bytes = spec + ws + 2 * (nx + ny + nz) * 16;
         if (!host_only && bytes > workspace_cap())
             return fail(GS_ERR_OUT_OF_MEMORY, "plan exceeds GS_MAX_WORKSPACE_BYTES");
     }
@@ -428,6 +454,11 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->kernel = k;
     p->d = d;
     p->n = nn;
+    p->cube = cube;
+    for (int i = 0; i < 3; ++i) {
+        p->nc[i] = nc[i];
+        p->nk[i] = nk[i];
+    }
     p->L = Lmax;
     for (int i = 0; i < d; ++i) {
         p->Lc[i] = L[i];
@@ -464,20 +495,20 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     for (int i = 0; i < d; ++i) {
         int same = -1;
         for (int j = 0; j < i; ++j)
-            if (p->Lk[j] == p->Lk[i]) same = j;
+            if (p->Lk[j] == p->Lk[i] && p->nk[j] == p->nk[i]) same = j;
         if (same >= 0) p->Fk[i] = p->Fk[same];
-        else gsh::factors_1d(p->table.tau, p->Lk[i], nn, p->Fk[i]);
+        else gsh::factors_1d(p->table.tau, p->Lk[i], p->nk[i], p->Fk[i]);
     }
     gsh::taylor_constants(k, d, p->table, p->A0, p->c2);
 
-    const size_t n1 = (size_t)nn + 1;
-    p->spec_bytes = (d == 3 ? n1 * n1 * n1 : n1 * n1) * sizeof(double);
-    const size_t x1 = n1 * (d == 3 ? (size_t)nn * nn : (size_t)nn);
+    const size_t n1 = (size_t)nk[0] + 1;       // kx planes
+    p->spec_bytes = n1 * (nk[1] + 1) * (d == 3 ? nk[2] + 1 : 1) * sizeof(double);
+    const size_t x1 = n1 * nk[1] * (d == 3 ? (size_t)nk[2] : 1);
     size_t x2 = 0;
     if (d == 3) {
-        // kx slab of the middle passes; X2 (2n n complex per plane) holds one slab, or
+        // kx slab of the middle passes; X2 (2 ny nz complex per plane) holds one slab, or
         // every plane when slab chains run concurrently
-        const size_t plane = 2 * (size_t)nn * nn * sizeof(double2);
+        const size_t plane = 2 * (size_t)nk[1] * nk[2] * sizeof(double2);
         int per = (int)n1;
         if (opt.slab_planes > 0) per = std::min<int>(opt.slab_planes, (int)n1);
         else if (opt.slab_planes == 0) per = (int)std::max<size_t>(1, std::min<size_t>(n1, slab_budget() / plane));
@@ -490,12 +521,21 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         p->slab = (int)n1;
         p->steps = {{1, 0}, {3, 0}, {5, 0}};
     }
-    p->work_bytes = (no_ws ? 0 : (x1 + x2) * sizeof(double2)) + 2 * (size_t)nn * sizeof(double2);
+    // twiddle tables: one of length n for a cube, else one per distinct axis length
+    size_t tw_bytes = 0;
+    for (int i = 0; i < d; ++i) {
+        bool seen = false;
+        for (int j = 0; j < i; ++j) seen = seen || nk[j] == nk[i];
+        if (!seen) tw_bytes += 2 * (size_t)nk[i] * sizeof(double2);
+    }
+    p->work_bytes = (no_ws ? 0 : (x1 + x2) * sizeof(double2)) + tw_bytes;
 
     if (host_only) {
-        gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D, p->spec_host);
-        log(1, "host-only plan kernel=%d d=%d n=%d L=(%g, %g, %g) S=%d Q=%zu delta=%.3g A0=%.6g c2=%.6g", (int)k, d,
-            nn, p->Lc[0], p->Lc[1], p->Lc[2], p->table.S, p->table.w.size(), p->table.delta, p->A0, p->c2);
+        gsh::assemble_spectrum(d, p->nk, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D,
+                               p->spec_host);
+        log(1, "host-only plan kernel=%d d=%d n=(%d, %d, %d) L=(%g, %g, %g) S=%d Q=%zu delta=%.3g A0=%.6g c2=%.6g",
+            (int)k, d, p->nc[0], p->nc[1], p->nc[2], p->Lc[0], p->Lc[1], p->Lc[2], p->table.S, p->table.w.size(),
+            p->table.delta, p->A0, p->c2);
         std::lock_guard<std::mutex> g(g_live_mu);
         g_live.insert(p);
         *out = p;
@@ -518,22 +558,35 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace X1) failed");
         if (st == GS_OK && !no_ws && x2 && (e = hipMalloc(&p->X2, x2 * sizeof(double2))) != hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace X2) failed");
-        if (st == GS_OK && (e = hipMalloc(&p->tw, 2 * (size_t)nn * sizeof(double2))) != hipSuccess)
-            st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(twiddles) failed");
+        // per-axis twiddle tables (the cubic passes use tw, which is the x axis' table)
+        for (int i = 0; i < d && st == GS_OK; ++i) {
+            int same = -1;
+            for (int j = 0; j < i; ++j)
+                if (nk[j] == nk[i]) same = j;
+            if (same >= 0) {
+                p->twk[i] = p->twk[same];
+                continue;
+            }
+            if ((e = hipMalloc(&p->twk[i], 2 * (size_t)nk[i] * sizeof(double2))) != hipSuccess) {
+                st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(twiddles) failed");
+                break;
+            }
+            std::vector<double> tw;
+            gsh::twiddles(nk[i], tw);
+            if ((e = hipMemcpy(p->twk[i], tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+                st = hip_fail(e, "hipMemcpy(twiddles)");
+        }
+        if (st == GS_OK) p->tw = p->twk[0];
         if (st == GS_OK && !no_ws &&
-            (e = hipMalloc(&p->epart, (size_t)gsk::energy_blocks(d, nn) * sizeof(double))) != hipSuccess)
+            (e = hipMalloc(&p->epart, (size_t)gsk::energy_blocks(d, nk[0], nk[1], nk[2]) * sizeof(double))) !=
+                hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(energy partial sums) failed");
         if (st == GS_OK && (e = hipMalloc(&p->mixpart, mixture_partial_doubles() * sizeof(double))) != hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(mixture partial sums) failed");
         if (st == GS_OK) {
-            std::vector<double> tw;
-            gsh::twiddles(nn, tw);
-            if ((e = hipMemcpy(p->tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
-                st = hip_fail(e, "hipMemcpy(twiddles)");
-        }
-        if (st == GS_OK) {
             if (opt.flags & GS_PLAN_HOST_ASSEMBLY) {
-                gsh::assemble_spectrum(d, nn, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D, p->spec_host);
+                gsh::assemble_spectrum(d, p->nk, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D,
+                                       p->spec_host);
                 if ((e = hipMemcpy(p->spec, p->spec_host.data(), p->spec_bytes, hipMemcpyHostToDevice)) != hipSuccess)
                     st = hip_fail(e, "hipMemcpy(spectrum)");
             } else {
@@ -586,7 +639,10 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
     info->d = p->d;
     info->n = p->n;
     info->L = p->L;
-    for (int i = 0; i < p->d; ++i) info->L_axes[i] = p->Lc[i];
+    for (int i = 0; i < p->d; ++i) {
+        info->L_axes[i] = p->Lc[i];
+        info->n_axes[i] = p->nc[i];
+    }
     info->beta = p->table.beta;
     info->eps = p->eps;
     info->delta = p->table.delta;
@@ -597,7 +653,7 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
     info->spectrum_bytes = p->spec_bytes;
     info->workspace_bytes = p->work_bytes;
     info->assembly_ms = p->assembly_ms;
-    info->assembly_gflop = 2.0 * info->Q * std::pow((double)p->n + 1, p->d) * 1e-9;
+    info->assembly_gflop = 2.0 * info->Q * (p->nk[0] + 1.0) * (p->nk[1] + 1.0) * (p->d == 3 ? p->nk[2] + 1.0 : 1.0) * 1e-9;
     info->host_only = p->host_only ? 1 : 0;
     info->slab_planes = p->slab;
     info->num_steps = (int)p->steps.size();
@@ -652,16 +708,16 @@ gs_status gs_plan_spectrum(gs_plan p, double* host_out, size_t capacity) {
 gs_status gs_plan_buffer(gs_plan p, int which, int to_device, double* host, size_t count) {
     if (!is_live(p) || !host) return fail(GS_ERR_INVALID_ARG, "invalid plan or pointer");
     if (p->host_only) return fail(GS_ERR_INVALID_ARG, "host-only plan has no device buffers");
-    const size_t n = p->n, n1 = n + 1;
+    const size_t nx = p->nk[0], ny = p->nk[1], nz = p->d == 3 ? p->nk[2] : 1;
     void* buf = nullptr;
     size_t doubles = 0;
     if ((which == 1 || which == 2) && !p->X1) return fail(GS_ERR_INVALID_ARG, "plan has no workspace");
     if (which == 1) {
         buf = p->X1;
-        doubles = 2 * n1 * (p->d == 3 ? n * n : n);
+        doubles = 2 * (nx + 1) * ny * nz;
     } else if (which == 2 && p->d == 3) {
         buf = p->X2;
-        doubles = 2 * 2 * n * n * (size_t)p->x2_planes;
+        doubles = 2 * 2 * ny * nz * (size_t)p->x2_planes;
     } else if (which == 3) {
         buf = p->spec;
         doubles = p->spec_bytes / sizeof(double);
@@ -742,9 +798,10 @@ gs_status time_plan(gs_plan_s* p, const double* rho, double* u, double& ms) {
 // the compiled defaults, flip each pass's cache-hint variant in turn and keep what is
 // faster, then try one and four rounds of co-resident blocks in the fused pass.
 gs_status plan_autotune(gs_plan_s* p) {
-    const std::string key = tune_device_key(p->device) + "|plan|d" + std::to_string(p->d) + "|n" +
-                            std::to_string(p->n) + (p->kernel == GS_DIPOLAR_3D ? "|dip" : "") + "|slab" +
-                            std::to_string(p->slab);
+    std::string dims = std::to_string(p->nc[0]);
+    for (int i = 1; i < p->d; ++i) dims += "x" + std::to_string(p->nc[i]);
+    const std::string key = tune_device_key(p->device) + "|plan|d" + std::to_string(p->d) + "|n" + dims +
+                            (p->kernel == GS_DIPOLAR_3D ? "|dip" : "") + "|slab" + std::to_string(p->slab);
     TuneEntry te;
     if (tune_lookup(key, te)) {
         p->hint_bits = te.schedule;
@@ -753,7 +810,7 @@ gs_status plan_autotune(gs_plan_s* p) {
         p->tuned_ms = te.ms;
         return GS_OK;
     }
-    const size_t pts = (size_t)std::pow((double)p->n, p->d);
+    const size_t pts = (size_t)p->nc[0] * p->nc[1] * (p->d == 3 ? p->nc[2] : 1);
     double *rho = nullptr, *u = nullptr;
     if (hipMalloc(&rho, pts * sizeof(double)) != hipSuccess || hipMalloc(&u, pts * sizeof(double)) != hipSuccess) {
         if (rho) (void)hipFree(rho);
@@ -778,7 +835,7 @@ gs_status plan_autotune(gs_plan_s* p) {
         else p->hint_bits = keep;
     }
     for (int m : {1, 4}) {
-        if (st != GS_OK || !gs_fused_persistent(p->d, p->n)) break;   // grid fixed by the group count
+        if (st != GS_OK || !p->cube || !gs_fused_persistent(p->d, p->n)) break;   // grid fixed by the group count
         const int keep = p->fused_mult;
         p->fused_mult = m;
         double ms = 0;

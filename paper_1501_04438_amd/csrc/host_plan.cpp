@@ -523,37 +523,39 @@ void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2)
 
 // ------------------------------------------------------------------ host assembly
 
-void assemble_spectrum(int d, int n, const double* Lk, const Table& t, const std::vector<double>* Fk, double A0,
-                       double c2, bool dxx, std::vector<double>& S) {
-    const int n1 = n + 1, Q = (int)t.w.size();
+void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, const std::vector<double>* Fk,
+                       double A0, double c2, bool dxx, std::vector<double>& S) {
+    const int na = nk[0] + 1, nb = nk[1] + 1, nc = nk[d - 1] + 1, Q = (int)t.w.size();
     const double dxa = PI / (2.0 * Lk[0]), dxb = PI / (2.0 * Lk[1]), dxc = PI / (2.0 * Lk[d - 1]);
     const std::vector<double>& Fa = Fk[0];
     const std::vector<double>& Fb = Fk[1];
     const std::vector<double>& Fc = Fk[d - 1];
-    const double invM = 1.0 / std::pow(2.0 * n, d);
-    S.assign(d == 3 ? (size_t)n1 * n1 * n1 : (size_t)n1 * n1, 0.0);
-    parallel_for(n1, [&](int a0, int a1) {
+    double M = 1.0;
+    for (int j = 0; j < d; ++j) M *= 2.0 * nk[j];
+    const double invM = 1.0 / M;
+    S.assign(d == 3 ? (size_t)na * nb * nc : (size_t)na * nb, 0.0);
+    parallel_for(na, [&](int a0, int a1) {
         std::vector<double> wa(Q);
         for (int a = a0; a < a1; ++a) {
             for (int q = 0; q < Q; ++q) wa[q] = t.w[q] * Fa[(size_t)a * Q + q];
             const double xa = a * dxa;
             const double fa = dxx ? -(xa * xa) * invM : invM;
             if (d == 2) {
-                for (int b = 0; b < n1; ++b) {
+                for (int b = 0; b < nb; ++b) {
                     double acc = 0.0;
                     for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q];
                     const double xb = b * dxb;
-                    S[(size_t)a * n1 + b] = (acc + A0 - c2 * (xa * xa + xb * xb)) * fa;
+                    S[(size_t)a * nb + b] = (acc + A0 - c2 * (xa * xa + xb * xb)) * fa;
                 }
                 continue;
             }
-            for (int b = 0; b < n1; ++b) {
+            for (int b = 0; b < nb; ++b) {
                 const double xb = b * dxb;
-                for (int cc = 0; cc < n1; ++cc) {
+                for (int cc = 0; cc < nc; ++cc) {
                     double acc = 0.0;
                     for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q] * Fc[(size_t)cc * Q + q];
                     const double xc = cc * dxc;
-                    S[((size_t)a * n1 + b) * n1 + cc] = (acc + A0 - c2 * (xa * xa + xb * xb + xc * xc)) * fa;
+                    S[((size_t)a * nb + b) * nc + cc] = (acc + A0 - c2 * (xa * xa + xb * xb + xc * xc)) * fa;
                 }
             }
         }

@@ -38,10 +38,10 @@ void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<dou
 // Taylor constants of the near-field correction (Section 2.3).
 void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2);
 
-// Host assembly of the stored octant (n+1)^d, 1/(2n)^d folded in.  Octant axes
-// (kx, ky[, kz]): Lk[i] and Fk[i] are the half-width and factors of axis x, y[, z].
-// dxx: multiply by -xi_x^2, the symbol of d_xx (Davey-Stewartson).
-void assemble_spectrum(int d, int n, const double* Lk, const Table& t, const std::vector<double>* Fk,
+// Host assembly of the stored octant prod_i (n_i + 1), 1/prod_i (2 n_i) folded in.  Octant
+// axes (kx, ky[, kz]): nk[i], Lk[i] and Fk[i] are the points, half-width and factors of axis
+// x, y[, z].  dxx: multiply by -xi_x^2, the symbol of d_xx (Davey-Stewartson).
+void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, const std::vector<double>* Fk,
                        double A0, double c2, bool dxx, std::vector<double>& S);
 
 // exp(-i pi m / n), m = 0..2n-1, as interleaved (re, im).

@@ -29,14 +29,14 @@ constexpr int MAX_K = 64;
 constexpr int GRAD_GRID = 1024;  // blocks of the gradient launch (they loop over tiles)
 
 struct MixGeom {
-    int d, n, rows, rpt;         // points per axis, grid rows, rows per tile
+    int d, n, ny, rows, rpt;     // points along x (a row), along y, grid rows, rows per tile
     double x0[3], h[3];          // axis x, y, z: coordinate of index i = x0 + i h
 };
 
 // Row r of the grid: (y, z) indices (2D: z = 0).
 __device__ __forceinline__ void row_yz(const MixGeom& g, int r, int& y, int& z) {
-    y = r % g.n;
-    z = r / g.n;
+    y = r % g.ny;
+    z = r / g.ny;
 }
 
 // Sum of one value per thread of a 256-thread block in a fixed order; valid in thread 0.
@@ -167,9 +167,10 @@ __global__ void __launch_bounds__(MT) k_mix_grad_finish(int d, int K, int c0, in
 MixGeom geom(gs_plan p) {
     MixGeom g;
     g.d = p->d;
-    g.n = p->n;
-    g.rows = p->d == 3 ? p->n * p->n : p->n;
-    g.rpt = std::max(1, std::min(ROWS, 4096 / p->n));
+    g.n = p->nk[0];
+    g.ny = p->nk[1];
+    g.rows = p->d == 3 ? p->nk[1] * p->nk[2] : p->nk[1];
+    g.rpt = std::max(1, std::min(ROWS, 4096 / g.n));
     for (int j = 0; j < 3; ++j) {
         g.x0[j] = 0.0;
         g.h[j] = 0.0;
@@ -177,7 +178,7 @@ MixGeom geom(gs_plan p) {
     for (int j = 0; j < p->d; ++j) {               // axis j (x, y, z) is array axis d-1-j
         const double L = p->Lc[p->d - 1 - j];
         g.x0[j] = -L;
-        g.h[j] = 2.0 * L / p->n;
+        g.h[j] = 2.0 * L / p->nk[j];
     }
     return g;
 }

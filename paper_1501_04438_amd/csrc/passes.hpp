@@ -78,23 +78,32 @@ template <int N> struct Geo {
     static constexpr int TX = PPX * G, TY = PPY * G, TZ = PPZ * 2 * GZ;
 };
 
+// Extents of a grid whose axes have their own n (x, y, z; 2D: z = 1).  A pass compiled with
+// CUBE = true takes every extent as its transform length N (compile time) and ignores these;
+// with CUBE = false the extents of the axes it does not transform come from here, and every
+// row and pencil is bounds-checked.
+struct Ext {
+    int nx = 0, ny = 0, nz = 0;
+};
+
 // ---------------------------------------------------------------------------
 // P1: x-direction real-to-complex of zero-padded rows.  Block = one z, 2*PPX rows.
 // Two real rows a, b form c = a + i b; its padded transform C is split into the
 // Hermitian spectra A = (C[m] + conj C[2n-m])/2, B = (C[m] - conj C[2n-m])/(2i).
 // ---------------------------------------------------------------------------
-template <int N, int NT = NT_P1>
+template <int N, int NT = NT_P1, bool CUBE = true>
 __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp<cpx> __restrict__ X1,
                                            gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
-                                           cpx* lds) {
+                                           cpx* lds, Ext ext = Ext()) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPX, A = Gm::A;
+    const int NY = CUBE ? N : ext.ny;          // rows (y) of a plane
     const int tA = tid % G, pA = tid / G;      // load role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive y
     const int y0 = bx * 2 * PP;
     // rows beyond n exist only when 2 PPX does not divide n
-    constexpr bool FULL = (N % (2 * PP) == 0);
-    const bool okA = active && (FULL || (y0 + 2 * pA) < N), okB = active && (FULL || (y0 + 2 * pB) < N);
+    constexpr bool FULL = CUBE && (N % (2 * PP) == 0);
+    const bool okA = active && (FULL || (y0 + 2 * pA) < NY), okB = active && (FULL || (y0 + 2 * pB) < NY);
     // the two real rows of pair p: y0 + p and y0 + PP + p when the tile divides the grid and
     // holds 8 pairs (each 16-byte store instruction on the transposed X1 side then fills whole
     // 128-byte lines: P1 at 256^3 0.0765 -> 0.0706 ms), else y0 + 2p and y0 + 2p + 1
@@ -104,14 +113,14 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
 
     cpx x[E];
     {
-        gp<const double> ra = rho + ((size_t)z * N + rowA) * N;
+        gp<const double> ra = rho + ((size_t)z * NY + rowA) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = tA + G * e;
             x[e] = okA ? cmk(ldg<NT & 1>(ra + j), ldg<NT & 1>(ra + (size_t)RS * N + j)) : cmk(0.0, 0.0);
         }
     }
-    gp<cpx> out = X1 + (size_t)z * (N + 1) * N + rowB;
+    gp<cpx> out = X1 + (size_t)z * (N + 1) * NY + rowB;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         cpx v[E];
@@ -136,7 +145,7 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
                 const cpx df = cmk(zk.x - zp.x, zk.y + zp.y);                        //  Z - conj P
                 const cpx sb = cmk(0.5 * df.y, -0.5 * df.x);                         // /(2i)
                 const int m = 2 * k + h;
-                gp<cpx> o = out + (size_t)m * N;
+                gp<cpx> o = out + (size_t)m * NY;
                 stg<(NT & 2) != 0>(o, sa);
                 stg<(NT & 2) != 0>(o + RS, sb);
             }
@@ -162,24 +171,25 @@ k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
 // ---------------------------------------------------------------------------
 // EN: also returns this thread's part of sum_i rho_i u_i over the outputs it stores (rho
 // read at those outputs before they are written, so u may alias rho), in a fixed order.
-template <int N, int NT = NT_P5, bool EN = false>
+template <int N, int NT = NT_P5, bool EN = false, bool CUBE = true>
 __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> u,
                                              gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
-                                             cpx* lds, gp<const double> erho = nullptr) {
+                                             cpx* lds, gp<const double> erho = nullptr, Ext ext = Ext()) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPX, A = Gm::A;
+    const int NY = CUBE ? N : ext.ny;          // rows (y) of a plane
     const int tA = tid % G, pA = tid / G;      // store role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive y
     const int y0 = bx * 2 * PP;
     // rows beyond n exist only when 2 PPX does not divide n
-    constexpr bool FULL = (N % (2 * PP) == 0);
-    const bool okA = active && (FULL || (y0 + 2 * pA) < N), okB = active && (FULL || (y0 + 2 * pB) < N);
+    constexpr bool FULL = CUBE && (N % (2 * PP) == 0);
+    const bool okA = active && (FULL || (y0 + 2 * pA) < NY), okB = active && (FULL || (y0 + 2 * pB) < NY);
     // rows of pair p as in x_r2c_tile (y0 + p and y0 + PP + p when the tile divides the grid and
     // holds 8 pairs: whole 128-byte lines per load instruction on the transposed X1 side)
     constexpr bool SPLIT = FULL && PP >= 8;
     constexpr int RS = SPLIT ? PP : 1;
     const int rowA = SPLIT ? y0 + pA : y0 + 2 * pA, rowB = SPLIT ? y0 + pB : y0 + 2 * pB;
-    gp<const cpx> in = X1 + (size_t)z * (N + 1) * N + rowB;
+    gp<const cpx> in = X1 + (size_t)z * (N + 1) * NY + rowB;
 
     cpx acc[E];
 #pragma unroll
@@ -194,7 +204,7 @@ __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<d
             const int mm = direct ? m : 2 * N - m;
             cpx a = cmk(0.0, 0.0), b = cmk(0.0, 0.0);
             if (okB) {
-                gp<const cpx> p = in + (size_t)mm * N;
+                gp<const cpx> p = in + (size_t)mm * NY;
                 a = ldg<NT & 1>(p);
                 b = ldg<NT & 1>(p + RS);
             }
@@ -209,7 +219,7 @@ __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<d
     }
     double part = 0.0;
     if (okA) {
-        const size_t o = ((size_t)z * N + rowA) * N;
+        const size_t o = ((size_t)z * NY + rowA) * N;
         gp<double> ua = u + o;
         if constexpr (EN) {
             gp<const double> ra = erho + o;
@@ -279,27 +289,28 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r_energy(const cpx* __restri
 // ---------------------------------------------------------------------------
 // P2: y-direction forward with zero padding.  Block = one kx, PPY consecutive z.
 // ---------------------------------------------------------------------------
-template <int N, int NT = NT_P2>
+template <int N, int NT = NT_P2, bool CUBE = true>
 __device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx> __restrict__ X2,
                                            gp<const cpx> __restrict__ tw, int kx0, int bx, int kxl, int tid,
-                                           bool active, cpx* lds) {
+                                           bool active, cpx* lds, Ext ext = Ext()) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
+    const int NX = CUBE ? N : ext.nx, NZ = CUBE ? N : ext.nz;
     const int tA = tid % G, pA = tid / G;      // load role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive z
     const int kx = kx0 + kxl;                         // slab-local and global kx
     const int z0 = bx * PP;
     // z beyond n exists only when PPY does not divide n
-    constexpr bool FULL = (N % PP == 0);
-    const bool okA = active && (FULL || (z0 + pA) < N), okB = active && (FULL || (z0 + pB) < N);
+    constexpr bool FULL = CUBE && (N % PP == 0);
+    const bool okA = active && (FULL || (z0 + pA) < NZ), okB = active && (FULL || (z0 + pB) < NZ);
 
     cpx x[E];
     {
-        gp<const cpx> src = X1 + ((size_t)(z0 + pA) * (N + 1) + kx) * N;
+        gp<const cpx> src = X1 + ((size_t)(z0 + pA) * (NX + 1) + kx) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = okA ? ldg<NT & 1>(src + tA + G * e) : cmk(0.0, 0.0);
     }
-    gp<cpx> dst = X2 + (size_t)kxl * 2 * N * N + z0 + pB;
+    gp<cpx> dst = X2 + (size_t)kxl * 2 * N * NZ + z0 + pB;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         cpx v[E];
@@ -309,7 +320,7 @@ __device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx
         fft<typename Gm::F, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
         if (okB) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) stg<(NT & 2) != 0>(dst + (size_t)(2 * (tB + G * e) + h) * N, v[e]);
+            for (int e = 0; e < E; ++e) stg<(NT & 2) != 0>(dst + (size_t)(2 * (tB + G * e) + h) * NZ, v[e]);
         }
         lds_barrier();
     }
@@ -326,20 +337,21 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1
 // ---------------------------------------------------------------------------
 // P4: y-direction inverse with cropping.  Block = one kx, PPY consecutive z.
 // ---------------------------------------------------------------------------
-template <int N, int NT = NT_P4>
+template <int N, int NT = NT_P4, bool CUBE = true>
 __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx> __restrict__ X1,
                                            gp<const cpx> __restrict__ tw, int kx0, int bx, int kxl, int tid,
-                                           bool active, cpx* lds) {
+                                           bool active, cpx* lds, Ext ext = Ext()) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
+    const int NX = CUBE ? N : ext.nx, NZ = CUBE ? N : ext.nz;
     const int tA = tid % G, pA = tid / G;      // store role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive z
     const int kx = kx0 + kxl;
     const int z0 = bx * PP;
     // z beyond n exists only when PPY does not divide n
-    constexpr bool FULL = (N % PP == 0);
-    const bool okA = active && (FULL || (z0 + pA) < N), okB = active && (FULL || (z0 + pB) < N);
-    gp<const cpx> src = X2 + (size_t)kxl * 2 * N * N + z0 + pB;
+    constexpr bool FULL = CUBE && (N % PP == 0);
+    const bool okA = active && (FULL || (z0 + pA) < NZ), okB = active && (FULL || (z0 + pB) < NZ);
+    gp<const cpx> src = X2 + (size_t)kxl * 2 * N * NZ + z0 + pB;
 
     cpx acc[E];
 #pragma unroll
@@ -349,7 +361,7 @@ __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx
         cpx v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            v[e] = okB ? ldg<NT & 1>(src + (size_t)(2 * (tB + G * e) + h) * N) : cmk(0.0, 0.0);
+            v[e] = okB ? ldg<NT & 1>(src + (size_t)(2 * (tB + G * e) + h) * NZ) : cmk(0.0, 0.0);
         fft<typename Gm::F, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
         if (h) twist_out<typename Gm::F>(v, tA, tw);
 #pragma unroll
@@ -357,7 +369,7 @@ __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx
         lds_barrier();
     }
     if (okA) {
-        gp<cpx> dst = X1 + ((size_t)(z0 + pA) * (N + 1) + kx) * N;
+        gp<cpx> dst = X1 + ((size_t)(z0 + pA) * (NX + 1) + kx) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) stg<(NT & 2) != 0>(dst + tA + G * e, acc[e]);
     }
@@ -418,24 +430,25 @@ __device__ __forceinline__ void swap_halves(cpx& a, cpx& b) {
     }
 }
 
+// NY: the y extent (3D pencils X2[kx][ky][:], ky = 0..2 NY - 1)
 template <int N, int DIM>
-__device__ __forceinline__ int fused_pencil(int slot) {
+__device__ __forceinline__ int fused_pencil(int slot, int NY) {
     if constexpr (DIM == 2) {
         return slot;
     } else {
-        const int kx = slot / (2 * N), s = slot % (2 * N);
+        const int kx = slot / (2 * NY), s = slot % (2 * NY);
         const int i = s >> 1;
-        const int ky = (s == 0) ? 0 : (s == 1) ? N : ((s & 1) ? 2 * N - i : i);
-        return kx * 2 * N + ky;
+        const int ky = (s == 0) ? 0 : (s == 1) ? NY : ((s & 1) ? 2 * NY - i : i);
+        return kx * 2 * NY + ky;
     }
 }
 
 template <int N, int DIM>
-__device__ __forceinline__ gp<const double> fused_row(gp<const double> spec, int pencil, int kx0) {
+__device__ __forceinline__ gp<const double> fused_row(gp<const double> spec, int pencil, int kx0, int NY) {
     if constexpr (DIM == 3) {
-        const int kx = kx0 + pencil / (2 * N), ky = pencil % (2 * N);
-        const int aky = ky <= N ? ky : 2 * N - ky;
-        return spec + ((size_t)kx * (N + 1) + aky) * (N + 1);
+        const int kx = kx0 + pencil / (2 * NY), ky = pencil % (2 * NY);
+        const int aky = ky <= NY ? ky : 2 * NY - ky;
+        return spec + ((size_t)kx * (NY + 1) + aky) * (N + 1);
     } else {
         return spec + (size_t)pencil * (N + 1);
     }
@@ -451,9 +464,9 @@ __device__ __forceinline__ void fused_load(gp<const cpx> X, int pencil, bool ok,
 
 template <int N, int DIM, int NT>
 __device__ __forceinline__ void fused_spec(gp<const double> spec, int pencil, int kx0, bool ok, int t, int h,
-                                           double (&sv)[FftCfgFused<N>::E]) {
+                                           double (&sv)[FftCfgFused<N>::E], int NY) {
     constexpr int E = FftCfgFused<N>::E, G = FftCfgFused<N>::G;
-    gp<const double> srow = fused_row<N, DIM>(spec, ok ? pencil : 0, kx0);
+    gp<const double> srow = fused_row<N, DIM>(spec, ok ? pencil : 0, kx0, NY);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int m = 2 * (t + G * e) + h;          // padded index along the pencil
@@ -467,7 +480,7 @@ template <int N, int DIM, int MODE, int NT = NT_P3>
 __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx> __restrict__ tw, int pencil, int kx0,
                                            bool ok, const DipoleArgs& dip, int t, int h, int pl,
                                            cpx (&v)[FftCfgFused<N>::E], const double (&sv)[FftCfgFused<N>::E],
-                                           cpx* lds, cpx* area) {
+                                           cpx* lds, cpx* area, int NX, int NY) {
     using Gm = Geo<N>;
     using FZ = typename Gm::FZ;
     constexpr int E = Gm::EZ, G = Gm::GZ, A = Gm::AZ;
@@ -476,13 +489,13 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
     fft<FZ, false, FW>(v, t, area, t, area, tw);
     if constexpr (MODE == SPEC_DIPOLAR) {
         // (n.xi)(m.xi) with Nyquist taken as 0 in the odd (cross) factors
-        const int kx = (DIM == 3) ? kx0 + pencil / (2 * N) : pencil;
-        const int ky = (DIM == 3) ? pencil % (2 * N) : 0;
+        const int kx = (DIM == 3) ? kx0 + pencil / (2 * NY) : pencil;
+        const int ky = (DIM == 3) ? pencil % (2 * NY) : 0;
         const double xe = kx * dip.dxi[0];
-        const int sy = ky < N ? ky : ky - 2 * N;
+        const int sy = ky < NY ? ky : ky - 2 * NY;
         const double ye = sy * dip.dxi[1];
-        const double xo = (kx == N) ? 0.0 : xe;
-        const double yo = (ky == N) ? 0.0 : ye;
+        const double xo = (kx == NX) ? 0.0 : xe;
+        const double yo = (ky == NY) ? 0.0 : ye;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int m = 2 * (t + G * e) + h;
@@ -531,28 +544,30 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
 }
 
 // One pencil group of the fused pass without prefetch (the batched launches).
-template <int N, int DIM, int MODE, int NT = NT_P3>
+template <int N, int DIM, int MODE, int NT = NT_P3, bool CUBE = true>
 __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const double> __restrict__ spec,
                                             gp<const cpx> __restrict__ tw, int npencils, int kx0,
-                                            const DipoleArgs& dip, int g, int tid, bool active, cpx* lds) {
+                                            const DipoleArgs& dip, int g, int tid, bool active, cpx* lds,
+                                            Ext ext = Ext()) {
     using Gm = Geo<N>;
     using FZ = typename Gm::FZ;
     constexpr int E = Gm::EZ, G = Gm::GZ, PP = Gm::PPZ, A = Gm::AZ;
     constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
+    const int NX = CUBE ? N : ext.nx, NY = CUBE ? N : ext.ny;
     int t, h, pl;
     FusedRoles<N>::get(tid, t, h, pl);
     cpx* area = lds + (pl * 2 + h) * A;
     const int slot = g * PP + pl;
     // in 3D the pencil count is a multiple of 2n, so groups of PP pencils never run past it
     // when PP divides 2n; 2D has n + 1 pencils
-    constexpr bool FULL = (DIM == 3 && (2 * N) % PP == 0);
+    constexpr bool FULL = CUBE && (DIM == 3 && (2 * N) % PP == 0);
     const bool ok = active && (FULL || slot < npencils);
-    const int pencil = ok ? fused_pencil<N, DIM>(slot) : 0;
+    const int pencil = ok ? fused_pencil<N, DIM>(slot, NY) : 0;
     cpx v[E];
     double sv[E];
     fused_load<N, DIM, NT>(X, pencil, ok, t, v);
-    fused_spec<N, DIM, NT>(spec, pencil, kx0, ok, t, h, sv);
-    fused_body<N, DIM, MODE, NT>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area);
+    fused_spec<N, DIM, NT>(spec, pencil, kx0, ok, t, h, sv, NY);
+    fused_body<N, DIM, MODE, NT>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area, NX, NY);
 }
 
 template <int N, int DIM, int MODE, int NT = NT_P3>
@@ -574,6 +589,60 @@ __global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ Xg, cons
             fused_group<N, DIM, MODE, NT>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg, npencils, kx0,
                                           dip, g, threadIdx.x, true, lds);
     }
+}
+
+// ---------------------------------------------------------------------------
+// The passes on grids whose axes have their own n (Section 2.5 with per-axis n_j): the
+// transform length N is the n of the axis the pass transforms, the other extents come in
+// `ext`, and every row and pencil is bounds-checked.  One block per tile or pencil group.
+// ---------------------------------------------------------------------------
+template <int N, int NT>
+__global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c_g(const double* __restrict__ rho, cpx* __restrict__ X1,
+                                                        const cpx* __restrict__ tw, Ext ext) {
+    __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
+    x_r2c_tile<N, NT, false>((gp<const double>)rho, (gp<cpx>)X1, (gp<const cpx>)tw, blockIdx.x, blockIdx.y,
+                             threadIdx.x, true, lds, ext);
+}
+
+template <int N, int NT, bool EN>
+__global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r_g(const cpx* __restrict__ X1, double* u,
+                                                        const cpx* __restrict__ tw, const double* rho,
+                                                        double* __restrict__ part, Ext ext) {
+    __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
+    __shared__ double red[Geo<N>::TX / 64 + 1];
+    const double v = x_c2r_tile<N, NT, EN, false>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                                  blockIdx.y, threadIdx.x, true, lds, (gp<const double>)rho, ext);
+    if constexpr (EN) {
+        const double s = block_sum<Geo<N>::TX>(v, red);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+template <int N, int NT>
+__global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd_g(const cpx* __restrict__ X1, cpx* __restrict__ X2,
+                                                        const cpx* __restrict__ tw, int kx0, Ext ext) {
+    __shared__ cpx lds[Geo<N>::PPY * Geo<N>::A];
+    y_fwd_tile<N, NT, false>((gp<const cpx>)X1, (gp<cpx>)X2, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y,
+                             threadIdx.x, true, lds, ext);
+}
+
+template <int N, int NT>
+__global__ void __launch_bounds__(Geo<N>::TY) k_y_inv_g(const cpx* __restrict__ X2, cpx* __restrict__ X1,
+                                                        const cpx* __restrict__ tw, int kx0, Ext ext) {
+    __shared__ cpx lds[Geo<N>::PPY * Geo<N>::A];
+    y_inv_tile<N, NT, false>((gp<const cpx>)X2, (gp<cpx>)X1, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y,
+                             threadIdx.x, true, lds, ext);
+}
+
+template <int N, int DIM, int MODE, int NT>
+__global__ void __launch_bounds__(Geo<N>::TZ) k_fused_g(cpx* __restrict__ Xg, const double* __restrict__ specg,
+                                                        const cpx* __restrict__ twg, int npencils, int kx0,
+                                                        DipoleArgs dip, Ext ext) {
+    __shared__ cpx lds[Geo<N>::PPZ * 2 * Geo<N>::AZ];
+    const int ngroups = (npencils + Geo<N>::PPZ - 1) / Geo<N>::PPZ;
+    if ((int)blockIdx.x < ngroups)
+        fused_group<N, DIM, MODE, NT, false>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg, npencils, kx0,
+                                             dip, blockIdx.x, threadIdx.x, true, lds, ext);
 }
 
 }  // namespace gsk

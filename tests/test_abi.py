@@ -73,7 +73,9 @@ def test_argument_validation_statuses():
     assert _create(kernel=6, d=2, beta=2.0)[0] == 1      # beta must be below d
     st, h = _create(kernel=6, d=3, beta=1.5)
     assert st == 0 and _lib.lib().gs_plan_destroy(h) == 0
-    assert _create(nlist=[16, 16, 32])[0] == 1           # n must agree on every axis
+    assert _create(nlist=[16, 20, 32])[0] == 2           # every axis' n must be compiled
+    assert "n = 20" in _lib.lib().gs_last_error().decode()
+    assert _create(nlist=[16, 1, 32])[0] == 1            # and at least 2
     assert _create(L=(4.0, 4.0, -1.0))[0] == 1
     assert _create(L=(1e-4, 4.0, 4.0))[0] == 1           # near-field ball wider than the short axis
     assert "shortest" in _lib.lib().gs_last_error().decode()
@@ -85,6 +87,14 @@ def test_argument_validation_statuses():
     F = (C.c_double * (17 * info.Q))()
     assert _lib.lib().gs_plan_factors_axis(h, 3, F, len(F)) == 1
     assert _lib.lib().gs_plan_factors_axis(h, 0, F, len(F)) == 0
+    assert _lib.lib().gs_plan_destroy(h) == 0
+    st, h = _create(nlist=[16, 24, 32], L=(2.0, 3.0, 4.0))   # one n per axis
+    assert st == 0
+    assert _lib.lib().gs_plan_query(h, C.byref(info)) == 0
+    assert tuple(info.n_axes) == (16, 24, 32) and info.n == 32
+    assert _lib.lib().gs_plan_factors_axis(h, 1, F, len(F)) == 1     # 25 rows: capacity 17 Q too small
+    F25 = (C.c_double * (25 * info.Q))()
+    assert _lib.lib().gs_plan_factors_axis(h, 1, F25, len(F25)) == 0
     assert _lib.lib().gs_plan_destroy(h) == 0
 
 

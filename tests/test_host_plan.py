@@ -12,15 +12,17 @@ from oracle.factors import factor_1d
 def _octant_ref(op):
     """The library's stored octant, indexed [kx][ky]([kz]) (axes reversed from the
     oracle's array-order G), with the Taylor terms and 1/M folded in."""
-    n, d = op.n, op.d
+    d = op.d
     lap = 0.0
     for i in range(d):                          # octant axis i = array axis d-1-i
-        xi = oracle.padded_frequencies(n, op.Ls[d - 1 - i])[: n + 1]
+        m = op.ns[d - 1 - i]
+        xi = oracle.padded_frequencies(m, op.Ls[d - 1 - i])[: m + 1]
         lap = lap + np.expand_dims(xi ** 2, tuple(j for j in range(d) if j != i))
     G = op.G_oct.transpose(tuple(range(d - 1, -1, -1)))
-    S = (G + op.A0 - op.c2 * lap) / (2 * n) ** d
+    S = (G + op.A0 - op.c2 * lap) / op.M
     if op.kernel == "davey_stewartson2d":          # times -xi_x^2 along octant axis 0 (x)
-        xi = oracle.padded_frequencies(n, op.Ls[d - 1])[: n + 1]
+        m = op.ns[d - 1]
+        xi = oracle.padded_frequencies(m, op.Ls[d - 1])[: m + 1]
         S = S * -(xi ** 2)[:, None]
     return S
 
@@ -36,7 +38,7 @@ def _factors_and_constants(p, kernel, d, n, beta=None):
     w, tau = p.table()
     for ax in range(d):
         Lj = p.Ls[ax]
-        assert np.max(np.abs(p.factors(ax) - factor_1d(tau, 2.0 * Lj, n))) <= 4e-16 * 4 * Lj
+        assert np.max(np.abs(p.factors(ax) - factor_1d(tau, 2.0 * Lj, p.ns[ax]))) <= 4e-16 * 4 * Lj
     if kernel == "gaussian_sum":
         return
     dl = p.info["delta"]
@@ -128,3 +130,28 @@ def test_full_size_factors_and_constants(kernel, d, n, L, eps):
     p = gs.Plan(kernel, n=n, L=L, eps=eps, host_only=True)
     assert p.info["S"] == oracle.gs_table.physical_table(kernel, d, (L,) * d, eps, 1e-4).S
     _factors_and_constants(p, kernel, d, n)
+
+
+@pytest.mark.parametrize("kernel,d,n,L,eps", [("coulomb3d", 3, (12, 24, 16), (3.0, 6.0, 4.0), 1e-14),
+                                              ("dipolar3d", 3, (16, 8, 24), (4.0, 5.0, 6.0), 1e-14),
+                                              ("poisson2d", 2, (48, 96), (6.0, 12.0), 1e-13),
+                                              ("davey_stewartson2d", 2, (32, 64), (4.0, 7.0), 1e-13),
+                                              ("coulomb2d", 2, (64, 24), (8.0, 3.0), 1e-14)])
+def test_host_plan_per_axis_points(kernel, d, n, L, eps):
+    """Grids whose axes have their own n (Section 2.5 with one n_j per axis): the factors of
+    each axis at its own frequencies k = 0..n_j, the octant of (n_z+1)(n_y+1)(n_x+1) values
+    with 1/prod_j (2 n_j) folded in, against the oracle."""
+    dip = ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8)) if kernel == "dipolar3d" else None
+    p = gs.Plan(kernel, n=n, L=L, eps=eps, dipole=dip, host_only=True)
+    op = oracle.make_plan(kernel, d, n, L, eps=eps, dipole=dip)
+    assert p.info["n_axes"] == tuple(n) and p.shape == tuple(n)
+    assert p.info["S"] == op.table.S
+    _factors_and_constants(p, kernel, d, n)
+    S = p.spectrum()
+    assert S.shape == tuple(m + 1 for m in reversed(n))
+    ref = _octant_ref(op)
+    if kernel == "davey_stewartson2d":
+        xi2 = oracle.padded_frequencies(n[-1], op.Ls[-1])[1: n[-1] + 1, None] ** 2
+        assert np.all(S[0] == 0.0)
+        S, ref = S[1:] / -xi2, ref[1:] / -xi2
+    assert np.max(np.abs(S - ref)) <= 1e-13 * np.max(np.abs(ref))

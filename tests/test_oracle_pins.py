@@ -771,3 +771,39 @@ def test_factors_small_tau_relative_to_their_size(tau):
             ex = mp.quad(lambda y: mp.e ** (-(tau * y) ** 2) * mp.cos(mp.pi * k * y / c),
                          mp.linspace(-c, c, 2 * max(k, 1) + 1))
             assert abs(F[k] - float(ex)) <= 1e-15 * abs(float(ex)), (k, F[k], ex)
+
+
+# --------------------------------------------------------------------------
+# Grids whose axes have their own n (Section 2.5: the box prod_j [-L_j, L_j] with
+# n_j points on axis j; equal steps h on unequal sides need unequal n).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kernel,n,L,sigma", [("coulomb3d", (64, 96, 128), (4.0, 6.0, 8.0), 0.6),
+                                              ("coulomb3d", (96, 48, 64), (6.0, 3.0, 4.0), 0.45),
+                                              ("poisson2d", (96, 192), (6.0, 12.0), 0.8),
+                                              ("coulomb2d", (192, 64), (12.0, 4.0), 0.5)])
+def test_per_axis_points_gaussian_closed_form(kernel, n, L, sigma):
+    """A resolved Gaussian exp(-|x|^2/sigma^2) inside a box with unequal sides and the same
+    step h = 1/8 on every axis (so unequal n_j): the potential matches the closed form to
+    1e-13 of its maximum, as on cubes."""
+    d = len(n)
+    rho = workloads.gaussian(n, L, d, sigma=sigma)
+    u = oracle.evaluate(oracle.make_plan(kernel, d, n, L, eps=1e-13 if kernel == "poisson2d" else 1e-14), rho)
+    X = np.broadcast_arrays(*workloads.mesh(n, L, d))
+    r = np.sqrt(sum(x * x for x in X))
+    ex = {"coulomb3d": cf.coulomb3d_gaussian, "coulomb2d": cf.coulomb2d_gaussian,
+          "poisson2d": cf.poisson2d_gaussian}[kernel](r, sigma)
+    assert relmax(u, ex) <= 1e-13
+
+
+def test_per_axis_points_axis_permutation():
+    """Exchanging two axes (their n, L and the density's axes) exchanges the potential's
+    axes: the per-axis n enters the factors, frequencies and padding of its own axis only."""
+    rng = np.random.default_rng(17)
+    n, L = (12, 20, 16), (3.0, 5.0, 4.0)
+    rho = rng.standard_normal(n)
+    u = oracle.evaluate(oracle.make_plan("coulomb3d", 3, n, L), rho)
+    perm = (2, 0, 1)
+    np_, Lp = tuple(n[i] for i in perm), tuple(L[i] for i in perm)
+    up = oracle.evaluate(oracle.make_plan("coulomb3d", 3, np_, Lp), np.transpose(rho, perm))
+    assert relmax(np.transpose(u, perm), up) <= 1e-14

@@ -44,14 +44,27 @@ def half_widths(L, d: int) -> tuple:
     return Ls
 
 
-def mesh(n: int, L, d: int):
-    """Coordinate arrays (x, y[, z]) broadcastable to the ``[z][y][x]`` grid."""
+def points(n, d: int) -> tuple:
+    """``(n,)*d`` for one value, else the given per-axis points (C order)."""
+    if np.ndim(n) == 0:
+        return (int(n),) * d
+    ns = tuple(int(v) for v in n)
+    if len(ns) != d:
+        raise ValueError("one n per axis")
+    return ns
+
+
+def mesh(n, L, d: int):
+    """Coordinate arrays (x, y[, z]) broadcastable to the ``[z][y][x]`` grid (n and L one
+    value or one per axis in C order)."""
     if d not in (2, 3):
         raise ValueError("d must be 2 or 3")
     Ls = half_widths(L, d)
+    ns = points(n, d)
     if d == 2:
-        return axis(n, Ls[1])[None, :], axis(n, Ls[0])[:, None]
-    return axis(n, Ls[2])[None, None, :], axis(n, Ls[1])[None, :, None], axis(n, Ls[0])[:, None, None]
+        return axis(ns[1], Ls[1])[None, :], axis(ns[0], Ls[0])[:, None]
+    return (axis(ns[2], Ls[2])[None, None, :], axis(ns[1], Ls[1])[None, :, None],
+            axis(ns[0], Ls[0])[:, None, None])
 
 
 @dataclass
@@ -90,14 +103,16 @@ def sample_mixture(m: Mixture, n: int, L: float) -> np.ndarray:
     return out
 
 
-def gaussian(n: int, L, d: int, sigma: float = 1.0, center=None,
+def gaussian(n, L, d: int, sigma: float = 1.0, center=None,
              gammas=None, scale: float = 1.0) -> np.ndarray:
     """``scale * exp(-sum_i gamma_i^2 (x_i - c_i)^2 / sigma^2)`` on the grid
-    (center and gammas in (x, y[, z]) order; L scalar or per axis in C order)."""
+    (center and gammas in (x, y[, z]) order; n and L scalar or per axis in C order)."""
     Ls = half_widths(L, d)
+    ns = points(n, d)
     center = np.zeros(d) if center is None else np.asarray(center, float)
     gammas = np.ones(d) if gammas is None else np.asarray(gammas, float)
-    f = [np.exp(-((gammas[i] * (axis(n, Ls[d - 1 - i]) - center[i])) ** 2) / sigma ** 2) for i in range(d)]
+    f = [np.exp(-((gammas[i] * (axis(ns[d - 1 - i], Ls[d - 1 - i]) - center[i])) ** 2) / sigma ** 2)
+         for i in range(d)]
     if d == 3:
         return scale * (f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :])
     return scale * (f[1][:, None] * f[0][None, :])
