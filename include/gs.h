@@ -89,6 +89,15 @@ typedef enum {
                                      gs_eval_backward and batches refuse it with
                                      GS_ERR_INVALID_ARG; not with GS_PLAN_AUTOTUNE) */
 
+#define GS_PLAN_UNPADDED_LAPLACIAN 16 /* the Taylor term's Laplacian on the density's own
+                                     grid (spectral, period 2 L_j: Algorithm 1 step 3 read
+                                     on the unpadded grid) instead of the padded grid of
+                                     the convolution; still folded into the stored spectrum
+                                     (the padded transform at all-even indices is the
+                                     n-point transform of rho).  Kernels whose Taylor term
+                                     acts on rho itself only (INVALID_ARG for the dipolar
+                                     and Davey-Stewartson potentials) */
+
 /* Size of the fixed device array gs_eval_static uses as its workspace. */
 #define GS_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 

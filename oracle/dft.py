@@ -78,3 +78,19 @@ def full_dft(x: np.ndarray, sign: int = -1) -> np.ndarray:
     m = (kdx @ idx.T) % N2
     mat = np.exp(sign * 1j * math.pi * m / n)
     return (mat @ x.reshape(-1)).reshape((N2,) * d)
+
+
+@lru_cache(maxsize=16)
+def _periodic_phase(n: int, sign: int) -> np.ndarray:
+    j = np.arange(n, dtype=np.int64)
+    m = (j[:, None] * j[None, :]) % n
+    ang = 2.0 * math.pi * m.astype(np.float64) / n
+    return np.cos(ang) + sign * 1j * np.sin(ang)          # (n, n): exp(sign * 2 pi i m / n)
+
+
+def periodic(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    """Unpadded DFT of length n_j along every axis (the grid's own period), dense per axis."""
+    X = x.astype(np.complex128)
+    for ax in range(x.ndim):
+        X = _apply(X, _periodic_phase(x.shape[ax], sign), ax)
+    return X

@@ -9,7 +9,9 @@ Precomputation (plan):
 Actual computation (evaluate):
   1. rho~ = DFT(pad(rho))                                (eqs. (FourSeriB3), (rho_hat))
   2. I1   = (1/M) crop(IDFT(G . rho~))                   (eq. (I1FFT))
-  3. Lap  = (1/M) crop(IDFT(-|xi|^2 . rho~))             (spectral Laplacian)
+  3. Lap  = (1/M) crop(IDFT(-|xi|^2 . rho~))             (spectral Laplacian; or, with
+     laplacian="unpadded", the spectral Laplacian on the density's own grid,
+     period 2 L_j: DFT_n, -|xi'|^2 with xi'_k = pi k / L_j, k in [-n_j/2, n_j/2), IDFT_n / prod n_j)
   4. I21~ = A0 rho + c2 Lap                              (eq. (taylor))
   5. u    = I1 + I21~
 with M = prod_j 2 n_j.  The Laplacian is taken on the padded grid with the Nyquist
@@ -73,6 +75,7 @@ class OraclePlan:
     Fs: tuple = ()          # per-axis factor matrices, C order
     beta: float | None = None   # exponent of the inverse-power kernel r^-beta
     ns: tuple = ()          # points per axis, C order
+    laplacian: str = "padded"   # grid of the Taylor term's Laplacian: "padded" or "unpadded"
 
     @property
     def h(self) -> float:
@@ -96,9 +99,15 @@ class OraclePlan:
 
 
 def make_plan(kernel: str, d: int, n, L, eps: float = 1e-14,
-              delta_rel: float = 1e-4, custom=None, dipole=None, beta: float | None = None) -> OraclePlan:
+              delta_rel: float = 1e-4, custom=None, dipole=None, beta: float | None = None,
+              laplacian: str = "padded") -> OraclePlan:
     """n, L: one value for every axis (the cube [-L, L]^d with n^d points), or one per axis
-    in C order; beta: the exponent of kernel "inverse_power" (U = |x|^-beta, 0 < beta < d)."""
+    in C order; beta: the exponent of kernel "inverse_power" (U = |x|^-beta, 0 < beta < d);
+    laplacian: the grid on which the Taylor term takes the density's Laplacian (Algorithm 1
+    step 3): "padded" (the 2n grid of the convolution) or "unpadded" (the density's own
+    grid, periodic)."""
+    if laplacian not in ("padded", "unpadded"):
+        raise ValueError("laplacian: padded or unpadded")
     Ls = box_half_widths(L, d)
     ns = grid_points(n, d)
     if kernel == "gaussian_sum":
@@ -124,7 +133,7 @@ def make_plan(kernel: str, d: int, n, L, eps: float = 1e-14,
     dn = dm = None
     if kernel == "dipolar3d":
         dn, dm = dipole
-    return OraclePlan(kernel, d, max(ns), table.L, table, Fs[-1], G, A0, c2, dn, dm, Ls, Fs, beta, ns)
+    return OraclePlan(kernel, d, max(ns), table.L, table, Fs[-1], G, A0, c2, dn, dm, Ls, Fs, beta, ns, laplacian)
 
 
 def grid_points(n, d: int) -> tuple:
@@ -191,6 +200,20 @@ def dipolar_symbol(plan: OraclePlan) -> np.ndarray:
     return sym
 
 
+def periodic_laplacian(plan: OraclePlan, f: np.ndarray) -> np.ndarray:
+    """Spectral Laplacian of f on its own grid (period 2 L_j on axis j): symbol
+    -sum_j (pi k_j / L_j)^2 with k_j in [-n_j/2, n_j/2) (the Nyquist mode k = -n_j/2 kept)."""
+    sym = 0.0
+    for ax, (m, Lj) in enumerate(zip(plan.ns, plan.Ls)):
+        k = np.arange(m)
+        ks = np.where(k < m // 2, k, k - m).astype(np.float64)
+        xi = math.pi * ks / Lj
+        shape = [1] * plan.d
+        shape[ax] = m
+        sym = sym + (xi * xi).reshape(shape)
+    return dft.periodic(-sym * dft.periodic(f), sign=+1).real / float(np.prod(plan.ns))
+
+
 def _coulomb_steps(plan: OraclePlan, rt: np.ndarray, f: np.ndarray, sign: int = +1) -> np.ndarray:
     """I1 + A0 f + c2 Lap f for padded coefficients rt of the source f."""
     M = plan.M
@@ -198,7 +221,10 @@ def _coulomb_steps(plan: OraclePlan, rt: np.ndarray, f: np.ndarray, sign: int = 
     I1 = dft.inverse(G * rt, sign).real / M
     if plan.A0 == 0.0 and plan.c2 == 0.0:
         return I1
-    lap = dft.inverse(-laplacian_symbol(plan) * rt, sign).real / M
+    if plan.laplacian == "unpadded":
+        lap = periodic_laplacian(plan, f)
+    else:
+        lap = dft.inverse(-laplacian_symbol(plan) * rt, sign).real / M
     return I1 + plan.A0 * f + plan.c2 * lap
 
 
@@ -230,24 +256,32 @@ def adjoint(plan: OraclePlan, v: np.ndarray) -> np.ndarray:
     v = np.asarray(v, dtype=np.float64)
     vt = dft.forward(v, sign=+1)                  # transpose of the crop-inverse
     M = plan.M
+    unpadded = plan.laplacian == "unpadded"
+    # the periodic Laplacian on the density's grid is symmetric: its transpose is itself
+    lap_v = periodic_laplacian(plan, v) if unpadded else None
+    lap_t = 0.0 if unpadded else -laplacian_symbol(plan) * vt
     if plan.kernel == "davey_stewartson2d":
         # transpose of rho -> [I1 + A0 f + c2 Lap f](f = d_xx rho)
-        w1 = full_spectrum(plan) * vt - plan.c2 * laplacian_symbol(plan) * vt + plan.A0 * vt
-        return dft.inverse(ds_symbol(plan) * w1, sign=-1).real / M
+        w1 = full_spectrum(plan) * vt + plan.c2 * lap_t + plan.A0 * vt
+        out = dft.inverse(ds_symbol(plan) * w1, sign=-1).real / M
+        if unpadded:       # transpose of f -> c2 Lap f composed with rho -> f
+            out = out + plan.c2 * dft.inverse(ds_symbol(plan) * dft.forward(lap_v, sign=+1), sign=-1).real / M
+        return out
     if plan.kernel != "dipolar3d":
         G = full_spectrum(plan)
         out = dft.inverse(G * vt, sign=-1).real / M
         if plan.A0 != 0.0 or plan.c2 != 0.0:
-            lap = dft.inverse(-laplacian_symbol(plan) * vt, sign=-1).real / M
+            lap = lap_v if unpadded else dft.inverse(lap_t, sign=-1).real / M
             out = out + plan.A0 * v + plan.c2 * lap
         return out
     nm = float(np.dot(plan.dipole_n, plan.dipole_m))
     G = full_spectrum(plan)
     sym = dipolar_symbol(plan)
-    lap_sym = laplacian_symbol(plan)
     # transpose of rho -> -3 [I1 + A0 f + c2 Lap f](src(rho))
-    w1 = G * vt - plan.c2 * lap_sym * vt + plan.A0 * vt
+    w1 = G * vt + plan.c2 * lap_t + plan.A0 * vt
     out = dft.inverse(-sym * w1, sign=-1).real / M
+    if unpadded:
+        out = out + plan.c2 * dft.inverse(-sym * dft.forward(lap_v, sign=+1), sign=-1).real / M
     return -nm * v - 3.0 * out
 
 

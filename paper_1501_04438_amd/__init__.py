@@ -20,7 +20,7 @@ import math
 import numpy as np
 
 from ._lib import (KERNEL_DIM, KERNELS, PLAN_AUTOTUNE, PLAN_HOST_ASSEMBLY, PLAN_HOST_ONLY, PLAN_NO_WORKSPACE,
-                   SCHEDULES, GSBatchInfo,
+                   PLAN_UNPADDED_LAPLACIAN, SCHEDULES, GSBatchInfo,
                    GSBatchOptions, GSError, GSOptions, GSPlanInfo, check, lib)
 
 __all__ = ["Plan", "Batch", "SCHEDULES", "potential", "energy", "eval_batch", "GSError", "device_count", "supported_sizes",
@@ -57,13 +57,16 @@ class Plan:
               are bitwise the same for every variant)
     workspace: False creates the plan without an evaluation workspace of its own; it is
               then evaluated with eval_static only
+    laplacian: "padded" (default) or "unpadded": the grid on which the near-field Taylor term
+              takes the density's Laplacian (the padded grid of the convolution, or the
+              density's own grid, periodic; kernels whose Taylor term acts on rho only)
     """
 
     def __init__(self, kernel: str, n: int, L, eps: float = 1e-14, d: int | None = None,
                  delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
                  host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0,
                  slab_streams: int = 0, autotune: bool = False, beta: float | None = None,
-                 workspace: bool = True):
+                 workspace: bool = True, laplacian: str = "padded"):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         d = KERNEL_DIM.get(kernel, d)
@@ -79,7 +82,10 @@ class Plan:
         opt.delta_rel = float(delta_rel)
         opt.device = int(device)
         opt.flags = ((PLAN_HOST_ONLY if host_only else 0) | (PLAN_HOST_ASSEMBLY if host_assembly else 0)
-                     | (PLAN_AUTOTUNE if autotune else 0) | (0 if workspace else PLAN_NO_WORKSPACE))
+                     | (PLAN_AUTOTUNE if autotune else 0) | (0 if workspace else PLAN_NO_WORKSPACE)
+                     | (PLAN_UNPADDED_LAPLACIAN if laplacian == "unpadded" else 0))
+        if laplacian not in ("padded", "unpadded"):
+            raise ValueError("laplacian: padded or unpadded")
         opt.slab_planes = int(slab_planes)
         opt.slab_streams = int(slab_streams)
         if beta is not None:

@@ -19,6 +19,7 @@ PLAN_HOST_ONLY = 1
 PLAN_HOST_ASSEMBLY = 2
 PLAN_AUTOTUNE = 4
 PLAN_NO_WORKSPACE = 8
+PLAN_UNPADDED_LAPLACIAN = 16
 
 
 class GSOptions(C.Structure):

@@ -11,6 +11,10 @@
 // B formed in registers.  2D: S[k1][k3] with B[q][k3] = Fy[k3][q] (passed as FC).
 // dxx != 0 multiplies the result by -xi_k1^2, the symbol of d_xx (Davey-Stewartson
 // potential: the Poisson spectrum applied to the second x-derivative of rho).
+// lapu != 0 takes the Taylor term's Laplacian on the density's own grid (period 2L): on
+// the padded grid of 2n points its symbol is 2^d (-|xi|^2) at the indices whose every
+// component is even (those are the n-point grid's frequencies, with the same xi) and 0
+// elsewhere, since the padded transform at even indices is the n-point transform of rho.
 //
 // v_mfma_f64_16x16x4f64 operand layout (one wave, lane l = 0..63):
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
@@ -34,7 +38,7 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
                                                   int ldk, int n1, int n1b, int n1c, int Qp,
                                                   double* __restrict__ out,
                                                   double A0, double c2, double dx1, double dx2, double dx3,
-                                                  double invM, int dxx) {
+                                                  double invM, int dxx, int lapu) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long ncols = (DIM == 3) ? (long)n1b * n1c : (long)n1c;
     const long col0 = ((long)blockIdx.x * 4 + wave) * 16;
@@ -81,12 +85,15 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
     const long c = col0 + (lane & 15);
     if (c < ncols) {
         double xs;
+        bool even;            // k2 and k3 even (the unpadded-grid Laplacian lives there)
         if constexpr (DIM == 3) {
             const double x2 = (double)(c / n1c) * dx2, x3 = (double)(c % n1c) * dx3;
             xs = x2 * x2 + x3 * x3;
+            even = ((c / n1c) % 2 == 0) && ((c % n1c) % 2 == 0);
         } else {
             const double x3 = (double)c * dx3;
             xs = x3 * x3;
+            even = (c % 2 == 0);
         }
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
@@ -96,7 +103,10 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
                 if (k1 < n1) {
                     const double x1 = (double)k1 * dx1;
                     const double f = dxx ? -(x1 * x1) * invM : invM;
-                    out[(size_t)k1 * ncols + c] = (acc[mb][r] + A0 - c2 * (x1 * x1 + xs)) * f;
+                    // Laplacian weight: 1 on the padded grid; on the density's own grid
+                    // 2^d at all-even indices, 0 elsewhere
+                    const double lw = lapu ? ((even && (k1 % 2 == 0)) ? (DIM == 3 ? 8.0 : 4.0) : 0.0) : 1.0;
+                    out[(size_t)k1 * ncols + c] = (acc[mb][r] + A0 - c2 * lw * (x1 * x1 + xs)) * f;
                 }
             }
         }

@@ -69,6 +69,7 @@ struct AssemblyArgs {
     double A0 = 0, c2 = 0, invM = 0;
     double dxi[3] = {0, 0, 0};        // pi / (2 L) of the axes of k1, k2, k3 (2D: k1, -, k3)
     int dxx = 0;                      // multiply by -xi_k1^2 (the d_xx symbol)
+    int lapu = 0;                     // Laplacian on the density's own grid (see assembly.hpp)
 };
 // Row blocks per wave chosen for n1; returns the padded k length the operands need.
 int assembly_ldk(int n1);

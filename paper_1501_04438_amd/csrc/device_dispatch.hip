@@ -131,10 +131,10 @@ static hipError_t launch_mb(const AssemblyArgs& a, hipStream_t s) {
     dim3 grid((unsigned)((ncols + 63) / 64), chunks);
     if (a.d == 3)
         k_assemble<MB, 3><<<grid, 256, 0, s>>>(a.AT, a.FB, a.FC, a.ldk, a.n1, n1b, n1c, a.Qp, a.out, a.A0, a.c2,
-                                               a.dxi[0], a.dxi[1], a.dxi[2], a.invM, a.dxx);
+                                               a.dxi[0], a.dxi[1], a.dxi[2], a.invM, a.dxx, a.lapu);
     else
         k_assemble<MB, 2><<<grid, 256, 0, s>>>(a.AT, a.FC, a.FC, a.ldk, a.n1, n1b, n1c, a.Qp, a.out, a.A0, a.c2,
-                                               a.dxi[0], a.dxi[2], a.dxi[2], a.invM, a.dxx);
+                                               a.dxi[0], a.dxi[2], a.dxi[2], a.invM, a.dxx, a.lapu);
     return hipGetLastError();
 }
 

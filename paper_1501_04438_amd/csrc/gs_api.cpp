@@ -143,6 +143,7 @@ gs_status device_assembly(gs_plan_s* p) {
         for (int j = 0; j < p->d; ++j) M *= 2.0 * p->nk[j];
         a.invM = 1.0 / M;
         a.dxx = p->kernel == GS_DAVEY_STEWARTSON_2D ? 1 : 0;
+        a.lapu = (p->flags & GS_PLAN_UNPADDED_LAPLACIAN) ? 1 : 0;
         if ((e = gsk::load_assembly(a)) != hipSuccess) {
             st = hip_fail(e, "spectrum assembly kernel load");
             break;
@@ -415,6 +416,9 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     const int nn = *std::max_element(nc, nc + d);
     const bool host_only = (opt.flags & GS_PLAN_HOST_ONLY) != 0;
     const bool no_ws = (opt.flags & GS_PLAN_NO_WORKSPACE) != 0;
+    if ((opt.flags & GS_PLAN_UNPADDED_LAPLACIAN) && (k == GS_DIPOLAR_3D || k == GS_DAVEY_STEWARTSON_2D))
+        return fail(GS_ERR_INVALID_ARG, "the unpadded-grid Laplacian applies to kernels whose Taylor term acts on "
+                                        "rho itself (not the dipolar or Davey-Stewartson source)");
     if (no_ws && (opt.flags & GS_PLAN_AUTOTUNE))
         return fail(GS_ERR_INVALID_ARG, "GS_PLAN_AUTOTUNE times gs_eval, which needs the workspace "
                                         "GS_PLAN_NO_WORKSPACE leaves out");
@@ -532,7 +536,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
 
     if (host_only) {
         gsh::assemble_spectrum(d, p->nk, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D,
-                               p->spec_host);
+                               (opt.flags & GS_PLAN_UNPADDED_LAPLACIAN) != 0, p->spec_host);
         log(1, "host-only plan kernel=%d d=%d n=(%d, %d, %d) L=(%g, %g, %g) S=%d Q=%zu delta=%.3g A0=%.6g c2=%.6g",
             (int)k, d, p->nc[0], p->nc[1], p->nc[2], p->Lc[0], p->Lc[1], p->Lc[2], p->table.S, p->table.w.size(),
             p->table.delta, p->A0, p->c2);
@@ -586,7 +590,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         if (st == GS_OK) {
             if (opt.flags & GS_PLAN_HOST_ASSEMBLY) {
                 gsh::assemble_spectrum(d, p->nk, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D,
-                                       p->spec_host);
+                                       (opt.flags & GS_PLAN_UNPADDED_LAPLACIAN) != 0, p->spec_host);
                 if ((e = hipMemcpy(p->spec, p->spec_host.data(), p->spec_bytes, hipMemcpyHostToDevice)) != hipSuccess)
                     st = hip_fail(e, "hipMemcpy(spectrum)");
             } else {

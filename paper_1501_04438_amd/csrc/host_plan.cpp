@@ -524,7 +524,8 @@ void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2)
 // ------------------------------------------------------------------ host assembly
 
 void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, const std::vector<double>* Fk,
-                       double A0, double c2, bool dxx, std::vector<double>& S) {
+                       double A0, double c2, bool dxx, bool lapu, std::vector<double>& S) {
+    const double lwe = lapu ? (d == 3 ? 8.0 : 4.0) : 1.0, lwo = lapu ? 0.0 : 1.0;   // all-even / other
     const int na = nk[0] + 1, nb = nk[1] + 1, nc = nk[d - 1] + 1, Q = (int)t.w.size();
     const double dxa = PI / (2.0 * Lk[0]), dxb = PI / (2.0 * Lk[1]), dxc = PI / (2.0 * Lk[d - 1]);
     const std::vector<double>& Fa = Fk[0];
@@ -545,7 +546,8 @@ void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, c
                     double acc = 0.0;
                     for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q];
                     const double xb = b * dxb;
-                    S[(size_t)a * nb + b] = (acc + A0 - c2 * (xa * xa + xb * xb)) * fa;
+                    const double lw = (a % 2 == 0 && b % 2 == 0) ? lwe : lwo;
+                    S[(size_t)a * nb + b] = (acc + A0 - c2 * lw * (xa * xa + xb * xb)) * fa;
                 }
                 continue;
             }
@@ -555,7 +557,8 @@ void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, c
                     double acc = 0.0;
                     for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q] * Fc[(size_t)cc * Q + q];
                     const double xc = cc * dxc;
-                    S[((size_t)a * nb + b) * nc + cc] = (acc + A0 - c2 * (xa * xa + xb * xb + xc * xc)) * fa;
+                    const double lw = (a % 2 == 0 && b % 2 == 0 && cc % 2 == 0) ? lwe : lwo;
+                    S[((size_t)a * nb + b) * nc + cc] = (acc + A0 - c2 * lw * (xa * xa + xb * xb + xc * xc)) * fa;
                 }
             }
         }

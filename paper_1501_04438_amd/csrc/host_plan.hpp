@@ -40,9 +40,11 @@ void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2)
 
 // Host assembly of the stored octant prod_i (n_i + 1), 1/prod_i (2 n_i) folded in.  Octant
 // axes (kx, ky[, kz]): nk[i], Lk[i] and Fk[i] are the points, half-width and factors of axis
-// x, y[, z].  dxx: multiply by -xi_x^2, the symbol of d_xx (Davey-Stewartson).
+// x, y[, z].  dxx: multiply by -xi_x^2, the symbol of d_xx (Davey-Stewartson).  lapu: the
+// Taylor term's Laplacian on the density's own grid (weight 2^d at all-even indices, 0 at
+// the others) instead of the padded grid's (weight 1).
 void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, const std::vector<double>* Fk,
-                       double A0, double c2, bool dxx, std::vector<double>& S);
+                       double A0, double c2, bool dxx, bool lapu, std::vector<double>& S);
 
 // exp(-i pi m / n), m = 0..2n-1, as interleaved (re, im).
 void twiddles(int n, std::vector<double>& tw);

@@ -36,7 +36,7 @@ static int run(const char* name, int kernel, int d, int n, const double* Lk, dou
     taylor_constants(kernel, d, t, A0, c2);
     std::vector<double> S;
     const int nk[3] = {n, n, n};
-    assemble_spectrum(d, nk, Lk, t, Fk, A0, c2, kernel == DAVEY_STEWARTSON_2D, S);
+    assemble_spectrum(d, nk, Lk, t, Fk, A0, c2, kernel == DAVEY_STEWARTSON_2D, false, S);
     std::vector<double> tw;
     twiddles(n, tw);
     std::printf("%s S=%d Q=%zu A0=%.17g c2=%.17g spec0=%.17g specsum=%.17g tw=%zu\n", name, t.S, t.w.size(), A0, c2,

@@ -440,3 +440,21 @@ def test_inverse_power_gaussian_closed_form(beta):
     r = np.sqrt(sum(x * x for x in X))
     assert relmax(u, cf.power_gaussian(r, beta, s, 3)) <= 1e-13
     assert abs(u[n // 2, n // 2, n // 2] - cf.power_gaussian_origin(beta, s, 3)) <= 1e-13 * u.max()
+
+
+# --------------------------------------------------------------------------
+# The Taylor term's Laplacian on the density's own grid (plan option).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kernel,d,n,L", [("coulomb3d", 3, 24, 5.0), ("coulomb3d", 3, (16, 24, 12), (4.0, 6.0, 3.0)),
+                                          ("poisson2d", 2, 96, 7.0), ("coulomb2d", 2, 48, 4.0),
+                                          ("inverse_power", 3, 16, 4.0)])
+def test_unpadded_laplacian_against_oracle(kernel, d, n, L):
+    kw = {"eps": 1e-13} if kernel == "poisson2d" else ({"beta": 0.8} if kernel == "inverse_power" else {})
+    plan = gs.Plan(kernel, n=n, L=L, d=d, laplacian="unpadded", **kw)
+    host = gs.Plan(kernel, n=n, L=L, d=d, laplacian="unpadded", host_only=True, **kw).spectrum()
+    assert np.max(np.abs(plan.spectrum() - host)) <= 1e-14 * np.max(np.abs(host))
+    rng = np.random.default_rng(650 + d)
+    rho = rng.standard_normal(plan.shape)
+    ref = oracle.evaluate(oracle.make_plan(kernel, d, n, L, laplacian="unpadded", **kw), rho)
+    assert relmax(gpu_eval(plan, rho), ref) <= TOL

@@ -14,10 +14,16 @@ def _octant_ref(op):
     oracle's array-order G), with the Taylor terms and 1/M folded in."""
     d = op.d
     lap = 0.0
+    even = True
     for i in range(d):                          # octant axis i = array axis d-1-i
         m = op.ns[d - 1 - i]
         xi = oracle.padded_frequencies(m, op.Ls[d - 1 - i])[: m + 1]
         lap = lap + np.expand_dims(xi ** 2, tuple(j for j in range(d) if j != i))
+        even = even & np.expand_dims(np.arange(m + 1) % 2 == 0, tuple(j for j in range(d) if j != i))
+    if op.laplacian == "unpadded":
+        # the n-point grid's frequencies are the padded grid's all-even indices (same xi);
+        # its transform is the padded one there, and 1/M carries 2^d more points
+        lap = lap * np.where(even, 2.0 ** d, 0.0)
     G = op.G_oct.transpose(tuple(range(d - 1, -1, -1)))
     S = (G + op.A0 - op.c2 * lap) / op.M
     if op.kernel == "davey_stewartson2d":          # times -xi_x^2 along octant axis 0 (x)
@@ -155,3 +161,18 @@ def test_host_plan_per_axis_points(kernel, d, n, L, eps):
         assert np.all(S[0] == 0.0)
         S, ref = S[1:] / -xi2, ref[1:] / -xi2
     assert np.max(np.abs(S - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("kernel,d,n,L,eps", [("coulomb3d", 3, 16, 6.0, 1e-14), ("poisson2d", 2, (48, 32), (6.0, 4.0), 1e-13),
+                                              ("coulomb2d", 2, 64, 7.0, 1e-14)])
+def test_host_plan_unpadded_laplacian(kernel, d, n, L, eps):
+    """The Taylor term's Laplacian on the density's own grid, folded into the spectrum at the
+    all-even indices (the oracle takes that Laplacian with n-point transforms)."""
+    p = gs.Plan(kernel, n=n, L=L, eps=eps, host_only=True, laplacian="unpadded")
+    op = oracle.make_plan(kernel, d, n, L, eps=eps, laplacian="unpadded")
+    S, ref = p.spectrum(), _octant_ref(op)
+    assert np.max(np.abs(S - ref)) <= 1e-13 * np.max(np.abs(ref))
+    pp = gs.Plan(kernel, n=n, L=L, eps=eps, host_only=True)
+    assert not np.array_equal(S, pp.spectrum())
+    with pytest.raises(gs.GSError):
+        gs.Plan("dipolar3d", n=16, L=4.0, dipole=((1, 0, 0), (0, 1, 0)), host_only=True, laplacian="unpadded")

@@ -18,6 +18,7 @@ import workloads
 from oracle import closed_forms as cf
 from oracle import dft, gs_table
 from oracle.factors import factor_1d
+from oracle.evaluate import periodic_laplacian
 from oracle.taylor import taylor_constants
 
 
@@ -807,3 +808,48 @@ def test_per_axis_points_axis_permutation():
     np_, Lp = tuple(n[i] for i in perm), tuple(L[i] for i in perm)
     up = oracle.evaluate(oracle.make_plan("coulomb3d", 3, np_, Lp), np.transpose(rho, perm))
     assert relmax(np.transpose(u, perm), up) <= 1e-14
+
+
+# --------------------------------------------------------------------------
+# The Taylor term's Laplacian on the density's own grid (Algorithm 1 step 3 read as the
+# spectral Laplacian of the sampled density, period 2L), the fidelity variant of the
+# Laplacian on the padded grid.
+# --------------------------------------------------------------------------
+
+def test_periodic_laplacian_exact_on_trigonometric_polynomials():
+    """cos(pi k x / L) sin(pi m y / L) on the periodic n-point grid: Laplacian
+    -(pi/L)^2 (k^2 + m^2) times itself, exactly up to rounding, for |k|, |m| < n/2 (and the
+    Nyquist cosine k = n/2 with (pi/h)^2)."""
+    n, L = (24, 16), (3.0, 2.0)
+    plan = oracle.make_plan("coulomb2d", 2, n, L, laplacian="unpadded")
+    X = np.broadcast_arrays(*workloads.mesh(n, L, 2))
+    for kx, ky in [(1, 2), (5, 7), (7, 11), (8, 12)]:     # (8, 12): both Nyquist cosines
+        f = np.cos(math.pi * kx * X[0] / L[1]) * np.cos(math.pi * ky * X[1] / L[0])
+        want = -((math.pi * kx / L[1]) ** 2 + (math.pi * ky / L[0]) ** 2) * f
+        assert np.max(np.abs(periodic_laplacian(plan, f) - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("kernel,d,n,L", [("coulomb3d", 3, 24, 5.0), ("poisson2d", 2, (32, 48), (4.0, 6.0)),
+                                          ("dipolar3d", 3, 16, 4.0), ("davey_stewartson2d", 2, 24, 4.0)])
+def test_unpadded_laplacian_variant(kernel, d, n, L):
+    """The two readings differ only through c2 Lap rho: on a resolved Gaussian both match the
+    closed form as closely (the correction is ~1e-17 at delta = 1e-4 L); on rough input
+    they differ by exactly c2 (Lap_unpadded - Lap_padded) rho; the adjoint stays the
+    transpose (dot test)."""
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    eps = 1e-13 if kernel in ("poisson2d", "davey_stewartson2d") else 1e-14
+    pp = oracle.make_plan(kernel, d, n, L, eps=eps, **kw)
+    pu = oracle.make_plan(kernel, d, n, L, eps=eps, laplacian="unpadded", **kw)
+    rng = np.random.default_rng(31)
+    ns = pp.ns
+    x, v = rng.standard_normal(ns), rng.standard_normal(ns)
+    up, uu = oracle.evaluate(pp, x), oracle.evaluate(pu, x)
+    assert np.max(np.abs(uu - up)) > 0.0
+    if kernel in ("coulomb3d", "poisson2d"):
+        from oracle import dft
+        lap_p = dft.inverse(-oracle.laplacian_symbol(pp) * dft.forward(x)).real / pp.M
+        lap_u = periodic_laplacian(pu, x)
+        assert np.max(np.abs((uu - up) - pp.c2 * (lap_u - lap_p))) <= 1e-14 * np.max(np.abs(up))
+    lhs = float(np.sum(oracle.evaluate(pu, x) * v))
+    rhs = float(np.sum(x * oracle.adjoint(pu, v)))
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(uu) * np.linalg.norm(v)
