@@ -323,6 +323,7 @@ def main() -> int:
 
     out["copy_GB_s"] = round(copy_bandwidth(torch), 1)
     if not args.no_extras:
+        out["autotuned_plan"] = autotuned_figures(gs, torch, plan, rho, K)
         out["adjoint"] = adjoint_figures(gs, torch, workloads, plan, rho, K, ms_step)
         out["batched"] = batched_figures(gs, torch, workloads)
         out["other_workloads"] = other_figures(gs, torch, workloads)
@@ -330,6 +331,35 @@ def main() -> int:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def autotuned_figures(gs, torch, plan, rho, K):
+    """The plan autotuner on the headline grid (cache hints, fused-pass grid rounds and the
+    tile shapes of the passes): its choice, and its evaluation time next to the compiled
+    defaults' (both timed here with events on the current stream, same bits)."""
+    tuned = gs.Plan("coulomb3d", n=plan.n, L=plan.L, eps=1e-14, autotune=True)
+    info = tuned.query()
+    u = torch.empty_like(rho)
+
+    def timed(p):
+        for _ in range(3):
+            p.eval(rho, out=u)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(K):
+            p.eval(rho, out=u)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    ms_default, ms_tuned = timed(plan), timed(tuned)
+    res = {"hint_bits": info["hint_bits"], "fused_grid_mult": info["fused_grid_mult"],
+           "tile_variants": info["tile_variants"], "candidates_timed": info["tune_candidates"],
+           "ms_tuned": round(ms_tuned, 5), "ms_default": round(ms_default, 5),
+           "bitwise_equal": bool(torch.equal(tuned.eval(rho), plan.eval(rho)))}
+    tuned.close()
+    return res
 
 
 def other_workloads_bytes(d: int, n: int) -> int:
@@ -372,7 +402,8 @@ def other_figures(gs, torch, workloads, reps: int = 20):
         pts = p.n ** p.d
         b = other_workloads_bytes(p.d, p.n)
         res[name] = {"ms": round(ms, 4), "Mpts_s": round(pts / ms / 1e3, 1), "alg_GB_s": round(b / ms / 1e6, 1),
-                     "hint_bits": plan.info["hint_bits"], "fused_grid_mult": plan.info["fused_grid_mult"]}
+                     "hint_bits": plan.info["hint_bits"], "fused_grid_mult": plan.info["fused_grid_mult"],
+                     "tile_variants": plan.info["tile_variants"]}
         plan.close()
     return res
 

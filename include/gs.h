@@ -78,7 +78,8 @@ typedef enum {
 #define GS_PLAN_HOST_ASSEMBLY  2  /* assemble the spectrum on the host and upload it
                                      instead of the MFMA assembly kernel */
 #define GS_PLAN_AUTOTUNE       4  /* pick the launch variants of the evaluation (cache
-                                     hints per pass, persistent grid of the fused pass)
+                                     hints per pass, persistent grid of the fused pass,
+                                     tile shapes of the cubic passes)
                                      by timing whole evaluations at plan creation, or
                                      take them from the autotune cache (see
                                      GS_SCHED_AUTO); results are bitwise the same for
@@ -120,6 +121,14 @@ typedef struct {
                                 its own planes; the results are the same bits);
                                 0 or 1 = in order on the plan's stream           */
     double beta;             /* GS_INVERSE_POWER: the exponent, 0 < beta < d      */
+    int tile_variants;       /* tile shapes of the cubic passes (bits 0-1: x passes, 1 =
+                                twice the row pairs per block; bits 2-3: y passes, 1 =
+                                half, 2 = twice the z-pencils per block; bits 4-5: fused
+                                pass, 1 = half, 2 = twice the pencils per block); 0 = the
+                                compiled defaults.  Compiled for n >= 128 where the LDS
+                                allows, ignored elsewhere and on grids whose axes differ;
+                                every value gives the same bits.  GS_PLAN_AUTOTUNE picks
+                                them by timing                                   */
 } gs_options;
 
 typedef struct {
@@ -149,6 +158,7 @@ typedef struct {
     int64_t n_axes[3];       /* points per axis, C order (first d entries); n above is
                                 their common value, or their largest on a grid whose
                                 axes differ                                      */
+    int tile_variants;       /* tile shapes in use (gs_options.tile_variants bits)  */
 } gs_plan_info;
 
 /* Fill `opt` with the defaults (delta_rel 1e-4, null stream, device -1). */

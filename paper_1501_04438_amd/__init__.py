@@ -52,9 +52,10 @@ class Plan:
             (Ly, Lx)) for a rectangular box or grid (Section 2.5)
     eps:    Gaussian-sum accuracy; delta_rel: near-field radius / max L (below min L / max L)
     dipole: (n_vec, m_vec) for "dipolar3d"; custom: (w, tau) for "gaussian_sum"
-    autotune: time the launch variants (cache hints per pass, fused-pass grid) at plan
-              creation and keep the fastest (cached per device and size; the results
+    autotune: time the launch variants (cache hints per pass, fused-pass grid, tile shapes)
+              at plan creation and keep the fastest (cached per device and size; the results
               are bitwise the same for every variant)
+    tile_variants: tile shapes of the cubic passes (gs_options.tile_variants bits; 0 = defaults)
     workspace: False creates the plan without an evaluation workspace of its own; it is
               then evaluated with eval_static only
     laplacian: "padded" (default) or "unpadded": the grid on which the near-field Taylor term
@@ -66,7 +67,7 @@ class Plan:
                  delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
                  host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0,
                  slab_streams: int = 0, autotune: bool = False, beta: float | None = None,
-                 workspace: bool = True, laplacian: str = "padded"):
+                 workspace: bool = True, laplacian: str = "padded", tile_variants: int = 0):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         d = KERNEL_DIM.get(kernel, d)
@@ -87,6 +88,7 @@ class Plan:
         if laplacian not in ("padded", "unpadded"):
             raise ValueError("laplacian: padded or unpadded")
         opt.slab_planes = int(slab_planes)
+        opt.tile_variants = int(tile_variants)
         opt.slab_streams = int(slab_streams)
         if beta is not None:
             opt.beta = float(beta)

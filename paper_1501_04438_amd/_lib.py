@@ -26,7 +26,7 @@ class GSOptions(C.Structure):
     _fields_ = [("delta_rel", C.c_double), ("dipole_n", C.c_double * 3), ("dipole_m", C.c_double * 3),
                 ("gs_w", C.POINTER(C.c_double)), ("gs_tau", C.POINTER(C.c_double)), ("gs_q", C.c_int),
                 ("stream", C.c_void_p), ("device", C.c_int), ("flags", C.c_int), ("slab_planes", C.c_int),
-                ("slab_streams", C.c_int), ("beta", C.c_double)]
+                ("slab_streams", C.c_int), ("beta", C.c_double), ("tile_variants", C.c_int)]
 
 
 class GSPlanInfo(C.Structure):
@@ -36,7 +36,7 @@ class GSPlanInfo(C.Structure):
                 ("assembly_gflop", C.c_double), ("host_only", C.c_int), ("slab_planes", C.c_int),
                 ("num_steps", C.c_int), ("slab_streams", C.c_int), ("x2_planes", C.c_int), ("tuned", C.c_int), ("hint_bits", C.c_int), ("fused_grid_mult", C.c_int),
                 ("tune_candidates", C.c_int), ("tuned_ms", C.c_double), ("L_axes", C.c_double * 3),
-                ("beta", C.c_double), ("n_axes", C.c_int64 * 3)]
+                ("beta", C.c_double), ("n_axes", C.c_int64 * 3), ("tile_variants", C.c_int)]
 
 
 SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3, "sized": 4}

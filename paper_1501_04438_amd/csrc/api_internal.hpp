@@ -38,6 +38,7 @@ struct gs_plan_s {
     double assembly_ms = 0.0;
     int slab = 0, nslabs = 1;                 // 3D: kx planes per slab of the middle passes
     int hint_bits = 27, fused_mult = 4;       // launch variants (see gsk::EvalArgs)
+    int tile_bits = 0;                        // tile shapes of the cubic passes (gsk::EvalArgs)
     int x2_planes = 0;                        // kx planes X2 holds (n+1: every slab at its own planes)
     int nstreams = 1;                         // concurrent slab chains of the middle passes
     std::vector<hipStream_t> sstreams;        // their streams (created on demand)

@@ -32,6 +32,9 @@ struct EvalArgs {
     // fused pass runs one block per pencil group).
     int hint_bits = 27;
     int fused_grid_mult = 4;
+    // Tile shapes of the cubic passes (bits 0-1 x passes, 2-3 y passes, 4-5 fused pass; 0 =
+    // compiled defaults; see eval_instance.hip); the same bits for every value.
+    int tile_bits = 0;
     // Energy (pass 5 only, when energy != nullptr): E = escale * sum_i rho_i u_i, per-block
     // partial sums in epart (energy_blocks(d, n) doubles), their fixed-order total in *energy.
     double* energy = nullptr;
@@ -56,6 +59,9 @@ hipError_t launch_energy_finish(const double* part, int count, double scale, dou
 // whose extents nx, ny (, nz) differ runs each pass at the length of the axis it transforms.
 hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which = -1);
 bool eval_size_supported(int d, int n);
+// Tile variants compiled for length n: bit 0 x double, 1 y half, 2 y double, 3 fused half,
+// 4 fused double.
+int tile_variants(int n);
 int eval_sizes(int d, long long* out, int cap);
 
 // Octant indices (k1, k2, k3) = (kx, ky, kz) in 3D and (k1, k3) = (kx, ky) in 2D.

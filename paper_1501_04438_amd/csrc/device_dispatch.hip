@@ -10,7 +10,8 @@ namespace gsk {
     hipError_t launch_eval_##N(const EvalArgs&, hipStream_t, int);   \
     hipError_t launch_eval_g_##N(const EvalArgs&, hipStream_t, int); \
     int energy_blocks_##N(int);                                      \
-    int energy_blocks_g_##N(int, int);
+    int energy_blocks_g_##N(int, int);                               \
+    int tile_variants_##N();
 GS_SIZE_LIST(GS_DECL)
 #undef GS_DECL
 
@@ -84,6 +85,16 @@ hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which) {
         GS_SIZE_LIST(GS_CASE)
 #undef GS_CASE
         default: return hipErrorInvalidValue;
+    }
+}
+
+int tile_variants(int n) {
+    switch (n) {
+#define GS_CASE(N) \
+    case N: return tile_variants_##N();
+        GS_SIZE_LIST(GS_CASE)
+#undef GS_CASE
+        default: return 0;
     }
 }
 

@@ -29,23 +29,154 @@ static int resident_blocks(const void* fn, int threads) {
     return cus * (per > 0 ? per : 1);
 }
 
-// P5, with the energy sum when the arguments ask for it.
-static hipError_t launch_x_inverse(const EvalArgs& a, hipStream_t s, dim3 gx) {
+// Tile-shape variants of the cubic passes (bits of EvalArgs::tile_bits; none changes a bit
+// of the result): x passes 2 bits (0: the default row pairs per block, 1: twice as many), y
+// passes 2 bits (0: default z-pencils per block, 1: half, 2: twice), fused pass 2 bits (0:
+// default pencils per block, 1: half, 2: twice).  Compiled for the lengths gs_tile_variants
+// names, where LDS allows; elsewhere every value selects the default.
+constexpr int LDS_LIMIT = 160 * 1024;
+template <int N> constexpr int px_of(int v) {
+    constexpr int P = Geo<N>::PPX;
+    // (whole tiles only: a tile that does not divide the grid would pair rows differently)
+    return (gs_tile_variants(N) && v == 1 && 2 * P * Geo<N>::A * 16 <= LDS_LIMIT && N % (4 * P) == 0) ? 2 * P : P;
+}
+template <int N> constexpr int py_of(int v) {
+    constexpr int P = Geo<N>::PPY;
+    if (!gs_tile_variants(N)) return P;
+    if (v == 1 && P >= 2) return P / 2;
+    if (v == 2 && 2 * P * Geo<N>::A * 16 <= LDS_LIMIT && 2 * P * Geo<N>::G <= 1024) return 2 * P;
+    return P;
+}
+template <int N> constexpr int pz_of(int v) {
+    constexpr int P = Geo<N>::PPZ;
+    if (!gs_tile_variants(N)) return P;
+    if (v == 1 && P >= 2) return P / 2;
+    if (v == 2 && 4 * P * Geo<N>::AZ * 16 <= LDS_LIMIT && 4 * P * Geo<N>::GZ <= 1024) return 2 * P;
+    return P;
+}
+
+// P5 with row pairs PX per block, with the energy sum when the arguments ask for it.
+template <int PX>
+static hipError_t launch_x_inverse_v(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
-    using Gm = Geo<N>;
+    constexpr int T = PX * Geo<N>::G;
     const cpx* const X1 = reinterpret_cast<const cpx*>(a.X1);
     const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
     const bool hint = (a.hint_bits >> 4) & 1;
+    const dim3 gx((N + 2 * PX - 1) / (2 * PX), a.d == 3 ? N : 1);
     if (a.energy) {
-        if (hint) k_x_c2r_energy<N, NT_P5><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart);
-        else k_x_c2r_energy<N, 0><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart);
+        if (hint) k_x_c2r_energy<N, NT_P5, PX><<<gx, T, 0, s>>>(X1, a.u, tw, a.rho, a.epart);
+        else k_x_c2r_energy<N, 0, PX><<<gx, T, 0, s>>>(X1, a.u, tw, a.rho, a.epart);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_energy_finish(a.epart, (int)(gx.x * gx.y), a.escale, a.energy, s);
+        return launch_energy_finish(a.epart, (int)(gx.x * gx.y) * (PX / Geo<N>::PPX), a.escale, a.energy, s);
     }
-    if (hint) k_x_c2r<N, NT_P5><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
-    else k_x_c2r<N, 0><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw);
+    if (hint) k_x_c2r<N, NT_P5, PX><<<gx, T, 0, s>>>(X1, a.u, tw);
+    else k_x_c2r<N, 0, PX><<<gx, T, 0, s>>>(X1, a.u, tw);
     return hipGetLastError();
+}
+
+static hipError_t launch_x_inverse(const EvalArgs& a, hipStream_t s) {
+    constexpr int N = GS_N;
+    if ((a.tile_bits & 3) == 1 && px_of<N>(1) != px_of<N>(0)) return launch_x_inverse_v<px_of<N>(1)>(a, s);
+    return launch_x_inverse_v<px_of<N>(0)>(a, s);
+}
+
+template <int PX>
+static hipError_t launch_x_forward_v(const EvalArgs& a, hipStream_t s) {
+    constexpr int N = GS_N;
+    const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
+    cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
+    const dim3 gx((N + 2 * PX - 1) / (2 * PX), a.d == 3 ? N : 1);
+    if ((a.hint_bits >> 0) & 1) k_x_r2c<N, NT_P1, PX><<<gx, PX * Geo<N>::G, 0, s>>>(a.rho, X1, tw);
+    else k_x_r2c<N, 0, PX><<<gx, PX * Geo<N>::G, 0, s>>>(a.rho, X1, tw);
+    return hipGetLastError();
+}
+
+static hipError_t launch_x_forward(const EvalArgs& a, hipStream_t s) {
+    constexpr int N = GS_N;
+    if ((a.tile_bits & 3) == 1 && px_of<N>(1) != px_of<N>(0)) return launch_x_forward_v<px_of<N>(1)>(a, s);
+    return launch_x_forward_v<px_of<N>(0)>(a, s);
+}
+
+// y passes (3D) with PY z-pencils per block: 2 forward, 4 inverse.
+template <int PY>
+static hipError_t launch_y_v(const EvalArgs& a, hipStream_t s, int pass) {
+    constexpr int N = GS_N;
+    cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
+    cpx* const X2 = reinterpret_cast<cpx*>(a.X2);
+    const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
+    const dim3 gy((N + PY - 1) / PY, a.kxn);
+    constexpr int T = PY * Geo<N>::G;
+    const bool hint = (a.hint_bits >> (pass - 1)) & 1;
+    if (pass == 2) {
+        if (hint) k_y_fwd<N, NT_P2, PY><<<gy, T, 0, s>>>(X1, X2, tw, a.kx0);
+        else k_y_fwd<N, 0, PY><<<gy, T, 0, s>>>(X1, X2, tw, a.kx0);
+    } else {
+        if (hint) k_y_inv<N, NT_P4, PY><<<gy, T, 0, s>>>(X2, X1, tw, a.kx0);
+        else k_y_inv<N, 0, PY><<<gy, T, 0, s>>>(X2, X1, tw, a.kx0);
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_y(const EvalArgs& a, hipStream_t s, int pass) {
+    static_assert(N <= GS_MAX_N_3D, "the y passes run in 3D only");
+    const int v = (a.tile_bits >> 2) & 3;
+    if (v == 1 && py_of<N>(1) != py_of<N>(0)) return launch_y_v<py_of<N>(1)>(a, s, pass);
+    if (v == 2 && py_of<N>(2) != py_of<N>(0)) return launch_y_v<py_of<N>(2)>(a, s, pass);
+    return launch_y_v<py_of<N>(0)>(a, s, pass);
+}
+
+// Fused pass with PZ pencils per block (3D: persistent rounds at n = 256; 2D: one block per
+// pencil group).
+template <int PZ>
+static hipError_t launch_fused_v(const EvalArgs& a, hipStream_t s, const DipoleArgs& dip) {
+    constexpr int N = GS_N;
+    constexpr int T = PZ * 2 * Geo<N>::GZ;
+    const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
+    const bool hint = (a.hint_bits >> 2) & 1;
+    if constexpr (N <= GS_MAX_N_3D) {
+      if (a.d == 3) {
+        cpx* const X2 = reinterpret_cast<cpx*>(a.X2);
+        static const int cap3 = resident_blocks((const void*)k_fused<N, 3, SPEC_PLAIN, 0, PZ>, T);
+        const int capf = a.max_blocks_fused > 0 ? a.max_blocks_fused : cap3;
+        const int np = a.kxn * 2 * N;
+        const int groups = (np + PZ - 1) / PZ;
+        const unsigned nb = gs_fused_persistent(3, N) ? fused_grid(groups, capf, a.fused_grid_mult) : (unsigned)groups;
+        if (a.dipolar) {
+            if (hint) k_fused<N, 3, SPEC_DIPOLAR, NT_P3, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+            else k_fused<N, 3, SPEC_DIPOLAR, 0, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+        } else {
+            if (hint) k_fused<N, 3, SPEC_PLAIN, NT_P3, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+            else k_fused<N, 3, SPEC_PLAIN, 0, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+        }
+        return hipGetLastError();
+      }
+    }
+    static_assert(!gs_fused_persistent(2, N), "the 2D fused pass runs one block per pencil group");
+    cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
+    const int np = N + 1;
+    const unsigned nb = (unsigned)((np + PZ - 1) / PZ);
+    if (hint) k_fused<N, 2, SPEC_PLAIN, NT_P3, PZ><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip);
+    else k_fused<N, 2, SPEC_PLAIN, 0, PZ><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip);
+    return hipGetLastError();
+}
+
+static hipError_t launch_fused(const EvalArgs& a, hipStream_t s, const DipoleArgs& dip) {
+    constexpr int N = GS_N;
+    const int v = (a.tile_bits >> 4) & 3;
+    if (v == 1 && pz_of<N>(1) != pz_of<N>(0)) return launch_fused_v<pz_of<N>(1)>(a, s, dip);
+    if (v == 2 && pz_of<N>(2) != pz_of<N>(0)) return launch_fused_v<pz_of<N>(2)>(a, s, dip);
+    return launch_fused_v<pz_of<N>(0)>(a, s, dip);
+}
+
+int GS_CAT(tile_variants_, GS_N)() {
+    // bit 0: an x variant exists; bits 1, 2: y half / double; bits 3, 4: fused half / double
+    constexpr int N = GS_N;
+    return (px_of<N>(1) != px_of<N>(0) ? 1 : 0) | (py_of<N>(1) != py_of<N>(0) ? 2 : 0) |
+           (py_of<N>(2) != py_of<N>(0) ? 4 : 0) | (pz_of<N>(1) != pz_of<N>(0) ? 8 : 0) |
+           (pz_of<N>(2) != pz_of<N>(0) ? 16 : 0);
 }
 
 int GS_CAT(energy_blocks_, GS_N)(int d) {
@@ -136,7 +267,6 @@ hipError_t GS_CAT(launch_eval_g_, GS_N)(const EvalArgs& a, hipStream_t s, int pa
 
 hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int which) {
     constexpr int N = GS_N;
-    using Gm = Geo<N>;
     DipoleArgs dip;
     for (int i = 0; i < 3; ++i) dip.dxi[i] = a.dxi[i];
     for (int i = 0; i < 3; ++i) {
@@ -144,56 +274,22 @@ hipError_t GS_CAT(launch_eval_, GS_N)(const EvalArgs& a, hipStream_t s, int whic
         dip.ccross[i] = a.ccross[i];
     }
     dip.nm_over_M = a.nm_over_M;
-    const int nz = (a.d == 3) ? N : 1;
-    cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
-    cpx* const X2 = reinterpret_cast<cpx*>(a.X2);
-    const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
-    static const int cap3 = resident_blocks((const void*)k_fused<N, 3, SPEC_PLAIN>, Gm::TZ);
-    const int capf = a.max_blocks_fused > 0 ? a.max_blocks_fused : cap3;
-    const dim3 gx((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX), nz);
     auto run = [&](int p) { return which < 0 || which == p; };
-    auto hint = [&](int p) { return (a.hint_bits >> (p - 1)) & 1; };
-    const int fm = a.fused_grid_mult;
-    if (run(1)) {
-        if (hint(1)) k_x_r2c<N, NT_P1><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw);
-        else k_x_r2c<N, 0><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw);
-    }
-    if constexpr (N <= GS_MAX_N_3D) {
-      if (a.d == 3) {
-        const dim3 gy((N + Gm::PPY - 1) / Gm::PPY, a.kxn);
-        const int np = a.kxn * 2 * N;
-        if (run(2)) {
-            if (hint(2)) k_y_fwd<N, NT_P2><<<gy, Gm::TY, 0, s>>>(X1, X2, tw, a.kx0);
-            else k_y_fwd<N, 0><<<gy, Gm::TY, 0, s>>>(X1, X2, tw, a.kx0);
+    hipError_t e = hipSuccess;
+    if (run(1) && (e = launch_x_forward(a, s)) != hipSuccess) return e;
+    if (a.d == 3) {
+        if constexpr (N <= GS_MAX_N_3D) {
+            if (run(2) && (e = launch_y<N>(a, s, 2)) != hipSuccess) return e;
+            if (run(3) && (e = launch_fused(a, s, dip)) != hipSuccess) return e;
+            if (run(4) && (e = launch_y<N>(a, s, 4)) != hipSuccess) return e;
+        } else {
+            return hipErrorInvalidValue;
         }
-        if (run(3)) {
-            const int groups = (np + Gm::PPZ - 1) / Gm::PPZ;
-            const unsigned nb = gs_fused_persistent(3, N) ? fused_grid(groups, capf, fm) : (unsigned)groups;
-            if (a.dipolar) {
-                if (hint(3)) k_fused<N, 3, SPEC_DIPOLAR, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
-                else k_fused<N, 3, SPEC_DIPOLAR, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
-            } else {
-                if (hint(3)) k_fused<N, 3, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
-                else k_fused<N, 3, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
-            }
-        }
-        if (run(4)) {
-            if (hint(4)) k_y_inv<N, NT_P4><<<gy, Gm::TY, 0, s>>>(X2, X1, tw, a.kx0);
-            else k_y_inv<N, 0><<<gy, Gm::TY, 0, s>>>(X2, X1, tw, a.kx0);
-        }
-        if (run(5)) return launch_x_inverse(a, s, gx);
-        return hipGetLastError();
-      }
+    } else if (run(3) && (e = launch_fused(a, s, dip)) != hipSuccess) {
+        return e;
     }
-    if (run(3)) {
-        static_assert(!gs_fused_persistent(2, N), "the 2D fused pass runs one block per pencil group");
-        const int np = N + 1;
-        const unsigned nb = (unsigned)((np + Gm::PPZ - 1) / Gm::PPZ);
-        if (hint(3)) k_fused<N, 2, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
-        else k_fused<N, 2, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, tw, np, 0, dip);
-    }
-    if (run(5)) return launch_x_inverse(a, s, gx);
-    return hipGetLastError();
+    if (run(5)) return launch_x_inverse(a, s);
+    return hipSuccess;
 }
 
 }  // namespace gsk

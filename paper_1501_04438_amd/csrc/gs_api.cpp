@@ -213,6 +213,7 @@ gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) 
     for (int i = 0; i < 3; ++i) a.dxi[i] = p->Lk[i] > 0.0 ? M_PI / (2.0 * p->Lk[i]) : 0.0;
     a.hint_bits = p->hint_bits;
     a.fused_grid_mult = p->fused_mult;
+    a.tile_bits = p->cube ? p->tile_bits : 0;
     if (p->kernel == GS_DIPOLAR_3D) {
         a.dipolar = 1;
         for (int i = 0; i < 3; ++i) a.cdiag[i] = 3.0 * p->dn[i] * p->dm[i];
@@ -472,6 +473,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->delta_rel = opt.delta_rel;
     p->flags = opt.flags;
     p->host_only = host_only;
+    p->tile_bits = opt.tile_variants & 63;
     p->stream = (hipStream_t)opt.stream;
     for (int i = 0; i < 3; ++i) {
         p->dn[i] = opt.dipole_n[i];
@@ -666,6 +668,7 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
     info->tuned = p->tuned ? 1 : 0;
     info->hint_bits = p->hint_bits;
     info->fused_grid_mult = p->fused_mult;
+    info->tile_variants = p->tile_bits;
     info->tune_candidates = p->tune_candidates;
     info->tuned_ms = p->tuned_ms;
     return GS_OK;
@@ -810,6 +813,7 @@ gs_status plan_autotune(gs_plan_s* p) {
     if (tune_lookup(key, te)) {
         p->hint_bits = te.schedule;
         p->fused_mult = te.tiles_per_task;
+        p->tile_bits = te.grid;
         p->tuned = true;
         p->tuned_ms = te.ms;
         return GS_OK;
@@ -848,18 +852,33 @@ gs_status plan_autotune(gs_plan_s* p) {
         if (st == GS_OK && ms < best) best = ms;
         else p->fused_mult = keep;
     }
+    // tile shapes of the cubic passes: each pass type's variants in turn (x: twice the row
+    // pairs; y and fused: half and twice the pencils per block), keeping what is faster
+    const int tv = p->cube ? gsk::tile_variants(p->n) : 0;
+    const int tries[5][2] = {{0, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}};   // (bit offset, value)
+    const int avail[5] = {1, 2, 4, 8, 16};
+    for (int i = 0; i < 5 && st == GS_OK; ++i) {
+        if (!(tv & avail[i]) || (p->d == 2 && tries[i][0] == 2)) continue;
+        const int keep = p->tile_bits;
+        p->tile_bits = (p->tile_bits & ~(3 << tries[i][0])) | (tries[i][1] << tries[i][0]);
+        double ms = 0;
+        st = time_plan(p, rho, u, ms);
+        p->tune_candidates++;
+        if (st == GS_OK && ms < best) best = ms;
+        else p->tile_bits = keep;
+    }
     (void)hipStreamSynchronize(p->stream);
     (void)hipFree(rho);
     (void)hipFree(u);
     if (st != GS_OK) return st;
     p->tuned = true;
     p->tuned_ms = best;
-    log(1, "plan autotune n=%d d=%d: hint bits %d, fused rounds %d, %.4f ms (%d variants timed)", p->n, p->d,
-        p->hint_bits, p->fused_mult, best, p->tune_candidates);
+    log(1, "plan autotune n=%d d=%d: hint bits %d, fused rounds %d, tile bits %d, %.4f ms (%d variants timed)",
+        p->n, p->d, p->hint_bits, p->fused_mult, p->tile_bits, best, p->tune_candidates);
     te.schedule = p->hint_bits;          // plan entries: schedule = hint bits,
-    te.tiles_per_task = p->fused_mult;   // tiles_per_task = fused grid rounds
+    te.tiles_per_task = p->fused_mult;   // tiles_per_task = fused grid rounds,
     te.largest_first = 0;
-    te.grid = 0;
+    te.grid = p->tile_bits;              // grid = tile-shape bits
     te.ms = best;
     tune_store(key, te);
     return GS_OK;

@@ -91,12 +91,14 @@ struct Ext {
 // Two real rows a, b form c = a + i b; its padded transform C is split into the
 // Hermitian spectra A = (C[m] + conj C[2n-m])/2, B = (C[m] - conj C[2n-m])/(2i).
 // ---------------------------------------------------------------------------
-template <int N, int NT = NT_P1, bool CUBE = true>
+// PX: row pairs per block (a tile-shape variant; the pairing of rows is the same for every PX,
+// so every variant computes the same bits)
+template <int N, int NT = NT_P1, bool CUBE = true, int PX = Geo<N>::PPX>
 __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp<cpx> __restrict__ X1,
                                            gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
                                            cpx* lds, Ext ext = Ext()) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPX, A = Gm::A;
+    constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
     const int NY = CUBE ? N : ext.ny;          // rows (y) of a plane
     const int tA = tid % G, pA = tid / G;      // load role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive y
@@ -104,12 +106,15 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
     // rows beyond n exist only when 2 PPX does not divide n
     constexpr bool FULL = CUBE && (N % (2 * PP) == 0);
     const bool okA = active && (FULL || (y0 + 2 * pA) < NY), okB = active && (FULL || (y0 + 2 * pB) < NY);
-    // the two real rows of pair p: y0 + p and y0 + PP + p when the tile divides the grid and
-    // holds 8 pairs (each 16-byte store instruction on the transposed X1 side then fills whole
-    // 128-byte lines: P1 at 256^3 0.0765 -> 0.0706 ms), else y0 + 2p and y0 + 2p + 1
-    constexpr bool SPLIT = FULL && PP >= 8;
-    constexpr int RS = SPLIT ? PP : 1;
-    const int rowA = SPLIT ? y0 + pA : y0 + 2 * pA, rowB = SPLIT ? y0 + pB : y0 + 2 * pB;
+    // the two real rows of pair p: y0 + 16 (p / 8) + p % 8 and 8 rows further when the tile
+    // divides the grid and holds a multiple of 8 pairs (each 16-byte store instruction on the
+    // transposed X1 side then fills whole 128-byte lines: P1 at 256^3 0.0765 -> 0.0706 ms),
+    // else y0 + 2p and y0 + 2p + 1
+    // (the pairing follows the default tile, Geo<N>::PPX pairs, for every PX: the same bits)
+    constexpr bool SPLIT = FULL && Gm::PPX % 8 == 0 && PP % 8 == 0;
+    constexpr int RS = SPLIT ? 8 : 1;
+    const int rowA = SPLIT ? y0 + 16 * (pA / 8) + pA % 8 : y0 + 2 * pA;
+    const int rowB = SPLIT ? y0 + 16 * (pB / 8) + pB % 8 : y0 + 2 * pB;
 
     cpx x[E];
     {
@@ -157,13 +162,13 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
 // At n = 2048 the compiler's own allocation takes 256 VGPRs + 42 accumulator registers (one wave
 // per SIMD); capped at two waves per SIMD it spills 172 bytes per lane and still runs faster
 // (measured 0.038 -> 0.033 ms for 2D 2048^2; the same cap slows the x-inverse and n = 1024).
-template <int N, int NT = NT_P1>
-__global__ void __launch_bounds__(Geo<N>::TX) __attribute__((amdgpu_waves_per_eu(N == 2048 ? 2 : 1)))
+template <int N, int NT = NT_P1, int PX = Geo<N>::PPX>
+__global__ void __launch_bounds__(PX * Geo<N>::G) __attribute__((amdgpu_waves_per_eu(N == 2048 ? 2 : 1)))
 k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
                                                       const cpx* __restrict__ tw) {
-    __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
-    x_r2c_tile<N, NT>((gp<const double>)rho, (gp<cpx>)X1, (gp<const cpx>)tw, blockIdx.x, blockIdx.y, threadIdx.x, true,
-                  lds);
+    __shared__ cpx lds[PX * Geo<N>::A];
+    x_r2c_tile<N, NT, true, PX>((gp<const double>)rho, (gp<cpx>)X1, (gp<const cpx>)tw, blockIdx.x, blockIdx.y,
+                                threadIdx.x, true, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,12 +176,12 @@ k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
 // ---------------------------------------------------------------------------
 // EN: also returns this thread's part of sum_i rho_i u_i over the outputs it stores (rho
 // read at those outputs before they are written, so u may alias rho), in a fixed order.
-template <int N, int NT = NT_P5, bool EN = false, bool CUBE = true>
+template <int N, int NT = NT_P5, bool EN = false, bool CUBE = true, int PX = Geo<N>::PPX>
 __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> u,
                                              gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
                                              cpx* lds, gp<const double> erho = nullptr, Ext ext = Ext()) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPX, A = Gm::A;
+    constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
     const int NY = CUBE ? N : ext.ny;          // rows (y) of a plane
     const int tA = tid % G, pA = tid / G;      // store role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive y
@@ -184,11 +189,13 @@ __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<d
     // rows beyond n exist only when 2 PPX does not divide n
     constexpr bool FULL = CUBE && (N % (2 * PP) == 0);
     const bool okA = active && (FULL || (y0 + 2 * pA) < NY), okB = active && (FULL || (y0 + 2 * pB) < NY);
-    // rows of pair p as in x_r2c_tile (y0 + p and y0 + PP + p when the tile divides the grid and
-    // holds 8 pairs: whole 128-byte lines per load instruction on the transposed X1 side)
-    constexpr bool SPLIT = FULL && PP >= 8;
-    constexpr int RS = SPLIT ? PP : 1;
-    const int rowA = SPLIT ? y0 + pA : y0 + 2 * pA, rowB = SPLIT ? y0 + pB : y0 + 2 * pB;
+    // rows of pair p as in x_r2c_tile (8 rows apart in groups of 16 when the tile divides the
+    // grid and holds a multiple of 8 pairs: whole 128-byte lines per load instruction on the
+    // transposed X1 side)
+    constexpr bool SPLIT = FULL && Gm::PPX % 8 == 0 && PP % 8 == 0;
+    constexpr int RS = SPLIT ? 8 : 1;
+    const int rowA = SPLIT ? y0 + 16 * (pA / 8) + pA % 8 : y0 + 2 * pA;
+    const int rowB = SPLIT ? y0 + 16 * (pB / 8) + pB % 8 : y0 + 2 * pB;
     gp<const cpx> in = X1 + (size_t)z * (N + 1) * NY + rowB;
 
     cpx acc[E];
@@ -264,37 +271,57 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return v;
 }
 
-template <int N, int NT = NT_P5>
-__global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
-                                                      const cpx* __restrict__ tw) {
-    __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
-    x_c2r_tile<N, NT>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x, blockIdx.y, threadIdx.x, true,
-                  lds);
+template <int N, int NT = NT_P5, int PX = Geo<N>::PPX>
+__global__ void __launch_bounds__(PX * Geo<N>::G) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
+                                                         const cpx* __restrict__ tw) {
+    __shared__ cpx lds[PX * Geo<N>::A];
+    x_c2r_tile<N, NT, false, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x, blockIdx.y,
+                                       threadIdx.x, true, lds);
 }
 
 // P5 with the energy sum: as k_x_c2r, plus sum rho u over the block's outputs into
 // part[block] (rho may alias u: each thread reads rho where it then writes u).
-template <int N, int NT = NT_P5>
-__global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r_energy(const cpx* __restrict__ X1, double* u,
-                                                             const cpx* __restrict__ tw, const double* rho,
-                                                             double* __restrict__ part) {
-    __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
-    __shared__ double red[Geo<N>::TX / 64 + 1];
-    const double v = x_c2r_tile<N, NT, true>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
-                                             blockIdx.y, threadIdx.x, true, lds, (gp<const double>)rho);
-    const double s = block_sum<Geo<N>::TX>(v, red);
-    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+// The partial sums are those of the default tile (PPX row pairs) whatever PX is: a block of
+// PX = k PPX pairs holds k default tiles, sums each over its own threads in the default order
+// and writes k partials where the k default blocks would, so the energy has the same bits
+// for every tile shape.
+template <int N, int NT = NT_P5, int PX = Geo<N>::PPX>
+__global__ void __launch_bounds__(PX * Geo<N>::G) k_x_c2r_energy(const cpx* __restrict__ X1, double* u,
+                                                                const cpx* __restrict__ tw, const double* rho,
+                                                                double* __restrict__ part) {
+    constexpr int P0 = Geo<N>::PPX, T0 = P0 * Geo<N>::G, NG = PX / P0, W = T0 < 64 ? T0 : 64;
+    static_assert(PX % P0 == 0 && (NG == 1 || T0 % 64 == 0), "whole default tiles of whole waves");
+    __shared__ cpx lds[PX * Geo<N>::A];
+    __shared__ double red[NG * (T0 / 64 + 1)];
+    double v = x_c2r_tile<N, NT, true, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw,
+                                                 blockIdx.x, blockIdx.y, threadIdx.x, true, lds,
+                                                 (gp<const double>)rho);
+    const int g = threadIdx.x / T0, local = threadIdx.x % T0;
+#pragma unroll
+    for (int o = W / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, W);
+    if constexpr (T0 > 64) {
+        double* r = red + g * (T0 / 64);
+        if ((local & 63) == 0) r[local >> 6] = v;
+        __syncthreads();
+        if (local == 0) {
+            v = r[0];
+#pragma unroll
+            for (int w = 1; w < T0 / 64; ++w) v += r[w];
+        }
+    }
+    if (local == 0) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NG + g] = v;
 }
 
 // ---------------------------------------------------------------------------
 // P2: y-direction forward with zero padding.  Block = one kx, PPY consecutive z.
 // ---------------------------------------------------------------------------
-template <int N, int NT = NT_P2, bool CUBE = true>
+// PY: z-pencils per block (a tile-shape variant: the same bits for every PY)
+template <int N, int NT = NT_P2, bool CUBE = true, int PY = Geo<N>::PPY>
 __device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx> __restrict__ X2,
                                            gp<const cpx> __restrict__ tw, int kx0, int bx, int kxl, int tid,
                                            bool active, cpx* lds, Ext ext = Ext()) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
+    constexpr int E = Gm::E, G = Gm::G, PP = PY, A = Gm::A;
     const int NX = CUBE ? N : ext.nx, NZ = CUBE ? N : ext.nz;
     const int tA = tid % G, pA = tid / G;      // load role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive z
@@ -326,23 +353,23 @@ __device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx
     }
 }
 
-template <int N, int NT = NT_P2>
-__global__ void __launch_bounds__(Geo<N>::TY) k_y_fwd(const cpx* __restrict__ X1, cpx* __restrict__ X2,
-                                                      const cpx* __restrict__ tw, int kx0) {
-    __shared__ cpx lds[Geo<N>::PPY * Geo<N>::A];
-    y_fwd_tile<N, NT>((gp<const cpx>)X1, (gp<cpx>)X2, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y, threadIdx.x, true,
-                  lds);
+template <int N, int NT = NT_P2, int PY = Geo<N>::PPY>
+__global__ void __launch_bounds__(PY * Geo<N>::G) k_y_fwd(const cpx* __restrict__ X1, cpx* __restrict__ X2,
+                                                         const cpx* __restrict__ tw, int kx0) {
+    __shared__ cpx lds[PY * Geo<N>::A];
+    y_fwd_tile<N, NT, true, PY>((gp<const cpx>)X1, (gp<cpx>)X2, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y,
+                                threadIdx.x, true, lds);
 }
 
 // ---------------------------------------------------------------------------
 // P4: y-direction inverse with cropping.  Block = one kx, PPY consecutive z.
 // ---------------------------------------------------------------------------
-template <int N, int NT = NT_P4, bool CUBE = true>
+template <int N, int NT = NT_P4, bool CUBE = true, int PY = Geo<N>::PPY>
 __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx> __restrict__ X1,
                                            gp<const cpx> __restrict__ tw, int kx0, int bx, int kxl, int tid,
                                            bool active, cpx* lds, Ext ext = Ext()) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = Gm::PPY, A = Gm::A;
+    constexpr int E = Gm::E, G = Gm::G, PP = PY, A = Gm::A;
     const int NX = CUBE ? N : ext.nx, NZ = CUBE ? N : ext.nz;
     const int tA = tid % G, pA = tid / G;      // store role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive z
@@ -375,12 +402,12 @@ __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx
     }
 }
 
-template <int N, int NT = NT_P4>
-__global__ void __launch_bounds__(Geo<N>::TY) k_y_inv(const cpx* __restrict__ X2, cpx* __restrict__ X1,
-                                                      const cpx* __restrict__ tw, int kx0) {
-    __shared__ cpx lds[Geo<N>::PPY * Geo<N>::A];
-    y_inv_tile<N, NT>((gp<const cpx>)X2, (gp<cpx>)X1, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y, threadIdx.x, true,
-                  lds);
+template <int N, int NT = NT_P4, int PY = Geo<N>::PPY>
+__global__ void __launch_bounds__(PY * Geo<N>::G) k_y_inv(const cpx* __restrict__ X2, cpx* __restrict__ X1,
+                                                         const cpx* __restrict__ tw, int kx0) {
+    __shared__ cpx lds[PY * Geo<N>::A];
+    y_inv_tile<N, NT, true, PY>((gp<const cpx>)X2, (gp<cpx>)X1, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y,
+                                threadIdx.x, true, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -544,14 +571,15 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
 }
 
 // One pencil group of the fused pass without prefetch (the batched launches).
-template <int N, int DIM, int MODE, int NT = NT_P3, bool CUBE = true>
+// PZ: pencils per block (a tile-shape variant: the same bits for every PZ)
+template <int N, int DIM, int MODE, int NT = NT_P3, bool CUBE = true, int PZ = Geo<N>::PPZ>
 __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const double> __restrict__ spec,
                                             gp<const cpx> __restrict__ tw, int npencils, int kx0,
                                             const DipoleArgs& dip, int g, int tid, bool active, cpx* lds,
                                             Ext ext = Ext()) {
     using Gm = Geo<N>;
     using FZ = typename Gm::FZ;
-    constexpr int E = Gm::EZ, G = Gm::GZ, PP = Gm::PPZ, A = Gm::AZ;
+    constexpr int E = Gm::EZ, G = Gm::GZ, PP = PZ, A = Gm::AZ;
     constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
     const int NX = CUBE ? N : ext.nx, NY = CUBE ? N : ext.ny;
     int t, h, pl;
@@ -570,24 +598,24 @@ __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const dou
     fused_body<N, DIM, MODE, NT>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area, NX, NY);
 }
 
-template <int N, int DIM, int MODE, int NT = NT_P3>
-__global__ void __launch_bounds__(Geo<N>::TZ) k_fused(cpx* __restrict__ Xg, const double* __restrict__ specg,
-                                                      const cpx* __restrict__ twg, int npencils, int kx0,
-                                                      DipoleArgs dip) {
-    __shared__ cpx lds[Geo<N>::PPZ * 2 * Geo<N>::AZ];
-    const int ngroups = (npencils + Geo<N>::PPZ - 1) / Geo<N>::PPZ;
+template <int N, int DIM, int MODE, int NT = NT_P3, int PZ = Geo<N>::PPZ>
+__global__ void __launch_bounds__(PZ * 2 * Geo<N>::GZ) k_fused(cpx* __restrict__ Xg, const double* __restrict__ specg,
+                                                              const cpx* __restrict__ twg, int npencils, int kx0,
+                                                              DipoleArgs dip) {
+    __shared__ cpx lds[PZ * 2 * Geo<N>::AZ];
+    const int ngroups = (npencils + PZ - 1) / PZ;
     if constexpr (!gs_fused_persistent(DIM, N)) {
         // one pencil group per block (the grid must cover all groups).  Without the
         // persistent loop the compiler does not keep the stage twiddles of every thread
         // live across groups: at n = 2048 in 2D, 250 VGPRs instead of 256 + 154 accumulator
         // registers, two waves per SIMD instead of one
         if ((int)blockIdx.x < ngroups)
-            fused_group<N, DIM, MODE, NT>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg, npencils, kx0,
-                                          dip, blockIdx.x, threadIdx.x, true, lds);
+            fused_group<N, DIM, MODE, NT, true, PZ>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
+                                                    npencils, kx0, dip, blockIdx.x, threadIdx.x, true, lds);
     } else {
         for (int g = blockIdx.x; g < ngroups; g += gridDim.x)
-            fused_group<N, DIM, MODE, NT>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg, npencils, kx0,
-                                          dip, g, threadIdx.x, true, lds);
+            fused_group<N, DIM, MODE, NT, true, PZ>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
+                                                    npencils, kx0, dip, g, threadIdx.x, true, lds);
     }
 }
 

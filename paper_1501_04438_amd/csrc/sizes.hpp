@@ -12,3 +12,7 @@
 // 0.051 -> 0.048; 512^3 2.64 -> 2.45; 1024^3 26.2 -> 25.0; 2D 2048^2 0.077 -> 0.059 ms;
 // Coulomb 64^3 to 128^3 equal within the spread between runs.
 constexpr bool gs_fused_persistent(int d, int n) { return d == 3 && n == 256; }
+
+// Lengths for which the cubic passes are also compiled in tile-shape variants (more or fewer
+// rows or pencils per block; the same bits) that the plan autotuner chooses among.
+constexpr bool gs_tile_variants(int n) { return n >= 128; }

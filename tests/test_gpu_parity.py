@@ -458,3 +458,47 @@ def test_unpadded_laplacian_against_oracle(kernel, d, n, L):
     rho = rng.standard_normal(plan.shape)
     ref = oracle.evaluate(oracle.make_plan(kernel, d, n, L, laplacian="unpadded", **kw), rho)
     assert relmax(gpu_eval(plan, rho), ref) <= TOL
+
+
+# --------------------------------------------------------------------------
+# Tile shapes of the cubic passes (rows or pencils per block): every variant the library
+# compiles gives the same bits; the plan autotuner picks among them.
+# --------------------------------------------------------------------------
+
+TILE_VARIANTS = [1, 1 << 2, 2 << 2, 1 << 4, 2 << 4, 1 | (2 << 2) | (1 << 4)]
+
+
+@pytest.mark.parametrize("kernel,d,n", [("coulomb3d", 3, 128), ("coulomb3d", 3, 192), ("coulomb3d", 3, 256),
+                                        ("dipolar3d", 3, 128), ("poisson2d", 2, 512), ("coulomb2d", 2, 2048)])
+def test_tile_variants_change_no_bit(kernel, d, n):
+    print(f"tile variants: {kernel} n={n}", flush=True)
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    if kernel == "poisson2d":
+        kw["eps"] = 1e-13
+    rng = np.random.default_rng(1000 + n)
+    x = cuda(rng.standard_normal((n,) * d))
+    ref = gs.Plan(kernel, n=n, L=6.0, **kw)
+    u0 = ref.eval(x)
+    u0e, e0 = ref.eval_energy(x)
+    for tv in TILE_VARIANTS:
+        plan = gs.Plan(kernel, n=n, L=6.0, tile_variants=tv, **kw)
+        assert plan.query()["tile_variants"] == tv
+        assert torch.equal(plan.eval(x), u0), tv
+        ue, e = plan.eval_energy(x)
+        assert torch.equal(ue, u0e) and torch.equal(e, e0), tv
+    if n <= 128:
+        o = oracle.evaluate(oracle.make_plan(kernel, d, n, 6.0, **kw), x.cpu().numpy())
+        assert relmax(u0.cpu().numpy(), o) <= TOL
+
+
+def test_autotuned_tile_shapes_bitwise(tmp_path, monkeypatch):
+    monkeypatch.setenv("GS_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    n = 128
+    x = cuda(np.random.default_rng(4).standard_normal((n, n, n)))
+    ref = gs.Plan("coulomb3d", n=n, L=5.0).eval(x)
+    tuned = gs.Plan("coulomb3d", n=n, L=5.0, autotune=True)
+    info = tuned.query()
+    assert info["tuned"] == 1 and info["tune_candidates"] >= 7      # hints, grid rounds and tile shapes
+    assert torch.equal(tuned.eval(x), ref)
+    again = gs.Plan("coulomb3d", n=n, L=5.0, autotune=True)
+    assert again.query()["tile_variants"] == info["tile_variants"] and again.query()["tune_candidates"] == 0
