@@ -8,7 +8,8 @@ exp(-(x^2 + 4y^2 + 16z^2)) plus an 8-component seeded Gaussian mixture on
 factors, spectrum assembly) built before the timed region, as the paper times
 evaluations only.  One step = one evaluation (all five passes).
 
-The timed loop launches the five passes separately with HIP events between
+Each step of the timed loop is one library call that launches the five passes
+back to back with HIP timing events (no system-scope fence) recorded between
 them on the launching stream, which gives every pass's device time; the
 dominant pass is reported against the HBM roofline with its algorithmic bytes.
 Also reported: the oracle on a bounded sample of the same workload on the host
@@ -163,6 +164,42 @@ def summarize_profiles(fetch_dir: str, write_dir: str, trace_dir: str, n: int = 
     return 0
 
 
+class HipEvents:
+    """Timing events of the HIP runtime (ctypes), created with hipEventDisableSystemFence."""
+
+    FLAGS = 0x20000000          # hipEventDisableSystemFence
+
+    def __init__(self):
+        import ctypes
+        self.C = ctypes
+        self.lib = ctypes.CDLL("libamdhip64.so")
+        self.lib.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        self.lib.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what} failed ({rc})")
+
+    def create(self):
+        e = self.C.c_void_p()
+        self._check(self.lib.hipEventCreateWithFlags(self.C.byref(e), self.FLAGS), "hipEventCreateWithFlags")
+        return e
+
+    def record(self, e, stream):
+        self._check(self.lib.hipEventRecord(e, self.C.c_void_p(stream)), "hipEventRecord")
+
+    def elapsed(self, a, b) -> float:
+        ms = self.C.c_float()
+        self._check(self.lib.hipEventElapsedTime(self.C.byref(ms), a, b), "hipEventElapsedTime")
+        return float(ms.value)
+
+    def destroy(self, events):
+        for e in events:
+            self.lib.hipEventDestroy(e)
+
+
 def cpu_baseline(n_sample: int, min_seconds: float = 10.0) -> dict:
     """The oracle, as it stands, on the same workload: whole evaluations repeated
     until at least min_seconds of host time (plan construction excluded)."""
@@ -258,23 +295,31 @@ def main() -> int:
     K = args.steps
     steps = plan.steps()                       # pass id of every launch of one evaluation
     S = len(steps)
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(S + 1)] for _ in range(K)]
+    # HIP events without the system-scope fence (a timing-only event; with the fence every
+    # record writes back and invalidates the caches, about 5 us between passes), recorded by
+    # the library on the stream the passes are launched on, between the passes of each step
+    hip = HipEvents()
+    ev = [[hip.create() for _ in range(S + 1)] for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(K):
-        ev[s][0].record()
-        for i in range(S):
-            plan.eval_step(rho, u, i)
-            ev[s][i + 1].record()
+        plan.eval_events(rho, u, ev[s])      # the passes back to back, an event after each
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
     ms_step = wall / K * 1e3
     pass_ms = {p: 0.0 for p in range(1, 6)}
     for i, p in enumerate(steps):
-        pass_ms[p] += float(np.mean([ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(K)]))
-    gpu_ms = float(np.mean([ev[s][0].elapsed_time(ev[s][S]) for s in range(K)]))
+        pass_ms[p] += float(np.mean([hip.elapsed(ev[s][i], ev[s][i + 1]) for s in range(K)]))
+    gpu_ms = float(np.mean([hip.elapsed(ev[s][0], ev[s][S]) for s in range(K)]))
+    hip.destroy([e for row in ev for e in row])
     value = n ** 3 / (wall / K) / 1e6
+    # the same K evaluations, one library call each (no events between the passes)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        plan.eval(rho, out=u)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) / K * 1e3
 
     nb = pass_bytes(n)
     dom = max(pass_ms, key=pass_ms.get)
@@ -308,6 +353,7 @@ def main() -> int:
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "gpu_ms_per_eval_events": round(gpu_ms, 5),
+        "ms_per_eval_without_pass_events": round(plain_ms, 5),
         "eval_alg_bytes": total_bytes,
         "eval_GB_s": round(total_bytes / (gpu_ms * 1e-3) / 1e9, 1),
         "eval_frac_hbm": round(total_bytes / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -410,7 +456,9 @@ def other_figures(gs, torch, workloads, reps: int = 20):
 
 def adjoint_figures(gs, torch, workloads, plan, rho, K, eval_ms):
     """The adjoint chain alone; energy + rho-gradient through autograd (gs.energy: the energy
-    summed inside the evaluation's last pass, the gradient cell * u); and the differentiation
+    summed inside the evaluation's last pass, the gradient cell * u, which autograd forms with
+    one more pass over the grid) and directly (plan.energy_and_gradient: the last pass writes
+    cell * u and sums the energy); and the differentiation
     workload: the energy of the 8-component mixture on the same grid with its gradient with
     respect to all 40 mixture parameters (gs.mixture_energy: density, evaluation with energy
     and gradient reduction in library kernels), each against the plain evaluation."""
@@ -435,6 +483,15 @@ def adjoint_figures(gs, torch, workloads, plan, rho, K, eval_ms):
         E.backward()
     torch.cuda.synchronize()
     dte = (time.perf_counter() - t0) / reps
+    gbuf = torch.empty_like(rho)
+    for _ in range(2):
+        plan.energy_and_gradient(rho, out=gbuf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        plan.energy_and_gradient(rho, out=gbuf)
+    torch.cuda.synchronize()
+    dtd = (time.perf_counter() - t0) / K
     m = workloads.config5_mixture()
     t = lambda x: torch.tensor(x, dtype=torch.float64, device="cuda:0", requires_grad=True)
     a, mu, s = t(m.a), t(m.mu), t(m.sigma)
@@ -455,6 +512,8 @@ def adjoint_figures(gs, torch, workloads, plan, rho, K, eval_ms):
     return {"backward_Mpts_s": round(n3 / dt / 1e6, 1), "backward_ms": round(dt * 1e3, 4),
             "energy_and_grad_Mpts_s": round(n3 / dte / 1e6, 1), "energy_and_grad_ms": round(dte * 1e3, 4),
             "energy_and_grad_over_eval": round(dte * 1e3 / eval_ms, 3),
+            "energy_and_grad_direct_ms": round(dtd * 1e3, 4),
+            "energy_and_grad_direct_over_eval": round(dtd * 1e3 / eval_ms, 3),
             "mixture_energy_and_40_param_grads_ms": round(dtm * 1e3, 4),
             "mixture_energy_and_40_param_grads_Mpts_s": round(n3 / dtm / 1e6, 1),
             "mixture_over_eval": round(dtm * 1e3 / eval_ms, 3)}

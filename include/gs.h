@@ -121,10 +121,11 @@ typedef struct {
                                 its own planes; the results are the same bits);
                                 0 or 1 = in order on the plan's stream           */
     double beta;             /* GS_INVERSE_POWER: the exponent, 0 < beta < d      */
-    int tile_variants;       /* tile shapes of the cubic passes (bits 0-1: x passes, 1 =
-                                twice the row pairs per block; bits 2-3: y passes, 1 =
-                                half, 2 = twice the z-pencils per block; bits 4-5: fused
-                                pass, 1 = half, 2 = twice the pencils per block); 0 = the
+    int tile_variants;       /* tile shapes of the cubic passes (bits 0-1: x-forward
+                                pass, 1 = twice the row pairs per block; bits 2-3: y
+                                passes, 1 = half, 2 = twice the z-pencils per block; bits
+                                4-5: fused pass, 1 = half, 2 = twice the pencils per
+                                block; bits 6-7: x-inverse pass, as bits 0-1); 0 = the
                                 compiled defaults.  Compiled for n >= 128 where the LDS
                                 allows, ignored elsewhere and on grids whose axes differ;
                                 every value gives the same bits.  GS_PLAN_AUTOTUNE picks
@@ -256,6 +257,15 @@ gs_status gs_eval_static(gs_plan p, const double* rho_dev, double* u_dev);
  * Errors: as gs_eval; INVALID_ARG for a NULL energy_dev.
  */
 gs_status gs_eval_energy(gs_plan p, const double* rho_dev, double* u_dev, double* energy_dev);
+
+/*
+ * The energy and its rho-gradient in one evaluation: grad_dev receives
+ * (prod_j h_j) u (the gradient of E = 1/2 (prod_j h_j) sum rho u, the operator being
+ * symmetric), energy_dev[0] the energy 1/2 sum_i rho_i grad_i, both formed in the last
+ * pass (fixed order, the same bits on every run).  grad_dev may alias rho_dev.
+ * Errors: as gs_eval_energy.
+ */
+gs_status gs_eval_energy_gradient(gs_plan p, const double* rho_dev, double* grad_dev, double* energy_dev);
 
 /*
  * Gaussian-mixture densities and the parameter gradient of a scalar through them (the
@@ -400,6 +410,12 @@ gs_status gs_eval_batch(int count, const gs_plan* plans,
  * gs_eval.  For timing and testing the passes separately. */
 int gs_plan_steps(gs_plan p, int* pass_ids, int capacity);
 gs_status gs_eval_step(gs_plan p, const double* rho_dev, double* u_dev, int step);
+
+/* gs_eval with an event recorded on the plan's stream before the first step and after
+ * every step (events: count = steps + 1 hipEvent_t handles created by the caller, for
+ * timing the passes of a whole evaluation launched back to back).  Errors: INVALID_ARG
+ * (count, plan), HIP. */
+gs_status gs_eval_events(gs_plan p, const double* rho_dev, double* u_dev, void* const* events, int count);
 
 /* Copies a plan buffer between the device and host memory, for testing the
  * passes one at a time: which = 1 workspace X1 ((n+1) n^(d-1) complex, layout

@@ -236,6 +236,19 @@ class Plan:
                                    C.c_void_p(E.data_ptr())))
         return u, E
 
+    def energy_and_gradient(self, rho, out=None):
+        """(E, dE/drho) of E = 1/2 cell sum rho u without autograd: one evaluation whose last
+        pass writes the gradient cell * u and sums the energy (a 0-d device tensor)."""
+        torch = _torch()
+        self._check_tensor(rho, "rho")
+        g = torch.empty_like(rho) if out is None else out
+        self._check_tensor(g, "out")
+        E = torch.empty((), dtype=torch.float64, device=rho.device)
+        self._stream()
+        check(lib().gs_eval_energy_gradient(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(g.data_ptr()),
+                                            C.c_void_p(E.data_ptr())))
+        return E, g
+
     def eval_backward(self, grad_u, out=None):
         """grad_rho = A^T grad_u (the transposed chain)."""
         torch = _torch()
@@ -256,6 +269,12 @@ class Plan:
     def eval_step(self, rho, u, step: int):
         self._stream()
         check(lib().gs_eval_step(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()), int(step)))
+
+    def eval_events(self, rho, u, events):
+        """eval with the given HIP event handles (steps + 1) recorded around every step."""
+        self._stream()
+        arr = (C.c_void_p * len(events))(*[e.value if hasattr(e, "value") else e for e in events])
+        check(lib().gs_eval_events(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()), arr, len(events)))
 
     def eval_pass(self, rho, u, p: int):
         """Run every step of pass p (1..5) in order (one slab plans: the pass itself)."""

@@ -75,6 +75,7 @@ SIGNATURES = {
     "gs_batch_eval": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "gs_batch_query": (C.c_int, [C.c_void_p, C.POINTER(GSBatchInfo)]),
     "gs_eval_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gs_eval_energy_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gs_mixture_density": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gs_mixture_gradient": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_double, C.c_void_p]),
@@ -82,6 +83,7 @@ SIGNATURES = {
     "gs_batch_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gs_batch_destroy": (C.c_int, [C.c_void_p]),
     "gs_eval_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "gs_eval_events": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int]),
     "gs_plan_steps": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int]),
     "gs_plan_buffer": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_size_t]),
     "gs_status_string": (C.c_char_p, [C.c_int]),

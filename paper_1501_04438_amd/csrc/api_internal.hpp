@@ -78,7 +78,8 @@ struct DeviceScope {
 gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a);
 // Queues the evaluation steps of p on its stream: all of them (step < 0) or one.  With
 // energy != nullptr the last pass also forms energy[0] = 1/2 cell sum in*out.
-gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double* energy = nullptr);
+gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double* energy = nullptr,
+                     bool gradient = false);
 // Doubles of the per-block partial sums the mixture gradient needs (plan-owned).
 size_t mixture_partial_doubles();
 // Complex values of the evaluation workspace of p (X1, and in 3D X2 of x2_planes planes).

@@ -40,6 +40,7 @@ struct EvalArgs {
     double* energy = nullptr;
     double* epart = nullptr;
     double escale = 0.0;
+    double oscale = 1.0;              // energy pass only: the outputs are stored times oscale
     // Grids whose axes have their own n (rectangular grids): the extents of the x, y, z axes
     // (n above is unused unless nx = ny (= nz) = n) and each axis' twiddle table.
     int nx = 0, ny = 0, nz = 0;

@@ -30,9 +30,10 @@ static int resident_blocks(const void* fn, int threads) {
 }
 
 // Tile-shape variants of the cubic passes (bits of EvalArgs::tile_bits; none changes a bit
-// of the result): x passes 2 bits (0: the default row pairs per block, 1: twice as many), y
-// passes 2 bits (0: default z-pencils per block, 1: half, 2: twice), fused pass 2 bits (0:
-// default pencils per block, 1: half, 2: twice).  Compiled for the lengths gs_tile_variants
+// of the result): x-forward pass bits 0-1 (0: the default row pairs per block, 1: twice as
+// many), y passes bits 2-3 (0: default z-pencils per block, 1: half, 2: twice), fused pass
+// bits 4-5 (0: default pencils per block, 1: half, 2: twice), x-inverse pass bits 6-7 (as
+// the x-forward pass).  Compiled for the lengths gs_tile_variants
 // names, where LDS allows; elsewhere every value selects the default.
 constexpr int LDS_LIMIT = 160 * 1024;
 template <int N> constexpr int px_of(int v) {
@@ -65,8 +66,8 @@ static hipError_t launch_x_inverse_v(const EvalArgs& a, hipStream_t s) {
     const bool hint = (a.hint_bits >> 4) & 1;
     const dim3 gx((N + 2 * PX - 1) / (2 * PX), a.d == 3 ? N : 1);
     if (a.energy) {
-        if (hint) k_x_c2r_energy<N, NT_P5, PX><<<gx, T, 0, s>>>(X1, a.u, tw, a.rho, a.epart);
-        else k_x_c2r_energy<N, 0, PX><<<gx, T, 0, s>>>(X1, a.u, tw, a.rho, a.epart);
+        if (hint) k_x_c2r_energy<N, NT_P5, PX><<<gx, T, 0, s>>>(X1, a.u, tw, a.rho, a.epart, a.oscale);
+        else k_x_c2r_energy<N, 0, PX><<<gx, T, 0, s>>>(X1, a.u, tw, a.rho, a.epart, a.oscale);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         return launch_energy_finish(a.epart, (int)(gx.x * gx.y) * (PX / Geo<N>::PPX), a.escale, a.energy, s);
@@ -78,7 +79,7 @@ static hipError_t launch_x_inverse_v(const EvalArgs& a, hipStream_t s) {
 
 static hipError_t launch_x_inverse(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
-    if ((a.tile_bits & 3) == 1 && px_of<N>(1) != px_of<N>(0)) return launch_x_inverse_v<px_of<N>(1)>(a, s);
+    if (((a.tile_bits >> 6) & 3) == 1 && px_of<N>(1) != px_of<N>(0)) return launch_x_inverse_v<px_of<N>(1)>(a, s);
     return launch_x_inverse_v<px_of<N>(0)>(a, s);
 }
 
@@ -172,7 +173,8 @@ static hipError_t launch_fused(const EvalArgs& a, hipStream_t s, const DipoleArg
 }
 
 int GS_CAT(tile_variants_, GS_N)() {
-    // bit 0: an x variant exists; bits 1, 2: y half / double; bits 3, 4: fused half / double
+    // bit 0: an x variant exists (either x pass); bits 1, 2: y half / double; bits 3, 4: fused
+    // half / double
     constexpr int N = GS_N;
     return (px_of<N>(1) != px_of<N>(0) ? 1 : 0) | (py_of<N>(1) != py_of<N>(0) ? 2 : 0) |
            (py_of<N>(2) != py_of<N>(0) ? 4 : 0) | (pz_of<N>(1) != pz_of<N>(0) ? 8 : 0) |
@@ -212,14 +214,14 @@ hipError_t GS_CAT(launch_eval_g_, GS_N)(const EvalArgs& a, hipStream_t s, int pa
             return hipGetLastError();
         }
         if (a.energy) {
-            if (hint) k_x_c2r_g<N, NT_P5, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart, ext);
-            else k_x_c2r_g<N, 0, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart, ext);
+            if (hint) k_x_c2r_g<N, NT_P5, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart, ext, a.oscale);
+            else k_x_c2r_g<N, 0, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart, ext, a.oscale);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             return launch_energy_finish(a.epart, (int)(gx.x * gx.y), a.escale, a.energy, s);
         }
-        if (hint) k_x_c2r_g<N, NT_P5, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, nullptr, nullptr, ext);
-        else k_x_c2r_g<N, 0, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, nullptr, nullptr, ext);
+        if (hint) k_x_c2r_g<N, NT_P5, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, nullptr, nullptr, ext, 1.0);
+        else k_x_c2r_g<N, 0, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, nullptr, nullptr, ext, 1.0);
         return hipGetLastError();
     }
     DipoleArgs dip;

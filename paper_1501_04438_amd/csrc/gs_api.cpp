@@ -290,7 +290,7 @@ static hipError_t run_concurrent(gs_plan p, gsk::EvalArgs& a) {
     return run_step(p, a, last, p->stream);
 }
 
-gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double* energy) {
+gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double* energy, bool gradient) {
     gsk::EvalArgs a;
     gs_status st = make_args(p, in, out, a);
     if (st != GS_OK) return st;
@@ -299,7 +299,10 @@ gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double*
         a.epart = p->epart;
         double cell = 1.0;
         for (int i = 0; i < p->d; ++i) cell *= 2.0 * p->Lc[i] / p->nc[i];
-        a.escale = 0.5 * cell;
+        // the energy 1/2 cell sum rho u; with gradient the outputs are cell u (its rho
+        // gradient) and the sum 1/2 sum rho (cell u)
+        a.escale = gradient ? 0.5 : 0.5 * cell;
+        a.oscale = gradient ? cell : 1.0;
     }
     if (!p->X1) return fail(GS_ERR_INVALID_ARG, "plan created without a workspace (GS_PLAN_NO_WORKSPACE): "
                                                   "evaluate it with gs_eval_static");
@@ -473,7 +476,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->delta_rel = opt.delta_rel;
     p->flags = opt.flags;
     p->host_only = host_only;
-    p->tile_bits = opt.tile_variants & 63;
+    p->tile_bits = opt.tile_variants & 255;
     p->stream = (hipStream_t)opt.stream;
     for (int i = 0; i < 3; ++i) {
         p->dn[i] = opt.dipole_n[i];
@@ -754,12 +757,35 @@ gs_status gs_eval_energy(gs_plan p, const double* rho_dev, double* u_dev, double
     return eval_chain(p, rho_dev, u_dev, -1, energy_dev);
 }
 
+gs_status gs_eval_energy_gradient(gs_plan p, const double* rho_dev, double* grad_dev, double* energy_dev) {
+    if (!energy_dev) return fail(GS_ERR_INVALID_ARG, "NULL energy pointer");
+    return eval_chain(p, rho_dev, grad_dev, -1, energy_dev, true);
+}
+
 gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho_dev) {
     // The transposed chain: zero-pad <-> crop exchanged and the transform signs
     // flipped.  With an even spectrum (every supported kernel) the sign flip is
     // the index reversal k -> -k, under which the spectrum is invariant, so the
     // transposed chain is the same sequence of passes.
     return eval_chain(p, grad_u_dev, grad_rho_dev, -1);
+}
+
+gs_status gs_eval_events(gs_plan p, const double* rho_dev, double* u_dev, void* const* events, int count) {
+    if (!is_live(p)) return fail(GS_ERR_INVALID_ARG, "invalid plan");
+    if (!events || count != (int)p->steps.size() + 1) return fail(GS_ERR_INVALID_ARG, "need one event per step plus one");
+    gsk::EvalArgs a;
+    gs_status st = make_args(p, rho_dev, u_dev, a);
+    if (st != GS_OK) return st;
+    if (!p->X1) return fail(GS_ERR_INVALID_ARG, "plan created without a workspace (GS_PLAN_NO_WORKSPACE)");
+    DeviceScope ds(p->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    hipError_t e = hipEventRecord((hipEvent_t)events[0], p->stream);
+    for (int i = 0; i < (int)p->steps.size() && e == hipSuccess; ++i) {
+        e = run_step(p, a, i, p->stream);
+        if (e == hipSuccess) e = hipEventRecord((hipEvent_t)events[i + 1], p->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "evaluation launch");
+    return GS_OK;
 }
 
 gs_status gs_eval_step(gs_plan p, const double* rho_dev, double* u_dev, int step) {
@@ -855,9 +881,9 @@ gs_status plan_autotune(gs_plan_s* p) {
     // tile shapes of the cubic passes: each pass type's variants in turn (x: twice the row
     // pairs; y and fused: half and twice the pencils per block), keeping what is faster
     const int tv = p->cube ? gsk::tile_variants(p->n) : 0;
-    const int tries[5][2] = {{0, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}};   // (bit offset, value)
-    const int avail[5] = {1, 2, 4, 8, 16};
-    for (int i = 0; i < 5 && st == GS_OK; ++i) {
+    const int tries[6][2] = {{0, 1}, {6, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}};   // (bit offset, value)
+    const int avail[6] = {1, 1, 2, 4, 8, 16};
+    for (int i = 0; i < 6 && st == GS_OK; ++i) {
         if (!(tv & avail[i]) || (p->d == 2 && tries[i][0] == 2)) continue;
         const int keep = p->tile_bits;
         p->tile_bits = (p->tile_bits & ~(3 << tries[i][0])) | (tries[i][1] << tries[i][0]);

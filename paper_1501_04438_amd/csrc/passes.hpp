@@ -175,11 +175,13 @@ k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
 // P5: x-direction complex-to-real with cropping.  Inverse of P1 (unnormalised).
 // ---------------------------------------------------------------------------
 // EN: also returns this thread's part of sum_i rho_i u_i over the outputs it stores (rho
-// read at those outputs before they are written, so u may alias rho), in a fixed order.
+// read at those outputs before they are written, so u may alias rho), in a fixed order, the
+// outputs (and the sum) taken times oscale (1 leaves them as they are).
 template <int N, int NT = NT_P5, bool EN = false, bool CUBE = true, int PX = Geo<N>::PPX>
 __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> u,
                                              gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
-                                             cpx* lds, gp<const double> erho = nullptr, Ext ext = Ext()) {
+                                             cpx* lds, gp<const double> erho = nullptr, Ext ext = Ext(),
+                                             double oscale = 1.0) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
     const int NY = CUBE ? N : ext.ny;          // rows (y) of a plane
@@ -229,6 +231,8 @@ __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<d
         const size_t o = ((size_t)z * NY + rowA) * N;
         gp<double> ua = u + o;
         if constexpr (EN) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = cscale(acc[e], oscale);
             gp<const double> ra = erho + o;
             double r0[E], r1[E];
 #pragma unroll
@@ -288,14 +292,14 @@ __global__ void __launch_bounds__(PX * Geo<N>::G) k_x_c2r(const cpx* __restrict_
 template <int N, int NT = NT_P5, int PX = Geo<N>::PPX>
 __global__ void __launch_bounds__(PX * Geo<N>::G) k_x_c2r_energy(const cpx* __restrict__ X1, double* u,
                                                                 const cpx* __restrict__ tw, const double* rho,
-                                                                double* __restrict__ part) {
+                                                                double* __restrict__ part, double oscale) {
     constexpr int P0 = Geo<N>::PPX, T0 = P0 * Geo<N>::G, NG = PX / P0, W = T0 < 64 ? T0 : 64;
     static_assert(PX % P0 == 0 && (NG == 1 || T0 % 64 == 0), "whole default tiles of whole waves");
     __shared__ cpx lds[PX * Geo<N>::A];
     __shared__ double red[NG * (T0 / 64 + 1)];
     double v = x_c2r_tile<N, NT, true, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw,
                                                  blockIdx.x, blockIdx.y, threadIdx.x, true, lds,
-                                                 (gp<const double>)rho);
+                                                 (gp<const double>)rho, Ext(), oscale);
     const int g = threadIdx.x / T0, local = threadIdx.x % T0;
 #pragma unroll
     for (int o = W / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, W);
@@ -635,11 +639,12 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c_g(const double* __restrict
 template <int N, int NT, bool EN>
 __global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r_g(const cpx* __restrict__ X1, double* u,
                                                         const cpx* __restrict__ tw, const double* rho,
-                                                        double* __restrict__ part, Ext ext) {
+                                                        double* __restrict__ part, Ext ext, double oscale) {
     __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
     __shared__ double red[Geo<N>::TX / 64 + 1];
     const double v = x_c2r_tile<N, NT, EN, false>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
-                                                  blockIdx.y, threadIdx.x, true, lds, (gp<const double>)rho, ext);
+                                                  blockIdx.y, threadIdx.x, true, lds, (gp<const double>)rho, ext,
+                                                  oscale);
     if constexpr (EN) {
         const double s = block_sum<Geo<N>::TX>(v, red);
         if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;

@@ -121,6 +121,7 @@ def test_host_only_plan_refuses_evaluation():
     assert L.gs_eval(h, C.c_void_p(16), C.c_void_p(16)) == 1
     assert L.gs_eval_backward(h, C.c_void_p(16), C.c_void_p(16)) == 1
     assert L.gs_eval_step(h, C.c_void_p(16), C.c_void_p(16), 3) == 1
+    assert L.gs_eval_events(h, C.c_void_p(16), C.c_void_p(16), None, 6) == 1
     assert L.gs_plan_steps(h, None, 0) == 5          # 3D: x, (y, fused, y) for one slab, x
     arr = (C.c_void_p * 1)(h.value)
     assert L.gs_eval_batch(1, arr, arr, arr) == 1

@@ -465,7 +465,7 @@ def test_unpadded_laplacian_against_oracle(kernel, d, n, L):
 # compiles gives the same bits; the plan autotuner picks among them.
 # --------------------------------------------------------------------------
 
-TILE_VARIANTS = [1, 1 << 2, 2 << 2, 1 << 4, 2 << 4, 1 | (2 << 2) | (1 << 4)]
+TILE_VARIANTS = [1, 1 << 6, 1 << 2, 2 << 2, 1 << 4, 2 << 4, 1 | (2 << 2) | (1 << 4) | (1 << 6)]
 
 
 @pytest.mark.parametrize("kernel,d,n", [("coulomb3d", 3, 128), ("coulomb3d", 3, 192), ("coulomb3d", 3, 256),

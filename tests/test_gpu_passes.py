@@ -113,3 +113,37 @@ def test_2d_passes(n):
     torch.cuda.synchronize()
     ref = (np.fft.irfft(x4.T, n=2 * n, axis=1) * 2 * n)[:, :n]
     assert rel(ut.cpu().numpy(), ref) < TOL, "P5"
+
+
+@pytest.mark.parametrize("n,slabs", [(64, 0), (48, 5)])
+def test_eval_events_same_bits_and_times(n, slabs):
+    """gs_eval_events: the evaluation's steps back to back with an event after each; the
+    output equals gs_eval's bit for bit, every interval is a positive time, and a wrong
+    event count is refused."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipEventCreateWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_uint]
+    hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+    hip.hipEventDestroy.argtypes = [C.c_void_p]
+    plan = gs.Plan("coulomb3d", n=n, L=5.0, slab_planes=slabs)
+    S = len(plan.steps())
+    ev = []
+    for _ in range(S + 1):
+        e = C.c_void_p()
+        assert hip.hipEventCreateWithFlags(C.byref(e), 0x20000000) == 0
+        ev.append(e)
+    rng = np.random.default_rng(n)
+    rt = torch.from_numpy(rng.standard_normal((n, n, n))).to("cuda:0")
+    ref = plan.eval(rt)
+    ut = torch.empty_like(rt)
+    plan.eval_events(rt, ut, ev)
+    torch.cuda.synchronize()
+    assert torch.equal(ut, ref)
+    for a, b in zip(ev[:-1], ev[1:]):
+        ms = C.c_float()
+        assert hip.hipEventElapsedTime(C.byref(ms), a, b) == 0
+        assert ms.value >= 0.0
+    with pytest.raises(gs.GSError):
+        plan.eval_events(rt, ut, ev[:-1])
+    for e in ev:
+        hip.hipEventDestroy(e)
