@@ -249,13 +249,13 @@ def dipolar3d_gaussian(x, y, z, nvec, mvec, sigma: float = 1.0):
     return -nm * rho - 3.0 * nDm
 
 
-def factor_mp(tau: float, c: float, k: int, dps: int = 40) -> float:
-    """int_{-c}^{c} exp(-tau^2 y^2) cos(pi k y / c) dy in closed form (mpmath)."""
+def factor_mp(tau: float, c: float, k: int, dps: int = 40, p: int = 2) -> float:
+    """int_{-c}^{c} exp(-tau^2 y^2) cos(xi y) dy, xi = 2 pi k / (p c), in closed form (mpmath)."""
     with mp.workdps(dps):
         c_ = mp.mpf(c)
-        xi = mp.pi * k / c_
+        xi = 2 * mp.pi * k / (p * c_)
         if tau == 0.0:
-            return float(2 * c_) if k == 0 else 0.0
+            return float(2 * c_) if k == 0 else float(2 * mp.sin(xi * c_) / xi)
         t = mp.mpf(tau)
         z = mp.mpc(t * c_, xi / (2 * t))
         return float(mp.sqrt(mp.pi) / t * mp.exp(-xi * xi / (4 * t * t)) * mp.re(mp.erf(z)))

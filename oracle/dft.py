@@ -1,17 +1,17 @@
 """Separable naive DFTs on the zero-padded grid (Section 2.2, eqs. (FourSeriB3), (rho_hat), (I1FFT)).
 
-The density, sampled on n points per axis, is zero-padded to 2n points (the
-box [-2L, 2L], Remark after eq. (tensor)); its trapezoidal Fourier coefficients
-are then unnormalised DFTs of length 2n along every axis, in which only the n
-non-zero inputs take part:
-    X[k] = sum_{j<n} x[j] exp(-2 pi i j k / (2n)),      k = 0..2n-1.
+The density, sampled on n points per axis, is zero-padded to p n points (the box
+[-p L, p L]; p = 2, the Remark after eq. (tensor), or p = 3, the box B_3 of
+eq. (FourSeriB3)); its trapezoidal Fourier coefficients are then unnormalised
+DFTs of length p n along every axis, in which only the n non-zero inputs take part:
+    X[k] = sum_{j<n} x[j] exp(-2 pi i j k / (p n)),      k = 0..p n-1.
 The inverse keeps the first n outputs (the original box):
-    y[j] = sum_{k<2n} Y[k] exp(+2 pi i j k / (2n)),     j = 0..n-1.
-The grid offset -L (and the padded box origin -2L) adds a phase that cancels
+    y[j] = sum_{k<p n} Y[k] exp(+2 pi i j k / (p n)),    j = 0..n-1.
+The grid offset -L (and the padded box origin) adds a phase that cancels
 between the forward and the inverse transform, so it is left out.
 
-Each transform is a dense (n x 2n) or (2n x n) matrix applied along one axis
-with a BLAS matmul; phases use the exact integer reduction (j k) mod 2n.
+Each transform is a dense (n x p n) or (p n x n) matrix applied along one axis
+with a BLAS matmul; phases use the exact integer reduction (j k) mod p n.
 """
 
 from __future__ import annotations
@@ -23,12 +23,12 @@ import numpy as np
 
 
 @lru_cache(maxsize=16)
-def _phase(n: int, sign: int) -> np.ndarray:
+def _phase(n: int, sign: int, p: int = 2) -> np.ndarray:
     j = np.arange(n, dtype=np.int64)
-    k = np.arange(2 * n, dtype=np.int64)
-    m = (j[:, None] * k[None, :]) % (2 * n)
-    ang = math.pi * m.astype(np.float64) / n
-    return np.cos(ang) + sign * 1j * np.sin(ang)          # (n, 2n): exp(sign * i pi m / n)
+    k = np.arange(p * n, dtype=np.int64)
+    m = (j[:, None] * k[None, :]) % (p * n)
+    ang = 2.0 * math.pi * m.astype(np.float64) / (p * n)
+    return np.cos(ang) + sign * 1j * np.sin(ang)          # (n, p n): exp(sign * 2 pi i m / (p n))
 
 
 def _apply_last(x: np.ndarray, mat: np.ndarray) -> np.ndarray:
@@ -42,42 +42,42 @@ def _apply(x: np.ndarray, mat: np.ndarray, axis: int) -> np.ndarray:
     return np.moveaxis(_apply_last(xt, mat), -1, axis)
 
 
-def pad_dft(x: np.ndarray, axis: int, sign: int = -1) -> np.ndarray:
-    """Length-2n DFT of x zero-padded along `axis` (n -> 2n)."""
+def pad_dft(x: np.ndarray, axis: int, sign: int = -1, p: int = 2) -> np.ndarray:
+    """Length-p n DFT of x zero-padded along `axis` (n -> p n)."""
     n = x.shape[axis]
-    return _apply(x, _phase(n, sign), axis)
+    return _apply(x, _phase(n, sign, p), axis)
 
 
-def crop_dft(X: np.ndarray, axis: int, sign: int = +1) -> np.ndarray:
-    """Length-2n DFT along `axis`, keeping the first n outputs (2n -> n)."""
-    n = X.shape[axis] // 2
-    return _apply(X, _phase(n, sign).T, axis)
+def crop_dft(X: np.ndarray, axis: int, sign: int = +1, p: int = 2) -> np.ndarray:
+    """Length-p n DFT along `axis`, keeping the first n outputs (p n -> n)."""
+    n = X.shape[axis] // p
+    return _apply(X, _phase(n, sign, p).T, axis)
 
 
-def forward(x: np.ndarray, sign: int = -1) -> np.ndarray:
+def forward(x: np.ndarray, sign: int = -1, p: int = 2) -> np.ndarray:
     X = x.astype(np.complex128)
     for ax in range(x.ndim - 1, -1, -1):
-        X = pad_dft(X, ax, sign)
+        X = pad_dft(X, ax, sign, p)
     return X
 
 
-def inverse(X: np.ndarray, sign: int = +1) -> np.ndarray:
+def inverse(X: np.ndarray, sign: int = +1, p: int = 2) -> np.ndarray:
     y = X
     for ax in range(X.ndim):
-        y = crop_dft(y, ax, sign)
+        y = crop_dft(y, ax, sign, p)
     return y
 
 
-def full_dft(x: np.ndarray, sign: int = -1) -> np.ndarray:
+def full_dft(x: np.ndarray, sign: int = -1, p: int = 2) -> np.ndarray:
     """Non-separable O(M^2) DFT of the zero-padded array: brute force for tiny grids."""
     n = x.shape[0]
     d = x.ndim
-    N2 = 2 * n
+    N = p * n
     idx = np.stack(np.meshgrid(*[np.arange(n)] * d, indexing="ij"), -1).reshape(-1, d)
-    kdx = np.stack(np.meshgrid(*[np.arange(N2)] * d, indexing="ij"), -1).reshape(-1, d)
-    m = (kdx @ idx.T) % N2
-    mat = np.exp(sign * 1j * math.pi * m / n)
-    return (mat @ x.reshape(-1)).reshape((N2,) * d)
+    kdx = np.stack(np.meshgrid(*[np.arange(N)] * d, indexing="ij"), -1).reshape(-1, d)
+    m = (kdx @ idx.T) % N
+    mat = np.exp(sign * 2j * math.pi * m / N)
+    return (mat @ x.reshape(-1)).reshape((N,) * d)
 
 
 @lru_cache(maxsize=16)

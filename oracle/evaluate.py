@@ -17,6 +17,13 @@ Actual computation (evaluate):
 with M = prod_j 2 n_j.  The Laplacian is taken on the padded grid with the Nyquist
 mode kept (|xi| = pi/h there).
 
+Padding (padding=3): the body of Section 2.2 pads the density to B_3 = [-3L, 3L]
+(eq. (FourSeriB3), n~ = 3n): every 2 above becomes 3, i.e. transforms of length
+3 n_j with n_j non-zero inputs, xi_k = pi k / (3 L_j) for k in [-3n_j/2, 3n_j/2),
+M = prod_j 3 n_j, while the factor integrals stay over [-2 L_j, 2 L_j] as eq.
+(tensor) writes them (at the new frequencies).  n_j must be even (the index range
+of eq. (FourSeriB3)).  The default, padding=2, is the Remark after eq. (tensor).
+
 Rectangular boxes (Section 2.5): the box is prod_j [-L_j, L_j] with n_j points on
 axis j (one n for every axis, or one per axis), so h_j = 2 L_j / n_j, the padded
 grid has 2 n_j points and xi^(j)_k = pi k / (2 L_j); the factors of
@@ -76,6 +83,7 @@ class OraclePlan:
     beta: float | None = None   # exponent of the inverse-power kernel r^-beta
     ns: tuple = ()          # points per axis, C order
     laplacian: str = "padded"   # grid of the Taylor term's Laplacian: "padded" or "unpadded"
+    padding: int = 2        # the density is zero-padded to [-p L, p L], p = 2 or 3
 
     @property
     def h(self) -> float:
@@ -95,21 +103,26 @@ class OraclePlan:
 
     @property
     def M(self) -> int:
-        return int(np.prod([2 * m for m in self.ns]))
+        return int(np.prod([self.padding * m for m in self.ns]))
 
 
 def make_plan(kernel: str, d: int, n, L, eps: float = 1e-14,
               delta_rel: float = 1e-4, custom=None, dipole=None, beta: float | None = None,
-              laplacian: str = "padded") -> OraclePlan:
+              laplacian: str = "padded", padding: int = 2) -> OraclePlan:
     """n, L: one value for every axis (the cube [-L, L]^d with n^d points), or one per axis
     in C order; beta: the exponent of kernel "inverse_power" (U = |x|^-beta, 0 < beta < d);
     laplacian: the grid on which the Taylor term takes the density's Laplacian (Algorithm 1
     step 3): "padded" (the 2n grid of the convolution) or "unpadded" (the density's own
-    grid, periodic)."""
+    grid, periodic); padding: 2 (the box [-2L, 2L]) or 3 (B_3, every n even)."""
     if laplacian not in ("padded", "unpadded"):
         raise ValueError("laplacian: padded or unpadded")
+    if padding not in (2, 3):
+        raise ValueError("padding: 2 or 3")
     Ls = box_half_widths(L, d)
     ns = grid_points(n, d)
+    if padding == 3 and any(m % 2 for m in ns):
+        raise ValueError("padding 3 needs an even number of points per axis")
+    p = padding
     if kernel == "gaussian_sum":
         w, tau = custom
         table = custom_table(w, tau, d, Ls)
@@ -117,14 +130,15 @@ def make_plan(kernel: str, d: int, n, L, eps: float = 1e-14,
         table = physical_table(kernel, d, Ls, eps, delta_rel, beta=beta)
         if table.d != d:
             raise ValueError("kernel and dimension disagree")
-    Fs = tuple(factor_1d(table.tau, 2.0 * Lj, m) for Lj, m in zip(Ls, ns))
+    # factors on the octant k = 0..p n / 2 of the padded frequencies
+    Fs = tuple(factor_1d(table.tau, 2.0 * Lj, p * m // 2, p) for Lj, m in zip(Ls, ns))
     # G[i0][i1]([i2]) = sum_q w_q F_0[i0, q] F_1[i1, q] (F_2[i2, q]), array axes
     Fw = Fs[0] * table.w[None, :]
     if d == 2:
         G = Fw @ Fs[1].T
     else:
-        G = np.empty(tuple(m + 1 for m in ns))
-        for a in range(ns[0] + 1):
+        G = np.empty(tuple(p * m // 2 + 1 for m in ns))
+        for a in range(p * ns[0] // 2 + 1):
             G[a] = (Fw[a][None, :] * Fs[1]) @ Fs[2].T
     if kernel == "gaussian_sum":
         A0, c2 = 0.0, 0.0
@@ -133,7 +147,8 @@ def make_plan(kernel: str, d: int, n, L, eps: float = 1e-14,
     dn = dm = None
     if kernel == "dipolar3d":
         dn, dm = dipole
-    return OraclePlan(kernel, d, max(ns), table.L, table, Fs[-1], G, A0, c2, dn, dm, Ls, Fs, beta, ns, laplacian)
+    return OraclePlan(kernel, d, max(ns), table.L, table, Fs[-1], G, A0, c2, dn, dm, Ls, Fs, beta, ns, laplacian,
+                      padding)
 
 
 def grid_points(n, d: int) -> tuple:
@@ -146,24 +161,25 @@ def grid_points(n, d: int) -> tuple:
     return ns
 
 
-def padded_frequencies(n: int, L: float, odd: bool = False) -> np.ndarray:
-    """xi_k = pi k'/(2L) for padded index k = 0..2n-1, k' = k - 2n for k >= n.
-    The Nyquist index k = n carries -pi n/(2L) (even use) or 0 (odd use)."""
-    k = np.arange(2 * n)
-    ks = np.where(k < n, k, k - 2 * n).astype(np.float64)
-    xi = math.pi * ks / (2.0 * L)
+def padded_frequencies(n: int, L: float, odd: bool = False, p: int = 2) -> np.ndarray:
+    """xi_k = pi k'/(p L) for padded index k = 0..p n-1, k' = k - p n for k >= p n / 2.
+    The Nyquist index k = p n / 2 carries -pi n/(2L) (even use) or 0 (odd use)."""
+    N = p * n
+    k = np.arange(N)
+    ks = np.where(k < N // 2, k, k - N).astype(np.float64)
+    xi = math.pi * ks / (p * L)
     if odd:
-        xi[n] = 0.0
+        xi[N // 2] = 0.0
     return xi
 
 
-def _fold_index(n: int) -> np.ndarray:
-    k = np.arange(2 * n)
-    return np.minimum(k, 2 * n - k)
+def _fold_index(n: int, p: int = 2) -> np.ndarray:
+    k = np.arange(p * n)
+    return np.minimum(k, p * n - k)
 
 
 def full_spectrum(plan: OraclePlan) -> np.ndarray:
-    return plan.G_oct[np.ix_(*[_fold_index(m) for m in plan.ns])]
+    return plan.G_oct[np.ix_(*[_fold_index(m, plan.padding) for m in plan.ns])]
 
 
 def _axes_vectors(plan: OraclePlan, odd: bool):
@@ -173,9 +189,9 @@ def _axes_vectors(plan: OraclePlan, odd: bool):
     out = []
     for comp in range(d):
         ax = d - 1 - comp                       # x is the last array axis
-        xi = padded_frequencies(plan.ns[ax], plan.Ls[ax], odd)
+        xi = padded_frequencies(plan.ns[ax], plan.Ls[ax], odd, plan.padding)
         shape = [1] * d
-        shape[ax] = 2 * plan.ns[ax]
+        shape[ax] = plan.padding * plan.ns[ax]
         out.append(xi.reshape(shape))
     return out
 
@@ -216,15 +232,15 @@ def periodic_laplacian(plan: OraclePlan, f: np.ndarray) -> np.ndarray:
 
 def _coulomb_steps(plan: OraclePlan, rt: np.ndarray, f: np.ndarray, sign: int = +1) -> np.ndarray:
     """I1 + A0 f + c2 Lap f for padded coefficients rt of the source f."""
-    M = plan.M
+    M, p = plan.M, plan.padding
     G = full_spectrum(plan)
-    I1 = dft.inverse(G * rt, sign).real / M
+    I1 = dft.inverse(G * rt, sign, p).real / M
     if plan.A0 == 0.0 and plan.c2 == 0.0:
         return I1
     if plan.laplacian == "unpadded":
         lap = periodic_laplacian(plan, f)
     else:
-        lap = dft.inverse(-laplacian_symbol(plan) * rt, sign).real / M
+        lap = dft.inverse(-laplacian_symbol(plan) * rt, sign, p).real / M
     return I1 + plan.A0 * f + plan.c2 * lap
 
 
@@ -237,15 +253,16 @@ def ds_symbol(plan: OraclePlan) -> np.ndarray:
 def evaluate(plan: OraclePlan, rho: np.ndarray) -> np.ndarray:
     rho = np.asarray(rho, dtype=np.float64)
     assert rho.shape == tuple(plan.ns)
-    rt = dft.forward(rho)
+    p = plan.padding
+    rt = dft.forward(rho, p=p)
     if plan.kernel == "davey_stewartson2d":
         src_t = ds_symbol(plan) * rt
-        src = dft.inverse(src_t).real / plan.M
+        src = dft.inverse(src_t, p=p).real / plan.M
         return _coulomb_steps(plan, src_t, src)
     if plan.kernel != "dipolar3d":
         return _coulomb_steps(plan, rt, rho)
     src_t = -dipolar_symbol(plan) * rt
-    src = dft.inverse(src_t).real / plan.M
+    src = dft.inverse(src_t, p=p).real / plan.M
     nm = float(np.dot(plan.dipole_n, plan.dipole_m))
     return -nm * rho - 3.0 * _coulomb_steps(plan, src_t, src)
 
@@ -254,7 +271,8 @@ def adjoint(plan: OraclePlan, v: np.ndarray) -> np.ndarray:
     """Transpose of `evaluate` as a real linear map: every step transposed in
     reverse order (crop -> zero-pad, pad -> crop, DFT sign flipped)."""
     v = np.asarray(v, dtype=np.float64)
-    vt = dft.forward(v, sign=+1)                  # transpose of the crop-inverse
+    p = plan.padding
+    vt = dft.forward(v, sign=+1, p=p)                  # transpose of the crop-inverse
     M = plan.M
     unpadded = plan.laplacian == "unpadded"
     # the periodic Laplacian on the density's grid is symmetric: its transpose is itself
@@ -263,15 +281,15 @@ def adjoint(plan: OraclePlan, v: np.ndarray) -> np.ndarray:
     if plan.kernel == "davey_stewartson2d":
         # transpose of rho -> [I1 + A0 f + c2 Lap f](f = d_xx rho)
         w1 = full_spectrum(plan) * vt + plan.c2 * lap_t + plan.A0 * vt
-        out = dft.inverse(ds_symbol(plan) * w1, sign=-1).real / M
+        out = dft.inverse(ds_symbol(plan) * w1, sign=-1, p=p).real / M
         if unpadded:       # transpose of f -> c2 Lap f composed with rho -> f
-            out = out + plan.c2 * dft.inverse(ds_symbol(plan) * dft.forward(lap_v, sign=+1), sign=-1).real / M
+            out = out + plan.c2 * dft.inverse(ds_symbol(plan) * dft.forward(lap_v, sign=+1, p=p), sign=-1, p=p).real / M
         return out
     if plan.kernel != "dipolar3d":
         G = full_spectrum(plan)
-        out = dft.inverse(G * vt, sign=-1).real / M
+        out = dft.inverse(G * vt, sign=-1, p=p).real / M
         if plan.A0 != 0.0 or plan.c2 != 0.0:
-            lap = lap_v if unpadded else dft.inverse(lap_t, sign=-1).real / M
+            lap = lap_v if unpadded else dft.inverse(lap_t, sign=-1, p=p).real / M
             out = out + plan.A0 * v + plan.c2 * lap
         return out
     nm = float(np.dot(plan.dipole_n, plan.dipole_m))
@@ -279,9 +297,9 @@ def adjoint(plan: OraclePlan, v: np.ndarray) -> np.ndarray:
     sym = dipolar_symbol(plan)
     # transpose of rho -> -3 [I1 + A0 f + c2 Lap f](src(rho))
     w1 = G * vt + plan.c2 * lap_t + plan.A0 * vt
-    out = dft.inverse(-sym * w1, sign=-1).real / M
+    out = dft.inverse(-sym * w1, sign=-1, p=p).real / M
     if unpadded:
-        out = out + plan.c2 * dft.inverse(-sym * dft.forward(lap_v, sign=+1), sign=-1).real / M
+        out = out + plan.c2 * dft.inverse(-sym * dft.forward(lap_v, sign=+1, p=p), sign=-1, p=p).real / M
     return -nm * v - 3.0 * out
 
 

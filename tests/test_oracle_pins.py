@@ -853,3 +853,132 @@ def test_unpadded_laplacian_variant(kernel, d, n, L):
     lhs = float(np.sum(oracle.evaluate(pu, x) * v))
     rhs = float(np.sum(x * oracle.adjoint(pu, v)))
     assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(uu) * np.linalg.norm(v)
+
+
+# --------------------------------------------------------------------------
+# Padding to B_3 (eq. (FourSeriB3) with n~ = 3n): transforms of length 3n, frequencies
+# pi k / (3L), the factor integrals still over [-2L, 2L] (eq. (tensor)).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("L,n", [(8.0, 32), (10.0, 128)])
+def test_factors_padding3_against_erf_closed_form(L, n):
+    """Factors at xi_k = 2 pi k / (3c), k = 0..3n/2, in every branch (tau = 0, the series,
+    Gauss-Legendre, the closed form) against the erf closed form, to a few ulps of 2c."""
+    c = 2 * L
+    taus = np.array([0.0, 1e-7, 1e-4, 0.003, 0.02, 0.1, 0.3, 0.6 / L * 5, 6.4 / c, 6.6 / c, 5.0, 300.0])
+    m = 3 * n // 2
+    F = factor_1d(taus, c, m, 3)
+    ks = sorted({0, 1, 2, 3, 7, n // 3, n // 2, n - 1, n, m - 1, m})
+    for q, t in enumerate(taus):
+        for k in ks:
+            ref = cf.factor_mp(float(t), c, k, p=3)
+            assert abs(F[k, q] - ref) <= 4e-16 * 2 * c, (t, k, F[k, q], ref)
+
+
+def test_factor_mp_general_frequency_against_quadrature():
+    """The closed form at frequencies that are not multiples of pi / c (mpmath quadrature)."""
+    c = 3.0
+    for tau, k in [(0.0, 1), (0.0, 5), (0.2, 1), (0.7, 4), (1.5, 7)]:
+        xi = 2 * mp.pi * k / (3 * c)
+        with mp.workdps(30):
+            ref = mp.quad(lambda y: mp.exp(-(tau * y) ** 2) * mp.cos(xi * y), [-c, 0, c])
+        assert abs(cf.factor_mp(tau, c, k, p=3) - float(ref)) <= 1e-15 * 2 * c
+
+
+def _brute_force_potential(w, tau, A0, c2, n, L, rho, p):
+    """The regular integral of eq. (I1FFT) with the trapezoidal coefficients of eq. (rho_hat)
+    written out as one kernel matrix: u_i = sum_j K(x_i - x_j) rho_j with
+    K(z) = (1/M) sum_k [sum_q w_q prod_j g_q(xi_kj) + A0 - c2 |xi_k|^2] exp(i xi_k . z),
+    k over [-p n_j / 2, p n_j / 2)^d, xi_kj = pi k_j / (p L_j), g_q by the closed form,
+    M = prod_j p n_j; no padding, transform or crop."""
+    d = len(n)
+    axes = []
+    for nj, Lj in zip(n, L):
+        ks = np.arange(-p * nj // 2, p * nj // 2)
+        g = np.array([[cf.factor_mp(float(t), 2 * Lj, abs(int(k)), p=p) for t in tau] for k in ks])   # (K, Q)
+        axes.append((ks, g, math.pi * ks / (p * Lj), 2 * Lj / nj))
+    M = float(np.prod([p * nj for nj in n]))
+    idx = list(np.ndindex(*n))
+    u = np.zeros(n)
+    # kernel values at every grid difference (C-order axes)
+    Kval = {}
+    for diff in np.ndindex(*[2 * nj - 1 for nj in n]):
+        z = [(dj - (nj - 1)) * ax[3] for dj, nj, ax in zip(diff, n, axes)]
+        tot = 0.0
+        grids = np.meshgrid(*[np.arange(len(ax[0])) for ax in axes], indexing="ij")
+        gk = np.zeros(grids[0].shape)
+        for q in range(len(w)):
+            term = w[q]
+            for a, ax in enumerate(axes):
+                term = term * ax[1][grids[a], q]
+            gk = gk + term
+        xis = [ax[2][grids[a]] for a, ax in enumerate(axes)]
+        sym = gk + A0 - c2 * sum(x * x for x in xis)
+        ph = sum(x * zj for x, zj in zip(xis, z))
+        tot = float(np.sum(sym * np.cos(ph))) / M
+        Kval[tuple(dj - (nj - 1) for dj, nj in zip(diff, n))] = tot
+    for i in idx:
+        s = 0.0
+        for j in idx:
+            s += Kval[tuple(a - b for a, b in zip(i, j))] * rho[j]
+        u[i] = s
+    return u
+
+
+@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("d,n,L", [(2, (6, 4), (1.5, 1.0)), (3, (4, 4, 2), (1.0, 1.0, 0.5))])
+def test_padding_brute_force_convolution(p, d, n, L):
+    """A Gaussian sum with terms in every factor branch (tau = 0, series, quadrature,
+    closed form) plus Taylor-like constants: the oracle's padded transforms equal the
+    kernel-matrix sum of the same coefficients (closed-form factors), for p = 2 and 3."""
+    w = [0.37, -0.8, 1.3, 0.45, 2.0]
+    tau = [0.0, 0.01, 0.45, 1.7, 9.0]
+    rng = np.random.default_rng(40 + p + d)
+    rho = rng.standard_normal(n)
+    plan = oracle.make_plan("gaussian_sum", d, n, L, custom=(w, tau), padding=p)
+    A0, c2 = 0.3, 0.02
+    plan.A0, plan.c2 = A0, c2
+    u = oracle.evaluate(plan, rho)
+    ref = _brute_force_potential(w, tau, A0, c2, n, L, rho, p)
+    assert relmax(u, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("kernel,d,n,L,sigma", [("coulomb3d", 3, 64, 8.0, 1.0),
+                                                ("poisson2d", 2, 64, 8.0, 1.0),
+                                                ("coulomb2d", 2, (48, 64), (6.0, 8.0), 0.8)])
+def test_padding3_resolved_gaussian_closed_form(kernel, d, n, L, sigma):
+    """A resolved Gaussian (h = 1/4): padding to B_3 reaches the closed form as closely as
+    padding to B_2 (the readings differ through the interpolant's ripples between the
+    samples, which the integral over two thirds of the period B_3 does not cancel)."""
+    rho = workloads.gaussian(n, L, d, sigma=sigma)
+    eps = 1e-13 if kernel == "poisson2d" else 1e-14
+    u3 = oracle.evaluate(oracle.make_plan(kernel, d, n, L, eps=eps, padding=3), rho)
+    ns = oracle.evaluate.__globals__["grid_points"](n, d)
+    X = np.broadcast_arrays(*workloads.mesh(ns, L, d))
+    r = np.sqrt(sum(x * x for x in X))
+    ex = {"coulomb3d": cf.coulomb3d_gaussian, "coulomb2d": cf.coulomb2d_gaussian,
+          "poisson2d": cf.poisson2d_gaussian}[kernel](r, sigma)
+    assert relmax(u3, ex) <= 1e-13
+
+
+@pytest.mark.parametrize("kernel,d", [("coulomb3d", 3), ("poisson2d", 2), ("dipolar3d", 3),
+                                      ("davey_stewartson2d", 2)])
+def test_padding3_adjoint_dot_and_symmetry(kernel, d):
+    rng = np.random.default_rng(19)
+    n, L = 10, 3.0
+    dip = ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8)) if kernel == "dipolar3d" else None
+    plan = oracle.make_plan(kernel, d, n, L, eps=1e-13, dipole=dip, padding=3)
+    r, v = rng.standard_normal((2,) + (n,) * d)
+    Ar, Atv = oracle.evaluate(plan, r), oracle.adjoint(plan, v)
+    lhs, rhs = float(np.sum(Ar * v)), float(np.sum(r * Atv))
+    assert abs(lhs - rhs) <= 1e-14 * np.sqrt(np.sum(Ar ** 2) * np.sum(v ** 2))
+    assert relmax(Atv, oracle.evaluate(plan, v)) < 1e-13
+
+
+def test_padding3_separable_dft_equals_full_dft_and_needs_even_n():
+    rng = np.random.default_rng(23)
+    for shape in ((4, 4, 4), (6, 6)):
+        x = rng.standard_normal(shape)
+        assert relmax(dft.forward(x, p=3), dft.full_dft(x, p=3)) < 1e-13
+    with pytest.raises(ValueError):
+        oracle.make_plan("coulomb3d", 3, 9, 2.0, padding=3)
