@@ -99,6 +99,21 @@ typedef enum {
                                      acts on rho itself only (INVALID_ARG for the dipolar
                                      and Davey-Stewartson potentials) */
 
+#define GS_PLAN_PAD3           32 /* zero-pad the density to B_3 = prod_j [-3 L_j, 3 L_j]
+                                     (Section 2.2, eq. (FourSeriB3) with 3 n_j points per
+                                     axis) instead of to [-2 L_j, 2 L_j] (the Remark after
+                                     eq. (tensor), the default): transforms of length 3 n_j,
+                                     frequencies pi k / (3 L_j), M = prod_j 3 n_j, the
+                                     factor integrals still over [-2 L_j, 2 L_j] (eq.
+                                     (tensor)).  Every n_j even (INVALID_ARG otherwise) with
+                                     3 n_j / 2 in the compiled size list (UNSUPPORTED_SIZE):
+                                     the passes run on a grid of 3 n_j / 2 points per axis
+                                     (the density in its first n_j points, zeros after,
+                                     padded twice), copied in before the first step and out
+                                     after the last; its copy adds (3/2)^d n^d doubles to
+                                     the workspace.  Not batched (the batched schedules
+                                     refuse it; GS_SCHED_AUTO evaluates it on its own) */
+
 /* Size of the fixed device array gs_eval_static uses as its workspace. */
 #define GS_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 
@@ -160,6 +175,7 @@ typedef struct {
                                 their common value, or their largest on a grid whose
                                 axes differ                                      */
     int tile_variants;       /* tile shapes in use (gs_options.tile_variants bits)  */
+    int padding;             /* the density is zero-padded to [-p L_j, p L_j]: p = 2 or 3 */
 } gs_plan_info;
 
 /* Fill `opt` with the defaults (delta_rel 1e-4, null stream, device -1). */
@@ -174,7 +190,8 @@ void gs_options_default(gs_options* opt);
  * R = 2 sqrt(sum_j (L_j/L)^2), the largest distance in the box: 2 sqrt(d)
  * for a cube), the one-dimensional factor integrals of eq. (tensor) (eq.
  * (tensor_ani) for rectangular boxes) at the padded frequencies
- * xi = pi k/(2 L_j), k = 0..n_j, of every axis, the Taylor constants A0, c2
+ * xi = pi k/(2 L_j), k = 0..n_j, of every axis (GS_PLAN_PAD3: pi k/(3 L_j),
+ * k = 0..3 n_j/2, and 3 n_j below), the Taylor constants A0, c2
  * (Section 2.3), and the stored spectrum octant [kx][ky][kz] (x first)
  *     S[k] = ( sum_q w_q prod_j g_q(xi_kj) + A0 - c2 |xi_k|^2 ) / prod_j (2 n_j),
  * assembled on the device by an FP64 matrix-core contraction.  Allocates the

@@ -20,7 +20,7 @@ import math
 import numpy as np
 
 from ._lib import (KERNEL_DIM, KERNELS, PLAN_AUTOTUNE, PLAN_HOST_ASSEMBLY, PLAN_HOST_ONLY, PLAN_NO_WORKSPACE,
-                   PLAN_UNPADDED_LAPLACIAN, SCHEDULES, GSBatchInfo,
+                   PLAN_UNPADDED_LAPLACIAN, PLAN_PAD3, SCHEDULES, GSBatchInfo,
                    GSBatchOptions, GSError, GSOptions, GSPlanInfo, check, lib)
 
 __all__ = ["Plan", "Batch", "SCHEDULES", "potential", "energy", "eval_batch", "GSError", "device_count", "supported_sizes",
@@ -61,13 +61,16 @@ class Plan:
     laplacian: "padded" (default) or "unpadded": the grid on which the near-field Taylor term
               takes the density's Laplacian (the padded grid of the convolution, or the
               density's own grid, periodic; kernels whose Taylor term acts on rho only)
+    padding: 2 (default; the density zero-padded to [-2L, 2L]) or 3 (to B_3 = [-3L, 3L],
+              Section 2.2; every n even, with 3n/2 a compiled transform length)
     """
 
     def __init__(self, kernel: str, n: int, L, eps: float = 1e-14, d: int | None = None,
                  delta_rel: float = 1e-4, dipole=None, custom=None, device: int = -1,
                  host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0,
                  slab_streams: int = 0, autotune: bool = False, beta: float | None = None,
-                 workspace: bool = True, laplacian: str = "padded", tile_variants: int = 0):
+                 workspace: bool = True, laplacian: str = "padded", tile_variants: int = 0,
+                 padding: int = 2):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         d = KERNEL_DIM.get(kernel, d)
@@ -78,15 +81,19 @@ class Plan:
         self.n = max(self.ns)
         self.Ls = _half_widths(L, self.d)
         self.L = max(self.Ls)
+        self.padding = int(padding)
         opt = GSOptions()
         lib().gs_options_default(C.byref(opt))
         opt.delta_rel = float(delta_rel)
         opt.device = int(device)
         opt.flags = ((PLAN_HOST_ONLY if host_only else 0) | (PLAN_HOST_ASSEMBLY if host_assembly else 0)
                      | (PLAN_AUTOTUNE if autotune else 0) | (0 if workspace else PLAN_NO_WORKSPACE)
-                     | (PLAN_UNPADDED_LAPLACIAN if laplacian == "unpadded" else 0))
+                     | (PLAN_UNPADDED_LAPLACIAN if laplacian == "unpadded" else 0)
+                     | (PLAN_PAD3 if padding == 3 else 0))
         if laplacian not in ("padded", "unpadded"):
             raise ValueError("laplacian: padded or unpadded")
+        if padding not in (2, 3):
+            raise ValueError("padding: 2 or 3")
         opt.slab_planes = int(slab_planes)
         opt.tile_variants = int(tile_variants)
         opt.slab_streams = int(slab_streams)
@@ -152,15 +159,17 @@ class Plan:
         return w, tau
 
     def factors(self, axis: int | None = None) -> np.ndarray:
-        """Factor matrix (n+1, Q) of array axis `axis` (default: the last, x)."""
+        """Factor matrix (p n / 2 + 1, Q) of array axis `axis` (default: the last, x), p the
+        padding factor."""
         ax = self.d - 1 if axis is None else int(axis)
-        F = np.empty((self.ns[ax] + 1, self.info["Q"]))
+        F = np.empty((self.padding * self.ns[ax] // 2 + 1, self.info["Q"]))
         check(lib().gs_plan_factors_axis(self._h, ax, F.ctypes.data_as(C.POINTER(C.c_double)), F.size))
         return F
 
     def spectrum(self) -> np.ndarray:
-        """The stored octant, indexed [kx][ky]([kz]) (x the first index)."""
-        S = np.empty(tuple(m + 1 for m in reversed(self.ns)))
+        """The stored octant, indexed [kx][ky]([kz]) (x the first index), p n_j / 2 + 1 values
+        per axis."""
+        S = np.empty(tuple(self.padding * m // 2 + 1 for m in reversed(self.ns)))
         check(lib().gs_plan_spectrum(self._h, S.ctypes.data_as(C.POINTER(C.c_double)), S.size))
         return S
 

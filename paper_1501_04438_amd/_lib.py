@@ -20,6 +20,7 @@ PLAN_HOST_ASSEMBLY = 2
 PLAN_AUTOTUNE = 4
 PLAN_NO_WORKSPACE = 8
 PLAN_UNPADDED_LAPLACIAN = 16
+PLAN_PAD3 = 32
 
 
 class GSOptions(C.Structure):
@@ -36,7 +37,8 @@ class GSPlanInfo(C.Structure):
                 ("assembly_gflop", C.c_double), ("host_only", C.c_int), ("slab_planes", C.c_int),
                 ("num_steps", C.c_int), ("slab_streams", C.c_int), ("x2_planes", C.c_int), ("tuned", C.c_int), ("hint_bits", C.c_int), ("fused_grid_mult", C.c_int),
                 ("tune_candidates", C.c_int), ("tuned_ms", C.c_double), ("L_axes", C.c_double * 3),
-                ("beta", C.c_double), ("n_axes", C.c_int64 * 3), ("tile_variants", C.c_int)]
+                ("beta", C.c_double), ("n_axes", C.c_int64 * 3), ("tile_variants", C.c_int),
+                ("padding", C.c_int)]
 
 
 SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3, "sized": 4}

@@ -14,11 +14,15 @@
 struct gs_plan_s {
     int kernel = 0, d = 0, n = 0;             // n: points per axis of a cubic grid, else the largest
     int nc[3] = {0, 0, 0};                    // points per axis, C order (z, y, x / y, x)
-    int nk[3] = {0, 0, 0};                    // points of the octant axes x, y[, z]
+    int nk[3] = {0, 0, 0};                    // transform points of the octant axes x, y[, z]
+    int nu[3] = {0, 0, 0};                    // points of the density's grid on the octant axes
+    int pad = 2;                              // zero padding to [-pad L, pad L] (2, or 3: B_3)
+    int nf = 0;                               // transform points per axis (cubic), else the largest
     bool cube = true;                         // every axis has the same n
     double L = 0, eps = 0, delta_rel = 0;     // L: largest half-width (the table's length unit)
     double Lc[3] = {0, 0, 0};                 // half-widths as given, C order (z, y, x / y, x)
-    double Lk[3] = {0, 0, 0};                 // half-widths of the octant axes x, y[, z]
+    double Lk[3] = {0, 0, 0};                 // half-widths of the transform grid's octant axes x, y[, z]
+                                              // (pad 3: 3/2 of the density's, see gs_plan_create)
     gsh::Table table;
     std::vector<double> Fk[3];                // factors (n+1) x Q of the octant axes x, y[, z]
     double A0 = 0, c2 = 0;
@@ -34,6 +38,7 @@ struct gs_plan_s {
     double2* twk[3] = {nullptr, nullptr, nullptr};   // per octant axis (rectangular grids; may alias)
     double* epart = nullptr;                  // per-block energy sums of the x-inverse pass
     double* mixpart = nullptr;                // per-block sums of the mixture gradient
+    double* E = nullptr;                      // pad 3: the density and potential on the transform grid
     size_t spec_bytes = 0, work_bytes = 0;
     double assembly_ms = 0.0;
     int slab = 0, nslabs = 1;                 // 3D: kx planes per slab of the middle passes
@@ -82,11 +87,12 @@ gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double*
                      bool gradient = false);
 // Doubles of the per-block partial sums the mixture gradient needs (plan-owned).
 size_t mixture_partial_doubles();
-// Complex values of the evaluation workspace of p (X1, and in 3D X2 of x2_planes planes).
+// Complex values of the evaluation workspace of p (X1, in 3D X2 of x2_planes planes, and
+// with padding 3 the transform-grid copy E of the density).
 size_t workspace_complex(gs_plan p);
-// Queues every evaluation step of p on its stream with the workspace X1, X2 given (device
-// memory of workspace_complex(p) complex values, X2 = X1 + the X1 part), in order.
-gs_status eval_chain_ws(gs_plan p, const double* in, double* out, double2* X1, double2* X2);
+// Queues every evaluation step of p on its stream with its workspace in ws (device memory
+// of workspace_complex(p) complex values: X1, then X2, then E), in order.
+gs_status eval_chain_ws(gs_plan p, const double* in, double* out, double2* ws);
 // Rebuilds p's step list for `planes` kx planes per slab (3D), run on `streams` streams
 // (X2 must hold every plane when streams > 1 or planes exceed x2_planes: returns false).
 bool set_slabs(gs_plan p, int planes, int streams);

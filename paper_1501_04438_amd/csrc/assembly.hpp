@@ -12,9 +12,10 @@
 // dxx != 0 multiplies the result by -xi_k1^2, the symbol of d_xx (Davey-Stewartson
 // potential: the Poisson spectrum applied to the second x-derivative of rho).
 // lapu != 0 takes the Taylor term's Laplacian on the density's own grid (period 2L): on
-// the padded grid of 2n points its symbol is 2^d (-|xi|^2) at the indices whose every
-// component is even (those are the n-point grid's frequencies, with the same xi) and 0
-// elsewhere, since the padded transform at even indices is the n-point transform of rho.
+// the padded grid of p n points (lapu = p, the padding factor) its symbol is p^d (-|xi|^2)
+// at the indices whose every component is divisible by p (those are the n-point grid's
+// frequencies, with the same xi) and 0 elsewhere, since the padded transform there is the
+// n-point transform of rho.
 //
 // v_mfma_f64_16x16x4f64 operand layout (one wave, lane l = 0..63):
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
@@ -85,16 +86,18 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
     const long c = col0 + (lane & 15);
     if (c < ncols) {
         double xs;
-        bool even;            // k2 and k3 even (the unpadded-grid Laplacian lives there)
+        bool even;            // k2 and k3 divisible by lapu (the unpadded-grid Laplacian lives there)
+        const int lu = lapu ? lapu : 1;
         if constexpr (DIM == 3) {
             const double x2 = (double)(c / n1c) * dx2, x3 = (double)(c % n1c) * dx3;
             xs = x2 * x2 + x3 * x3;
-            even = ((c / n1c) % 2 == 0) && ((c % n1c) % 2 == 0);
+            even = ((c / n1c) % lu == 0) && ((c % n1c) % lu == 0);
         } else {
             const double x3 = (double)c * dx3;
             xs = x3 * x3;
-            even = (c % 2 == 0);
+            even = (c % lu == 0);
         }
+        const double lwe = (DIM == 3) ? (double)(lu * lu * lu) : (double)(lu * lu);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
@@ -104,8 +107,8 @@ __global__ void __launch_bounds__(256) k_assemble(const double* __restrict__ AT,
                     const double x1 = (double)k1 * dx1;
                     const double f = dxx ? -(x1 * x1) * invM : invM;
                     // Laplacian weight: 1 on the padded grid; on the density's own grid
-                    // 2^d at all-even indices, 0 elsewhere
-                    const double lw = lapu ? ((even && (k1 % 2 == 0)) ? (DIM == 3 ? 8.0 : 4.0) : 0.0) : 1.0;
+                    // p^d at indices all divisible by p, 0 elsewhere
+                    const double lw = lapu ? ((even && (k1 % lu == 0)) ? lwe : 0.0) : 1.0;
                     out[(size_t)k1 * ncols + c] = (acc[mb][r] + A0 - c2 * lw * (x1 * x1 + xs)) * f;
                 }
             }

@@ -317,10 +317,11 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
         if (!p->X1) return fail(GS_ERR_INVALID_ARG, "a batched plan needs its workspace (GS_PLAN_NO_WORKSPACE)");
         if (!seen.insert(p).second) return fail(GS_ERR_INVALID_ARG, "a plan appears twice in the batch");
         if (p->device != plans[0]->device) return fail(GS_ERR_INVALID_ARG, "batch spans devices");
-        if (!p->cube || !gsk::batch_size_supported(p->d, p->n)) {
+        if (!p->cube || p->pad != 2 || !gsk::batch_size_supported(p->d, p->n)) {
             if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED)
                 return fail(GS_ERR_UNSUPPORTED_SIZE,
-                            "batched kernels cover grids with the same n <= 128 of the compiled list on every axis");
+                            "batched kernels cover grids padded to twice their box with the same n <= 128 of "
+                            "the compiled list on every axis");
             kernels_ok = false;
         }
         if (p->nslabs != 1) {

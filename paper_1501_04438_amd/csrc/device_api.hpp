@@ -47,7 +47,20 @@ struct EvalArgs {
     const double2* twx = nullptr;
     const double2* twy = nullptr;
     const double2* twz = nullptr;
+    // Padding 3 (host side only): the passes run on the transform grid's copy E (rho = u =
+    // E); the caller's density pad_in (px, py, pz points) is copied into E before the first
+    // step and the potential out to pad_out after the last.
+    const double* pad_in = nullptr;
+    double* pad_out = nullptr;
+    int px = 0, py = 0, pz = 0;
 };
+
+// The density (nx, ny, nz points, x fastest) into the first points of each axis of a grid
+// of (Nx, Ny, Nz) points, zeros at the others; and those points of such a grid back out.
+hipError_t launch_pad_embed(const double* rho, double* E, int nx, int ny, int nz, int Nx, int Ny, int Nz,
+                            hipStream_t s);
+hipError_t launch_pad_crop(const double* E, double* u, int nx, int ny, int nz, int Nx, int Ny, int Nz,
+                           hipStream_t s);
 
 // Blocks of the x-inverse pass (the energy partial sums it writes) of an (nx, ny, nz) grid
 // (2D: nz = 1).
@@ -76,7 +89,7 @@ struct AssemblyArgs {
     double A0 = 0, c2 = 0, invM = 0;
     double dxi[3] = {0, 0, 0};        // pi / (2 L) of the axes of k1, k2, k3 (2D: k1, -, k3)
     int dxx = 0;                      // multiply by -xi_k1^2 (the d_xx symbol)
-    int lapu = 0;                     // Laplacian on the density's own grid (see assembly.hpp)
+    int lapu = 0;                     // 0, or the padding factor: Laplacian on the density's own grid (assembly.hpp)
 };
 // Row blocks per wave chosen for n1; returns the padded k length the operands need.
 int assembly_ldk(int n1);

@@ -69,6 +69,38 @@ hipError_t launch_energy_finish(const double* part, int count, double scale, dou
     return hipGetLastError();
 }
 
+// One thread per point of a row of the transform grid (blockIdx.y = y, blockIdx.z = z).
+__global__ void __launch_bounds__(256) k_pad_embed(const double* __restrict__ rho, double* __restrict__ E,
+                                                   int nx, int ny, int nz, int Nx, int Ny) {
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= Nx) return;
+    double v = 0.0;
+    if (x < nx && y < ny && z < nz) v = rho[((size_t)z * ny + y) * nx + x];
+    E[((size_t)z * Ny + y) * Nx + x] = v;
+}
+
+// One thread per point of a row of the density's grid.
+__global__ void __launch_bounds__(256) k_pad_crop(const double* __restrict__ E, double* __restrict__ u,
+                                                  int nx, int ny, int Nx, int Ny) {
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= nx) return;
+    u[((size_t)z * ny + y) * nx + x] = E[((size_t)z * Ny + y) * Nx + x];
+}
+
+hipError_t launch_pad_embed(const double* rho, double* E, int nx, int ny, int nz, int Nx, int Ny, int Nz,
+                            hipStream_t s) {
+    if (nx > Nx || ny > Ny || nz > Nz || Ny > 65535 || Nz > 65535) return hipErrorInvalidValue;
+    k_pad_embed<<<dim3((Nx + 255) / 256, Ny, Nz), 256, 0, s>>>(rho, E, nx, ny, nz, Nx, Ny);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_crop(const double* E, double* u, int nx, int ny, int nz, int Nx, int Ny, int Nz,
+                           hipStream_t s) {
+    if (nx > Nx || ny > Ny || nz > Nz || ny > 65535 || nz > 65535) return hipErrorInvalidValue;
+    k_pad_crop<<<dim3((nx + 255) / 256, ny, nz), 256, 0, s>>>(E, u, nx, ny, Nx, Ny);
+    return hipGetLastError();
+}
+
 hipError_t launch_eval(const EvalArgs& a, hipStream_t s, int which) {
     if (!cubic(a)) {
         for (int p = 1; p <= 5; ++p) {

@@ -90,7 +90,8 @@ void free_device(gs_plan_s* p) {
     }
     if (p->epart) (void)hipFree(p->epart);
     if (p->mixpart) (void)hipFree(p->mixpart);
-    p->epart = p->mixpart = nullptr;
+    if (p->E) (void)hipFree(p->E);
+    p->epart = p->mixpart = p->E = nullptr;
     for (hipStream_t st : p->sstreams) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : p->sevents) (void)hipEventDestroy(ev);
     p->sstreams.clear();
@@ -143,7 +144,7 @@ gs_status device_assembly(gs_plan_s* p) {
         for (int j = 0; j < p->d; ++j) M *= 2.0 * p->nk[j];
         a.invM = 1.0 / M;
         a.dxx = p->kernel == GS_DAVEY_STEWARTSON_2D ? 1 : 0;
-        a.lapu = (p->flags & GS_PLAN_UNPADDED_LAPLACIAN) ? 1 : 0;
+        a.lapu = (p->flags & GS_PLAN_UNPADDED_LAPLACIAN) ? p->pad : 0;
         if ((e = gsk::load_assembly(a)) != hipSuccess) {
             st = hip_fail(e, "spectrum assembly kernel load");
             break;
@@ -197,7 +198,7 @@ gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) 
     if (p->host_only) return fail(GS_ERR_INVALID_ARG, "host-only plan cannot evaluate");
     if (!in || !out) return fail(GS_ERR_INVALID_ARG, "NULL device pointer");
     a.d = p->d;
-    a.n = p->n;
+    a.n = p->nf;
     a.nx = p->nk[0];
     a.ny = p->nk[1];
     a.nz = p->d == 3 ? p->nk[2] : 1;
@@ -206,6 +207,15 @@ gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) 
     a.twz = p->d == 3 ? p->twk[2] : nullptr;
     a.rho = in;
     a.u = out;
+    if (p->pad == 3) {
+        a.pad_in = in;
+        a.pad_out = out;
+        a.px = p->nu[0];
+        a.py = p->nu[1];
+        a.pz = p->d == 3 ? p->nu[2] : 1;
+        a.rho = p->E;
+        a.u = p->E;
+    }
     a.X1 = p->X1;
     a.X2 = p->X2;
     a.spec = p->spec;
@@ -256,7 +266,16 @@ static hipError_t run_step(gs_plan p, gsk::EvalArgs& a, int step, hipStream_t s)
     // X2 holding every plane: the slab's planes sit at its own offset
     if (p->d == 3 && p->x2_planes == p->nk[0] + 1 && p->nslabs > 1)
         b.X2 = a.X2 + (size_t)a.kx0 * 2 * p->nk[1] * p->nk[2];
-    return gsk::launch_eval(b, s, pass);
+    const int nz = p->d == 3 ? p->nk[2] : 1;
+    hipError_t e = hipSuccess;
+    // padding 3: the density into the transform grid before the first step
+    if (p->pad == 3 && step == 0)
+        e = gsk::launch_pad_embed(a.pad_in, a.u, a.px, a.py, a.pz, p->nk[0], p->nk[1], nz, s);
+    if (e == hipSuccess) e = gsk::launch_eval(b, s, pass);
+    // and the potential out of it after the last
+    if (e == hipSuccess && p->pad == 3 && step == (int)p->steps.size() - 1)
+        e = gsk::launch_pad_crop(a.u, a.pad_out, a.px, a.py, a.pz, p->nk[0], p->nk[1], nz, s);
+    return e;
 }
 
 // The slab chains (y-forward, fused, y-inverse of one kx slab) on p->nstreams streams:
@@ -321,18 +340,32 @@ gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double*
     return GS_OK;
 }
 
-size_t workspace_complex(gs_plan p) {
+// X1, X2 and (padding 3) E in complex values
+static void workspace_parts(gs_plan p, size_t& x1, size_t& x2, size_t& e) {
     const size_t nx = p->nk[0], ny = p->nk[1], nz = p->d == 3 ? p->nk[2] : 1;
-    if (p->d == 2) return (nx + 1) * ny;
-    return (nx + 1) * ny * nz + 2 * ny * nz * (size_t)p->x2_planes;
+    x1 = (nx + 1) * ny * nz;
+    x2 = p->d == 3 ? 2 * ny * nz * (size_t)p->x2_planes : 0;
+    e = p->pad == 3 ? (nx * ny * nz + 1) / 2 : 0;
 }
 
-gs_status eval_chain_ws(gs_plan p, const double* in, double* out, double2* X1, double2* X2) {
+size_t workspace_complex(gs_plan p) {
+    size_t x1, x2, e;
+    workspace_parts(p, x1, x2, e);
+    return x1 + x2 + e;
+}
+
+gs_status eval_chain_ws(gs_plan p, const double* in, double* out, double2* ws) {
     gsk::EvalArgs a;
     gs_status st = make_args(p, in, out, a);
     if (st != GS_OK) return st;
-    a.X1 = X1;
-    a.X2 = p->d == 3 ? X2 : nullptr;
+    size_t x1, x2, ne;
+    workspace_parts(p, x1, x2, ne);
+    a.X1 = ws;
+    a.X2 = p->d == 3 ? ws + x1 : nullptr;
+    if (p->pad == 3) {
+        a.rho = reinterpret_cast<const double*>(ws + x1 + x2);
+        a.u = reinterpret_cast<double*>(ws + x1 + x2);
+    }
     DeviceScope ds(p->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
     hipError_t e = hipSuccess;
@@ -408,14 +441,21 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     if (k != GS_GAUSSIAN_SUM && !(eps > 0.0 && eps < 1.0)) return fail(GS_ERR_INVALID_ARG, "eps out of (0, 1)");
     if (k != GS_GAUSSIAN_SUM && eps < 1e-15)
         return fail(GS_ERR_ACCURACY, "eps below the double-precision floor of the Gaussian-sum tables");
-    int nc[3] = {1, 1, 1}, nk[3] = {1, 1, 1};
+    // padding 3 (B_3): the transforms of length 3 n_j run as the padding 2 of a grid of
+    // 3 n_j / 2 points (the density in its first n_j points, zeros after), which needs n_j even
+    const int pad = (opt.flags & GS_PLAN_PAD3) ? 3 : 2;
+    int nc[3] = {1, 1, 1}, nk[3] = {1, 1, 1}, nu[3] = {1, 1, 1};
     bool cube = true;
     for (int i = 0; i < d; ++i) {
         nc[i] = (int)n[i];
-        nk[i] = (int)n[d - 1 - i];
+        nu[i] = (int)n[d - 1 - i];
+        if (pad == 3 && nu[i] % 2 != 0)
+            return fail(GS_ERR_INVALID_ARG, "padding to B_3 needs an even number of points on every axis");
+        nk[i] = pad == 3 ? 3 * nu[i] / 2 : nu[i];
         cube = cube && n[i] == n[0];
-        if (!gsk::eval_size_supported(d, nc[i]))
-            return fail(GS_ERR_UNSUPPORTED_SIZE, "no kernels compiled for n = " + std::to_string(nc[i]));
+        if (!gsk::eval_size_supported(d, nk[i]))
+            return fail(GS_ERR_UNSUPPORTED_SIZE, "no kernels compiled for transforms of n = " + std::to_string(nk[i]) +
+                                                     (pad == 3 ? " (3/2 of the grid's points)" : ""));
     }
     const int nn = *std::max_element(nc, nc + d);
     const bool host_only = (opt.flags & GS_PLAN_HOST_ONLY) != 0;
@@ -445,7 +485,8 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     }
     {
         const size_t nx = nk[0], ny = nk[1], nz = d == 3 ? nk[2] : 1;
-        const size_t ws = no_ws ? 0 : (d == 3 ? 3 * (nx + 1) * ny * nz * 16 : (nx + 1) * ny * 16);
+        const size_t ws = no_ws ? 0 : (d == 3 ? 3 * (nx + 1) * ny * nz * 16 : (nx + 1) * ny * 16) +
+                                          (pad == 3 ? nx * ny * nz * 8 : 0);
         const size_t spec = (nx + 1) * (ny + 1) * (d == 3 ? nz + 1 : 1) * 8;
         const size_t bytes = spec + ws + 2 * (nx + ny + nz) * 16;
         if (!host_only && bytes > workspace_cap())
@@ -462,15 +503,20 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->kernel = k;
     p->d = d;
     p->n = nn;
+    p->nf = *std::max_element(nk, nk + d);
+    p->pad = pad;
     p->cube = cube;
     for (int i = 0; i < 3; ++i) {
         p->nc[i] = nc[i];
         p->nk[i] = nk[i];
+        p->nu[i] = nu[i];
     }
     p->L = Lmax;
     for (int i = 0; i < d; ++i) {
         p->Lc[i] = L[i];
-        p->Lk[i] = L[d - 1 - i];               // octant axes x, y[, z]: C order reversed
+        // octant axes x, y[, z]: C order reversed; with padding 3 the transform grid has the
+        // same step on 3/2 the half-width (its padded box is B_3)
+        p->Lk[i] = pad == 3 ? 1.5 * L[d - 1 - i] : L[d - 1 - i];
     }
     p->eps = eps;
     p->delta_rel = opt.delta_rel;
@@ -505,8 +551,9 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         int same = -1;
         for (int j = 0; j < i; ++j)
             if (p->Lk[j] == p->Lk[i] && p->nk[j] == p->nk[i]) same = j;
+        // integrals over [-2 L_j, 2 L_j] (eq. (tensor)) at the padded grid's frequencies
         if (same >= 0) p->Fk[i] = p->Fk[same];
-        else gsh::factors_1d(p->table.tau, p->Lk[i], p->nk[i], p->Fk[i]);
+        else gsh::factors_1d(p->table.tau, L[d - 1 - i], p->nk[i], p->Fk[i], pad);
     }
     gsh::taylor_constants(k, d, p->table, p->A0, p->c2);
 
@@ -537,11 +584,13 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         for (int j = 0; j < i; ++j) seen = seen || nk[j] == nk[i];
         if (!seen) tw_bytes += 2 * (size_t)nk[i] * sizeof(double2);
     }
-    p->work_bytes = (no_ws ? 0 : (x1 + x2) * sizeof(double2)) + tw_bytes;
+    const size_t ebytes = pad == 3 ? (size_t)nk[0] * nk[1] * (d == 3 ? nk[2] : 1) * sizeof(double) : 0;
+    p->work_bytes = (no_ws ? 0 : (x1 + x2) * sizeof(double2) + ebytes) + tw_bytes;
+    const int lapu = (opt.flags & GS_PLAN_UNPADDED_LAPLACIAN) ? pad : 0;
 
     if (host_only) {
-        gsh::assemble_spectrum(d, p->nk, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D,
-                               (opt.flags & GS_PLAN_UNPADDED_LAPLACIAN) != 0, p->spec_host);
+        gsh::assemble_spectrum(d, p->nk, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D, lapu,
+                               p->spec_host);
         log(1, "host-only plan kernel=%d d=%d n=(%d, %d, %d) L=(%g, %g, %g) S=%d Q=%zu delta=%.3g A0=%.6g c2=%.6g",
             (int)k, d, p->nc[0], p->nc[1], p->nc[2], p->Lc[0], p->Lc[1], p->Lc[2], p->table.S, p->table.w.size(),
             p->table.delta, p->A0, p->c2);
@@ -567,6 +616,8 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace X1) failed");
         if (st == GS_OK && !no_ws && x2 && (e = hipMalloc(&p->X2, x2 * sizeof(double2))) != hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace X2) failed");
+        if (st == GS_OK && !no_ws && ebytes && (e = hipMalloc(&p->E, ebytes)) != hipSuccess)
+            st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(workspace E) failed");
         // per-axis twiddle tables (the cubic passes use tw, which is the x axis' table)
         for (int i = 0; i < d && st == GS_OK; ++i) {
             int same = -1;
@@ -595,7 +646,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         if (st == GS_OK) {
             if (opt.flags & GS_PLAN_HOST_ASSEMBLY) {
                 gsh::assemble_spectrum(d, p->nk, p->Lk, p->table, p->Fk, p->A0, p->c2, k == GS_DAVEY_STEWARTSON_2D,
-                                       (opt.flags & GS_PLAN_UNPADDED_LAPLACIAN) != 0, p->spec_host);
+                                       lapu, p->spec_host);
                 if ((e = hipMemcpy(p->spec, p->spec_host.data(), p->spec_bytes, hipMemcpyHostToDevice)) != hipSuccess)
                     st = hip_fail(e, "hipMemcpy(spectrum)");
             } else {
@@ -652,6 +703,7 @@ gs_status gs_plan_query(gs_plan p, gs_plan_info* info) {
         info->L_axes[i] = p->Lc[i];
         info->n_axes[i] = p->nc[i];
     }
+    info->padding = p->pad;
     info->beta = p->table.beta;
     info->eps = p->eps;
     info->delta = p->table.delta;
@@ -834,7 +886,8 @@ gs_status plan_autotune(gs_plan_s* p) {
     std::string dims = std::to_string(p->nc[0]);
     for (int i = 1; i < p->d; ++i) dims += "x" + std::to_string(p->nc[i]);
     const std::string key = tune_device_key(p->device) + "|plan|d" + std::to_string(p->d) + "|n" + dims +
-                            (p->kernel == GS_DIPOLAR_3D ? "|dip" : "") + "|slab" + std::to_string(p->slab);
+                            (p->kernel == GS_DIPOLAR_3D ? "|dip" : "") + (p->pad == 3 ? "|pad3" : "") + "|slab" +
+                            std::to_string(p->slab);
     TuneEntry te;
     if (tune_lookup(key, te)) {
         p->hint_bits = te.schedule;
@@ -869,7 +922,7 @@ gs_status plan_autotune(gs_plan_s* p) {
         else p->hint_bits = keep;
     }
     for (int m : {1, 4}) {
-        if (st != GS_OK || !p->cube || !gs_fused_persistent(p->d, p->n)) break;   // grid fixed by the group count
+        if (st != GS_OK || !p->cube || !gs_fused_persistent(p->d, p->nf)) break;   // grid fixed by the group count
         const int keep = p->fused_mult;
         p->fused_mult = m;
         double ms = 0;
@@ -880,7 +933,7 @@ gs_status plan_autotune(gs_plan_s* p) {
     }
     // tile shapes of the cubic passes: each pass type's variants in turn (x: twice the row
     // pairs; y and fused: half and twice the pencils per block), keeping what is faster
-    const int tv = p->cube ? gsk::tile_variants(p->n) : 0;
+    const int tv = p->cube ? gsk::tile_variants(p->nf) : 0;
     const int tries[6][2] = {{0, 1}, {6, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}};   // (bit offset, value)
     const int avail[6] = {1, 1, 2, 4, 8, 16};
     for (int i = 0; i < 6 && st == GS_OK; ++i) {

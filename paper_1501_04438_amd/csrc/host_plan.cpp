@@ -347,30 +347,34 @@ struct CompSum {
 };
 
 // Small tau c: g(tau, xi_k) = sum_i (-tau^2)^i / i! M_2i(k) with the exact moments
-// M_2i(k) = int_{-c}^{c} y^2i cos(pi k y / c) dy = c^(2i+1) m_2i(pi k),
+// M_2i(k) = int_{-c}^{c} y^2i cos(xi_k y) dy = c^(2i+1) m_2i(a), a = xi_k c = 2 pi k / pad,
 //   m_2i(0) = 2 / (2i + 1),
-//   m_0(a) = 0, m_2i(a) = (4i cos a - 2i (2i - 1) m_2i-2(a)) / a^2   (a = pi k, k >= 1),
-// by parts twice (sin a = 0).  For tau c <= 0.05 the recurrence's growth at small k,
-// (2i)!/(pi k)^2i, is outweighed by the series weight (tau c)^2i / i!: each term is
-// exact to a few roundings of itself, and ten terms reach below 1e-25 relative.
-static void factor_series(double t, double c, int n, int Q, int q, std::vector<double>& F) {
+//   m_0(a) = 2 sin a / a, m_2i(a) = 2 sin a / a + (4i cos a - 2i (2i - 1) m_2i-2(a)) / a^2,
+// by parts twice (sin a = 0 for pad = 2, a = pi k).  For tau c <= 0.05 the recurrence's
+// growth at small k, (2i)!/a^2i, is outweighed by the series weight (tau c)^2i / i!: each
+// term is exact to a few roundings of itself, and ten terms reach below 1e-25 relative.
+static void factor_series(double t, double c, int n, int pad, int Q, int q, std::vector<double>& F) {
     const long double tc2 = (long double)t * t * c * c;
     for (int k = 0; k <= n; ++k) {
-        const long double a = (long double)PI * k, a2 = a * a;
-        const long double cosa = (k & 1) ? -1.0L : 1.0L;
-        long double m = (k == 0) ? 2.0L : 0.0L;          // m_0
+        // a = pi r / pad with r = 2k mod 2 pad: cos and sin exact where r / pad is whole
+        const int r = (2 * k) % (2 * pad);
+        const long double a = 2.0L * (long double)PI * k / pad, a2 = a * a;
+        const long double ang = 3.141592653589793238462643383279502884L * r / pad;
+        const long double cosa = (r % pad == 0) ? ((r == 0) ? 1.0L : -1.0L) : cosl(ang);
+        const long double s2a = (r % pad == 0 || k == 0) ? 0.0L : 2.0L * sinl(ang) / a;   // 2 sin a / a
+        long double m = (k == 0) ? 2.0L : s2a;           // m_0
         long double coef = 1.0L, sum = 0.0L;             // (-tau^2 c^2)^i / i!
         for (int i = 0; i < 10; ++i) {
             sum += coef * m;
             const int j = 2 * (i + 1);                  // next moment index
-            m = (k == 0) ? 2.0L / (j + 1) : (2.0L * j * cosa - (long double)j * (j - 1) * m) / a2;
+            m = (k == 0) ? 2.0L / (j + 1) : s2a + (2.0L * j * cosa - (long double)j * (j - 1) * m) / a2;
             coef *= -tc2 / (i + 1);
         }
         F[(size_t)k * Q + q] = (double)(sum * c);
     }
 }
 
-void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<double>& F) {
+void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<double>& F, int pad) {
     const int Q = (int)tau.size();
     const double c = 2.0 * L;
     F.assign((size_t)(n + 1) * Q, 0.0);
@@ -378,25 +382,33 @@ void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<dou
     for (int q = 0; q < Q; ++q) {
         const double t = tau[q];
         if (t == 0.0) {
-            F[q] = 2.0 * c;                      // k = 0 only: xi_k c = pi k
+            // 2 sin(xi_k c) / xi_k: 2c at k = 0; exactly 0 for pad = 2 (xi_k c = pi k)
+            F[q] = 2.0 * c;
+            for (int k = 1; k <= n; ++k) {
+                const int r = (2 * k) % (2 * pad);
+                if (r % pad == 0) continue;
+                const double xi = 2.0 * PI * k / (pad * c);
+                F[(size_t)k * Q + q] =
+                    (double)(2.0L * sinl(3.141592653589793238462643383279502884L * r / pad)) / xi;
+            }
         } else if (t * c >= TAU_C_CLOSED) {
             for (int k = 0; k <= n; ++k) {
-                const double xi = PI * k / c;
+                const double xi = 2.0 * PI * k / (pad * c);
                 F[(size_t)k * Q + q] = std::sqrt(PI) / t * std::exp(-(xi * xi) / (4.0 * t * t));
             }
         } else if (t * c <= TAU_C_SERIES) {
-            factor_series(t, c, n, Q, q, F);
+            factor_series(t, c, n, pad, Q, q, F);
         } else {
             mid.push_back(q);
         }
     }
     if (mid.empty()) return;
-    // Composite Gauss-Legendre on [0, c] (even integrand, factor 2): P panels of
-    // GL_M nodes, at most one half-period of cos(xi_k y) per panel.  At node
-    // y = c (p + s)/P the phase pi k (p + s)/P is split into an exactly reduced
-    // integer part pi ((k p) mod 2P)/P and a part pi k s/P <= pi.  The panel
-    // contributions are summed with compensation (up to 2048 panels).
-    const int P = std::max(n, 8);
+    // Composite Gauss-Legendre on [0, c] (even integrand, factor 2): P = max(2n / pad, 8)
+    // panels of GL_M nodes, at most one half-period of cos(xi_k y) per panel.  At node
+    // y = c (p + s)/P the phase 2 pi k (p + s)/(pad P) is split into an exactly reduced
+    // integer part pi ((2 k p) mod 2 pad P)/(pad P) and a part 2 pi k s/(pad P) <= pi.
+    // The panel contributions are summed with compensation (up to 2048 panels).
+    const int P = std::max(2 * n / pad, 8);
     const int Qm = (int)mid.size();
     std::vector<double> xg, wg;
     gauss_legendre(GL_M, xg, wg);
@@ -412,9 +424,10 @@ void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<dou
                 gw[((size_t)p * Qm + qi) * GL_M + i] = hp * wg[i] * std::exp(-(t * y) * (t * y));
             }
         }
-    std::vector<double> cosA(2 * P), sinA(2 * P);
-    for (int m = 0; m < 2 * P; ++m) {
-        const long double a = 3.141592653589793238462643383279502884L * (long double)m / (long double)P;
+    const int R = 2 * pad * P;                       // phase period in units of pi / (pad P)
+    std::vector<double> cosA(R), sinA(R);
+    for (int m = 0; m < R; ++m) {
+        const long double a = 3.141592653589793238462643383279502884L * (long double)m / (long double)(pad * P);
         cosA[m] = (double)cosl(a);
         sinA[m] = (double)sinl(a);
     }
@@ -423,13 +436,14 @@ void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<dou
         std::vector<double> cb(GL_M), sb(GL_M);
         for (int k = k0; k < k1; ++k) {
             for (int i = 0; i < GL_M; ++i) {
-                const long double B = 3.141592653589793238462643383279502884L * ((long double)k * s[i]) / P;
+                const long double B =
+                    3.141592653589793238462643383279502884L * ((long double)(2 * k) * s[i]) / (pad * P);
                 cb[i] = (double)cosl(B);
                 sb[i] = (double)sinl(B);
             }
             std::fill(acc.begin(), acc.end(), CompSum());
             for (int p = 0; p < P; ++p) {
-                const int m = (int)(((long long)k * p) % (2 * P));
+                const int m = (int)(((long long)2 * k * p) % R);
                 const double ca = cosA[m], sa = sinA[m];
                 const double* g = &gw[(size_t)p * Qm * GL_M];
                 for (int qi = 0; qi < Qm; ++qi) {
@@ -524,8 +538,10 @@ void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2)
 // ------------------------------------------------------------------ host assembly
 
 void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, const std::vector<double>* Fk,
-                       double A0, double c2, bool dxx, bool lapu, std::vector<double>& S) {
-    const double lwe = lapu ? (d == 3 ? 8.0 : 4.0) : 1.0, lwo = lapu ? 0.0 : 1.0;   // all-even / other
+                       double A0, double c2, bool dxx, int lapu, std::vector<double>& S) {
+    // Laplacian weights at indices all divisible by lapu / elsewhere (lapu = 0: 1 everywhere)
+    const double lwe = lapu ? std::pow((double)lapu, d) : 1.0, lwo = lapu ? 0.0 : 1.0;
+    const int lu = lapu ? lapu : 1;
     const int na = nk[0] + 1, nb = nk[1] + 1, nc = nk[d - 1] + 1, Q = (int)t.w.size();
     const double dxa = PI / (2.0 * Lk[0]), dxb = PI / (2.0 * Lk[1]), dxc = PI / (2.0 * Lk[d - 1]);
     const std::vector<double>& Fa = Fk[0];
@@ -546,7 +562,7 @@ void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, c
                     double acc = 0.0;
                     for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q];
                     const double xb = b * dxb;
-                    const double lw = (a % 2 == 0 && b % 2 == 0) ? lwe : lwo;
+                    const double lw = (a % lu == 0 && b % lu == 0) ? lwe : lwo;
                     S[(size_t)a * nb + b] = (acc + A0 - c2 * lw * (xa * xa + xb * xb)) * fa;
                 }
                 continue;
@@ -557,7 +573,7 @@ void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, c
                     double acc = 0.0;
                     for (int q = 0; q < Q; ++q) acc += wa[q] * Fb[(size_t)b * Q + q] * Fc[(size_t)cc * Q + q];
                     const double xc = cc * dxc;
-                    const double lw = (a % 2 == 0 && b % 2 == 0 && cc % 2 == 0) ? lwe : lwo;
+                    const double lw = (a % lu == 0 && b % lu == 0 && cc % lu == 0) ? lwe : lwo;
                     S[((size_t)a * nb + b) * nc + cc] = (acc + A0 - c2 * lw * (xa * xa + xb * xb + xc * xc)) * fa;
                 }
             }

@@ -32,19 +32,21 @@ bool power_table(double beta, double Lu, double hi, double delta_rel, double eps
 // Max error of the rescaled tables on their fit interval (for tests and reports).
 double coulomb_table_error(int S, double lo, double hi);
 
-// F[k*Q + q] = int_{-2L}^{2L} exp(-tau_q^2 y^2) cos(pi k y / (2L)) dy, k = 0..n.
-void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<double>& F);
+// F[k*Q + q] = int_{-2L}^{2L} exp(-tau_q^2 y^2) cos(xi_k y) dy, k = 0..n, at the frequencies
+// xi_k = pi k / (pad L) of the density padded to [-pad L, pad L] (pad = 2, or 3 for B_3).
+void factors_1d(const std::vector<double>& tau, double L, int n, std::vector<double>& F, int pad = 2);
 
 // Taylor constants of the near-field correction (Section 2.3).
 void taylor_constants(int kernel, int d, const Table& t, double& A0, double& c2);
 
 // Host assembly of the stored octant prod_i (n_i + 1), 1/prod_i (2 n_i) folded in.  Octant
 // axes (kx, ky[, kz]): nk[i], Lk[i] and Fk[i] are the points, half-width and factors of axis
-// x, y[, z].  dxx: multiply by -xi_x^2, the symbol of d_xx (Davey-Stewartson).  lapu: the
-// Taylor term's Laplacian on the density's own grid (weight 2^d at all-even indices, 0 at
-// the others) instead of the padded grid's (weight 1).
+// x, y[, z].  dxx: multiply by -xi_x^2, the symbol of d_xx (Davey-Stewartson).  lapu: 0 for
+// the Taylor term's Laplacian on the padded grid (weight 1), else the padding factor p and
+// that Laplacian on the density's own grid (weight p^d at indices all divisible by p, where
+// the padded transform is the density's n-point transform; 0 at the others).
 void assemble_spectrum(int d, const int* nk, const double* Lk, const Table& t, const std::vector<double>* Fk,
-                       double A0, double c2, bool dxx, bool lapu, std::vector<double>& S);
+                       double A0, double c2, bool dxx, int lapu, std::vector<double>& S);
 
 // exp(-i pi m / n), m = 0..2n-1, as interleaved (re, im).
 void twiddles(int n, std::vector<double>& tw);

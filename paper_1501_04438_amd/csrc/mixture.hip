@@ -167,9 +167,9 @@ __global__ void __launch_bounds__(MT) k_mix_grad_finish(int d, int K, int c0, in
 MixGeom geom(gs_plan p) {
     MixGeom g;
     g.d = p->d;
-    g.n = p->nk[0];
-    g.ny = p->nk[1];
-    g.rows = p->d == 3 ? p->nk[1] * p->nk[2] : p->nk[1];
+    g.n = p->nu[0];                                // the density's grid (not the transform grid)
+    g.ny = p->nu[1];
+    g.rows = p->d == 3 ? p->nu[1] * p->nu[2] : p->nu[1];
     g.rpt = std::max(1, std::min(ROWS, 4096 / g.n));
     for (int j = 0; j < 3; ++j) {
         g.x0[j] = 0.0;
@@ -178,7 +178,7 @@ MixGeom geom(gs_plan p) {
     for (int j = 0; j < p->d; ++j) {               // axis j (x, y, z) is array axis d-1-j
         const double L = p->Lc[p->d - 1 - j];
         g.x0[j] = -L;
-        g.h[j] = 2.0 * L / p->nk[j];
+        g.h[j] = 2.0 * L / p->nu[j];
     }
     return g;
 }

@@ -63,6 +63,5 @@ extern "C" gs_status gs_eval_static(gs_plan p, const double* rho_dev, double* u_
     double2* ws = nullptr;
     const gs_status st = scratch_on(p->device, ws);
     if (st != GS_OK) return st;
-    const size_t x1 = p->d == 3 ? (size_t)(p->nk[0] + 1) * p->nk[1] * p->nk[2] : 0;
-    return gsapi::eval_chain_ws(p, rho_dev, u_dev, ws, ws + x1);
+    return gsapi::eval_chain_ws(p, rho_dev, u_dev, ws);
 }

@@ -22,8 +22,8 @@ def test_log_level_reports_plans_and_errors():
     env = dict(os.environ, GS_LOG_LEVEL="2", PYTHONPATH=ROOT)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, env=env, cwd=ROOT)
     assert r.returncode == 0, r.stderr
-    assert "[gs] host-only plan kernel=0 d=3 n=16 L=(3, 4, 5)" in r.stderr
-    assert "[gs] error 2: no kernels compiled for this n" in r.stderr
+    assert "[gs] host-only plan kernel=0 d=3 n=(16, 16, 16) L=(3, 4, 5)" in r.stderr
+    assert "[gs] error 2: no kernels compiled for transforms of n = 20" in r.stderr
     env["GS_LOG_LEVEL"] = "0"
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, env=env, cwd=ROOT)
     assert "[gs]" not in r.stderr

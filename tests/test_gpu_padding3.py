@@ -1,0 +1,178 @@
+"""Padding to B_3 (Section 2.2, eq. (FourSeriB3) with 3 n_j points per axis; GS_PLAN_PAD3).
+
+The passes run on a grid of 3 n_j / 2 points per axis that holds the density in its first
+n_j points (zeros after), padded twice: transforms of length 3 n_j, frequencies
+pi k / (3 L_j), M = prod_j 3 n_j, factor integrals over [-2 L_j, 2 L_j].  HIP path through
+the C ABI against the oracle's padding-3 reading, element by element, max-norm relative
+error <= 1e-12: cubes whose transform grid runs the cubic passes (16 -> 24 up to
+128 -> 192, the tile variants there), rectangular grids (the per-axis passes), 2D, the
+dipolar and Davey-Stewartson symbols, the unpadded-grid Laplacian, the adjoint, the energy,
+the mixture gradient, the allocation-free entry point and the automatic batch."""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import paper_1501_04438_amd as gs
+import workloads
+from oracle import closed_forms as cf
+from paper_1501_04438_amd._lib import lib
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def kw_of(kernel):
+    if kernel == "dipolar3d":
+        return {"dipole": ((0.3, -0.5, 0.8), (0.9, 0.1, -0.2))}
+    if kernel in ("poisson2d", "davey_stewartson2d"):
+        return {"eps": 1e-13}
+    if kernel == "inverse_power":
+        return {"beta": 1.3}
+    return {}
+
+
+CASES = [("coulomb3d", 3, 16, 4.0), ("coulomb3d", 3, 32, 6.0), ("coulomb3d", 3, 64, 8.0),
+         ("coulomb3d", 3, 128, 10.0),
+         ("coulomb3d", 3, (16, 32, 64), (2.0, 4.0, 8.0)), ("coulomb3d", 3, (8, 128, 16), (1.0, 16.0, 2.0)),
+         ("dipolar3d", 3, 32, 6.0), ("inverse_power", 3, 16, 3.0),
+         ("poisson2d", 2, 64, 8.0), ("coulomb2d", 2, 128, 12.0), ("poisson2d", 2, (32, 128), (3.0, 12.0)),
+         ("davey_stewartson2d", 2, 32, 5.0), ("inverse_power", 2, 64, 6.0)]
+
+
+@pytest.mark.parametrize("kernel,d,n,L", CASES)
+def test_random_input_against_oracle(kernel, d, n, L):
+    print(f"padding 3: {kernel} n={n} L={L}", flush=True)
+    kw = kw_of(kernel)
+    plan = gs.Plan(kernel, n=n, L=L, d=d, padding=3, **kw)
+    assert plan.info["padding"] == 3
+    rng = np.random.default_rng(300 + sum(np.atleast_1d(n)))
+    rho = rng.standard_normal(plan.shape)
+    u = plan.eval(cuda(rho))
+    torch.cuda.synchronize()
+    ref = oracle.evaluate(oracle.make_plan(kernel, d, n, L, padding=3, **kw), rho)
+    assert relmax(u.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("kernel,d,n,L", [("coulomb3d", 3, 32, 5.0), ("coulomb2d", 2, (64, 32), (6.0, 3.0))])
+def test_unpadded_laplacian_with_padding3(kernel, d, n, L):
+    plan = gs.Plan(kernel, n=n, L=L, d=d, padding=3, laplacian="unpadded")
+    rng = np.random.default_rng(77)
+    rho = rng.standard_normal(plan.shape)
+    u = plan.eval(cuda(rho)).cpu().numpy()
+    ref = oracle.evaluate(oracle.make_plan(kernel, d, n, L, padding=3, laplacian="unpadded"), rho)
+    assert relmax(u, ref) <= TOL
+
+
+def test_resolved_gaussian_closed_form():
+    """h = 1/4: padding to B_3 reaches the closed form to 1e-13 of its maximum."""
+    n, L = 64, 8.0
+    rho = workloads.gaussian(n, L, 3, sigma=1.0)
+    u = gs.Plan("coulomb3d", n=n, L=L, padding=3).eval(cuda(rho)).cpu().numpy()
+    X = np.broadcast_arrays(*workloads.mesh(n, L, 3))
+    r = np.sqrt(sum(x * x for x in X))
+    assert relmax(u, cf.coulomb3d_gaussian(r, 1.0)) <= 1e-13
+
+
+@pytest.mark.parametrize("kernel,d,n,L", [("coulomb3d", 3, (16, 32, 64), (2.0, 4.0, 8.0)),
+                                          ("dipolar3d", 3, 16, 3.0), ("davey_stewartson2d", 2, 32, 4.0)])
+def test_adjoint_and_dot(kernel, d, n, L):
+    kw = kw_of(kernel)
+    plan = gs.Plan(kernel, n=n, L=L, d=d, padding=3, **kw)
+    rng = np.random.default_rng(88)
+    a, v = rng.standard_normal(plan.shape), rng.standard_normal(plan.shape)
+    ua, atv = plan.eval(cuda(a)), plan.eval_backward(cuda(v))
+    torch.cuda.synchronize()
+    ref = oracle.adjoint(oracle.make_plan(kernel, d, n, L, padding=3, **kw), v)
+    assert relmax(atv.cpu().numpy(), ref) <= TOL
+    lhs, rhs = float((ua * cuda(v)).sum()), float((cuda(a) * atv).sum())
+    assert abs(lhs - rhs) <= 1e-13 * float(ua.norm() * atv.norm())
+
+
+def test_energy_static_slabs_events_and_batch():
+    """The energy formed in the last pass (same potential bits), gs_eval_static, kx slabs
+    and gs_eval_events (same bits), and GS_SCHED_AUTO evaluating the plan on its own."""
+    n, L = 32, 5.0
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal((n, n, n))
+    plan = gs.Plan("coulomb3d", n=n, L=L, padding=3)
+    x = cuda(a)
+    ua = plan.eval(x)
+    u2, E = plan.eval_energy(x)
+    assert torch.equal(u2, ua)
+    Eo = oracle.energy(oracle.make_plan("coulomb3d", 3, n, L, padding=3), a)
+    assert abs(float(E) - Eo) <= 1e-13 * float((0.5 * plan.cell * (x * ua)).abs().sum())
+    E2, g = plan.energy_and_gradient(x)
+    assert abs(float(E2) - float(E)) <= 1e-14 * float((0.5 * plan.cell * (x * ua)).abs().sum())
+    assert torch.allclose(g, plan.cell * ua, rtol=1e-15, atol=0.0)
+    for sp in (1, 7):
+        assert torch.equal(gs.Plan("coulomb3d", n=n, L=L, padding=3, slab_planes=sp).eval(x), ua)
+    bare = gs.Plan("coulomb3d", n=n, L=L, padding=3, workspace=False)
+    u3 = torch.empty_like(x)
+    bare._stream()
+    assert lib().gs_eval_static(bare._h, C.c_void_p(x.data_ptr()), C.c_void_p(u3.data_ptr())) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(u3, ua)
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipEventCreateWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_uint]
+    hip.hipEventDestroy.argtypes = [C.c_void_p]
+    ev = []
+    for _ in range(len(plan.steps()) + 1):
+        e = C.c_void_p()
+        assert hip.hipEventCreateWithFlags(C.byref(e), 0x20000000) == 0
+        ev.append(e)
+    u4 = torch.empty_like(x)
+    plan.eval_events(x, u4, ev)
+    torch.cuda.synchronize()
+    assert torch.equal(u4, ua)
+    for e in ev:
+        hip.hipEventDestroy(e)
+    other = gs.Plan("coulomb3d", n=16, L=3.0)
+    y = cuda(rng.standard_normal((16, 16, 16)))
+    with pytest.raises(gs.GSError):
+        gs.Batch([plan, other], schedule="queue")
+    b = gs.Batch([plan, other], schedule="auto")
+    outs = b.eval([x, y])
+    torch.cuda.synchronize()
+    assert b.info["schedule"] == "sequential"
+    assert torch.equal(outs[0], ua) and torch.equal(outs[1], other.eval(y))
+
+
+def test_mixture_gradient_and_autotune():
+    n, L, K = 32, 8.0, 5
+    plan = gs.Plan("coulomb3d", n=n, L=L, padding=3)
+    rng = np.random.default_rng(51)
+    t = lambda v: torch.tensor(v, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    a, mu, s = t(rng.uniform(-1, 1, K)), t(rng.uniform(-2, 2, (K, 3))), t(rng.uniform(0.6, 1.4, K))
+    rho = plan.mixture_density(a, mu, s)
+    assert torch.equal(rho, gs.Plan("coulomb3d", n=n, L=L).mixture_density(a, mu, s))
+    E = gs.mixture_energy(a, mu, s, plan)
+    g = torch.autograd.grad(E, (a, mu, s))
+    Eo, ga, gmu, gsig = oracle.energy_gradient_params(oracle.make_plan("coulomb3d", 3, n, L, padding=3),
+                                                      a.detach().cpu().numpy(), mu.detach().cpu().numpy(),
+                                                      s.detach().cpu().numpy())
+    got = np.concatenate([x.cpu().numpy().ravel() for x in g])
+    go = np.concatenate([ga, gmu.ravel(), gsig])
+    assert abs(float(E) - Eo) <= 1e-12 * abs(Eo)
+    assert np.max(np.abs(got - go)) <= 1e-12 * np.max(np.abs(go))
+    tuned = gs.Plan("coulomb3d", n=128, L=10.0, padding=3, autotune=True)
+    x = cuda(rng.standard_normal((128, 128, 128)))
+    assert torch.equal(tuned.eval(x), gs.Plan("coulomb3d", n=128, L=10.0, padding=3).eval(x))

@@ -12,23 +12,23 @@ from oracle.factors import factor_1d
 def _octant_ref(op):
     """The library's stored octant, indexed [kx][ky]([kz]) (axes reversed from the
     oracle's array-order G), with the Taylor terms and 1/M folded in."""
-    d = op.d
+    d, p = op.d, op.padding
     lap = 0.0
     even = True
     for i in range(d):                          # octant axis i = array axis d-1-i
         m = op.ns[d - 1 - i]
-        xi = oracle.padded_frequencies(m, op.Ls[d - 1 - i])[: m + 1]
+        xi = oracle.padded_frequencies(m, op.Ls[d - 1 - i], p=p)[: p * m // 2 + 1]
         lap = lap + np.expand_dims(xi ** 2, tuple(j for j in range(d) if j != i))
-        even = even & np.expand_dims(np.arange(m + 1) % 2 == 0, tuple(j for j in range(d) if j != i))
+        even = even & np.expand_dims(np.arange(p * m // 2 + 1) % p == 0, tuple(j for j in range(d) if j != i))
     if op.laplacian == "unpadded":
-        # the n-point grid's frequencies are the padded grid's all-even indices (same xi);
-        # its transform is the padded one there, and 1/M carries 2^d more points
-        lap = lap * np.where(even, 2.0 ** d, 0.0)
+        # the n-point grid's frequencies are the padded grid's indices divisible by p (same
+        # xi); its transform is the padded one there, and 1/M carries p^d more points
+        lap = lap * np.where(even, float(p) ** d, 0.0)
     G = op.G_oct.transpose(tuple(range(d - 1, -1, -1)))
     S = (G + op.A0 - op.c2 * lap) / op.M
     if op.kernel == "davey_stewartson2d":          # times -xi_x^2 along octant axis 0 (x)
         m = op.ns[d - 1]
-        xi = oracle.padded_frequencies(m, op.Ls[d - 1])[: m + 1]
+        xi = oracle.padded_frequencies(m, op.Ls[d - 1], p=p)[: p * m // 2 + 1]
         S = S * -(xi ** 2)[:, None]
     return S
 
@@ -42,9 +42,11 @@ def _factors_and_constants(p, kernel, d, n, beta=None):
     is about 1e-6 delta^4, a difference of moments of size delta^4."""
     from oracle.taylor import taylor_constants
     w, tau = p.table()
+    pad = p.padding
     for ax in range(d):
         Lj = p.Ls[ax]
-        assert np.max(np.abs(p.factors(ax) - factor_1d(tau, 2.0 * Lj, p.ns[ax]))) <= 4e-16 * 4 * Lj
+        ref = factor_1d(tau, 2.0 * Lj, pad * p.ns[ax] // 2, pad)
+        assert np.max(np.abs(p.factors(ax) - ref)) <= 4e-16 * 4 * Lj
     if kernel == "gaussian_sum":
         return
     dl = p.info["delta"]
@@ -176,3 +178,34 @@ def test_host_plan_unpadded_laplacian(kernel, d, n, L, eps):
     assert not np.array_equal(S, pp.spectrum())
     with pytest.raises(gs.GSError):
         gs.Plan("dipolar3d", n=16, L=4.0, dipole=((1, 0, 0), (0, 1, 0)), host_only=True, laplacian="unpadded")
+
+
+@pytest.mark.parametrize("kernel,d,n,L,eps,lap", [("coulomb3d", 3, 16, 6.0, 1e-14, "padded"),
+                                                  ("poisson2d", 2, (64, 32), (8.0, 4.0), 1e-13, "padded"),
+                                                  ("coulomb2d", 2, 64, 7.0, 1e-14, "unpadded"),
+                                                  ("dipolar3d", 3, (8, 16, 32), (2.0, 4.0, 8.0), 1e-14, "padded"),
+                                                  ("davey_stewartson2d", 2, 32, 5.0, 1e-13, "padded"),
+                                                  ("inverse_power", 3, 16, 4.0, 1e-14, "unpadded")])
+def test_host_plan_padding3(kernel, d, n, L, eps, lap):
+    """Padding to B_3: factors at xi_k = pi k / (3 L_j), k = 0..3 n_j / 2 (integrals still over
+    [-2 L_j, 2 L_j]), the octant of 3 n_j / 2 + 1 values per axis with 1/prod_j (3 n_j)
+    folded in (and the unpadded-grid Laplacian at indices divisible by 3), against the
+    oracle; odd n and an uncompiled 3 n / 2 are refused."""
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    if kernel == "inverse_power":
+        kw = {"beta": 1.4}
+    p = gs.Plan(kernel, n=n, L=L, eps=eps, d=d, host_only=True, padding=3, laplacian=lap, **kw)
+    op = oracle.make_plan(kernel, d, n, L, eps=eps, padding=3, laplacian=lap, **kw)
+    assert p.info["padding"] == 3 and p.info["S"] == op.table.S
+    _factors_and_constants(p, kernel, d, n, beta=kw.get("beta"))
+    S, ref = p.spectrum(), _octant_ref(op)
+    if kernel == "davey_stewartson2d":
+        m = op.ns[-1]
+        xi2 = oracle.padded_frequencies(m, op.Ls[-1], p=3)[1: 3 * m // 2 + 1, None] ** 2
+        assert np.all(S[0] == 0.0)
+        S, ref = S[1:] / -xi2, ref[1:] / -xi2
+    assert np.max(np.abs(S - ref)) <= 1e-13 * np.max(np.abs(ref))
+    with pytest.raises(gs.GSError):
+        gs.Plan("coulomb3d", n=12, L=3.0, host_only=True, padding=3)        # 18: not compiled
+    with pytest.raises(gs.GSError):
+        gs.Plan("coulomb2d", n=(16, 9), L=3.0, host_only=True, padding=3)   # odd n
