@@ -54,8 +54,9 @@ template <bool INV> __device__ __forceinline__ cpx mul_mi(cpx a) {
 }
 
 // ---------------------------------------------------------------------------
-// Exact unit roots exp(-2 pi i e / R) for R dividing 96 (radices 2,3,4,6,8,12,16
-// and the padding twists of 16, 24, 32 and 48 points).
+// Unit roots exp(-2 pi i e / R), correctly rounded, for R dividing 96 (radices
+// 2,3,4,6,8,12,16 and the padding twists of 16, 24, 32 and 48 points), 40 (radices 5
+// and 10, the twists of 20 points) or 56 (radices 7 and 14, the twists of 28 points).
 // ---------------------------------------------------------------------------
 struct CS { double c, s; };
 
@@ -81,11 +82,51 @@ constexpr CS first_quadrant(int a) {
                    : CS{2.0, 2.0};   // unreachable for the supported radices
 }
 
+// cos and sin of a*pi/20, a in [0, 10]
+constexpr CS first_quadrant20(int a) {
+    return a == 0  ? CS{1.0, 0.0}
+         : a == 1  ? CS{0.98768834059513772619, 0.15643446504023086901}
+         : a == 2  ? CS{0.951056516295153572116, 0.309016994374947424102}
+         : a == 3  ? CS{0.89100652418836786236, 0.45399049973954679156}
+         : a == 4  ? CS{0.809016994374947424102, 0.587785252292473129169}
+         : a == 5  ? CS{0.707106781186547524401, 0.707106781186547524401}
+         : a == 6  ? CS{0.587785252292473129169, 0.809016994374947424102}
+         : a == 7  ? CS{0.45399049973954679156, 0.89100652418836786236}
+         : a == 8  ? CS{0.309016994374947424102, 0.951056516295153572116}
+         : a == 9  ? CS{0.15643446504023086901, 0.98768834059513772619}
+         : a == 10 ? CS{0.0, 1.0}
+                   : CS{2.0, 2.0};
+}
+
+// cos and sin of a*pi/28, a in [0, 14]
+constexpr CS first_quadrant28(int a) {
+    return a == 0  ? CS{1.0, 0.0}
+         : a == 1  ? CS{0.993712209893242583533, 0.111964476103307858469}
+         : a == 2  ? CS{0.974927912181823607018, 0.222520933956314404289}
+         : a == 3  ? CS{0.943883330308367562895, 0.330279061955167081775}
+         : a == 4  ? CS{0.900968867902419126236, 0.433883739117558120476}
+         : a == 5  ? CS{0.846724199228284168353, 0.532032076515336563558}
+         : a == 6  ? CS{0.781831482468029808708, 0.623489801858733530525}
+         : a == 7  ? CS{0.707106781186547524401, 0.707106781186547524401}
+         : a == 8  ? CS{0.623489801858733530525, 0.781831482468029808708}
+         : a == 9  ? CS{0.532032076515336563558, 0.846724199228284168353}
+         : a == 10 ? CS{0.433883739117558120476, 0.900968867902419126236}
+         : a == 11 ? CS{0.330279061955167081775, 0.943883330308367562895}
+         : a == 12 ? CS{0.222520933956314404289, 0.974927912181823607018}
+         : a == 13 ? CS{0.111964476103307858469, 0.993712209893242583533}
+         : a == 14 ? CS{0.0, 1.0}
+                   : CS{2.0, 2.0};
+}
+
+// Angle unit pi / B of the table that holds the roots of order R (0: none)
+constexpr int root_base(int R) { return 96 % R == 0 ? 48 : 40 % R == 0 ? 20 : 56 % R == 0 ? 28 : 0; }
+
 // cos/sin of 2 pi e / R
 constexpr CS unit_root(int e, int R) {
-    int a = ((e % R + R) % R) * (96 / R);     // angle = a * pi / 48, a in [0, 96)
-    int q = a / 24, r = a % 24;
-    CS b = first_quadrant(r);
+    const int B = root_base(R), Q = B / 2;
+    int a = ((e % R + R) % R) * (2 * B / R);  // angle = a * pi / B, a in [0, 2B)
+    int q = a / Q, r = a % Q;
+    CS b = B == 48 ? first_quadrant(r) : B == 20 ? first_quadrant20(r) : first_quadrant28(r);
     return q == 0 ? CS{b.c, b.s} : q == 1 ? CS{-b.s, b.c} : q == 2 ? CS{-b.c, -b.s} : CS{b.s, -b.c};
 }
 
@@ -100,6 +141,7 @@ template <int E, int R, bool INV> __device__ __forceinline__ cpx twiddle_const(c
         else if constexpr (quarter == 2) return cmk(-x.x, -x.y);
         else return mul_mi<!INV>(x);
     } else {
+        static_assert(root_base(R) != 0, "unit roots of this order are not tabulated");
         constexpr CS w = unit_root(e, R);
         // forward: exp(-i theta) = c - i s; inverse: c + i s
         constexpr double s = INV ? w.s : -w.s;
@@ -146,6 +188,57 @@ template <int S, bool INV> struct Dft<4, S, INV> {
     }
 };
 
+// Five points: X_k = x0 + sum_j x_j W^{jk}.  With t1 = x1 + x4, t2 = x2 + x3, t3 = x1 - x4,
+// t4 = x2 - x3 and c_m, s_m the cosine and sine of 2 pi m / 5:
+//   X1, X4 = x0 + c1 t1 + c2 t2 -+ i (s1 t3 + s2 t4)
+//   X2, X3 = x0 + c2 t1 + c1 t2 -+ i (s2 t3 - s1 t4)      (forward; signs of i swapped inverse)
+template <int S, bool INV> struct Dft<5, S, INV> {
+    __device__ __forceinline__ static void run(cpx* v) {
+        constexpr double c1 = 0.309016994374947424102, s1 = 0.951056516295153572116;
+        constexpr double c2 = -0.809016994374947424102, s2 = 0.587785252292473129169;
+        const cpx x0 = v[0];
+        const cpx t1 = cadd(v[S], v[4 * S]), t3 = csub(v[S], v[4 * S]);
+        const cpx t2 = cadd(v[2 * S], v[3 * S]), t4 = csub(v[2 * S], v[3 * S]);
+        const cpx a1 = cmk(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
+        const cpx a2 = cmk(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
+        const cpx b1 = mul_mi<INV>(cmk(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+        const cpx b2 = mul_mi<INV>(cmk(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+        v[0] = cadd(x0, cadd(t1, t2));
+        v[S] = cadd(a1, b1);
+        v[4 * S] = csub(a1, b1);
+        v[2 * S] = cadd(a2, b2);
+        v[3 * S] = csub(a2, b2);
+    }
+};
+
+// Seven points, the same pairing: t_m = x_m + x_{7-m}, d_m = x_m - x_{7-m} (m = 1, 2, 3),
+//   X_k, X_{7-k} = x0 + sum_m cos(2 pi m k / 7) t_m -+ i sum_m sin(2 pi m k / 7) d_m.
+template <int S, bool INV> struct Dft<7, S, INV> {
+    __device__ __forceinline__ static void run(cpx* v) {
+        constexpr double c1 = 0.623489801858733530525, s1 = 0.781831482468029808708;
+        constexpr double c2 = -0.222520933956314404289, s2 = 0.974927912181823607018;
+        constexpr double c3 = -0.900968867902419126236, s3 = 0.433883739117558120476;
+        const cpx x0 = v[0];
+        const cpx t1 = cadd(v[S], v[6 * S]), d1 = csub(v[S], v[6 * S]);
+        const cpx t2 = cadd(v[2 * S], v[5 * S]), d2 = csub(v[2 * S], v[5 * S]);
+        const cpx t3 = cadd(v[3 * S], v[4 * S]), d3 = csub(v[3 * S], v[4 * S]);
+        // cos(2 pi m k / 7) and sin(2 pi m k / 7) for k = 1, 2, 3 (mk reduced mod 7)
+        const cpx a1 = cmk(x0.x + c1 * t1.x + c2 * t2.x + c3 * t3.x, x0.y + c1 * t1.y + c2 * t2.y + c3 * t3.y);
+        const cpx a2 = cmk(x0.x + c2 * t1.x + c3 * t2.x + c1 * t3.x, x0.y + c2 * t1.y + c3 * t2.y + c1 * t3.y);
+        const cpx a3 = cmk(x0.x + c3 * t1.x + c1 * t2.x + c2 * t3.x, x0.y + c3 * t1.y + c1 * t2.y + c2 * t3.y);
+        const cpx b1 = mul_mi<INV>(cmk(s1 * d1.x + s2 * d2.x + s3 * d3.x, s1 * d1.y + s2 * d2.y + s3 * d3.y));
+        const cpx b2 = mul_mi<INV>(cmk(s2 * d1.x - s3 * d2.x - s1 * d3.x, s2 * d1.y - s3 * d2.y - s1 * d3.y));
+        const cpx b3 = mul_mi<INV>(cmk(s3 * d1.x - s1 * d2.x + s2 * d3.x, s3 * d1.y - s1 * d2.y + s2 * d3.y));
+        v[0] = cadd(x0, cadd(t1, cadd(t2, t3)));
+        v[S] = cadd(a1, b1);
+        v[6 * S] = csub(a1, b1);
+        v[2 * S] = cadd(a2, b2);
+        v[5 * S] = csub(a2, b2);
+        v[3 * S] = cadd(a3, b3);
+        v[4 * S] = csub(a3, b3);
+    }
+};
+
 // DFT of length R1*R2 by one Cooley-Tukey split: j = R2 j1 + j2, k = k1 + R1 k2.
 template <int R1, int R2, int S, bool INV> struct DftComposite {
     static constexpr int R = R1 * R2;
@@ -187,6 +280,12 @@ template <int S, bool INV> struct Dft<12, S, INV> {
 template <int S, bool INV> struct Dft<16, S, INV> {
     __device__ __forceinline__ static void run(cpx* v) { DftComposite<4, 4, S, INV>::run(v); }
 };
+template <int S, bool INV> struct Dft<10, S, INV> {
+    __device__ __forceinline__ static void run(cpx* v) { DftComposite<2, 5, S, INV>::run(v); }
+};
+template <int S, bool INV> struct Dft<14, S, INV> {
+    __device__ __forceinline__ static void run(cpx* v) { DftComposite<2, 7, S, INV>::run(v); }
+};
 
 // ---------------------------------------------------------------------------
 // Transform plans: length N carried by G = N/E threads with E values each, the
@@ -216,6 +315,17 @@ template <> struct FftCfg<256> : FftPlan<256, 16, 2, 16, 16> {};
 template <> struct FftCfg<512> : FftPlan<512, 8, 3, 8, 8, 8> {};
 template <> struct FftCfg<1024> : FftPlan<1024, 16, 3, 16, 16, 4> {};
 template <> struct FftCfg<2048> : FftPlan<2048, 16, 3, 16, 16, 8> {};
+// 5-smooth and 7-smooth lengths: 20 or 28 values per thread
+template <> struct FftCfg<20> : FftPlan<20, 20, 2, 4, 5> {};
+template <> struct FftCfg<40> : FftPlan<40, 20, 2, 4, 10> {};
+template <> struct FftCfg<80> : FftPlan<80, 20, 3, 4, 4, 5> {};
+template <> struct FftCfg<160> : FftPlan<160, 20, 3, 4, 4, 10> {};
+template <> struct FftCfg<320> : FftPlan<320, 20, 4, 4, 4, 4, 5> {};
+template <> struct FftCfg<640> : FftPlan<640, 20, 4, 4, 4, 4, 10> {};
+template <> struct FftCfg<28> : FftPlan<28, 28, 2, 4, 7> {};
+template <> struct FftCfg<56> : FftPlan<56, 28, 2, 4, 14> {};
+template <> struct FftCfg<112> : FftPlan<112, 28, 3, 4, 4, 7> {};
+template <> struct FftCfg<224> : FftPlan<224, 28, 3, 4, 4, 14> {};
 
 // Plans for the fused spectrum pass, whose registers also hold the spectrum row:
 // fewer values per thread where that matters (n = 256: 8 values, radices 8, 8, 4,

@@ -61,7 +61,7 @@ def test_argument_validation_statuses():
     assert _create(kernel=9)[0] == 1
     assert _create(L=-1.0)[0] == 1
     assert _create(eps=0.0)[0] == 1
-    assert _create(n=20)[0] == 2                         # no kernels for n = 20
+    assert _create(n=22)[0] == 2                         # no kernels for n = 22 (a factor 11)
     assert _create(n=4096)[0] == 2
     assert _create(eps=1e-20)[0] == 3                    # below the table floor
     assert _create(kernel=2, d=2, eps=1e-15)[0] == 3     # ln-table rounding floor
@@ -73,8 +73,8 @@ def test_argument_validation_statuses():
     assert _create(kernel=6, d=2, beta=2.0)[0] == 1      # beta must be below d
     st, h = _create(kernel=6, d=3, beta=1.5)
     assert st == 0 and _lib.lib().gs_plan_destroy(h) == 0
-    assert _create(nlist=[16, 20, 32])[0] == 2           # every axis' n must be compiled
-    assert "n = 20" in _lib.lib().gs_last_error().decode()
+    assert _create(nlist=[16, 22, 32])[0] == 2           # every axis' n must be compiled
+    assert "n = 22" in _lib.lib().gs_last_error().decode()
     assert _create(nlist=[16, 1, 32])[0] == 1            # and at least 2
     assert _create(L=(4.0, 4.0, -1.0))[0] == 1
     assert _create(L=(1e-4, 4.0, 4.0))[0] == 1           # near-field ball wider than the short axis
@@ -135,6 +135,8 @@ def test_status_strings_and_sizes():
         assert L.gs_status_string(s).decode() == name
     s3, s2 = gs.supported_sizes(3), gs.supported_sizes(2)
     assert 256 in s3 and 2048 not in s3 and 2048 in s2 and s3 == sorted(s3)
+    # 5-smooth and 7-smooth lengths (radix-5 and radix-7 stages)
+    assert {20, 40, 80, 160, 320, 640, 28, 56, 112, 224} <= set(s3)
 
 
 def test_plan_query_fields():

@@ -62,7 +62,9 @@ CASES = [("coulomb3d", 3, 16, 8.0, 1e-14), ("coulomb3d", 3, 24, 10.0, 1e-14), ("
          ("coulomb2d", 2, 48, (0.75, 12.0), 1e-14), ("poisson2d", 2, 32, (6.0, 9.0), 1e-13),
          ("dipolar3d", 3, 12, (5.0, 4.0, 3.0), 1e-14),
          # Davey-Stewartson (Example 4.5), cube and rectangle
-         ("davey_stewartson2d", 2, 64, 8.0, 1e-13), ("davey_stewartson2d", 2, 32, (5.0, 3.0), 1e-13)]
+         ("davey_stewartson2d", 2, 64, 8.0, 1e-13), ("davey_stewartson2d", 2, 32, (5.0, 3.0), 1e-13),
+         # transform lengths with factors 5 and 7
+         ("coulomb3d", 3, 20, 5.0, 1e-14), ("poisson2d", 2, 320, 12.0, 1e-13), ("coulomb2d", 2, 56, 7.0, 1e-14)]
 
 
 @pytest.mark.parametrize("kernel,d,n,L,eps", CASES)
