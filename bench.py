@@ -553,6 +553,10 @@ def batched_figures(gs, torch, workloads, reps: int = 10):
                      ("phased", dict(schedule="phased")),
                      ("sized", dict(schedule="sized")),
                      ("sized_graph", dict(schedule="sized", graph=True)),
+                     ("concurrent", dict(schedule="concurrent")),
+                     ("concurrent_graph", dict(schedule="concurrent", graph=True)),
+                     ("streams", dict(schedule="streams")),
+                     ("streams_graph", dict(schedule="streams", graph=True)),
                      ("queue", dict(schedule="queue")),
                      ("queue_graph", dict(schedule="queue", graph=True)),
                      ("auto_graph", dict(schedule="auto", graph=True))]:

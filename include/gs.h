@@ -330,9 +330,17 @@ gs_status gs_eval_backward(gs_plan p, const double* grad_u_dev, double* grad_rho
  *                       specialised to its size).
  *   GS_SCHED_SEQUENTIAL each plan's own gs_eval launches, one problem after the
  *                       other (the unbatched baseline).
+ *   GS_SCHED_CONCURRENT the launches of GS_SCHED_SIZED, each grid size's chain of
+ *                       passes on its own stream (four streams forked from the
+ *                       batch stream and joined back), the sizes running at the
+ *                       same time.
+ *   GS_SCHED_STREAMS    each plan's own gs_eval launches, the plans (largest first)
+ *                       dealt round-robin to four concurrent streams; any plans
+ *                       (no batched kernels needed).
  *   GS_SCHED_AUTO       the fastest of the others (and of their task sizes) for
  *                       this device and multiset of problem shapes, measured on
- *                       the first gs_batch_eval and cached in the process and,
+ *                       the first gs_batch_eval (as graph replays when use_graph
+ *                       is set) and cached in the process and,
  *                       if the environment variable GS_AUTOTUNE_CACHE names a
  *                       file, in that JSON file across processes.
  */
@@ -341,7 +349,9 @@ typedef enum {
     GS_SCHED_QUEUE = 1,
     GS_SCHED_PHASED = 2,
     GS_SCHED_SEQUENTIAL = 3,
-    GS_SCHED_SIZED = 4
+    GS_SCHED_SIZED = 4,
+    GS_SCHED_CONCURRENT = 5,
+    GS_SCHED_STREAMS = 6
 } gs_schedule;
 
 typedef struct gs_batch_s* gs_batch;

@@ -346,7 +346,9 @@ class Batch:
     schedule: "auto" (measured on the first eval, cached; GS_AUTOTUNE_CACHE names a
     JSON file to keep it across processes), "queue" (one persistent launch),
     "phased" (one launch per pass type), "sized" (one launch per pass type and grid
-    size) or "sequential" (each plan's own eval).
+    size), "concurrent" (the sized launches, each grid size's chain on its own stream),
+    "sequential" (each plan's own eval) or "streams" (each plan's own eval, the plans
+    dealt to four concurrent streams).
     graph=True captures the launch sequence in a hipGraph and replays it.
     Every schedule gives each problem bitwise the result of plan.eval.
     """

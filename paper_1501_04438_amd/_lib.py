@@ -41,7 +41,7 @@ class GSPlanInfo(C.Structure):
                 ("padding", C.c_int)]
 
 
-SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3, "sized": 4}
+SCHEDULES = {"auto": 0, "queue": 1, "phased": 2, "sequential": 3, "sized": 4, "concurrent": 5, "streams": 6}
 
 
 class GSBatchOptions(C.Structure):

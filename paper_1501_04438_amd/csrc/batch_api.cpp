@@ -49,9 +49,19 @@ struct gs_batch_s {
     bool staged_pending = false;
     hipGraphExec_t exec = nullptr;
     std::vector<const void*> graph_sig;   // what the captured launches baked in
+    // the concurrent schedules: side streams forked from `own` and joined back into it
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_done;
+    hipEvent_t ev_fork = nullptr;
 };
 
 namespace {
+
+// Side streams of the concurrent schedules (the device's default number of hardware queues).
+constexpr int kSideStreams = 4;
+
+// Schedules that run each plan's own launches (no batched kernels, no task list).
+bool own_launches(int schedule) { return schedule == GS_SCHED_SEQUENTIAL || schedule == GS_SCHED_STREAMS; }
 
 // Polls of a dependency wait before it gives up (about 2 us each: seconds in all,
 // orders of magnitude beyond the longest task).
@@ -70,6 +80,9 @@ bool batch_live(gs_batch b) {
 void release(gs_batch_s* b) {
     DeviceScope ds(b->device);
     if (b->own) (void)hipStreamSynchronize(b->own);
+    for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : b->side_done) (void)hipEventDestroy(ev);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->d_probs) (void)hipFree(b->d_probs);
     if (b->d_tasks) (void)hipFree(b->d_tasks);
@@ -191,15 +204,93 @@ int launch_grid(const gs_batch_s* b, const TuneEntry& c) {
     return grid;
 }
 
+// Creates the side streams on first use (default priority, non-blocking) and forks them from
+// the batch stream: work queued on them after this runs after everything queued on `own`.
+hipError_t fork_side(gs_batch_s* b) {
+    hipError_t e = hipSuccess;
+    if (b->side.empty()) {
+        b->side.assign(kSideStreams, nullptr);
+        b->side_done.assign(kSideStreams, nullptr);
+        for (int i = 0; i < kSideStreams && e == hipSuccess; ++i)
+            e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+        for (int i = 0; i < kSideStreams && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&b->side_done[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    if ((e = hipEventRecord(b->ev_fork, b->own)) != hipSuccess) return e;
+    for (hipStream_t st : b->side)
+        if ((e = hipStreamWaitEvent(st, b->ev_fork, 0)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// Joins the side streams back into the batch stream.
+hipError_t join_side(gs_batch_s* b) {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) {
+        if ((e = hipEventRecord(b->side_done[i], b->side[i])) == hipSuccess)
+            e = hipStreamWaitEvent(b->own, b->side_done[i], 0);
+    }
+    return e;
+}
+
+// GS_SCHED_CONCURRENT: the sized launches of each grid size, in pass order, on side stream
+// (size class index mod kSideStreams).
+hipError_t launch_concurrent(gs_batch_s* b) {
+    hipError_t e = fork_side(b);
+    if (e != hipSuccess) return e;
+    std::vector<int> sizes;                         // size classes in order of appearance
+    for (size_t i = 0; i + 3 < b->runs.size(); i += 4)
+        if (std::find(sizes.begin(), sizes.end(), b->runs[i + 1]) == sizes.end()) sizes.push_back(b->runs[i + 1]);
+    for (size_t c = 0; c < sizes.size() && e == hipSuccess; ++c) {
+        std::vector<int> mine;
+        for (size_t i = 0; i + 3 < b->runs.size(); i += 4)
+            if (b->runs[i + 1] == sizes[c]) mine.insert(mine.end(), b->runs.begin() + i, b->runs.begin() + i + 4);
+        e = gsk::launch_batch_sized(b->d_probs, b->d_tasks, mine, b->side[c % kSideStreams]);
+    }
+    const hipError_t j = join_side(b);
+    return e != hipSuccess ? e : j;
+}
+
+// GS_SCHED_STREAMS: each plan's own evaluation launches, the plans (largest first) dealt
+// round-robin to the side streams.
+gs_status launch_streams(gs_batch_s* b, const double* const* rho, double* const* u) {
+    hipError_t e = fork_side(b);
+    if (e != hipSuccess) return hip_fail(e, "batch stream fork");
+    std::vector<int> order(b->plans.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    auto pts = [&](int i) {
+        const gs_plan p = b->plans[i];
+        return (double)p->nc[0] * p->nc[1] * (p->d == 3 ? p->nc[2] : 1);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pts(x) > pts(y); });
+    gs_status st = GS_OK;
+    for (size_t k = 0; k < order.size() && st == GS_OK; ++k) {
+        const int i = order[k];
+        gs_plan p = b->plans[i];
+        const hipStream_t keep = p->stream;
+        p->stream = b->side[k % kSideStreams];
+        st = eval_chain(p, rho[i], u[i], -1);
+        p->stream = keep;
+    }
+    e = join_side(b);
+    if (st != GS_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "batch stream join");
+    return GS_OK;
+}
+
 gs_status launch(gs_batch_s* b, const TuneEntry& c, const double* const* rho, double* const* u) {
     hipError_t e = hipSuccess;
     const int grid = launch_grid(b, c);
+    if (c.schedule == GS_SCHED_STREAMS) return launch_streams(b, rho, u);
     if (c.schedule == GS_SCHED_QUEUE) {
         e = gsk::launch_batch_queue(b->d_probs, b->d_tasks, b->queues, b->d_ctr, b->nctr, grid, kSpinLimit, b->own);
     } else if (c.schedule == GS_SCHED_PHASED) {
         e = gsk::launch_batch_phased(b->d_probs, b->d_tasks, b->pass_off, b->pass_cnt, grid, b->own);
     } else if (c.schedule == GS_SCHED_SIZED) {
         e = gsk::launch_batch_sized(b->d_probs, b->d_tasks, b->runs, b->own);
+    } else if (c.schedule == GS_SCHED_CONCURRENT) {
+        e = launch_concurrent(b);
     } else {
         for (size_t i = 0; i < b->plans.size(); ++i) {
             gs_plan p = b->plans[i];
@@ -229,18 +320,41 @@ std::string shape_key(const gs_batch_s* b) {
 
 gs_status time_candidate(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const TuneEntry& c,
                          const double* const* rho, double* const* u, double& ms) {
-    if (c.schedule != GS_SCHED_SEQUENTIAL) {
+    if (!own_launches(c.schedule)) {
         const gs_status st = upload_tasks(b, m, c.tiles_per_task, c.largest_first, c.schedule);
         if (st != GS_OK) return st;
     }
+    // a batch that replays a graph times each candidate as a graph replay (launch costs
+    // differ most between the schedules there)
+    hipGraphExec_t ex = nullptr;
+    if (b->req.use_graph) {
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        const gs_status cst = launch(b, c, rho, u);
+        e = hipStreamEndCapture(b->own, &g);
+        if (cst != GS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return cst;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    }
+    auto run = [&]() -> gs_status {
+        if (!ex) return launch(b, c, rho, u);
+        const hipError_t e = hipGraphLaunch(ex, b->own);
+        return e == hipSuccess ? GS_OK : hip_fail(e, "hipGraphLaunch");
+    };
     hipEvent_t t0 = nullptr, t1 = nullptr;
     (void)hipEventCreate(&t0);
     (void)hipEventCreate(&t1);
-    gs_status st = launch(b, c, rho, u);          // warm-up
+    gs_status st = run();                         // warm-up
     ms = 1e300;
     for (int r = 0; r < 3 && st == GS_OK; ++r) {
         (void)hipEventRecord(t0, b->own);
-        st = launch(b, c, rho, u);
+        st = run();
         (void)hipEventRecord(t1, b->own);
         const hipError_t e = hipEventSynchronize(t1);
         if (e != hipSuccess) st = hip_fail(e, "autotune timing");
@@ -250,14 +364,18 @@ gs_status time_candidate(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, 
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
+    if (ex) {
+        (void)hipStreamSynchronize(b->own);
+        (void)hipGraphExecDestroy(ex);
+    }
     return st;
 }
 
 gs_status autotune(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const double* const* rho,
                    double* const* u) {
-    const std::string key = tune_device_key(b->device) + "|batch|" + shape_key(b);
+    const std::string key = tune_device_key(b->device) + "|batch|" + shape_key(b) + (b->req.use_graph ? "|graph" : "");
     TuneEntry best;
-    if (tune_lookup(key, best) && (best.schedule == GS_SCHED_SEQUENTIAL || b->kernels_ok)) {
+    if (tune_lookup(key, best) && (own_launches(best.schedule) || b->kernels_ok)) {
         b->cfg = best;
         b->autotuned = true;
         b->tuned_ms = best.ms;
@@ -270,8 +388,10 @@ gs_status autotune(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const 
         for (int mult : {4, 16, 64}) cand.push_back({GS_SCHED_QUEUE, mult, 1, 0, 0.0});
         for (int mult : {1, 4, 16}) cand.push_back({GS_SCHED_PHASED, mult, 1, 0, 0.0});
         for (int mult : {1, 4}) cand.push_back({GS_SCHED_SIZED, mult, 1, 0, 0.0});
+        for (int mult : {1, 4}) cand.push_back({GS_SCHED_CONCURRENT, mult, 1, 0, 0.0});
     }
     cand.push_back({GS_SCHED_SEQUENTIAL, 1, 1, 0, 0.0});
+    cand.push_back({GS_SCHED_STREAMS, 1, 1, 0, 0.0});
     best.ms = 1e300;
     for (TuneEntry c : cand) {
         double ms = 0.0;
@@ -307,7 +427,7 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
     gs_batch_options_default(&opt);
     if (opt_in) opt = *opt_in;
     if (count < 1 || !plans) return fail(GS_ERR_INVALID_ARG, "invalid batch arguments");
-    if (opt.schedule < GS_SCHED_AUTO || opt.schedule > GS_SCHED_SIZED || opt.tiles_per_task < 0 || opt.grid < 0)
+    if (opt.schedule < GS_SCHED_AUTO || opt.schedule > GS_SCHED_STREAMS || opt.tiles_per_task < 0 || opt.grid < 0)
         return fail(GS_ERR_INVALID_ARG, "invalid batch options");
     std::unordered_set<gs_plan> seen;
     bool kernels_ok = true;
@@ -318,14 +438,16 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
         if (!seen.insert(p).second) return fail(GS_ERR_INVALID_ARG, "a plan appears twice in the batch");
         if (p->device != plans[0]->device) return fail(GS_ERR_INVALID_ARG, "batch spans devices");
         if (!p->cube || p->pad != 2 || !gsk::batch_size_supported(p->d, p->n)) {
-            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED)
+            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED ||
+                opt.schedule == GS_SCHED_CONCURRENT)
                 return fail(GS_ERR_UNSUPPORTED_SIZE,
                             "batched kernels cover grids padded to twice their box with the same n <= 128 of "
                             "the compiled list on every axis");
             kernels_ok = false;
         }
         if (p->nslabs != 1) {
-            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED)
+            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED ||
+                opt.schedule == GS_SCHED_CONCURRENT)
                 return fail(GS_ERR_INVALID_ARG, "a batched plan must run its middle passes in one slab");
             kernels_ok = false;
         }
@@ -382,7 +504,7 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
         // acquire per task, so its tasks are larger
         const int def = opt.schedule == GS_SCHED_QUEUE ? kQueueTilesPerTask : 4;
         b->cfg = {opt.schedule, opt.tiles_per_task > 0 ? opt.tiles_per_task : def, 1, opt.grid, 0.0};
-        if (opt.schedule != GS_SCHED_SEQUENTIAL) st = upload_tasks(b, m, b->cfg.tiles_per_task, 1, opt.schedule);
+        if (!own_launches(opt.schedule)) st = upload_tasks(b, m, b->cfg.tiles_per_task, 1, opt.schedule);
         b->resolved = true;
     }
     if (st != GS_OK) {
@@ -421,7 +543,7 @@ gs_status gs_batch_eval(gs_batch b, const double* const* rho, double* const* u) 
         if ((st = autotune(b, m, rho, u)) != GS_OK) return st;
         b->resolved = true;
     }
-    if (b->cfg.schedule != GS_SCHED_SEQUENTIAL &&
+    if (!own_launches(b->cfg.schedule) &&
         (st = upload_tasks(b, m, b->cfg.tiles_per_task, b->cfg.largest_first, b->cfg.schedule)) != GS_OK)
         return st;
     if (b->req.use_graph) {
@@ -429,7 +551,7 @@ gs_status gs_batch_eval(gs_batch b, const double* const* rho, double* const* u) 
         // schedule the rho / u pointers themselves
         std::vector<const void*> sig = {b->d_tasks, (const void*)(intptr_t)b->ntasks,
                                         (const void*)(intptr_t)b->cfg.schedule};
-        if (b->cfg.schedule == GS_SCHED_SEQUENTIAL)
+        if (own_launches(b->cfg.schedule))
             for (size_t i = 0; i < b->plans.size(); ++i) {
                 sig.push_back(rho[i]);
                 sig.push_back(u[i]);

@@ -68,7 +68,8 @@ def mixed():
 
 
 @pytest.mark.parametrize("schedule,tpt", [("sequential", 1), ("phased", 1), ("phased", 2), ("sized", 1),
-                                          ("sized", 3), ("queue", 1), ("queue", 3)])
+                                          ("sized", 3), ("queue", 1), ("queue", 3), ("concurrent", 1),
+                                          ("concurrent", 3), ("streams", 1)])
 @pytest.mark.parametrize("graph", [False, True])
 def test_schedules_bitwise_equal_single(mixed, schedule, tpt, graph):
     plans, rhos, refs = mixed
@@ -83,7 +84,7 @@ def test_schedules_bitwise_equal_single(mixed, schedule, tpt, graph):
     info = b.info
     assert info["schedule"] == schedule and info["count"] == len(plans)
     assert info["wait_timeouts"] == 0
-    if schedule != "sequential":
+    if schedule not in ("sequential", "streams"):
         assert info["num_tasks"] == sum(info["tasks_per_pass"])
     if schedule == "queue":
         # one queue per die of the device, problems pinned to a die
@@ -94,7 +95,7 @@ def test_schedules_bitwise_equal_single(mixed, schedule, tpt, graph):
 def test_new_pointers_and_alias(mixed):
     """A second call with other tensors (descriptors re-uploaded, graph kept), then u aliasing rho."""
     plans, rhos, refs = mixed
-    for schedule in ("queue", "phased", "sized"):
+    for schedule in ("queue", "phased", "sized", "concurrent", "streams"):
         b = gs.Batch(plans, schedule=schedule, graph=True)
         b.eval(rhos)
         copies = [r.clone() for r in rhos]
@@ -155,12 +156,15 @@ def test_batch_rejects_bad_input(mixed):
     big = gs.Plan("coulomb3d", n=256, L=10.0)
     with pytest.raises(gs.GSError):
         gs.Batch([plans[0], big], schedule="queue")
-    # the automatic schedule falls back to sequential solves for sizes beyond the batched kernels
+    with pytest.raises(gs.GSError):
+        gs.Batch([plans[0], big], schedule="concurrent")
+    # the automatic schedule falls back to the plans' own solves (in order or on concurrent
+    # streams) for sizes beyond the batched kernels
     b = gs.Batch([plans[0], big], schedule="auto")
     r2 = cuda(np.random.default_rng(1).standard_normal((256,) * 3))
     outs = b.eval([rhos[0], r2])
     torch.cuda.synchronize()
-    assert b.info["schedule"] == "sequential"
+    assert b.info["schedule"] in ("sequential", "streams")
     assert torch.equal(outs[1], big.eval(r2))
 
 

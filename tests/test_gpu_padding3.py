@@ -152,7 +152,7 @@ def test_energy_static_slabs_events_and_batch():
     b = gs.Batch([plan, other], schedule="auto")
     outs = b.eval([x, y])
     torch.cuda.synchronize()
-    assert b.info["schedule"] == "sequential"
+    assert b.info["schedule"] in ("sequential", "streams")
     assert torch.equal(outs[0], ua) and torch.equal(outs[1], other.eval(y))
 
 
