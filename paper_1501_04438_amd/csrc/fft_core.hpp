@@ -315,6 +315,10 @@ template <> struct FftCfg<256> : FftPlan<256, 16, 2, 16, 16> {};
 template <> struct FftCfg<512> : FftPlan<512, 8, 3, 8, 8, 8> {};
 template <> struct FftCfg<1024> : FftPlan<1024, 16, 3, 16, 16, 4> {};
 template <> struct FftCfg<2048> : FftPlan<2048, 16, 3, 16, 16, 8> {};
+// 3 * 2^7 and up (the transform grids of padding to B_3 at n = 256, 512, 1024)
+template <> struct FftCfg<384> : FftPlan<384, 12, 4, 4, 4, 4, 6> {};
+template <> struct FftCfg<768> : FftPlan<768, 12, 4, 4, 4, 4, 12> {};
+template <> struct FftCfg<1536> : FftPlan<1536, 24, 4, 8, 8, 8, 3> {};
 // 5-smooth and 7-smooth lengths: 20 or 28 values per thread
 template <> struct FftCfg<20> : FftPlan<20, 20, 2, 4, 5> {};
 template <> struct FftCfg<40> : FftPlan<40, 20, 2, 4, 10> {};

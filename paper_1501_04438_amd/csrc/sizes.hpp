@@ -1,8 +1,9 @@
 // sizes.hpp -- transform lengths n the library is compiled for (one object per size):
-// 2^a 3^b (b <= 1), 5 * 2^a and 7 * 2^a.
+// 2^a 3^b (b <= 1; 384, 768 and 1536 make padding to B_3 reach n = 256, 512 and 1024),
+// 5 * 2^a and 7 * 2^a.
 // The build script reads this list.
 #pragma once
-#define GS_SIZE_LIST(X) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(40) X(48) X(56) X(64) X(80) X(96) X(112) X(128) X(160) X(192) X(224) X(256) X(320) X(512) X(640) X(1024) X(2048)
+#define GS_SIZE_LIST(X) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(40) X(48) X(56) X(64) X(80) X(96) X(112) X(128) X(160) X(192) X(224) X(256) X(320) X(384) X(512) X(640) X(768) X(1024) X(1536) X(2048)
 #define GS_MAX_N_3D 1024
 
 // Grid of the fused pass: persistent (rounds of co-resident blocks looping over pencil

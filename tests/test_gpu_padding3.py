@@ -55,7 +55,8 @@ CASES = [("coulomb3d", 3, 16, 4.0), ("coulomb3d", 3, 32, 6.0), ("coulomb3d", 3, 
          ("coulomb3d", 3, (16, 32, 64), (2.0, 4.0, 8.0)), ("coulomb3d", 3, (8, 128, 16), (1.0, 16.0, 2.0)),
          ("dipolar3d", 3, 32, 6.0), ("inverse_power", 3, 16, 3.0),
          ("poisson2d", 2, 64, 8.0), ("coulomb2d", 2, 128, 12.0), ("poisson2d", 2, (32, 128), (3.0, 12.0)),
-         ("davey_stewartson2d", 2, 32, 5.0), ("inverse_power", 2, 64, 6.0)]
+         ("davey_stewartson2d", 2, 32, 5.0), ("inverse_power", 2, 64, 6.0),
+         ("poisson2d", 2, 512, 12.0), ("coulomb2d", 2, 1024, 12.0), ("coulomb2d", 2, (256, 512), (6.0, 12.0))]
 
 
 @pytest.mark.parametrize("kernel,d,n,L", CASES)
@@ -82,14 +83,20 @@ def test_unpadded_laplacian_with_padding3(kernel, d, n, L):
     assert relmax(u, ref) <= TOL
 
 
-def test_resolved_gaussian_closed_form():
-    """h = 1/4: padding to B_3 reaches the closed form to 1e-13 of its maximum."""
-    n, L = 64, 8.0
-    rho = workloads.gaussian(n, L, 3, sigma=1.0)
-    u = gs.Plan("coulomb3d", n=n, L=L, padding=3).eval(cuda(rho)).cpu().numpy()
+@pytest.mark.parametrize("n,L", [(64, 8.0), (256, 10.0)])
+def test_resolved_gaussian_closed_form(n, L):
+    """A resolved Gaussian: padding to B_3 reaches the closed form to 1e-13 of its maximum,
+    at 64^3 and at 256^3 (transforms of 768 points on the grid of 384 per axis), where it
+    also agrees with padding to B_2 to 1e-13."""
+    print(f"padding 3 closed form n={n}", flush=True)
+    rho = cuda(workloads.gaussian(n, L, 3, sigma=1.0))
+    u = gs.Plan("coulomb3d", n=n, L=L, padding=3).eval(rho)
     X = np.broadcast_arrays(*workloads.mesh(n, L, 3))
     r = np.sqrt(sum(x * x for x in X))
-    assert relmax(u, cf.coulomb3d_gaussian(r, 1.0)) <= 1e-13
+    ex = cf.coulomb3d_gaussian(r, 1.0)
+    assert relmax(u.cpu().numpy(), ex) <= 1e-13
+    u2 = gs.Plan("coulomb3d", n=n, L=L).eval(rho)
+    assert float((u - u2).abs().max()) <= 1e-13 * float(u2.abs().max())
 
 
 @pytest.mark.parametrize("kernel,d,n,L", [("coulomb3d", 3, (16, 32, 64), (2.0, 4.0, 8.0)),
