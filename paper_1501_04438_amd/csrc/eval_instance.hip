@@ -60,7 +60,7 @@ template <int N> constexpr int pz_of(int v) {
 template <int PX>
 static hipError_t launch_x_inverse_v(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
-    constexpr int T = PX * Geo<N>::G;
+    constexpr int T = p5_threads<N, PX>();
     const cpx* const X1 = reinterpret_cast<const cpx*>(a.X1);
     const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
     const bool hint = (a.hint_bits >> 4) & 1;

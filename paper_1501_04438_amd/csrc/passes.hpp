@@ -62,6 +62,18 @@ constexpr int NT_P1 = 1, NT_P2 = 2, NT_P3 = 1, NT_P4 = 1, NT_P5 = 2;
 // ---------------------------------------------------------------------------
 // Launch geometry per transform length.
 // ---------------------------------------------------------------------------
+// Exchanges the upper 32 lanes of a with the lower 32 lanes of b (all four words).
+__device__ __forceinline__ void swap_halves(cpx& a, cpx& b) {
+    unsigned* pa = reinterpret_cast<unsigned*>(&a);
+    unsigned* pb = reinterpret_cast<unsigned*>(&b);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(pa[i], pb[i], false, false);
+        pa[i] = r[0];
+        pb[i] = r[1];
+    }
+}
+
 template <int N> struct Geo {
     using F = FftCfg<N>;          // transforms of the x and y passes
     using FZ = FftCfgFused<N>;    // transforms of the fused pass
@@ -275,12 +287,92 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return v;
 }
 
+// P5 of a cubic grid with the two halves of the padded inverse (h = 0, 1) on the two 32-lane
+// halves of every wave: each thread loads and transforms one half, once (x_c2r_tile loads
+// and transforms both halves in turn), and the halves' sum is formed by a lane swap, each
+// lane then storing half of the pair's outputs (E/2 values of each row).  The same sums in
+// the same order as x_c2r_tile, so the same bits; two LDS areas per row pair.  For the
+// tiles whose PX G threads per half fill whole half-waves.  Returns the thread's part of
+// the energy sum (EN), as x_c2r_tile does.
+// Decided per length, so that every tile shape of a length (PPX and 2 PPX row pairs) has the
+// same layout: the default tile fills whole half-waves and the doubled tile's two LDS areas
+// per pair fit in the 160 KiB of a CU.
+template <int N> constexpr bool p5_split_len() {
+    return (Geo<N>::PPX * Geo<N>::G) % 32 == 0 && 2 * 2 * Geo<N>::PPX * Geo<N>::A * 16 <= 160 * 1024;
+}
+template <int N, int PX> constexpr bool p5_split() { return p5_split_len<N>() && (PX * Geo<N>::G) % 32 == 0; }
+template <int N, int PX> constexpr int p5_threads() { return (p5_split<N, PX>() ? 2 : 1) * PX * Geo<N>::G; }
+
+template <int N, int NT, bool EN, int PX>
+__device__ __forceinline__ double x_c2r_tile_split(gp<const cpx> __restrict__ X1, gp<double> u,
+                                                   gp<const cpx> __restrict__ tw, int bx, int z, int tid, cpx* lds,
+                                                   gp<const double> erho, double oscale) {
+    using Gm = Geo<N>;
+    constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
+    static_assert(p5_split<N, PX>(), "whole half-waves");
+    const int w = tid >> 6, l = tid & 63, h = l >> 5;
+    const int tq = 32 * w + (l & 31);           // thread within its half
+    const int tA = tq % G, pA = tq / G;         // store role: consecutive x
+    const int pB = tq % PP, tB = tq / PP;       // load role: consecutive y
+    const int y0 = bx * 2 * PP;
+    constexpr bool FULL = (N % (2 * PP) == 0);
+    const bool okA = FULL || (y0 + 2 * pA) < N, okB = FULL || (y0 + 2 * pB) < N;
+    constexpr bool SPLIT = FULL && Gm::PPX % 8 == 0 && PP % 8 == 0;
+    constexpr int RS = SPLIT ? 8 : 1;
+    const int rowA = SPLIT ? y0 + 16 * (pA / 8) + pA % 8 : y0 + 2 * pA;
+    const int rowB = SPLIT ? y0 + 16 * (pB / 8) + pB % 8 : y0 + 2 * pB;
+    gp<const cpx> in = X1 + (size_t)z * (N + 1) * N + rowB;
+    cpx v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = 2 * (tB + G * e) + h;           // padded index 0..2n-1
+        const bool direct = m <= N;
+        const int mm = direct ? m : 2 * N - m;
+        cpx a = cmk(0.0, 0.0), b = cmk(0.0, 0.0);
+        if (okB) {
+            gp<const cpx> p = in + (size_t)mm * N;
+            a = ldg<NT & 1>(p);
+            b = ldg<NT & 1>(p + RS);
+        }
+        if (!direct) { a.y = -a.y; b.y = -b.y; }
+        v[e] = cmk(a.x - b.y, a.y + b.x);              // a + i b
+    }
+    fft<typename Gm::F, true>(v, tB, lds + (h * PP + pB) * A, tA, lds + (h * PP + pA) * A, tw);
+    if (h) twist_out<typename Gm::F>(v, tA, tw);
+    const size_t o = ((size_t)z * N + rowA) * N;
+    gp<double> ua = u + o;
+    double part = 0.0;
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {
+        // lanes h = 0 end with the sum for element e, lanes h = 1 with that for e + E/2
+        cpx a = v[e], b = v[e + E / 2];
+        swap_halves(a, b);
+        cpx r = cadd(a, b);
+        const int j = tA + G * (h * (E / 2) + e);
+        if (okA) {
+            if constexpr (EN) {
+                r = cscale(r, oscale);
+                part += erho[o + j] * r.x + erho[o + (size_t)RS * N + j] * r.y;
+            }
+            stg<(NT & 2) != 0>(ua + j, r.x);
+            stg<(NT & 2) != 0>(ua + (size_t)RS * N + j, r.y);
+        }
+    }
+    return part;
+}
+
 template <int N, int NT = NT_P5, int PX = Geo<N>::PPX>
-__global__ void __launch_bounds__(PX * Geo<N>::G) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
-                                                         const cpx* __restrict__ tw) {
-    __shared__ cpx lds[PX * Geo<N>::A];
-    x_c2r_tile<N, NT, false, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x, blockIdx.y,
-                                       threadIdx.x, true, lds);
+__global__ void __launch_bounds__((p5_threads<N, PX>())) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
+                                                               const cpx* __restrict__ tw) {
+    if constexpr (p5_split<N, PX>()) {
+        __shared__ cpx lds[2 * PX * Geo<N>::A];
+        (void)x_c2r_tile_split<N, NT, false, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                                 blockIdx.y, threadIdx.x, lds, nullptr, 1.0);
+    } else {
+        __shared__ cpx lds[PX * Geo<N>::A];
+        x_c2r_tile<N, NT, false, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                           blockIdx.y, threadIdx.x, true, lds);
+    }
 }
 
 // P5 with the energy sum: as k_x_c2r, plus sum rho u over the block's outputs into
@@ -289,17 +381,26 @@ __global__ void __launch_bounds__(PX * Geo<N>::G) k_x_c2r(const cpx* __restrict_
 // PX = k PPX pairs holds k default tiles, sums each over its own threads in the default order
 // and writes k partials where the k default blocks would, so the energy has the same bits
 // for every tile shape.
+// (With the split halves a default tile's threads are 2 PPX G consecutive threads, whole
+// waves, the same for every PX: its sum keeps its bits across tile shapes.)
 template <int N, int NT = NT_P5, int PX = Geo<N>::PPX>
-__global__ void __launch_bounds__(PX * Geo<N>::G) k_x_c2r_energy(const cpx* __restrict__ X1, double* u,
-                                                                const cpx* __restrict__ tw, const double* rho,
-                                                                double* __restrict__ part, double oscale) {
-    constexpr int P0 = Geo<N>::PPX, T0 = P0 * Geo<N>::G, NG = PX / P0, W = T0 < 64 ? T0 : 64;
+__global__ void __launch_bounds__((p5_threads<N, PX>())) k_x_c2r_energy(const cpx* __restrict__ X1, double* u,
+                                                                      const cpx* __restrict__ tw, const double* rho,
+                                                                      double* __restrict__ part, double oscale) {
+    constexpr bool SPL = p5_split<N, PX>();
+    static_assert(SPL == p5_split<N, Geo<N>::PPX>(), "one P5 layout for every tile shape of a length");
+    constexpr int P0 = Geo<N>::PPX, T0 = (SPL ? 2 : 1) * P0 * Geo<N>::G, NG = PX / P0, W = T0 < 64 ? T0 : 64;
     static_assert(PX % P0 == 0 && (NG == 1 || T0 % 64 == 0), "whole default tiles of whole waves");
-    __shared__ cpx lds[PX * Geo<N>::A];
+    __shared__ cpx lds[(SPL ? 2 : 1) * PX * Geo<N>::A];
     __shared__ double red[NG * (T0 / 64 + 1)];
-    double v = x_c2r_tile<N, NT, true, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw,
-                                                 blockIdx.x, blockIdx.y, threadIdx.x, true, lds,
-                                                 (gp<const double>)rho, Ext(), oscale);
+    double v;
+    if constexpr (SPL)
+        v = x_c2r_tile_split<N, NT, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                              blockIdx.y, threadIdx.x, lds, (gp<const double>)rho, oscale);
+    else
+        v = x_c2r_tile<N, NT, true, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                              blockIdx.y, threadIdx.x, true, lds, (gp<const double>)rho, Ext(),
+                                              oscale);
     const int g = threadIdx.x / T0, local = threadIdx.x % T0;
 #pragma unroll
     for (int o = W / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, W);
@@ -449,17 +550,6 @@ template <int N> struct FusedRoles {
     }
 };
 
-// Exchanges the upper 32 lanes of a with the lower 32 lanes of b (all four words).
-__device__ __forceinline__ void swap_halves(cpx& a, cpx& b) {
-    unsigned* pa = reinterpret_cast<unsigned*>(&a);
-    unsigned* pb = reinterpret_cast<unsigned*>(&b);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const auto r = __builtin_amdgcn_permlane32_swap(pa[i], pb[i], false, false);
-        pa[i] = r[0];
-        pb[i] = r[1];
-    }
-}
 
 // NY: the y extent (3D pencils X2[kx][ky][:], ky = 0..2 NY - 1)
 template <int N, int DIM>
