@@ -145,6 +145,10 @@ typedef struct {
                                 allows, ignored elsewhere and on grids whose axes differ;
                                 every value gives the same bits.  GS_PLAN_AUTOTUNE picks
                                 them by timing                                   */
+    int launch_hints;        /* 1 + the cache-hint bits of the passes (bit p-1 set: pass p
+                                uses its non-temporal hint variant, gs_plan_info.hint_bits);
+                                0 = the compiled default.  Every value gives the same bits;
+                                GS_PLAN_AUTOTUNE picks them by timing            */
 } gs_options;
 
 typedef struct {

@@ -56,6 +56,7 @@ class Plan:
               at plan creation and keep the fastest (cached per device and size; the results
               are bitwise the same for every variant)
     tile_variants: tile shapes of the cubic passes (gs_options.tile_variants bits; 0 = defaults)
+    hint_bits: cache-hint variants of the passes (bit p-1: pass p non-temporal; None = defaults)
     workspace: False creates the plan without an evaluation workspace of its own; it is
               then evaluated with eval_static only
     laplacian: "padded" (default) or "unpadded": the grid on which the near-field Taylor term
@@ -70,7 +71,7 @@ class Plan:
                  host_only: bool = False, host_assembly: bool = False, stream=None, slab_planes: int = 0,
                  slab_streams: int = 0, autotune: bool = False, beta: float | None = None,
                  workspace: bool = True, laplacian: str = "padded", tile_variants: int = 0,
-                 padding: int = 2):
+                 padding: int = 2, hint_bits: int | None = None):
         if kernel not in KERNELS:
             raise ValueError(f"unknown kernel {kernel!r}")
         d = KERNEL_DIM.get(kernel, d)
@@ -96,6 +97,8 @@ class Plan:
             raise ValueError("padding: 2 or 3")
         opt.slab_planes = int(slab_planes)
         opt.tile_variants = int(tile_variants)
+        if hint_bits is not None:
+            opt.launch_hints = 1 + (int(hint_bits) & 31)
         opt.slab_streams = int(slab_streams)
         if beta is not None:
             opt.beta = float(beta)

@@ -27,7 +27,8 @@ class GSOptions(C.Structure):
     _fields_ = [("delta_rel", C.c_double), ("dipole_n", C.c_double * 3), ("dipole_m", C.c_double * 3),
                 ("gs_w", C.POINTER(C.c_double)), ("gs_tau", C.POINTER(C.c_double)), ("gs_q", C.c_int),
                 ("stream", C.c_void_p), ("device", C.c_int), ("flags", C.c_int), ("slab_planes", C.c_int),
-                ("slab_streams", C.c_int), ("beta", C.c_double), ("tile_variants", C.c_int)]
+                ("slab_streams", C.c_int), ("beta", C.c_double), ("tile_variants", C.c_int),
+                ("launch_hints", C.c_int)]
 
 
 class GSPlanInfo(C.Structure):

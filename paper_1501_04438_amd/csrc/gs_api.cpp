@@ -523,6 +523,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->flags = opt.flags;
     p->host_only = host_only;
     p->tile_bits = opt.tile_variants & 255;
+    if (opt.launch_hints > 0) p->hint_bits = (opt.launch_hints - 1) & 31;
     p->stream = (hipStream_t)opt.stream;
     for (int i = 0; i < 3; ++i) {
         p->dn[i] = opt.dipole_n[i];

@@ -486,6 +486,10 @@ def test_tile_variants_change_no_bit(kernel, d, n):
         assert torch.equal(plan.eval(x), u0), tv
         ue, e = plan.eval_energy(x)
         assert torch.equal(ue, u0e) and torch.equal(e, e0), tv
+    for hb in (0, 31, 27 ^ (1 << 4)):
+        plan = gs.Plan(kernel, n=n, L=6.0, hint_bits=hb, **kw)
+        assert plan.query()["hint_bits"] == hb
+        assert torch.equal(plan.eval(x), u0), hb
     if n <= 128:
         o = oracle.evaluate(oracle.make_plan(kernel, d, n, 6.0, **kw), x.cpu().numpy())
         assert relmax(u0.cpu().numpy(), o) <= TOL
