@@ -415,12 +415,31 @@ def other_workloads_bytes(d: int, n: int) -> int:
     return 16 * n * n + 64 * (n + 1) * n + 8 * (n + 1) ** 2
 
 
+def grid_chain_bytes(nx: int, ny: int, nz: int) -> int:
+    """Algorithmic bytes of the five 3D passes on a grid of nx x ny x nz points (each axis its
+    own n): X1 [z][kx][y] and X2 [kx][ky][z] complex, the spectrum octant once."""
+    real = 8 * nx * ny * nz
+    x1 = 16 * (nx + 1) * ny * nz
+    x2 = 32 * (nx + 1) * ny * nz
+    spec = 8 * (nx + 1) * (ny + 1) * (nz + 1)
+    return (real + x1) + (x1 + x2) + (2 * x2 + spec) + (x2 + x1) + (x1 + real)
+
+
+def padding3_bytes(n: int) -> int:
+    """Padding to B_3 of an n^3 grid: the chain on the 3n/2 transform grid, the density copied
+    in (read n^3, write (3n/2)^3) and the potential out (read and write n^3)."""
+    m = 3 * n // 2
+    return grid_chain_bytes(m, m, m) + 8 * n ** 3 + 8 * m ** 3 + 16 * n ** 3
+
+
 def other_figures(gs, torch, workloads, reps: int = 20):
     """Evaluation throughput of the other workloads: 2D Poisson, Coulomb and Davey-Stewartson at 2048^2,
     3D dipolar at 128^3, 3D Coulomb at 128^3, and the rectangular boxes of the
     anisotropic tables (3D 96^3 with gamma = 8, 2D 192^2 with gamma = 16); working
     sets partly resident in the Infinity Cache, so their bandwidth fraction can
-    exceed what HBM alone allows."""
+    exceed what HBM alone allows.  Then the widened rows at the headline size: the
+    inverse power r^-1.5, the unpadded-grid Laplacian, padding to B_3, a 128 x 256 x 512
+    grid with one step and a 320^3 grid (radix-5 stages)."""
     res = {}
     cases = [("poisson2d_2048", workloads.config3_2d("poisson2d", 2048), {"eps": 1e-13}),
              ("coulomb2d_2048", workloads.config3_2d("coulomb2d", 2048), {}),
@@ -429,7 +448,20 @@ def other_figures(gs, torch, workloads, reps: int = 20):
              ("coulomb3d_128", workloads.config2(128), {}),
              ("rect_coulomb3d_96_gamma8", workloads.rect_box(3, 8.0), {}),
              ("rect_coulomb2d_192_gamma16", workloads.rect_box(2, 16.0), {})]
-    for name, p, kw in cases:
+    # the widened rows at the headline size: inverse power, the two fidelity variants, a grid
+    # with its own n per axis (one step h = 1/25.6) and a length with a factor 5
+    c2 = workloads.config2(256)
+    ext = [("inverse_power3d_256_beta1.5", workloads.Problem("inverse_power", 3, 256, c2.L, c2.rho),
+            {"beta": 1.5, "d": 3}, sum(pass_bytes(256).values())),
+           ("unpadded_laplacian_coulomb3d_256", c2, {"laplacian": "unpadded"}, sum(pass_bytes(256).values())),
+           ("padding3_coulomb3d_256", c2, {"padding": 3}, padding3_bytes(256)),
+           ("per_axis_coulomb3d_128x256x512",
+            workloads.Problem("coulomb3d", 3, (128, 256, 512), (5.0, 10.0, 20.0),
+                              workloads.gaussian((128, 256, 512), (5.0, 10.0, 20.0), 3, sigma=2.0)),
+            {}, grid_chain_bytes(512, 256, 128)),
+           ("radix5_coulomb3d_320", workloads.config2(320), {}, sum(pass_bytes(320).values()))]
+    cases = [(a, b, c, None) for a, b, c in cases] + ext
+    for name, p, kw, nbytes in cases:
         if kw is None:
             kw = {"dipole": (p.extra["n"], p.extra["m"])}
         plan = gs.Plan(p.kernel, n=p.n, L=p.L, autotune=True, **kw)
@@ -445,9 +477,12 @@ def other_figures(gs, torch, workloads, reps: int = 20):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        pts = p.n ** p.d
-        b = other_workloads_bytes(p.d, p.n)
+        pts = 1
+        for v in plan.shape:
+            pts *= int(v)
+        b = nbytes if nbytes is not None else other_workloads_bytes(p.d, p.n)
         res[name] = {"ms": round(ms, 4), "Mpts_s": round(pts / ms / 1e3, 1), "alg_GB_s": round(b / ms / 1e6, 1),
+                     "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
                      "hint_bits": plan.info["hint_bits"], "fused_grid_mult": plan.info["fused_grid_mult"],
                      "tile_variants": plan.info["tile_variants"]}
         plan.close()
