@@ -402,22 +402,56 @@ __device__ __forceinline__ void mul_powers(cpx* v, cpx w1, cpx w4) {
     }
 }
 
+// Twiddle roots of a stage (NSPRE > 1) for butterfly j: W_N^base = W_2N^{2 base} and its
+// fourth power.  With h = 1 the root is W_2N^{2 base + N/(NSPRE R)}: the padding twist
+// x_j W_2N^j of the odd half, carried through the stages (see fft).
+template <int N, int R, int NSPRE>
+__device__ __forceinline__ void stage_roots(int j, int h, gp<const cpx> __restrict__ tw, cpx& w1, cpx& w4) {
+    constexpr int U = N / (NSPRE * R);
+    const int base = (j % NSPRE) * U;
+    w1 = tw[2 * base + h * U];
+    w4 = (R > 4) ? tw[8 * base + 4 * h * U] : w1;          // 8 base + 4 U < 2N for R > 4
+}
+
 // One Stockham stage on registers: twiddles (unless first) and E/R DFTs of radix R.
 // The twiddles W_N^{base r} are powers of W_N^{base} (two table reads per butterfly).
 template <int N, int E, int R, int NSPRE, bool INV>
-__device__ __forceinline__ void stage_compute(cpx (&v)[E], int t, gp<const cpx> __restrict__ tw) {
+__device__ __forceinline__ void stage_compute(cpx (&v)[E], int t, gp<const cpx> __restrict__ tw, int h = 0) {
     constexpr int G = N / E, B = E / R;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         if constexpr (NSPRE > 1) {
-            const int j = t + b * G;
-            const int base = (j % NSPRE) * (N / (NSPRE * R));
-            const cpx w1 = tw[2 * base];                          // W_N^base = W_2N^{2 base}
-            const cpx w4 = (R > 4) ? tw[8 * base] : w1;           // W_N^{4 base}, 4 base < N
+            cpx w1, w4;
+            stage_roots<N, R, NSPRE>(t + b * G, h, tw, w1, w4);
             mul_powers<R, B, INV>(&v[b], w1, w4);
         }
         Dft<R, B, INV>::run(&v[b]);
     }
+}
+
+// The same stage transposed: the DFTs first, then the twiddles (for the transposed engine).
+template <int N, int E, int R, int NSPRE, bool INV>
+__device__ __forceinline__ void stage_compute_t(cpx (&v)[E], int t, gp<const cpx> __restrict__ tw, int h) {
+    constexpr int G = N / E, B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        Dft<R, B, INV>::run(&v[b]);
+        if constexpr (NSPRE > 1) {
+            cpx w1, w4;
+            stage_roots<N, R, NSPRE>(t + b * G, h, tw, w1, w4);
+            mul_powers<R, B, INV>(&v[b], w1, w4);
+        }
+    }
+}
+
+// The constant part of the padding twist: v[b + r B] *= W_{2 R0}^r (conjugated when INV),
+// r the input index within the first stage's radix-R0 butterflies.
+template <class P, bool INV>
+__device__ __forceinline__ void twist_const(cpx (&v)[P::E]) {
+    constexpr int E = P::E, R0 = P::R[0], B = E / R0;
+    [&]<int... I>(std::integer_sequence<int, I...>) {
+        ((v[I] = twiddle_const<I / B, 2 * R0, INV>(v[I])), ...);
+    }(std::make_integer_sequence<int, E>{});
 }
 
 // Padding twist before a forward transform: x[j] *= W_2N^j for j = t + G e, as
@@ -466,9 +500,18 @@ __device__ __forceinline__ void stage_gather(cpx (&v)[C::E], int t, const cpx* l
 // transform lie in one wave (only wave-level ordering is then needed); otherwise
 // it contains block barriers and every thread of the block must call it.  The
 // areas must not be in use by other threads when it is entered.
+//
+// h = 1 (a per-thread value) computes the transform of x_j W_2N^j, the odd half of a padded
+// transform, without a separate twist: writing j = (t + G b) + r N/R0 for input r of a
+// first-stage butterfly, W_2N^j = W_2N^{t + G b} W_{2 R0}^r; the caller applies the constant
+// W_{2 R0}^r (twist_const) and the factor W_2N^{t + G b}, common to the butterfly, rides on
+// its outputs.  After a stage with NSPRE = P and radix R the factor at position q is
+// W_2N^{floor(q / PR)}; at the next stage it becomes, for input r of a butterfly,
+// W_2N^{floor(j / P)} W_2N^{r N / (P R)}: the second part joins that stage's twiddle root
+// (stage_roots), the first again rides on the outputs, and after the last stage (PR = N) it is 1.
 template <class C, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft(cpx (&v)[C::E], int t1, cpx* lds1, int t2, cpx* lds2,
-                                    gp<const cpx> __restrict__ tw) {
+                                    gp<const cpx> __restrict__ tw, int h = 0) {
     constexpr int N = C::N;
     constexpr int E = C::E;
     constexpr int R0 = C::R[0], R1 = C::R[1], R2 = C::R[2], R3 = C::R[3];
@@ -477,22 +520,79 @@ __device__ __forceinline__ void fft(cpx (&v)[C::E], int t1, cpx* lds1, int t2, c
         stage_scatter<C, R0, 1>(v, t1, lds1);
         lds_sync<WAVE>();
         stage_gather<C>(v, t2, lds2);
-        stage_compute<N, E, R1, R0, INV>(v, t2, tw);
+        stage_compute<N, E, R1, R0, INV>(v, t2, tw, h);
     }
     if constexpr (C::NS >= 3) {
         lds_sync<WAVE>();
         stage_scatter<C, R1, R0>(v, t2, lds2);
         lds_sync<WAVE>();
         stage_gather<C>(v, t2, lds2);
-        stage_compute<N, E, R2, R0 * R1, INV>(v, t2, tw);
+        stage_compute<N, E, R2, R0 * R1, INV>(v, t2, tw, h);
     }
     if constexpr (C::NS >= 4) {
         lds_sync<WAVE>();
         stage_scatter<C, R2, R0 * R1>(v, t2, lds2);
         lds_sync<WAVE>();
         stage_gather<C>(v, t2, lds2);
-        stage_compute<N, E, R3, R0 * R1 * R2, INV>(v, t2, tw);
+        stage_compute<N, E, R3, R0 * R1 * R2, INV>(v, t2, tw, h);
     }
+}
+
+// Reverse exchange of the stage (R, NSPRE): each thread writes its values where fft's
+// gather reads them and reads them back where fft's scatter wrote them.
+template <class C>
+__device__ __forceinline__ void stage_ungather(const cpx (&v)[C::E], int t, cpx* lds) {
+    constexpr int E = C::E, G = C::G;
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[lds_slot<C>(t + G * e)] = v[e];
+}
+
+template <class C, int R, int NSPRE>
+__device__ __forceinline__ void stage_unscatter(cpx (&v)[C::E], int t, const cpx* lds) {
+    constexpr int E = C::E, G = C::G, B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = t + b * G;
+        const int base = (j / NSPRE) * NSPRE * R + (j % NSPRE);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b + r * B] = lds[lds_slot<C>(base + r * NSPRE)];
+    }
+}
+
+// The transposed engine: the stages of fft in reverse order, each transposed (DFTs, then
+// twiddles) and the exchanges reversed.  The DFT matrix being symmetric, this is the same
+// transform (INV: the inverse) from the same layout to the same layout (thread t holds
+// elements t + G e before and after); with h = 1 it is the transpose of fft's twisted
+// transform, i.e. the transform followed by the cropping twist y_j W_2N^{-j} (INV), the
+// constant part applied last (the odd half of a cropped inverse, without a separate twist).
+// The area must not be in use by other threads when it is entered.
+template <class C, bool INV, bool WAVE = false>
+__device__ __forceinline__ void fft_t(cpx (&v)[C::E], int t, cpx* lds, gp<const cpx> __restrict__ tw, int h) {
+    constexpr int N = C::N;
+    constexpr int E = C::E;
+    constexpr int R0 = C::R[0], R1 = C::R[1], R2 = C::R[2], R3 = C::R[3];
+    if constexpr (C::NS >= 4) {
+        stage_compute_t<N, E, R3, R0 * R1 * R2, INV>(v, t, tw, h);
+        stage_ungather<C>(v, t, lds);
+        lds_sync<WAVE>();
+        stage_unscatter<C, R2, R0 * R1>(v, t, lds);
+        lds_sync<WAVE>();
+    }
+    if constexpr (C::NS >= 3) {
+        stage_compute_t<N, E, R2, R0 * R1, INV>(v, t, tw, h);
+        stage_ungather<C>(v, t, lds);
+        lds_sync<WAVE>();
+        stage_unscatter<C, R1, R0>(v, t, lds);
+        lds_sync<WAVE>();
+    }
+    if constexpr (C::NS >= 2) {
+        stage_compute_t<N, E, R1, R0, INV>(v, t, tw, h);
+        stage_ungather<C>(v, t, lds);
+        lds_sync<WAVE>();
+        stage_unscatter<C, R0, 1>(v, t, lds);
+    }
+    stage_compute_t<N, E, R0, 1, INV>(v, t, tw, h);
+    if (h) twist_const<C, INV>(v);
 }
 
 }  // namespace gsk

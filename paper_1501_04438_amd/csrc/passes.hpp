@@ -606,8 +606,9 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
     using FZ = typename Gm::FZ;
     constexpr int E = Gm::EZ, G = Gm::GZ, A = Gm::AZ;
     constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
-    if (h) twist_in<FZ>(v, t, tw);
-    fft<FZ, false, FW>(v, t, area, t, area, tw);
+    // the odd half's padding twist rides in the transforms (fft, fft_t with h = 1)
+    if (h) twist_const<FZ, false>(v);
+    fft<FZ, false, FW>(v, t, area, t, area, tw, h);
     if constexpr (MODE == SPEC_DIPOLAR) {
         // (n.xi)(m.xi) with Nyquist taken as 0 in the odd (cross) factors
         const int kx = (DIM == 3) ? kx0 + pencil / (2 * NY) : pencil;
@@ -632,8 +633,7 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
         for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sv[e]);
     }
     lds_sync<FW>();
-    fft<FZ, true, FW>(v, t, area, t, area, tw);
-    if (h) twist_out<FZ>(v, t, tw);
+    fft_t<FZ, true, FW>(v, t, area, tw, h);
     gp<cpx> base = X + (size_t)pencil * N;
     if constexpr (FusedRoles<N>::SWAP) {
         // lanes l < 32 (even half) take the odd half's values e < E/2 from lane l + 32,
