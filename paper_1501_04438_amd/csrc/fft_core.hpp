@@ -454,24 +454,15 @@ __device__ __forceinline__ void twist_const(cpx (&v)[P::E]) {
     }(std::make_integer_sequence<int, E>{});
 }
 
-// Padding twist before a forward transform: x[j] *= W_2N^j for j = t + G e, as
-// W_2N^t (one table read) times the constant W_2E^e.
+// Padding twist before a forward transform, applied on its own: x[j] *= W_2N^j for
+// j = t + G e, as W_2N^t (one table read) times the constant W_2E^e (for a pass whose
+// registers do not leave room for the twisted roots of fft's h = 1).
 template <class P>
 __device__ __forceinline__ void twist_in(cpx (&v)[P::E], int t, gp<const cpx> __restrict__ tw) {
     constexpr int E = P::E;
     const cpx c = tw[t];
     [&]<int... I>(std::integer_sequence<int, I...>) {
         ((v[I] = cmul(twiddle_const<I, 2 * E, false>(v[I]), c)), ...);
-    }(std::make_integer_sequence<int, E>{});
-}
-
-// Cropping twist after an inverse transform: y[j] *= conj(W_2N^j), j = t + G e.
-template <class P>
-__device__ __forceinline__ void twist_out(cpx (&v)[P::E], int t, gp<const cpx> __restrict__ tw) {
-    constexpr int E = P::E;
-    const cpx c = tw[t];
-    [&]<int... I>(std::integer_sequence<int, I...>) {
-        ((v[I] = cmulc(twiddle_const<I, 2 * E, true>(v[I]), c)), ...);
     }(std::make_integer_sequence<int, E>{});
 }
 
@@ -561,37 +552,39 @@ __device__ __forceinline__ void stage_unscatter(cpx (&v)[C::E], int t, const cpx
 
 // The transposed engine: the stages of fft in reverse order, each transposed (DFTs, then
 // twiddles) and the exchanges reversed.  The DFT matrix being symmetric, this is the same
-// transform (INV: the inverse) from the same layout to the same layout (thread t holds
-// elements t + G e before and after); with h = 1 it is the transpose of fft's twisted
-// transform, i.e. the transform followed by the cropping twist y_j W_2N^{-j} (INV), the
-// constant part applied last (the odd half of a cropped inverse, without a separate twist).
-// The area must not be in use by other threads when it is entered.
+// transform (INV: the inverse); it takes fft's output layout to fft's input layout: on entry
+// thread t2 holds elements t2 + G e (area lds2), on exit thread t1 holds t1 + G e (area
+// lds1), the roles switching at the last exchange.  With h = 1 it is the transpose of fft's
+// twisted transform, i.e. the transform followed by the cropping twist y_j W_2N^{-j} (INV),
+// whose constant part is applied last: the odd half of a cropped inverse without a separate
+// twist.  The areas must not be in use by other threads when it is entered; WAVE as in fft.
 template <class C, bool INV, bool WAVE = false>
-__device__ __forceinline__ void fft_t(cpx (&v)[C::E], int t, cpx* lds, gp<const cpx> __restrict__ tw, int h) {
+__device__ __forceinline__ void fft_t(cpx (&v)[C::E], int t1, cpx* lds1, int t2, cpx* lds2,
+                                      gp<const cpx> __restrict__ tw, int h) {
     constexpr int N = C::N;
     constexpr int E = C::E;
     constexpr int R0 = C::R[0], R1 = C::R[1], R2 = C::R[2], R3 = C::R[3];
     if constexpr (C::NS >= 4) {
-        stage_compute_t<N, E, R3, R0 * R1 * R2, INV>(v, t, tw, h);
-        stage_ungather<C>(v, t, lds);
+        stage_compute_t<N, E, R3, R0 * R1 * R2, INV>(v, t2, tw, h);
+        stage_ungather<C>(v, t2, lds2);
         lds_sync<WAVE>();
-        stage_unscatter<C, R2, R0 * R1>(v, t, lds);
+        stage_unscatter<C, R2, R0 * R1>(v, t2, lds2);
         lds_sync<WAVE>();
     }
     if constexpr (C::NS >= 3) {
-        stage_compute_t<N, E, R2, R0 * R1, INV>(v, t, tw, h);
-        stage_ungather<C>(v, t, lds);
+        stage_compute_t<N, E, R2, R0 * R1, INV>(v, t2, tw, h);
+        stage_ungather<C>(v, t2, lds2);
         lds_sync<WAVE>();
-        stage_unscatter<C, R1, R0>(v, t, lds);
+        stage_unscatter<C, R1, R0>(v, t2, lds2);
         lds_sync<WAVE>();
     }
     if constexpr (C::NS >= 2) {
-        stage_compute_t<N, E, R1, R0, INV>(v, t, tw, h);
-        stage_ungather<C>(v, t, lds);
+        stage_compute_t<N, E, R1, R0, INV>(v, t2, tw, h);
+        stage_ungather<C>(v, t2, lds2);
         lds_sync<WAVE>();
-        stage_unscatter<C, R0, 1>(v, t, lds);
+        stage_unscatter<C, R0, 1>(v, t1, lds1);
     }
-    stage_compute_t<N, E, R0, 1, INV>(v, t, tw, h);
+    stage_compute_t<N, E, R0, 1, INV>(v, t1, tw, h);
     if (h) twist_const<C, INV>(v);
 }
 

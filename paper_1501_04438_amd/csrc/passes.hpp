@@ -143,6 +143,8 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
         cpx v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = x[e];
+        // the separate twist measured faster here than the twisted roots (its h = 1 roots
+        // of the 16 x 16 plan double the stage-2 power products in the unrolled h loop)
         if (h) twist_in<typename Gm::F>(v, tA, tw);
         fft<typename Gm::F, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
         lds_barrier();
@@ -232,8 +234,7 @@ __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<d
             if (!direct) { a.y = -a.y; b.y = -b.y; }
             v[e] = cmk(a.x - b.y, a.y + b.x);          // a + i b
         }
-        fft<typename Gm::F, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
-        if (h) twist_out<typename Gm::F>(v, tA, tw);
+        fft_t<typename Gm::F, true>(v, tA, lds + pA * A, tB, lds + pB * A, tw, h);   // cropping twist included
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], v[e]);
         lds_barrier();
@@ -337,8 +338,7 @@ __device__ __forceinline__ double x_c2r_tile_split(gp<const cpx> __restrict__ X1
         if (!direct) { a.y = -a.y; b.y = -b.y; }
         v[e] = cmk(a.x - b.y, a.y + b.x);              // a + i b
     }
-    fft<typename Gm::F, true>(v, tB, lds + (h * PP + pB) * A, tA, lds + (h * PP + pA) * A, tw);
-    if (h) twist_out<typename Gm::F>(v, tA, tw);
+    fft_t<typename Gm::F, true>(v, tA, lds + (h * PP + pA) * A, tB, lds + (h * PP + pB) * A, tw, h);
     const size_t o = ((size_t)z * N + rowA) * N;
     gp<double> ua = u + o;
     double part = 0.0;
@@ -448,8 +448,8 @@ __device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx
         cpx v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = x[e];
-        if (h) twist_in<typename Gm::F>(v, tA, tw);
-        fft<typename Gm::F, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
+        if (h) twist_const<typename Gm::F, false>(v);        // the rest of the twist rides in fft
+        fft<typename Gm::F, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw, h);
         if (okB) {
 #pragma unroll
             for (int e = 0; e < E; ++e) stg<(NT & 2) != 0>(dst + (size_t)(2 * (tB + G * e) + h) * NZ, v[e]);
@@ -494,8 +494,7 @@ __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx
 #pragma unroll
         for (int e = 0; e < E; ++e)
             v[e] = okB ? ldg<NT & 1>(src + (size_t)(2 * (tB + G * e) + h) * NZ) : cmk(0.0, 0.0);
-        fft<typename Gm::F, true>(v, tB, lds + pB * A, tA, lds + pA * A, tw);
-        if (h) twist_out<typename Gm::F>(v, tA, tw);
+        fft_t<typename Gm::F, true>(v, tA, lds + pA * A, tB, lds + pB * A, tw, h);   // cropping twist included
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], v[e]);
         lds_barrier();
@@ -633,7 +632,7 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
         for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sv[e]);
     }
     lds_sync<FW>();
-    fft_t<FZ, true, FW>(v, t, area, tw, h);
+    fft_t<FZ, true, FW>(v, t, area, t, area, tw, h);
     gp<cpx> base = X + (size_t)pencil * N;
     if constexpr (FusedRoles<N>::SWAP) {
         // lanes l < 32 (even half) take the odd half's values e < E/2 from lane l + 32,
