@@ -213,9 +213,10 @@ def cpu_baseline(n_sample: int, min_seconds: float = 10.0) -> dict:
     p = workloads.config2(n_sample)
     plan = oracle.make_plan("coulomb3d", 3, n_sample, p.L, eps=1e-14)
     evals, dt = 0, 0.0
+    u_ref = None
     while dt < min_seconds:
         t0 = time.perf_counter()
-        oracle.evaluate(plan, p.rho)
+        u_ref = oracle.evaluate(plan, p.rho)
         dt += time.perf_counter() - t0
         evals += 1
     model = "unknown"
@@ -227,9 +228,49 @@ def cpu_baseline(n_sample: int, min_seconds: float = 10.0) -> dict:
                     break
     except OSError:
         pass
-    return {"value": evals * n_sample ** 3 / dt / 1e6, "unit": "Mpts/s", "cores": int(threads), "kind": "oracle",
-            "cpu_model": model,
-            "sample": f"{evals} evaluation(s) of the same workload at {n_sample}^3 (plan excluded), {dt:.1f} s"}
+    out = {"value": evals * n_sample ** 3 / dt / 1e6, "unit": "Mpts/s", "cores": int(threads), "kind": "oracle",
+           "cpu_model": model,
+           "sample": f"{evals} evaluation(s) of the same workload at {n_sample}^3 (plan excluded), {dt:.1f} s"}
+    out["cpu_fft_reference"] = cpu_fft_reference(oracle, plan, p.rho, u_ref, int(threads))
+    return out
+
+
+def cpu_fft_reference(oracle, plan, rho, u_ref, workers: int) -> dict:
+    """A fairer CPU speed comparison than the oracle (not the oracle): the same folded spectrum
+    applied with scipy.fft on the zero-padded grid, u = crop(IFFT(S . FFT(pad rho))), on all
+    host cores; one evaluation, its agreement with the oracle's output reported."""
+    import numpy as np
+    import scipy.fft as sf
+    n = rho.shape[0]
+    S = oracle.full_spectrum(plan) + plan.A0 - plan.c2 * oracle.laplacian_symbol(plan)
+    rp = np.zeros((2 * n,) * 3)
+    t0 = time.perf_counter()
+    rp[:n, :n, :n] = rho
+    X = sf.fftn(rp, workers=workers)
+    X *= S
+    u = sf.ifftn(X, workers=workers).real[:n, :n, :n]
+    dt = time.perf_counter() - t0
+    err = float(np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref)))
+    return {"value": n ** 3 / dt / 1e6, "unit": "Mpts/s", "cores": workers, "kind": "scipy.fft, folded spectrum",
+            "sample": f"one evaluation at {n}^3, {dt:.2f} s", "max_rel_diff_vs_oracle": err}
+
+
+def dgemm_tflops(torch, m: int = 8192, reps: int = 5) -> float:
+    """FP64 matrix product of two m x m matrices (the vendor BLAS): the measured FP64 matrix
+    peak, reported next to the datasheet's for the spectrum assembly."""
+    a = torch.rand((m, m), dtype=torch.float64, device="cuda:0")
+    b = torch.rand((m, m), dtype=torch.float64, device="cuda:0")
+    c = a @ b
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        c = a @ b
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b, c
+    return 2.0 * m ** 3 / (ms * 1e-3) / 1e12
 
 
 def copy_bandwidth(torch, mib: int = 2048, reps: int = 20) -> float:
@@ -311,7 +352,8 @@ def main() -> int:
     pass_ms = {p: 0.0 for p in range(1, 6)}
     for i, p in enumerate(steps):
         pass_ms[p] += float(np.mean([hip.elapsed(ev[s][i], ev[s][i + 1]) for s in range(K)]))
-    gpu_ms = float(np.mean([hip.elapsed(ev[s][0], ev[s][S]) for s in range(K)]))
+    per_step = [hip.elapsed(ev[s][0], ev[s][S]) for s in range(K)]
+    gpu_ms = float(np.mean(per_step))
     hip.destroy([e for row in ev for e in row])
     value = n ** 3 / (wall / K) / 1e6
     # the same K evaluations, one library call each (no events between the passes)
@@ -353,6 +395,8 @@ def main() -> int:
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "gpu_ms_per_eval_events": round(gpu_ms, 5),
+        "gpu_ms_per_eval_events_median": round(float(np.median(per_step)), 5),
+        "gpu_ms_per_eval_events_min": round(float(np.min(per_step)), 5),
         "ms_per_eval_without_pass_events": round(plain_ms, 5),
         "eval_alg_bytes": total_bytes,
         "eval_GB_s": round(total_bytes / (gpu_ms * 1e-3) / 1e9, 1),
@@ -368,6 +412,10 @@ def main() -> int:
     }
 
     out["copy_GB_s"] = round(copy_bandwidth(torch), 1)
+    if not args.no_extras:
+        dg = dgemm_tflops(torch)
+        out["dgemm_TFLOPs"] = round(dg, 2)
+        out["assembly"]["frac_measured_dgemm"] = round(out["assembly"]["tflops"] / dg, 4)
     if not args.no_extras:
         out["autotuned_plan"] = autotuned_figures(gs, torch, plan, rho, K)
         out["adjoint"] = adjoint_figures(gs, torch, workloads, plan, rho, K, ms_step)
