@@ -15,6 +15,8 @@
 // stage may differ from the one that runs the later ones (t1/lds1 versus
 // t2/lds2): passes use that to turn a coalesced load of one layout into a
 // coalesced store of another through the LDS exchange the FFT needs anyway.
+// The odd half's twist x_j exp(-i pi j/n) can ride through the stages (fft with h = 1),
+// and an inverse followed by the cropping twist runs on the transposed engine (fft_t).
 //
 // Twiddles come from a per-size table W[m] = exp(-i pi m / N), m < 2N,
 // computed on the host in extended precision.
