@@ -444,8 +444,8 @@ gs_status gs_eval_step(gs_plan p, const double* rho_dev, double* u_dev, int step
 
 /* gs_eval with an event recorded on the plan's stream before the first step and after
  * every step (events: count = steps + 1 hipEvent_t handles created by the caller, for
- * timing the passes of a whole evaluation launched back to back).  Errors: INVALID_ARG
- * (count, plan), HIP. */
+ * timing the passes of a whole evaluation launched back to back; a NULL entry records
+ * nothing at that point).  Errors: INVALID_ARG (count, plan), HIP. */
 gs_status gs_eval_events(gs_plan p, const double* rho_dev, double* u_dev, void* const* events, int count);
 
 /* Copies a plan buffer between the device and host memory, for testing the

@@ -283,7 +283,7 @@ class Plan:
         check(lib().gs_eval_step(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()), int(step)))
 
     def eval_events(self, rho, u, events):
-        """eval with the given HIP event handles (steps + 1) recorded around every step."""
+        """eval with the given HIP event handles (steps + 1) recorded around every step (None: no record)."""
         self._stream()
         arr = (C.c_void_p * len(events))(*[e.value if hasattr(e, "value") else e for e in events])
         check(lib().gs_eval_events(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()), arr, len(events)))

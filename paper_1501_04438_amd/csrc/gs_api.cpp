@@ -832,10 +832,11 @@ gs_status gs_eval_events(gs_plan p, const double* rho_dev, double* u_dev, void* 
     if (!p->X1) return fail(GS_ERR_INVALID_ARG, "plan created without a workspace (GS_PLAN_NO_WORKSPACE)");
     DeviceScope ds(p->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
-    hipError_t e = hipEventRecord((hipEvent_t)events[0], p->stream);
+    // a NULL handle records nothing (each record costs the stream a few microseconds)
+    hipError_t e = events[0] ? hipEventRecord((hipEvent_t)events[0], p->stream) : hipSuccess;
     for (int i = 0; i < (int)p->steps.size() && e == hipSuccess; ++i) {
         e = run_step(p, a, i, p->stream);
-        if (e == hipSuccess) e = hipEventRecord((hipEvent_t)events[i + 1], p->stream);
+        if (e == hipSuccess && events[i + 1]) e = hipEventRecord((hipEvent_t)events[i + 1], p->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "evaluation launch");
     return GS_OK;

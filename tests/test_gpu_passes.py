@@ -118,8 +118,8 @@ def test_2d_passes(n):
 @pytest.mark.parametrize("n,slabs", [(64, 0), (48, 5)])
 def test_eval_events_same_bits_and_times(n, slabs):
     """gs_eval_events: the evaluation's steps back to back with an event after each; the
-    output equals gs_eval's bit for bit, every interval is a positive time, and a wrong
-    event count is refused."""
+    output equals gs_eval's bit for bit, every interval is a positive time, NULL entries
+    record nothing, and a wrong event count is refused."""
     import ctypes as C
     hip = C.CDLL("libamdhip64.so")
     hip.hipEventCreateWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_uint]
@@ -143,6 +143,16 @@ def test_eval_events_same_bits_and_times(n, slabs):
         ms = C.c_float()
         assert hip.hipEventElapsedTime(C.byref(ms), a, b) == 0
         assert ms.value >= 0.0
+    # NULL entries record nothing: events around one fused-pass launch only
+    i = plan.steps().index(3)
+    marks = [e if j in (i, i + 1) else None for j, e in enumerate(ev)]
+    ut.zero_()
+    plan.eval_events(rt, ut, marks)
+    torch.cuda.synchronize()
+    assert torch.equal(ut, ref)
+    ms = C.c_float()
+    assert hip.hipEventElapsedTime(C.byref(ms), ev[i], ev[i + 1]) == 0
+    assert ms.value >= 0.0
     with pytest.raises(gs.GSError):
         plan.eval_events(rt, ut, ev[:-1])
     for e in ev:
