@@ -270,20 +270,23 @@ gs_status gs_eval_static(gs_plan p, const double* rho_dev, double* u_dev);
 /*
  * gs_eval plus the Hartree-type energy E = 1/2 int rho u by the grid sum
  * E = 1/2 (prod_j h_j) sum_i rho_i u_i (the energy of the differentiation
- * workload), formed inside the last pass: the x-inverse pass reads rho where it
- * writes u and leaves one partial sum per block, and one more block adds them in
- * a fixed order, so E is the same bits on every run.  energy_dev is device memory
- * for one double, written asynchronously on the plan's stream; u may alias rho.
- * The rho-gradient of E is (prod_j h_j) u (the operator is symmetric).
- * Errors: as gs_eval; INVALID_ARG for a NULL energy_dev.
+ * workload).  The sum is formed inside the fused spectrum pass by Parseval's
+ * identity: u is the inverse transform of S rho^ on the padded grid (S the folded
+ * spectrum, 1/M included), so sum_i rho_i u_i = sum_k S(k) |rho^(k)|^2 over the
+ * padded spectrum, with no second read of rho.  Each pencil of that pass leaves one
+ * partial sum and two more kernels add them in a fixed order, so E is the same bits
+ * on every run and for every launch shape (tile variants, persistent grid).
+ * energy_dev is device memory for one double, written asynchronously on the plan's
+ * stream; u may alias rho.  The rho-gradient of E is (prod_j h_j) u (the operator is
+ * symmetric).  Errors: as gs_eval; INVALID_ARG for a NULL energy_dev.
  */
 gs_status gs_eval_energy(gs_plan p, const double* rho_dev, double* u_dev, double* energy_dev);
 
 /*
  * The energy and its rho-gradient in one evaluation: grad_dev receives
  * (prod_j h_j) u (the gradient of E = 1/2 (prod_j h_j) sum rho u, the operator being
- * symmetric), energy_dev[0] the energy 1/2 sum_i rho_i grad_i, both formed in the last
- * pass (fixed order, the same bits on every run).  grad_dev may alias rho_dev.
+ * symmetric; the x-inverse pass stores u times prod_j h_j), energy_dev[0] the energy,
+ * summed as in gs_eval_energy (the same bits as there).  grad_dev may alias rho_dev.
  * Errors: as gs_eval_energy.
  */
 gs_status gs_eval_energy_gradient(gs_plan p, const double* rho_dev, double* grad_dev, double* energy_dev);

@@ -237,7 +237,7 @@ class Plan:
 
     def eval_energy(self, rho, out=None):
         """(u, E): the potential and E = 1/2 cell sum rho u (a 0-d device tensor), the sum
-        formed in the evaluation's last pass in a fixed order."""
+        formed in the fused spectrum pass (Parseval's identity) and totalled in a fixed order."""
         torch = _torch()
         self._check_tensor(rho, "rho")
         u = torch.empty_like(rho) if out is None else out
@@ -250,7 +250,8 @@ class Plan:
 
     def energy_and_gradient(self, rho, out=None):
         """(E, dE/drho) of E = 1/2 cell sum rho u without autograd: one evaluation whose last
-        pass writes the gradient cell * u and sums the energy (a 0-d device tensor)."""
+        pass writes the gradient cell * u, the energy summed as in eval_energy (a 0-d device
+        tensor)."""
         torch = _torch()
         self._check_tensor(rho, "rho")
         g = torch.empty_like(rho) if out is None else out

@@ -36,7 +36,7 @@ struct gs_plan_s {
     double2* X2 = nullptr;
     double2* tw = nullptr;                    // twiddles of length n (cubic grids)
     double2* twk[3] = {nullptr, nullptr, nullptr};   // per octant axis (rectangular grids; may alias)
-    double* epart = nullptr;                  // per-block energy sums of the x-inverse pass
+    double* epart = nullptr;                  // per-pencil energy sums of the fused pass
     double* mixpart = nullptr;                // per-block sums of the mixture gradient
     double* E = nullptr;                      // pad 3: the density and potential on the transform grid
     size_t spec_bytes = 0, work_bytes = 0;

@@ -35,12 +35,14 @@ struct EvalArgs {
     // Tile shapes of the cubic passes (bits 0-1 x passes, 2-3 y passes, 4-5 fused pass; 0 =
     // compiled defaults; see eval_instance.hip); the same bits for every value.
     int tile_bits = 0;
-    // Energy (pass 5 only, when energy != nullptr): E = escale * sum_i rho_i u_i, per-block
-    // partial sums in epart (energy_blocks(d, n) doubles), their fixed-order total in *energy.
+    // Energy (when energy != nullptr): E = escale * sum_i rho_i u_i, summed in the fused pass
+    // by Parseval's identity, one partial per pencil in epart (epencils of them, then room for
+    // energy_total_scratch() more), their fixed-order total written to *energy after pass 5.
     double* energy = nullptr;
     double* epart = nullptr;
+    int epencils = 0;
     double escale = 0.0;
-    double oscale = 1.0;              // energy pass only: the outputs are stored times oscale
+    double oscale = 1.0;              // with the energy: the outputs are stored times oscale
     // Grids whose axes have their own n (rectangular grids): the extents of the x, y, z axes
     // (n above is unused unless nx = ny (= nz) = n) and each axis' twiddle table.
     int nx = 0, ny = 0, nz = 0;
@@ -62,11 +64,15 @@ hipError_t launch_pad_embed(const double* rho, double* E, int nx, int ny, int nz
 hipError_t launch_pad_crop(const double* E, double* u, int nx, int ny, int nz, int Nx, int Ny, int Nz,
                            hipStream_t s);
 
-// Blocks of the x-inverse pass (the energy partial sums it writes) of an (nx, ny, nz) grid
-// (2D: nz = 1).
-int energy_blocks(int d, int nx, int ny, int nz);
+// Pencils of the fused pass (one energy partial sum each) of an (nx, ny, .) transform grid:
+// 3D (nx + 1) 2 ny, 2D nx + 1.
+int energy_pencils(int d, int nx, int ny);
+// Doubles the energy total needs after the partials (its first-stage sums).
+int energy_total_scratch();
 // energy[0] = scale * (part[0] + ... + part[count-1]) in a fixed order (one block).
 hipError_t launch_energy_finish(const double* part, int count, double scale, double* energy, hipStream_t s);
+// The same total for any count: chunk sums into part[count ..] first when count is large.
+hipError_t launch_energy_total(double* part, int count, double scale, double* energy, hipStream_t s);
 
 // Passes: 1 x_r2c, 2 y_fwd, 3 fused, 4 y_inv, 5 x_c2r.  `which` < 0 runs all five on the
 // slab given in the arguments (a whole evaluation when the slab covers kx = 0..n).  A grid

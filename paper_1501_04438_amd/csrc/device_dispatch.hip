@@ -1,5 +1,7 @@
 // device_dispatch.hip -- size dispatch of the evaluation passes and the
 // spectrum-assembly launcher.
+#include <algorithm>
+
 #include "assembly.hpp"
 #include "device_api.hpp"
 #include "sizes.hpp"
@@ -9,8 +11,6 @@ namespace gsk {
 #define GS_DECL(N)                                                   \
     hipError_t launch_eval_##N(const EvalArgs&, hipStream_t, int);   \
     hipError_t launch_eval_g_##N(const EvalArgs&, hipStream_t, int); \
-    int energy_blocks_##N(int);                                      \
-    int energy_blocks_g_##N(int, int);                               \
     int tile_variants_##N();
 GS_SIZE_LIST(GS_DECL)
 #undef GS_DECL
@@ -19,24 +19,7 @@ static bool cubic(const EvalArgs& a) {
     return a.nx == a.n && a.ny == a.n && (a.d == 2 || a.nz == a.n);
 }
 
-int energy_blocks(int d, int nx, int ny, int nz) {
-    if (nx == ny && (d == 2 || nz == nx)) {
-        switch (nx) {
-#define GS_CASE(N) \
-    case N: return energy_blocks_##N(d);
-            GS_SIZE_LIST(GS_CASE)
-#undef GS_CASE
-            default: return 0;
-        }
-    }
-    switch (nx) {
-#define GS_CASE(N) \
-    case N: return energy_blocks_g_##N(ny, d == 3 ? nz : 1);
-        GS_SIZE_LIST(GS_CASE)
-#undef GS_CASE
-        default: return 0;
-    }
-}
+int energy_pencils(int d, int nx, int ny) { return d == 3 ? (nx + 1) * 2 * ny : nx + 1; }
 
 // One pass of a rectangular grid at the length of the axis it transforms.
 static hipError_t launch_pass_g(const EvalArgs& a, hipStream_t s, int pass) {
@@ -51,12 +34,19 @@ static hipError_t launch_pass_g(const EvalArgs& a, hipStream_t s, int pass) {
 }
 
 // One block: thread t sums part[t], part[t + 256], ... in order, then the fixed-order block
-// sum; the same bits on every run.
+// sum; the same bits on every run.  The loads are issued eight at a time (the additions keep
+// their order; a missing term adds 0).
 __global__ void __launch_bounds__(256) k_energy_finish(const double* __restrict__ part, int count, double scale,
                                                        double* __restrict__ energy) {
     __shared__ double red[4];
     double v = 0.0;
-    for (int i = threadIdx.x; i < count; i += 256) v += part[i];
+    for (int i0 = threadIdx.x; i0 < count; i0 += 8 * 256) {
+        double q[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) q[k] = (i0 + 256 * k < count) ? part[i0 + 256 * k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v += q[k];
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -67,6 +57,42 @@ __global__ void __launch_bounds__(256) k_energy_finish(const double* __restrict_
 hipError_t launch_energy_finish(const double* part, int count, double scale, double* energy, hipStream_t s) {
     k_energy_finish<<<1, 256, 0, s>>>(part, count, scale, energy);
     return hipGetLastError();
+}
+
+// First stage of the energy total over many partial sums: block b sums part[b chunk ..
+// (b + 1) chunk) as k_energy_finish does (thread order, then the waves in order) into out[b].
+__global__ void __launch_bounds__(256) k_energy_chunks(const double* __restrict__ part, int count, int chunk,
+                                                       double* __restrict__ out) {
+    __shared__ double red[4];
+    const int b0 = blockIdx.x * chunk, b1 = min(count, b0 + chunk);
+    double v = 0.0;
+    for (int i0 = b0 + (int)threadIdx.x; i0 < b1; i0 += 8 * 256) {
+        double q[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) q[k] = (i0 + 256 * k < b1) ? part[i0 + 256 * k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v += q[k];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+constexpr int kEnergyChunks = 256;
+
+int energy_total_scratch() { return kEnergyChunks; }
+
+hipError_t launch_energy_total(double* part, int count, double scale, double* energy, hipStream_t s) {
+    if (count <= 4096) return launch_energy_finish(part, count, scale, energy, s);
+    const int nb = std::min(kEnergyChunks, (count + 4095) / 4096);
+    const int chunk = (count + nb - 1) / nb;
+    double* sums = part + count;
+    k_energy_chunks<<<nb, 256, 0, s>>>(part, count, chunk, sums);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_energy_finish(sums, nb, scale, energy, s);
 }
 
 // One thread per point of a row of the transform grid (blockIdx.y = y, blockIdx.z = z).

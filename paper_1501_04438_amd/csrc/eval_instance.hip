@@ -56,7 +56,7 @@ template <int N> constexpr int pz_of(int v) {
     return P;
 }
 
-// P5 with row pairs PX per block, with the energy sum when the arguments ask for it.
+// P5 with row pairs PX per block; with the energy, the total of the fused pass's pencil sums.
 template <int PX>
 static hipError_t launch_x_inverse_v(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
@@ -65,16 +65,17 @@ static hipError_t launch_x_inverse_v(const EvalArgs& a, hipStream_t s) {
     const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
     const bool hint = (a.hint_bits >> 4) & 1;
     const dim3 gx((N + 2 * PX - 1) / (2 * PX), a.d == 3 ? N : 1);
-    if (a.energy) {
-        if (hint) k_x_c2r_energy<N, NT_P5, PX><<<gx, T, 0, s>>>(X1, a.u, tw, a.rho, a.epart, a.oscale);
-        else k_x_c2r_energy<N, 0, PX><<<gx, T, 0, s>>>(X1, a.u, tw, a.rho, a.epart, a.oscale);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        return launch_energy_finish(a.epart, (int)(gx.x * gx.y) * (PX / Geo<N>::PPX), a.escale, a.energy, s);
+    if (a.energy && a.oscale != 1.0) {
+        if (hint) k_x_c2r<N, NT_P5, PX, true><<<gx, T, 0, s>>>(X1, a.u, tw, a.oscale);
+        else k_x_c2r<N, 0, PX, true><<<gx, T, 0, s>>>(X1, a.u, tw, a.oscale);
+    } else {
+        if (hint) k_x_c2r<N, NT_P5, PX><<<gx, T, 0, s>>>(X1, a.u, tw);
+        else k_x_c2r<N, 0, PX><<<gx, T, 0, s>>>(X1, a.u, tw);
     }
-    if (hint) k_x_c2r<N, NT_P5, PX><<<gx, T, 0, s>>>(X1, a.u, tw);
-    else k_x_c2r<N, 0, PX><<<gx, T, 0, s>>>(X1, a.u, tw);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.energy) return e;
+    // the energy's pencil sums were written by the fused pass
+    return launch_energy_total(a.epart, a.epencils, a.escale, a.energy, s);
 }
 
 static hipError_t launch_x_inverse(const EvalArgs& a, hipStream_t s) {
@@ -145,6 +146,19 @@ static hipError_t launch_fused_v(const EvalArgs& a, hipStream_t s, const DipoleA
         const int np = a.kxn * 2 * N;
         const int groups = (np + PZ - 1) / PZ;
         const unsigned nb = gs_fused_persistent(3, N) ? fused_grid(groups, capf, a.fused_grid_mult) : (unsigned)groups;
+        if constexpr (PZ == pz_of<N>(0)) {
+            if (a.energy) {
+                // with the energy sum of every pencil (the default tile only)
+                if (a.dipolar) {
+                    if (hint) k_fused<N, 3, SPEC_DIPOLAR, NT_P3, PZ, true><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
+                    else k_fused<N, 3, SPEC_DIPOLAR, 0, PZ, true><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
+                } else {
+                    if (hint) k_fused<N, 3, SPEC_PLAIN, NT_P3, PZ, true><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
+                    else k_fused<N, 3, SPEC_PLAIN, 0, PZ, true><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
+                }
+                return hipGetLastError();
+            }
+        }
         if (a.dipolar) {
             if (hint) k_fused<N, 3, SPEC_DIPOLAR, NT_P3, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
             else k_fused<N, 3, SPEC_DIPOLAR, 0, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
@@ -159,6 +173,13 @@ static hipError_t launch_fused_v(const EvalArgs& a, hipStream_t s, const DipoleA
     cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
     const int np = N + 1;
     const unsigned nb = (unsigned)((np + PZ - 1) / PZ);
+    if constexpr (PZ == pz_of<N>(0)) {
+        if (a.energy) {
+            if (hint) k_fused<N, 2, SPEC_PLAIN, NT_P3, PZ, true><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip, a.epart);
+            else k_fused<N, 2, SPEC_PLAIN, 0, PZ, true><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip, a.epart);
+            return hipGetLastError();
+        }
+    }
     if (hint) k_fused<N, 2, SPEC_PLAIN, NT_P3, PZ><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip);
     else k_fused<N, 2, SPEC_PLAIN, 0, PZ><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip);
     return hipGetLastError();
@@ -166,7 +187,7 @@ static hipError_t launch_fused_v(const EvalArgs& a, hipStream_t s, const DipoleA
 
 static hipError_t launch_fused(const EvalArgs& a, hipStream_t s, const DipoleArgs& dip) {
     constexpr int N = GS_N;
-    const int v = (a.tile_bits >> 4) & 3;
+    const int v = a.energy ? 0 : (a.tile_bits >> 4) & 3;
     if (v == 1 && pz_of<N>(1) != pz_of<N>(0)) return launch_fused_v<pz_of<N>(1)>(a, s, dip);
     if (v == 2 && pz_of<N>(2) != pz_of<N>(0)) return launch_fused_v<pz_of<N>(2)>(a, s, dip);
     return launch_fused_v<pz_of<N>(0)>(a, s, dip);
@@ -179,17 +200,6 @@ int GS_CAT(tile_variants_, GS_N)() {
     return (px_of<N>(1) != px_of<N>(0) ? 1 : 0) | (py_of<N>(1) != py_of<N>(0) ? 2 : 0) |
            (py_of<N>(2) != py_of<N>(0) ? 4 : 0) | (pz_of<N>(1) != pz_of<N>(0) ? 8 : 0) |
            (pz_of<N>(2) != pz_of<N>(0) ? 16 : 0);
-}
-
-int GS_CAT(energy_blocks_, GS_N)(int d) {
-    constexpr int N = GS_N;
-    return (N + 2 * Geo<N>::PPX - 1) / (2 * Geo<N>::PPX) * (d == 3 ? N : 1);
-}
-
-// Rectangular grids (each axis its own n): x-pass blocks when N is the x length.
-int GS_CAT(energy_blocks_g_, GS_N)(int ny, int nz) {
-    constexpr int N = GS_N;
-    return (ny + 2 * Geo<N>::PPX - 1) / (2 * Geo<N>::PPX) * nz;
 }
 
 // Pass `pass` of a grid whose axes have their own n, N being the length the pass transforms
@@ -213,16 +223,17 @@ hipError_t GS_CAT(launch_eval_g_, GS_N)(const EvalArgs& a, hipStream_t s, int pa
             else k_x_r2c_g<N, 0><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw, ext);
             return hipGetLastError();
         }
-        if (a.energy) {
-            if (hint) k_x_c2r_g<N, NT_P5, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart, ext, a.oscale);
-            else k_x_c2r_g<N, 0, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, a.rho, a.epart, ext, a.oscale);
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            return launch_energy_finish(a.epart, (int)(gx.x * gx.y), a.escale, a.energy, s);
+        if (a.energy && a.oscale != 1.0) {
+            if (hint) k_x_c2r_g<N, NT_P5, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, ext, a.oscale);
+            else k_x_c2r_g<N, 0, true><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, ext, a.oscale);
+        } else {
+            if (hint) k_x_c2r_g<N, NT_P5, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, ext, 1.0);
+            else k_x_c2r_g<N, 0, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, ext, 1.0);
         }
-        if (hint) k_x_c2r_g<N, NT_P5, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, nullptr, nullptr, ext, 1.0);
-        else k_x_c2r_g<N, 0, false><<<gx, Gm::TX, 0, s>>>(X1, a.u, tw, nullptr, nullptr, ext, 1.0);
-        return hipGetLastError();
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !a.energy) return e;
+        // the energy's pencil sums were written by the fused pass
+        return launch_energy_total(a.epart, a.epencils, a.escale, a.energy, s);
     }
     DipoleArgs dip;
     for (int i = 0; i < 3; ++i) {
@@ -245,12 +256,23 @@ hipError_t GS_CAT(launch_eval_g_, GS_N)(const EvalArgs& a, hipStream_t s, int pa
             const cpx* const twz = reinterpret_cast<const cpx*>(a.twz);
             const int np = a.kxn * 2 * ext.ny;
             const unsigned nb = (unsigned)((np + Gm::PPZ - 1) / Gm::PPZ);
+            double* const ep = a.epart;
             if (a.dipolar) {
-                if (hint) k_fused_g<N, 3, SPEC_DIPOLAR, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
-                else k_fused_g<N, 3, SPEC_DIPOLAR, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+                if (a.energy) {
+                    if (hint) k_fused_g<N, 3, SPEC_DIPOLAR, NT_P3, true><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext, ep);
+                    else k_fused_g<N, 3, SPEC_DIPOLAR, 0, true><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext, ep);
+                } else {
+                    if (hint) k_fused_g<N, 3, SPEC_DIPOLAR, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+                    else k_fused_g<N, 3, SPEC_DIPOLAR, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+                }
             } else {
-                if (hint) k_fused_g<N, 3, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
-                else k_fused_g<N, 3, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+                if (a.energy) {
+                    if (hint) k_fused_g<N, 3, SPEC_PLAIN, NT_P3, true><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext, ep);
+                    else k_fused_g<N, 3, SPEC_PLAIN, 0, true><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext, ep);
+                } else {
+                    if (hint) k_fused_g<N, 3, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+                    else k_fused_g<N, 3, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X2, a.spec, twz, np, a.kx0, dip, ext);
+                }
             }
         } else {
             return hipErrorInvalidValue;
@@ -262,6 +284,11 @@ hipError_t GS_CAT(launch_eval_g_, GS_N)(const EvalArgs& a, hipStream_t s, int pa
     const cpx* const twy = reinterpret_cast<const cpx*>(a.twy);
     const int np = ext.nx + 1;
     const unsigned nb = (unsigned)((np + Gm::PPZ - 1) / Gm::PPZ);
+    if (a.energy) {
+        if (hint) k_fused_g<N, 2, SPEC_PLAIN, NT_P3, true><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, twy, np, 0, dip, ext, a.epart);
+        else k_fused_g<N, 2, SPEC_PLAIN, 0, true><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, twy, np, 0, dip, ext, a.epart);
+        return hipGetLastError();
+    }
     if (hint) k_fused_g<N, 2, SPEC_PLAIN, NT_P3><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, twy, np, 0, dip, ext);
     else k_fused_g<N, 2, SPEC_PLAIN, 0><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, twy, np, 0, dip, ext);
     return hipGetLastError();

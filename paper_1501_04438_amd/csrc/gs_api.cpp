@@ -316,11 +316,12 @@ gs_status eval_chain(gs_plan p, const double* in, double* out, int step, double*
     if (energy) {
         a.energy = energy;
         a.epart = p->epart;
+        a.epencils = gsk::energy_pencils(p->d, a.nx, a.ny);
         double cell = 1.0;
         for (int i = 0; i < p->d; ++i) cell *= 2.0 * p->Lc[i] / p->nc[i];
-        // the energy 1/2 cell sum rho u; with gradient the outputs are cell u (its rho
-        // gradient) and the sum 1/2 sum rho (cell u)
-        a.escale = gradient ? 0.5 : 0.5 * cell;
+        // the energy 1/2 cell sum rho u (the fused pass sums rho u); with gradient the outputs
+        // are cell u, its rho gradient
+        a.escale = 0.5 * cell;
         a.oscale = gradient ? cell : 1.0;
     }
     if (!p->X1) return fail(GS_ERR_INVALID_ARG, "plan created without a workspace (GS_PLAN_NO_WORKSPACE): "
@@ -639,7 +640,8 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
         }
         if (st == GS_OK) p->tw = p->twk[0];
         if (st == GS_OK && !no_ws &&
-            (e = hipMalloc(&p->epart, (size_t)gsk::energy_blocks(d, nk[0], nk[1], nk[2]) * sizeof(double))) !=
+            (e = hipMalloc(&p->epart, ((size_t)gsk::energy_pencils(d, nk[0], nk[1]) + gsk::energy_total_scratch()) *
+                                          sizeof(double))) !=
                 hipSuccess)
             st = fail(GS_ERR_OUT_OF_MEMORY, "hipMalloc(energy partial sums) failed");
         if (st == GS_OK && (e = hipMalloc(&p->mixpart, mixture_partial_doubles() * sizeof(double))) != hipSuccess)

@@ -188,14 +188,11 @@ k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
 // ---------------------------------------------------------------------------
 // P5: x-direction complex-to-real with cropping.  Inverse of P1 (unnormalised).
 // ---------------------------------------------------------------------------
-// EN: also returns this thread's part of sum_i rho_i u_i over the outputs it stores (rho
-// read at those outputs before they are written, so u may alias rho), in a fixed order, the
-// outputs (and the sum) taken times oscale (1 leaves them as they are).
-template <int N, int NT = NT_P5, bool EN = false, bool CUBE = true, int PX = Geo<N>::PPX>
-__device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> u,
-                                             gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
-                                             cpx* lds, gp<const double> erho = nullptr, Ext ext = Ext(),
-                                             double oscale = 1.0) {
+// SC: the outputs are stored times oscale (the rho gradient of the energy, cell u).
+template <int N, int NT = NT_P5, bool SC = false, bool CUBE = true, int PX = Geo<N>::PPX>
+__device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> u,
+                                           gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
+                                           cpx* lds, Ext ext = Ext(), double oscale = 1.0) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
     const int NY = CUBE ? N : ext.ny;          // rows (y) of a plane
@@ -239,23 +236,12 @@ __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<d
         for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], v[e]);
         lds_barrier();
     }
-    double part = 0.0;
     if (okA) {
         const size_t o = ((size_t)z * NY + rowA) * N;
         gp<double> ua = u + o;
-        if constexpr (EN) {
+        if constexpr (SC) {
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[e] = cscale(acc[e], oscale);
-            gp<const double> ra = erho + o;
-            double r0[E], r1[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int j = tA + G * e;
-                r0[e] = ra[j];
-                r1[e] = ra[(size_t)RS * N + j];
-            }
-#pragma unroll
-            for (int e = 0; e < E; ++e) part += r0[e] * acc[e].x + r1[e] * acc[e].y;
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -264,28 +250,6 @@ __device__ __forceinline__ double x_c2r_tile(gp<const cpx> __restrict__ X1, gp<d
             stg<(NT & 2) != 0>(ua + (size_t)RS * N + j, acc[e].y);
         }
     }
-    return part;
-}
-
-// Sum of one value per thread over a block of THREADS (a power of two) in a fixed order:
-// a xor butterfly within each wave, then the waves in index order (red: THREADS/64 slots).
-// Every thread of the block must call it; the result is valid in thread 0.
-template <int THREADS>
-__device__ __forceinline__ double block_sum(double v, double* red) {
-    constexpr int W = THREADS < 64 ? THREADS : 64;
-#pragma unroll
-    for (int o = W / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, W);
-    if constexpr (THREADS > 64) {
-        const int tid = threadIdx.x;
-        if ((tid & 63) == 0) red[tid >> 6] = v;
-        __syncthreads();
-        if (tid == 0) {
-            v = red[0];
-#pragma unroll
-            for (int w = 1; w < THREADS / 64; ++w) v += red[w];
-        }
-    }
-    return v;
 }
 
 // P5 of a cubic grid with the two halves of the padded inverse (h = 0, 1) on the two 32-lane
@@ -293,8 +257,8 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // and transforms both halves in turn), and the halves' sum is formed by a lane swap, each
 // lane then storing half of the pair's outputs (E/2 values of each row).  The same sums in
 // the same order as x_c2r_tile, so the same bits; two LDS areas per row pair.  For the
-// tiles whose PX G threads per half fill whole half-waves.  Returns the thread's part of
-// the energy sum (EN), as x_c2r_tile does.
+// tiles whose PX G threads per half fill whole half-waves.  The outputs are stored times
+// oscale with SC, as x_c2r_tile does.
 // Decided per length, so that every tile shape of a length (PPX and 2 PPX row pairs) has the
 // same layout: the default tile fills whole half-waves and the doubled tile's two LDS areas
 // per pair fit in the 160 KiB of a CU.
@@ -304,10 +268,10 @@ template <int N> constexpr bool p5_split_len() {
 template <int N, int PX> constexpr bool p5_split() { return p5_split_len<N>() && (PX * Geo<N>::G) % 32 == 0; }
 template <int N, int PX> constexpr int p5_threads() { return (p5_split<N, PX>() ? 2 : 1) * PX * Geo<N>::G; }
 
-template <int N, int NT, bool EN, int PX>
-__device__ __forceinline__ double x_c2r_tile_split(gp<const cpx> __restrict__ X1, gp<double> u,
-                                                   gp<const cpx> __restrict__ tw, int bx, int z, int tid, cpx* lds,
-                                                   gp<const double> erho, double oscale) {
+template <int N, int NT, bool SC, int PX>
+__device__ __forceinline__ void x_c2r_tile_split(gp<const cpx> __restrict__ X1, gp<double> u,
+                                                 gp<const cpx> __restrict__ tw, int bx, int z, int tid, cpx* lds,
+                                                 double oscale) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
     static_assert(p5_split<N, PX>(), "whole half-waves");
@@ -339,9 +303,7 @@ __device__ __forceinline__ double x_c2r_tile_split(gp<const cpx> __restrict__ X1
         v[e] = cmk(a.x - b.y, a.y + b.x);              // a + i b
     }
     fft_t<typename Gm::F, true>(v, tA, lds + (h * PP + pA) * A, tB, lds + (h * PP + pB) * A, tw, h);
-    const size_t o = ((size_t)z * N + rowA) * N;
-    gp<double> ua = u + o;
-    double part = 0.0;
+    gp<double> ua = u + ((size_t)z * N + rowA) * N;
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) {
         // lanes h = 0 end with the sum for element e, lanes h = 1 with that for e + E/2
@@ -350,71 +312,27 @@ __device__ __forceinline__ double x_c2r_tile_split(gp<const cpx> __restrict__ X1
         cpx r = cadd(a, b);
         const int j = tA + G * (h * (E / 2) + e);
         if (okA) {
-            if constexpr (EN) {
-                r = cscale(r, oscale);
-                part += erho[o + j] * r.x + erho[o + (size_t)RS * N + j] * r.y;
-            }
+            if constexpr (SC) r = cscale(r, oscale);
             stg<(NT & 2) != 0>(ua + j, r.x);
             stg<(NT & 2) != 0>(ua + (size_t)RS * N + j, r.y);
         }
     }
-    return part;
 }
 
-template <int N, int NT = NT_P5, int PX = Geo<N>::PPX>
+// P5; SC: the outputs stored times oscale (the energy's rho gradient cell u; the energy
+// itself is summed by the fused pass).
+template <int N, int NT = NT_P5, int PX = Geo<N>::PPX, bool SC = false>
 __global__ void __launch_bounds__((p5_threads<N, PX>())) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
-                                                               const cpx* __restrict__ tw) {
+                                                               const cpx* __restrict__ tw, double oscale = 1.0) {
     if constexpr (p5_split<N, PX>()) {
         __shared__ cpx lds[2 * PX * Geo<N>::A];
-        (void)x_c2r_tile_split<N, NT, false, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
-                                                 blockIdx.y, threadIdx.x, lds, nullptr, 1.0);
+        x_c2r_tile_split<N, NT, SC, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x, blockIdx.y,
+                                        threadIdx.x, lds, oscale);
     } else {
         __shared__ cpx lds[PX * Geo<N>::A];
-        x_c2r_tile<N, NT, false, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
-                                           blockIdx.y, threadIdx.x, true, lds);
+        x_c2r_tile<N, NT, SC, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                        blockIdx.y, threadIdx.x, true, lds, Ext(), oscale);
     }
-}
-
-// P5 with the energy sum: as k_x_c2r, plus sum rho u over the block's outputs into
-// part[block] (rho may alias u: each thread reads rho where it then writes u).
-// The partial sums are those of the default tile (PPX row pairs) whatever PX is: a block of
-// PX = k PPX pairs holds k default tiles, sums each over its own threads in the default order
-// and writes k partials where the k default blocks would, so the energy has the same bits
-// for every tile shape.
-// (With the split halves a default tile's threads are 2 PPX G consecutive threads, whole
-// waves, the same for every PX: its sum keeps its bits across tile shapes.)
-template <int N, int NT = NT_P5, int PX = Geo<N>::PPX>
-__global__ void __launch_bounds__((p5_threads<N, PX>())) k_x_c2r_energy(const cpx* __restrict__ X1, double* u,
-                                                                      const cpx* __restrict__ tw, const double* rho,
-                                                                      double* __restrict__ part, double oscale) {
-    constexpr bool SPL = p5_split<N, PX>();
-    static_assert(SPL == p5_split<N, Geo<N>::PPX>(), "one P5 layout for every tile shape of a length");
-    constexpr int P0 = Geo<N>::PPX, T0 = (SPL ? 2 : 1) * P0 * Geo<N>::G, NG = PX / P0, W = T0 < 64 ? T0 : 64;
-    static_assert(PX % P0 == 0 && (NG == 1 || T0 % 64 == 0), "whole default tiles of whole waves");
-    __shared__ cpx lds[(SPL ? 2 : 1) * PX * Geo<N>::A];
-    __shared__ double red[NG * (T0 / 64 + 1)];
-    double v;
-    if constexpr (SPL)
-        v = x_c2r_tile_split<N, NT, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
-                                              blockIdx.y, threadIdx.x, lds, (gp<const double>)rho, oscale);
-    else
-        v = x_c2r_tile<N, NT, true, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
-                                              blockIdx.y, threadIdx.x, true, lds, (gp<const double>)rho, Ext(),
-                                              oscale);
-    const int g = threadIdx.x / T0, local = threadIdx.x % T0;
-#pragma unroll
-    for (int o = W / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, W);
-    if constexpr (T0 > 64) {
-        double* r = red + g * (T0 / 64);
-        if ((local & 63) == 0) r[local >> 6] = v;
-        __syncthreads();
-        if (local == 0) {
-            v = r[0];
-#pragma unroll
-            for (int w = 1; w < T0 / 64; ++w) v += r[w];
-        }
-    }
-    if (local == 0) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NG + g] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -594,13 +512,54 @@ __device__ __forceinline__ void fused_spec(gp<const double> spec, int pencil, in
     }
 }
 
+// The energy sum of one pencil by Parseval's identity: with the folded spectrum S (1/M
+// included) the potential is the inverse transform of S rho^, so sum_x rho u over the grid is
+// sum_k S(k) |rho^(k)|^2 over the whole padded spectrum.  The x transform keeps kx = 0..NX of
+// its 2 NX values; the spectrum is even in every axis, so each kept plane other than kx = 0
+// and kx = NX stands for its mirror too (weight 2).  Each pencil's sum (acc over its threads,
+// in a fixed order) goes to part[index of the pencil in the whole grid], so the bits do not
+// depend on the launch shape.  Called by every thread of the block (the non-swap layout sums
+// the waves of a pencil through LDS behind block barriers).
+template <int N, int DIM>
+__device__ __forceinline__ void fused_energy_store(double acc, bool ok, int pencil, int kx0, int t, int h, int pl,
+                                                   int NX, int NY, gp<double> part) {
+    constexpr int G = Geo<N>::GZ;
+    if constexpr (FusedRoles<N>::SWAP) {
+        // a pencil: G lanes in each 32-lane half of one wave
+#pragma unroll
+        for (int o = G / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        acc += __shfl_xor(acc, 32, 64);
+    } else {
+        // a pencil: 2 G / 64 whole waves, each in one half
+        static_assert((2 * G) % 64 == 0, "whole waves per pencil");
+        constexpr int WP = 2 * G / 64;
+        __shared__ double red[16];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (t == 0 && h == 0) {
+            acc = red[pl * WP];
+#pragma unroll
+            for (int i = 1; i < WP; ++i) acc += red[pl * WP + i];
+        }
+        __syncthreads();
+    }
+    if (ok && t == 0 && h == 0) {
+        const int kx = (DIM == 3) ? kx0 + pencil / (2 * NY) : pencil;
+        const double w = (kx == 0 || kx == NX) ? 1.0 : 2.0;
+        part[(DIM == 3 ? (size_t)kx0 * 2 * NY : 0) + pencil] = w * acc;
+    }
+}
+
 // Transform, spectrum multiplication, inverse transform and even/odd combination
-// of one pencil held in v (spectrum values in sv); stores the pencil if ok.
-template <int N, int DIM, int MODE, int NT = NT_P3>
+// of one pencil held in v (spectrum values in sv); stores the pencil if ok.  EN: also the
+// pencil's energy sum into part (fused_energy_store).
+template <int N, int DIM, int MODE, int NT = NT_P3, bool EN = false>
 __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx> __restrict__ tw, int pencil, int kx0,
                                            bool ok, const DipoleArgs& dip, int t, int h, int pl,
                                            cpx (&v)[FftCfgFused<N>::E], const double (&sv)[FftCfgFused<N>::E],
-                                           cpx* lds, cpx* area, int NX, int NY) {
+                                           cpx* lds, cpx* area, int NX, int NY, gp<double> part = nullptr) {
     using Gm = Geo<N>;
     using FZ = typename Gm::FZ;
     constexpr int E = Gm::EZ, G = Gm::GZ, A = Gm::AZ;
@@ -608,6 +567,7 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
     // the odd half's padding twist rides in the transforms (fft, fft_t with h = 1)
     if (h) twist_const<FZ, false>(v);
     fft<FZ, false, FW>(v, t, area, t, area, tw, h);
+    double acc = 0.0;
     if constexpr (MODE == SPEC_DIPOLAR) {
         // (n.xi)(m.xi) with Nyquist taken as 0 in the odd (cross) factors
         const int kx = (DIM == 3) ? kx0 + pencil / (2 * NY) : pencil;
@@ -625,12 +585,18 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
             const double zo = (m == N) ? 0.0 : ze;
             const double f = dip.cdiag[0] * xe * xe + dip.cdiag[1] * ye * ye + dip.cdiag[2] * ze * ze +
                              dip.ccross[0] * xo * yo + dip.ccross[1] * xo * zo + dip.ccross[2] * yo * zo;
-            v[e] = cscale(v[e], f * sv[e] - dip.nm_over_M);
+            const double s = f * sv[e] - dip.nm_over_M;
+            if constexpr (EN) acc += s * (v[e].x * v[e].x + v[e].y * v[e].y);
+            v[e] = cscale(v[e], s);
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sv[e]);
+        for (int e = 0; e < E; ++e) {
+            if constexpr (EN) acc += sv[e] * (v[e].x * v[e].x + v[e].y * v[e].y);
+            v[e] = cscale(v[e], sv[e]);
+        }
     }
+    if constexpr (EN) fused_energy_store<N, DIM>(acc, ok, pencil, kx0, t, h, pl, NX, NY, part);
     lds_sync<FW>();
     fft_t<FZ, true, FW>(v, t, area, t, area, tw, h);
     gp<cpx> base = X + (size_t)pencil * N;
@@ -665,11 +631,11 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
 
 // One pencil group of the fused pass without prefetch (the batched launches).
 // PZ: pencils per block (a tile-shape variant: the same bits for every PZ)
-template <int N, int DIM, int MODE, int NT = NT_P3, bool CUBE = true, int PZ = Geo<N>::PPZ>
+template <int N, int DIM, int MODE, int NT = NT_P3, bool CUBE = true, int PZ = Geo<N>::PPZ, bool EN = false>
 __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const double> __restrict__ spec,
                                             gp<const cpx> __restrict__ tw, int npencils, int kx0,
                                             const DipoleArgs& dip, int g, int tid, bool active, cpx* lds,
-                                            Ext ext = Ext()) {
+                                            Ext ext = Ext(), gp<double> part = nullptr) {
     using Gm = Geo<N>;
     using FZ = typename Gm::FZ;
     constexpr int E = Gm::EZ, G = Gm::GZ, PP = PZ, A = Gm::AZ;
@@ -688,13 +654,14 @@ __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const dou
     double sv[E];
     fused_load<N, DIM, NT>(X, pencil, ok, t, v);
     fused_spec<N, DIM, NT>(spec, pencil, kx0, ok, t, h, sv, NY);
-    fused_body<N, DIM, MODE, NT>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area, NX, NY);
+    fused_body<N, DIM, MODE, NT, EN>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area, NX, NY, part);
 }
 
-template <int N, int DIM, int MODE, int NT = NT_P3, int PZ = Geo<N>::PPZ>
+// EN: also the energy sum of every pencil into part (fused_energy_store).
+template <int N, int DIM, int MODE, int NT = NT_P3, int PZ = Geo<N>::PPZ, bool EN = false>
 __global__ void __launch_bounds__(PZ * 2 * Geo<N>::GZ) k_fused(cpx* __restrict__ Xg, const double* __restrict__ specg,
                                                               const cpx* __restrict__ twg, int npencils, int kx0,
-                                                              DipoleArgs dip) {
+                                                              DipoleArgs dip, double* __restrict__ part = nullptr) {
     __shared__ cpx lds[PZ * 2 * Geo<N>::AZ];
     const int ngroups = (npencils + PZ - 1) / PZ;
     if constexpr (!gs_fused_persistent(DIM, N)) {
@@ -703,12 +670,14 @@ __global__ void __launch_bounds__(PZ * 2 * Geo<N>::GZ) k_fused(cpx* __restrict__
         // live across groups: at n = 2048 in 2D, 250 VGPRs instead of 256 + 154 accumulator
         // registers, two waves per SIMD instead of one
         if ((int)blockIdx.x < ngroups)
-            fused_group<N, DIM, MODE, NT, true, PZ>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
-                                                    npencils, kx0, dip, blockIdx.x, threadIdx.x, true, lds);
+            fused_group<N, DIM, MODE, NT, true, PZ, EN>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
+                                                        npencils, kx0, dip, blockIdx.x, threadIdx.x, true, lds, Ext(),
+                                                        (gp<double>)part);
     } else {
         for (int g = blockIdx.x; g < ngroups; g += gridDim.x)
-            fused_group<N, DIM, MODE, NT, true, PZ>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
-                                                    npencils, kx0, dip, g, threadIdx.x, true, lds);
+            fused_group<N, DIM, MODE, NT, true, PZ, EN>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
+                                                        npencils, kx0, dip, g, threadIdx.x, true, lds, Ext(),
+                                                        (gp<double>)part);
     }
 }
 
@@ -725,19 +694,12 @@ __global__ void __launch_bounds__(Geo<N>::TX) k_x_r2c_g(const double* __restrict
                              threadIdx.x, true, lds, ext);
 }
 
-template <int N, int NT, bool EN>
+template <int N, int NT, bool SC>
 __global__ void __launch_bounds__(Geo<N>::TX) k_x_c2r_g(const cpx* __restrict__ X1, double* u,
-                                                        const cpx* __restrict__ tw, const double* rho,
-                                                        double* __restrict__ part, Ext ext, double oscale) {
+                                                        const cpx* __restrict__ tw, Ext ext, double oscale) {
     __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
-    __shared__ double red[Geo<N>::TX / 64 + 1];
-    const double v = x_c2r_tile<N, NT, EN, false>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
-                                                  blockIdx.y, threadIdx.x, true, lds, (gp<const double>)rho, ext,
-                                                  oscale);
-    if constexpr (EN) {
-        const double s = block_sum<Geo<N>::TX>(v, red);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
-    }
+    x_c2r_tile<N, NT, SC, false>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x, blockIdx.y,
+                                 threadIdx.x, true, lds, ext, oscale);
 }
 
 template <int N, int NT>
@@ -756,15 +718,16 @@ __global__ void __launch_bounds__(Geo<N>::TY) k_y_inv_g(const cpx* __restrict__ 
                              threadIdx.x, true, lds, ext);
 }
 
-template <int N, int DIM, int MODE, int NT>
+template <int N, int DIM, int MODE, int NT, bool EN = false>
 __global__ void __launch_bounds__(Geo<N>::TZ) k_fused_g(cpx* __restrict__ Xg, const double* __restrict__ specg,
                                                         const cpx* __restrict__ twg, int npencils, int kx0,
-                                                        DipoleArgs dip, Ext ext) {
+                                                        DipoleArgs dip, Ext ext, double* __restrict__ part = nullptr) {
     __shared__ cpx lds[Geo<N>::PPZ * 2 * Geo<N>::AZ];
     const int ngroups = (npencils + Geo<N>::PPZ - 1) / Geo<N>::PPZ;
     if ((int)blockIdx.x < ngroups)
-        fused_group<N, DIM, MODE, NT, false>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg, npencils, kx0,
-                                             dip, blockIdx.x, threadIdx.x, true, lds, ext);
+        fused_group<N, DIM, MODE, NT, false, Geo<N>::PPZ, EN>((gp<cpx>)Xg, (gp<const double>)specg,
+                                                              (gp<const cpx>)twg, npencils, kx0, dip, blockIdx.x,
+                                                              threadIdx.x, true, lds, ext, (gp<double>)part);
 }
 
 }  // namespace gsk

@@ -156,18 +156,23 @@ def test_adjoint_against_oracle_transpose(kernel, d, n, L, kw):
 
 @pytest.mark.parametrize("kernel,d,n,L", [("coulomb3d", 3, 12, 4.0), ("coulomb3d", 3, 24, (3.0, 4.0, 5.0)),
                                           ("dipolar3d", 3, 96, 8.0), ("coulomb3d", 3, 256, 10.0),
-                                          ("poisson2d", 2, 48, 7.0), ("coulomb2d", 2, 2048, 12.0)])
-def test_energy_formed_in_the_last_pass(kernel, d, n, L):
-    """gs_eval_energy: u bitwise that of gs_eval; E = 1/2 cell sum rho u against a float64
-    sum of the same product (1e-14 of sum |1/2 cell rho u|) and against the oracle's energy
-    (small grids); the same bits on repeated calls and with u aliasing rho."""
+                                          ("dipolar3d", 3, 256, 10.0), ("coulomb3d", 3, (24, 32, 16), (3.0, 4.0, 2.0)),
+                                          ("dipolar3d", 3, (16, 24, 32), (2.0, 3.0, 4.0)),
+                                          ("poisson2d", 2, 48, 7.0), ("poisson2d", 2, (24, 40), (3.0, 5.0)),
+                                          ("coulomb2d", 2, 1024, 12.0), ("coulomb2d", 2, 2048, 12.0)])
+def test_energy_formed_in_the_fused_pass(kernel, d, n, L):
+    """gs_eval_energy (the sum by Parseval's identity in the fused pass): u bitwise that of
+    gs_eval; E = 1/2 cell sum rho u against a float64 sum of the same product in space
+    (1e-14 of sum |1/2 cell rho u|) and against the oracle's energy (small grids); the same
+    bits on repeated calls and with u aliasing rho.  Cubic and per-axis grids, the dipolar
+    multiplier, and pencils of one wave, of parts of a wave and of several waves."""
     print(f"energy: {kernel} n={n} L={L}", flush=True)
     kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
     if kernel == "poisson2d":
         kw["eps"] = 1e-13
     plan = gs.Plan(kernel, n=n, L=L, **kw)
-    rng = np.random.default_rng(800 + n)
-    x = rng.standard_normal((n,) * d)
+    rng = np.random.default_rng(800 + plan.n)
+    x = rng.standard_normal(plan.shape)
     rho = torch.from_numpy(x).to("cuda:0")
     u_ref = plan.eval(rho)
     u, E = plan.eval_energy(rho)
@@ -182,9 +187,49 @@ def test_energy_formed_in_the_last_pass(kernel, d, n, L):
     _, E3 = plan.eval_energy(y, out=y)
     torch.cuda.synchronize()
     assert torch.equal(y, u_ref) and torch.equal(E3, E)
-    if n <= 48:
+    if plan.n <= 48:
         Eo = oracle.energy(oracle.make_plan(kernel, d, n, L, **kw), x)
         assert abs(float(E) - Eo) <= 1e-13 * float(prod.abs().sum())
+
+
+@pytest.mark.parametrize("kernel,n", [("coulomb3d", 128), ("dipolar3d", 128), ("coulomb3d", 256)])
+def test_energy_same_bits_for_every_launch_shape(kernel, n):
+    """The energy's partials belong to pencils, not to blocks: the same bits for the default
+    launch, other tile shapes and cache hints, and a split into kx slabs (three slabs, also
+    on side streams; at n = 256 the persistent fused grid then covers a third of the
+    pencils per launch)."""
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    rng = np.random.default_rng(91)
+    rho = torch.from_numpy(rng.standard_normal((n, n, n))).to("cuda:0")
+    base = gs.Plan(kernel, n=n, L=8.0, **kw)
+    u0, E0 = base.eval_energy(rho)
+    torch.cuda.synchronize()
+    variants = [dict(tile_variants=0x59), dict(hint_bits=0), dict(slab_planes=n // 3 + 1),
+                dict(slab_planes=n // 3 + 1, slab_streams=2)]
+    for v in variants:
+        print(f"energy launch shape: {kernel} {v}", flush=True)
+        plan = gs.Plan(kernel, n=n, L=8.0, **kw, **v)
+        u, E = plan.eval_energy(rho)
+        torch.cuda.synchronize()
+        assert torch.equal(u, u0), v
+        assert torch.equal(E, E0), v
+
+
+def test_energy_padding3_against_oracle():
+    """The energy of a plan padded to B_3 (the pencils of the 3n/2 transform grid) against the
+    float64 sum in space and the oracle's energy with the same padding."""
+    n, L = 32, 4.0
+    plan = gs.Plan("coulomb3d", n=n, L=L, padding=3)
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal((n, n, n))
+    rho = torch.from_numpy(x).to("cuda:0")
+    u, E = plan.eval_energy(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(u, plan.eval(rho))
+    prod = 0.5 * plan.cell * (rho * u)
+    assert abs(float(E) - float(prod.sum())) <= 1e-14 * float(prod.abs().sum())
+    Eo = oracle.energy(oracle.make_plan("coulomb3d", 3, n, L, padding=3), x)
+    assert abs(float(E) - Eo) <= 1e-13 * float(prod.abs().sum())
 
 
 MIX_CASES = [("coulomb3d", 3, 32, 10.0, 8), ("coulomb3d", 3, 48, (6.0, 8.0, 10.0), 11),
@@ -229,8 +274,8 @@ def test_mixture_path_against_oracle(kernel, d, n, L, K):
                                           ("poisson2d", 2, 512, 8.0)])
 def test_energy_and_gradient_in_one_evaluation(kernel, d, n, L):
     """gs_eval_energy_gradient: the gradient cell * u written by the last pass is bitwise the
-    product of the cell volume and gs_eval's u; the energy agrees with gs_eval_energy's to
-    1e-14 of sum |1/2 cell rho u|; repeatable; the gradient may overwrite rho."""
+    product of the cell volume and gs_eval's u; the energy is gs_eval_energy's, bit for bit
+    (both summed in the fused pass); repeatable; the gradient may overwrite rho."""
     kw = {"eps": 1e-13} if kernel == "poisson2d" else {}
     plan = gs.Plan(kernel, n=n, L=L, **kw)
     rng = np.random.default_rng(44)
@@ -239,8 +284,7 @@ def test_energy_and_gradient_in_one_evaluation(kernel, d, n, L):
     E, g = plan.energy_and_gradient(rho)
     torch.cuda.synchronize()
     assert torch.equal(g, plan.cell * u)
-    prod = 0.5 * plan.cell * (rho * u)
-    assert abs(float(E) - float(E1)) <= 1e-14 * float(prod.abs().sum())
+    assert torch.equal(E, E1)
     E2, _ = plan.energy_and_gradient(rho)
     assert torch.equal(E2, E)
     y = rho.clone()
