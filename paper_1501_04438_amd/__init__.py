@@ -221,9 +221,9 @@ class Plan:
                                        C.c_void_p(sigma.data_ptr()), C.c_void_p(rho.data_ptr())))
         return rho
 
-    def mixture_gradient(self, a, mu, sigma, g, scale: float = 1.0):
+    def mixture_gradient(self, a, mu, sigma, g, scale: float = 1.0, flat: bool = False):
         """(d/da, d/dmu, d/dsigma) of a scalar whose grid gradient is scale * g, through the mixture
-        density (the library's fixed-order reduction)."""
+        density (the library's fixed-order reduction); flat: the K (d + 2) values in one tensor."""
         torch = _torch()
         a, mu, sigma = (t.detach().contiguous() for t in (a, mu, sigma))
         self._check_tensor(g, "g")
@@ -233,6 +233,8 @@ class Plan:
         check(lib().gs_mixture_gradient(self._h, K, C.c_void_p(a.data_ptr()), C.c_void_p(mu.data_ptr()),
                                         C.c_void_p(sigma.data_ptr()), C.c_void_p(g.data_ptr()), float(scale),
                                         C.c_void_p(out.data_ptr())))
+        if flat:
+            return out
         return out[:K], out[K:K + K * d].view(K, d), out[K + K * d:]
 
     def eval_energy(self, rho, out=None):
@@ -465,8 +467,10 @@ def _make_function():
         @staticmethod
         def backward(ctx, grad_e):
             a, mu, sigma, u = ctx.saved_tensors
-            ga, gmu, gs_ = ctx.plan.mixture_gradient(a, mu, sigma, u, ctx.plan.cell)
-            return ga * grad_e, gmu * grad_e, gs_ * grad_e, None
+            # the three gradients in one buffer: one product scales them all
+            out = ctx.plan.mixture_gradient(a, mu, sigma, u, ctx.plan.cell, flat=True) * grad_e
+            K, d = a.numel(), ctx.plan.d
+            return out[:K], out[K:K + K * d].view(K, d), out[K + K * d:], None
 
     return GSPotential, GSEnergy, GSMixtureEnergy
 
