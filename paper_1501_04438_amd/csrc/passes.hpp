@@ -439,10 +439,11 @@ __global__ void __launch_bounds__(PY * Geo<N>::G) k_y_inv(const cpx* __restrict_
 // (h = 1) half of the padded spectrum.  DIM = 3: pencils X2[kx][ky][:],
 // spectrum row S[kx][|ky|][:]; DIM = 2: pencils X1[kx][:], row S[kx][:].
 //
-// Lane roles: a pencil's G-thread halves sit in one wave at lanes l and l + 32
-// (G <= 32), so the even/odd combination after the inverse is a cross-half lane
-// swap (v_permlane32_swap) and an add, with no LDS round trip; for G > 32 the
-// halves are combined through LDS.  Persistent: a block walks pencil groups
+// Lane roles: a pencil's G-thread halves sit at lanes l and l + 32 of the same waves
+// (G <= 32: one wave; G = 128: four waves, each holding 32 threads of both halves), so the
+// even/odd combination after the inverse is a cross-half lane swap (v_permlane32_swap) and
+// an add, with no LDS round trip; at G = 64 each half fills one wave (its exchanges then
+// need no block barrier) and the halves are combined through LDS.  Persistent: a block walks pencil groups
 // g = blockIdx.x, + gridDim.x, ...  (No register prefetch: the registers it needs
 // cost a wave per SIMD, which hides more latency than the prefetch did.)  In 3D
 // the pencils of a kx plane are visited in the order ky = 0, n, 1, 2n-1, 2,
@@ -451,14 +452,22 @@ __global__ void __launch_bounds__(PY * Geo<N>::G) k_y_inv(const cpx* __restrict_
 // ---------------------------------------------------------------------------
 template <int N> struct FusedRoles {
     static constexpr int G = Geo<N>::GZ;
-    static constexpr bool SWAP = (G <= 32);
+    // (G = 128: 2D n = 1024, 2048 and the 3D n = 1024 fused plan; the lane swap saves the
+    // LDS round trip and two block barriers per pencil: 0.057 -> 0.055 ms at 2D 2048^2)
+    static constexpr bool SWAP = (G <= 32) || (G % 128 == 0);
     // t: thread within its half-transform, h: half (0 even, 1 odd), pl: pencil in the block
     __device__ __forceinline__ static void get(int tid, int& t, int& h, int& pl) {
-        if constexpr (SWAP) {
+        if constexpr (G <= 32) {
             const int w = tid >> 6, l = tid & 63;
             h = l >> 5;
             t = l % G;
             pl = w * (32 / G) + (l & 31) / G;
+        } else if constexpr (SWAP) {
+            constexpr int WPP = G / 32;
+            const int w = tid >> 6, l = tid & 63;
+            h = l >> 5;
+            pl = w / WPP;
+            t = (w % WPP) * 32 + (l & 31);
         } else {
             t = tid % G;
             h = (tid / G) & 1;
@@ -518,19 +527,19 @@ __device__ __forceinline__ void fused_spec(gp<const double> spec, int pencil, in
 // its 2 NX values; the spectrum is even in every axis, so each kept plane other than kx = 0
 // and kx = NX stands for its mirror too (weight 2).  Each pencil's sum (acc over its threads,
 // in a fixed order) goes to part[index of the pencil in the whole grid], so the bits do not
-// depend on the launch shape.  Called by every thread of the block (the non-swap layout sums
-// the waves of a pencil through LDS behind block barriers).
+// depend on the launch shape.  Called by every thread of the block (for G > 32 a pencil's
+// waves are summed through LDS behind block barriers).
 template <int N, int DIM>
 __device__ __forceinline__ void fused_energy_store(double acc, bool ok, int pencil, int kx0, int t, int h, int pl,
                                                    int NX, int NY, gp<double> part) {
     constexpr int G = Geo<N>::GZ;
-    if constexpr (FusedRoles<N>::SWAP) {
+    if constexpr (G <= 32) {
         // a pencil: G lanes in each 32-lane half of one wave
 #pragma unroll
         for (int o = G / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
         acc += __shfl_xor(acc, 32, 64);
     } else {
-        // a pencil: 2 G / 64 whole waves, each in one half
+        // a pencil: 2 G / 64 whole waves (one half each at G = 64, both halves at G = 128)
         static_assert((2 * G) % 64 == 0, "whole waves per pencil");
         constexpr int WP = 2 * G / 64;
         __shared__ double red[16];
