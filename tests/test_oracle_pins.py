@@ -18,7 +18,7 @@ import workloads
 from oracle import closed_forms as cf
 from oracle import dft, gs_table
 from oracle.factors import factor_1d
-from oracle.evaluate import periodic_laplacian
+from oracle.evaluate import full_spectrum, laplacian_symbol, periodic_laplacian
 from oracle.taylor import taylor_constants
 
 
@@ -982,3 +982,29 @@ def test_padding3_separable_dft_equals_full_dft_and_needs_even_n():
         assert relmax(dft.forward(x, p=3), dft.full_dft(x, p=3)) < 1e-13
     with pytest.raises(ValueError):
         oracle.make_plan("coulomb3d", 3, 9, 2.0, padding=3)
+
+
+@pytest.mark.parametrize("kernel,d,n,L", [("coulomb3d", 3, 16, 4.0), ("coulomb3d", 3, (8, 12, 16), (2.0, 3.0, 4.0)),
+                                          ("poisson2d", 2, 24, 6.0)])
+def test_energy_parseval_reading(kernel, d, n, L):
+    """The energy's Fourier-side reading: with u = crop(IDFT(S rho^) / M) on the padded grid
+    (S = G + A0 - c2 |xi|^2, the oracle's own steps), sum_x rho u = (1/M) sum_k S |rho^|^2, and
+    over the kept half kx = 0..n of the real transform the planes kx = 0 and kx = n count once,
+    the others twice (S is even in every axis).  Checked against the oracle's energy by the
+    grid sum in space (numpy FFTs, not the oracle's transforms)."""
+    kw = {"eps": 1e-13} if kernel == "poisson2d" else {}
+    plan = oracle.make_plan(kernel, d, n, L, **kw)
+    rng = np.random.default_rng(5)
+    rho = rng.standard_normal(plan.ns)
+    E = oracle.energy(plan, rho)
+    pad = np.zeros(tuple(2 * m for m in plan.ns))
+    pad[tuple(slice(0, m) for m in plan.ns)] = rho
+    S = full_spectrum(plan) + plan.A0 - plan.c2 * laplacian_symbol(plan)
+    nx = plan.ns[-1]
+    R = np.fft.rfftn(pad)                               # kx = 0..nx kept (last axis)
+    w = np.full(nx + 1, 2.0)
+    w[0] = w[nx] = 1.0
+    M = float(np.prod(pad.shape))
+    E_f = 0.5 * plan.cell * float(np.sum(w * S[..., :nx + 1] * np.abs(R) ** 2)) / M
+    scale = 0.5 * plan.cell * float(np.sum(np.abs(rho * oracle.evaluate(plan, rho))))
+    assert abs(E_f - E) <= 1e-14 * scale, (E_f, E)
