@@ -67,11 +67,18 @@ __host__ __device__ constexpr int batch_counter(int prob, int pass) { return 1 +
 __device__ __forceinline__ int hw_xcc_id() { return (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
 
 // Threads and LDS slots of one tile of pass p at size N; tiles per problem.
+// P5 tiles take the single-problem kernel's split form where it has one (the two halves of
+// the padded inverse on the two lane halves of every wave: twice the threads and LDS areas
+// per tile, the same LDS per block, E complex values fewer live per thread).
 template <int N> __host__ __device__ constexpr int tile_threads(int pass) {
-    return (pass == 1 || pass == 5) ? Geo<N>::TX : (pass == 3 ? Geo<N>::TZ : Geo<N>::TY);
+    return pass == 1 ? Geo<N>::TX
+                     : (pass == 5 ? p5_threads<N, Geo<N>::PPX>() : (pass == 3 ? Geo<N>::TZ : Geo<N>::TY));
 }
 template <int N> __host__ __device__ constexpr int tile_lds(int pass) {
-    return pass == 3 ? 2 * Geo<N>::PPZ * Geo<N>::AZ : ((pass == 1 || pass == 5) ? Geo<N>::PPX : Geo<N>::PPY) * Geo<N>::A;
+    return pass == 3   ? 2 * Geo<N>::PPZ * Geo<N>::AZ
+           : pass == 1 ? Geo<N>::PPX * Geo<N>::A
+           : pass == 5 ? (p5_split<N, Geo<N>::PPX>() ? 2 : 1) * Geo<N>::PPX * Geo<N>::A
+                       : Geo<N>::PPY * Geo<N>::A;
 }
 template <int N> __host__ __device__ inline int tile_count(int pass, int d) {
     using Gm = Geo<N>;
@@ -125,7 +132,9 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& P, int tile0, int
     if constexpr (PASS == 1 || PASS == 5) {
         constexpr int nbx = (N + 2 * Gm::PPX - 1) / (2 * Gm::PPX);
         const int bx = tile % nbx, z = tile / nbx;
-        if constexpr (PASS == 1) x_r2c_tile<N>(rho, X1, tw, bx, z, tid, active, l);
+        if constexpr (PASS == 1) x_r2c_tile<N, NT_P1, true, Gm::PPX, true>(rho, X1, tw, bx, z, tid, active, l);
+        else if constexpr (p5_split<N, Gm::PPX>())
+            x_c2r_tile_split<N, NT_P5, false, Gm::PPX>(X1, u, tw, bx, z, tid, l, 1.0, active);
         else x_c2r_tile<N>(X1, u, tw, bx, z, tid, active, l);
     } else if constexpr (PASS == 2 || PASS == 4) {
         constexpr int nbz = (N + Gm::PPY - 1) / Gm::PPY;
@@ -177,9 +186,17 @@ __device__ __forceinline__ void batch_task(const BatchProblem& P, const BatchTas
     }
 }
 
+// The union kernels (every size's tile code in one function) are held to three waves per
+// SIMD, which their LDS (three blocks per CU) allows: 168 VGPRs with a few dozen bytes of
+// spill in the 96-point dipolar fused code, against 225 VGPRs (two waves) unbounded; the tile
+// codes keep fewer values live for this (P1 loads its rows again for the second half, P5
+// runs the split form).  Measured on the 64-problem workload: queue 2.66 -> 2.52 ms, phased
+// 2.52 -> 2.41 ms, the same bits.
+constexpr int BATCH_UNION_WAVES = 3;
+
 // Phased schedule: the tasks of one pass, block-strided.
 template <int PASS>
-__global__ void __launch_bounds__(BATCH_THREADS) k_batch_pass(const BatchProblem* __restrict__ probs,
+__global__ void __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(BATCH_UNION_WAVES))) k_batch_pass(const BatchProblem* __restrict__ probs,
                                                               const BatchTask* __restrict__ tasks, int ntasks) {
     __shared__ cpx lds[batch_lds_slots()];
     for (int k = blockIdx.x; k < ntasks; k += gridDim.x) {
@@ -218,7 +235,7 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_size(const BatchProblem
 // A dependency wait gives up after spin_limit polls (far beyond any task's
 // duration): it raises the error flag ctr[nctr] and carries on, so every wave
 // reaches the end of the launch whatever happens; the host reads the flag.
-__global__ void __launch_bounds__(BATCH_THREADS) k_batch_queue(const BatchProblem* __restrict__ probs,
+__global__ void __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(BATCH_UNION_WAVES))) k_batch_queue(const BatchProblem* __restrict__ probs,
                                                                const BatchTask* __restrict__ tasks, BatchQueues Q,
                                                                unsigned* __restrict__ ctr, int nctr,
                                                                unsigned spin_limit) {

@@ -105,7 +105,10 @@ struct Ext {
 // ---------------------------------------------------------------------------
 // PX: row pairs per block (a tile-shape variant; the pairing of rows is the same for every PX,
 // so every variant computes the same bits)
-template <int N, int NT = NT_P1, bool CUBE = true, int PX = Geo<N>::PPX>
+// RL: the rows are loaded again for the second half instead of being kept in registers across
+// both (same values, same bits; E fewer complex values live through the first half's transform,
+// which the batched kernels, sized for every length at once, need for their occupancy)
+template <int N, int NT = NT_P1, bool CUBE = true, int PX = Geo<N>::PPX, bool RL = false>
 __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp<cpx> __restrict__ X1,
                                            gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
                                            cpx* lds, Ext ext = Ext()) {
@@ -128,8 +131,8 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
     const int rowA = SPLIT ? y0 + 16 * (pA / 8) + pA % 8 : y0 + 2 * pA;
     const int rowB = SPLIT ? y0 + 16 * (pB / 8) + pB % 8 : y0 + 2 * pB;
 
-    cpx x[E];
-    {
+    cpx x[RL ? 1 : E];
+    if constexpr (!RL) {
         gp<const double> ra = rho + ((size_t)z * NY + rowA) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -141,8 +144,20 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         cpx v[E];
+        if constexpr (RL) {
+            const double* rb = (const double*)rho;
+            // an opaque base for the second load, so that it is not merged with the first
+            if (h) asm volatile("" : "+s"(rb));
+            gp<const double> ra = (gp<const double>)rb + ((size_t)z * NY + rowA) * N;
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = x[e];
+            for (int e = 0; e < E; ++e) {
+                const int j = tA + G * e;
+                v[e] = okA ? cmk(ldg<NT & 1>(ra + j), ldg<NT & 1>(ra + (size_t)RS * N + j)) : cmk(0.0, 0.0);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = x[e];
+        }
         // the separate twist measured faster here than the twisted roots (its h = 1 roots
         // of the 16 x 16 plan double the stage-2 power products in the unrolled h loop)
         if (h) twist_in<typename Gm::F>(v, tA, tw);
@@ -271,7 +286,7 @@ template <int N, int PX> constexpr int p5_threads() { return (p5_split<N, PX>() 
 template <int N, int NT, bool SC, int PX>
 __device__ __forceinline__ void x_c2r_tile_split(gp<const cpx> __restrict__ X1, gp<double> u,
                                                  gp<const cpx> __restrict__ tw, int bx, int z, int tid, cpx* lds,
-                                                 double oscale) {
+                                                 double oscale, bool active = true) {
     using Gm = Geo<N>;
     constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
     static_assert(p5_split<N, PX>(), "whole half-waves");
@@ -281,7 +296,7 @@ __device__ __forceinline__ void x_c2r_tile_split(gp<const cpx> __restrict__ X1, 
     const int pB = tq % PP, tB = tq / PP;       // load role: consecutive y
     const int y0 = bx * 2 * PP;
     constexpr bool FULL = (N % (2 * PP) == 0);
-    const bool okA = FULL || (y0 + 2 * pA) < N, okB = FULL || (y0 + 2 * pB) < N;
+    const bool okA = active && (FULL || (y0 + 2 * pA) < N), okB = active && (FULL || (y0 + 2 * pB) < N);
     constexpr bool SPLIT = FULL && Gm::PPX % 8 == 0 && PP % 8 == 0;
     constexpr int RS = SPLIT ? 8 : 1;
     const int rowA = SPLIT ? y0 + 16 * (pA / 8) + pA % 8 : y0 + 2 * pA;
