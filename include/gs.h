@@ -143,8 +143,13 @@ typedef struct {
                                 block; bits 6-7: x-inverse pass, as bits 0-1); 0 = the
                                 compiled defaults.  Compiled for n >= 128 where the LDS
                                 allows, ignored elsewhere and on grids whose axes differ;
-                                every value gives the same bits.  GS_PLAN_AUTOTUNE picks
-                                them by timing                                   */
+                                every such value gives the same bits.  Bit 8: the fused
+                                pass on its radix-plan variant (n = 128, 256, 512, 1024,
+                                2048: 16 values per thread where the default holds 8, 8
+                                where it holds 16; bits 4-5 then ignored), which agrees
+                                with the default to rounding, not bitwise; a plan with
+                                it is batched only by its own launches.
+                                GS_PLAN_AUTOTUNE picks them by timing            */
     int launch_hints;        /* 1 + the cache-hint bits of the passes (bit p-1 set: pass p
                                 uses its non-temporal hint variant, gs_plan_info.hint_bits);
                                 0 = the compiled default.  Every value gives the same bits;
@@ -365,7 +370,7 @@ typedef struct gs_batch_s* gs_batch;
 
 typedef struct {
     int schedule;        /* gs_schedule                                               */
-    int tiles_per_task;  /* block-fulls of tiles per task (>= 1); 0 = default (queue 16,
+    int tiles_per_task;  /* block-fulls of tiles per task (>= 1); 0 = default (queue 8,
                             phased 4) or tuned                                        */
     int grid;            /* persistent blocks; 0 = as many as can be co-resident.  The
                             queue schedule with per-die queues raises a smaller grid to

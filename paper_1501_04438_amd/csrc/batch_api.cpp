@@ -67,7 +67,7 @@ bool own_launches(int schedule) { return schedule == GS_SCHED_SEQUENTIAL || sche
 // orders of magnitude beyond the longest task).
 constexpr unsigned kSpinLimit = 1u << 22;
 // Default block-fulls of tiles per task of the queue schedule.
-constexpr int kQueueTilesPerTask = 16;
+constexpr int kQueueTilesPerTask = 8;
 
 std::mutex g_batch_mu;
 std::unordered_set<gs_batch_s*> g_batches;
@@ -385,8 +385,8 @@ gs_status autotune(gs_batch_s* b, const std::vector<gsk::BatchMember>& m, const 
     }
     std::vector<TuneEntry> cand;
     if (b->kernels_ok) {
-        for (int mult : {4, 16, 64}) cand.push_back({GS_SCHED_QUEUE, mult, 1, 0, 0.0});
-        for (int mult : {1, 4, 16}) cand.push_back({GS_SCHED_PHASED, mult, 1, 0, 0.0});
+        for (int mult : {4, 8, 16, 64}) cand.push_back({GS_SCHED_QUEUE, mult, 1, 0, 0.0});
+        for (int mult : {1, 2, 4, 16}) cand.push_back({GS_SCHED_PHASED, mult, 1, 0, 0.0});
         for (int mult : {1, 4}) cand.push_back({GS_SCHED_SIZED, mult, 1, 0, 0.0});
         for (int mult : {1, 4}) cand.push_back({GS_SCHED_CONCURRENT, mult, 1, 0, 0.0});
     }
@@ -449,6 +449,16 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
             if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED ||
                 opt.schedule == GS_SCHED_CONCURRENT)
                 return fail(GS_ERR_INVALID_ARG, "a batched plan must run its middle passes in one slab");
+            kernels_ok = false;
+        }
+        // the batched kernels run the fused pass's default radix plan: a plan on the variant
+        // (which rounds differently) keeps the schedules that run its own launches
+        if (p->cube && (p->tile_bits & 256)) {
+            if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED ||
+                opt.schedule == GS_SCHED_CONCURRENT)
+                return fail(GS_ERR_INVALID_ARG,
+                            "a plan on the fused pass's radix-plan variant is batched by its own launches only "
+                            "(sequential or streams schedule)");
             kernels_ok = false;
         }
     }

@@ -130,41 +130,42 @@ static hipError_t launch_y(const EvalArgs& a, hipStream_t s, int pass) {
     return launch_y_v<py_of<N>(0)>(a, s, pass);
 }
 
-// Fused pass with PZ pencils per block (3D: persistent rounds at n = 256; 2D: one block per
-// pencil group).
-template <int PZ>
+// Fused pass with PZ pencils per block on radix plan RV (3D: persistent rounds at n = 256;
+// 2D: one block per pencil group).  The energy instances exist for each plan's default tile.
+template <int PZ, int RV = 0>
 static hipError_t launch_fused_v(const EvalArgs& a, hipStream_t s, const DipoleArgs& dip) {
     constexpr int N = GS_N;
-    constexpr int T = PZ * 2 * Geo<N>::GZ;
+    constexpr int T = PZ * 2 * GeoZ<N, RV>::GZ;
+    constexpr bool ETILE = (PZ == GeoZ<N, RV>::PPZ);
     const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
     const bool hint = (a.hint_bits >> 2) & 1;
     if constexpr (N <= GS_MAX_N_3D) {
       if (a.d == 3) {
         cpx* const X2 = reinterpret_cast<cpx*>(a.X2);
-        static const int cap3 = resident_blocks((const void*)k_fused<N, 3, SPEC_PLAIN, 0, PZ>, T);
+        static const int cap3 = resident_blocks((const void*)k_fused<N, 3, SPEC_PLAIN, 0, PZ, false, RV>, T);
         const int capf = a.max_blocks_fused > 0 ? a.max_blocks_fused : cap3;
         const int np = a.kxn * 2 * N;
         const int groups = (np + PZ - 1) / PZ;
         const unsigned nb = gs_fused_persistent(3, N) ? fused_grid(groups, capf, a.fused_grid_mult) : (unsigned)groups;
-        if constexpr (PZ == pz_of<N>(0)) {
+        if constexpr (ETILE) {
             if (a.energy) {
                 // with the energy sum of every pencil (the default tile only)
                 if (a.dipolar) {
-                    if (hint) k_fused<N, 3, SPEC_DIPOLAR, NT_P3, PZ, true><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
-                    else k_fused<N, 3, SPEC_DIPOLAR, 0, PZ, true><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
+                    if (hint) k_fused<N, 3, SPEC_DIPOLAR, NT_P3, PZ, true, RV><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
+                    else k_fused<N, 3, SPEC_DIPOLAR, 0, PZ, true, RV><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
                 } else {
-                    if (hint) k_fused<N, 3, SPEC_PLAIN, NT_P3, PZ, true><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
-                    else k_fused<N, 3, SPEC_PLAIN, 0, PZ, true><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
+                    if (hint) k_fused<N, 3, SPEC_PLAIN, NT_P3, PZ, true, RV><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
+                    else k_fused<N, 3, SPEC_PLAIN, 0, PZ, true, RV><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip, a.epart);
                 }
                 return hipGetLastError();
             }
         }
         if (a.dipolar) {
-            if (hint) k_fused<N, 3, SPEC_DIPOLAR, NT_P3, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
-            else k_fused<N, 3, SPEC_DIPOLAR, 0, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+            if (hint) k_fused<N, 3, SPEC_DIPOLAR, NT_P3, PZ, false, RV><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+            else k_fused<N, 3, SPEC_DIPOLAR, 0, PZ, false, RV><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
         } else {
-            if (hint) k_fused<N, 3, SPEC_PLAIN, NT_P3, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
-            else k_fused<N, 3, SPEC_PLAIN, 0, PZ><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+            if (hint) k_fused<N, 3, SPEC_PLAIN, NT_P3, PZ, false, RV><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
+            else k_fused<N, 3, SPEC_PLAIN, 0, PZ, false, RV><<<nb, T, 0, s>>>(X2, a.spec, tw, np, a.kx0, dip);
         }
         return hipGetLastError();
       }
@@ -173,20 +174,25 @@ static hipError_t launch_fused_v(const EvalArgs& a, hipStream_t s, const DipoleA
     cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
     const int np = N + 1;
     const unsigned nb = (unsigned)((np + PZ - 1) / PZ);
-    if constexpr (PZ == pz_of<N>(0)) {
+    if constexpr (ETILE) {
         if (a.energy) {
-            if (hint) k_fused<N, 2, SPEC_PLAIN, NT_P3, PZ, true><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip, a.epart);
-            else k_fused<N, 2, SPEC_PLAIN, 0, PZ, true><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip, a.epart);
+            if (hint) k_fused<N, 2, SPEC_PLAIN, NT_P3, PZ, true, RV><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip, a.epart);
+            else k_fused<N, 2, SPEC_PLAIN, 0, PZ, true, RV><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip, a.epart);
             return hipGetLastError();
         }
     }
-    if (hint) k_fused<N, 2, SPEC_PLAIN, NT_P3, PZ><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip);
-    else k_fused<N, 2, SPEC_PLAIN, 0, PZ><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip);
+    if (hint) k_fused<N, 2, SPEC_PLAIN, NT_P3, PZ, false, RV><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip);
+    else k_fused<N, 2, SPEC_PLAIN, 0, PZ, false, RV><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip);
     return hipGetLastError();
 }
 
+// Tile bit 8 selects the fused pass's radix-plan variant (FusedPlan<N, 1>, at its own
+// default pencils per block; bits 4-5 then do not apply) where one is compiled.
 static hipError_t launch_fused(const EvalArgs& a, hipStream_t s, const DipoleArgs& dip) {
     constexpr int N = GS_N;
+    if constexpr (fused_radix_variant<N>()) {
+        if ((a.tile_bits >> 8) & 1) return launch_fused_v<GeoZ<N, 1>::PPZ, 1>(a, s, dip);
+    }
     const int v = a.energy ? 0 : (a.tile_bits >> 4) & 3;
     if (v == 1 && pz_of<N>(1) != pz_of<N>(0)) return launch_fused_v<pz_of<N>(1)>(a, s, dip);
     if (v == 2 && pz_of<N>(2) != pz_of<N>(0)) return launch_fused_v<pz_of<N>(2)>(a, s, dip);
@@ -195,11 +201,11 @@ static hipError_t launch_fused(const EvalArgs& a, hipStream_t s, const DipoleArg
 
 int GS_CAT(tile_variants_, GS_N)() {
     // bit 0: an x variant exists (either x pass); bits 1, 2: y half / double; bits 3, 4: fused
-    // half / double
+    // half / double; bit 5: a radix-plan variant of the fused pass
     constexpr int N = GS_N;
     return (px_of<N>(1) != px_of<N>(0) ? 1 : 0) | (py_of<N>(1) != py_of<N>(0) ? 2 : 0) |
            (py_of<N>(2) != py_of<N>(0) ? 4 : 0) | (pz_of<N>(1) != pz_of<N>(0) ? 8 : 0) |
-           (pz_of<N>(2) != pz_of<N>(0) ? 16 : 0);
+           (pz_of<N>(2) != pz_of<N>(0) ? 16 : 0) | (fused_radix_variant<N>() ? 32 : 0);
 }
 
 // Pass `pass` of a grid whose axes have their own n, N being the length the pass transforms

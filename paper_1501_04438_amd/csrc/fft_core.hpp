@@ -344,6 +344,22 @@ template <> struct FftCfgFused<256> : FftPlan<256, 8, 3, 8, 8, 4, 1, SLOTS_PAD8>
 // which is faster for them.
 template <> struct FftCfgFused<1024> : FftPlan<1024, 8, 4, 8, 8, 4, 4> {};
 
+// Radix-plan variants of the fused pass that the plan autotuner times against the default
+// (RV = 1; elsewhere RV = 1 names the default plan): the other value count per thread at the
+// power-of-two lengths from 128 up (16 values where the default holds 8, and 8 where it holds
+// 16), so the autotuner chooses between more registers per thread with fewer stages and
+// exchanges, and more threads with more of them.  A different factorisation rounds
+// differently: a plan on a variant agrees with the default to rounding, not bitwise.
+template <int N, int RV> struct FusedPlan : FftCfgFused<N> {};
+template <> struct FusedPlan<128, 1> : FftPlan<128, 16, 2, 16, 8> {};
+template <> struct FusedPlan<256, 1> : FftPlan<256, 16, 2, 16, 16> {};
+template <> struct FusedPlan<512, 1> : FftPlan<512, 16, 3, 16, 16, 2> {};
+template <> struct FusedPlan<1024, 1> : FftPlan<1024, 16, 3, 16, 16, 4> {};
+template <> struct FusedPlan<2048, 1> : FftPlan<2048, 8, 4, 8, 8, 4, 8> {};
+template <int N> constexpr bool fused_radix_variant() {
+    return N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048;
+}
+
 // Block barrier ordering LDS only: global loads in flight (prefetches) are not
 // drained, unlike __syncthreads(), whose workgroup fence covers global memory.
 __device__ __forceinline__ void lds_barrier() {

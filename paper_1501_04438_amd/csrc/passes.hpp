@@ -74,9 +74,18 @@ __device__ __forceinline__ void swap_halves(cpx& a, cpx& b) {
     }
 }
 
+// Geometry of the fused pass on radix plan RV (FusedPlan): values and threads per
+// half-transform, LDS area, pencils per block.
+template <int N, int RV = 0> struct GeoZ {
+    using FZ = FusedPlan<N, RV>;
+    static constexpr int EZ = FZ::E, GZ = FZ::G, AZ = LdsAreaOf<FZ>::size;
+    static constexpr int PPZ = (2 * GZ >= 128) ? 1 : 128 / (2 * GZ);
+    static constexpr int TZ = PPZ * 2 * GZ;
+};
+
 template <int N> struct Geo {
     using F = FftCfg<N>;          // transforms of the x and y passes
-    using FZ = FftCfgFused<N>;    // transforms of the fused pass
+    using FZ = FftCfgFused<N>;    // transforms of the fused pass (default radix plan)
     static constexpr int E = F::E, G = F::G, A = LdsArea<N>::size;
     static constexpr int EZ = FZ::E, GZ = FZ::G, AZ = LdsAreaOf<FZ>::size;
     // P1/P5: pairs of real rows per block (2*PPX rows of y, 16-byte complex each)
@@ -465,8 +474,8 @@ __global__ void __launch_bounds__(PY * Geo<N>::G) k_y_inv(const cpx* __restrict_
 // 2n-2, ...: the two pencils +ky and -ky that share a spectrum row sit in the
 // same block.
 // ---------------------------------------------------------------------------
-template <int N> struct FusedRoles {
-    static constexpr int G = Geo<N>::GZ;
+template <int N, int RV = 0> struct FusedRoles {
+    static constexpr int G = GeoZ<N, RV>::GZ;
     // (G = 128: 2D n = 1024, 2048 and the 3D n = 1024 fused plan; the lane swap saves the
     // LDS round trip and two block barriers per pencil: 0.057 -> 0.055 ms at 2D 2048^2)
     static constexpr bool SWAP = (G <= 32) || (G % 128 == 0);
@@ -516,18 +525,18 @@ __device__ __forceinline__ gp<const double> fused_row(gp<const double> spec, int
     }
 }
 
-template <int N, int DIM, int NT>
-__device__ __forceinline__ void fused_load(gp<const cpx> X, int pencil, bool ok, int t, cpx (&v)[FftCfgFused<N>::E]) {
-    constexpr int E = FftCfgFused<N>::E, G = FftCfgFused<N>::G;
+template <int N, int DIM, int NT, int RV = 0>
+__device__ __forceinline__ void fused_load(gp<const cpx> X, int pencil, bool ok, int t, cpx (&v)[GeoZ<N, RV>::EZ]) {
+    constexpr int E = GeoZ<N, RV>::EZ, G = GeoZ<N, RV>::GZ;
     gp<const cpx> base = X + (size_t)pencil * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = ok ? ldg<NT & 1>(base + t + G * e) : cmk(0.0, 0.0);
 }
 
-template <int N, int DIM, int NT>
+template <int N, int DIM, int NT, int RV = 0>
 __device__ __forceinline__ void fused_spec(gp<const double> spec, int pencil, int kx0, bool ok, int t, int h,
-                                           double (&sv)[FftCfgFused<N>::E], int NY) {
-    constexpr int E = FftCfgFused<N>::E, G = FftCfgFused<N>::G;
+                                           double (&sv)[GeoZ<N, RV>::EZ], int NY) {
+    constexpr int E = GeoZ<N, RV>::EZ, G = GeoZ<N, RV>::GZ;
     gp<const double> srow = fused_row<N, DIM>(spec, ok ? pencil : 0, kx0, NY);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -544,10 +553,10 @@ __device__ __forceinline__ void fused_spec(gp<const double> spec, int pencil, in
 // in a fixed order) goes to part[index of the pencil in the whole grid], so the bits do not
 // depend on the launch shape.  Called by every thread of the block (for G > 32 a pencil's
 // waves are summed through LDS behind block barriers).
-template <int N, int DIM>
+template <int N, int DIM, int RV = 0>
 __device__ __forceinline__ void fused_energy_store(double acc, bool ok, int pencil, int kx0, int t, int h, int pl,
                                                    int NX, int NY, gp<double> part) {
-    constexpr int G = Geo<N>::GZ;
+    constexpr int G = GeoZ<N, RV>::GZ;
     if constexpr (G <= 32) {
         // a pencil: G lanes in each 32-lane half of one wave
 #pragma unroll
@@ -579,12 +588,12 @@ __device__ __forceinline__ void fused_energy_store(double acc, bool ok, int penc
 // Transform, spectrum multiplication, inverse transform and even/odd combination
 // of one pencil held in v (spectrum values in sv); stores the pencil if ok.  EN: also the
 // pencil's energy sum into part (fused_energy_store).
-template <int N, int DIM, int MODE, int NT = NT_P3, bool EN = false>
+template <int N, int DIM, int MODE, int NT = NT_P3, bool EN = false, int RV = 0>
 __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx> __restrict__ tw, int pencil, int kx0,
                                            bool ok, const DipoleArgs& dip, int t, int h, int pl,
-                                           cpx (&v)[FftCfgFused<N>::E], const double (&sv)[FftCfgFused<N>::E],
+                                           cpx (&v)[GeoZ<N, RV>::EZ], const double (&sv)[GeoZ<N, RV>::EZ],
                                            cpx* lds, cpx* area, int NX, int NY, gp<double> part = nullptr) {
-    using Gm = Geo<N>;
+    using Gm = GeoZ<N, RV>;
     using FZ = typename Gm::FZ;
     constexpr int E = Gm::EZ, G = Gm::GZ, A = Gm::AZ;
     constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
@@ -620,11 +629,11 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
             v[e] = cscale(v[e], sv[e]);
         }
     }
-    if constexpr (EN) fused_energy_store<N, DIM>(acc, ok, pencil, kx0, t, h, pl, NX, NY, part);
+    if constexpr (EN) fused_energy_store<N, DIM, RV>(acc, ok, pencil, kx0, t, h, pl, NX, NY, part);
     lds_sync<FW>();
     fft_t<FZ, true, FW>(v, t, area, t, area, tw, h);
     gp<cpx> base = X + (size_t)pencil * N;
-    if constexpr (FusedRoles<N>::SWAP) {
+    if constexpr (FusedRoles<N, RV>::SWAP) {
         // lanes l < 32 (even half) take the odd half's values e < E/2 from lane l + 32,
         // which takes the even half's values e >= E/2: each lane then holds the sums
         // for its own store slots
@@ -654,19 +663,19 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
 }
 
 // One pencil group of the fused pass without prefetch (the batched launches).
-// PZ: pencils per block (a tile-shape variant: the same bits for every PZ)
-template <int N, int DIM, int MODE, int NT = NT_P3, bool CUBE = true, int PZ = Geo<N>::PPZ, bool EN = false>
+// PZ: pencils per block (a tile-shape variant: the same bits for every PZ); RV: radix plan
+// (FusedPlan)
+template <int N, int DIM, int MODE, int NT = NT_P3, bool CUBE = true, int PZ = Geo<N>::PPZ, bool EN = false,
+          int RV = 0>
 __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const double> __restrict__ spec,
                                             gp<const cpx> __restrict__ tw, int npencils, int kx0,
                                             const DipoleArgs& dip, int g, int tid, bool active, cpx* lds,
                                             Ext ext = Ext(), gp<double> part = nullptr) {
-    using Gm = Geo<N>;
-    using FZ = typename Gm::FZ;
+    using Gm = GeoZ<N, RV>;
     constexpr int E = Gm::EZ, G = Gm::GZ, PP = PZ, A = Gm::AZ;
-    constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
     const int NX = CUBE ? N : ext.nx, NY = CUBE ? N : ext.ny;
     int t, h, pl;
-    FusedRoles<N>::get(tid, t, h, pl);
+    FusedRoles<N, RV>::get(tid, t, h, pl);
     cpx* area = lds + (pl * 2 + h) * A;
     const int slot = g * PP + pl;
     // in 3D the pencil count is a multiple of 2n, so groups of PP pencils never run past it
@@ -676,17 +685,17 @@ __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const dou
     const int pencil = ok ? fused_pencil<N, DIM>(slot, NY) : 0;
     cpx v[E];
     double sv[E];
-    fused_load<N, DIM, NT>(X, pencil, ok, t, v);
-    fused_spec<N, DIM, NT>(spec, pencil, kx0, ok, t, h, sv, NY);
-    fused_body<N, DIM, MODE, NT, EN>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area, NX, NY, part);
+    fused_load<N, DIM, NT, RV>(X, pencil, ok, t, v);
+    fused_spec<N, DIM, NT, RV>(spec, pencil, kx0, ok, t, h, sv, NY);
+    fused_body<N, DIM, MODE, NT, EN, RV>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area, NX, NY, part);
 }
 
-// EN: also the energy sum of every pencil into part (fused_energy_store).
-template <int N, int DIM, int MODE, int NT = NT_P3, int PZ = Geo<N>::PPZ, bool EN = false>
-__global__ void __launch_bounds__(PZ * 2 * Geo<N>::GZ) k_fused(cpx* __restrict__ Xg, const double* __restrict__ specg,
+// EN: also the energy sum of every pencil into part (fused_energy_store); RV: radix plan.
+template <int N, int DIM, int MODE, int NT = NT_P3, int PZ = Geo<N>::PPZ, bool EN = false, int RV = 0>
+__global__ void __launch_bounds__((PZ * 2 * GeoZ<N, RV>::GZ)) k_fused(cpx* __restrict__ Xg, const double* __restrict__ specg,
                                                               const cpx* __restrict__ twg, int npencils, int kx0,
                                                               DipoleArgs dip, double* __restrict__ part = nullptr) {
-    __shared__ cpx lds[PZ * 2 * Geo<N>::AZ];
+    __shared__ cpx lds[PZ * 2 * GeoZ<N, RV>::AZ];
     const int ngroups = (npencils + PZ - 1) / PZ;
     if constexpr (!gs_fused_persistent(DIM, N)) {
         // one pencil group per block (the grid must cover all groups).  Without the
@@ -694,14 +703,14 @@ __global__ void __launch_bounds__(PZ * 2 * Geo<N>::GZ) k_fused(cpx* __restrict__
         // live across groups: at n = 2048 in 2D, 250 VGPRs instead of 256 + 154 accumulator
         // registers, two waves per SIMD instead of one
         if ((int)blockIdx.x < ngroups)
-            fused_group<N, DIM, MODE, NT, true, PZ, EN>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
-                                                        npencils, kx0, dip, blockIdx.x, threadIdx.x, true, lds, Ext(),
-                                                        (gp<double>)part);
+            fused_group<N, DIM, MODE, NT, true, PZ, EN, RV>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
+                                                            npencils, kx0, dip, blockIdx.x, threadIdx.x, true, lds,
+                                                            Ext(), (gp<double>)part);
     } else {
         for (int g = blockIdx.x; g < ngroups; g += gridDim.x)
-            fused_group<N, DIM, MODE, NT, true, PZ, EN>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
-                                                        npencils, kx0, dip, g, threadIdx.x, true, lds, Ext(),
-                                                        (gp<double>)part);
+            fused_group<N, DIM, MODE, NT, true, PZ, EN, RV>((gp<cpx>)Xg, (gp<const double>)specg, (gp<const cpx>)twg,
+                                                            npencils, kx0, dip, g, threadIdx.x, true, lds, Ext(),
+                                                            (gp<double>)part);
     }
 }
 

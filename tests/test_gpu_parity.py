@@ -268,13 +268,24 @@ def test_plan_autotune_changes_no_bit(kernel, n, tmp_path, monkeypatch):
     tuned = gs.Plan(kernel, n=n, L=5.0, autotune=True, **kw)
     info = tuned.query()
     assert info["tuned"] == 1 and info["tune_candidates"] >= 3 and info["tuned_ms"] > 0
-    assert torch.equal(tuned.eval(x), ref)
+    same_as_default(tuned, x, ref)
     entries = json.loads((tmp_path / "tune.json").read_text())
     assert any("|plan|" in k for k in entries)
     again = gs.Plan(kernel, n=n, L=5.0, autotune=True, **kw)
     assert again.query()["tune_candidates"] == 0
     assert again.query()["hint_bits"] == info["hint_bits"]
-    assert torch.equal(again.eval(x), ref)
+    assert again.query()["tile_variants"] == info["tile_variants"]
+    assert torch.equal(again.eval(x), tuned.eval(x))
+
+
+def same_as_default(tuned, x, ref):
+    """A tuned plan gives the default plan's bits, except on the fused pass's radix-plan
+    variant (tile bit 8), whose other factorisation agrees to rounding."""
+    u = tuned.eval(x)
+    if tuned.query()["tile_variants"] & 256:
+        assert float((u - ref).abs().max()) <= 1e-14 * float(ref.abs().max())
+    else:
+        assert torch.equal(u, ref)
 
 
 @pytest.mark.parametrize("planes,streams", [(13, 2), (9, 3), (65, 2)])
@@ -502,7 +513,60 @@ def test_autotuned_tile_shapes_bitwise(tmp_path, monkeypatch):
     ref = gs.Plan("coulomb3d", n=n, L=5.0).eval(x)
     tuned = gs.Plan("coulomb3d", n=n, L=5.0, autotune=True)
     info = tuned.query()
-    assert info["tuned"] == 1 and info["tune_candidates"] >= 7      # hints, grid rounds and tile shapes
-    assert torch.equal(tuned.eval(x), ref)
+    assert info["tuned"] == 1 and info["tune_candidates"] >= 8      # hints, grid rounds, tile shapes, radix plan
+    same_as_default(tuned, x, ref)
     again = gs.Plan("coulomb3d", n=n, L=5.0, autotune=True)
     assert again.query()["tile_variants"] == info["tile_variants"] and again.query()["tune_candidates"] == 0
+
+
+# --------------------------------------------------------------------------
+# Radix-plan variant of the fused pass (tile bit 8): another factorisation of the same
+# transforms, so parity with the oracle at the usual bar, agreement with the default plan to
+# rounding, and the energy formed in the pass on the same bits as the variant's evaluation.
+# --------------------------------------------------------------------------
+
+RADIX_CASES = [("coulomb3d", 3, 128, 10.0), ("dipolar3d", 3, 128, 8.0), ("coulomb3d", 3, 256, 10.0),
+               ("poisson2d", 2, 256, 9.0), ("coulomb2d", 2, 512, 12.0), ("poisson2d", 2, 1024, 12.0),
+               ("coulomb2d", 2, 2048, 12.0)]
+
+
+@pytest.mark.parametrize("kernel,d,n,L", RADIX_CASES)
+def test_fused_radix_variant_against_oracle(kernel, d, n, L):
+    print(f"radix variant: {kernel} n={n}", flush=True)
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    if kernel == "poisson2d":
+        kw["eps"] = 1e-13
+    rng = np.random.default_rng(3100 + n)
+    rho = rng.standard_normal((n,) * d)
+    x = cuda(rho)
+    plan = gs.Plan(kernel, n=n, L=L, tile_variants=256, **kw)
+    assert plan.query()["tile_variants"] == 256
+    u = plan.eval(x)
+    base = gs.Plan(kernel, n=n, L=L, **kw)
+    u0 = base.eval(x)
+    umax = float(u0.abs().max())
+    assert not torch.equal(u, u0)                     # another factorisation ran
+    assert float((u - u0).abs().max()) <= 1e-14 * umax
+    ue, e = plan.eval_energy(x)
+    assert torch.equal(ue, u)
+    cell = plan.h ** d
+    e_space = 0.5 * cell * float((x * u).sum())
+    assert abs(float(e) - e_space) <= 1e-13 * 0.5 * cell * float((x * u).abs().sum())
+    o = oracle.evaluate(oracle.make_plan(kernel, d, n, L, **kw), rho)
+    del ue
+    assert relmax(u.cpu().numpy(), o) <= TOL
+
+
+def test_fused_radix_variant_batched_by_own_launches():
+    n = 128
+    rng = np.random.default_rng(3)
+    x, y = cuda(rng.standard_normal((n, n, n))), cuda(rng.standard_normal((32, 32, 32)))
+    var = gs.Plan("coulomb3d", n=n, L=10.0, tile_variants=256)
+    small = gs.Plan("coulomb3d", n=32, L=5.0)
+    with pytest.raises(RuntimeError, match="radix-plan variant"):
+        gs.Batch([var, small], schedule="queue")
+    b = gs.Batch([var, small], schedule="auto")
+    outs = b.eval([x, y])
+    torch.cuda.synchronize()
+    assert b.info["schedule"] in ("sequential", "streams")
+    assert torch.equal(outs[0], var.eval(x)) and torch.equal(outs[1], small.eval(y))
