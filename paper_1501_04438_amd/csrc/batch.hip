@@ -70,6 +70,9 @@ void batch_problems(const std::vector<BatchMember>& m, std::vector<unsigned char
     }
 }
 
+// Tasks per pass of one problem below which its tasks are made smaller than the requested size.
+constexpr int kMinTasksPerPass = 24;
+
 // Pass-major tasks of the members listed in `order` (indices into m), appended to T.
 static void build_tasks(const std::vector<BatchMember>& m, const std::vector<int>& order, int mult,
                         std::vector<BatchTask>& T, int pass_off[6], int pass_cnt[6]) {
@@ -80,8 +83,13 @@ static void build_tasks(const std::vector<BatchMember>& m, const std::vector<int
             const int d = m[b].d, n = m[b].n;
             if (d == 2 && (p == 2 || p == 4)) continue;
             const int dep = (p == 1) ? 0 : (d == 2 ? p - 2 : p - 1);
-            const int step = (BATCH_THREADS / threads_for(n, p)) * std::max(1, mult);
+            const int per = BATCH_THREADS / threads_for(n, p);     // tiles per block-full
             const int nt = tiles_for(n, p, d);
+            // a pass of few block-fulls gets smaller tasks (down to one block-full): at least
+            // kMinTasksPerPass of them where it has that many, so that a small problem's pass
+            // is not left to a few blocks working through long tasks while the others wait
+            const int fulls = (nt + per - 1) / per;
+            const int step = per * std::max(1, std::min(std::max(1, mult), fulls / kMinTasksPerPass));
             for (int t = 0; t < nt; t += step) {
                 BatchTask k;
                 k.prob = b;
