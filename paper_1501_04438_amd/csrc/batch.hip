@@ -107,7 +107,28 @@ static void build_tasks(const std::vector<BatchMember>& m, const std::vector<int
     pass_off[0] = pass_cnt[0] = 0;
 }
 
-static double member_work(const BatchMember& x) { return std::pow((double)x.n, x.d) * (x.d == 3 ? 2.5 : 1.0); }
+// Relative cost per grid point of a 3D problem in the batched kernels, by n: measured with the
+// phased schedule on batches of one size (ns per point: 32: 0.071, 48: 0.065, 64: 0.046,
+// 96: 0.058, 128: 0.048), taken relative to 128; the lengths below 32 extrapolated.  Small and
+// radix-3 lengths cost more per point, so weighing problems by their point count alone left
+// the die with the most small problems 5 % behind the others.
+static double point_cost_3d(int n) {
+    switch (n) {
+        case 8: return 2.0;
+        case 12: return 1.8;
+        case 16: return 1.6;
+        case 24: return 1.5;
+        case 32: return 1.48;
+        case 48: return 1.35;
+        case 64: return 0.96;
+        case 96: return 1.21;
+        default: return 1.0;
+    }
+}
+
+static double member_work(const BatchMember& x) {
+    return std::pow((double)x.n, x.d) * (x.d == 3 ? 2.5 * point_cost_3d(x.n) : 1.0);
+}
 
 static std::vector<int> size_order(const std::vector<BatchMember>& m, bool largest_first) {
     std::vector<int> order(m.size());
