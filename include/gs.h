@@ -371,7 +371,10 @@ typedef struct gs_batch_s* gs_batch;
 typedef struct {
     int schedule;        /* gs_schedule                                               */
     int tiles_per_task;  /* block-fulls of tiles per task (>= 1); 0 = default (queue 8,
-                            phased 4) or tuned                                        */
+                            phased 4) or tuned.  An upper bound: a problem's pass that
+                            would split into fewer than 24 tasks gets smaller ones
+                            (down to one block-full), so small problems keep their
+                            die's blocks busy                                         */
     int grid;            /* persistent blocks; 0 = as many as can be co-resident.  The
                             queue schedule with per-die queues raises a smaller grid to
                             the co-resident count (every die must run blocks)          */
