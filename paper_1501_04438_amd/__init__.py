@@ -55,7 +55,8 @@ class Plan:
     autotune: time the launch variants (cache hints per pass, fused-pass grid, tile shapes)
               at plan creation and keep the fastest (cached per device and size; the results
               are bitwise the same for every variant)
-    tile_variants: tile shapes of the cubic passes (gs_options.tile_variants bits; 0 = defaults)
+    tile_variants: tile shapes of the cubic passes and, bit 8, the fused pass's radix-plan
+        variant (gs_options.tile_variants bits; 0 = defaults)
     hint_bits: cache-hint variants of the passes (bit p-1: pass p non-temporal; None = defaults)
     workspace: False creates the plan without an evaluation workspace of its own; it is
               then evaluated with eval_static only
