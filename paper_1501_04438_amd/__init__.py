@@ -52,9 +52,10 @@ class Plan:
             (Ly, Lx)) for a rectangular box or grid (Section 2.5)
     eps:    Gaussian-sum accuracy; delta_rel: near-field radius / max L (below min L / max L)
     dipole: (n_vec, m_vec) for "dipolar3d"; custom: (w, tau) for "gaussian_sum"
-    autotune: time the launch variants (cache hints per pass, fused-pass grid, tile shapes)
-              at plan creation and keep the fastest (cached per device and size; the results
-              are bitwise the same for every variant)
+    autotune: time the launch variants (cache hints per pass, fused-pass grid, tile shapes,
+              the fused pass's radix plan) at plan creation and keep the fastest (cached per
+              device and size; the results are bitwise the same for every variant but the
+              radix plan, which agrees to rounding and is kept only when 1 % faster)
     tile_variants: tile shapes of the cubic passes and, bit 8, the fused pass's radix-plan
         variant (gs_options.tile_variants bits; 0 = defaults)
     hint_bits: cache-hint variants of the passes (bit p-1: pass p non-temporal; None = defaults)
