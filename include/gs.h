@@ -79,11 +79,14 @@ typedef enum {
                                      instead of the MFMA assembly kernel */
 #define GS_PLAN_AUTOTUNE       4  /* pick the launch variants of the evaluation (cache
                                      hints per pass, persistent grid of the fused pass,
-                                     tile shapes of the cubic passes)
-                                     by timing whole evaluations at plan creation, or
-                                     take them from the autotune cache (see
-                                     GS_SCHED_AUTO); results are bitwise the same for
-                                     every variant */
+                                     tile shapes of the cubic passes, the fused pass's
+                                     radix plan) by timing whole evaluations at plan
+                                     creation on scratch buffers, or take them from the
+                                     autotune cache (see GS_SCHED_AUTO); results are
+                                     bitwise the same for every variant except the radix
+                                     plan (gs_options.tile_variants bit 8), which agrees
+                                     to rounding and is kept only when faster by more
+                                     than 1 % */
 #define GS_PLAN_NO_WORKSPACE   8  /* allocate no evaluation workspace: the plan holds its
                                      spectrum and twiddles only and is evaluated with
                                      gs_eval_static (gs_eval, gs_eval_step,
