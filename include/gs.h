@@ -150,8 +150,11 @@ typedef struct {
                                 pass on its radix-plan variant (n = 128, 256, 512, 1024,
                                 2048: 16 values per thread where the default holds 8, 8
                                 where it holds 16; bits 4-5 then ignored), which agrees
-                                with the default to rounding, not bitwise; a plan with
-                                it is batched only by its own launches.
+                                with the default to rounding, not bitwise; bits 9 and
+                                10: the x-forward and x-inverse passes on theirs (the
+                                same lengths and value counts; bits 0-1 and 6-7 then
+                                ignored).  A plan on any of these is batched only by its
+                                own launches.
                                 GS_PLAN_AUTOTUNE picks them by timing            */
     int launch_hints;        /* 1 + the cache-hint bits of the passes (bit p-1 set: pass p
                                 uses its non-temporal hint variant, gs_plan_info.hint_bits);

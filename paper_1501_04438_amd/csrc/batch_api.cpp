@@ -451,13 +451,13 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
                 return fail(GS_ERR_INVALID_ARG, "a batched plan must run its middle passes in one slab");
             kernels_ok = false;
         }
-        // the batched kernels run the fused pass's default radix plan: a plan on the variant
-        // (which rounds differently) keeps the schedules that run its own launches
-        if (p->cube && (p->tile_bits & 256)) {
+        // the batched kernels run the default radix plans: a plan on a variant (which rounds
+        // differently) keeps the schedules that run its own launches
+        if (p->cube && (p->tile_bits & (7 << 8))) {
             if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED ||
                 opt.schedule == GS_SCHED_CONCURRENT)
                 return fail(GS_ERR_INVALID_ARG,
-                            "a plan on the fused pass's radix-plan variant is batched by its own launches only "
+                            "a plan on a radix-plan variant is batched by its own launches only "
                             "(sequential or streams schedule)");
             kernels_ok = false;
         }

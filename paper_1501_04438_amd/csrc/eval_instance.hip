@@ -56,21 +56,22 @@ template <int N> constexpr int pz_of(int v) {
     return P;
 }
 
-// P5 with row pairs PX per block; with the energy, the total of the fused pass's pencil sums.
-template <int PX>
+// P5 with row pairs PX per block on radix plan XV; with the energy, the total of the fused
+// pass's pencil sums.
+template <int PX, int XV = 0>
 static hipError_t launch_x_inverse_v(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
-    constexpr int T = p5_threads<N, PX>();
+    constexpr int T = p5_threads<N, PX, XV>();
     const cpx* const X1 = reinterpret_cast<const cpx*>(a.X1);
     const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
     const bool hint = (a.hint_bits >> 4) & 1;
     const dim3 gx((N + 2 * PX - 1) / (2 * PX), a.d == 3 ? N : 1);
     if (a.energy && a.oscale != 1.0) {
-        if (hint) k_x_c2r<N, NT_P5, PX, true><<<gx, T, 0, s>>>(X1, a.u, tw, a.oscale);
-        else k_x_c2r<N, 0, PX, true><<<gx, T, 0, s>>>(X1, a.u, tw, a.oscale);
+        if (hint) k_x_c2r<N, NT_P5, PX, true, XV><<<gx, T, 0, s>>>(X1, a.u, tw, a.oscale);
+        else k_x_c2r<N, 0, PX, true, XV><<<gx, T, 0, s>>>(X1, a.u, tw, a.oscale);
     } else {
-        if (hint) k_x_c2r<N, NT_P5, PX><<<gx, T, 0, s>>>(X1, a.u, tw);
-        else k_x_c2r<N, 0, PX><<<gx, T, 0, s>>>(X1, a.u, tw);
+        if (hint) k_x_c2r<N, NT_P5, PX, false, XV><<<gx, T, 0, s>>>(X1, a.u, tw);
+        else k_x_c2r<N, 0, PX, false, XV><<<gx, T, 0, s>>>(X1, a.u, tw);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.energy) return e;
@@ -78,25 +79,35 @@ static hipError_t launch_x_inverse_v(const EvalArgs& a, hipStream_t s) {
     return launch_energy_total(a.epart, a.epencils, a.escale, a.energy, s);
 }
 
+// Tile bit 10 selects the x-inverse pass's radix-plan variant (XPlan<N, 1>, at the default row
+// pairs per block; bits 6-7 then do not apply) where one is compiled.
 static hipError_t launch_x_inverse(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
+    if constexpr (x_radix_variant<N>()) {
+        if ((a.tile_bits >> 10) & 1) return launch_x_inverse_v<Geo<N>::PPX, 1>(a, s);
+    }
     if (((a.tile_bits >> 6) & 3) == 1 && px_of<N>(1) != px_of<N>(0)) return launch_x_inverse_v<px_of<N>(1)>(a, s);
     return launch_x_inverse_v<px_of<N>(0)>(a, s);
 }
 
-template <int PX>
+template <int PX, int XV = 0>
 static hipError_t launch_x_forward_v(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
+    constexpr int T = PX * GeoX<N, XV>::G;
     const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
     cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
     const dim3 gx((N + 2 * PX - 1) / (2 * PX), a.d == 3 ? N : 1);
-    if ((a.hint_bits >> 0) & 1) k_x_r2c<N, NT_P1, PX><<<gx, PX * Geo<N>::G, 0, s>>>(a.rho, X1, tw);
-    else k_x_r2c<N, 0, PX><<<gx, PX * Geo<N>::G, 0, s>>>(a.rho, X1, tw);
+    if ((a.hint_bits >> 0) & 1) k_x_r2c<N, NT_P1, PX, XV><<<gx, T, 0, s>>>(a.rho, X1, tw);
+    else k_x_r2c<N, 0, PX, XV><<<gx, T, 0, s>>>(a.rho, X1, tw);
     return hipGetLastError();
 }
 
+// Tile bit 9: the x-forward pass's radix-plan variant, as bit 10 for the x-inverse pass.
 static hipError_t launch_x_forward(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
+    if constexpr (x_radix_variant<N>()) {
+        if ((a.tile_bits >> 9) & 1) return launch_x_forward_v<Geo<N>::PPX, 1>(a, s);
+    }
     if ((a.tile_bits & 3) == 1 && px_of<N>(1) != px_of<N>(0)) return launch_x_forward_v<px_of<N>(1)>(a, s);
     return launch_x_forward_v<px_of<N>(0)>(a, s);
 }
@@ -201,11 +212,12 @@ static hipError_t launch_fused(const EvalArgs& a, hipStream_t s, const DipoleArg
 
 int GS_CAT(tile_variants_, GS_N)() {
     // bit 0: an x variant exists (either x pass); bits 1, 2: y half / double; bits 3, 4: fused
-    // half / double; bit 5: a radix-plan variant of the fused pass
+    // half / double; bit 5: a radix-plan variant of the fused pass; bit 6: of the x passes
     constexpr int N = GS_N;
     return (px_of<N>(1) != px_of<N>(0) ? 1 : 0) | (py_of<N>(1) != py_of<N>(0) ? 2 : 0) |
            (py_of<N>(2) != py_of<N>(0) ? 4 : 0) | (pz_of<N>(1) != pz_of<N>(0) ? 8 : 0) |
-           (pz_of<N>(2) != pz_of<N>(0) ? 16 : 0) | (fused_radix_variant<N>() ? 32 : 0);
+           (pz_of<N>(2) != pz_of<N>(0) ? 16 : 0) | (fused_radix_variant<N>() ? 32 : 0) |
+           (x_radix_variant<N>() ? 64 : 0);
 }
 
 // Pass `pass` of a grid whose axes have their own n, N being the length the pass transforms

@@ -350,15 +350,28 @@ template <> struct FftCfgFused<1024> : FftPlan<1024, 8, 4, 8, 8, 4, 4> {};
 // 16), so the autotuner chooses between more registers per thread with fewer stages and
 // exchanges, and more threads with more of them.  A different factorisation rounds
 // differently: a plan on a variant agrees with the default to rounding, not bitwise.
-template <int N, int RV> struct FusedPlan : FftCfgFused<N> {};
-template <> struct FusedPlan<128, 1> : FftPlan<128, 16, 2, 16, 8> {};
-template <> struct FusedPlan<256, 1> : FftPlan<256, 16, 2, 16, 16> {};
-template <> struct FusedPlan<512, 1> : FftPlan<512, 16, 3, 16, 16, 2> {};
-template <> struct FusedPlan<1024, 1> : FftPlan<1024, 16, 3, 16, 16, 4> {};
-template <> struct FusedPlan<2048, 1> : FftPlan<2048, 8, 4, 8, 8, 4, 8> {};
+// (RV = 0 names FftCfgFused<N> itself, so the default kernels are the same instances.)
+template <int N, int RV> struct FusedPlanSel { using type = FftCfgFused<N>; };
+template <> struct FusedPlanSel<128, 1> { using type = FftPlan<128, 16, 2, 16, 8>; };
+template <> struct FusedPlanSel<256, 1> { using type = FftPlan<256, 16, 2, 16, 16>; };
+template <> struct FusedPlanSel<512, 1> { using type = FftPlan<512, 16, 3, 16, 16, 2>; };
+template <> struct FusedPlanSel<1024, 1> { using type = FftPlan<1024, 16, 3, 16, 16, 4>; };
+template <> struct FusedPlanSel<2048, 1> { using type = FftPlan<2048, 8, 4, 8, 8, 4, 8>; };
+template <int N, int RV> using FusedPlan = typename FusedPlanSel<N, RV>::type;
 template <int N> constexpr bool fused_radix_variant() {
     return N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048;
 }
+
+// The same for the x passes (XV = 1; the x-forward and x-inverse passes choose apart): the
+// other value count per thread than FftCfg at the same lengths (XV = 0: FftCfg<N> itself).
+template <int N, int XV> struct XPlanSel { using type = FftCfg<N>; };
+template <> struct XPlanSel<128, 1> { using type = FftPlan<128, 16, 2, 16, 8>; };
+template <> struct XPlanSel<256, 1> { using type = FftPlan<256, 8, 3, 8, 8, 4>; };
+template <> struct XPlanSel<512, 1> { using type = FftPlan<512, 16, 3, 16, 16, 2>; };
+template <> struct XPlanSel<1024, 1> { using type = FftPlan<1024, 8, 4, 8, 8, 4, 4>; };
+template <> struct XPlanSel<2048, 1> { using type = FftPlan<2048, 8, 4, 8, 8, 4, 8>; };
+template <int N, int XV> using XPlan = typename XPlanSel<N, XV>::type;
+template <int N> constexpr bool x_radix_variant() { return fused_radix_variant<N>(); }
 
 // Block barrier ordering LDS only: global loads in flight (prefetches) are not
 // drained, unlike __syncthreads(), whose workgroup fence covers global memory.

@@ -523,7 +523,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->delta_rel = opt.delta_rel;
     p->flags = opt.flags;
     p->host_only = host_only;
-    p->tile_bits = opt.tile_variants & 511;
+    p->tile_bits = opt.tile_variants & 2047;
     if (opt.launch_hints > 0) p->hint_bits = (opt.launch_hints - 1) & 31;
     p->stream = (hipStream_t)opt.stream;
     for (int i = 0; i < 3; ++i) {
@@ -938,18 +938,20 @@ gs_status plan_autotune(gs_plan_s* p) {
     // tile shapes of the cubic passes: each pass type's variants in turn (x: twice the row
     // pairs; y and fused: half and twice the pencils per block), keeping what is faster; last
     // the fused pass's radix-plan variant (its own pencils per block; it rounds differently,
-    // so it is kept only if faster by more than 1 %, beyond the spread of repeated timings)
+    // so it is kept only if faster by more than 1 %, beyond the spread of repeated timings), and
+    // the x-forward and x-inverse passes' radix-plan variants likewise
     const int tv = p->cube ? gsk::tile_variants(p->nf) : 0;
-    const int tries[7][2] = {{0, 1}, {6, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {8, 1}};   // (bit offset, value)
-    const int avail[7] = {1, 1, 2, 4, 8, 16, 32};
-    for (int i = 0; i < 7 && st == GS_OK; ++i) {
+    const int tries[9][2] = {{0, 1}, {6, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {8, 1}, {9, 1}, {10, 1}};   // (bit offset, value)
+    const int avail[9] = {1, 1, 2, 4, 8, 16, 32, 64, 64};
+    for (int i = 0; i < 9 && st == GS_OK; ++i) {
         if (!(tv & avail[i]) || (p->d == 2 && tries[i][0] == 2)) continue;
         const int keep = p->tile_bits;
-        p->tile_bits = (p->tile_bits & ~(3 << tries[i][0])) | (tries[i][1] << tries[i][0]);
+        const int field = tries[i][0] >= 8 ? 1 : 3;      // one-bit fields from bit 8 on
+        p->tile_bits = (p->tile_bits & ~(field << tries[i][0])) | (tries[i][1] << tries[i][0]);
         double ms = 0;
         st = time_plan(p, rho, u, ms);
         p->tune_candidates++;
-        const double margin = tries[i][0] == 8 ? 0.99 : 1.0;
+        const double margin = tries[i][0] >= 8 ? 0.99 : 1.0;
         if (st == GS_OK && ms < margin * best) best = ms;
         else p->tile_bits = keep;
     }

@@ -99,6 +99,13 @@ template <int N> struct Geo {
     static constexpr int TX = PPX * G, TY = PPY * G, TZ = PPZ * 2 * GZ;
 };
 
+// Transforms of the x passes on radix plan XV (XPlan): values and threads per row transform
+// (rows per block and LDS area as in Geo).
+template <int N, int XV = 0> struct GeoX {
+    using F = XPlan<N, XV>;
+    static constexpr int E = F::E, G = F::G;
+};
+
 // Extents of a grid whose axes have their own n (x, y, z; 2D: z = 1).  A pass compiled with
 // CUBE = true takes every extent as its transform length N (compile time) and ignores these;
 // with CUBE = false the extents of the axes it does not transform come from here, and every
@@ -117,12 +124,14 @@ struct Ext {
 // RL: the rows are loaded again for the second half instead of being kept in registers across
 // both (same values, same bits; E fewer complex values live through the first half's transform,
 // which the batched kernels, sized for every length at once, need for their occupancy)
-template <int N, int NT = NT_P1, bool CUBE = true, int PX = Geo<N>::PPX, bool RL = false>
+// XV: radix plan of the row transforms (XPlan).
+template <int N, int NT = NT_P1, bool CUBE = true, int PX = Geo<N>::PPX, bool RL = false, int XV = 0>
 __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp<cpx> __restrict__ X1,
                                            gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
                                            cpx* lds, Ext ext = Ext()) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
+    using Fx = typename GeoX<N, XV>::F;
+    constexpr int E = Fx::E, G = Fx::G, PP = PX, A = Gm::A;
     const int NY = CUBE ? N : ext.ny;          // rows (y) of a plane
     const int tA = tid % G, pA = tid / G;      // load role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive y
@@ -169,8 +178,8 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
         }
         // the separate twist measured faster here than the twisted roots (its h = 1 roots
         // of the 16 x 16 plan double the stage-2 power products in the unrolled h loop)
-        if (h) twist_in<typename Gm::F>(v, tA, tw);
-        fft<typename Gm::F, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
+        if (h) twist_in<Fx>(v, tA, tw);
+        fft<Fx, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw);
         lds_barrier();
 #pragma unroll
         for (int e = 0; e < E; ++e) lds[pB * A + lds_pad(tB + G * e)] = v[e];
@@ -200,25 +209,26 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
 // At n = 2048 the compiler's own allocation takes 256 VGPRs + 42 accumulator registers (one wave
 // per SIMD); capped at two waves per SIMD it spills 172 bytes per lane and still runs faster
 // (measured 0.038 -> 0.033 ms for 2D 2048^2; the same cap slows the x-inverse and n = 1024).
-template <int N, int NT = NT_P1, int PX = Geo<N>::PPX>
-__global__ void __launch_bounds__(PX * Geo<N>::G) __attribute__((amdgpu_waves_per_eu(N == 2048 ? 2 : 1)))
+template <int N, int NT = NT_P1, int PX = Geo<N>::PPX, int XV = 0>
+__global__ void __launch_bounds__((PX * GeoX<N, XV>::G)) __attribute__((amdgpu_waves_per_eu(N == 2048 ? 2 : 1)))
 k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
                                                       const cpx* __restrict__ tw) {
     __shared__ cpx lds[PX * Geo<N>::A];
-    x_r2c_tile<N, NT, true, PX>((gp<const double>)rho, (gp<cpx>)X1, (gp<const cpx>)tw, blockIdx.x, blockIdx.y,
-                                threadIdx.x, true, lds);
+    x_r2c_tile<N, NT, true, PX, false, XV>((gp<const double>)rho, (gp<cpx>)X1, (gp<const cpx>)tw, blockIdx.x,
+                                           blockIdx.y, threadIdx.x, true, lds);
 }
 
 // ---------------------------------------------------------------------------
 // P5: x-direction complex-to-real with cropping.  Inverse of P1 (unnormalised).
 // ---------------------------------------------------------------------------
 // SC: the outputs are stored times oscale (the rho gradient of the energy, cell u).
-template <int N, int NT = NT_P5, bool SC = false, bool CUBE = true, int PX = Geo<N>::PPX>
+template <int N, int NT = NT_P5, bool SC = false, bool CUBE = true, int PX = Geo<N>::PPX, int XV = 0>
 __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> u,
                                            gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
                                            cpx* lds, Ext ext = Ext(), double oscale = 1.0) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
+    using Fx = typename GeoX<N, XV>::F;
+    constexpr int E = Fx::E, G = Fx::G, PP = PX, A = Gm::A;
     const int NY = CUBE ? N : ext.ny;          // rows (y) of a plane
     const int tA = tid % G, pA = tid / G;      // store role: consecutive x
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive y
@@ -255,7 +265,7 @@ __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<dou
             if (!direct) { a.y = -a.y; b.y = -b.y; }
             v[e] = cmk(a.x - b.y, a.y + b.x);          // a + i b
         }
-        fft_t<typename Gm::F, true>(v, tA, lds + pA * A, tB, lds + pB * A, tw, h);   // cropping twist included
+        fft_t<Fx, true>(v, tA, lds + pA * A, tB, lds + pB * A, tw, h);   // cropping twist included
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], v[e]);
         lds_barrier();
@@ -286,19 +296,24 @@ __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<dou
 // Decided per length, so that every tile shape of a length (PPX and 2 PPX row pairs) has the
 // same layout: the default tile fills whole half-waves and the doubled tile's two LDS areas
 // per pair fit in the 160 KiB of a CU.
-template <int N> constexpr bool p5_split_len() {
-    return (Geo<N>::PPX * Geo<N>::G) % 32 == 0 && 2 * 2 * Geo<N>::PPX * Geo<N>::A * 16 <= 160 * 1024;
+template <int N, int XV = 0> constexpr bool p5_split_len() {
+    return (Geo<N>::PPX * GeoX<N, XV>::G) % 32 == 0 && 2 * 2 * Geo<N>::PPX * Geo<N>::A * 16 <= 160 * 1024;
 }
-template <int N, int PX> constexpr bool p5_split() { return p5_split_len<N>() && (PX * Geo<N>::G) % 32 == 0; }
-template <int N, int PX> constexpr int p5_threads() { return (p5_split<N, PX>() ? 2 : 1) * PX * Geo<N>::G; }
+template <int N, int PX, int XV = 0> constexpr bool p5_split() {
+    return p5_split_len<N, XV>() && (PX * GeoX<N, XV>::G) % 32 == 0 && 2 * PX * GeoX<N, XV>::G <= 1024;
+}
+template <int N, int PX, int XV = 0> constexpr int p5_threads() {
+    return (p5_split<N, PX, XV>() ? 2 : 1) * PX * GeoX<N, XV>::G;
+}
 
-template <int N, int NT, bool SC, int PX>
+template <int N, int NT, bool SC, int PX, int XV = 0>
 __device__ __forceinline__ void x_c2r_tile_split(gp<const cpx> __restrict__ X1, gp<double> u,
                                                  gp<const cpx> __restrict__ tw, int bx, int z, int tid, cpx* lds,
                                                  double oscale, bool active = true) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = PX, A = Gm::A;
-    static_assert(p5_split<N, PX>(), "whole half-waves");
+    using Fx = typename GeoX<N, XV>::F;
+    constexpr int E = Fx::E, G = Fx::G, PP = PX, A = Gm::A;
+    static_assert(p5_split<N, PX, XV>(), "whole half-waves");
     const int w = tid >> 6, l = tid & 63, h = l >> 5;
     const int tq = 32 * w + (l & 31);           // thread within its half
     const int tA = tq % G, pA = tq / G;         // store role: consecutive x
@@ -326,7 +341,7 @@ __device__ __forceinline__ void x_c2r_tile_split(gp<const cpx> __restrict__ X1, 
         if (!direct) { a.y = -a.y; b.y = -b.y; }
         v[e] = cmk(a.x - b.y, a.y + b.x);              // a + i b
     }
-    fft_t<typename Gm::F, true>(v, tA, lds + (h * PP + pA) * A, tB, lds + (h * PP + pB) * A, tw, h);
+    fft_t<Fx, true>(v, tA, lds + (h * PP + pA) * A, tB, lds + (h * PP + pB) * A, tw, h);
     gp<double> ua = u + ((size_t)z * N + rowA) * N;
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) {
@@ -345,17 +360,17 @@ __device__ __forceinline__ void x_c2r_tile_split(gp<const cpx> __restrict__ X1, 
 
 // P5; SC: the outputs stored times oscale (the energy's rho gradient cell u; the energy
 // itself is summed by the fused pass).
-template <int N, int NT = NT_P5, int PX = Geo<N>::PPX, bool SC = false>
-__global__ void __launch_bounds__((p5_threads<N, PX>())) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
-                                                               const cpx* __restrict__ tw, double oscale = 1.0) {
-    if constexpr (p5_split<N, PX>()) {
+template <int N, int NT = NT_P5, int PX = Geo<N>::PPX, bool SC = false, int XV = 0>
+__global__ void __launch_bounds__((p5_threads<N, PX, XV>())) k_x_c2r(const cpx* __restrict__ X1, double* __restrict__ u,
+                                                                   const cpx* __restrict__ tw, double oscale = 1.0) {
+    if constexpr (p5_split<N, PX, XV>()) {
         __shared__ cpx lds[2 * PX * Geo<N>::A];
-        x_c2r_tile_split<N, NT, SC, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x, blockIdx.y,
-                                        threadIdx.x, lds, oscale);
+        x_c2r_tile_split<N, NT, SC, PX, XV>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                            blockIdx.y, threadIdx.x, lds, oscale);
     } else {
         __shared__ cpx lds[PX * Geo<N>::A];
-        x_c2r_tile<N, NT, SC, true, PX>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
-                                        blockIdx.y, threadIdx.x, true, lds, Ext(), oscale);
+        x_c2r_tile<N, NT, SC, true, PX, XV>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                            blockIdx.y, threadIdx.x, true, lds, Ext(), oscale);
     }
 }
 

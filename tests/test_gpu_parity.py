@@ -279,10 +279,10 @@ def test_plan_autotune_changes_no_bit(kernel, n, tmp_path, monkeypatch):
 
 
 def same_as_default(tuned, x, ref):
-    """A tuned plan gives the default plan's bits, except on the fused pass's radix-plan
-    variant (tile bit 8), whose other factorisation agrees to rounding."""
+    """A tuned plan gives the default plan's bits, except on a radix-plan variant (tile bits
+    8-10: fused, x-forward, x-inverse pass), whose other factorisation agrees to rounding."""
     u = tuned.eval(x)
-    if tuned.query()["tile_variants"] & 256:
+    if tuned.query()["tile_variants"] & RADIX_BITS:
         assert float((u - ref).abs().max()) <= 1e-14 * float(ref.abs().max())
     else:
         assert torch.equal(u, ref)
@@ -520,10 +520,13 @@ def test_autotuned_tile_shapes_bitwise(tmp_path, monkeypatch):
 
 
 # --------------------------------------------------------------------------
-# Radix-plan variant of the fused pass (tile bit 8): another factorisation of the same
-# transforms, so parity with the oracle at the usual bar, agreement with the default plan to
-# rounding, and the energy formed in the pass on the same bits as the variant's evaluation.
+# Radix-plan variants (tile bits 8, 9, 10: the fused, x-forward and x-inverse passes): another
+# factorisation of the same transforms, so parity with the oracle at the usual bar, agreement
+# with the default plan to rounding, and the energy formed in the fused pass on the same bits as
+# the variant's evaluation.
 # --------------------------------------------------------------------------
+
+RADIX_BITS = 7 << 8
 
 RADIX_CASES = [("coulomb3d", 3, 128, 10.0), ("dipolar3d", 3, 128, 8.0), ("coulomb3d", 3, 256, 10.0),
                ("poisson2d", 2, 256, 9.0), ("coulomb2d", 2, 512, 12.0), ("poisson2d", 2, 1024, 12.0),
@@ -532,36 +535,40 @@ RADIX_CASES = [("coulomb3d", 3, 128, 10.0), ("dipolar3d", 3, 128, 8.0), ("coulom
 
 @pytest.mark.parametrize("kernel,d,n,L", RADIX_CASES)
 def test_fused_radix_variant_against_oracle(kernel, d, n, L):
-    print(f"radix variant: {kernel} n={n}", flush=True)
+    print(f"radix variants: {kernel} n={n}", flush=True)
     kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
     if kernel == "poisson2d":
         kw["eps"] = 1e-13
     rng = np.random.default_rng(3100 + n)
     rho = rng.standard_normal((n,) * d)
     x = cuda(rho)
-    plan = gs.Plan(kernel, n=n, L=L, tile_variants=256, **kw)
-    assert plan.query()["tile_variants"] == 256
-    u = plan.eval(x)
-    base = gs.Plan(kernel, n=n, L=L, **kw)
-    u0 = base.eval(x)
+    u0 = gs.Plan(kernel, n=n, L=L, **kw).eval(x)
     umax = float(u0.abs().max())
-    assert not torch.equal(u, u0)                     # another factorisation ran
-    assert float((u - u0).abs().max()) <= 1e-14 * umax
-    ue, e = plan.eval_energy(x)
-    assert torch.equal(ue, u)
-    cell = plan.h ** d
-    e_space = 0.5 * cell * float((x * u).sum())
-    assert abs(float(e) - e_space) <= 1e-13 * 0.5 * cell * float((x * u).abs().sum())
     o = oracle.evaluate(oracle.make_plan(kernel, d, n, L, **kw), rho)
-    del ue
-    assert relmax(u.cpu().numpy(), o) <= TOL
+    for tv in (1 << 8, 1 << 9, 1 << 10, RADIX_BITS):
+        plan = gs.Plan(kernel, n=n, L=L, tile_variants=tv, **kw)
+        assert plan.query()["tile_variants"] == tv
+        u = plan.eval(x)
+        assert not torch.equal(u, u0), tv                 # another factorisation ran
+        assert float((u - u0).abs().max()) <= 1e-14 * umax, tv
+        ue, e = plan.eval_energy(x)
+        assert torch.equal(ue, u), tv
+        cell = plan.h ** d
+        e_space = 0.5 * cell * float((x * u).sum())
+        assert abs(float(e) - e_space) <= 1e-13 * 0.5 * cell * float((x * u).abs().sum()), tv
+        del ue
+        assert relmax(u.cpu().numpy(), o) <= TOL, tv
+        ub = plan.eval_backward(x)                        # the adjoint runs the same launches
+        assert torch.equal(ub, u), tv
+        del u, ub
+        plan.close()
 
 
 def test_fused_radix_variant_batched_by_own_launches():
     n = 128
     rng = np.random.default_rng(3)
     x, y = cuda(rng.standard_normal((n, n, n))), cuda(rng.standard_normal((32, 32, 32)))
-    var = gs.Plan("coulomb3d", n=n, L=10.0, tile_variants=256)
+    var = gs.Plan("coulomb3d", n=n, L=10.0, tile_variants=1 << 10)
     small = gs.Plan("coulomb3d", n=32, L=5.0)
     with pytest.raises(RuntimeError, match="radix-plan variant"):
         gs.Batch([var, small], schedule="queue")
