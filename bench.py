@@ -485,7 +485,7 @@ def autotuned_figures(gs, torch, plan, rho, K):
     """The plan autotuner on the headline grid (cache hints, fused-pass grid rounds, the
     tile shapes of the passes and the fused pass's radix plan): its choice, and its
     evaluation time next to the compiled defaults' (both timed here with events on the
-    current stream; the same bits unless it chose a radix-plan variant, tile bits 8-10,
+    current stream; the same bits unless it chose a radix-plan variant, tile bits 8-12,
     which agrees to rounding: its largest difference is reported)."""
     tuned = gs.Plan("coulomb3d", n=plan.n, L=plan.L, eps=1e-14, autotune=True)
     info = tuned.query()
@@ -507,7 +507,7 @@ def autotuned_figures(gs, torch, plan, rho, K):
     res = {"hint_bits": info["hint_bits"], "fused_grid_mult": info["fused_grid_mult"],
            "tile_variants": info["tile_variants"], "candidates_timed": info["tune_candidates"],
            "ms_tuned": round(ms_tuned, 5), "ms_default": round(ms_default, 5),
-           "radix_variant": bool(info["tile_variants"] & (7 << 8))}
+           "radix_variant": bool(info["tile_variants"] & (31 << 8))}
     ut, ud = tuned.eval(rho), plan.eval(rho)
     res["bitwise_equal"] = bool(torch.equal(ut, ud))
     res["max_rel_diff_vs_default"] = float((ut - ud).abs().max() / ud.abs().max())

@@ -153,8 +153,10 @@ typedef struct {
                                 with the default to rounding, not bitwise; bits 9 and
                                 10: the x-forward and x-inverse passes on theirs (the
                                 same lengths and value counts; bits 0-1 and 6-7 then
-                                ignored).  A plan on any of these is batched only by its
-                                own launches.
+                                ignored); bits 11 and 12: the y-forward and y-inverse
+                                passes (3D; bits 2-3 then ignored for that pass).  A
+                                plan on any of these is batched only by its own
+                                launches.
                                 GS_PLAN_AUTOTUNE picks them by timing            */
     int launch_hints;        /* 1 + the cache-hint bits of the passes (bit p-1 set: pass p
                                 uses its non-temporal hint variant, gs_plan_info.hint_bits);

@@ -453,7 +453,7 @@ gs_status gs_batch_create(gs_batch* out, int count, const gs_plan* plans, const 
         }
         // the batched kernels run the default radix plans: a plan on a variant (which rounds
         // differently) keeps the schedules that run its own launches
-        if (p->cube && (p->tile_bits & (7 << 8))) {
+        if (p->cube && (p->tile_bits & (31 << 8))) {
             if (opt.schedule == GS_SCHED_QUEUE || opt.schedule == GS_SCHED_PHASED || opt.schedule == GS_SCHED_SIZED ||
                 opt.schedule == GS_SCHED_CONCURRENT)
                 return fail(GS_ERR_INVALID_ARG,

@@ -113,28 +113,33 @@ static hipError_t launch_x_forward(const EvalArgs& a, hipStream_t s) {
 }
 
 // y passes (3D) with PY z-pencils per block: 2 forward, 4 inverse.
-template <int PY>
+template <int PY, int YV = 0>
 static hipError_t launch_y_v(const EvalArgs& a, hipStream_t s, int pass) {
     constexpr int N = GS_N;
     cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
     cpx* const X2 = reinterpret_cast<cpx*>(a.X2);
     const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
     const dim3 gy((N + PY - 1) / PY, a.kxn);
-    constexpr int T = PY * Geo<N>::G;
+    constexpr int T = PY * GeoX<N, YV>::G;
     const bool hint = (a.hint_bits >> (pass - 1)) & 1;
     if (pass == 2) {
-        if (hint) k_y_fwd<N, NT_P2, PY><<<gy, T, 0, s>>>(X1, X2, tw, a.kx0);
-        else k_y_fwd<N, 0, PY><<<gy, T, 0, s>>>(X1, X2, tw, a.kx0);
+        if (hint) k_y_fwd<N, NT_P2, PY, YV><<<gy, T, 0, s>>>(X1, X2, tw, a.kx0);
+        else k_y_fwd<N, 0, PY, YV><<<gy, T, 0, s>>>(X1, X2, tw, a.kx0);
     } else {
-        if (hint) k_y_inv<N, NT_P4, PY><<<gy, T, 0, s>>>(X2, X1, tw, a.kx0);
-        else k_y_inv<N, 0, PY><<<gy, T, 0, s>>>(X2, X1, tw, a.kx0);
+        if (hint) k_y_inv<N, NT_P4, PY, YV><<<gy, T, 0, s>>>(X2, X1, tw, a.kx0);
+        else k_y_inv<N, 0, PY, YV><<<gy, T, 0, s>>>(X2, X1, tw, a.kx0);
     }
     return hipGetLastError();
 }
 
+// Tile bits 11 (y-forward) and 12 (y-inverse) select the pass's radix-plan variant (XPlan<N, 1>
+// at the default z-pencils per block; bits 2-3 then do not apply to that pass).
 template <int N>
 static hipError_t launch_y(const EvalArgs& a, hipStream_t s, int pass) {
     static_assert(N <= GS_MAX_N_3D, "the y passes run in 3D only");
+    if constexpr (x_radix_variant<N>()) {
+        if ((a.tile_bits >> (pass == 2 ? 11 : 12)) & 1) return launch_y_v<Geo<N>::PPY, 1>(a, s, pass);
+    }
     const int v = (a.tile_bits >> 2) & 3;
     if (v == 1 && py_of<N>(1) != py_of<N>(0)) return launch_y_v<py_of<N>(1)>(a, s, pass);
     if (v == 2 && py_of<N>(2) != py_of<N>(0)) return launch_y_v<py_of<N>(2)>(a, s, pass);
@@ -212,12 +217,13 @@ static hipError_t launch_fused(const EvalArgs& a, hipStream_t s, const DipoleArg
 
 int GS_CAT(tile_variants_, GS_N)() {
     // bit 0: an x variant exists (either x pass); bits 1, 2: y half / double; bits 3, 4: fused
-    // half / double; bit 5: a radix-plan variant of the fused pass; bit 6: of the x passes
+    // half / double; bit 5: a radix-plan variant of the fused pass; bit 6: of the x passes;
+    // bit 7: of the y passes
     constexpr int N = GS_N;
     return (px_of<N>(1) != px_of<N>(0) ? 1 : 0) | (py_of<N>(1) != py_of<N>(0) ? 2 : 0) |
            (py_of<N>(2) != py_of<N>(0) ? 4 : 0) | (pz_of<N>(1) != pz_of<N>(0) ? 8 : 0) |
            (pz_of<N>(2) != pz_of<N>(0) ? 16 : 0) | (fused_radix_variant<N>() ? 32 : 0) |
-           (x_radix_variant<N>() ? 64 : 0);
+           (x_radix_variant<N>() ? 64 : 0) | (x_radix_variant<N>() && N <= GS_MAX_N_3D ? 128 : 0);
 }
 
 // Pass `pass` of a grid whose axes have their own n, N being the length the pass transforms

@@ -523,7 +523,7 @@ gs_status gs_plan_create(gs_plan* out, gs_kernel k, int d, const int64_t* n, con
     p->delta_rel = opt.delta_rel;
     p->flags = opt.flags;
     p->host_only = host_only;
-    p->tile_bits = opt.tile_variants & 2047;
+    p->tile_bits = opt.tile_variants & 8191;
     if (opt.launch_hints > 0) p->hint_bits = (opt.launch_hints - 1) & 31;
     p->stream = (hipStream_t)opt.stream;
     for (int i = 0; i < 3; ++i) {
@@ -939,12 +939,14 @@ gs_status plan_autotune(gs_plan_s* p) {
     // pairs; y and fused: half and twice the pencils per block), keeping what is faster; last
     // the fused pass's radix-plan variant (its own pencils per block; it rounds differently,
     // so it is kept only if faster by more than 1 %, beyond the spread of repeated timings), and
-    // the x-forward and x-inverse passes' radix-plan variants likewise
+    // the x and y passes' radix-plan variants likewise
     const int tv = p->cube ? gsk::tile_variants(p->nf) : 0;
-    const int tries[9][2] = {{0, 1}, {6, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {8, 1}, {9, 1}, {10, 1}};   // (bit offset, value)
-    const int avail[9] = {1, 1, 2, 4, 8, 16, 32, 64, 64};
-    for (int i = 0; i < 9 && st == GS_OK; ++i) {
-        if (!(tv & avail[i]) || (p->d == 2 && tries[i][0] == 2)) continue;
+    const int tries[11][2] = {{0, 1}, {6, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2},
+                              {8, 1}, {9, 1}, {10, 1}, {11, 1}, {12, 1}};   // (bit offset, value)
+    const int avail[11] = {1, 1, 2, 4, 8, 16, 32, 64, 64, 128, 128};
+    for (int i = 0; i < 11 && st == GS_OK; ++i) {
+        const bool ypass = tries[i][0] == 2 || tries[i][0] == 11 || tries[i][0] == 12;
+        if (!(tv & avail[i]) || (p->d == 2 && ypass)) continue;
         const int keep = p->tile_bits;
         const int field = tries[i][0] >= 8 ? 1 : 3;      // one-bit fields from bit 8 on
         p->tile_bits = (p->tile_bits & ~(field << tries[i][0])) | (tries[i][1] << tries[i][0]);

@@ -378,12 +378,14 @@ __global__ void __launch_bounds__((p5_threads<N, PX, XV>())) k_x_c2r(const cpx* 
 // P2: y-direction forward with zero padding.  Block = one kx, PPY consecutive z.
 // ---------------------------------------------------------------------------
 // PY: z-pencils per block (a tile-shape variant: the same bits for every PY)
-template <int N, int NT = NT_P2, bool CUBE = true, int PY = Geo<N>::PPY>
+// YV: radix plan of the pencil transforms (XPlan, as for the x passes)
+template <int N, int NT = NT_P2, bool CUBE = true, int PY = Geo<N>::PPY, int YV = 0>
 __device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx> __restrict__ X2,
                                            gp<const cpx> __restrict__ tw, int kx0, int bx, int kxl, int tid,
                                            bool active, cpx* lds, Ext ext = Ext()) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = PY, A = Gm::A;
+    using Fy = typename GeoX<N, YV>::F;
+    constexpr int E = Fy::E, G = Fy::G, PP = PY, A = Gm::A;
     const int NX = CUBE ? N : ext.nx, NZ = CUBE ? N : ext.nz;
     const int tA = tid % G, pA = tid / G;      // load role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // store role: consecutive z
@@ -405,8 +407,8 @@ __device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx
         cpx v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = x[e];
-        if (h) twist_const<typename Gm::F, false>(v);        // the rest of the twist rides in fft
-        fft<typename Gm::F, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw, h);
+        if (h) twist_const<Fy, false>(v);        // the rest of the twist rides in fft
+        fft<Fy, false>(v, tA, lds + pA * A, tB, lds + pB * A, tw, h);
         if (okB) {
 #pragma unroll
             for (int e = 0; e < E; ++e) stg<(NT & 2) != 0>(dst + (size_t)(2 * (tB + G * e) + h) * NZ, v[e]);
@@ -415,23 +417,24 @@ __device__ __forceinline__ void y_fwd_tile(gp<const cpx> __restrict__ X1, gp<cpx
     }
 }
 
-template <int N, int NT = NT_P2, int PY = Geo<N>::PPY>
-__global__ void __launch_bounds__(PY * Geo<N>::G) k_y_fwd(const cpx* __restrict__ X1, cpx* __restrict__ X2,
-                                                         const cpx* __restrict__ tw, int kx0) {
+template <int N, int NT = NT_P2, int PY = Geo<N>::PPY, int YV = 0>
+__global__ void __launch_bounds__((PY * GeoX<N, YV>::G)) k_y_fwd(const cpx* __restrict__ X1, cpx* __restrict__ X2,
+                                                                const cpx* __restrict__ tw, int kx0) {
     __shared__ cpx lds[PY * Geo<N>::A];
-    y_fwd_tile<N, NT, true, PY>((gp<const cpx>)X1, (gp<cpx>)X2, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y,
+    y_fwd_tile<N, NT, true, PY, YV>((gp<const cpx>)X1, (gp<cpx>)X2, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y,
                                 threadIdx.x, true, lds);
 }
 
 // ---------------------------------------------------------------------------
 // P4: y-direction inverse with cropping.  Block = one kx, PPY consecutive z.
 // ---------------------------------------------------------------------------
-template <int N, int NT = NT_P4, bool CUBE = true, int PY = Geo<N>::PPY>
+template <int N, int NT = NT_P4, bool CUBE = true, int PY = Geo<N>::PPY, int YV = 0>
 __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx> __restrict__ X1,
                                            gp<const cpx> __restrict__ tw, int kx0, int bx, int kxl, int tid,
                                            bool active, cpx* lds, Ext ext = Ext()) {
     using Gm = Geo<N>;
-    constexpr int E = Gm::E, G = Gm::G, PP = PY, A = Gm::A;
+    using Fy = typename GeoX<N, YV>::F;
+    constexpr int E = Fy::E, G = Fy::G, PP = PY, A = Gm::A;
     const int NX = CUBE ? N : ext.nx, NZ = CUBE ? N : ext.nz;
     const int tA = tid % G, pA = tid / G;      // store role: consecutive y
     const int pB = tid % PP, tB = tid / PP;    // load role: consecutive z
@@ -451,7 +454,7 @@ __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx
 #pragma unroll
         for (int e = 0; e < E; ++e)
             v[e] = okB ? ldg<NT & 1>(src + (size_t)(2 * (tB + G * e) + h) * NZ) : cmk(0.0, 0.0);
-        fft_t<typename Gm::F, true>(v, tA, lds + pA * A, tB, lds + pB * A, tw, h);   // cropping twist included
+        fft_t<Fy, true>(v, tA, lds + pA * A, tB, lds + pB * A, tw, h);   // cropping twist included
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], v[e]);
         lds_barrier();
@@ -463,11 +466,11 @@ __device__ __forceinline__ void y_inv_tile(gp<const cpx> __restrict__ X2, gp<cpx
     }
 }
 
-template <int N, int NT = NT_P4, int PY = Geo<N>::PPY>
-__global__ void __launch_bounds__(PY * Geo<N>::G) k_y_inv(const cpx* __restrict__ X2, cpx* __restrict__ X1,
-                                                         const cpx* __restrict__ tw, int kx0) {
+template <int N, int NT = NT_P4, int PY = Geo<N>::PPY, int YV = 0>
+__global__ void __launch_bounds__((PY * GeoX<N, YV>::G)) k_y_inv(const cpx* __restrict__ X2, cpx* __restrict__ X1,
+                                                                const cpx* __restrict__ tw, int kx0) {
     __shared__ cpx lds[PY * Geo<N>::A];
-    y_inv_tile<N, NT, true, PY>((gp<const cpx>)X2, (gp<cpx>)X1, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y,
+    y_inv_tile<N, NT, true, PY, YV>((gp<const cpx>)X2, (gp<cpx>)X1, (gp<const cpx>)tw, kx0, blockIdx.x, blockIdx.y,
                                 threadIdx.x, true, lds);
 }
 

@@ -280,7 +280,7 @@ def test_plan_autotune_changes_no_bit(kernel, n, tmp_path, monkeypatch):
 
 def same_as_default(tuned, x, ref):
     """A tuned plan gives the default plan's bits, except on a radix-plan variant (tile bits
-    8-10: fused, x-forward, x-inverse pass), whose other factorisation agrees to rounding."""
+    8-12: fused, x and y passes), whose other factorisation agrees to rounding."""
     u = tuned.eval(x)
     if tuned.query()["tile_variants"] & RADIX_BITS:
         assert float((u - ref).abs().max()) <= 1e-14 * float(ref.abs().max())
@@ -520,13 +520,14 @@ def test_autotuned_tile_shapes_bitwise(tmp_path, monkeypatch):
 
 
 # --------------------------------------------------------------------------
-# Radix-plan variants (tile bits 8, 9, 10: the fused, x-forward and x-inverse passes): another
+# Radix-plan variants (tile bits 8 to 12: the fused, x-forward, x-inverse, y-forward and
+# y-inverse passes): another
 # factorisation of the same transforms, so parity with the oracle at the usual bar, agreement
 # with the default plan to rounding, and the energy formed in the fused pass on the same bits as
 # the variant's evaluation.
 # --------------------------------------------------------------------------
 
-RADIX_BITS = 7 << 8
+RADIX_BITS = 31 << 8
 
 RADIX_CASES = [("coulomb3d", 3, 128, 10.0), ("dipolar3d", 3, 128, 8.0), ("coulomb3d", 3, 256, 10.0),
                ("poisson2d", 2, 256, 9.0), ("coulomb2d", 2, 512, 12.0), ("poisson2d", 2, 1024, 12.0),
@@ -545,7 +546,8 @@ def test_fused_radix_variant_against_oracle(kernel, d, n, L):
     u0 = gs.Plan(kernel, n=n, L=L, **kw).eval(x)
     umax = float(u0.abs().max())
     o = oracle.evaluate(oracle.make_plan(kernel, d, n, L, **kw), rho)
-    for tv in (1 << 8, 1 << 9, 1 << 10, RADIX_BITS):
+    bits = [1 << 8, 1 << 9, 1 << 10] + ([1 << 11, 1 << 12] if d == 3 else [])
+    for tv in bits + [RADIX_BITS if d == 3 else 7 << 8]:
         plan = gs.Plan(kernel, n=n, L=L, tile_variants=tv, **kw)
         assert plan.query()["tile_variants"] == tv
         u = plan.eval(x)
