@@ -475,6 +475,7 @@ def main() -> int:
         out["adjoint"] = adjoint_figures(gs, torch, workloads, plan, rho, K, ms_step)
         out["batched"] = batched_figures(gs, torch, workloads)
         out["other_workloads"] = other_figures(gs, torch, workloads)
+        out["graph_replay"] = graph_figures(gs, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
     print(json.dumps(out), flush=True)
@@ -512,6 +513,50 @@ def autotuned_figures(gs, torch, plan, rho, K):
     res["bitwise_equal"] = bool(torch.equal(ut, ud))
     res["max_rel_diff_vs_default"] = float((ut - ud).abs().max() / ud.abs().max())
     tuned.close()
+    return res
+
+
+def graph_figures(gs, torch, reps: int = 200):
+    """An evaluation captured in a HIP graph (torch.cuda.CUDAGraph around plan.eval) and
+    replayed, against the same evaluation launched eagerly: the launch cost that small grids
+    pay (the same bits either way)."""
+    res = {}
+    for kernel, n, L in (("coulomb3d", 32, 8.0), ("coulomb2d", 192, 12.0), ("coulomb3d", 64, 8.0),
+                         ("coulomb3d", 128, 10.0)):
+        d = 2 if kernel.endswith("2d") else 3
+        plan = gs.Plan(kernel, n=n, L=L, eps=1e-14)
+        x = torch.randn((n,) * d, dtype=torch.float64, device="cuda:0")
+        u = torch.empty_like(x)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                plan.eval(x, out=u)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.eval(x, out=u)
+
+        def timed(fn):
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        ms_eager = timed(lambda: plan.eval(x, out=u))
+        ue = u.clone()
+        ms_graph = timed(g.replay)
+        res[f"{kernel}_{n}"] = {"ms_eager": round(ms_eager, 5), "ms_graph": round(ms_graph, 5),
+                                "launches": len(plan.steps()), "same_bits": bool(torch.equal(u, ue))}
+        del g
+        plan.close()
     return res
 
 

@@ -579,3 +579,52 @@ def test_fused_radix_variant_batched_by_own_launches():
     torch.cuda.synchronize()
     assert b.info["schedule"] in ("sequential", "streams")
     assert torch.equal(outs[0], var.eval(x)) and torch.equal(outs[1], small.eval(y))
+
+
+# --------------------------------------------------------------------------
+# An evaluation is a sequence of kernel launches on the plan's stream (no allocation, no
+# memset, no synchronization), so a caller can capture it in a HIP graph and replay it.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kernel,d,n,L", [("coulomb3d", 3, 32, 8.0), ("coulomb2d", 2, 192, 12.0),
+                                          ("dipolar3d", 3, 48, 6.0), ("coulomb3d", 3, 256, 10.0)])
+def test_evaluation_captured_in_a_graph(kernel, d, n, L):
+    print(f"graph capture: {kernel} n={n}", flush=True)
+    kw = {"dipole": ((0.6, 0.8, 0.0), (0.0, 0.6, 0.8))} if kernel == "dipolar3d" else {}
+    plan = gs.Plan(kernel, n=n, L=L, **kw)
+    rng = np.random.default_rng(4400 + n)
+    x = cuda(rng.standard_normal((n,) * d))
+    x2 = cuda(rng.standard_normal((n,) * d))
+    ref, (ref_e_u, ref_e) = plan.eval(x).clone(), plan.eval_energy(x)
+    ref2 = plan.eval(x2).clone()
+    torch.cuda.synchronize()
+    u = torch.empty_like(x)
+    ue = torch.empty_like(x)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            plan.eval(x, out=u)
+            plan.eval_energy(x, out=ue)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.eval(x, out=u)
+        _, e = plan.eval_energy(x, out=ue)
+    for rep in range(3):
+        u.zero_()
+        ue.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref), rep
+        assert torch.equal(ue, ref_e_u) and torch.equal(e, ref_e), rep
+        eager = plan.eval(x2)                  # eager work on the same plan between replays
+        torch.cuda.synchronize()
+        assert torch.equal(eager, ref2), rep
+    x.copy_(x2)                                # new data in the captured input buffer
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(u, ref2)
+    del g
