@@ -883,9 +883,11 @@ gs_status time_plan(gs_plan_s* p, const double* rho, double* u, double& ms) {
     return st;
 }
 
-// Greedy search over the launch variants (none changes the result): starting from
-// the compiled defaults, flip each pass's cache-hint variant in turn and keep what is
-// faster, then try one and four rounds of co-resident blocks in the fused pass.
+// Greedy search over the launch variants: starting from the compiled defaults, flip each
+// pass's cache-hint variant in turn and keep what is faster, then try one and four rounds of
+// co-resident blocks in the fused pass, then the tile shapes and the radix plans.  None but
+// the radix plans changes the result (they agree with the default to rounding).  Timed on
+// scratch buffers, so the caller's data is never evaluated by a candidate.
 gs_status plan_autotune(gs_plan_s* p) {
     std::string dims = std::to_string(p->nc[0]);
     for (int i = 1; i < p->d; ++i) dims += "x" + std::to_string(p->nc[i]);
