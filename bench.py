@@ -586,7 +586,7 @@ def padding3_bytes(n: int) -> int:
 
 def other_figures(gs, torch, workloads, reps: int = 20):
     """Evaluation throughput of the other workloads: 2D Poisson, Coulomb and Davey-Stewartson at 2048^2,
-    3D dipolar at 128^3, 3D Coulomb at 128^3, and the rectangular boxes of the
+    2D Poisson and Coulomb at 1024^2, 3D dipolar at 128^3, 3D Coulomb at 128^3, and the rectangular boxes of the
     anisotropic tables (3D 96^3 with gamma = 8, 2D 192^2 with gamma = 16); working
     sets partly resident in the Infinity Cache, so their bandwidth fraction can
     exceed what HBM alone allows.  Then the widened rows at the headline size: the
@@ -596,6 +596,8 @@ def other_figures(gs, torch, workloads, reps: int = 20):
     cases = [("poisson2d_2048", workloads.config3_2d("poisson2d", 2048), {"eps": 1e-13}),
              ("coulomb2d_2048", workloads.config3_2d("coulomb2d", 2048), {}),
              ("davey_stewartson2d_2048", workloads.config3_2d("davey_stewartson2d", 2048), {"eps": 1e-13}),
+             ("poisson2d_1024", workloads.config3_2d("poisson2d", 1024), {"eps": 1e-13}),
+             ("coulomb2d_1024", workloads.config3_2d("coulomb2d", 1024), {}),
              ("dipolar3d_128", workloads.config3_dipolar(128), None),
              ("coulomb3d_128", workloads.config2(128), {}),
              ("rect_coulomb3d_96_gamma8", workloads.rect_box(3, 8.0), {}),
