@@ -457,7 +457,10 @@ gs_status gs_eval_batch(int count, const gs_plan* plans,
  * x-R2C, 2 = y-forward, 3 = fused, 4 = y-inverse, 5 = x-C2R) into pass_ids
  * (up to capacity) and returns the number of steps (-1 for an invalid plan).
  * gs_eval_step runs step `step` only: running 0..steps-1 in order equals
- * gs_eval.  For timing and testing the passes separately. */
+ * gs_eval.  For timing and testing the passes separately.  A step consumes what
+ * the previous step leaves in the workspace; in particular the 2D fused pass at
+ * n = 1024 takes the pencils kx = 0 and kx = n as real (as the x-R2C step leaves
+ * them: it transforms the two together as one complex pencil). */
 int gs_plan_steps(gs_plan p, int* pass_ids, int capacity);
 gs_status gs_eval_step(gs_plan p, const double* rho_dev, double* u_dev, int step);
 

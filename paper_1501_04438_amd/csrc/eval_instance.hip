@@ -189,7 +189,7 @@ static hipError_t launch_fused_v(const EvalArgs& a, hipStream_t s, const DipoleA
     static_assert(!gs_fused_persistent(2, N), "the 2D fused pass runs one block per pencil group");
     cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
     const int np = N + 1;
-    const unsigned nb = (unsigned)((np + PZ - 1) / PZ);
+    const unsigned nb = (unsigned)((fused_slots<N, 2, RV>(np) + PZ - 1) / PZ);
     if constexpr (ETILE) {
         if (a.energy) {
             if (hint) k_fused<N, 2, SPEC_PLAIN, NT_P3, PZ, true, RV><<<nb, T, 0, s>>>(X1, a.spec, tw, np, 0, dip, a.epart);
@@ -307,7 +307,7 @@ hipError_t GS_CAT(launch_eval_g_, GS_N)(const EvalArgs& a, hipStream_t s, int pa
     if (pass != 3 || a.d != 2) return hipErrorInvalidValue;
     const cpx* const twy = reinterpret_cast<const cpx*>(a.twy);
     const int np = ext.nx + 1;
-    const unsigned nb = (unsigned)((np + Gm::PPZ - 1) / Gm::PPZ);
+    const unsigned nb = (unsigned)((fused_slots<N, 2>(np) + Gm::PPZ - 1) / Gm::PPZ);
     if (a.energy) {
         if (hint) k_fused_g<N, 2, SPEC_PLAIN, NT_P3, true><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, twy, np, 0, dip, ext, a.epart);
         else k_fused_g<N, 2, SPEC_PLAIN, 0, true><<<nb, Gm::TZ, 0, s>>>(X1, a.spec, twy, np, 0, dip, ext, a.epart);

@@ -532,6 +532,24 @@ __device__ __forceinline__ int fused_pencil(int slot, int NY) {
     }
 }
 
+// 2D, long pencils: the pencils kx = 0 and kx = NX, both real along y (the x transform of real
+// rows is real at its zero and Nyquist frequencies), ride in one complex pencil a + i b: one
+// transform pair for both, so NX pencil slots instead of NX + 1 (at n = 1024 the launch is
+// otherwise two whole rounds of co-resident blocks plus one block).  After the forward
+// transform C = A + i B, the mirror W(m) = C(-m) separates the two spectra,
+// A = (C + conj W) / 2 and i B = (C - conj W) / 2, which take their own spectrum rows S0 and
+// SN; the inverse of S0 A + SN (i B) is the pair of real results a' + i b'.
+// Taken where the plan holds 8 values per thread in 128-thread halves (2D n = 1024): there the
+// packed path's registers fit beside the transform's (170 -> 192 VGPRs, two waves per SIMD
+// either way); the 16-value plans have no room for it (n = 2048: one wave per SIMD instead of
+// two).
+template <int N, int DIM, int RV = 0> constexpr bool fused_pack() {
+    return DIM == 2 && N >= 1024 && GeoZ<N, RV>::EZ <= 8 && GeoZ<N, RV>::GZ <= 128;
+}
+template <int N, int DIM, int RV = 0> __host__ __device__ constexpr int fused_slots(int npencils) {
+    return fused_pack<N, DIM, RV>() ? npencils - 1 : npencils;
+}
+
 template <int N, int DIM>
 __device__ __forceinline__ gp<const double> fused_row(gp<const double> spec, int pencil, int kx0, int NY) {
     if constexpr (DIM == 3) {
@@ -549,6 +567,15 @@ __device__ __forceinline__ void fused_load(gp<const cpx> X, int pencil, bool ok,
     gp<const cpx> base = X + (size_t)pencil * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = ok ? ldg<NT & 1>(base + t + G * e) : cmk(0.0, 0.0);
+}
+
+// The packed pencil (fused_pack): the real parts of pencils 0 and NX as one complex pencil.
+template <int N, int NT, int RV = 0>
+__device__ __forceinline__ void fused_load_pair(gp<const cpx> X, int NX, int t, cpx (&v)[GeoZ<N, RV>::EZ]) {
+    constexpr int E = GeoZ<N, RV>::EZ, G = GeoZ<N, RV>::GZ;
+    gp<const cpx> b0 = X, bn = X + (size_t)NX * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cmk(ldg<NT & 1>(b0 + t + G * e).x, ldg<NT & 1>(bn + t + G * e).x);
 }
 
 template <int N, int DIM, int NT, int RV = 0>
@@ -680,6 +707,95 @@ __device__ __forceinline__ void fused_body(gp<cpx> __restrict__ X, gp<const cpx>
     }
 }
 
+// fused_body for the plans that pack pencils 0 and NX into one (fused_pack; 2D, so the plain
+// spectrum): the same steps, with the packed pencil split into its two spectra between the
+// transforms.  Every pencil of the block passes the same barriers; only the packed one
+// exchanges its values through the LDS.
+template <int N, int DIM, int MODE, int NT = NT_P3, bool EN = false, int RV = 0>
+__device__ __forceinline__ void fused_body_pack(gp<cpx> __restrict__ X, gp<const cpx> __restrict__ tw, int pencil,
+                                                int kx0, bool ok, int t, int h, int pl,
+                                                cpx (&v)[GeoZ<N, RV>::EZ], const double (&sv)[GeoZ<N, RV>::EZ],
+                                                cpx* lds, cpx* area, int NX, int NY, gp<double> part,
+                                                bool packed, gp<const double> srow_n) {
+    using Gm = GeoZ<N, RV>;
+    using FZ = typename Gm::FZ;
+    constexpr int E = Gm::EZ, G = Gm::GZ, A = Gm::AZ;
+    constexpr bool FW = (G <= 64), CW = (2 * G <= 64);
+    static_assert(DIM == 2 && MODE == SPEC_PLAIN, "pencils are packed in 2D only");
+    if (h) twist_const<FZ, false>(v);
+    fft<FZ, false, FW>(v, t, area, t, area, tw, h);
+    double acc = 0.0, accn = 0.0;
+    lds_sync<FW>();
+    if (packed) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) area[lds_slot<FZ>(t + G * e)] = v[e];
+    }
+    lds_sync<FW>();
+    if (packed) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = t + G * e, m = 2 * j + h;
+            const int jm = h ? (N - 1 - j) : (j == 0 ? 0 : N - j);    // the half index of -m
+            const cpx w = area[lds_slot<FZ>(jm)];
+            const cpx a = cmk(0.5 * (v[e].x + w.x), 0.5 * (v[e].y - w.y));   // A = (C + conj W) / 2
+            const cpx b = cmk(0.5 * (v[e].x - w.x), 0.5 * (v[e].y + w.y));   // i B = (C - conj W) / 2
+            const double sn = ldg<(NT & 4) != 0>(srow_n + (m <= N ? m : 2 * N - m));
+            if constexpr (EN) {
+                acc += sv[e] * (a.x * a.x + a.y * a.y);
+                accn += sn * (b.x * b.x + b.y * b.y);
+            }
+            v[e] = cadd(cscale(a, sv[e]), cscale(b, sn));
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if constexpr (EN) acc += sv[e] * (v[e].x * v[e].x + v[e].y * v[e].y);
+            v[e] = cscale(v[e], sv[e]);
+        }
+    }
+    if constexpr (EN) {
+        fused_energy_store<N, DIM, RV>(acc, ok, pencil, kx0, t, h, pl, NX, NY, part);
+        fused_energy_store<N, DIM, RV>(accn, packed, NX, kx0, t, h, pl, NX, NY, part);
+    }
+    lds_sync<FW>();
+    fft_t<FZ, true, FW>(v, t, area, t, area, tw, h);
+    gp<cpx> base = X + (size_t)pencil * N;
+    gp<cpx> base_n = X + (size_t)NX * N;
+    // the packed pencil stores its real part to pencil 0 and its imaginary part to pencil NX
+    auto store = [&](int j, cpx r) {
+        if (packed) {
+            stg<(NT & 2) != 0>(base + j, cmk(r.x, 0.0));
+            stg<(NT & 2) != 0>(base_n + j, cmk(r.y, 0.0));
+        } else {
+            stg<(NT & 2) != 0>(base + j, r);
+        }
+    };
+    if constexpr (FusedRoles<N, RV>::SWAP) {
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            cpx a = v[e], b = v[e + E / 2];
+            swap_halves(a, b);
+            if (ok) store(t + G * (h * (E / 2) + e), cadd(a, b));
+        }
+        lds_sync<FW>();
+    } else {
+        lds_sync<FW>();
+#pragma unroll
+        for (int e = 0; e < E; ++e) area[lds_slot<FZ>(t + G * e)] = v[e];
+        lds_sync<CW>();
+        if (ok) {
+            const cpx* a0 = lds + (pl * 2) * A;
+            const cpx* a1 = a0 + A;
+#pragma unroll
+            for (int ee = 0; ee < E / 2; ++ee) {
+                const int j = t + G * (h * (E / 2) + ee);
+                store(j, cadd(a0[lds_slot<FZ>(j)], a1[lds_slot<FZ>(j)]));
+            }
+        }
+        lds_sync<CW>();
+    }
+}
+
 // One pencil group of the fused pass without prefetch (the batched launches).
 // PZ: pencils per block (a tile-shape variant: the same bits for every PZ); RV: radix plan
 // (FusedPlan)
@@ -697,15 +813,24 @@ __device__ __forceinline__ void fused_group(gp<cpx> __restrict__ X, gp<const dou
     cpx* area = lds + (pl * 2 + h) * A;
     const int slot = g * PP + pl;
     // in 3D the pencil count is a multiple of 2n, so groups of PP pencils never run past it
-    // when PP divides 2n; 2D has n + 1 pencils
+    // when PP divides 2n; 2D has n + 1 pencils (n slots when pencils 0 and n ride together)
     constexpr bool FULL = CUBE && (DIM == 3 && (2 * N) % PP == 0);
-    const bool ok = active && (FULL || slot < npencils);
+    const bool ok = active && (FULL || slot < fused_slots<N, DIM, RV>(npencils));
     const int pencil = ok ? fused_pencil<N, DIM>(slot, NY) : 0;
     cpx v[E];
     double sv[E];
-    fused_load<N, DIM, NT, RV>(X, pencil, ok, t, v);
-    fused_spec<N, DIM, NT, RV>(spec, pencil, kx0, ok, t, h, sv, NY);
-    fused_body<N, DIM, MODE, NT, EN, RV>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area, NX, NY, part);
+    if constexpr (fused_pack<N, DIM, RV>()) {
+        const bool packed = ok && slot == 0;
+        if (packed) fused_load_pair<N, NT, RV>(X, NX, t, v);
+        else fused_load<N, DIM, NT, RV>(X, pencil, ok, t, v);
+        fused_spec<N, DIM, NT, RV>(spec, pencil, kx0, ok, t, h, sv, NY);
+        fused_body_pack<N, DIM, MODE, NT, EN, RV>(X, tw, pencil, kx0, ok, t, h, pl, v, sv, lds, area, NX, NY, part,
+                                                  packed, fused_row<N, DIM>(spec, NX, kx0, NY));
+    } else {
+        fused_load<N, DIM, NT, RV>(X, pencil, ok, t, v);
+        fused_spec<N, DIM, NT, RV>(spec, pencil, kx0, ok, t, h, sv, NY);
+        fused_body<N, DIM, MODE, NT, EN, RV>(X, tw, pencil, kx0, ok, dip, t, h, pl, v, sv, lds, area, NX, NY, part);
+    }
 }
 
 // EN: also the energy sum of every pencil into part (fused_energy_store); RV: radix plan.
@@ -714,7 +839,7 @@ __global__ void __launch_bounds__((PZ * 2 * GeoZ<N, RV>::GZ)) k_fused(cpx* __res
                                                               const cpx* __restrict__ twg, int npencils, int kx0,
                                                               DipoleArgs dip, double* __restrict__ part = nullptr) {
     __shared__ cpx lds[PZ * 2 * GeoZ<N, RV>::AZ];
-    const int ngroups = (npencils + PZ - 1) / PZ;
+    const int ngroups = (fused_slots<N, DIM, RV>(npencils) + PZ - 1) / PZ;
     if constexpr (!gs_fused_persistent(DIM, N)) {
         // one pencil group per block (the grid must cover all groups).  Without the
         // persistent loop the compiler does not keep the stage twiddles of every thread
@@ -774,7 +899,7 @@ __global__ void __launch_bounds__(Geo<N>::TZ) k_fused_g(cpx* __restrict__ Xg, co
                                                         const cpx* __restrict__ twg, int npencils, int kx0,
                                                         DipoleArgs dip, Ext ext, double* __restrict__ part = nullptr) {
     __shared__ cpx lds[Geo<N>::PPZ * 2 * Geo<N>::AZ];
-    const int ngroups = (npencils + Geo<N>::PPZ - 1) / Geo<N>::PPZ;
+    const int ngroups = (fused_slots<N, DIM>(npencils) + Geo<N>::PPZ - 1) / Geo<N>::PPZ;
     if ((int)blockIdx.x < ngroups)
         fused_group<N, DIM, MODE, NT, false, Geo<N>::PPZ, EN>((gp<cpx>)Xg, (gp<const double>)specg,
                                                               (gp<const cpx>)twg, npencils, kx0, dip, blockIdx.x,
