@@ -59,6 +59,8 @@ CASES = [("coulomb3d", 3, (12, 24, 16), (3.0, 6.0, 4.0)),
          ("poisson2d", 2, (96, 192), (6.0, 12.0)),
          ("coulomb2d", 2, (192, 64), (12.0, 4.0)),
          ("coulomb2d", 2, (256, 2048), (2.0, 16.0)),
+         # fused axis of 1024 points: its zero and Nyquist pencils (kx = 0, 96) ride together
+         ("poisson2d", 2, (1024, 96), (12.0, 1.125)),
          ("davey_stewartson2d", 2, (32, 64), (4.0, 7.0)),
          ("inverse_power", 2, (48, 12), (8.0, 2.0))]
 
@@ -167,3 +169,20 @@ def test_batch_takes_rectangular_grids_sequentially():
     torch.cuda.synchronize()
     assert b.info["schedule"] in ("sequential", "streams")
     assert torch.equal(outs[0], rect.eval(r1)) and torch.equal(outs[1], cube.eval(r2))
+
+
+def test_packed_pencils_energy_rectangular():
+    """The 2D fused pass of 1024 points on a grid with 96 columns: the energy formed in the
+    pass (the packed pencil's two spectra summed apart) against the sum in space, and the
+    potential on the same bits as gs_eval."""
+    n, L = (1024, 96), (12.0, 1.125)
+    rng = np.random.default_rng(96)
+    rho = cuda(rng.standard_normal(n))
+    plan = gs.Plan("coulomb2d", n=n, L=L)
+    u0 = plan.eval(rho)
+    u, e = plan.eval_energy(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(u, u0)
+    cell = (2 * L[0] / n[0]) * (2 * L[1] / n[1])
+    e_space = 0.5 * cell * float((rho * u).sum())
+    assert abs(float(e) - e_space) <= 1e-13 * 0.5 * cell * float((rho * u).abs().sum())
