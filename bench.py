@@ -578,10 +578,11 @@ def grid_chain_bytes(nx: int, ny: int, nz: int) -> int:
 
 
 def padding3_bytes(n: int) -> int:
-    """Padding to B_3 of an n^3 grid: the chain on the 3n/2 transform grid, the density copied
-    in (read n^3, write (3n/2)^3) and the potential out (read and write n^3)."""
+    """Padding to B_3 of an n^3 grid: the chain on the 3n/2 transform grid, whose x-forward
+    pass reads the n^3 density itself and whose x-inverse pass writes the n^3 potential (no
+    copies of the transform grid's size)."""
     m = 3 * n // 2
-    return grid_chain_bytes(m, m, m) + 8 * n ** 3 + 8 * m ** 3 + 16 * n ** 3
+    return grid_chain_bytes(m, m, m) - 2 * 8 * m ** 3 + 2 * 8 * n ** 3
 
 
 def other_figures(gs, torch, workloads, reps: int = 20):

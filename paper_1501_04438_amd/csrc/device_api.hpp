@@ -55,6 +55,10 @@ struct EvalArgs {
     const double* pad_in = nullptr;
     double* pad_out = nullptr;
     int px = 0, py = 0, pz = 0;
+    // Padding 3 on a cubic transform grid: no copies; the x-forward pass reads the density rho
+    // (px, py, pz points) in place and the x-inverse pass writes the potential u at those
+    // points only.
+    int emb = 0;
 };
 
 // The density (nx, ny, nz points, x fastest) into the first points of each axis of a grid

@@ -79,10 +79,52 @@ static hipError_t launch_x_inverse_v(const EvalArgs& a, hipStream_t s) {
     return launch_energy_total(a.epart, a.epencils, a.escale, a.energy, s);
 }
 
+// Padding to B_3 on a cubic transform grid (lengths 3n/2): P1 and P5 with the density and the
+// potential at their own extents (a.px, a.py, a.pz), at the default tile.
+static hipError_t launch_x_emb(const EvalArgs& a, hipStream_t s, int pass) {
+    constexpr int N = GS_N;
+    if constexpr (N % 3 == 0) {
+        using Gm = Geo<N>;
+        Ext ext;
+        ext.nx = a.px;
+        ext.ny = a.py;
+        ext.nz = a.d == 3 ? a.pz : 1;
+        if (ext.nx > N || ext.ny > N || ext.nz > (a.d == 3 ? N : 1)) return hipErrorInvalidValue;
+        const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
+        const dim3 gx((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX), a.d == 3 ? N : 1);
+        if (pass == 1) {
+            cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
+            if (a.hint_bits & 1) k_x_r2c_emb<N, NT_P1><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw, ext);
+            else k_x_r2c_emb<N, 0><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw, ext);
+            return hipGetLastError();
+        }
+        const cpx* const X1 = reinterpret_cast<const cpx*>(a.X1);
+        constexpr int T = p5_threads<N, Gm::PPX>();
+        const bool hint = (a.hint_bits >> 4) & 1;
+        const bool sc = a.energy && a.oscale != 1.0;
+        if (sc) {
+            if (hint) k_x_c2r_emb<N, NT_P5, true><<<gx, T, 0, s>>>(X1, a.u, tw, ext, a.oscale);
+            else k_x_c2r_emb<N, 0, true><<<gx, T, 0, s>>>(X1, a.u, tw, ext, a.oscale);
+        } else {
+            if (hint) k_x_c2r_emb<N, NT_P5, false><<<gx, T, 0, s>>>(X1, a.u, tw, ext, 1.0);
+            else k_x_c2r_emb<N, 0, false><<<gx, T, 0, s>>>(X1, a.u, tw, ext, 1.0);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !a.energy) return e;
+        return launch_energy_total(a.epart, a.epencils, a.escale, a.energy, s);
+    } else {
+        (void)a;
+        (void)s;
+        (void)pass;
+        return hipErrorInvalidValue;
+    }
+}
+
 // Tile bit 10 selects the x-inverse pass's radix-plan variant (XPlan<N, 1>, at the default row
 // pairs per block; bits 6-7 then do not apply) where one is compiled.
 static hipError_t launch_x_inverse(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
+    if (a.emb) return launch_x_emb(a, s, 5);
     if constexpr (x_radix_variant<N>()) {
         if ((a.tile_bits >> 10) & 1) return launch_x_inverse_v<Geo<N>::PPX, 1>(a, s);
     }
@@ -105,6 +147,7 @@ static hipError_t launch_x_forward_v(const EvalArgs& a, hipStream_t s) {
 // Tile bit 9: the x-forward pass's radix-plan variant, as bit 10 for the x-inverse pass.
 static hipError_t launch_x_forward(const EvalArgs& a, hipStream_t s) {
     constexpr int N = GS_N;
+    if (a.emb) return launch_x_emb(a, s, 1);
     if constexpr (x_radix_variant<N>()) {
         if ((a.tile_bits >> 9) & 1) return launch_x_forward_v<Geo<N>::PPX, 1>(a, s);
     }

@@ -213,8 +213,13 @@ gs_status make_args(gs_plan p, const double* in, double* out, gsk::EvalArgs& a) 
         a.px = p->nu[0];
         a.py = p->nu[1];
         a.pz = p->d == 3 ? p->nu[2] : 1;
-        a.rho = p->E;
-        a.u = p->E;
+        if (p->cube) {
+            // the x passes read the density and write the potential at their own extents
+            a.emb = 1;
+        } else {
+            a.rho = p->E;
+            a.u = p->E;
+        }
     }
     a.X1 = p->X1;
     a.X2 = p->X2;
@@ -269,11 +274,12 @@ static hipError_t run_step(gs_plan p, gsk::EvalArgs& a, int step, hipStream_t s)
     const int nz = p->d == 3 ? p->nk[2] : 1;
     hipError_t e = hipSuccess;
     // padding 3: the density into the transform grid before the first step
-    if (p->pad == 3 && step == 0)
+    // (cubic transform grids: the x passes read and write the caller's arrays themselves)
+    if (p->pad == 3 && !a.emb && step == 0)
         e = gsk::launch_pad_embed(a.pad_in, a.u, a.px, a.py, a.pz, p->nk[0], p->nk[1], nz, s);
     if (e == hipSuccess) e = gsk::launch_eval(b, s, pass);
     // and the potential out of it after the last
-    if (e == hipSuccess && p->pad == 3 && step == (int)p->steps.size() - 1)
+    if (e == hipSuccess && p->pad == 3 && !a.emb && step == (int)p->steps.size() - 1)
         e = gsk::launch_pad_crop(a.u, a.pad_out, a.px, a.py, a.pz, p->nk[0], p->nk[1], nz, s);
     return e;
 }
@@ -363,7 +369,7 @@ gs_status eval_chain_ws(gs_plan p, const double* in, double* out, double2* ws) {
     workspace_parts(p, x1, x2, ne);
     a.X1 = ws;
     a.X2 = p->d == 3 ? ws + x1 : nullptr;
-    if (p->pad == 3) {
+    if (p->pad == 3 && !a.emb) {
         a.rho = reinterpret_cast<const double*>(ws + x1 + x2);
         a.u = reinterpret_cast<double*>(ws + x1 + x2);
     }

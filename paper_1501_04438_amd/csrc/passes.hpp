@@ -125,7 +125,10 @@ struct Ext {
 // both (same values, same bits; E fewer complex values live through the first half's transform,
 // which the batched kernels, sized for every length at once, need for their occupancy)
 // XV: radix plan of the row transforms (XPlan).
-template <int N, int NT = NT_P1, bool CUBE = true, int PX = Geo<N>::PPX, bool RL = false, int XV = 0>
+// EMB (with CUBE): the density is the first ext.nx x ext.ny x ext.nz points of the transform
+// grid, read from an array of those extents, zeros elsewhere (padding to B_3 without a copy).
+template <int N, int NT = NT_P1, bool CUBE = true, int PX = Geo<N>::PPX, bool RL = false, int XV = 0,
+          bool EMB = false>
 __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp<cpx> __restrict__ X1,
                                            gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
                                            cpx* lds, Ext ext = Ext()) {
@@ -150,7 +153,17 @@ __device__ __forceinline__ void x_r2c_tile(gp<const double> __restrict__ rho, gp
     const int rowB = SPLIT ? y0 + 16 * (pB / 8) + pB % 8 : y0 + 2 * pB;
 
     cpx x[RL ? 1 : E];
-    if constexpr (!RL) {
+    if constexpr (EMB) {
+        static_assert(CUBE && !RL, "embedded density on the cubic tiles");
+        const bool r0 = okA && z < ext.nz && rowA < ext.ny, r1 = okA && z < ext.nz && rowA + RS < ext.ny;
+        gp<const double> ra = rho + ((size_t)z * ext.ny + rowA) * ext.nx;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = tA + G * e;
+            const bool in = j < ext.nx;
+            x[e] = cmk(r0 && in ? ldg<NT & 1>(ra + j) : 0.0, r1 && in ? ldg<NT & 1>(ra + (size_t)RS * ext.nx + j) : 0.0);
+        }
+    } else if constexpr (!RL) {
         gp<const double> ra = rho + ((size_t)z * NY + rowA) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -222,7 +235,10 @@ k_x_r2c(const double* __restrict__ rho, cpx* __restrict__ X1,
 // P5: x-direction complex-to-real with cropping.  Inverse of P1 (unnormalised).
 // ---------------------------------------------------------------------------
 // SC: the outputs are stored times oscale (the rho gradient of the energy, cell u).
-template <int N, int NT = NT_P5, bool SC = false, bool CUBE = true, int PX = Geo<N>::PPX, int XV = 0>
+// EMB (with CUBE): the potential is stored for the first ext.nx x ext.ny x ext.nz points of the
+// transform grid only, into an array of those extents (padding to B_3 without a copy).
+template <int N, int NT = NT_P5, bool SC = false, bool CUBE = true, int PX = Geo<N>::PPX, int XV = 0,
+          bool EMB = false>
 __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<double> u,
                                            gp<const cpx> __restrict__ tw, int bx, int z, int tid, bool active,
                                            cpx* lds, Ext ext = Ext(), double oscale = 1.0) {
@@ -270,7 +286,23 @@ __device__ __forceinline__ void x_c2r_tile(gp<const cpx> __restrict__ X1, gp<dou
         for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], v[e]);
         lds_barrier();
     }
-    if (okA) {
+    if constexpr (EMB) {
+        static_assert(CUBE, "embedded potential on the cubic tiles");
+        const bool r0 = okA && z < ext.nz && rowA < ext.ny, r1 = okA && z < ext.nz && rowA + RS < ext.ny;
+        gp<double> ua = u + ((size_t)z * ext.ny + rowA) * ext.nx;
+        if constexpr (SC) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = cscale(acc[e], oscale);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = tA + G * e;
+            if (j < ext.nx) {
+                if (r0) stg<(NT & 2) != 0>(ua + j, acc[e].x);
+                if (r1) stg<(NT & 2) != 0>(ua + (size_t)RS * ext.nx + j, acc[e].y);
+            }
+        }
+    } else if (okA) {
         const size_t o = ((size_t)z * NY + rowA) * N;
         gp<double> ua = u + o;
         if constexpr (SC) {
@@ -306,10 +338,10 @@ template <int N, int PX, int XV = 0> constexpr int p5_threads() {
     return (p5_split<N, PX, XV>() ? 2 : 1) * PX * GeoX<N, XV>::G;
 }
 
-template <int N, int NT, bool SC, int PX, int XV = 0>
+template <int N, int NT, bool SC, int PX, int XV = 0, bool EMB = false>
 __device__ __forceinline__ void x_c2r_tile_split(gp<const cpx> __restrict__ X1, gp<double> u,
                                                  gp<const cpx> __restrict__ tw, int bx, int z, int tid, cpx* lds,
-                                                 double oscale, bool active = true) {
+                                                 double oscale, bool active = true, Ext ext = Ext()) {
     using Gm = Geo<N>;
     using Fx = typename GeoX<N, XV>::F;
     constexpr int E = Fx::E, G = Fx::G, PP = PX, A = Gm::A;
@@ -342,7 +374,11 @@ __device__ __forceinline__ void x_c2r_tile_split(gp<const cpx> __restrict__ X1, 
         v[e] = cmk(a.x - b.y, a.y + b.x);              // a + i b
     }
     fft_t<Fx, true>(v, tA, lds + (h * PP + pA) * A, tB, lds + (h * PP + pB) * A, tw, h);
-    gp<double> ua = u + ((size_t)z * N + rowA) * N;
+    // EMB: only the first ext.nx x ext.ny x ext.nz points, into an array of those extents
+    const int OX = EMB ? ext.nx : N, OY = EMB ? ext.ny : N;
+    const bool r0 = okA && (!EMB || (z < ext.nz && rowA < ext.ny));
+    const bool r1 = okA && (!EMB || (z < ext.nz && rowA + RS < ext.ny));
+    gp<double> ua = u + ((size_t)z * OY + rowA) * OX;
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) {
         // lanes h = 0 end with the sum for element e, lanes h = 1 with that for e + E/2
@@ -350,10 +386,10 @@ __device__ __forceinline__ void x_c2r_tile_split(gp<const cpx> __restrict__ X1, 
         swap_halves(a, b);
         cpx r = cadd(a, b);
         const int j = tA + G * (h * (E / 2) + e);
-        if (okA) {
+        if (EMB ? (r0 || r1) && j < ext.nx : okA) {
             if constexpr (SC) r = cscale(r, oscale);
-            stg<(NT & 2) != 0>(ua + j, r.x);
-            stg<(NT & 2) != 0>(ua + (size_t)RS * N + j, r.y);
+            if (!EMB || r0) stg<(NT & 2) != 0>(ua + j, r.x);
+            if (!EMB || r1) stg<(NT & 2) != 0>(ua + (size_t)RS * OX + j, r.y);
         }
     }
 }
@@ -371,6 +407,34 @@ __global__ void __launch_bounds__((p5_threads<N, PX, XV>())) k_x_c2r(const cpx* 
         __shared__ cpx lds[PX * Geo<N>::A];
         x_c2r_tile<N, NT, SC, true, PX, XV>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
                                             blockIdx.y, threadIdx.x, true, lds, Ext(), oscale);
+    }
+}
+
+// P1 and P5 of padding to B_3 on a cubic transform grid: the density (ext points per axis, in
+// the first points of each axis) read, and the potential written, in place of copies into and
+// out of a grid-sized array.
+template <int N, int NT>
+__global__ void __launch_bounds__(Geo<N>::TX) __attribute__((amdgpu_waves_per_eu(N == 2048 ? 2 : 1)))
+k_x_r2c_emb(const double* __restrict__ rho, cpx* __restrict__ X1, const cpx* __restrict__ tw, Ext ext) {
+    __shared__ cpx lds[Geo<N>::PPX * Geo<N>::A];
+    x_r2c_tile<N, NT, true, Geo<N>::PPX, false, 0, true>((gp<const double>)rho, (gp<cpx>)X1, (gp<const cpx>)tw,
+                                                         blockIdx.x, blockIdx.y, threadIdx.x, true, lds, ext);
+}
+
+template <int N, int NT, bool SC>
+__global__ void __launch_bounds__((p5_threads<N, Geo<N>::PPX>())) k_x_c2r_emb(const cpx* __restrict__ X1,
+                                                                              double* __restrict__ u,
+                                                                              const cpx* __restrict__ tw, Ext ext,
+                                                                              double oscale) {
+    constexpr int PX = Geo<N>::PPX;
+    if constexpr (p5_split<N, PX>()) {
+        __shared__ cpx lds[2 * PX * Geo<N>::A];
+        x_c2r_tile_split<N, NT, SC, PX, 0, true>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                                 blockIdx.y, threadIdx.x, lds, oscale, true, ext);
+    } else {
+        __shared__ cpx lds[PX * Geo<N>::A];
+        x_c2r_tile<N, NT, SC, true, PX, 0, true>((gp<const cpx>)X1, (gp<double>)u, (gp<const cpx>)tw, blockIdx.x,
+                                                 blockIdx.y, threadIdx.x, true, lds, ext, oscale);
     }
 }
 
