@@ -578,11 +578,16 @@ def grid_chain_bytes(nx: int, ny: int, nz: int) -> int:
 
 
 def padding3_bytes(n: int) -> int:
-    """Padding to B_3 of an n^3 grid: the chain on the 3n/2 transform grid, whose x-forward
-    pass reads the n^3 density itself and whose x-inverse pass writes the n^3 potential (no
+    """Padding to B_3 of an n^3 grid: the chain on the m = 3n/2 transform grid, whose x-forward
+    pass reads the n^3 density itself, whose y-inverse pass runs for the planes z < n only and
+    whose x-inverse pass reads the rows y < n of those planes and writes the n^3 potential (no
     copies of the transform grid's size)."""
     m = 3 * n // 2
-    return grid_chain_bytes(m, m, m) - 2 * 8 * m ** 3 + 2 * 8 * n ** 3
+    x1 = 16 * (m + 1) * m * m       # [z][kx][y] complex
+    x2 = 32 * (m + 1) * m * m       # [kx][ky][z] complex
+    spec = 8 * (m + 1) ** 3
+    f = n / m
+    return round(8 * n ** 3 + x1 + (x1 + x2) + (2 * x2 + spec) + (x2 + x1) * f + x1 * f * f + 8 * n ** 3)
 
 
 def other_figures(gs, torch, workloads, reps: int = 20):

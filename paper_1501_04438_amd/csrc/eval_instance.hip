@@ -91,7 +91,7 @@ static hipError_t launch_x_emb(const EvalArgs& a, hipStream_t s, int pass) {
         ext.nz = a.d == 3 ? a.pz : 1;
         if (ext.nx > N || ext.ny > N || ext.nz > (a.d == 3 ? N : 1)) return hipErrorInvalidValue;
         const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
-        const dim3 gx((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX), a.d == 3 ? N : 1);
+        dim3 gx((N + 2 * Gm::PPX - 1) / (2 * Gm::PPX), a.d == 3 ? N : 1);
         if (pass == 1) {
             cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
             if (a.hint_bits & 1) k_x_r2c_emb<N, NT_P1><<<gx, Gm::TX, 0, s>>>(a.rho, X1, tw, ext);
@@ -101,6 +101,9 @@ static hipError_t launch_x_emb(const EvalArgs& a, hipStream_t s, int pass) {
         const cpx* const X1 = reinterpret_cast<const cpx*>(a.X1);
         constexpr int T = p5_threads<N, Gm::PPX>();
         const bool hint = (a.hint_bits >> 4) & 1;
+        // the x-inverse pass only for the rows and planes that hold potential values
+        gx.x = (ext.ny + 2 * Gm::PPX - 1) / (2 * Gm::PPX);
+        gx.y = ext.nz;
         const bool sc = a.energy && a.oscale != 1.0;
         if (sc) {
             if (hint) k_x_c2r_emb<N, NT_P5, true><<<gx, T, 0, s>>>(X1, a.u, tw, ext, a.oscale);
@@ -162,7 +165,10 @@ static hipError_t launch_y_v(const EvalArgs& a, hipStream_t s, int pass) {
     cpx* const X1 = reinterpret_cast<cpx*>(a.X1);
     cpx* const X2 = reinterpret_cast<cpx*>(a.X2);
     const cpx* const tw = reinterpret_cast<const cpx*>(a.tw);
-    const dim3 gy((N + PY - 1) / PY, a.kxn);
+    // padding to B_3 in place (a.emb): the y-inverse pass only for the planes z < pz, the only
+    // ones the x-inverse pass reads
+    const int zs = (pass == 4 && a.emb) ? a.pz : N;
+    const dim3 gy((zs + PY - 1) / PY, a.kxn);
     constexpr int T = PY * GeoX<N, YV>::G;
     const bool hint = (a.hint_bits >> (pass - 1)) & 1;
     if (pass == 2) {
