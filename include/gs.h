@@ -112,9 +112,13 @@ typedef enum {
                                      3 n_j / 2 in the compiled size list (UNSUPPORTED_SIZE):
                                      the passes run on a grid of 3 n_j / 2 points per axis
                                      (the density in its first n_j points, zeros after,
-                                     padded twice), copied in before the first step and out
-                                     after the last; its copy adds (3/2)^d n^d doubles to
-                                     the workspace.  Not batched (the batched schedules
+                                     padded twice).  On a cubic grid the x passes read the
+                                     density and write the potential in place (the inverse
+                                     passes only where the potential is kept); otherwise
+                                     the density is copied in before the first step and the
+                                     potential out after the last, the copy adding
+                                     (3/2)^d n^d doubles to the workspace (allocated for
+                                     both).  Not batched (the batched schedules
                                      refuse it; GS_SCHED_AUTO evaluates it on its own) */
 
 /* Size of the fixed device array gs_eval_static uses as its workspace. */
